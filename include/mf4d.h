@@ -1,0 +1,167 @@
+/*
+ * mf4d -- coupled point + field 4D region growing on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the library libmf4d.so.  Plain pointers and sizes only.
+ *
+ * The data model follows Sauer & Ma, "Multifaceted 4D Feature Segmentation
+ * and Extraction in Point and Field-based Datasets", Section 3.1: field
+ * samples F(t) = {x_f, y_f, z_f, v_f(t)} on a fixed regular grid and point
+ * samples P(t) = {x_p(t), y_p(t), z_p(t), v_p(t)} that move and form
+ * trajectories.  The grown feature has a field part and a point part and
+ * spans timesteps (Section 1, contributions).
+ *
+ * Operation.  Nodes are voxel-steps (x, y, z, t) and particle-steps (i, t).
+ * A voxel-step is admissible iff f_lo <= f <= f_hi and a particle-step iff
+ * a_lo <= a <= a_hi, compared in fp32 on the stored values; NaN is never
+ * admissible.  (Each sample type is tested only on its own value, as the
+ * paper's D_f and D_p compare each sample type only with its own variable,
+ * Section 3.2.3.)  Undirected edges join a voxel to its six spatial face
+ * neighbours and to the same voxel at t-1 and t+1 (no wrap-around); a
+ * particle-step to the voxel whose volume holds it (the field-to-point index
+ * of Section 3.1; voxel i covers [i, i+1) per axis in voxel units, and a
+ * position outside [0, dim) or NaN lies in no voxel); and a particle-step to
+ * the same particle at t-1 and t+1 (trajectories connect points between
+ * timesteps, Section 1).  The grown set is every node reachable from the
+ * admissible seeds through admissible nodes.  Seeds that are not admissible
+ * are dropped and counted.
+ *
+ * Layouts.
+ *   field      fp32 [T][Z][Y][X]
+ *   xyz        fp32 [T][P][3], positions already in voxel units
+ *   attr       fp32 [T][P]
+ *   seeds      int32 [S][4] = (x, y, z, t)
+ *   field mask uint32 words: voxel-step bit ((t*Z + z)*Y + y)*X + x lives in
+ *              word bit >> 5 at bit position bit & 31; bits past the end of
+ *              the grid in the last word are zero
+ *   particle mask uint8 [T][P], 1 = member
+ *
+ * Ownership and streams.  A context owns every device buffer it allocates.
+ * Caller pointers are borrowed for the duration of a call only; each pointer
+ * argument is accompanied by `where` (MF4D_HOST or MF4D_DEVICE).  All work is
+ * ordered on the HIP stream given at creation (NULL = the null stream).
+ * Load and read calls return once their copies are complete; mf4d_grow
+ * returns once the grown set is complete on the device.
+ *
+ * Errors.  Every call returns MF4D_OK or a negative status and records a
+ * message readable with mf4d_last_error() (per thread).  Arguments are
+ * validated before any state changes, so a failed call leaves the context as
+ * it was (except MF4D_ERR_HIP, after which the context should be destroyed).
+ * No C++ exception crosses this interface.
+ */
+#ifndef MF4D_H
+#define MF4D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mf4d_ctx mf4d_ctx;
+
+enum {
+    MF4D_OK = 0,
+    MF4D_ERR_ARG = -1,           /* bad pointer, size or value */
+    MF4D_ERR_RANGE = -2,         /* a seed outside the grid */
+    MF4D_ERR_OOM = -3,           /* device allocation failed */
+    MF4D_ERR_HIP = -4,           /* a HIP runtime call failed */
+    MF4D_ERR_STATE = -5,         /* call out of order (e.g. grow before load) */
+    MF4D_ERR_NOT_CONVERGED = -6, /* round cap reached; masks hold a valid subset */
+    MF4D_ERR_UNSUPPORTED = -7    /* shape outside what this build supports */
+};
+
+enum { MF4D_HOST = 0, MF4D_DEVICE = 1 };
+
+typedef struct mf4d_stats {
+    int64_t rounds;           /* global rounds, counting the last one that found no work */
+    int64_t tile_visits;      /* tile sweeps executed over all rounds */
+    int64_t particle_visits;  /* particle closures executed over all rounds */
+    int64_t members_field;    /* |M ∩ voxel-steps| (filled by mf4d_read_field_mask) */
+    int64_t members_particle; /* |M ∩ particle-steps| (filled by mf4d_read_particle_mask) */
+    int64_t seeds_dropped;    /* seed entries that failed the field criterion */
+    int64_t active_tiles;     /* tiles holding at least one admissible voxel-step */
+    double ms_admit_field;    /* admissibility pass over the field (one kernel) */
+    double ms_admit;          /* admissibility pass over field and particles */
+    double ms_rounds;         /* seeding and all rounds */
+    double ms_total;          /* the whole mf4d_grow call on the device */
+} mf4d_stats;
+
+/* Library version string. */
+const char *mf4d_version(void);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *mf4d_last_error(void);
+
+/* Create a context on HIP device `device`, ordering its work on `hip_stream`
+ * (a hipStream_t, or NULL for the null stream).  *out receives the context.
+ * Errors: MF4D_ERR_ARG (out NULL, bad device), MF4D_ERR_HIP. */
+int mf4d_create(mf4d_ctx **out, int device, void *hip_stream);
+
+/* Release every device buffer of the context.  NULL is accepted. */
+void mf4d_destroy(mf4d_ctx *ctx);
+
+/* Tile shape used for the bit-packed labels: 32 (x, one word) x 8 (y) x 8 (z)
+ * x bt (t) voxel-steps, bt in {4, 8, 16}.  Must be called before
+ * mf4d_load_field; the default is bt = 8.
+ * Errors: MF4D_ERR_ARG (other values), MF4D_ERR_STATE (field already loaded). */
+int mf4d_set_tile(mf4d_ctx *ctx, int bt);
+
+/* Load the field samples F(t) (Section 3.1): fp32 [T][Z][Y][X].  Replaces any
+ * earlier field and drops loaded particles (they are binned against this
+ * grid).  Requires X*Y*Z*T (padded to whole tiles) < 2^32.
+ * Errors: MF4D_ERR_ARG, MF4D_ERR_UNSUPPORTED (too large), MF4D_ERR_OOM. */
+int mf4d_load_field(mf4d_ctx *ctx, const float *field, int X, int Y, int Z, int T, int where);
+
+/* Load the point samples P(t) (Section 3.1): positions xyz fp32 [T][P][3] in
+ * voxel units and values attr fp32 [T][P], with the same T as the field.
+ * Bins every particle-step into the voxel covering it (the field-to-point
+ * index of Section 3.1).  P = 0 clears the particles.
+ * Errors: MF4D_ERR_STATE (no field), MF4D_ERR_ARG (T differs, bad sizes),
+ * MF4D_ERR_UNSUPPORTED (P*T padded >= 2^31), MF4D_ERR_OOM. */
+int mf4d_load_particles(mf4d_ctx *ctx, const float *xyz, const float *attr, int64_t P, int T,
+                        int where);
+
+/* Membership criteria: inclusive fp32 bands for field and particle values.
+ * Errors: MF4D_ERR_ARG (a NaN bound). */
+int mf4d_set_criteria(mf4d_ctx *ctx, float f_lo, float f_hi, float a_lo, float a_hi);
+
+/* Seeds int32 [S][4] = (x, y, z, t).  Duplicates are allowed.
+ * Errors: MF4D_ERR_STATE (no field), MF4D_ERR_RANGE (a seed outside the
+ * grid; nothing changes), MF4D_ERR_ARG. */
+int mf4d_set_seeds(mf4d_ctx *ctx, const int32_t *xyzt, int64_t S, int where);
+
+/* Cap on rounds per mf4d_grow / mf4d_grow_resume call (0 = no cap). */
+int mf4d_set_max_rounds(mf4d_ctx *ctx, int64_t cap);
+
+/* Grow the feature from scratch: admissibility of every node, seeding, and
+ * rounds of tile sweeps and particle coupling until a round changes no bit.
+ * `out` (nullable) receives statistics.
+ * Errors: MF4D_ERR_STATE (no field or no criteria), MF4D_ERR_NOT_CONVERGED
+ * (the round cap was reached: the labels hold a subset of the feature that
+ * is reachable from the seeds; mf4d_grow_resume continues), MF4D_ERR_HIP. */
+int mf4d_grow(mf4d_ctx *ctx, mf4d_stats *out);
+
+/* Continue rounds from the current labels after MF4D_ERR_NOT_CONVERGED.
+ * Errors: as mf4d_grow; MF4D_ERR_STATE if there is nothing to resume. */
+int mf4d_grow_resume(mf4d_ctx *ctx, mf4d_stats *out);
+
+/* Write the field part of the grown feature as canonical bit words (layout
+ * above) to dst, which holds nwords >= ceil(X*Y*Z*T / 32) words.  Counts the
+ * members into the statistics of the last grow (see mf4d_last_stats).
+ * Errors: MF4D_ERR_STATE (nothing grown), MF4D_ERR_ARG (dst too small). */
+int mf4d_read_field_mask(mf4d_ctx *ctx, uint32_t *dst, size_t nwords, int where);
+
+/* Write the particle part of the grown feature as uint8 [T][P] to dst,
+ * which holds n >= T*P bytes.
+ * Errors: MF4D_ERR_STATE (nothing grown or no particles), MF4D_ERR_ARG. */
+int mf4d_read_particle_mask(mf4d_ctx *ctx, uint8_t *dst, size_t n, int where);
+
+/* Statistics of the last grow, including member counts of the last reads. */
+int mf4d_last_stats(mf4d_ctx *ctx, mf4d_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MF4D_H */

@@ -1,0 +1,159 @@
+"""Thin Python wrapper of the mf4d C ABI: one object per library context.
+
+Arrays are numpy arrays (host memory, MF4D_HOST) or torch tensors on the GPU
+(device memory, MF4D_DEVICE).  Torch supplies device memory and the stream;
+the library does all of the work.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import MF4D_DEVICE, MF4D_HOST, MF4DError, Stats  # noqa: F401
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _is_device_tensor(a) -> bool:
+    return hasattr(a, "is_cuda") and a.is_cuda
+
+
+def _arg(a, dtype):
+    """(pointer, where, keep-alive) for a numpy array or a device tensor."""
+    if _is_device_tensor(a):
+        torch = _torch()
+        want = {np.float32: torch.float32, np.int32: torch.int32, np.uint32: torch.int32,
+                np.uint8: torch.uint8}[dtype]
+        if a.dtype != want and not (dtype is np.uint32 and a.dtype in (torch.int32,)):
+            raise TypeError(f"tensor dtype {a.dtype}, expected {want}")
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return ctypes.c_void_p(a.data_ptr()), MF4D_DEVICE, a
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    return arr.ctypes.data_as(ctypes.c_void_p), MF4D_HOST, arr
+
+
+class Grower:
+    """A library context on one GPU, ordering its work on one HIP stream."""
+
+    def __init__(self, device: int = 0, stream=None, tile_t: int | None = None):
+        self.lib = _lib.load_library()
+        if stream is None:
+            torch = _torch()
+            stream = torch.cuda.current_stream(device).cuda_stream
+        self.ctx = ctypes.c_void_p()
+        self._check(self.lib.mf4d_create(ctypes.byref(self.ctx), device, ctypes.c_void_p(stream)))
+        self.device = device
+        self.dims = None
+        self.T = None
+        self.P = 0
+        if tile_t is not None:
+            self._check(self.lib.mf4d_set_tile(self.ctx, tile_t))
+
+    def _check(self, rc):
+        return _lib.check(rc, self.lib)
+
+    def close(self):
+        if self.ctx:
+            self.lib.mf4d_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- inputs -----------------------------------------------------------
+    def load_field(self, field):
+        T, Z, Y, X = field.shape
+        p, where, keep = _arg(field, np.float32)
+        self._check(self.lib.mf4d_load_field(self.ctx, p, X, Y, Z, T, where))
+        self.dims, self.T, self.P = (X, Y, Z), T, 0
+        del keep
+
+    def load_particles(self, xyz, attr):
+        T, P = attr.shape[0], attr.shape[1]
+        if tuple(xyz.shape) != (T, P, 3):
+            raise ValueError("xyz must be [T][P][3] matching attr [T][P]")
+        px, wx, kx = _arg(xyz, np.float32)
+        pa, wa, ka = _arg(attr, np.float32)
+        if wx != wa:
+            raise ValueError("xyz and attr must both live on the host or both on the device")
+        self._check(self.lib.mf4d_load_particles(self.ctx, px, pa, P, T, wx))
+        self.P = P
+        del kx, ka
+
+    def set_criteria(self, f_lo, f_hi=np.inf, a_lo=-np.inf, a_hi=np.inf):
+        self._check(self.lib.mf4d_set_criteria(self.ctx, float(np.float32(f_lo)),
+                                               float(np.float32(f_hi)), float(np.float32(a_lo)),
+                                               float(np.float32(a_hi))))
+
+    def set_seeds(self, seeds):
+        n = int(seeds.shape[0]) if len(seeds.shape) else 0
+        p, where, keep = _arg(seeds, np.int32)
+        self._check(self.lib.mf4d_set_seeds(self.ctx, p, n, where))
+        del keep
+
+    def set_max_rounds(self, cap: int):
+        self._check(self.lib.mf4d_set_max_rounds(self.ctx, int(cap)))
+
+    # -- growth -----------------------------------------------------------
+    def grow(self) -> dict:
+        st = Stats()
+        self._check(self.lib.mf4d_grow(self.ctx, ctypes.byref(st)))
+        return st.as_dict()
+
+    def grow_resume(self) -> dict:
+        st = Stats()
+        self._check(self.lib.mf4d_grow_resume(self.ctx, ctypes.byref(st)))
+        return st.as_dict()
+
+    def stats(self) -> dict:
+        st = Stats()
+        self._check(self.lib.mf4d_last_stats(self.ctx, ctypes.byref(st)))
+        return st.as_dict()
+
+    # -- outputs ----------------------------------------------------------
+    def field_words(self) -> int:
+        X, Y, Z = self.dims
+        return (X * Y * Z * self.T + 31) // 32
+
+    def read_field_mask(self, out=None):
+        """uint32 canonical bit words.  `out` may be a device tensor (int32)."""
+        n = self.field_words()
+        if out is None:
+            out = np.zeros(n, np.uint32)
+        if _is_device_tensor(out):
+            if out.numel() < n:
+                raise ValueError("out too small")
+            self._check(self.lib.mf4d_read_field_mask(self.ctx, ctypes.c_void_p(out.data_ptr()),
+                                                      out.numel(), MF4D_DEVICE))
+        else:
+            self._check(self.lib.mf4d_read_field_mask(
+                self.ctx, out.ctypes.data_as(ctypes.c_void_p), out.size, MF4D_HOST))
+        return out
+
+    def read_particle_mask(self, out=None):
+        """uint8 [T][P].  `out` may be a device tensor (uint8)."""
+        n = self.T * self.P
+        if out is None:
+            out = np.zeros((self.T, self.P), np.uint8)
+        if _is_device_tensor(out):
+            self._check(self.lib.mf4d_read_particle_mask(
+                self.ctx, ctypes.c_void_p(out.data_ptr()), out.numel(), MF4D_DEVICE))
+        else:
+            self._check(self.lib.mf4d_read_particle_mask(
+                self.ctx, out.ctypes.data_as(ctypes.c_void_p), n, MF4D_HOST))
+        return out

@@ -1,0 +1,51 @@
+"""The C ABI library: it loads and exports every function include/mf4d.h
+declares (no compute calls; this runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1903_12294_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(mf4d_[a-z_0-9]+)\s*\(", src))
+    return names
+
+
+def test_library_is_built():
+    assert os.path.exists(_lib.LIB_PATH), "run __graft_entry__.build() first"
+
+
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    declared = _declared()
+    assert len(declared) >= 15
+    missing = [n for n in sorted(declared) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_header():
+    assert _declared() == set(_lib.SIGNATURES)
+
+
+def test_version_and_error_without_gpu():
+    lib = _lib.load_library()
+    assert lib.mf4d_version().startswith(b"mf4d")
+    # NULL context arguments are rejected before any device call
+    assert lib.mf4d_set_max_rounds(None, 1) == _lib.MF4D_ERR_ARG
+    assert b"NULL" in lib.mf4d_last_error()
+    assert lib.mf4d_grow(None, None) == _lib.MF4D_ERR_ARG
+
+
+def test_missing_library_raises(tmp_path):
+    with pytest.raises(_lib.LibraryMissing):
+        _lib.load_library(str(tmp_path / "nope.so"))
