@@ -73,8 +73,15 @@ enum {
 
 enum { MF4D_HOST = 0, MF4D_DEVICE = 1 };
 
+/* How the rounds of a grow are scheduled (both give the same result). */
+enum {
+    MF4D_SCHED_PERSISTENT = 0, /* one cooperative kernel runs every round (default) */
+    MF4D_SCHED_LAUNCH = 1      /* three kernel launches per round */
+};
+
 typedef struct mf4d_stats {
-    int64_t rounds;           /* global rounds, counting the last one that found no work */
+    int64_t rounds;           /* rounds run: each sweeps its work list, pulls, closes and pushes;
+                                 the grow stops when the next round's work list is empty */
     int64_t tile_visits;      /* tile sweeps executed over all rounds */
     int64_t particle_visits;  /* particle closures executed over all rounds */
     int64_t members_field;    /* |M ∩ voxel-steps| (filled by mf4d_read_field_mask) */
@@ -131,6 +138,12 @@ int mf4d_set_criteria(mf4d_ctx *ctx, float f_lo, float f_hi, float a_lo, float a
  * grid; nothing changes), MF4D_ERR_ARG. */
 int mf4d_set_seeds(mf4d_ctx *ctx, const int32_t *xyzt, int64_t S, int where);
 
+/* Round scheduling, MF4D_SCHED_PERSISTENT or MF4D_SCHED_LAUNCH.  The
+ * environment variable MF4D_SCHED=launch selects the latter at creation.  A
+ * persistent launch that the device cannot hold co-resident falls back to
+ * launches.  Errors: MF4D_ERR_ARG (unknown mode). */
+int mf4d_set_schedule(mf4d_ctx *ctx, int mode);
+
 /* Cap on rounds per mf4d_grow / mf4d_grow_resume call (0 = no cap). */
 int mf4d_set_max_rounds(mf4d_ctx *ctx, int64_t cap);
 
@@ -156,6 +169,25 @@ int mf4d_read_field_mask(mf4d_ctx *ctx, uint32_t *dst, size_t nwords, int where)
  * which holds n >= T*P bytes.
  * Errors: MF4D_ERR_STATE (nothing grown or no particles), MF4D_ERR_ARG. */
 int mf4d_read_particle_mask(mf4d_ctx *ctx, uint8_t *dst, size_t n, int where);
+
+/* Batched queries (up to 256, each with its own criteria and seeds), grown
+ * together as the bit-planes of one 256-bit label per node.  crit fp32
+ * [Q][4] = (f_lo, f_hi, a_lo, a_hi) per query; seeds int32 [S][5] =
+ * (x, y, z, t, q).  Every query means the same as a single grow with its own
+ * criteria and seeds.
+ * Errors: MF4D_ERR_STATE (no field), MF4D_ERR_ARG (Q not in 1..256, a NaN
+ * bound), MF4D_ERR_RANGE (a seed outside the grid or naming q >= Q). */
+int mf4d_set_queries(mf4d_ctx *ctx, int Q, const float *crit, const int32_t *qxyzt, int64_t S,
+                     int where);
+
+/* Grow every query and write the results: fplanes uint32 [X*Y*Z*T][8] in
+ * canonical voxel order, query q in bit (q & 31) of word (q >> 5); pplanes
+ * uint32 [T][P][8] likewise (NULL allowed when no particles are loaded).
+ * Planes q >= Q are zero.  Device outputs are grown in place.
+ * Errors: MF4D_ERR_STATE (no field or no queries), MF4D_ERR_ARG (buffers
+ * too small), MF4D_ERR_OOM, MF4D_ERR_HIP. */
+int mf4d_grow_batched(mf4d_ctx *ctx, uint32_t *fplanes, size_t fwords, uint32_t *pplanes,
+                      size_t pwords, int where, mf4d_stats *out);
 
 /* Statistics of the last grow, including member counts of the last reads. */
 int mf4d_last_stats(mf4d_ctx *ctx, mf4d_stats *out);

@@ -22,6 +22,8 @@ MF4D_ERR_NOT_CONVERGED = -6
 MF4D_ERR_UNSUPPORTED = -7
 MF4D_HOST = 0
 MF4D_DEVICE = 1
+MF4D_SCHED_PERSISTENT = 0
+MF4D_SCHED_LAUNCH = 1
 
 ERROR_NAMES = {
     MF4D_ERR_ARG: "ARG", MF4D_ERR_RANGE: "RANGE", MF4D_ERR_OOM: "OOM", MF4D_ERR_HIP: "HIP",
@@ -60,12 +62,16 @@ SIGNATURES = {
     "mf4d_load_particles": (c_int, [c_void_p, c_void_p, c_void_p, c_int64, c_int, c_int]),
     "mf4d_set_criteria": (c_int, [c_void_p, c_float, c_float, c_float, c_float]),
     "mf4d_set_seeds": (c_int, [c_void_p, c_void_p, c_int64, c_int]),
+    "mf4d_set_schedule": (c_int, [c_void_p, c_int]),
     "mf4d_set_max_rounds": (c_int, [c_void_p, c_int64]),
     "mf4d_grow": (c_int, [c_void_p, POINTER(Stats)]),
     "mf4d_grow_resume": (c_int, [c_void_p, POINTER(Stats)]),
     "mf4d_read_field_mask": (c_int, [c_void_p, c_void_p, c_size_t, c_int]),
     "mf4d_read_particle_mask": (c_int, [c_void_p, c_void_p, c_size_t, c_int]),
     "mf4d_last_stats": (c_int, [c_void_p, POINTER(Stats)]),
+    "mf4d_set_queries": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_int64, c_int]),
+    "mf4d_grow_batched": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, c_int,
+                                  POINTER(Stats)]),
 }
 
 

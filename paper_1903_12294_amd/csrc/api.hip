@@ -4,12 +4,17 @@
 
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <new>
 #include <string>
 
 #include "mf4d_internal.h"
+#include "batched.h"
+
+#include <algorithm>
+#include <vector>
 
 using namespace mf4d;
 
@@ -67,6 +72,7 @@ struct mf4d_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     int bt = 8;
+    int schedule = MF4D_SCHED_PERSISTENT;
 
     bool has_field = false;
     Geom g{};
@@ -74,7 +80,8 @@ struct mf4d_ctx {
     uint32_t* Af = nullptr;
     uint32_t* Lf = nullptr;
     uint8_t* active = nullptr;
-    uint8_t* dirty = nullptr;
+    uint32_t* dirty = nullptr;
+    uint8_t* chg = nullptr;
     uint32_t* work = nullptr;
 
     bool has_particles = false;
@@ -83,12 +90,13 @@ struct mf4d_ctx {
     float* attr_t = nullptr;
     unsigned long long* Ap = nullptr;
     unsigned long long* Lp = nullptr;
-    uint2* pend[2] = {nullptr, nullptr};
+    uint2* clist = nullptr;
     uint32_t* pdirty = nullptr;
     uint32_t* dlist = nullptr;
 
     uint32_t* counters = nullptr;
     unsigned long long* stat64 = nullptr;
+    uint32_t* bar = nullptr;
     uint32_t* h_counters = nullptr;
     unsigned long long* h_stat = nullptr;
 
@@ -101,13 +109,25 @@ struct mf4d_ctx {
 
     // grow state: 0 nothing grown, 1 converged, 2 stopped by the round cap
     int state = 0;
-    int cur = 0;
-    uint32_t last_npend = 0;
+    uint32_t round = 0;  // index of the next round to run
     mf4d_stats stats{};
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 
     void* staging = nullptr;
     size_t staging_bytes = 0;
+
+    // batched queries
+    int Q = 0;
+    float* btab = nullptr;
+    int32_t* qseeds = nullptr;
+    int64_t QS = 0, qseeds_cap = 0;
+    uint32_t NTB = 0;
+    int NXb = 0, NYb = 0, NZb = 0, NTb = 0;
+    uint8_t* b_active = nullptr;
+    uint32_t* b_dirty = nullptr;
+    uint8_t* b_chg = nullptr;
+    uint32_t* b_work = nullptr;
+    uint32_t* b_counters = nullptr;
 };
 
 namespace {
@@ -119,6 +139,12 @@ void free_field(mf4d_ctx* c) {
     dev_free(c->active);
     dev_free(c->dirty);
     dev_free(c->work);
+    dev_free(c->chg);
+    dev_free(c->b_active);
+    dev_free(c->b_dirty);
+    dev_free(c->b_chg);
+    dev_free(c->b_work);
+    c->NTB = 0;
     c->has_field = false;
 }
 
@@ -127,8 +153,7 @@ void free_particles(mf4d_ctx* c) {
     dev_free(c->attr_t);
     dev_free(c->Ap);
     dev_free(c->Lp);
-    dev_free(c->pend[0]);
-    dev_free(c->pend[1]);
+    dev_free(c->clist);
     dev_free(c->pdirty);
     dev_free(c->dlist);
     c->has_particles = false;
@@ -160,44 +185,69 @@ int read_counters(mf4d_ctx* c) {
     return sync(c);
 }
 
-// The round loop: compact the dirty tiles into a work list; stop when it is
-// empty; else sweep those tiles, then pull particle-steps whose voxel joined,
-// close the trajectories of particles that gained steps and push their voxels.
-int run_rounds(mf4d_ctx* c, int64_t* rounds_done) {
+Dev make_dev(mf4d_ctx* c) {
+    Dev d{};
+    d.g = c->g;
+    d.pg = c->pg;
+    d.field = c->field;
+    d.Af = c->Af;
+    d.Lf = c->Lf;
+    d.active = c->active;
+    d.dirty = c->dirty;
+    d.chg = c->chg;
+    d.work = c->work;
+    d.bins = c->bins;
+    d.attr_t = c->attr_t;
+    d.Ap = c->Ap;
+    d.Lp = c->Lp;
+    d.clist = c->clist;
+    d.pdirty = c->pdirty;
+    d.dlist = c->dlist;
+    d.counters = c->counters;
+    d.stat64 = c->stat64;
+    d.bar = c->bar;
+    for (int i = 0; i < 4; ++i) d.crit[i] = c->crit[i];
+    return d;
+}
+
+// Rounds until a round's work list is empty (converged) or the cap is hit.
+// Persistent: one cooperative launch runs every round; if it cannot be
+// launched, or a grid barrier timed out, the rounds run as launches instead.
+int run_rounds(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
+    const uint32_t cap = (uint32_t)(c->max_rounds > 0 ? c->max_rounds : 0);
+    const uint32_t r0 = c->round;
+    if (c->schedule == MF4D_SCHED_PERSISTENT) {
+        launch_fill_u32(c->counters + C_ERR, 0, 2, c->stream);  // C_ERR, C_ROUNDS
+        launch_fill_u32(c->bar, 0, 4, c->stream);
+        if (launch_rounds_persistent(d, r0, cap, c->device, c->stream)) {
+            int rc = read_counters(c);
+            if (rc) return rc;
+            if (c->h_counters[C_ERR] == 0) {
+                const uint32_t done = c->h_counters[C_ROUNDS];
+                c->round = r0 + done;
+                *rounds_done = done;
+                c->state = c->h_counters[C_NWORK0 + (c->round & 1)] == 0 ? 1 : 2;
+                return MF4D_OK;
+            }
+            return fail(MF4D_ERR_HIP, "persistent rounds: a grid barrier timed out");
+        }
+        (void)hipGetLastError();
+    }
     int64_t r = 0;
-    const bool parts = c->has_particles;
     while (true) {
-        launch_fill_u32(c->counters + C_NWORK, 0, 1, c->stream);
-        launch_compact_tiles(c->g, c->dirty, c->work, c->counters + C_NWORK, c->stream);
         int rc = read_counters(c);
         if (rc) return rc;
-        const uint32_t nwork = c->h_counters[C_NWORK];
+        const uint32_t nwork = c->h_counters[C_NWORK0 + (c->round & 1)];
         if (nwork == 0) {
             c->state = 1;
             break;
         }
-        if (c->max_rounds > 0 && r >= c->max_rounds) {
-            // keep the work list for a resume: its tiles go back to dirty
-            launch_mark_work(c->work, c->counters + C_NWORK, nwork, c->dirty, c->stream);
+        if (cap && r >= cap) {
             c->state = 2;
             break;
         }
-        launch_sweep(c->g, c->Af, c->Lf, c->active, c->work, c->counters + C_NWORK, nwork, c->dirty,
-                     c->stat64 + S_TILE_VISITS, c->stream);
-        if (parts) {
-            const int nx = 1 - c->cur;
-            const uint32_t npend = c->h_counters[C_PEND0 + c->cur];
-            launch_fill_u32(c->counters + C_PEND0 + nx, 0, 1, c->stream);
-            launch_fill_u32(c->counters + C_NDIRTYP, 0, 1, c->stream);
-            launch_pull(c->pg, c->pend[c->cur], c->counters + C_PEND0 + c->cur, npend, c->pend[nx],
-                        c->counters + C_PEND0 + nx, c->Lf, c->Lp, c->pdirty, c->dlist,
-                        c->counters + C_NDIRTYP, c->stream);
-            launch_close_push(c->g, c->pg, c->dlist, c->counters + C_NDIRTYP,
-                              (uint32_t)(c->pg.P < (1 << 20) ? c->pg.P : (1 << 20)), c->Ap, c->Lp,
-                              c->pdirty, c->bins, c->Af, c->Lf, c->active, c->dirty,
-                              c->stat64 + S_PART_VISITS, c->stream);
-            c->cur = nx;
-        }
+        launch_round(d, c->round, nwork, c->stream);
+        ++c->round;
         ++r;
     }
     *rounds_done = r;
@@ -260,6 +310,11 @@ int mf4d_create(mf4d_ctx** out, int device, void* hip_stream) {
     c->stream = (hipStream_t)hip_stream;
     int rc = dev_alloc(&c->counters, C_NCOUNTERS);
     if (!rc) rc = dev_alloc(&c->stat64, S_NSTAT);
+    if (!rc) rc = dev_alloc(&c->bar, 64);
+    if (!rc) {
+        const char* env = getenv("MF4D_SCHED");
+        if (env && strcmp(env, "launch") == 0) c->schedule = MF4D_SCHED_LAUNCH;
+    }
     if (!rc && hipHostMalloc((void**)&c->h_counters, C_NCOUNTERS * sizeof(uint32_t)) != hipSuccess)
         rc = fail(MF4D_ERR_OOM, "pinned host allocation failed");
     if (!rc && hipHostMalloc((void**)&c->h_stat, S_NSTAT * sizeof(unsigned long long)) != hipSuccess)
@@ -283,7 +338,11 @@ void mf4d_destroy(mf4d_ctx* c) {
     free_particles(c);
     dev_free(c->counters);
     dev_free(c->stat64);
+    dev_free(c->bar);
     dev_free(c->seeds);
+    dev_free(c->btab);
+    dev_free(c->qseeds);
+    dev_free(c->b_counters);
     if (c->staging) (void)hipFree(c->staging);
     if (c->h_counters) (void)hipHostFree(c->h_counters);
     if (c->h_stat) (void)hipHostFree(c->h_stat);
@@ -316,6 +375,8 @@ int mf4d_load_field(mf4d_ctx* c, const float* field, int X, int Y, int Z, int T,
     const uint64_t nt = (uint64_t)g.NXt * g.NYt * g.NZt * g.NTt;
     g.WPT = 64u * g.BT;
     g.nwords = nt * g.WPT;
+    if (g.NZt > 65535 || T > 65535)
+        return fail(MF4D_ERR_UNSUPPORTED, "Z/8 and T must stay within a 65535 grid dimension");
     if (g.nwords * 32ull >= (1ull << 32) || (uint64_t)X * Y * Z * T >= (1ull << 32) - 1)
         return fail(MF4D_ERR_UNSUPPORTED, "grid of %llu voxel-steps (padded %llu) needs >= 2^32 bits",
                     (unsigned long long)X * Y * Z * T, (unsigned long long)g.nwords * 32ull);
@@ -328,9 +389,10 @@ int mf4d_load_field(mf4d_ctx* c, const float* field, int X, int Y, int Z, int T,
     int rc = dev_alloc(&c->field, V);
     if (!rc) rc = dev_alloc(&c->Af, g.nwords);
     if (!rc) rc = dev_alloc(&c->Lf, g.nwords);
-    if (!rc) rc = dev_alloc(&c->active, (size_t)g.NT + 4);
-    if (!rc) rc = dev_alloc(&c->dirty, (size_t)g.NT + 4);
-    if (!rc) rc = dev_alloc(&c->work, g.NT);
+    if (!rc) rc = dev_alloc(&c->active, (size_t)g.NT + 8);
+    if (!rc) rc = dev_alloc(&c->dirty, 2 * (size_t)g.NT);
+    if (!rc) rc = dev_alloc(&c->chg, 2 * (size_t)g.NT + 8);
+    if (!rc) rc = dev_alloc(&c->work, 2 * (size_t)g.NT);
     if (rc) {
         free_field(c);
         return rc;
@@ -382,8 +444,7 @@ int mf4d_load_particles(mf4d_ctx* c, const float* xyz, const float* attr, int64_
     if (!rc) rc = dev_alloc(&c->attr_t, Q);
     if (!rc) rc = dev_alloc(&c->Ap, (size_t)P * pg.W);
     if (!rc) rc = dev_alloc(&c->Lp, (size_t)P * pg.W);
-    if (!rc) rc = dev_alloc(&c->pend[0], Q);
-    if (!rc) rc = dev_alloc(&c->pend[1], Q);
+    if (!rc) rc = dev_alloc(&c->clist, Q);
     if (!rc) rc = dev_alloc(&c->pdirty, (size_t)(P + 31) / 32);
     if (!rc) rc = dev_alloc(&c->dlist, (size_t)P);
     if (rc) {
@@ -497,35 +558,32 @@ int mf4d_set_max_rounds(mf4d_ctx* c, int64_t cap) {
     return MF4D_OK;
 }
 
+int mf4d_set_schedule(mf4d_ctx* c, int mode) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    if (mode != MF4D_SCHED_PERSISTENT && mode != MF4D_SCHED_LAUNCH)
+        return fail(MF4D_ERR_ARG, "unknown schedule %d", mode);
+    c->schedule = mode;
+    return MF4D_OK;
+}
+
 int mf4d_grow(mf4d_ctx* c, mf4d_stats* out) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
     if (!c->has_field) return fail(MF4D_ERR_STATE, "no field loaded");
     if (!c->has_crit) return fail(MF4D_ERR_STATE, "no criteria set");
     HIP_TRY(hipSetDevice(c->device));
-    const Geom& g = c->g;
     hipStream_t s = c->stream;
+    const Dev d = make_dev(c);
     c->state = 0;
-    launch_fill_u32(c->Lf, 0, g.nwords, s);
-    launch_fill_u32((uint32_t*)c->active, 0, (g.NT + 3) / 4, s);
-    launch_fill_u32((uint32_t*)c->dirty, 0, (g.NT + 3) / 4, s);
-    launch_fill_u32(c->counters, 0, C_NCOUNTERS, s);
-    launch_fill_u32((uint32_t*)c->stat64, 0, S_NSTAT * 2, s);
-    if (c->has_particles) {
-        launch_fill_u32((uint32_t*)c->Lp, 0, (uint64_t)c->pg.P * c->pg.W * 2, s);
-        launch_fill_u32(c->pdirty, 0, (uint64_t)(c->pg.P + 31) / 32, s);
-    }
+    c->round = 0;
+    launch_reset(d, s);
     HIP_TRY(hipEventRecord(c->ev[0], s));
-    launch_admit_field(g, c->field, c->crit[0], c->crit[1], c->Af, c->active, s);
+    launch_admit_field(d, s);
     HIP_TRY(hipEventRecord(c->ev[1], s));
-    if (c->has_particles)
-        launch_admit_particles(c->pg, c->attr_t, c->bins, c->crit[2], c->crit[3], c->Ap, c->pend[0],
-                               c->counters + C_PEND0, s);
+    launch_admit_particles(d, s);
     HIP_TRY(hipEventRecord(c->ev[2], s));
-    launch_count_active(g, c->active, c->stat64 + S_ACTIVE_TILES, s);
-    launch_seeds(g, c->seeds, c->S, c->Af, c->Lf, c->active, c->dirty, c->counters + C_DROPPED, s);
-    c->cur = 0;
+    launch_seeds(d, c->seeds, c->S, s);
     int64_t rounds = 0;
-    int rc = run_rounds(c, &rounds);
+    int rc = run_rounds(c, d, &rounds);
     if (rc) return rc;
     HIP_TRY(hipEventRecord(c->ev[3], s));
     rc = finish_stats(c, out, true, rounds);
@@ -538,10 +596,10 @@ int mf4d_grow_resume(mf4d_ctx* c, mf4d_stats* out) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
     if (c->state != 2) return fail(MF4D_ERR_STATE, "nothing to resume");
     HIP_TRY(hipSetDevice(c->device));
+    const Dev d = make_dev(c);
     HIP_TRY(hipEventRecord(c->ev[2], c->stream));
-    int rc = MF4D_OK;
     int64_t rounds = 0;
-    rc = run_rounds(c, &rounds);
+    int rc = run_rounds(c, d, &rounds);
     if (rc) return rc;
     HIP_TRY(hipEventRecord(c->ev[3], c->stream));
     rc = finish_stats(c, out, false, rounds);
@@ -567,7 +625,7 @@ int mf4d_read_field_mask(mf4d_ctx* c, uint32_t* dst, size_t nwords, int where) {
         out = (uint32_t*)st;
     }
     launch_fill_u32((uint32_t*)(c->stat64 + S_MEMBERS_F), 0, 2, c->stream);
-    launch_read_field(c->g, c->Lf, out, c->stat64 + S_MEMBERS_F, c->stream);
+    launch_read_field(make_dev(c), out, c->stream);
     if (where == MF4D_HOST)
         HIP_TRY(hipMemcpyAsync(dst, out, need * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(c->h_stat + S_MEMBERS_F, c->stat64 + S_MEMBERS_F,
@@ -595,7 +653,7 @@ int mf4d_read_particle_mask(mf4d_ctx* c, uint8_t* dst, size_t n, int where) {
         out = (uint8_t*)st;
     }
     launch_fill_u32((uint32_t*)(c->stat64 + S_MEMBERS_P), 0, 2, c->stream);
-    launch_read_particles(c->pg, c->Lp, out, c->stat64 + S_MEMBERS_P, c->stream);
+    launch_read_particles(make_dev(c), out, c->stream);
     if (where == MF4D_HOST)
         HIP_TRY(hipMemcpyAsync(dst, out, need, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(c->h_stat + S_MEMBERS_P, c->stat64 + S_MEMBERS_P,
@@ -603,6 +661,184 @@ int mf4d_read_particle_mask(mf4d_ctx* c, uint8_t* dst, size_t n, int where) {
     int rc = sync(c);
     if (rc) return rc;
     c->stats.members_particle = (int64_t)c->h_stat[S_MEMBERS_P];
+    return MF4D_OK;
+}
+
+int mf4d_set_queries(mf4d_ctx* c, int Q, const float* crit, const int32_t* qxyzt, int64_t S,
+                     int where) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    if (!c->has_field) return fail(MF4D_ERR_STATE, "load the field before the queries");
+    if (Q < 1 || Q > 256) return fail(MF4D_ERR_ARG, "Q = %d not in 1..256", Q);
+    if (!crit || S < 0 || (S > 0 && !qxyzt)) return fail(MF4D_ERR_ARG, "bad query arrays");
+    if (where != MF4D_HOST && where != MF4D_DEVICE) return fail(MF4D_ERR_ARG, "bad where");
+    if (S > (1ll << 30)) return fail(MF4D_ERR_UNSUPPORTED, "too many seeds");
+    HIP_TRY(hipSetDevice(c->device));
+    std::vector<float> cr((size_t)Q * 4);
+    std::vector<int32_t> sd((size_t)S * 5);
+    const hipMemcpyKind k = where == MF4D_HOST ? hipMemcpyHostToHost : hipMemcpyDeviceToHost;
+    HIP_TRY(hipMemcpy(cr.data(), crit, cr.size() * sizeof(float), k));
+    if (S > 0) HIP_TRY(hipMemcpy(sd.data(), qxyzt, sd.size() * sizeof(int32_t), k));
+    for (float v : cr)
+        if (v != v) return fail(MF4D_ERR_ARG, "a query bound is NaN");
+    for (int64_t i = 0; i < S; ++i) {
+        const int32_t* q = &sd[i * 5];
+        if (q[0] < 0 || q[0] >= c->g.X || q[1] < 0 || q[1] >= c->g.Y || q[2] < 0 ||
+            q[2] >= c->g.Z || q[3] < 0 || q[3] >= c->g.T)
+            return fail(MF4D_ERR_RANGE, "query seed %lld outside the grid", (long long)i);
+        if (q[4] < 0 || q[4] >= Q)
+            return fail(MF4D_ERR_RANGE, "query seed %lld names query %d of %d", (long long)i, q[4], Q);
+    }
+    // sorted bounds and prefix masks: {q : lo_q <= v} is a prefix of the
+    // ascending order of lo, {q : hi_q >= v} a prefix of the descending order
+    std::vector<float> tab(kTabWords, 0.0f);
+    uint32_t* masks = reinterpret_cast<uint32_t*>(tab.data() + 1024);
+    for (int type = 0; type < 2; ++type) {
+        for (int side = 0; side < 2; ++side) {
+            std::vector<int> order(Q);
+            for (int q = 0; q < Q; ++q) order[q] = q;
+            const int col = type * 2 + side;
+            if (side == 0)
+                std::stable_sort(order.begin(), order.end(),
+                                 [&](int a, int b) { return cr[a * 4 + col] < cr[b * 4 + col]; });
+            else
+                std::stable_sort(order.begin(), order.end(),
+                                 [&](int a, int b) { return cr[a * 4 + col] > cr[b * 4 + col]; });
+            float* sorted = tab.data() + 256 * col;
+            uint32_t* m = masks + col * 257 * 8;
+            for (int i = 0; i < Q; ++i) sorted[i] = cr[order[i] * 4 + col];
+            for (int i = 0; i < Q; ++i) {
+                for (int w = 0; w < 8; ++w) m[(i + 1) * 8 + w] = m[i * 8 + w];
+                m[(i + 1) * 8 + (order[i] >> 5)] |= 1u << (order[i] & 31);
+            }
+        }
+    }
+    if (!c->btab) {
+        int rc = dev_alloc(&c->btab, (size_t)kTabWords);
+        if (rc) return rc;
+    }
+    if (S > c->qseeds_cap) {
+        int32_t* ns = nullptr;
+        int rc = dev_alloc(&ns, (size_t)S * 5);
+        if (rc) return rc;
+        dev_free(c->qseeds);
+        c->qseeds = ns;
+        c->qseeds_cap = S;
+    }
+    HIP_TRY(hipMemcpy(c->btab, tab.data(), kTabWords * sizeof(float), hipMemcpyHostToDevice));
+    if (S > 0)
+        HIP_TRY(hipMemcpy(c->qseeds, sd.data(), sd.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    c->Q = Q;
+    c->QS = S;
+    return MF4D_OK;
+}
+
+int mf4d_grow_batched(mf4d_ctx* c, uint32_t* fplanes, size_t fwords, uint32_t* pplanes,
+                      size_t pwords, int where, mf4d_stats* out) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    if (!c->has_field) return fail(MF4D_ERR_STATE, "no field loaded");
+    if (c->Q == 0) return fail(MF4D_ERR_STATE, "no queries set");
+    if (where != MF4D_HOST && where != MF4D_DEVICE) return fail(MF4D_ERR_ARG, "bad where");
+    const Geom& g = c->g;
+    const uint64_t V = (uint64_t)g.X * g.Y * g.Z * g.T;
+    const uint64_t P = c->has_particles ? (uint64_t)c->pg.P : 0;
+    if (!fplanes || fwords < 8 * V) return fail(MF4D_ERR_ARG, "field planes need %llu words", (unsigned long long)(8 * V));
+    if (P > 0 && (!pplanes || pwords < 8 * P * g.T))
+        return fail(MF4D_ERR_ARG, "particle planes need %llu words", (unsigned long long)(8 * P * g.T));
+    if ((reinterpret_cast<uintptr_t>(fplanes) & 15) || (reinterpret_cast<uintptr_t>(pplanes) & 15))
+        return fail(MF4D_ERR_ARG, "plane buffers must be 16-byte aligned");
+    HIP_TRY(hipSetDevice(c->device));
+    if (c->NTB == 0) {
+        const int NXb = (g.X + 7) / 8, NYb = (g.Y + 3) / 4, NZb = (g.Z + 3) / 4, NTb = (g.T + 3) / 4;
+        const uint64_t ntb = (uint64_t)NXb * NYb * NZb * NTb;
+        int rc = dev_alloc(&c->b_active, (size_t)ntb + 8);
+        if (!rc) rc = dev_alloc(&c->b_dirty, 2 * (size_t)ntb);
+        if (!rc) rc = dev_alloc(&c->b_chg, 2 * (size_t)ntb + 8);
+        if (!rc) rc = dev_alloc(&c->b_work, 2 * (size_t)ntb);
+        if (!rc && !c->b_counters) rc = dev_alloc(&c->b_counters, BC_NCOUNTERS);
+        if (rc) {
+            dev_free(c->b_active);
+            dev_free(c->b_dirty);
+            dev_free(c->b_chg);
+            dev_free(c->b_work);
+            return rc;
+        }
+        c->NXb = NXb; c->NYb = NYb; c->NZb = NZb; c->NTb = NTb;
+        c->NTB = (uint32_t)ntb;
+    }
+    uint32_t* fo = fplanes;
+    uint32_t* po = pplanes;
+    if (where == MF4D_HOST) {
+        void* st = nullptr;
+        int rc = staging_for(c, (size_t)(8 * V + 8 * P * g.T) * sizeof(uint32_t), &st);
+        if (rc) return rc;
+        fo = (uint32_t*)st;
+        po = fo + 8 * V;
+    }
+    DevB d{};
+    d.g = g;
+    d.X = g.X; d.Y = g.Y; d.Z = g.Z; d.T = g.T;
+    d.NXb = c->NXb; d.NYb = c->NYb; d.NZb = c->NZb; d.NTb = c->NTb;
+    d.NTB = c->NTB;
+    d.Q = c->Q;
+    d.P = (int64_t)P;
+    d.Tpad = c->has_particles ? c->pg.Tpad : 1;
+    d.field = c->field;
+    d.attr_t = c->attr_t;
+    d.bins = c->bins;
+    d.fplanes = fo;
+    d.pplanes = P > 0 ? po : nullptr;
+    d.tab = c->btab;
+    d.active = c->b_active;
+    d.dirty = c->b_dirty;
+    d.chg = c->b_chg;
+    d.work = c->b_work;
+    d.clist = c->clist;
+    d.pdirty = c->pdirty;
+    d.dlist = c->dlist;
+    d.counters = c->b_counters;
+    d.stat64 = c->stat64;
+    hipStream_t s = c->stream;
+    HIP_TRY(hipEventRecord(c->ev[0], s));
+    launch_b_prepare(d, c->qseeds, c->QS, s);
+    HIP_TRY(hipEventRecord(c->ev[1], s));
+    uint32_t r = 0;
+    while (true) {
+        HIP_TRY(hipMemcpyAsync(c->h_counters, c->b_counters, BC_NCOUNTERS * sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, s));
+        int rc = sync(c);
+        if (rc) return rc;
+        const uint32_t nwork = c->h_counters[BC_NWORK0 + (r & 1)];
+        if (nwork == 0) break;
+        launch_b_round(d, r, nwork, s);
+        ++r;
+    }
+    HIP_TRY(hipEventRecord(c->ev[3], s));
+    HIP_TRY(hipMemcpyAsync(c->h_stat, c->stat64, S_NSTAT * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, s));
+    int rc = sync(c);
+    if (rc) return rc;
+    mf4d_stats st{};
+    st.rounds = r;
+    st.tile_visits = (int64_t)c->h_stat[S_TILE_VISITS];
+    st.particle_visits = (int64_t)c->h_stat[S_PART_VISITS];
+    st.seeds_dropped = (int64_t)c->h_counters[BC_DROPPED];
+    st.members_field = -1;
+    st.members_particle = -1;
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+    st.ms_admit = ms;
+    HIP_TRY(hipEventElapsedTime(&ms, c->ev[1], c->ev[3]));
+    st.ms_rounds = ms;
+    HIP_TRY(hipEventElapsedTime(&ms, c->ev[0], c->ev[3]));
+    st.ms_total = ms;
+    if (where == MF4D_HOST) {
+        HIP_TRY(hipMemcpyAsync(fplanes, fo, 8 * V * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        if (P > 0)
+            HIP_TRY(hipMemcpyAsync(pplanes, po, 8 * P * g.T * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        rc = sync(c);
+        if (rc) return rc;
+    }
+    if (out) *out = st;
     return MF4D_OK;
 }
 

@@ -1,0 +1,51 @@
+// Device state of the batched (up to 256 queries) grower.
+#pragma once
+
+#include "mf4d_internal.h"
+
+namespace mf4d {
+
+enum BCounter : int {
+    BC_NWORK0 = 0,
+    BC_NWORK1 = 1,
+    BC_NDIRTYP = 2,
+    BC_NLIST = 3,
+    BC_DROPPED = 4,
+    BC_NCOUNTERS = 8
+};
+
+// Float offsets inside the table buffer: sorted bounds (256 each), then the
+// four prefix-mask tables of 257 x 8 words (field lo, field hi, particle lo,
+// particle hi).
+constexpr int kTabWords = 1024 + 4 * 257 * 8;
+
+struct DevB {
+    Geom g;  // tile geometry of the single-query binning (decodes particle bins)
+    int X, Y, Z, T;
+    int NXb, NYb, NZb, NTb;  // tiles of 8 x 4 x 4 x 4 voxel-steps
+    uint32_t NTB;
+    int Q;
+    int64_t P;
+    int Tpad;
+    const float* field;      // fp32 [T][Z][Y][X]
+    const float* attr_t;     // fp32 [P][Tpad]
+    const uint32_t* bins;    // [P][Tpad] tile-layout bit position or kNoVoxel
+    uint32_t* fplanes;       // [V][8] labels = output
+    uint32_t* pplanes;       // [T][P][8] labels = output
+    const float* tab;        // kTabWords
+    uint8_t* active;         // NTB (+8)
+    uint32_t* dirty;         // 2 x NTB
+    uint8_t* chg;            // 2 x NTB (+8)
+    uint32_t* work;          // 2 x NTB
+    uint2* clist;            // coupled steps (flat step index, canonical voxel index)
+    uint32_t* pdirty;        // P bits
+    uint32_t* dlist;         // P
+    uint32_t* counters;      // BCounter
+    unsigned long long* stat64;
+};
+
+void launch_b_prepare(const DevB& d, const int32_t* seeds, int64_t S, hipStream_t s);
+void launch_b_round(const DevB& d, uint32_t round, uint32_t nwork_host, hipStream_t s);
+void launch_b_count(const DevB& d, hipStream_t s);
+
+}  // namespace mf4d

@@ -1,0 +1,555 @@
+// Batched growing: up to 256 queries (each its own seeds and criteria) as the
+// bit-planes of one 256-bit label per node, grown together in one pass over
+// the data.  Query q lives in bit (q & 31) of word (q >> 5) of every node.
+//
+// Admissibility of a value v for all queries at once: with the lower bounds
+// sorted ascending, {q : lo_q <= v} is the first rank_lo(v) queries of that
+// order, a prefix mask read from a table; likewise for the upper bounds sorted
+// descending.  The node's 256-bit mask is the AND of the two table rows.
+//
+// Field labels are grown in place in the caller's [V][8] output (canonical
+// voxel order); particle labels in the caller's [T][P][8] output.  Work is
+// organised in tiles of 8 (x) x 4 (y) x 4 (z) x 4 (t) voxel-steps, one thread
+// per voxel-step, with the round protocol of the single-query grower: sweep,
+// pull, close/push, double-buffered work lists by round parity.
+#include "mf4d_internal.h"
+#include "batched.h"
+
+namespace mf4d {
+
+namespace {
+
+constexpr int kWave = 64;
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+struct Mask8 {
+    uint32_t w[8];
+};
+
+// #{i : s[i] <= v} for s ascending (n <= 256); NaN v gives 0.
+__device__ __forceinline__ int rank_le(const float* s, int n, float v) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (s[mid] <= v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+// #{i : s[i] >= v} for s descending.
+__device__ __forceinline__ int rank_ge(const float* s, int n, float v) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (s[mid] >= v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// Tables: sorted bounds and prefix masks, for one sample type.
+struct BandTables {
+    const float* lo_sorted;  // ascending, Q
+    const float* hi_sorted;  // descending, Q
+    const uint32_t* lo_mask; // [Q+1][8]
+    const uint32_t* hi_mask; // [Q+1][8]
+};
+
+__device__ __forceinline__ Mask8 band_mask(const BandTables& tb, int Q, float v) {
+    const int rl = rank_le(tb.lo_sorted, Q, v);
+    const int rh = rank_ge(tb.hi_sorted, Q, v);
+    Mask8 m;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) m.w[k] = tb.lo_mask[rl * 8 + k] & tb.hi_mask[rh * 8 + k];
+    return m;
+}
+
+__device__ __forceinline__ BandTables field_tables(const DevB& d) {
+    return BandTables{d.tab, d.tab + 256, reinterpret_cast<const uint32_t*>(d.tab + 1024),
+                      reinterpret_cast<const uint32_t*>(d.tab + 1024) + 257 * 8};
+}
+__device__ __forceinline__ BandTables particle_tables(const DevB& d) {
+    return BandTables{d.tab + 512, d.tab + 768,
+                      reinterpret_cast<const uint32_t*>(d.tab + 1024) + 2 * 257 * 8,
+                      reinterpret_cast<const uint32_t*>(d.tab + 1024) + 3 * 257 * 8};
+}
+
+__device__ __forceinline__ uint32_t btile_of(const DevB& d, int x, int y, int z, int t) {
+    return ((uint32_t)((t >> 2) * d.NZb + (z >> 2)) * d.NYb + (y >> 2)) * d.NXb + (x >> 3);
+}
+
+__device__ __forceinline__ void btile_coords(const DevB& d, uint32_t tile, int& bx, int& by, int& bz,
+                                             int& bt) {
+    bx = tile % d.NXb;
+    tile /= d.NXb;
+    by = tile % d.NYb;
+    tile /= d.NYb;
+    bz = tile % d.NZb;
+    bt = tile / d.NZb;
+}
+
+__device__ __forceinline__ uint64_t vindex(const DevB& d, int x, int y, int z, int t) {
+    return (((uint64_t)t * d.Z + z) * d.Y + y) * d.X + x;
+}
+
+// Canonical voxel of a tile-layout bit position (the single-query binning).
+__device__ __forceinline__ void bit_to_xyzt(const Geom& g, uint32_t b, int& x, int& y, int& z,
+                                            int& t) {
+    const uint32_t word = b >> 5;
+    const uint32_t tile = word >> (6 + g.logBT);
+    const uint32_t wi = word & (g.WPT - 1);
+    uint32_t r = tile;
+    const int tx = r % g.NXt;
+    r /= g.NXt;
+    const int ty = r % g.NYt;
+    r /= g.NYt;
+    const int tz = r % g.NZt;
+    const int tt = r / g.NZt;
+    x = tx * 32 + (b & 31);
+    y = ty * 8 + (wi & 7);
+    z = tz * 8 + ((wi >> 3) & 7);
+    t = (tt << g.logBT) + (wi >> 6);
+}
+
+__device__ __forceinline__ void bschedule(const DevB& d, uint32_t tile, int par) {
+    if (atomicExch(&d.dirty[par * d.NTB + tile], 1u) == 0u) {
+        const uint32_t k = atomicAdd(&d.counters[BC_NWORK0 + par], 1u);
+        d.work[par * d.NTB + k] = tile;
+    }
+}
+
+// Voxel bits set from outside a sweep: schedule its tile and the tiles whose
+// face it touches, and flag the tile for the pull.
+__device__ void bmark_voxel(const DevB& d, int x, int y, int z, int t, int par) {
+    const uint32_t tile = btile_of(d, x, y, z, t);
+    bschedule(d, tile, par);
+    d.chg[par * d.NTB + tile] = 1;
+    const uint32_t sy = d.NXb, sz = d.NXb * d.NYb, st = sz * d.NZb;
+    uint32_t nb[8];
+    int k = 0;
+    if ((x & 7) == 0 && x > 0) nb[k++] = tile - 1;
+    if ((x & 7) == 7 && x + 1 < d.X) nb[k++] = tile + 1;
+    if ((y & 3) == 0 && y > 0) nb[k++] = tile - sy;
+    if ((y & 3) == 3 && y + 1 < d.Y) nb[k++] = tile + sy;
+    if ((z & 3) == 0 && z > 0) nb[k++] = tile - sz;
+    if ((z & 3) == 3 && z + 1 < d.Z) nb[k++] = tile + sz;
+    if ((t & 3) == 0 && t > 0) nb[k++] = tile - st;
+    if ((t & 3) == 3 && t + 1 < d.T) nb[k++] = tile + st;
+    for (int i = 0; i < k; ++i)
+        if (d.active[nb[i]]) bschedule(d, nb[i], par);
+}
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_tmp,
+                                                        uint32_t& total) {
+    const int lane = lane_id(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_tmp[wave] = x;
+    __syncthreads();
+    uint32_t wbase = 0;
+    total = 0;
+    for (int w = 0; w < nw; ++w) {
+        if (w < wave) wbase += s_tmp[w];
+        total += s_tmp[w];
+    }
+    __syncthreads();
+    return wbase + x - v;
+}
+
+__device__ __forceinline__ uint32_t block_append(uint32_t n, uint32_t* counter, uint32_t* s_tmp) {
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan(n, s_tmp, total);
+    if (threadIdx.x == 0) s_tmp[16] = total ? atomicAdd(counter, total) : 0u;
+    __syncthreads();
+    const uint32_t base = s_tmp[16];
+    __syncthreads();
+    return base + ex;
+}
+
+// ---------------------------------------------------------------------------
+
+// Clear both output planes, mark tiles that hold a node admissible for some
+// query.  One thread per voxel-step (canonical order).
+__global__ __launch_bounds__(256) void kb_admit_field(DevB d) {
+    const BandTables tb = field_tables(d);
+    const uint64_t V = (uint64_t)d.X * d.Y * d.Z * d.T;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < V; v += stride) {
+        const float f = __builtin_nontemporal_load(d.field + v);
+        const Mask8 m = band_mask(tb, d.Q, f);
+        uint4* o = reinterpret_cast<uint4*>(d.fplanes + v * 8);
+        o[0] = make_uint4(0, 0, 0, 0);
+        o[1] = make_uint4(0, 0, 0, 0);
+        uint32_t any = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) any |= m.w[k];
+        if (any) {
+            const int x = (int)(v % d.X);
+            const uint64_t r = v / d.X;
+            const int y = (int)(r % d.Y);
+            const uint64_t r2 = r / d.Y;
+            const int z = (int)(r2 % d.Z), t = (int)(r2 / d.Z);
+            d.active[btile_of(d, x, y, z, t)] = 1;
+        }
+    }
+}
+
+// Clear the particle planes and list the coupled steps: admissible for some
+// query and lying in a voxel, as (flat step index, canonical voxel index).
+__global__ __launch_bounds__(256) void kb_admit_particles(DevB d) {
+    __shared__ uint32_t s_tmp[20];
+    const BandTables tb = particle_tables(d);
+    const uint64_t n = (uint64_t)d.P * d.Tpad;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t np = (uint64_t)d.T * d.P * 2;  // uint4 per particle-step: 2
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < np; i += stride)
+        reinterpret_cast<uint4*>(d.pplanes)[i] = make_uint4(0, 0, 0, 0);
+    for (uint64_t b0 = blockIdx.x * (uint64_t)blockDim.x; b0 < n; b0 += stride) {
+        const uint64_t e = b0 + threadIdx.x;
+        bool c = false;
+        uint32_t vox = 0;
+        if (e < n) {
+            const float a = d.attr_t[e];
+            const Mask8 m = band_mask(tb, d.Q, a);
+            uint32_t any = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) any |= m.w[k];
+            const uint32_t b = d.bins[e];
+            if (any && b != kNoVoxel) {
+                int x, y, z, t;
+                bit_to_xyzt(d.g, b, x, y, z, t);
+                vox = (uint32_t)vindex(d, x, y, z, t);
+                c = true;
+            }
+        }
+        const uint32_t k = block_append(c ? 1u : 0u, &d.counters[BC_NLIST], s_tmp);
+        if (c) d.clist[k] = make_uint2((uint32_t)e, vox);
+    }
+}
+
+__global__ void kb_seeds(DevB d, const int32_t* __restrict__ seeds, int64_t S) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= S) return;
+    const int32_t* s = seeds + 5 * i;
+    const int x = s[0], y = s[1], z = s[2], t = s[3], q = s[4];
+    const uint64_t v = vindex(d, x, y, z, t);
+    const Mask8 m = band_mask(field_tables(d), d.Q, d.field[v]);
+    const uint32_t bit = 1u << (q & 31);
+    if (m.w[q >> 5] & bit) {
+        if (!(atomicOr(&d.fplanes[v * 8 + (q >> 5)], bit) & bit)) bmark_voxel(d, x, y, z, t, 0);
+    } else {
+        atomicAdd(&d.counters[BC_DROPPED], 1u);
+    }
+}
+
+// Sweep one tile (block of 512 threads, one voxel-step each) to a local fixed
+// point: Jacobi steps through LDS over the 8 in-tile neighbours, the out-of-
+// tile neighbours entering as fixed halos.
+__device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_lab,
+                            uint32_t* s_flags) {
+    int bx, by, bz, bt;
+    btile_coords(d, tile, bx, by, bz, bt);
+    const int tid = threadIdx.x;
+    const int xl = tid & 7, yl = (tid >> 3) & 3, zl = (tid >> 5) & 3, tl = tid >> 7;
+    const int x = bx * 8 + xl, y = by * 4 + yl, z = bz * 4 + zl, t = bt * 4 + tl;
+    const bool in = x < d.X && y < d.Y && z < d.Z && t < d.T;
+    if (tid == 0) {
+        d.dirty[par * d.NTB + tile] = 0u;
+        s_flags[0] = 0;
+    }
+    uint32_t a[8], l[8], l0[8], h[8];
+    const uint64_t v = in ? vindex(d, x, y, z, t) : 0;
+    if (in) {
+        const Mask8 m = band_mask(field_tables(d), d.Q, d.field[v]);
+        const uint4* lp = reinterpret_cast<const uint4*>(d.fplanes + v * 8);
+        const uint4 l01 = lp[0], l23 = lp[1];
+        l[0] = l01.x; l[1] = l01.y; l[2] = l01.z; l[3] = l01.w;
+        l[4] = l23.x; l[5] = l23.y; l[6] = l23.z; l[7] = l23.w;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            a[k] = m.w[k];
+            h[k] = 0;
+        }
+        // halos: neighbours outside the tile (inside the grid)
+        const uint64_t sx = 1, sy = d.X, sz = (uint64_t)d.X * d.Y, st = sz * d.Z;
+        uint64_t hn[8];
+        int nh = 0;
+        if (xl == 0 && x > 0) hn[nh++] = v - sx;
+        if (xl == 7 && x + 1 < d.X) hn[nh++] = v + sx;
+        if (yl == 0 && y > 0) hn[nh++] = v - sy;
+        if (yl == 3 && y + 1 < d.Y) hn[nh++] = v + sy;
+        if (zl == 0 && z > 0) hn[nh++] = v - sz;
+        if (zl == 3 && z + 1 < d.Z) hn[nh++] = v + sz;
+        if (tl == 0 && t > 0) hn[nh++] = v - st;
+        if (tl == 3 && t + 1 < d.T) hn[nh++] = v + st;
+        for (int i = 0; i < nh; ++i) {
+            const uint4* hp = reinterpret_cast<const uint4*>(d.fplanes + hn[i] * 8);
+            const uint4 h01 = hp[0], h23 = hp[1];
+            h[0] |= h01.x; h[1] |= h01.y; h[2] |= h01.z; h[3] |= h01.w;
+            h[4] |= h23.x; h[5] |= h23.y; h[6] |= h23.z; h[7] |= h23.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) a[k] = l[k] = h[k] = 0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) l0[k] = l[k];
+    // in-tile neighbour thread ids (or -1)
+    const int nx0 = xl > 0 ? tid - 1 : -1, nx1 = xl < 7 ? tid + 1 : -1;
+    const int ny0 = yl > 0 ? tid - 8 : -1, ny1 = yl < 3 ? tid + 8 : -1;
+    const int nz0 = zl > 0 ? tid - 32 : -1, nz1 = zl < 3 ? tid + 32 : -1;
+    const int nt0 = tl > 0 ? tid - 128 : -1, nt1 = tl < 3 ? tid + 128 : -1;
+    const int nbr[8] = {nx0, nx1, ny0, ny1, nz0, nz1, nt0, nt1};
+    while (true) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s_lab[k * 512 + tid] = l[k];
+        __syncthreads();
+        uint32_t diff = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            uint32_t nbv = l[k] | h[k];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (nbr[j] >= 0) nbv |= s_lab[k * 512 + nbr[j]];
+            const uint32_t s = nbv & a[k];
+            diff |= s ^ l[k];
+            l[k] = s;
+        }
+        if (!__syncthreads_or(diff != 0)) break;
+    }
+    uint32_t any = 0;
+    if (in) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t nw = l[k] & ~l0[k];
+            if (nw) atomicOr(&d.fplanes[v * 8 + k], nw);
+            any |= nw;
+        }
+    }
+    if (any) {
+        uint32_t faces = 1u << 8;  // bit 8: tile changed
+        if (xl == 0) faces |= 1u << 0;
+        if (xl == 7) faces |= 1u << 1;
+        if (yl == 0) faces |= 1u << 2;
+        if (yl == 3) faces |= 1u << 3;
+        if (zl == 0) faces |= 1u << 4;
+        if (zl == 3) faces |= 1u << 5;
+        if (tl == 0) faces |= 1u << 6;
+        if (tl == 3) faces |= 1u << 7;
+        atomicOr(&s_flags[0], faces);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const uint32_t f = s_flags[0];
+        if (f) {
+            d.chg[par * d.NTB + tile] = 1;
+            const int nx = par ^ 1;
+            const uint32_t sy = d.NXb, sz = d.NXb * d.NYb, st = sz * d.NZb;
+            uint32_t nb[8];
+            int k = 0;
+            if ((f & 1) && bx > 0) nb[k++] = tile - 1;
+            if ((f & 2) && bx + 1 < d.NXb) nb[k++] = tile + 1;
+            if ((f & 4) && by > 0) nb[k++] = tile - sy;
+            if ((f & 8) && by + 1 < d.NYb) nb[k++] = tile + sy;
+            if ((f & 16) && bz > 0) nb[k++] = tile - sz;
+            if ((f & 32) && bz + 1 < d.NZb) nb[k++] = tile + sz;
+            if ((f & 64) && bt > 0) nb[k++] = tile - st;
+            if ((f & 128) && bt + 1 < d.NTb) nb[k++] = tile + st;
+            for (int i = 0; i < k; ++i)
+                if (d.active[nb[i]]) bschedule(d, nb[i], nx);
+        }
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(512) void kb_sweep(DevB d, int par) {
+    __shared__ uint32_t s_lab[8 * 512];
+    __shared__ uint32_t s_flags[4];
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.counters[BC_NDIRTYP] = 0;
+    const uint32_t nwork = d.counters[BC_NWORK0 + par];
+    uint32_t visits = 0;
+    for (uint32_t w = blockIdx.x; w < nwork; w += gridDim.x) {
+        bsweep_tile(d, d.work[par * d.NTB + w], par, s_lab, s_flags);
+        ++visits;
+    }
+    if (threadIdx.x == 0 && visits) atomicAdd(&d.stat64[S_TILE_VISITS], (unsigned long long)visits);
+}
+
+// Pull: a coupled step gains the queries for which its voxel is a member and
+// it is admissible.
+__global__ __launch_bounds__(256) void kb_pull(DevB d, int par) {
+    __shared__ uint32_t s_tmp[20];
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.counters[BC_NWORK0 + par] = 0;
+    const BandTables tb = particle_tables(d);
+    const uint32_t n = d.counters[BC_NLIST];
+    for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < n; b0 += gridDim.x * blockDim.x) {
+        const uint32_t i = b0 + threadIdx.x;
+        bool first = false;
+        uint32_t p = 0;
+        if (i < n) {
+            const uint2 ent = d.clist[i];
+            const uint32_t vox = ent.y;
+            int x = (int)(vox % d.X);
+            uint32_t r = vox / d.X;
+            const int y = r % d.Y;
+            r /= d.Y;
+            const int z = r % d.Z, t = r / d.Z;
+            if (d.chg[par * d.NTB + btile_of(d, x, y, z, t)]) {
+                p = ent.x / (uint32_t)d.Tpad;
+                const uint32_t ts = ent.x - p * (uint32_t)d.Tpad;
+                const uint32_t* lf = d.fplanes + (uint64_t)vox * 8;
+                uint32_t* lp = d.pplanes + ((uint64_t)ts * d.P + p) * 8;
+                bool any = false;
+                bool got = false;
+                Mask8 m;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    m.w[k] = lf[k] & ~lp[k];
+                    any |= m.w[k] != 0;
+                }
+                if (any) {
+                    const Mask8 am = band_mask(tb, d.Q, d.attr_t[ent.x]);
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const uint32_t nw = m.w[k] & am.w[k];
+                        if (nw && (~atomicOr(&lp[k], nw) & nw)) got = true;
+                    }
+                }
+                if (got) {
+                    const uint32_t pb = 1u << (p & 31);
+                    first = !(atomicOr(&d.pdirty[p >> 5], pb) & pb);
+                }
+            }
+        }
+        const uint32_t k = block_append(first ? 1u : 0u, &d.counters[BC_NDIRTYP], s_tmp);
+        if (first) d.dlist[k] = p;
+    }
+}
+
+// Close and push one particle for every query plane: forward and backward
+// passes along its steps spread members over admissible runs; each step that
+// gains queries pushes them into its voxel where the voxel is admissible.
+__device__ void bclose_particle(const DevB& d, uint32_t p, int par) {
+    atomicAnd(&d.pdirty[p >> 5], ~(1u << (p & 31)));
+    const BandTables tp = particle_tables(d);
+    const BandTables tf = field_tables(d);
+    for (int dir = 0; dir < 2; ++dir) {
+        uint32_t carry[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int i = 0; i < d.T; ++i) {
+            const int t = dir == 0 ? i : d.T - 1 - i;
+            uint32_t* lp = d.pplanes + ((uint64_t)t * d.P + p) * 8;
+            const Mask8 am = band_mask(tp, d.Q, d.attr_t[(uint64_t)p * d.Tpad + t]);
+            uint32_t nw[8];
+            uint32_t anynew = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t cur = lp[k];
+                const uint32_t l = cur | (carry[k] & am.w[k]);
+                nw[k] = l & ~cur;
+                anynew |= nw[k];
+                carry[k] = l;
+            }
+            if (!anynew) continue;
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (nw[k]) atomicOr(&lp[k], nw[k]);
+            const uint32_t b = d.bins[(uint64_t)p * d.Tpad + t];
+            if (b == kNoVoxel) continue;
+            int x, y, z, tt;
+            bit_to_xyzt(d.g, b, x, y, z, tt);
+            const uint64_t v = vindex(d, x, y, z, tt);
+            const Mask8 af = band_mask(tf, d.Q, d.field[v]);
+            bool gained = false;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t pw = nw[k] & af.w[k];
+                if (pw && (~atomicOr(&d.fplanes[v * 8 + k], pw) & pw)) gained = true;
+            }
+            if (gained) bmark_voxel(d, x, y, z, tt, par);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void kb_close(DevB d, int par) {
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = tid; i < d.NTB; i += stride) d.chg[par * d.NTB + i] = 0;
+    const uint32_t nd = d.counters[BC_NDIRTYP];
+    if (tid == 0 && nd) atomicAdd(&d.stat64[S_PART_VISITS], (unsigned long long)nd);
+    for (uint32_t i = tid; i < nd; i += stride) bclose_particle(d, d.dlist[i], par ^ 1);
+}
+
+__global__ void kb_reset(DevB d) {
+    const uint64_t tid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = tid; i < 2ull * d.NTB; i += stride) d.dirty[i] = 0;
+    for (uint64_t i = tid; i < (2ull * d.NTB + 3) / 4; i += stride)
+        reinterpret_cast<uint32_t*>(d.chg)[i] = 0;
+    for (uint64_t i = tid; i < ((uint64_t)d.NTB + 3) / 4; i += stride)
+        reinterpret_cast<uint32_t*>(d.active)[i] = 0;
+    for (uint64_t i = tid; i < (uint64_t)(d.P + 31) / 32; i += stride) d.pdirty[i] = 0;
+    if (tid < BC_NCOUNTERS) d.counters[tid] = 0;
+    if (tid < S_NSTAT) d.stat64[tid] = 0;
+}
+
+__global__ void kb_count(DevB d) {
+    const uint64_t nf = (uint64_t)d.X * d.Y * d.Z * d.T * 8;
+    const uint64_t np = (uint64_t)d.T * d.P * 8;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    unsigned long long cf = 0, cp = 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nf; i += stride)
+        cf += __popc(d.fplanes[i]);
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < np; i += stride)
+        cp += __popc(d.pplanes[i]);
+    for (int o = 32; o > 0; o >>= 1) {
+        cf += __shfl_xor(cf, o);
+        cp += __shfl_xor(cp, o);
+    }
+    if (lane_id() == 0) {
+        if (cf) atomicAdd(&d.stat64[S_MEMBERS_F], cf);
+        if (cp) atomicAdd(&d.stat64[S_MEMBERS_P], cp);
+    }
+}
+
+inline unsigned grid_for(uint64_t n, unsigned block, unsigned cap) {
+    uint64_t b = (n + block - 1) / block;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+void launch_b_prepare(const DevB& d, const int32_t* seeds, int64_t S, hipStream_t s) {
+    const uint64_t V = (uint64_t)d.X * d.Y * d.Z * d.T;
+    hipLaunchKernelGGL(kb_reset, dim3(grid_for(2ull * d.NTB + d.P / 32 + 1, 256, 2048)), dim3(256),
+                       0, s, d);
+    hipLaunchKernelGGL(kb_admit_field, dim3(grid_for(V, 256, 16384)), dim3(256), 0, s, d);
+    if (d.P > 0)
+        hipLaunchKernelGGL(kb_admit_particles,
+                           dim3(grid_for((uint64_t)d.P * d.Tpad, 256, 8192)), dim3(256), 0, s, d);
+    if (S > 0)
+        hipLaunchKernelGGL(kb_seeds, dim3(grid_for(S, 256, 1u << 20)), dim3(256), 0, s, d, seeds, S);
+}
+
+void launch_b_round(const DevB& d, uint32_t round, uint32_t nwork_host, hipStream_t s) {
+    const int par = round & 1;
+    hipLaunchKernelGGL(kb_sweep, dim3(grid_for(nwork_host, 1, 8192)), dim3(512), 0, s, d, par);
+    if (d.P > 0) {
+        hipLaunchKernelGGL(kb_pull, dim3(grid_for((uint64_t)d.P * d.Tpad, 256, 2048)), dim3(256), 0,
+                           s, d, par);
+        const uint64_t nclose = (uint64_t)d.NTB > (uint64_t)d.P ? (uint64_t)d.NTB : (uint64_t)d.P;
+        hipLaunchKernelGGL(kb_close, dim3(grid_for(nclose, 256, 2048)), dim3(256), 0, s, d, par);
+    } else {
+        hipLaunchKernelGGL(kb_close, dim3(grid_for(d.NTB, 256, 2048)), dim3(256), 0, s, d, par);
+    }
+}
+
+void launch_b_count(const DevB& d, hipStream_t s) {
+    const uint64_t V = (uint64_t)d.X * d.Y * d.Z * d.T;
+    hipLaunchKernelGGL(kb_count, dim3(grid_for(V * 8, 256, 8192)), dim3(256), 0, s, d);
+}
+
+}  // namespace mf4d

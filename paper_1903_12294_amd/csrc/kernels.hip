@@ -1,9 +1,18 @@
 // HIP kernels of the coupled point + field region grower, for gfx950 (wave64).
 //
-// Field nodes are kept as bit-packed tiles (see Geom in mf4d_internal.h); the
+// Field nodes are kept as bit-packed tiles (Geom in mf4d_internal.h); the
 // particle part as one bit per particle-step in 64-bit words per particle.
 // Every label bit only goes 0 -> 1, so the order in which waves apply their
-// updates cannot change the fixed point they reach.
+// updates cannot change the fixed point they reach (the least fixed point of a
+// monotone operator); stale reads only delay a bit to a later round, and every
+// change that another tile or particle must see schedules that work.
+//
+// A round has three phases: sweep the tiles on this round's work list, pull
+// coupled particle-steps whose voxel joined, close the trajectories of the
+// particles that gained steps and push their voxels.  Work lists, dirty flags
+// and "changed" flags are double-buffered by round parity.  The phases run
+// either as three launches per round or inside one cooperative persistent
+// kernel separated by grid barriers.
 #include "mf4d_internal.h"
 
 namespace mf4d {
@@ -13,19 +22,6 @@ namespace {
 constexpr int kWave = 64;
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
-
-// Index in a wave-wide append of the lanes with pred set: one atomicAdd per wave.
-// Every lane of the wave must call it.
-__device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t* counter) {
-    const uint64_t m = __ballot(pred);
-    if (m == 0) return 0;
-    const int lane = lane_id();
-    const int leader = __ffsll((unsigned long long)m) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
-    base = __shfl(base, leader);
-    return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-}
 
 __device__ __forceinline__ bool in_band(float v, float lo, float hi) { return lo <= v && v <= hi; }
 
@@ -74,46 +70,351 @@ __device__ __forceinline__ void tile_coords(const Geom& g, uint32_t tile, int& t
     tt = tile / g.NZt;
 }
 
-// A voxel bit set from outside a tile sweep (seed or particle push): its own
-// tile must be swept, and so must every tile whose face it touches, because
-// the owning tile's sweep only reports bits that are new to that sweep.
-__device__ void mark_voxel(const Geom& g, uint32_t b, const uint8_t* active, uint8_t* dirty) {
+__device__ __forceinline__ bool test_bit(const uint32_t* a, uint32_t b) {
+    return (a[b >> 5] >> (b & 31)) & 1u;
+}
+
+__device__ __forceinline__ uint32_t load_relaxed(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_relaxed(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive prefix of v over a 256-thread block; `total` gets the block sum.
+// Every thread of the block must call it.
+__device__ __forceinline__ uint32_t block_exclusive_scan256(uint32_t v, uint32_t* s_tmp,
+                                                           uint32_t& total) {
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_tmp[wave] = x;
+    __syncthreads();
+    uint32_t wbase = 0;
+    for (int w = 0; w < wave; ++w) wbase += s_tmp[w];
+    total = s_tmp[0] + s_tmp[1] + s_tmp[2] + s_tmp[3];
+    __syncthreads();
+    return wbase + x - v;
+}
+
+// Block-wide append: each thread reserves `n` slots; one atomic per block.
+__device__ __forceinline__ uint32_t block_append256(uint32_t n, uint32_t* counter, uint32_t* s_tmp) {
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan256(n, s_tmp, total);
+    if (threadIdx.x == 0) s_tmp[4] = total ? atomicAdd(counter, total) : 0u;
+    __syncthreads();
+    const uint32_t base = s_tmp[4];
+    __syncthreads();
+    return base + ex;
+}
+
+// ---------------------------------------------------------------------------
+// scheduling
+
+// Put a tile on the work list of round parity `par` (once per round).
+__device__ __forceinline__ void schedule(const Dev& d, uint32_t tile, int par) {
+    if (atomicExch(&d.dirty[par * d.g.NT + tile], 1u) == 0u) {
+        const uint32_t k = atomicAdd(&d.counters[C_NWORK0 + par], 1u);
+        d.work[par * d.g.NT + k] = tile;
+    }
+}
+
+// A voxel bit set from outside a tile sweep (seed or particle push), before
+// round parity `par`: its own tile must be swept, and so must every tile whose
+// face it touches (the owning tile's sweep only reports bits new to that
+// sweep); the owning tile's coupled steps must be pulled.
+__device__ void mark_voxel(const Dev& d, uint32_t b, int par) {
+    const Geom& g = d.g;
     const uint32_t word = b >> 5;
     const int xb = b & 31;
     const uint32_t tile = word >> (6 + g.logBT);
     const uint32_t wi = word & (g.WPT - 1);
     const int yl = wi & 7, zl = (wi >> 3) & 7, tl = wi >> 6;
-    dirty[tile] = 1;
+    schedule(d, tile, par);
+    d.chg[par * g.NT + tile] = 1;
     int tx, ty, tz, tt;
     tile_coords(g, tile, tx, ty, tz, tt);
     const uint32_t sy = g.NXt, sz = g.NXt * g.NYt, st = sz * g.NZt;
-    uint32_t nb[4];
+    uint32_t nb[8];
     int k = 0;
     if (xb == 0 && tx > 0) nb[k++] = tile - 1;
     if (xb == 31 && tx + 1 < g.NXt) nb[k++] = tile + 1;
     if (yl == 0 && ty > 0) nb[k++] = tile - sy;
     if (yl == 7 && ty + 1 < g.NYt) nb[k++] = tile + sy;
-    for (int i = 0; i < k; ++i)
-        if (active[nb[i]]) dirty[nb[i]] = 1;
-    k = 0;
     if (zl == 0 && tz > 0) nb[k++] = tile - sz;
     if (zl == 7 && tz + 1 < g.NZt) nb[k++] = tile + sz;
     if (tl == 0 && tt > 0) nb[k++] = tile - st;
     if (tl == g.BT - 1 && tt + 1 < g.NTt) nb[k++] = tile + st;
     for (int i = 0; i < k; ++i)
-        if (active[nb[i]]) dirty[nb[i]] = 1;
-}
-
-__device__ __forceinline__ bool test_bit(const uint32_t* a, uint32_t b) {
-    return (a[b >> 5] >> (b & 31)) & 1u;
+        if (d.active[nb[i]]) schedule(d, nb[i], par);
 }
 
 // ---------------------------------------------------------------------------
+// the three phases of a round
+
+// Sweep one tile to a local fixed point with one wavefront.  Lane = (z_l, y_l);
+// each lane holds the BT words of its (y, z) column over the tile's timesteps
+// in registers.  Per iteration: one Jacobi step in y and z (lane shuffles),
+// complete fills along x inside each word, and complete forward / backward
+// passes along t.  Neighbour-tile words enter as fixed halos; when a face of
+// this tile gains bits, the tile across that face is scheduled for the next
+// round.  Every lane of the wave must call it.
+template <int BT>
+__device__ void sweep_tile(const Dev& d, uint32_t tile, int par) {
+    const Geom& g = d.g;
+    const int lane = lane_id();
+    const int yl = lane & 7, zl = lane >> 3;
+    const uint32_t sy = g.NXt, sz = g.NXt * g.NYt, st = sz * g.NZt;
+    int tx, ty, tz, tt;
+    tile_coords(g, tile, tx, ty, tz, tt);
+    if (lane == 0) d.dirty[par * g.NT + tile] = 0u;
+    const uint32_t* Ab = d.Af + (size_t)tile * (64 * BT);
+    uint32_t* Lb = d.Lf + (size_t)tile * (64 * BT);
+    uint32_t a[BT], l[BT], l0[BT], xin[BT], yh[BT], zh[BT];
+#pragma unroll
+    for (int t = 0; t < BT; ++t) {
+        a[t] = Ab[t * 64 + lane];
+        l[t] = Lb[t * 64 + lane];
+    }
+    const uint32_t* Lxm = tx > 0 ? Lb - 64 * BT : nullptr;
+    const uint32_t* Lxp = tx + 1 < g.NXt ? Lb + 64 * BT : nullptr;
+    const uint32_t* Ly = nullptr;
+    int yoff = 0;
+    if (yl == 0 && ty > 0) { Ly = Lb - (size_t)sy * 64 * BT; yoff = 7; }
+    if (yl == 7 && ty + 1 < g.NYt) { Ly = Lb + (size_t)sy * 64 * BT; yoff = -7; }
+    const uint32_t* Lz = nullptr;
+    int zoff = 0;
+    if (zl == 0 && tz > 0) { Lz = Lb - (size_t)sz * 64 * BT; zoff = 56; }
+    if (zl == 7 && tz + 1 < g.NZt) { Lz = Lb + (size_t)sz * 64 * BT; zoff = -56; }
+#pragma unroll
+    for (int t = 0; t < BT; ++t) {
+        xin[t] = (Lxm ? (Lxm[t * 64 + lane] >> 31) : 0u) | (Lxp ? (Lxp[t * 64 + lane] << 31) : 0u);
+        yh[t] = Ly ? Ly[t * 64 + lane + yoff] : 0u;
+        zh[t] = Lz ? Lz[t * 64 + lane + zoff] : 0u;
+        l0[t] = l[t];
+    }
+    const uint32_t tm = tt > 0 ? (Lb - (size_t)st * 64 * BT)[(BT - 1) * 64 + lane] : 0u;
+    const uint32_t tp = tt + 1 < g.NTt ? (Lb + (size_t)st * 64 * BT)[lane] : 0u;
+    while (true) {
+        uint32_t s[BT];
+#pragma unroll
+        for (int t = 0; t < BT; ++t) {
+            const uint32_t v = l[t];
+            const uint32_t ym = __shfl_up(v, 1), yp = __shfl_down(v, 1);
+            const uint32_t zm = __shfl_up(v, 8), zp = __shfl_down(v, 8);
+            uint32_t nb = v | (v << 1) | (v >> 1) | xin[t] | yh[t] | zh[t];
+            nb |= (yl > 0 ? ym : 0u) | (yl < 7 ? yp : 0u) | (zl > 0 ? zm : 0u) | (zl < 7 ? zp : 0u);
+            s[t] = fill_runs32(nb & a[t], a[t]);
+        }
+        s[0] |= fill_runs32(tm & a[0], a[0]);
+#pragma unroll
+        for (int t = 1; t < BT; ++t) s[t] |= fill_runs32(s[t - 1] & a[t], a[t]);
+        s[BT - 1] |= fill_runs32(tp & a[BT - 1], a[BT - 1]);
+#pragma unroll
+        for (int t = BT - 2; t >= 0; --t) s[t] |= fill_runs32(s[t + 1] & a[t], a[t]);
+        uint32_t diff = 0;
+#pragma unroll
+        for (int t = 0; t < BT; ++t) {
+            diff |= s[t] ^ l[t];
+            l[t] = s[t];
+        }
+        if (__ballot(diff != 0) == 0) break;
+    }
+    uint32_t any = 0, fx0 = 0, fx1 = 0;
+#pragma unroll
+    for (int t = 0; t < BT; ++t) {
+        const uint32_t nw = l[t] & ~l0[t];
+        if (nw) atomicOr(&Lb[t * 64 + lane], nw);
+        any |= nw;
+        fx0 |= nw & 1u;
+        fx1 |= nw >> 31;
+    }
+    const uint32_t nt0 = l[0] & ~l0[0], nt1 = l[BT - 1] & ~l0[BT - 1];
+    if (__ballot(any != 0)) {
+        const bool fxm = __ballot(fx0 != 0) != 0, fxp = __ballot(fx1 != 0) != 0;
+        const bool fym = __ballot(yl == 0 && any) != 0, fyp = __ballot(yl == 7 && any) != 0;
+        const bool fzm = __ballot(zl == 0 && any) != 0, fzp = __ballot(zl == 7 && any) != 0;
+        const bool ftm = __ballot(nt0 != 0) != 0, ftp = __ballot(nt1 != 0) != 0;
+        if (lane == 0) {
+            d.chg[par * g.NT + tile] = 1;
+            const int nx = par ^ 1;
+            uint32_t nb[8];
+            int k = 0;
+            if (fxm && tx > 0) nb[k++] = tile - 1;
+            if (fxp && tx + 1 < g.NXt) nb[k++] = tile + 1;
+            if (fym && ty > 0) nb[k++] = tile - sy;
+            if (fyp && ty + 1 < g.NYt) nb[k++] = tile + sy;
+            if (fzm && tz > 0) nb[k++] = tile - sz;
+            if (fzp && tz + 1 < g.NZt) nb[k++] = tile + sz;
+            if (ftm && tt > 0) nb[k++] = tile - st;
+            if (ftp && tt + 1 < g.NTt) nb[k++] = tile + st;
+            for (int i = 0; i < k; ++i)
+                if (d.active[nb[i]]) schedule(d, nb[i], nx);
+        }
+    }
+}
+
+// Pull, block-level (every thread of the block calls it for the same chunk):
+// a coupled particle-step joins when the voxel holding it is a member.  Only
+// steps in tiles whose members changed since their last pull are tested.  A
+// particle that gains a step goes once on the dirty list.
+__device__ void pull_chunk(const Dev& d, uint32_t cb, uint32_t n, int par, uint32_t* s_tmp) {
+    const PGeom& pg = d.pg;
+    const int tshift = 5 + 6 + d.g.logBT;
+    const uint8_t* chg = d.chg + par * d.g.NT;
+    uint2 ent[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t i = cb + k * 256 + threadIdx.x;
+        ent[k] = i < n ? d.clist[i] : make_uint2(0u, kNoVoxel);
+    }
+    bool mem[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        mem[k] = ent[k].y != kNoVoxel && chg[ent[k].y >> tshift] && test_bit(d.Lf, ent[k].y);
+    uint32_t first[4];
+    uint32_t nfirst = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        first[k] = kNoVoxel;
+        if (mem[k]) {
+            uint32_t p, ts;
+            if (pg.logTpad >= 0) {
+                p = ent[k].x >> pg.logTpad;
+                ts = ent[k].x & (pg.Tpad - 1);
+            } else {
+                p = ent[k].x / (uint32_t)pg.Tpad;
+                ts = ent[k].x - p * (uint32_t)pg.Tpad;
+            }
+            const uint32_t wi = p * (uint32_t)pg.W + (ts >> 6);
+            const unsigned long long bit = 1ull << (ts & 63);
+            if (!(d.Lp[wi] & bit) && !(atomicOr(&d.Lp[wi], bit) & bit)) {
+                const uint32_t pb = 1u << (p & 31);
+                if (!(atomicOr(&d.pdirty[p >> 5], pb) & pb)) {
+                    first[k] = p;
+                    ++nfirst;
+                }
+            }
+        }
+    }
+    uint32_t base = block_append256(nfirst, &d.counters[C_NDIRTYP], s_tmp);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (first[k] != kNoVoxel) d.dlist[base++] = first[k];
+}
+
+__device__ __forceinline__ void push_steps(const Dev& d, uint32_t p, int w, unsigned long long nw,
+                                           int par) {
+    while (nw) {
+        const int t = __builtin_ctzll(nw);
+        nw &= nw - 1;
+        const uint32_t b = d.bins[(size_t)p * d.pg.Tpad + w * 64 + t];
+        if (b != kNoVoxel && test_bit(d.Af, b)) {
+            const uint32_t bit = 1u << (b & 31);
+            if (!(atomicOr(&d.Lf[b >> 5], bit) & bit)) mark_voxel(d, b, par);
+        }
+    }
+}
+
+// Close and push one dirty particle: its member steps spread over each run of
+// admissible steps that holds them (its trajectory), and every step that joins
+// pushes its voxel in when that voxel is admissible, for round parity `par`.
+__device__ void close_particle(const Dev& d, uint32_t p, int par) {
+    atomicAnd(&d.pdirty[p >> 5], ~(1u << (p & 31)));
+    const int W = d.pg.W;
+    unsigned long long* lw = d.Lp + (size_t)p * W;
+    const unsigned long long* aw = d.Ap + (size_t)p * W;
+    if (W == 1) {
+        const unsigned long long a = aw[0], l0 = lw[0];
+        const unsigned long long l = fill_runs64(l0, a);
+        const unsigned long long nw = l & ~l0;
+        if (nw) {
+            atomicOr(&lw[0], nw);
+            push_steps(d, p, 0, nw, par);
+        }
+        return;
+    }
+    // runs crossing word boundaries: carry upward, then downward
+    unsigned long long carry = 0;
+    for (int w = 0; w < W; ++w) {
+        const unsigned long long a = aw[w], l0 = lw[w];
+        unsigned long long l = fill_runs64(l0 | (carry & a & 1ull), a);
+        carry = l >> 63;
+        const unsigned long long nw = l & ~l0;
+        if (nw) {
+            atomicOr(&lw[w], nw);
+            push_steps(d, p, w, nw, par);
+        }
+    }
+    carry = 0;
+    for (int w = W - 1; w >= 0; --w) {
+        const unsigned long long a = aw[w], l0 = lw[w];
+        unsigned long long l = fill_runs64(l0 | ((carry << 63) & a), a);
+        carry = l & 1ull;
+        const unsigned long long nw = l & ~l0;
+        if (nw) {
+            atomicOr(&lw[w], nw);
+            push_steps(d, p, w, nw, par);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Grid barrier for the persistent kernel: a monotone arrival counter; every
+// block waits until all blocks have arrived `epoch` times.  The wait is
+// bounded: after ~2^22 polls it records an error and returns false, so no wave
+// can hang; every block then leaves the round loop.
+__device__ bool grid_sync(const Dev& d, uint32_t& epoch) {
+    __shared__ uint32_t s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        epoch += gridDim.x;
+        __hip_atomic_fetch_add(d.bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t ok = 1;
+        uint32_t polls = 0;
+        while (__hip_atomic_load(d.bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++polls > (1u << 22)) {
+                atomicExch(&d.counters[C_ERR], 1u);
+                ok = 0;
+                break;
+            }
+        }
+        if (load_relaxed(&d.counters[C_ERR])) ok = 0;
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, uint64_t n) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x)
         p[i] = v;
+}
+
+// Zero the per-grow scheduling state in one launch.
+__global__ void k_reset(Dev d) {
+    const uint64_t tid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t n_dirty = 2ull * d.g.NT;
+    const uint64_t n_chg = (2ull * d.g.NT + 3) / 4;
+    const uint64_t n_act = ((uint64_t)d.g.NT + 3) / 4;
+    const uint64_t n_pd = (uint64_t)(d.pg.P + 31) / 32;
+    for (uint64_t i = tid; i < n_dirty; i += stride) d.dirty[i] = 0;
+    for (uint64_t i = tid; i < n_chg; i += stride) reinterpret_cast<uint32_t*>(d.chg)[i] = 0;
+    for (uint64_t i = tid; i < n_act; i += stride) reinterpret_cast<uint32_t*>(d.active)[i] = 0;
+    for (uint64_t i = tid; i < n_pd; i += stride) d.pdirty[i] = 0;
+    if (tid < C_NCOUNTERS) d.counters[tid] = 0;
+    if (tid < S_NSTAT) d.stat64[tid] = 0;
+    if (tid < 4) d.bar[tid] = 0;
 }
 
 // Load: bin every particle-step into the voxel covering it and transpose the
@@ -159,13 +460,16 @@ __global__ __launch_bounds__(256) void k_bin_particles(Geom g, PGeom pg,
     }
 }
 
-// Admissibility of every voxel-step, bit-packed into tiles.  Block = 256
-// threads for the 64 rows (z_l, y_l) of one (t, tz, ty); x in passes of 256.
-// Each lane tests 4 consecutive x; 8 lanes OR their nibbles into one word.
-__global__ __launch_bounds__(256) void k_admit_field(Geom g, const float* __restrict__ f, float lo,
-                                                     float hi, uint32_t* __restrict__ A,
-                                                     uint8_t* __restrict__ active) {
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Admissibility of every voxel-step, bit-packed into tiles, and the labels
+// cleared.  Block = 256 threads for the 64 rows (z_l, y_l) of one (t, tz, ty);
+// x in passes of 256.  Each lane tests 4 consecutive x (one 16-byte
+// non-temporal load); 8 lanes OR their nibbles into one word.
+__global__ __launch_bounds__(256) void k_admit_field(Dev d) {
     __shared__ uint32_t sw[8 * 64];
+    const Geom& g = d.g;
+    const float lo = d.crit[0], hi = d.crit[1];
     const int ty = blockIdx.x, tz = blockIdx.y, t = blockIdx.z;
     const int tt = t >> g.logBT, tl = t & (g.BT - 1);
     const int wave = threadIdx.x >> 6, lane = lane_id();
@@ -173,17 +477,18 @@ __global__ __launch_bounds__(256) void k_admit_field(Geom g, const float* __rest
     for (int tx0 = 0; tx0 < g.NXt; tx0 += 8) {
         const int ntx = min(8, g.NXt - tx0);
         const int x = tx0 * 32 + 4 * lane;
-        float4 v[16];
+        v4f v[16];
 #pragma unroll
         for (int rr = 0; rr < 16; ++rr) {
             const int row = wave * 16 + rr;
             const int y = ty * 8 + (row & 7), z = tz * 8 + (row >> 3);
-            v[rr] = make_float4(__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""),
-                                __builtin_nanf(""));
+            const float nan = __builtin_nanf("");
+            v[rr] = (v4f){nan, nan, nan, nan};
             if (y < g.Y && z < g.Z) {
-                const float* rp = f + ((size_t)(t * g.Z + z) * g.Y + y) * g.X;
+                const float* rp = d.field + ((size_t)(t * g.Z + z) * g.Y + y) * g.X;
                 if (vec) {
-                    if (x < g.X) v[rr] = *reinterpret_cast<const float4*>(rp + x);
+                    if (x < g.X)
+                        v[rr] = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(rp + x));
                 } else {
                     if (x < g.X) v[rr].x = rp[x];
                     if (x + 1 < g.X) v[rr].y = rp[x + 1];
@@ -195,10 +500,10 @@ __global__ __launch_bounds__(256) void k_admit_field(Geom g, const float* __rest
 #pragma unroll
         for (int rr = 0; rr < 16; ++rr) {
             const int row = wave * 16 + rr;
-            uint32_t nib = (uint32_t)in_band(v[rr].x, lo, hi) |
-                           ((uint32_t)in_band(v[rr].y, lo, hi) << 1) |
-                           ((uint32_t)in_band(v[rr].z, lo, hi) << 2) |
-                           ((uint32_t)in_band(v[rr].w, lo, hi) << 3);
+            const uint32_t nib = (uint32_t)in_band(v[rr].x, lo, hi) |
+                                 ((uint32_t)in_band(v[rr].y, lo, hi) << 1) |
+                                 ((uint32_t)in_band(v[rr].z, lo, hi) << 2) |
+                                 ((uint32_t)in_band(v[rr].w, lo, hi) << 3);
             uint32_t w = nib << (4 * (lane & 7));
             w |= __shfl_xor(w, 1);
             w |= __shfl_xor(w, 2);
@@ -210,406 +515,306 @@ __global__ __launch_bounds__(256) void k_admit_field(Geom g, const float* __rest
             const int txl = i >> 6, row = i & 63;
             const uint32_t tile = tile_of(g, tx0 + txl, ty, tz, tt);
             const uint32_t w = sw[i];
-            A[(size_t)tile * g.WPT + tl * 64 + row] = w;
-            if (__ballot(w != 0) != 0 && lane == 0) active[tile] = 1;
+            const size_t wi = (size_t)tile * g.WPT + tl * 64 + row;
+            d.Af[wi] = w;
+            d.Lf[wi] = 0u;
+            if (__ballot(w != 0) != 0 && lane == 0) d.active[tile] = 1;
         }
         __syncthreads();
     }
 }
 
-__global__ void k_count_active(Geom g, const uint8_t* __restrict__ active,
-                               unsigned long long* stat) {
+__global__ void k_count_active(Dev d) {
     uint32_t c = 0;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < g.NT; i += gridDim.x * blockDim.x)
-        c += active[i];
-    const uint64_t m = __ballot(c != 0);
-    // reduce counts across the wave
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < d.g.NT;
+         i += gridDim.x * blockDim.x)
+        c += d.active[i];
     for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
-    if (lane_id() == 0 && m) atomicAdd(stat, (unsigned long long)c);
+    if (lane_id() == 0 && c) atomicAdd(&d.stat64[S_ACTIVE_TILES], (unsigned long long)c);
 }
 
-// Admissibility of every particle-step: one ballot per 64 flat steps gives the
-// step bits of one word (or of 64 / Tpad particles).  Admissible steps that lie
-// in a voxel are appended to the coupled list (flat index, voxel bit).
-__global__ __launch_bounds__(256) void k_admit_particles(PGeom pg, const float* __restrict__ at,
-                                                         const uint32_t* __restrict__ bins,
-                                                         float lo, float hi,
-                                                         unsigned long long* __restrict__ Ap,
-                                                         uint2* __restrict__ pend,
-                                                         uint32_t* __restrict__ npend) {
-    const uint64_t n = (uint64_t)pg.P * pg.Tpad;
+// Admissibility of every particle-step, and the labels cleared.  Lanes load 4
+// consecutive steps (16 bytes, non-temporal); the lanes covering one label
+// word (up to 64 steps) OR their nibbles together.  Requires Tpad >= 4.
+__global__ __launch_bounds__(256) void k_admit_particles(Dev d) {
+    const PGeom& pg = d.pg;
+    const float lo = d.crit[2], hi = d.crit[3];
+    const uint64_t n4 = ((uint64_t)pg.P * pg.Tpad) >> 2;
+    const int lanes_per_word = (pg.Tpad >= 64 ? 64 : pg.Tpad) >> 2;
     const int lane = lane_id();
-    const uint64_t wave0 = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
-    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-    for (uint64_t base = wave0 * 256; base < n; base += nwaves * 256) {
-        float a[4];
+    const int sub = lane & (lanes_per_word - 1);
+    const v4f* src = reinterpret_cast<const v4f*>(d.attr_t);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t base0 = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~63u);
+    for (uint64_t base = base0; base < n4; base += 4 * stride) {
+        v4f v[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const uint64_t e = base + k * 64 + lane;
-            a[k] = e < n ? at[e] : __builtin_nanf("");
+            const uint64_t i = base + k * stride + lane;
+            const float nan = __builtin_nanf("");
+            v[k] = i < n4 ? __builtin_nontemporal_load(src + i) : (v4f){nan, nan, nan, nan};
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const uint64_t e0 = base + k * 64;
-            const uint64_t e = e0 + lane;
-            const bool adm = in_band(a[k], lo, hi);
-            const uint64_t m = __ballot(adm);
-            if (e0 < n) {
-                if (pg.Tpad >= 64) {
-                    if (lane == 0) Ap[e0 >> 6] = m;
-                } else {
-                    const int per = 64 >> pg.logTpad;
-                    if (lane < per) {
-                        const uint64_t p = (e0 >> pg.logTpad) + lane;
-                        if (p < (uint64_t)pg.P)
-                            Ap[p] = (m >> (lane * pg.Tpad)) & ((1ull << pg.Tpad) - 1ull);
-                    }
-                }
+            const uint64_t i = base + k * stride + lane;
+            const uint32_t nib = (uint32_t)in_band(v[k].x, lo, hi) |
+                                 ((uint32_t)in_band(v[k].y, lo, hi) << 1) |
+                                 ((uint32_t)in_band(v[k].z, lo, hi) << 2) |
+                                 ((uint32_t)in_band(v[k].w, lo, hi) << 3);
+            unsigned long long x = (unsigned long long)nib << (4 * sub);
+            for (int o = 1; o < lanes_per_word; o <<= 1) x |= __shfl_xor(x, o);
+            if (sub == 0 && i < n4) {
+                // 64 steps per word (Tpad >= 64), else one word per particle
+                const uint64_t wi = pg.Tpad >= 64 ? (i >> 4) : (i / (uint64_t)lanes_per_word);
+                d.Ap[wi] = x;
+                d.Lp[wi] = 0ull;
             }
-            const uint32_t b = adm ? bins[e] : kNoVoxel;
-            const bool c = adm && b != kNoVoxel;
-            const uint32_t idx = wave_append(c, npend);
-            if (c) pend[idx] = make_uint2((uint32_t)e, b);
         }
     }
 }
 
-__global__ void k_seeds(Geom g, const int32_t* __restrict__ seeds, int64_t S,
-                        const uint32_t* __restrict__ A, uint32_t* L,
-                        const uint8_t* __restrict__ active, uint8_t* dirty, uint32_t* dropped) {
+// Same for Tpad < 4 (T <= 2): one thread per particle.
+__global__ void k_admit_particles_short(Dev d) {
+    const PGeom& pg = d.pg;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < pg.P;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        unsigned long long x = 0;
+        for (int t = 0; t < pg.Tpad; ++t)
+            if (in_band(d.attr_t[p * pg.Tpad + t], d.crit[2], d.crit[3])) x |= 1ull << t;
+        d.Ap[p] = x;
+        d.Lp[p] = 0ull;
+    }
+}
+
+// Coupled list: every admissible particle-step that lies in a voxel, as
+// (flat index, voxel bit); one thread per label word, one atomic per block.
+__global__ __launch_bounds__(256) void k_couple(Dev d) {
+    __shared__ uint32_t s_tmp[8];
+    const PGeom& pg = d.pg;
+    const uint64_t nw = (uint64_t)pg.P * pg.W;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t b0 = blockIdx.x * (uint64_t)blockDim.x; b0 < nw; b0 += stride) {
+        const uint64_t i = b0 + threadIdx.x;
+        const unsigned long long m = i < nw ? d.Ap[i] : 0ull;
+        const uint64_t p = pg.W == 1 ? i : i / pg.W;
+        const uint32_t t0 = pg.W == 1 ? 0u : (uint32_t)(i - p * pg.W) * 64u;
+        const uint32_t* row = d.bins + p * pg.Tpad + t0;
+        uint32_t cnt = 0;
+        for (unsigned long long r = m; r; r &= r - 1) cnt += row[__builtin_ctzll(r)] != kNoVoxel;
+        uint32_t k = block_append256(cnt, &d.counters[C_NLIST], s_tmp);
+        for (unsigned long long r = m; r; r &= r - 1) {
+            const int t = __builtin_ctzll(r);
+            const uint32_t b = row[t];
+            if (b != kNoVoxel) d.clist[k++] = make_uint2((uint32_t)(p * pg.Tpad + t0 + t), b);
+        }
+    }
+}
+
+__global__ void k_seeds(Dev d, const int32_t* __restrict__ seeds, int64_t S) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= S) return;
     const int32_t* s = seeds + 4 * i;
-    const uint32_t b = bit_index(g, s[0], s[1], s[2], s[3]);
-    if (test_bit(A, b)) {
+    const uint32_t b = bit_index(d.g, s[0], s[1], s[2], s[3]);
+    if (test_bit(d.Af, b)) {
         const uint32_t bit = 1u << (b & 31);
-        const uint32_t old = atomicOr(&L[b >> 5], bit);
-        if (!(old & bit)) mark_voxel(g, b, active, dirty);
+        if (!(atomicOr(&d.Lf[b >> 5], bit) & bit)) mark_voxel(d, b, 0);
     } else {
-        atomicAdd(dropped, 1u);
+        atomicAdd(&d.counters[C_DROPPED], 1u);
     }
 }
 
-// Dirty tile flags -> compact work list (ballot prefix, one atomic per wave).
-__global__ void k_compact_tiles(uint32_t NT, uint8_t* __restrict__ dirty, uint32_t* __restrict__ work,
-                                uint32_t* nwork) {
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t base = blockIdx.x * blockDim.x; base < NT; base += stride) {
-        const uint32_t i = base + threadIdx.x;
-        bool d = false;
-        if (i < NT) {
-            d = dirty[i] != 0;
-            if (d) dirty[i] = 0;
-        }
-        const uint32_t idx = wave_append(d, nwork);
-        if (d) work[idx] = i;
-    }
-}
+// ---- one round as three launches ----
 
-// Put a work list back as dirty flags (a round cap stopped before sweeping it).
-__global__ void k_mark_work(const uint32_t* __restrict__ work, const uint32_t* __restrict__ nwork_p,
-                            uint8_t* dirty) {
-    const uint32_t n = *nwork_p;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        dirty[work[i]] = 1;
-}
-
-// One wavefront sweeps one tile to a local fixed point.  Lane = (z_l, y_l);
-// each lane holds the BT words of its (y, z) column over the tile's timesteps
-// in registers.  Per iteration: one Jacobi step in y and z (lane shuffles),
-// complete fills along x inside each word, and complete forward / backward
-// passes along t.  Neighbour-tile words enter as fixed halos; when a face of
-// this tile gains bits, the tile across that face is marked for the next round.
 template <int BT>
-__global__ __launch_bounds__(256) void k_sweep(Geom g, const uint32_t* __restrict__ A, uint32_t* L,
-                                               const uint8_t* __restrict__ active,
-                                               const uint32_t* __restrict__ work,
-                                               const uint32_t* __restrict__ nwork_p,
-                                               uint8_t* dirty, unsigned long long* visits) {
-    const int lane = lane_id();
-    const int yl = lane & 7, zl = lane >> 3;
-    const uint32_t nwork = *nwork_p;
+__global__ __launch_bounds__(256) void k_round_sweep(Dev d, int par) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.counters[C_NDIRTYP] = 0;
+    const uint32_t nwork = d.counters[C_NWORK0 + par];
     const uint32_t wave0 = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    const uint32_t sy = g.NXt, sz = g.NXt * g.NYt, st = sz * g.NZt;
-    uint32_t myvisits = 0;
-    for (uint32_t wi = wave0; wi < nwork; wi += nwaves) {
-        const uint32_t tile = work[wi];
-        int tx, ty, tz, tt;
-        tile_coords(g, tile, tx, ty, tz, tt);
-        const uint32_t* Ab = A + (size_t)tile * (64 * BT);
-        uint32_t* Lb = L + (size_t)tile * (64 * BT);
-        uint32_t a[BT], l[BT], l0[BT], xin[BT], yh[BT], zh[BT];
-#pragma unroll
-        for (int t = 0; t < BT; ++t) {
-            a[t] = Ab[t * 64 + lane];
-            l[t] = Lb[t * 64 + lane];
-        }
-        const uint32_t* Lxm = tx > 0 ? Lb - 64 * BT : nullptr;
-        const uint32_t* Lxp = tx + 1 < g.NXt ? Lb + 64 * BT : nullptr;
-        const uint32_t* Ly = nullptr;
-        int yoff = 0;
-        if (yl == 0 && ty > 0) { Ly = Lb - (size_t)sy * 64 * BT; yoff = 7; }
-        if (yl == 7 && ty + 1 < g.NYt) { Ly = Lb + (size_t)sy * 64 * BT; yoff = -7; }
-        const uint32_t* Lz = nullptr;
-        int zoff = 0;
-        if (zl == 0 && tz > 0) { Lz = Lb - (size_t)sz * 64 * BT; zoff = 56; }
-        if (zl == 7 && tz + 1 < g.NZt) { Lz = Lb + (size_t)sz * 64 * BT; zoff = -56; }
-#pragma unroll
-        for (int t = 0; t < BT; ++t) {
-            xin[t] = (Lxm ? (Lxm[t * 64 + lane] >> 31) : 0u) | (Lxp ? (Lxp[t * 64 + lane] << 31) : 0u);
-            yh[t] = Ly ? Ly[t * 64 + lane + yoff] : 0u;
-            zh[t] = Lz ? Lz[t * 64 + lane + zoff] : 0u;
-            l0[t] = l[t];
-        }
-        const uint32_t tm = tt > 0 ? (Lb - (size_t)st * 64 * BT)[(BT - 1) * 64 + lane] : 0u;
-        const uint32_t tp = tt + 1 < g.NTt ? (Lb + (size_t)st * 64 * BT)[lane] : 0u;
-        while (true) {
-            uint32_t s[BT];
-#pragma unroll
-            for (int t = 0; t < BT; ++t) {
-                const uint32_t v = l[t];
-                const uint32_t ym = __shfl_up(v, 1), yp = __shfl_down(v, 1);
-                const uint32_t zm = __shfl_up(v, 8), zp = __shfl_down(v, 8);
-                uint32_t nb = v | (v << 1) | (v >> 1) | xin[t] | yh[t] | zh[t];
-                nb |= (yl > 0 ? ym : 0u) | (yl < 7 ? yp : 0u) | (zl > 0 ? zm : 0u) |
-                      (zl < 7 ? zp : 0u);
-                s[t] = fill_runs32(nb & a[t], a[t]);
-            }
-            s[0] |= fill_runs32(tm & a[0], a[0]);
-#pragma unroll
-            for (int t = 1; t < BT; ++t) s[t] |= fill_runs32(s[t - 1] & a[t], a[t]);
-            s[BT - 1] |= fill_runs32(tp & a[BT - 1], a[BT - 1]);
-#pragma unroll
-            for (int t = BT - 2; t >= 0; --t) s[t] |= fill_runs32(s[t + 1] & a[t], a[t]);
-            uint32_t diff = 0;
-#pragma unroll
-            for (int t = 0; t < BT; ++t) {
-                diff |= s[t] ^ l[t];
-                l[t] = s[t];
-            }
-            if (__ballot(diff != 0) == 0) break;
-        }
-        uint32_t any = 0, fx0 = 0, fx1 = 0;
-#pragma unroll
-        for (int t = 0; t < BT; ++t) {
-            const uint32_t nw = l[t] & ~l0[t];
-            if (nw) atomicOr(&Lb[t * 64 + lane], nw);
-            any |= nw;
-            fx0 |= nw & 1u;
-            fx1 |= nw >> 31;
-        }
-        const uint32_t nt0 = l[0] & ~l0[0], nt1 = l[BT - 1] & ~l0[BT - 1];
-        const uint64_t b_any = __ballot(any != 0);
-        if (b_any) {
-            const bool fxm = __ballot(fx0 != 0) != 0, fxp = __ballot(fx1 != 0) != 0;
-            const bool fym = __ballot(yl == 0 && any) != 0, fyp = __ballot(yl == 7 && any) != 0;
-            const bool fzm = __ballot(zl == 0 && any) != 0, fzp = __ballot(zl == 7 && any) != 0;
-            const bool ftm = __ballot(nt0 != 0) != 0, ftp = __ballot(nt1 != 0) != 0;
-            if (lane == 0) {
-                uint32_t nb[8];
-                int k = 0;
-                if (fxm && tx > 0) nb[k++] = tile - 1;
-                if (fxp && tx + 1 < g.NXt) nb[k++] = tile + 1;
-                if (fym && ty > 0) nb[k++] = tile - sy;
-                if (fyp && ty + 1 < g.NYt) nb[k++] = tile + sy;
-                if (fzm && tz > 0) nb[k++] = tile - sz;
-                if (fzp && tz + 1 < g.NZt) nb[k++] = tile + sz;
-                if (ftm && tt > 0) nb[k++] = tile - st;
-                if (ftp && tt + 1 < g.NTt) nb[k++] = tile + st;
-                for (int i = 0; i < k; ++i)
-                    if (active[nb[i]]) dirty[nb[i]] = 1;
-            }
-        }
-        ++myvisits;
+    uint32_t visits = 0;
+    for (uint32_t w = wave0; w < nwork; w += nwaves) {
+        sweep_tile<BT>(d, d.work[par * d.g.NT + w], par);
+        ++visits;
     }
-    if (lane == 0 && myvisits) atomicAdd(visits, (unsigned long long)myvisits);
+    if (lane_id() == 0 && visits) atomicAdd(&d.stat64[S_TILE_VISITS], (unsigned long long)visits);
 }
 
-// Pull: a pending coupled particle-step joins when the voxel holding it is a
-// member.  Steps that joined (now or earlier) leave the pending list; a
-// particle that gained a step goes on the dirty-particle list once.
-__global__ __launch_bounds__(256) void k_pull(PGeom pg, const uint2* __restrict__ pin,
-                                              const uint32_t* __restrict__ nin_p,
-                                              uint2* __restrict__ pout, uint32_t* nout,
-                                              const uint32_t* __restrict__ Lf,
-                                              unsigned long long* Lp, uint32_t* pdirty,
-                                              uint32_t* dlist, uint32_t* ndlist) {
-    const uint32_t nin = *nin_p;
+__global__ __launch_bounds__(256) void k_round_pull(Dev d, int par) {
+    __shared__ uint32_t s_tmp[8];
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.counters[C_NWORK0 + par] = 0;
+    const uint32_t n = d.counters[C_NLIST];
+    for (uint32_t cb = blockIdx.x * 1024u; cb < n; cb += gridDim.x * 1024u)
+        pull_chunk(d, cb, n, par, s_tmp);
+}
+
+__global__ __launch_bounds__(256) void k_round_close(Dev d, int par) {
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t base = blockIdx.x * blockDim.x; base < nin; base += stride) {
-        const uint32_t i = base + threadIdx.x;
-        bool keep = false, first = false;
-        uint2 ent = make_uint2(0, 0);
-        uint32_t p = 0;
-        if (i < nin) {
-            ent = pin[i];
-            const uint32_t e = ent.x;
-            uint32_t t;
-            if (pg.logTpad >= 0) {
-                p = e >> pg.logTpad;
-                t = e & (pg.Tpad - 1);
-            } else {
-                p = e / (uint32_t)pg.Tpad;
-                t = e - p * (uint32_t)pg.Tpad;
-            }
-            const uint32_t wi = p * (uint32_t)pg.W + (t >> 6);
-            const unsigned long long bit = 1ull << (t & 63);
-            if (!(Lp[wi] & bit)) {
-                if (test_bit(Lf, ent.y)) {
-                    atomicOr(&Lp[wi], bit);
-                    const uint32_t pb = 1u << (p & 31);
-                    first = !(atomicOr(&pdirty[p >> 5], pb) & pb);
-                } else {
-                    keep = true;
-                }
-            }
-        }
-        const uint32_t k = wave_append(keep, nout);
-        if (keep) pout[k] = ent;
-        const uint32_t d = wave_append(first, ndlist);
-        if (first) dlist[d] = p;
-    }
+    for (uint32_t i = tid; i < d.g.NT; i += stride) d.chg[par * d.g.NT + i] = 0;
+    const uint32_t nd = d.counters[C_NDIRTYP];
+    if (tid == 0 && nd) atomicAdd(&d.stat64[S_PART_VISITS], (unsigned long long)nd);
+    for (uint32_t i = tid; i < nd; i += stride) close_particle(d, d.dlist[i], par ^ 1);
 }
 
-// Close and push: a dirty particle's member steps spread over each run of
-// admissible steps that holds them (its trajectory), and every step that
-// joins pushes its voxel in when that voxel is admissible.
-__global__ __launch_bounds__(256) void k_close_push(Geom g, PGeom pg, const uint32_t* __restrict__ dlist,
-                                                    const uint32_t* __restrict__ nd_p,
-                                                    const unsigned long long* __restrict__ Ap,
-                                                    unsigned long long* Lp, uint32_t* pdirty,
-                                                    const uint32_t* __restrict__ bins,
-                                                    const uint32_t* __restrict__ Af, uint32_t* Lf,
-                                                    const uint8_t* __restrict__ active,
-                                                    uint8_t* dirty, unsigned long long* visits) {
-    const uint32_t nd = *nd_p;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && nd) atomicAdd(visits, (unsigned long long)nd);
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += gridDim.x * blockDim.x) {
-        const uint32_t p = dlist[i];
-        atomicAnd(&pdirty[p >> 5], ~(1u << (p & 31)));
-        const int W = pg.W;
-        unsigned long long* lw = Lp + (size_t)p * W;
-        const unsigned long long* aw = Ap + (size_t)p * W;
-        // forward pass (carry over word boundaries upward), then backward
-        unsigned long long carry = 0;
-        for (int w = 0; w < W; ++w) {
-            const unsigned long long a = aw[w], l0 = lw[w];
-            unsigned long long l = l0 | (carry & a & 1ull);
-            l = fill_runs64(l, a);
-            carry = l >> 63;
-            const unsigned long long nw = l & ~l0;
-            if (nw) {
-                atomicOr(&lw[w], nw);
-                unsigned long long m = nw;
-                while (m) {
-                    const int t = __builtin_ctzll(m);
-                    m &= m - 1;
-                    const uint32_t b = bins[(size_t)p * pg.Tpad + w * 64 + t];
-                    if (b != kNoVoxel && test_bit(Af, b)) {
-                        const uint32_t bit = 1u << (b & 31);
-                        if (!(atomicOr(&Lf[b >> 5], bit) & bit)) mark_voxel(g, b, active, dirty);
-                    }
-                }
-            }
+// ---- all rounds in one cooperative launch ----
+template <int BT>
+__global__ __launch_bounds__(256) void k_rounds(Dev d, uint32_t round0, uint32_t max_rounds) {
+    __shared__ uint32_t s_tmp[8];
+    uint32_t epoch = 0;
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t nthreads = gridDim.x * blockDim.x;
+    const uint32_t wave0 = tid >> 6, nwaves = nthreads >> 6;
+    const bool parts = d.pg.P > 0;
+    uint32_t r = round0;
+    uint32_t visits = 0;
+    while (true) {
+        const int par = r & 1;
+        const uint32_t nwork = load_relaxed(&d.counters[C_NWORK0 + par]);
+        if (nwork == 0 || (max_rounds && r - round0 >= max_rounds)) break;
+        // sweep
+        if (tid == 0) store_relaxed(&d.counters[C_NDIRTYP], 0u);
+        for (uint32_t w = wave0; w < nwork; w += nwaves) {
+            sweep_tile<BT>(d, d.work[par * d.g.NT + w], par);
+            ++visits;
         }
-        carry = 0;
-        for (int w = W - 1; w >= 0; --w) {
-            const unsigned long long a = aw[w], l0 = lw[w];
-            unsigned long long l = l0 | ((carry << 63) & a);
-            l = fill_runs64(l, a);
-            carry = l & 1ull;
-            const unsigned long long nw = l & ~l0;
-            if (nw) {
-                atomicOr(&lw[w], nw);
-                unsigned long long m = nw;
-                while (m) {
-                    const int t = __builtin_ctzll(m);
-                    m &= m - 1;
-                    const uint32_t b = bins[(size_t)p * pg.Tpad + w * 64 + t];
-                    if (b != kNoVoxel && test_bit(Af, b)) {
-                        const uint32_t bit = 1u << (b & 31);
-                        if (!(atomicOr(&Lf[b >> 5], bit) & bit)) mark_voxel(g, b, active, dirty);
-                    }
-                }
-            }
+        if (!grid_sync(d, epoch)) break;
+        // pull
+        if (tid == 0) store_relaxed(&d.counters[C_NWORK0 + par], 0u);
+        if (parts) {
+            const uint32_t n = load_relaxed(&d.counters[C_NLIST]);
+            for (uint32_t cb = blockIdx.x * 1024u; cb < n; cb += gridDim.x * 1024u)
+                pull_chunk(d, cb, n, par, s_tmp);
         }
+        if (!grid_sync(d, epoch)) break;
+        // close and push
+        for (uint32_t i = tid; i < d.g.NT; i += nthreads) d.chg[par * d.g.NT + i] = 0;
+        if (parts) {
+            const uint32_t nd = load_relaxed(&d.counters[C_NDIRTYP]);
+            if (tid == 0 && nd) atomicAdd(&d.stat64[S_PART_VISITS], (unsigned long long)nd);
+            for (uint32_t i = tid; i < nd; i += nthreads) close_particle(d, d.dlist[i], par ^ 1);
+        }
+        if (!grid_sync(d, epoch)) break;
+        ++r;
     }
+    if (lane_id() == 0 && visits) atomicAdd(&d.stat64[S_TILE_VISITS], (unsigned long long)visits);
+    if (tid == 0) store_relaxed(&d.counters[C_ROUNDS], r - round0);
 }
+
+// ---- read-out ----
 
 // Field labels -> canonical bit words ((t*Z + z)*Y + y)*X + x, with a member
-// count.  Fast path when X is a multiple of 32 (a canonical word is one tile
-// word); otherwise bit by bit.
-__global__ __launch_bounds__(256) void k_read_field(Geom g, const uint32_t* __restrict__ L,
-                                                    uint32_t* __restrict__ out,
-                                                    unsigned long long* members) {
+// count.  When X is a multiple of 32 a canonical word is one tile word: a block
+// stages up to 8 x-consecutive tiles in LDS (rows padded by one word against
+// bank conflicts) and writes whole canonical rows.  Otherwise bit by bit.
+template <int BT>
+__global__ __launch_bounds__(256) void k_read_field_tiles(Dev d, uint32_t* __restrict__ out) {
+    constexpr int WPT = 64 * BT;
+    __shared__ uint32_t sl[8 * (WPT + 1)];
+    const Geom& g = d.g;
+    const int ty = blockIdx.x, tz = blockIdx.y, tt = blockIdx.z;
+    uint32_t cnt = 0;
+    for (int tx0 = 0; tx0 < g.NXt; tx0 += 8) {
+        const int ntx = min(8, g.NXt - tx0);
+        const uint32_t* src = d.Lf + (size_t)tile_of(g, tx0, ty, tz, tt) * WPT;
+        for (int i = threadIdx.x; i < ntx * WPT; i += 256) {
+            const int txl = i / WPT, w = i - txl * WPT;
+            sl[txl * (WPT + 1) + w] = src[i];
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < ntx * WPT; i += 256) {
+            const int txl = i % ntx, w = i / ntx;
+            const int yl = w & 7, zl = (w >> 3) & 7, tl = w >> 6;
+            const int y = ty * 8 + yl, z = tz * 8 + zl, t = tt * BT + tl;
+            if (y < g.Y && z < g.Z && t < g.T) {
+                const uint32_t v = sl[txl * (WPT + 1) + w];
+                out[((size_t)(t * g.Z + z) * g.Y + y) * g.NXt + tx0 + txl] = v;
+                cnt += __popc(v);
+            }
+        }
+        __syncthreads();
+    }
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+    if (lane_id() == 0 && cnt) atomicAdd(&d.stat64[S_MEMBERS_F], (unsigned long long)cnt);
+}
+
+__global__ __launch_bounds__(256) void k_read_field_bits(Dev d, uint32_t* __restrict__ out) {
+    const Geom& g = d.g;
     const uint64_t V = (uint64_t)g.X * g.Y * g.Z * g.T;
     const uint64_t nw = (V + 31) >> 5;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     uint32_t cnt = 0;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nw; i += stride) {
         uint32_t w = 0;
-        if ((g.X & 31) == 0) {
-            const uint32_t wpr = g.X >> 5;
-            const uint32_t row = (uint32_t)(i / wpr);
-            const int x0 = (int)(i - (uint64_t)row * wpr) * 32;
-            const int y = row % g.Y;
-            const uint32_t r2 = row / g.Y;
-            const int z = r2 % g.Z, t = r2 / g.Z;
-            w = L[bit_index(g, x0, y, z, t) >> 5];
-        } else {
-            for (int k = 0; k < 32; ++k) {
-                const uint64_t bi = i * 32 + k;
-                if (bi >= V) break;
-                const uint32_t x = (uint32_t)(bi % g.X);
-                const uint64_t r = bi / g.X;
-                const int y = r % g.Y;
-                const uint64_t r2 = r / g.Y;
-                const int z = r2 % g.Z, t = (int)(r2 / g.Z);
-                if (test_bit(L, bit_index(g, (int)x, y, z, t))) w |= 1u << k;
-            }
+        for (int k = 0; k < 32; ++k) {
+            const uint64_t bi = i * 32 + k;
+            if (bi >= V) break;
+            const uint32_t x = (uint32_t)(bi % g.X);
+            const uint64_t r = bi / g.X;
+            const int y = r % g.Y;
+            const uint64_t r2 = r / g.Y;
+            const int z = r2 % g.Z, t = (int)(r2 / g.Z);
+            if (test_bit(d.Lf, bit_index(g, (int)x, y, z, t))) w |= 1u << k;
         }
         out[i] = w;
         cnt += __popc(w);
     }
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-    if (lane_id() == 0 && cnt) atomicAdd(members, (unsigned long long)cnt);
+    if (lane_id() == 0 && cnt) atomicAdd(&d.stat64[S_MEMBERS_F], (unsigned long long)cnt);
 }
 
-// Particle labels -> uint8 [T][P].  A thread owns 4 consecutive particles and
-// writes their 4 bytes per timestep as one 32-bit store when aligned.
-__global__ __launch_bounds__(256) void k_read_particles(PGeom pg, const unsigned long long* __restrict__ Lp,
-                                                        uint8_t* __restrict__ out,
-                                                        unsigned long long* members) {
+// Particle labels -> uint8 [T][P].  Fast path (one label word per particle,
+// P a multiple of 16): a thread owns 16 consecutive particles and writes their
+// 16 bytes of each timestep as one 16-byte store.
+__global__ __launch_bounds__(256) void k_read_particles16(Dev d, uint8_t* __restrict__ out) {
+    const PGeom& pg = d.pg;
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t p0 = q * 16;
+    uint32_t cnt = 0;
+    if (p0 < pg.P) {
+        unsigned long long lw[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            lw[k] = d.Lp[p0 + k];
+            cnt += __popcll(lw[k]);
+        }
+        for (int t = 0; t < pg.T; ++t) {
+            uint32_t v[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                v[j] = (uint32_t)((lw[4 * j] >> t) & 1) | ((uint32_t)((lw[4 * j + 1] >> t) & 1) << 8) |
+                       ((uint32_t)((lw[4 * j + 2] >> t) & 1) << 16) |
+                       ((uint32_t)((lw[4 * j + 3] >> t) & 1) << 24);
+            *reinterpret_cast<uint4*>(out + (int64_t)t * pg.P + p0) = make_uint4(v[0], v[1], v[2], v[3]);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+    if (lane_id() == 0 && cnt) atomicAdd(&d.stat64[S_MEMBERS_P], (unsigned long long)cnt);
+}
+
+// General particle read-out: a thread owns 4 consecutive particles.
+__global__ __launch_bounds__(256) void k_read_particles(Dev d, uint8_t* __restrict__ out) {
+    const PGeom& pg = d.pg;
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t p0 = q * 4;
     uint32_t cnt = 0;
     if (p0 < pg.P) {
         const int np = (int)min((int64_t)4, pg.P - p0);
-        const bool vec = np == 4 && (pg.P & 3) == 0;
         for (int w = 0; w < pg.W; ++w) {
             unsigned long long lw[4] = {0, 0, 0, 0};
             for (int k = 0; k < np; ++k) {
-                lw[k] = Lp[(size_t)(p0 + k) * pg.W + w];
+                lw[k] = d.Lp[(size_t)(p0 + k) * pg.W + w];
                 cnt += __popcll(lw[k]);
             }
             const int tend = min(64, pg.T - w * 64);
             for (int tl = 0; tl < tend; ++tl) {
                 const int64_t t = w * 64 + tl;
                 uint8_t* o = out + t * pg.P + p0;
-                if (vec) {
-                    const uint32_t v = (uint32_t)((lw[0] >> tl) & 1) | ((uint32_t)((lw[1] >> tl) & 1) << 8) |
-                                       ((uint32_t)((lw[2] >> tl) & 1) << 16) |
-                                       ((uint32_t)((lw[3] >> tl) & 1) << 24);
-                    *reinterpret_cast<uint32_t*>(o) = v;
-                } else {
-                    for (int k = 0; k < np; ++k) o[k] = (uint8_t)((lw[k] >> tl) & 1);
-                }
+                for (int k = 0; k < np; ++k) o[k] = (uint8_t)((lw[k] >> tl) & 1);
             }
         }
     }
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-    if (lane_id() == 0 && cnt) atomicAdd(members, (unsigned long long)cnt);
+    if (lane_id() == 0 && cnt) atomicAdd(&d.stat64[S_MEMBERS_P], (unsigned long long)cnt);
 }
 
 inline unsigned grid_for(uint64_t n, unsigned block, unsigned cap) {
@@ -617,6 +822,23 @@ inline unsigned grid_for(uint64_t n, unsigned block, unsigned cap) {
     if (b < 1) b = 1;
     if (b > cap) b = cap;
     return (unsigned)b;
+}
+
+template <int BT>
+bool coop_rounds(const Dev& d, uint32_t round0, uint32_t max_rounds, int device, hipStream_t s) {
+    int per_cu = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rounds<BT>, 256, 0) != hipSuccess ||
+        per_cu <= 0)
+        return false;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        ncu <= 0)
+        return false;
+    Dev dd = d;
+    uint32_t r0 = round0, mr = max_rounds;
+    void* args[] = {&dd, &r0, &mr};
+    const dim3 grid((unsigned)(per_cu * ncu));
+    return hipLaunchCooperativeKernel((const void*)k_rounds<BT>, grid, dim3(256), args, 0, s) ==
+           hipSuccess;
 }
 
 }  // namespace
@@ -629,6 +851,11 @@ void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, p, v, n);
 }
 
+void launch_reset(const Dev& d, hipStream_t s) {
+    const uint64_t n = 2ull * d.g.NT + (uint64_t)(d.pg.P + 31) / 32;
+    hipLaunchKernelGGL(k_reset, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, d);
+}
+
 void launch_bin_particles(const Geom& g, const PGeom& pg, const float* xyz, const float* attr,
                           uint32_t* bins, float* attr_t, hipStream_t s) {
     if (pg.P == 0) return;
@@ -636,99 +863,79 @@ void launch_bin_particles(const Geom& g, const PGeom& pg, const float* xyz, cons
     hipLaunchKernelGGL(k_bin_particles, dim3(nb), dim3(256), 0, s, g, pg, xyz, attr, bins, attr_t);
 }
 
-void launch_admit_field(const Geom& g, const float* field, float lo, float hi, uint32_t* A,
-                        uint8_t* active, hipStream_t s) {
-    hipLaunchKernelGGL(k_admit_field, dim3(g.NYt, g.NZt, g.T), dim3(256), 0, s, g, field, lo, hi,
-                       A, active);
+void launch_admit_field(const Dev& d, hipStream_t s) {
+    hipLaunchKernelGGL(k_admit_field, dim3(d.g.NYt, d.g.NZt, d.g.T), dim3(256), 0, s, d);
+    hipLaunchKernelGGL(k_count_active, dim3(grid_for(d.g.NT, 256, 1024)), dim3(256), 0, s, d);
 }
 
-void launch_count_active(const Geom& g, const uint8_t* active, unsigned long long* stat,
-                         hipStream_t s) {
-    hipLaunchKernelGGL(k_count_active, dim3(grid_for(g.NT, 256, 1024)), dim3(256), 0, s, g, active,
-                       stat);
+void launch_admit_particles(const Dev& d, hipStream_t s) {
+    const PGeom& pg = d.pg;
+    if (pg.P == 0) return;
+    if (pg.Tpad >= 4) {
+        const uint64_t n4 = ((uint64_t)pg.P * pg.Tpad) >> 2;
+        hipLaunchKernelGGL(k_admit_particles, dim3(grid_for(n4 / 4, 256, 16384)), dim3(256), 0, s, d);
+    } else {
+        hipLaunchKernelGGL(k_admit_particles_short, dim3(grid_for(pg.P, 256, 4096)), dim3(256), 0, s,
+                           d);
+    }
+    hipLaunchKernelGGL(k_couple, dim3(grid_for((uint64_t)pg.P * pg.W, 256, 8192)), dim3(256), 0, s,
+                       d);
 }
 
-void launch_admit_particles(const PGeom& pg, const float* attr_t, const uint32_t* bins, float lo,
-                            float hi, unsigned long long* Ap, uint2* pend, uint32_t* npend,
-                            hipStream_t s) {
-    const uint64_t n = (uint64_t)pg.P * pg.Tpad;
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_admit_particles, dim3(grid_for(n / 4, 256, 16384)), dim3(256), 0, s, pg,
-                       attr_t, bins, lo, hi, Ap, pend, npend);
-}
-
-void launch_seeds(const Geom& g, const int32_t* seeds, int64_t S, const uint32_t* A, uint32_t* L,
-                  const uint8_t* active, uint8_t* dirty, uint32_t* dropped, hipStream_t s) {
+void launch_seeds(const Dev& d, const int32_t* seeds, int64_t S, hipStream_t s) {
     if (S == 0) return;
-    hipLaunchKernelGGL(k_seeds, dim3(grid_for(S, 256, 1u << 20)), dim3(256), 0, s, g, seeds, S, A,
-                       L, active, dirty, dropped);
+    hipLaunchKernelGGL(k_seeds, dim3(grid_for(S, 256, 1u << 20)), dim3(256), 0, s, d, seeds, S);
 }
 
-void launch_compact_tiles(const Geom& g, uint8_t* dirty, uint32_t* work, uint32_t* nwork,
-                          hipStream_t s) {
-    hipLaunchKernelGGL(k_compact_tiles, dim3(grid_for(g.NT, 256, 2048)), dim3(256), 0, s, g.NT,
-                       dirty, work, nwork);
-}
-
-void launch_mark_work(const uint32_t* work, const uint32_t* nwork, uint32_t nwork_host,
-                      uint8_t* dirty, hipStream_t s) {
-    if (nwork_host == 0) return;
-    hipLaunchKernelGGL(k_mark_work, dim3(grid_for(nwork_host, 256, 4096)), dim3(256), 0, s, work,
-                       nwork, dirty);
-}
-
-void launch_sweep(const Geom& g, const uint32_t* A, uint32_t* L, const uint8_t* active,
-                  const uint32_t* work, const uint32_t* nwork, uint32_t nwork_host,
-                  uint8_t* dirty, unsigned long long* visits, hipStream_t s) {
-    if (nwork_host == 0) return;
+void launch_round(const Dev& d, uint32_t round, uint32_t nwork_host, hipStream_t s) {
+    const int par = round & 1;
     const unsigned blocks = grid_for((uint64_t)nwork_host * 64, 256, 8192);
-    switch (g.BT) {
-        case 4:
-            hipLaunchKernelGGL(k_sweep<4>, dim3(blocks), dim3(256), 0, s, g, A, L, active, work,
-                               nwork, dirty, visits);
-            break;
-        case 8:
-            hipLaunchKernelGGL(k_sweep<8>, dim3(blocks), dim3(256), 0, s, g, A, L, active, work,
-                               nwork, dirty, visits);
-            break;
-        default:
-            hipLaunchKernelGGL(k_sweep<16>, dim3(blocks), dim3(256), 0, s, g, A, L, active, work,
-                               nwork, dirty, visits);
-            break;
+    switch (d.g.BT) {
+        case 4: hipLaunchKernelGGL(k_round_sweep<4>, dim3(blocks), dim3(256), 0, s, d, par); break;
+        case 8: hipLaunchKernelGGL(k_round_sweep<8>, dim3(blocks), dim3(256), 0, s, d, par); break;
+        default: hipLaunchKernelGGL(k_round_sweep<16>, dim3(blocks), dim3(256), 0, s, d, par); break;
+    }
+    const uint64_t Q = (uint64_t)d.pg.P * d.pg.Tpad;
+    hipLaunchKernelGGL(k_round_pull, dim3(grid_for(Q / 4, 256, 2048)), dim3(256), 0, s, d, par);
+    const uint64_t nclose = (uint64_t)d.g.NT > (uint64_t)d.pg.P ? (uint64_t)d.g.NT : (uint64_t)d.pg.P;
+    hipLaunchKernelGGL(k_round_close, dim3(grid_for(nclose, 256, 2048)), dim3(256), 0, s, d, par);
+}
+
+bool launch_rounds_persistent(const Dev& d, uint32_t round0, uint32_t max_rounds, int device,
+                              hipStream_t s) {
+    switch (d.g.BT) {
+        case 4: return coop_rounds<4>(d, round0, max_rounds, device, s);
+        case 8: return coop_rounds<8>(d, round0, max_rounds, device, s);
+        default: return coop_rounds<16>(d, round0, max_rounds, device, s);
     }
 }
 
-void launch_pull(const PGeom& pg, const uint2* pin, const uint32_t* nin, uint32_t nin_host,
-                 uint2* pout, uint32_t* nout, const uint32_t* Lf, unsigned long long* Lp,
-                 uint32_t* pdirty, uint32_t* dlist, uint32_t* ndlist, hipStream_t s) {
-    if (nin_host == 0) return;
-    hipLaunchKernelGGL(k_pull, dim3(grid_for(nin_host, 256, 8192)), dim3(256), 0, s, pg, pin, nin,
-                       pout, nout, Lf, Lp, pdirty, dlist, ndlist);
-}
-
-void launch_close_push(const Geom& g, const PGeom& pg, const uint32_t* dlist,
-                       const uint32_t* ndlist, uint32_t ndlist_host,
-                       const unsigned long long* Ap, unsigned long long* Lp, uint32_t* pdirty,
-                       const uint32_t* bins, const uint32_t* Af, uint32_t* Lf,
-                       const uint8_t* active, uint8_t* dirty, unsigned long long* visits,
-                       hipStream_t s) {
-    if (ndlist_host == 0) return;
-    hipLaunchKernelGGL(k_close_push, dim3(grid_for(ndlist_host, 256, 2048)), dim3(256), 0, s, g,
-                       pg, dlist, ndlist, Ap, Lp, pdirty, bins, Af, Lf, active, dirty, visits);
-}
-
-void launch_read_field(const Geom& g, const uint32_t* L, uint32_t* out,
-                       unsigned long long* members, hipStream_t s) {
+void launch_read_field(const Dev& d, uint32_t* out, hipStream_t s) {
+    const Geom& g = d.g;
+    if ((g.X & 31) == 0) {
+        const dim3 grid(g.NYt, g.NZt, g.NTt);
+        switch (g.BT) {
+            case 4: hipLaunchKernelGGL(k_read_field_tiles<4>, grid, dim3(256), 0, s, d, out); break;
+            case 8: hipLaunchKernelGGL(k_read_field_tiles<8>, grid, dim3(256), 0, s, d, out); break;
+            default: hipLaunchKernelGGL(k_read_field_tiles<16>, grid, dim3(256), 0, s, d, out); break;
+        }
+        return;
+    }
     const uint64_t V = (uint64_t)g.X * g.Y * g.Z * g.T;
-    hipLaunchKernelGGL(k_read_field, dim3(grid_for((V + 31) / 32, 256, 16384)), dim3(256), 0, s, g,
-                       L, out, members);
+    hipLaunchKernelGGL(k_read_field_bits, dim3(grid_for((V + 31) / 32, 256, 16384)), dim3(256), 0,
+                       s, d, out);
 }
 
-void launch_read_particles(const PGeom& pg, const unsigned long long* Lp, uint8_t* out,
-                           unsigned long long* members, hipStream_t s) {
+void launch_read_particles(const Dev& d, uint8_t* out, hipStream_t s) {
+    const PGeom& pg = d.pg;
     if (pg.P == 0) return;
+    if (pg.W == 1 && (pg.P & 15) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
+        hipLaunchKernelGGL(k_read_particles16, dim3(grid_for(pg.P / 16, 256, 1u << 20)), dim3(256),
+                           0, s, d, out);
+        return;
+    }
     hipLaunchKernelGGL(k_read_particles, dim3(grid_for((pg.P + 3) / 4, 256, 1u << 20)), dim3(256),
-                       0, s, pg, Lp, out, members);
+                       0, s, d, out);
 }
 
 }  // namespace mf4d

@@ -38,11 +38,13 @@ struct PGeom {
 
 // Counters kept in one small device array.
 enum Counter : int {
-    C_NWORK = 0,   // tiles on the current work list
-    C_PEND0 = 1,   // pending coupled particle-steps, buffer 0
-    C_PEND1 = 2,   // pending coupled particle-steps, buffer 1
-    C_NDIRTYP = 3, // particles on the dirty list
+    C_NWORK0 = 0,  // tiles on work list 0 (even rounds)
+    C_NWORK1 = 1,  // tiles on work list 1 (odd rounds)
+    C_NDIRTYP = 2, // particles on the dirty list
+    C_NLIST = 3,   // coupled particle-steps on the flat list
     C_DROPPED = 4, // dropped seeds
+    C_ERR = 5,     // set by the persistent kernel if a grid barrier timed out
+    C_ROUNDS = 6,  // rounds completed by the persistent kernel
     C_NCOUNTERS = 8
 };
 
@@ -55,38 +57,44 @@ enum Stat64 : int {
     S_NSTAT = 8
 };
 
+// Every device buffer of a context, passed by value to the kernels.
+struct Dev {
+    Geom g;
+    PGeom pg;
+    const float* field;      // fp32 [T][Z][Y][X]
+    uint32_t* Af;            // admissibility bits, tile layout
+    uint32_t* Lf;            // label bits, tile layout
+    uint8_t* active;         // NT: tile holds an admissible voxel-step
+    uint32_t* dirty;         // 2 x NT: tile scheduled for round parity 0 / 1
+    uint8_t* chg;            // 2 x NT: tile's members changed since its last pull
+    uint32_t* work;          // 2 x NT: work lists of round parity 0 / 1
+    const uint32_t* bins;    // [P][Tpad] voxel bit of each particle-step, or kNoVoxel
+    const float* attr_t;     // [P][Tpad] particle values (NaN padding)
+    unsigned long long* Ap;  // [P][W] admissibility bits
+    unsigned long long* Lp;  // [P][W] label bits
+    uint2* clist;            // coupled steps (flat index, voxel bit)
+    uint32_t* pdirty;        // P bits: particle on this round's dirty list
+    uint32_t* dlist;         // dirty particles
+    uint32_t* counters;      // Counter
+    unsigned long long* stat64;
+    uint32_t* bar;           // grid barrier arrival counter
+    float crit[4];
+};
+
 // ---- launchers (kernels.hip) ----
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
+void launch_reset(const Dev& d, hipStream_t s);
 void launch_bin_particles(const Geom& g, const PGeom& pg, const float* xyz, const float* attr,
                           uint32_t* bins, float* attr_t, hipStream_t s);
-void launch_admit_field(const Geom& g, const float* field, float lo, float hi, uint32_t* A,
-                        uint8_t* active, hipStream_t s);
-void launch_count_active(const Geom& g, const uint8_t* active, unsigned long long* stat,
-                         hipStream_t s);
-void launch_admit_particles(const PGeom& pg, const float* attr_t, const uint32_t* bins, float lo,
-                            float hi, unsigned long long* Ap, uint2* pend, uint32_t* npend,
-                            hipStream_t s);
-void launch_seeds(const Geom& g, const int32_t* seeds, int64_t S, const uint32_t* A, uint32_t* L,
-                  const uint8_t* active, uint8_t* dirty, uint32_t* dropped, hipStream_t s);
-void launch_compact_tiles(const Geom& g, uint8_t* dirty, uint32_t* work, uint32_t* nwork,
-                          hipStream_t s);
-void launch_mark_work(const uint32_t* work, const uint32_t* nwork, uint32_t nwork_host,
-                      uint8_t* dirty, hipStream_t s);
-void launch_sweep(const Geom& g, const uint32_t* A, uint32_t* L, const uint8_t* active,
-                  const uint32_t* work, const uint32_t* nwork, uint32_t nwork_host,
-                  uint8_t* dirty, unsigned long long* visits, hipStream_t s);
-void launch_pull(const PGeom& pg, const uint2* pin, const uint32_t* nin, uint32_t nin_host,
-                 uint2* pout, uint32_t* nout, const uint32_t* Lf, unsigned long long* Lp,
-                 uint32_t* pdirty, uint32_t* dlist, uint32_t* ndlist, hipStream_t s);
-void launch_close_push(const Geom& g, const PGeom& pg, const uint32_t* dlist,
-                       const uint32_t* ndlist, uint32_t ndlist_host,
-                       const unsigned long long* Ap, unsigned long long* Lp, uint32_t* pdirty,
-                       const uint32_t* bins, const uint32_t* Af, uint32_t* Lf,
-                       const uint8_t* active, uint8_t* dirty, unsigned long long* visits,
-                       hipStream_t s);
-void launch_read_field(const Geom& g, const uint32_t* L, uint32_t* out,
-                       unsigned long long* members, hipStream_t s);
-void launch_read_particles(const PGeom& pg, const unsigned long long* Lp, uint8_t* out,
-                           unsigned long long* members, hipStream_t s);
+void launch_admit_field(const Dev& d, hipStream_t s);
+void launch_admit_particles(const Dev& d, hipStream_t s);
+void launch_seeds(const Dev& d, const int32_t* seeds, int64_t S, hipStream_t s);
+// One round as three launches (sweep, pull, close/push).
+void launch_round(const Dev& d, uint32_t round, uint32_t nwork_host, hipStream_t s);
+// Rounds in one cooperative persistent launch; false if it cannot be launched.
+bool launch_rounds_persistent(const Dev& d, uint32_t round0, uint32_t max_rounds, int device,
+                              hipStream_t s);
+void launch_read_field(const Dev& d, uint32_t* out, hipStream_t s);
+void launch_read_particles(const Dev& d, uint8_t* out, hipStream_t s);
 
 }  // namespace mf4d

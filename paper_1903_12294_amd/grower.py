@@ -41,7 +41,8 @@ def _arg(a, dtype):
 class Grower:
     """A library context on one GPU, ordering its work on one HIP stream."""
 
-    def __init__(self, device: int = 0, stream=None, tile_t: int | None = None):
+    def __init__(self, device: int = 0, stream=None, tile_t: int | None = None,
+                 schedule: str | None = None):
         self.lib = _lib.load_library()
         if stream is None:
             torch = _torch()
@@ -54,6 +55,8 @@ class Grower:
         self.P = 0
         if tile_t is not None:
             self._check(self.lib.mf4d_set_tile(self.ctx, tile_t))
+        if schedule is not None:
+            self.set_schedule(schedule)
 
     def _check(self, rc):
         return _lib.check(rc, self.lib)
@@ -106,6 +109,11 @@ class Grower:
         self._check(self.lib.mf4d_set_seeds(self.ctx, p, n, where))
         del keep
 
+    def set_schedule(self, mode):
+        """"persistent" (one cooperative kernel) or "launch" (launches per round)."""
+        m = {"persistent": _lib.MF4D_SCHED_PERSISTENT, "launch": _lib.MF4D_SCHED_LAUNCH}[mode]
+        self._check(self.lib.mf4d_set_schedule(self.ctx, m))
+
     def set_max_rounds(self, cap: int):
         self._check(self.lib.mf4d_set_max_rounds(self.ctx, int(cap)))
 
@@ -157,3 +165,34 @@ class Grower:
             self._check(self.lib.mf4d_read_particle_mask(
                 self.ctx, out.ctypes.data_as(ctypes.c_void_p), n, MF4D_HOST))
         return out
+
+    # -- batched queries ----------------------------------------------------
+    def set_queries(self, crit, seeds):
+        """crit fp32 [Q][4] = (f_lo, f_hi, a_lo, a_hi); seeds int32 [S][5] = (x, y, z, t, q)."""
+        crit = np.ascontiguousarray(crit, np.float32)
+        seeds = np.ascontiguousarray(seeds, np.int32).reshape(-1, 5)
+        self._check(self.lib.mf4d_set_queries(self.ctx, crit.shape[0],
+                                              crit.ctypes.data_as(ctypes.c_void_p),
+                                              seeds.ctypes.data_as(ctypes.c_void_p),
+                                              seeds.shape[0], MF4D_HOST))
+        self.Q = crit.shape[0]
+
+    def grow_batched(self, fplanes=None, pplanes=None) -> tuple:
+        """Grow all queries.  Outputs are device tensors (int32, grown in place)
+        or, when None, numpy arrays: fplanes [V][8], pplanes [T][P][8] uint32."""
+        X, Y, Z = self.dims
+        V = X * Y * Z * self.T
+        st = Stats()
+        if fplanes is None:
+            fplanes = np.zeros((V, 8), np.uint32)
+            pplanes = np.zeros((self.T, self.P, 8), np.uint32)
+            self._check(self.lib.mf4d_grow_batched(
+                self.ctx, fplanes.ctypes.data_as(ctypes.c_void_p), fplanes.size,
+                pplanes.ctypes.data_as(ctypes.c_void_p) if self.P else None, pplanes.size,
+                MF4D_HOST, ctypes.byref(st)))
+        else:
+            pp = ctypes.c_void_p(pplanes.data_ptr()) if pplanes is not None else None
+            self._check(self.lib.mf4d_grow_batched(
+                self.ctx, ctypes.c_void_p(fplanes.data_ptr()), fplanes.numel(), pp,
+                0 if pplanes is None else pplanes.numel(), MF4D_DEVICE, ctypes.byref(st)))
+        return fplanes, pplanes, st.as_dict()

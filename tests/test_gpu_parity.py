@@ -17,10 +17,10 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def _grow_gpu(inst, tile_t=None, device_inputs=True, crit=None, seeds=None):
+def _grow_gpu(inst, tile_t=None, device_inputs=True, crit=None, seeds=None, schedule=None):
     from paper_1903_12294_amd import Grower
     _need_gpu()
-    g = Grower(device=0, tile_t=tile_t)
+    g = Grower(device=0, tile_t=tile_t, schedule=schedule)
     try:
         if device_inputs:
             dev = torch.device("cuda:0")
@@ -59,10 +59,11 @@ def _assert_parity(inst, tag="", **kw):
     return st, ost
 
 
+@pytest.mark.parametrize("schedule", ["persistent", "launch"])
 @pytest.mark.parametrize("case", golden_io.all_cases(), ids=lambda c: c["name"])
-def test_golden_fixtures_on_gpu(case):
+def test_golden_fixtures_on_gpu(case, schedule):
     inst = dict(case)
-    _assert_parity(inst, tag=case["name"])
+    _assert_parity(inst, tag=case["name"], schedule=schedule)
 
 
 @pytest.mark.parametrize("seed", range(24))
@@ -73,16 +74,18 @@ def test_random_small_ragged(seed):
     T = int(rng.integers(1, 20))
     P = int(rng.integers(0, 300))
     inst = _random_instance(rng, X, Y, Z, T, P, 5)
-    _assert_parity(inst, tag=f"random{seed}", tile_t=[4, 8, 16][seed % 3])
+    _assert_parity(inst, tag=f"random{seed}", tile_t=[4, 8, 16][seed % 3],
+                   schedule=["persistent", "launch"][(seed // 3) % 2])
 
 
+@pytest.mark.parametrize("schedule", ["persistent", "launch"])
 @pytest.mark.parametrize("tile_t", [4, 8, 16])
 @pytest.mark.parametrize("variant", ["field", "noise", "stress_tau"])
-def test_config1(tile_t, variant):
+def test_config1(tile_t, variant, schedule):
     kw = dict(attr_mode="noise") if variant == "noise" else (
         dict(tau_p_offset=-0.15) if variant == "stress_tau" else {})
     inst = synth.make_config(1, **kw)
-    _assert_parity(inst, tag=f"cfg1-{variant}", tile_t=tile_t)
+    _assert_parity(inst, tag=f"cfg1-{variant}", tile_t=tile_t, schedule=schedule)
 
 
 def test_config1_host_inputs():
@@ -99,10 +102,11 @@ def test_ragged_multi_tile(shape):
     _assert_parity(inst, tag=f"ragged{shape}")
 
 
+@pytest.mark.parametrize("schedule", ["persistent", "launch"])
 @pytest.mark.parametrize("variant", ["field", "noise"])
-def test_config2(variant):
+def test_config2(variant, schedule):
     inst = synth.make_config(2, attr_mode=variant)
-    st, ost = _assert_parity(inst, tag=f"cfg2-{variant}")
+    st, ost = _assert_parity(inst, tag=f"cfg2-{variant}", schedule=schedule)
     print(f"[cfg2] rounds {st['rounds']} visits {st['tile_visits']} depth {ost['depth']}")
 
 
@@ -162,14 +166,15 @@ def test_errors_leave_state_unchanged():
     assert np.array_equal(fm, ofm)
 
 
-def test_round_cap_then_resume():
+@pytest.mark.parametrize("schedule", ["persistent", "launch"])
+def test_round_cap_then_resume(schedule):
     from paper_1903_12294_amd import Grower, MF4DError
     from paper_1903_12294_amd import _lib
     _need_gpu()
     inst = synth.make_config(1, attr_mode="noise")
     ofm, opm, _ = oracle_grow(inst["field"], inst["xyz"], inst["attr"], inst["crit"],
                               inst["seeds"])
-    g = Grower(device=0, tile_t=4)
+    g = Grower(device=0, tile_t=4, schedule=schedule)
     try:
         g.load_field(inst["field"])
         g.load_particles(inst["xyz"], inst["attr"])
@@ -195,11 +200,12 @@ def test_round_cap_then_resume():
         g.close()
 
 
-def test_repeat_grows_identical():
+@pytest.mark.parametrize("schedule", ["persistent", "launch"])
+def test_repeat_grows_identical(schedule):
     inst = synth.make_config(2, attr_mode="noise")
     from paper_1903_12294_amd import Grower
     _need_gpu()
-    g = Grower(device=0)
+    g = Grower(device=0, schedule=schedule)
     try:
         g.load_field(inst["field"])
         g.load_particles(inst["xyz"], inst["attr"])
