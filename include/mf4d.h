@@ -59,6 +59,7 @@ extern "C" {
 #endif
 
 typedef struct mf4d_ctx mf4d_ctx;
+typedef struct mf4d_net mf4d_net;
 
 enum {
     MF4D_OK = 0,
@@ -72,6 +73,9 @@ enum {
 };
 
 enum { MF4D_HOST = 0, MF4D_DEVICE = 1 };
+
+/* Admissibility modes (mf4d_set_admit_mode). */
+enum { MF4D_ADMIT_TILES = 0, MF4D_ADMIT_ALL = 1 };
 
 /* How the rounds of a grow are scheduled (both give the same result). */
 enum {
@@ -144,6 +148,14 @@ int mf4d_set_seeds(mf4d_ctx *ctx, const int32_t *xyzt, int64_t S, int where);
  * launches.  Errors: MF4D_ERR_ARG (unknown mode). */
 int mf4d_set_schedule(mf4d_ctx *ctx, int mode);
 
+/* Which voxel-steps a grow tests against the field criterion (same result
+ * either way).  MF4D_ADMIT_TILES (default): only tiles whose (min, max) field
+ * range, summarised once at load, meets the band -- no other tile can hold an
+ * admissible voxel.  MF4D_ADMIT_ALL: every voxel-step, one streaming pass.
+ * The environment variable MF4D_ADMIT=all selects the latter at creation.
+ * Errors: MF4D_ERR_ARG (unknown mode). */
+int mf4d_set_admit_mode(mf4d_ctx *ctx, int mode);
+
 /* Cap on rounds per mf4d_grow / mf4d_grow_resume call (0 = no cap). */
 int mf4d_set_max_rounds(mf4d_ctx *ctx, int64_t cap);
 
@@ -188,6 +200,67 @@ int mf4d_set_queries(mf4d_ctx *ctx, int Q, const float *crit, const int32_t *qxy
  * too small), MF4D_ERR_OOM, MF4D_ERR_HIP. */
 int mf4d_grow_batched(mf4d_ctx *ctx, uint32_t *fplanes, size_t fwords, uint32_t *pplanes,
                       size_t pwords, int where, mf4d_stats *out);
+
+/* ---- brick-activity predictor --------------------------------------------
+ * A 3-layer 3D convolutional network (8 -> 16 -> 16 -> 1 channels, 3x3x3,
+ * zero "same" padding, ReLU, logits) over the grid of bricks of 8^3 voxels of
+ * each timestep.  Inputs are per brick-step (field min, max, mean minus the
+ * field lower bound; log1p(particle-steps) / 4) at t and at t-1, in bf16
+ * channels-last [T][Db][Hb][Wb][16] (channels 8..15 zero).  It predicts
+ * whether a brick-step will hold a member of the grown feature; the grower
+ * uses it only to choose which candidate tiles to test before the rounds (the
+ * rest are tested by the first sweep that reaches them), so the result never
+ * depends on it.  Weights bf16 on the matrix cores with fp32 accumulation;
+ * fp32 master parameters, Adam.  Parameter layout (fp32, 10833 values): per
+ * layer W [cout][cin][3][3][3] then b [cout]. */
+
+/* Number of parameters (10833). */
+int mf4d_net_num_params(void);
+
+/* Create a network with zero parameters on `device`, ordering its work on
+ * `hip_stream`.  Errors: MF4D_ERR_ARG, MF4D_ERR_OOM, MF4D_ERR_HIP. */
+int mf4d_net_create(mf4d_net **out, int device, void *hip_stream);
+void mf4d_net_destroy(mf4d_net *net);
+const char *mf4d_net_last_error(void);
+
+/* Copy parameters in (resets the Adam state) or out.  where: MF4D_HOST or
+ * MF4D_DEVICE. */
+int mf4d_net_set_params(mf4d_net *net, const float *params, int where);
+int mf4d_net_get_params(mf4d_net *net, float *params, int where);
+
+/* Logits fp32 [N][D][H][W] of inputs x bf16 [N][D][H][W][16]; device
+ * pointers only.  Errors: MF4D_ERR_ARG, MF4D_ERR_UNSUPPORTED (>= 2^31
+ * positions). */
+int mf4d_net_forward(mf4d_net *net, const uint16_t *x, int N, int D, int H, int W, float *logits,
+                     int where);
+
+/* Gradients (fp32, parameter layout, device) of the mean binary cross entropy
+ * with positive weight `pos_weight` against labels y uint8 [N][D][H][W];
+ * *loss receives the loss.  Device pointers only. */
+int mf4d_net_grad(mf4d_net *net, const uint16_t *x, const uint8_t *y, int N, int D, int H, int W,
+                  float pos_weight, float *grads, float *loss, int where);
+
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on that loss; device pointers;
+ * *loss (nullable) receives the loss before the step. */
+int mf4d_net_train_step(mf4d_net *net, const uint16_t *x, const uint8_t *y, int N, int D, int H,
+                        int W, float pos_weight, float lr, float *loss);
+
+/* Brick grid of the loaded field: dims4 = (T, Db, Hb, Wb). */
+int mf4d_brick_dims(mf4d_ctx *ctx, int *dims4);
+
+/* Network inputs for the loaded data under the current criteria (layout
+ * above), n >= T*Db*Hb*Wb*16 elements. */
+int mf4d_features(mf4d_ctx *ctx, uint16_t *dst, size_t n, int where);
+
+/* Labels of the last grow: uint8 [T][Db][Hb][Wb], 1 = the brick-step holds a
+ * member voxel-step. */
+int mf4d_brick_labels(mf4d_ctx *ctx, uint8_t *dst, size_t n, int where);
+
+/* Use `net` (NULL: none) to choose the tiles tested before the rounds: a
+ * candidate tile is tested up front when one of its brick-steps has a logit
+ * >= logit_threshold.  The context keeps the pointer; the net must outlive
+ * its use.  Errors: MF4D_ERR_ARG (NaN threshold). */
+int mf4d_set_predictor(mf4d_ctx *ctx, mf4d_net *net, float logit_threshold);
 
 /* Statistics of the last grow, including member counts of the last reads. */
 int mf4d_last_stats(mf4d_ctx *ctx, mf4d_stats *out);

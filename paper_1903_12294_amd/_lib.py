@@ -22,6 +22,8 @@ MF4D_ERR_NOT_CONVERGED = -6
 MF4D_ERR_UNSUPPORTED = -7
 MF4D_HOST = 0
 MF4D_DEVICE = 1
+MF4D_ADMIT_TILES = 0
+MF4D_ADMIT_ALL = 1
 MF4D_SCHED_PERSISTENT = 0
 MF4D_SCHED_LAUNCH = 1
 
@@ -63,6 +65,7 @@ SIGNATURES = {
     "mf4d_set_criteria": (c_int, [c_void_p, c_float, c_float, c_float, c_float]),
     "mf4d_set_seeds": (c_int, [c_void_p, c_void_p, c_int64, c_int]),
     "mf4d_set_schedule": (c_int, [c_void_p, c_int]),
+    "mf4d_set_admit_mode": (c_int, [c_void_p, c_int]),
     "mf4d_set_max_rounds": (c_int, [c_void_p, c_int64]),
     "mf4d_grow": (c_int, [c_void_p, POINTER(Stats)]),
     "mf4d_grow_resume": (c_int, [c_void_p, POINTER(Stats)]),
@@ -72,6 +75,21 @@ SIGNATURES = {
     "mf4d_set_queries": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_int64, c_int]),
     "mf4d_grow_batched": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, c_int,
                                   POINTER(Stats)]),
+    "mf4d_net_num_params": (c_int, []),
+    "mf4d_net_create": (c_int, [POINTER(c_void_p), c_int, c_void_p]),
+    "mf4d_net_destroy": (None, [c_void_p]),
+    "mf4d_net_last_error": (c_char_p, []),
+    "mf4d_net_set_params": (c_int, [c_void_p, c_void_p, c_int]),
+    "mf4d_net_get_params": (c_int, [c_void_p, c_void_p, c_int]),
+    "mf4d_net_forward": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_void_p, c_int]),
+    "mf4d_net_grad": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_float,
+                              c_void_p, POINTER(c_float), c_int]),
+    "mf4d_net_train_step": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int,
+                                    c_float, c_float, POINTER(c_float)]),
+    "mf4d_brick_dims": (c_int, [c_void_p, POINTER(c_int)]),
+    "mf4d_features": (c_int, [c_void_p, c_void_p, c_size_t, c_int]),
+    "mf4d_brick_labels": (c_int, [c_void_p, c_void_p, c_size_t, c_int]),
+    "mf4d_set_predictor": (c_int, [c_void_p, c_void_p, c_float]),
 }
 
 

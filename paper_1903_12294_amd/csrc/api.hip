@@ -12,11 +12,17 @@
 
 #include "mf4d_internal.h"
 #include "batched.h"
+#include "nn.h"
 
 #include <algorithm>
 #include <vector>
 
 using namespace mf4d;
+
+namespace mf4d {
+int net_infer(mf4d_net* n, const uint16_t* x, int N, int D, int H, int W, float* logits,
+              hipStream_t s);
+}
 
 namespace {
 
@@ -83,6 +89,9 @@ struct mf4d_ctx {
     uint32_t* dirty = nullptr;
     uint8_t* chg = nullptr;
     uint32_t* work = nullptr;
+    float2* tsum = nullptr;
+    uint32_t* cand = nullptr;
+    int admit_all = 0;
 
     bool has_particles = false;
     PGeom pg{};
@@ -93,6 +102,7 @@ struct mf4d_ctx {
     uint2* clist = nullptr;
     uint32_t* pdirty = nullptr;
     uint32_t* dlist = nullptr;
+    float2* psum = nullptr;
 
     uint32_t* counters = nullptr;
     unsigned long long* stat64 = nullptr;
@@ -128,6 +138,15 @@ struct mf4d_ctx {
     uint8_t* b_chg = nullptr;
     uint32_t* b_work = nullptr;
     uint32_t* b_counters = nullptr;
+
+    // brick statistics and the activity predictor
+    BrickDims bd{};
+    float4* bstats = nullptr;   // [T][Db][Hb][Wb] (min, max, mean, particle-steps)
+    uint16_t* feat = nullptr;   // bf16 [T][Db][Hb][Wb][16]
+    float* blogits = nullptr;   // [T][Db][Hb][Wb]
+    uint8_t* tpred = nullptr;   // NT
+    mf4d_net* net = nullptr;
+    float pred_thr = 0.0f;
 };
 
 namespace {
@@ -140,6 +159,12 @@ void free_field(mf4d_ctx* c) {
     dev_free(c->dirty);
     dev_free(c->work);
     dev_free(c->chg);
+    dev_free(c->tsum);
+    dev_free(c->cand);
+    dev_free(c->bstats);
+    dev_free(c->feat);
+    dev_free(c->blogits);
+    dev_free(c->tpred);
     dev_free(c->b_active);
     dev_free(c->b_dirty);
     dev_free(c->b_chg);
@@ -156,6 +181,7 @@ void free_particles(mf4d_ctx* c) {
     dev_free(c->clist);
     dev_free(c->pdirty);
     dev_free(c->dlist);
+    dev_free(c->psum);
     c->has_particles = false;
     c->pg = PGeom{};
 }
@@ -206,6 +232,11 @@ Dev make_dev(mf4d_ctx* c) {
     d.counters = c->counters;
     d.stat64 = c->stat64;
     d.bar = c->bar;
+    d.tsum = c->tsum;
+    d.psum = c->psum;
+    d.cand = c->cand;
+    d.tpred = nullptr;
+    d.admit_all = c->admit_all;
     for (int i = 0; i < 4; ++i) d.crit[i] = c->crit[i];
     return d;
 }
@@ -314,6 +345,8 @@ int mf4d_create(mf4d_ctx** out, int device, void* hip_stream) {
     if (!rc) {
         const char* env = getenv("MF4D_SCHED");
         if (env && strcmp(env, "launch") == 0) c->schedule = MF4D_SCHED_LAUNCH;
+        const char* adm = getenv("MF4D_ADMIT");
+        if (adm && strcmp(adm, "all") == 0) c->admit_all = 1;
     }
     if (!rc && hipHostMalloc((void**)&c->h_counters, C_NCOUNTERS * sizeof(uint32_t)) != hipSuccess)
         rc = fail(MF4D_ERR_OOM, "pinned host allocation failed");
@@ -393,6 +426,14 @@ int mf4d_load_field(mf4d_ctx* c, const float* field, int X, int Y, int Z, int T,
     if (!rc) rc = dev_alloc(&c->dirty, 2 * (size_t)g.NT);
     if (!rc) rc = dev_alloc(&c->chg, 2 * (size_t)g.NT + 8);
     if (!rc) rc = dev_alloc(&c->work, 2 * (size_t)g.NT);
+    if (!rc) rc = dev_alloc(&c->tsum, (size_t)g.NT);
+    if (!rc) rc = dev_alloc(&c->cand, (size_t)g.NT);
+    const BrickDims bd{T, (Z + 7) / 8, (Y + 7) / 8, (X + 7) / 8};
+    const size_t nbricks = (size_t)bd.T * bd.D * bd.H * bd.W;
+    if (!rc) rc = dev_alloc(&c->bstats, nbricks);
+    if (!rc) rc = dev_alloc(&c->feat, nbricks * 16);
+    if (!rc) rc = dev_alloc(&c->blogits, nbricks);
+    if (!rc) rc = dev_alloc(&c->tpred, (size_t)g.NT);
     if (rc) {
         free_field(c);
         return rc;
@@ -402,12 +443,15 @@ int mf4d_load_field(mf4d_ctx* c, const float* field, int X, int Y, int Z, int T,
                            c->stream));
     launch_fill_u32(c->Af, 0, g.nwords, c->stream);
     launch_fill_u32(c->Lf, 0, g.nwords, c->stream);
+    launch_summaries(g, c->field, c->tsum, c->stream);
+    launch_brick_stats(g, PGeom{}, bd, c->field, nullptr, c->bstats, c->stream);
     rc = sync(c);
     if (rc) {
         free_field(c);
         return rc;
     }
     c->g = g;
+    c->bd = bd;
     c->has_field = true;
     return MF4D_OK;
 }
@@ -447,6 +491,7 @@ int mf4d_load_particles(mf4d_ctx* c, const float* xyz, const float* attr, int64_
     if (!rc) rc = dev_alloc(&c->clist, Q);
     if (!rc) rc = dev_alloc(&c->pdirty, (size_t)(P + 31) / 32);
     if (!rc) rc = dev_alloc(&c->dlist, (size_t)P);
+    if (!rc) rc = dev_alloc(&c->psum, (size_t)P);
     if (rc) {
         free_particles(c);
         return rc;
@@ -473,6 +518,8 @@ int mf4d_load_particles(mf4d_ctx* c, const float* xyz, const float* attr, int64_
         da = tmp + nxyz;
     }
     launch_bin_particles(c->g, pg, dx, da, c->bins, c->attr_t, c->stream);
+    launch_particle_summaries(pg, c->attr_t, c->psum, c->stream);
+    launch_brick_stats(c->g, pg, c->bd, c->field, c->bins, c->bstats, c->stream);
     launch_fill_u32(c->pdirty, 0, (P + 31) / 32, c->stream);
     rc = sync(c);
     if (tmp) (void)hipFree(tmp);
@@ -558,6 +605,14 @@ int mf4d_set_max_rounds(mf4d_ctx* c, int64_t cap) {
     return MF4D_OK;
 }
 
+int mf4d_set_admit_mode(mf4d_ctx* c, int mode) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    if (mode != MF4D_ADMIT_TILES && mode != MF4D_ADMIT_ALL)
+        return fail(MF4D_ERR_ARG, "unknown admissibility mode %d", mode);
+    c->admit_all = mode == MF4D_ADMIT_ALL;
+    return MF4D_OK;
+}
+
 int mf4d_set_schedule(mf4d_ctx* c, int mode) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
     if (mode != MF4D_SCHED_PERSISTENT && mode != MF4D_SCHED_LAUNCH)
@@ -577,7 +632,16 @@ int mf4d_grow(mf4d_ctx* c, mf4d_stats* out) {
     c->round = 0;
     launch_reset(d, s);
     HIP_TRY(hipEventRecord(c->ev[0], s));
-    launch_admit_field(d, s);
+    Dev dp = d;
+    if (c->net && !c->admit_all) {
+        // the predictor marks the candidate tiles to test before the rounds
+        launch_features(c->bd, c->bstats, c->crit[0], c->feat, s);
+        int rc = net_infer(c->net, c->feat, c->bd.T, c->bd.D, c->bd.H, c->bd.W, c->blogits, s);
+        if (rc) return fail(rc, "predictor: %s", net_last_error());
+        launch_tile_predict(c->g, c->bd, c->blogits, c->pred_thr, c->tpred, s);
+        dp.tpred = c->tpred;
+    }
+    launch_admit_field(dp, s);
     HIP_TRY(hipEventRecord(c->ev[1], s));
     launch_admit_particles(d, s);
     HIP_TRY(hipEventRecord(c->ev[2], s));
@@ -839,6 +903,56 @@ int mf4d_grow_batched(mf4d_ctx* c, uint32_t* fplanes, size_t fwords, uint32_t* p
         if (rc) return rc;
     }
     if (out) *out = st;
+    return MF4D_OK;
+}
+
+int mf4d_set_predictor(mf4d_ctx* c, mf4d_net* net, float logit_threshold) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    if (logit_threshold != logit_threshold) return fail(MF4D_ERR_ARG, "threshold is NaN");
+    c->net = net;
+    c->pred_thr = logit_threshold;
+    return MF4D_OK;
+}
+
+int mf4d_features(mf4d_ctx* c, uint16_t* dst, size_t n, int where) {
+    if (!c || !dst) return fail(MF4D_ERR_ARG, "NULL argument");
+    if (!c->has_field || !c->has_crit) return fail(MF4D_ERR_STATE, "load a field and set criteria first");
+    const size_t need = (size_t)c->bd.T * c->bd.D * c->bd.H * c->bd.W * 16;
+    if (n < need) return fail(MF4D_ERR_ARG, "dst holds %zu elements, %zu needed", n, need);
+    HIP_TRY(hipSetDevice(c->device));
+    launch_features(c->bd, c->bstats, c->crit[0], c->feat, c->stream);
+    HIP_TRY(hipMemcpyAsync(dst, c->feat, need * sizeof(uint16_t),
+                           where == MF4D_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                           c->stream));
+    return sync(c);
+}
+
+int mf4d_brick_labels(mf4d_ctx* c, uint8_t* dst, size_t n, int where) {
+    if (!c || !dst) return fail(MF4D_ERR_ARG, "NULL argument");
+    if (c->state == 0) return fail(MF4D_ERR_STATE, "nothing grown");
+    const size_t need = (size_t)c->bd.T * c->bd.D * c->bd.H * c->bd.W;
+    if (n < need) return fail(MF4D_ERR_ARG, "dst holds %zu bytes, %zu needed", n, need);
+    HIP_TRY(hipSetDevice(c->device));
+    uint8_t* out = dst;
+    if (where == MF4D_HOST) {
+        void* st = nullptr;
+        int rc = staging_for(c, need, &st);
+        if (rc) return rc;
+        out = (uint8_t*)st;
+    }
+    launch_brick_labels(c->g, c->bd, c->Lf, c->active, out, c->stream);
+    if (where == MF4D_HOST)
+        HIP_TRY(hipMemcpyAsync(dst, out, need, hipMemcpyDeviceToHost, c->stream));
+    return sync(c);
+}
+
+int mf4d_brick_dims(mf4d_ctx* c, int* dims4) {
+    if (!c || !dims4) return fail(MF4D_ERR_ARG, "NULL argument");
+    if (!c->has_field) return fail(MF4D_ERR_STATE, "no field loaded");
+    dims4[0] = c->bd.T;
+    dims4[1] = c->bd.D;
+    dims4[2] = c->bd.H;
+    dims4[3] = c->bd.W;
     return MF4D_OK;
 }
 

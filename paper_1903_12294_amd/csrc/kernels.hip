@@ -74,6 +74,52 @@ __device__ __forceinline__ bool test_bit(const uint32_t* a, uint32_t b) {
     return (a[b >> 5] >> (b & 31)) & 1u;
 }
 
+// Canonical voxel of a tile-layout bit position.
+__device__ __forceinline__ size_t voxel_of_bit(const Geom& g, uint32_t b) {
+    const uint32_t word = b >> 5;
+    const uint32_t wi = word & (g.WPT - 1);
+    int tx, ty, tz, tt;
+    tile_coords(g, word >> (6 + g.logBT), tx, ty, tz, tt);
+    const int x = tx * 32 + (b & 31), y = ty * 8 + (wi & 7), z = tz * 8 + ((wi >> 3) & 7);
+    const int t = (tt << g.logBT) + (wi >> 6);
+    return (((size_t)t * g.Z + z) * g.Y + y) * g.X + x;
+}
+
+// Admissibility of voxel b.  A tile that is not active holds no admissible
+// voxel (its bit words are not rewritten this grow); a deferred tile has not
+// been tested yet, so the field value itself is tested.
+__device__ __forceinline__ bool admissible_bit(const Dev& d, uint32_t b) {
+    const uint8_t a = d.active[b >> (5 + 6 + d.g.logBT)];
+    if (a == 1) return test_bit(d.Af, b);
+    if (a == 2) return in_band(d.field[voxel_of_bit(d.g, b)], d.crit[0], d.crit[1]);
+    return false;
+}
+
+// Admissibility words of one (z_l, y_l) row of a tile at timestep t: one
+// lane's 32 x-bits (eight 16-byte non-temporal loads when whole and aligned).
+__device__ __forceinline__ uint32_t row_admissibility(const Dev& d, int tx, int y, int z, int t) {
+    const Geom& g = d.g;
+    if (t >= g.T || y >= g.Y || z >= g.Z) return 0u;
+    const float lo = d.crit[0], hi = d.crit[1];
+    const float* rp = d.field + ((size_t)(t * g.Z + z) * g.Y + y) * g.X + tx * 32;
+    const int nx = min(32, g.X - tx * 32);
+    uint32_t w = 0;
+    if ((g.X & 3) == 0 && nx == 32) {
+        typedef float v4f_ __attribute__((ext_vector_type(4)));
+        v4f_ v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = __builtin_nontemporal_load(reinterpret_cast<const v4f_*>(rp) + k);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            w |= ((uint32_t)in_band(v[k].x, lo, hi) | ((uint32_t)in_band(v[k].y, lo, hi) << 1) |
+                  ((uint32_t)in_band(v[k].z, lo, hi) << 2) | ((uint32_t)in_band(v[k].w, lo, hi) << 3))
+                 << (4 * k);
+    } else {
+        for (int k = 0; k < nx; ++k) w |= (uint32_t)in_band(rp[k], lo, hi) << k;
+    }
+    return w;
+}
+
 __device__ __forceinline__ uint32_t load_relaxed(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -172,24 +218,38 @@ __device__ void sweep_tile(const Dev& d, uint32_t tile, int par) {
     int tx, ty, tz, tt;
     tile_coords(g, tile, tx, ty, tz, tt);
     if (lane == 0) d.dirty[par * g.NT + tile] = 0u;
-    const uint32_t* Ab = d.Af + (size_t)tile * (64 * BT);
+    uint32_t* Ab = d.Af + (size_t)tile * (64 * BT);
     uint32_t* Lb = d.Lf + (size_t)tile * (64 * BT);
     uint32_t a[BT], l[BT], l0[BT], xin[BT], yh[BT], zh[BT];
+    if (d.active[tile] == 2) {
+        // deferred tile: test its admissibility now
+        uint32_t any = 0;
 #pragma unroll
-    for (int t = 0; t < BT; ++t) {
-        a[t] = Ab[t * 64 + lane];
-        l[t] = Lb[t * 64 + lane];
+        for (int t = 0; t < BT; ++t) {
+            a[t] = row_admissibility(d, tx, ty * 8 + yl, tz * 8 + zl, (tt << g.logBT) + t);
+            Ab[t * 64 + lane] = a[t];
+            any |= a[t];
+        }
+        const bool has = __ballot(any != 0) != 0;
+        if (lane == 0) d.active[tile] = has ? 1 : 0;
+    } else {
+#pragma unroll
+        for (int t = 0; t < BT; ++t) a[t] = Ab[t * 64 + lane];
     }
-    const uint32_t* Lxm = tx > 0 ? Lb - 64 * BT : nullptr;
-    const uint32_t* Lxp = tx + 1 < g.NXt ? Lb + 64 * BT : nullptr;
+#pragma unroll
+    for (int t = 0; t < BT; ++t) l[t] = Lb[t * 64 + lane];
+    // halos come only from active neighbours: an inactive tile's labels are
+    // stale (never cleared this grow) and all zero by definition
+    const uint32_t* Lxm = tx > 0 && d.active[tile - 1] ? Lb - 64 * BT : nullptr;
+    const uint32_t* Lxp = tx + 1 < g.NXt && d.active[tile + 1] ? Lb + 64 * BT : nullptr;
     const uint32_t* Ly = nullptr;
     int yoff = 0;
-    if (yl == 0 && ty > 0) { Ly = Lb - (size_t)sy * 64 * BT; yoff = 7; }
-    if (yl == 7 && ty + 1 < g.NYt) { Ly = Lb + (size_t)sy * 64 * BT; yoff = -7; }
+    if (yl == 0 && ty > 0 && d.active[tile - sy]) { Ly = Lb - (size_t)sy * 64 * BT; yoff = 7; }
+    if (yl == 7 && ty + 1 < g.NYt && d.active[tile + sy]) { Ly = Lb + (size_t)sy * 64 * BT; yoff = -7; }
     const uint32_t* Lz = nullptr;
     int zoff = 0;
-    if (zl == 0 && tz > 0) { Lz = Lb - (size_t)sz * 64 * BT; zoff = 56; }
-    if (zl == 7 && tz + 1 < g.NZt) { Lz = Lb + (size_t)sz * 64 * BT; zoff = -56; }
+    if (zl == 0 && tz > 0 && d.active[tile - sz]) { Lz = Lb - (size_t)sz * 64 * BT; zoff = 56; }
+    if (zl == 7 && tz + 1 < g.NZt && d.active[tile + sz]) { Lz = Lb + (size_t)sz * 64 * BT; zoff = -56; }
 #pragma unroll
     for (int t = 0; t < BT; ++t) {
         xin[t] = (Lxm ? (Lxm[t * 64 + lane] >> 31) : 0u) | (Lxp ? (Lxp[t * 64 + lane] << 31) : 0u);
@@ -197,8 +257,9 @@ __device__ void sweep_tile(const Dev& d, uint32_t tile, int par) {
         zh[t] = Lz ? Lz[t * 64 + lane + zoff] : 0u;
         l0[t] = l[t];
     }
-    const uint32_t tm = tt > 0 ? (Lb - (size_t)st * 64 * BT)[(BT - 1) * 64 + lane] : 0u;
-    const uint32_t tp = tt + 1 < g.NTt ? (Lb + (size_t)st * 64 * BT)[lane] : 0u;
+    const uint32_t tm =
+        tt > 0 && d.active[tile - st] ? (Lb - (size_t)st * 64 * BT)[(BT - 1) * 64 + lane] : 0u;
+    const uint32_t tp = tt + 1 < g.NTt && d.active[tile + st] ? (Lb + (size_t)st * 64 * BT)[lane] : 0u;
     while (true) {
         uint32_t s[BT];
 #pragma unroll
@@ -313,7 +374,7 @@ __device__ __forceinline__ void push_steps(const Dev& d, uint32_t p, int w, unsi
         const int t = __builtin_ctzll(nw);
         nw &= nw - 1;
         const uint32_t b = d.bins[(size_t)p * d.pg.Tpad + w * 64 + t];
-        if (b != kNoVoxel && test_bit(d.Af, b)) {
+        if (b != kNoVoxel && admissible_bit(d, b)) {
             const uint32_t bit = 1u << (b & 31);
             if (!(atomicOr(&d.Lf[b >> 5], bit) & bit)) mark_voxel(d, b, par);
         }
@@ -524,11 +585,116 @@ __global__ __launch_bounds__(256) void k_admit_field(Dev d) {
     }
 }
 
+// Load time: (min, max) of each tile's non-NaN field values ((+inf, -inf)
+// when it has none).  A tile can hold a voxel with lo <= f <= hi only if
+// max >= lo and min <= hi, so these decide, exactly, which tiles a grow must
+// test at all.  Block = one tile; lane = (z_l, y_l) row, x by 16-byte loads.
+__global__ __launch_bounds__(256) void k_tile_summaries(Geom g, const float* __restrict__ f,
+                                                        float2* __restrict__ tsum) {
+    __shared__ float s_mn[4], s_mx[4];
+    const uint32_t tile = blockIdx.x;
+    int tx, ty, tz, tt;
+    tile_coords(g, tile, tx, ty, tz, tt);
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const int y = ty * 8 + (lane & 7), z = tz * 8 + (lane >> 3);
+    float mn = __builtin_inff(), mx = -__builtin_inff();
+    for (int tl = wave; tl < g.BT; tl += 4) {
+        const int t = (tt << g.logBT) + tl;
+        if (t >= g.T || y >= g.Y || z >= g.Z) continue;
+        const float* rp = f + ((size_t)(t * g.Z + z) * g.Y + y) * g.X;
+        for (int k = 0; k < 32; ++k) {
+            const int x = tx * 32 + k;
+            if (x >= g.X) break;
+            const float v = rp[x];
+            if (v == v) {
+                mn = fminf(mn, v);
+                mx = fmaxf(mx, v);
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        mn = fminf(mn, __shfl_xor(mn, o));
+        mx = fmaxf(mx, __shfl_xor(mx, o));
+    }
+    if (lane == 0) {
+        s_mn[wave] = mn;
+        s_mx[wave] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        tsum[tile] = make_float2(fminf(fminf(s_mn[0], s_mn[1]), fminf(s_mn[2], s_mn[3])),
+                                 fmaxf(fmaxf(s_mx[0], s_mx[1]), fmaxf(s_mx[2], s_mx[3])));
+}
+
+// Load time: (min, max) of each particle's non-NaN values over its steps.
+__global__ void k_particle_summaries(PGeom pg, const float* __restrict__ at, float2* __restrict__ psum) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < pg.P;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        float mn = __builtin_inff(), mx = -__builtin_inff();
+        for (int t = 0; t < pg.T; ++t) {
+            const float v = at[p * pg.Tpad + t];
+            if (v == v) {
+                mn = fminf(mn, v);
+                mx = fmaxf(mx, v);
+            }
+        }
+        psum[p] = make_float2(mn, mx);
+    }
+}
+
+// Tiles whose value range meets the field band, as a list.
+__global__ __launch_bounds__(256) void k_tile_candidates(Dev d) {
+    __shared__ uint32_t s_tmp[8];
+    const float lo = d.crit[0], hi = d.crit[1];
+    for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < d.g.NT; b0 += gridDim.x * blockDim.x) {
+        const uint32_t i = b0 + threadIdx.x;
+        bool c = false;
+        if (i < d.g.NT) {
+            const float2 r = d.tsum[i];
+            c = r.y >= lo && r.x <= hi;
+        }
+        const uint32_t k = block_append256(c ? 1u : 0u, &d.counters[C_NCAND], s_tmp);
+        if (c) d.cand[k] = i;
+    }
+}
+
+// Admissibility of the voxel-steps of candidate tiles, and their labels
+// cleared.  Block = one tile at a time; each wave handles t-slices, each lane
+// one (z_l, y_l) row of 32 x.  With a predictor, candidates it does not mark
+// are only cleared and deferred to the first sweep that reaches them.
+__global__ __launch_bounds__(256) void k_admit_tiles(Dev d) {
+    const Geom& g = d.g;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const uint32_t n = d.counters[C_NCAND];
+    for (uint32_t ci = blockIdx.x; ci < n; ci += gridDim.x) {
+        const uint32_t tile = d.cand[ci];
+        int tx, ty, tz, tt;
+        tile_coords(g, tile, tx, ty, tz, tt);
+        const bool defer = d.tpred && !d.tpred[tile];
+        const int y = ty * 8 + (lane & 7), z = tz * 8 + (lane >> 3);
+        uint32_t any = 0;
+        for (int tl = wave; tl < g.BT; tl += 4) {
+            const size_t wi = (size_t)tile * g.WPT + tl * 64 + lane;
+            if (!defer) {
+                const uint32_t w = row_admissibility(d, tx, y, z, (tt << g.logBT) + tl);
+                d.Af[wi] = w;
+                any |= w;
+            }
+            d.Lf[wi] = 0u;
+        }
+        if (defer) {
+            if (threadIdx.x == 0) d.active[tile] = 2;
+        } else if (__ballot(any != 0) != 0 && lane == 0) {
+            d.active[tile] = 1;
+        }
+    }
+}
+
 __global__ void k_count_active(Dev d) {
     uint32_t c = 0;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < d.g.NT;
          i += gridDim.x * blockDim.x)
-        c += d.active[i];
+        c += d.active[i] != 0;
     for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
     if (lane_id() == 0 && c) atomicAdd(&d.stat64[S_ACTIVE_TILES], (unsigned long long)c);
 }
@@ -552,7 +718,13 @@ __global__ __launch_bounds__(256) void k_admit_particles(Dev d) {
         for (int k = 0; k < 4; ++k) {
             const uint64_t i = base + k * stride + lane;
             const float nan = __builtin_nanf("");
-            v[k] = i < n4 ? __builtin_nontemporal_load(src + i) : (v4f){nan, nan, nan, nan};
+            v[k] = (v4f){nan, nan, nan, nan};
+            if (i < n4) {
+                // skip particles none of whose values can meet the band
+                const uint64_t p = pg.logTpad >= 0 ? ((i << 2) >> pg.logTpad) : ((i << 2) / pg.Tpad);
+                const float2 r = d.psum[p];
+                if (r.y >= lo && r.x <= hi) v[k] = __builtin_nontemporal_load(src + i);
+            }
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -615,7 +787,7 @@ __global__ void k_seeds(Dev d, const int32_t* __restrict__ seeds, int64_t S) {
     if (i >= S) return;
     const int32_t* s = seeds + 4 * i;
     const uint32_t b = bit_index(d.g, s[0], s[1], s[2], s[3]);
-    if (test_bit(d.Af, b)) {
+    if (admissible_bit(d, b)) {
         const uint32_t bit = 1u << (b & 31);
         if (!(atomicOr(&d.Lf[b >> 5], bit) & bit)) mark_voxel(d, b, 0);
     } else {
@@ -715,10 +887,11 @@ __global__ __launch_bounds__(256) void k_read_field_tiles(Dev d, uint32_t* __res
     uint32_t cnt = 0;
     for (int tx0 = 0; tx0 < g.NXt; tx0 += 8) {
         const int ntx = min(8, g.NXt - tx0);
-        const uint32_t* src = d.Lf + (size_t)tile_of(g, tx0, ty, tz, tt) * WPT;
+        const uint32_t tile0 = tile_of(g, tx0, ty, tz, tt);
+        const uint32_t* src = d.Lf + (size_t)tile0 * WPT;
         for (int i = threadIdx.x; i < ntx * WPT; i += 256) {
             const int txl = i / WPT, w = i - txl * WPT;
-            sl[txl * (WPT + 1) + w] = src[i];
+            sl[txl * (WPT + 1) + w] = d.active[tile0 + txl] ? src[i] : 0u;
         }
         __syncthreads();
         for (int i = threadIdx.x; i < ntx * WPT; i += 256) {
@@ -753,7 +926,8 @@ __global__ __launch_bounds__(256) void k_read_field_bits(Dev d, uint32_t* __rest
             const int y = r % g.Y;
             const uint64_t r2 = r / g.Y;
             const int z = r2 % g.Z, t = (int)(r2 / g.Z);
-            if (test_bit(d.Lf, bit_index(g, (int)x, y, z, t))) w |= 1u << k;
+            const uint32_t b = bit_index(g, (int)x, y, z, t);
+            if (d.active[b >> (5 + 6 + g.logBT)] && test_bit(d.Lf, b)) w |= 1u << k;
         }
         out[i] = w;
         cnt += __popc(w);
@@ -863,8 +1037,23 @@ void launch_bin_particles(const Geom& g, const PGeom& pg, const float* xyz, cons
     hipLaunchKernelGGL(k_bin_particles, dim3(nb), dim3(256), 0, s, g, pg, xyz, attr, bins, attr_t);
 }
 
+void launch_summaries(const Geom& g, const float* field, float2* tsum, hipStream_t s) {
+    hipLaunchKernelGGL(k_tile_summaries, dim3(g.NT), dim3(256), 0, s, g, field, tsum);
+}
+
+void launch_particle_summaries(const PGeom& pg, const float* attr_t, float2* psum, hipStream_t s) {
+    if (pg.P == 0) return;
+    hipLaunchKernelGGL(k_particle_summaries, dim3(grid_for(pg.P, 256, 8192)), dim3(256), 0, s, pg,
+                       attr_t, psum);
+}
+
 void launch_admit_field(const Dev& d, hipStream_t s) {
-    hipLaunchKernelGGL(k_admit_field, dim3(d.g.NYt, d.g.NZt, d.g.T), dim3(256), 0, s, d);
+    if (d.admit_all) {
+        hipLaunchKernelGGL(k_admit_field, dim3(d.g.NYt, d.g.NZt, d.g.T), dim3(256), 0, s, d);
+    } else {
+        hipLaunchKernelGGL(k_tile_candidates, dim3(grid_for(d.g.NT, 256, 1024)), dim3(256), 0, s, d);
+        hipLaunchKernelGGL(k_admit_tiles, dim3(grid_for(d.g.NT, 1, 8192)), dim3(256), 0, s, d);
+    }
     hipLaunchKernelGGL(k_count_active, dim3(grid_for(d.g.NT, 256, 1024)), dim3(256), 0, s, d);
 }
 

@@ -45,6 +45,7 @@ enum Counter : int {
     C_DROPPED = 4, // dropped seeds
     C_ERR = 5,     // set by the persistent kernel if a grid barrier timed out
     C_ROUNDS = 6,  // rounds completed by the persistent kernel
+    C_NCAND = 7,   // candidate tiles
     C_NCOUNTERS = 8
 };
 
@@ -64,7 +65,8 @@ struct Dev {
     const float* field;      // fp32 [T][Z][Y][X]
     uint32_t* Af;            // admissibility bits, tile layout
     uint32_t* Lf;            // label bits, tile layout
-    uint8_t* active;         // NT: tile holds an admissible voxel-step
+    uint8_t* active;         // NT: 0 no admissible voxel-step, 1 tested and has some,
+                             // 2 deferred (labels cleared, admissibility not tested yet)
     uint32_t* dirty;         // 2 x NT: tile scheduled for round parity 0 / 1
     uint8_t* chg;            // 2 x NT: tile's members changed since its last pull
     uint32_t* work;          // 2 x NT: work lists of round parity 0 / 1
@@ -78,7 +80,12 @@ struct Dev {
     uint32_t* counters;      // Counter
     unsigned long long* stat64;
     uint32_t* bar;           // grid barrier arrival counter
+    const float2* tsum;      // NT: (min, max) of the tile's field values (load time)
+    const float2* psum;      // P: (min, max) of each particle's values (load time)
+    uint32_t* cand;          // candidate tile list (tiles whose range meets the band)
+    const uint8_t* tpred;    // NT or null: candidate tiles to test before the rounds
     float crit[4];
+    int admit_all;           // 1: test every voxel-step; 0: only candidate tiles
 };
 
 // ---- launchers (kernels.hip) ----
@@ -86,6 +93,8 @@ void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 void launch_reset(const Dev& d, hipStream_t s);
 void launch_bin_particles(const Geom& g, const PGeom& pg, const float* xyz, const float* attr,
                           uint32_t* bins, float* attr_t, hipStream_t s);
+void launch_summaries(const Geom& g, const float* field, float2* tsum, hipStream_t s);
+void launch_particle_summaries(const PGeom& pg, const float* attr_t, float2* psum, hipStream_t s);
 void launch_admit_field(const Dev& d, hipStream_t s);
 void launch_admit_particles(const Dev& d, hipStream_t s);
 void launch_seeds(const Dev& d, const int32_t* seeds, int64_t S, hipStream_t s);

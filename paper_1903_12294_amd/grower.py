@@ -42,7 +42,7 @@ class Grower:
     """A library context on one GPU, ordering its work on one HIP stream."""
 
     def __init__(self, device: int = 0, stream=None, tile_t: int | None = None,
-                 schedule: str | None = None):
+                 schedule: str | None = None, admit: str | None = None):
         self.lib = _lib.load_library()
         if stream is None:
             torch = _torch()
@@ -57,6 +57,8 @@ class Grower:
             self._check(self.lib.mf4d_set_tile(self.ctx, tile_t))
         if schedule is not None:
             self.set_schedule(schedule)
+        if admit is not None:
+            self.set_admit_mode(admit)
 
     def _check(self, rc):
         return _lib.check(rc, self.lib)
@@ -113,6 +115,11 @@ class Grower:
         """"persistent" (one cooperative kernel) or "launch" (launches per round)."""
         m = {"persistent": _lib.MF4D_SCHED_PERSISTENT, "launch": _lib.MF4D_SCHED_LAUNCH}[mode]
         self._check(self.lib.mf4d_set_schedule(self.ctx, m))
+
+    def set_admit_mode(self, mode):
+        """"tiles" (only tiles whose value range meets the band) or "all"."""
+        m = {"tiles": _lib.MF4D_ADMIT_TILES, "all": _lib.MF4D_ADMIT_ALL}[mode]
+        self._check(self.lib.mf4d_set_admit_mode(self.ctx, m))
 
     def set_max_rounds(self, cap: int):
         self._check(self.lib.mf4d_set_max_rounds(self.ctx, int(cap)))

@@ -1,0 +1,133 @@
+"""GPU tests of the brick-activity predictor: its forward pass and gradients
+against the fp64 reference (oracle/nn_ref.py), its training, and the grower
+staying bit-exact whatever the predictor says."""
+import numpy as np
+import pytest
+
+from oracle import nn_ref, oracle_grow
+from paper_1903_12294_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _bf16_round(a):
+    return torch.from_numpy(np.asarray(a, np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def _inputs(rng, shape):
+    N, D, H, W = shape
+    x8 = rng.normal(size=(N, D, H, W, 8)).astype(np.float32)
+    x = np.zeros((N, D, H, W, 16), np.float32)
+    x[..., :8] = x8
+    xt = torch.from_numpy(x).to(torch.bfloat16).to("cuda:0").contiguous()
+    return xt, _bf16_round(x8)
+
+
+@pytest.mark.parametrize("shape", [(2, 5, 6, 19), (1, 4, 4, 16), (3, 3, 9, 5)])
+def test_forward_and_gradients_match_fp64_reference(shape):
+    from paper_1903_12294_amd.learned import Net, init_params, join_params, split_params
+    _need_gpu()
+    rng = np.random.default_rng(sum(shape))
+    flat = init_params(7) + 0.02 * rng.normal(size=10833).astype(np.float32)
+    flat = flat.astype(np.float32)
+    parts = split_params(flat)
+    ref_params = [(_bf16_round(p) if i % 2 == 0 else np.asarray(p, np.float64))
+                  for i, p in enumerate(parts)]
+    xt, x_ref = _inputs(rng, shape)
+    y = (rng.random(shape) < 0.3).astype(np.uint8)
+    yt = torch.from_numpy(y).to("cuda:0")
+    net = Net(0)
+    try:
+        net.set_params(flat)
+        assert np.array_equal(net.get_params(), flat)
+        logits = net.forward(xt).cpu().numpy().astype(np.float64)
+        g, loss = net.grad(xt, yt, 2.5)
+        g = g.cpu().numpy().astype(np.float64)
+    finally:
+        net.close()
+    z, cache = nn_ref.forward(ref_params, x_ref)
+    loss_ref, dz = nn_ref.bce_loss(z, y, 2.5)
+    grads_ref = join_params(nn_ref.backward(ref_params, cache, dz)).astype(np.float64)
+    scale = np.abs(z).max() + 1e-6
+    assert np.abs(logits - z).max() < 2e-2 * scale, np.abs(logits - z).max()
+    assert abs(loss - loss_ref) < 1e-2 * abs(loss_ref)
+    off = 0
+    for cin, cout in [(8, 16), (16, 16), (16, 1)]:
+        n = cout * cin * 27 + cout
+        a, b = g[off:off + n], grads_ref[off:off + n]
+        rel = np.linalg.norm(a - b) / (np.linalg.norm(b) + 1e-12)
+        assert rel < 3e-2, (cin, cout, rel)
+        off += n
+
+
+def test_training_reduces_loss():
+    from paper_1903_12294_amd.learned import Net, init_params, make_dataset, train
+    _need_gpu()
+    data = make_dataset([11, 12], config=1)
+    net = Net(0)
+    try:
+        net.set_params(init_params(3))
+        hist = train(net, data, epochs=40, lr=3e-3)
+    finally:
+        net.close()
+    assert hist[-1] < 0.7 * hist[0], hist
+
+
+@pytest.mark.parametrize("variant", ["field", "noise"])
+def test_learned_schedule_is_exact(variant):
+    from paper_1903_12294_amd import Grower
+    from paper_1903_12294_amd.learned import Net, init_params, set_predictor
+    _need_gpu()
+    inst = synth.make_config(2, attr_mode=variant)
+    ofm, opm, _ = oracle_grow(inst["field"], inst["xyz"], inst["attr"], inst["crit"], inst["seeds"])
+    net = Net(0)
+    g = Grower(device=0)
+    try:
+        g.load_field(inst["field"])
+        g.load_particles(inst["xyz"], inst["attr"])
+        g.set_criteria(*inst["crit"])
+        g.set_seeds(inst["seeds"])
+        nan_params = np.full(10833, np.nan, np.float32)
+        for params, thr in [(init_params(1), 0.0), (init_params(2), -np.inf),
+                            (init_params(2), np.inf), (nan_params, 0.0)]:
+            net.set_params(params)
+            set_predictor(g, net, thr)
+            for schedule in ("persistent", "launch"):
+                g.set_schedule(schedule)
+                g.grow()
+                assert np.array_equal(g.read_field_mask(), ofm), (thr, schedule)
+                assert np.array_equal(g.read_particle_mask(), opm), (thr, schedule)
+        set_predictor(g, None)
+        g.grow()
+        assert np.array_equal(g.read_field_mask(), ofm)
+    finally:
+        g.close()
+        net.close()
+
+
+def test_labels_are_members_per_brick():
+    from paper_1903_12294_amd import Grower
+    from paper_1903_12294_amd.learned import labels
+    from tests import golden_io
+    _need_gpu()
+    inst = synth.make_config(1)
+    g = Grower(device=0)
+    try:
+        g.load_field(inst["field"])
+        g.load_particles(inst["xyz"], inst["attr"])
+        g.set_criteria(*inst["crit"])
+        g.set_seeds(inst["seeds"])
+        g.grow()
+        y = labels(g).cpu().numpy()
+        Mf = golden_io.unpack_field(g.read_field_mask(), inst["field"].shape)
+    finally:
+        g.close()
+    T, Z, Y, X = Mf.shape
+    exp = Mf.reshape(T, Z // 8, 8, Y // 8, 8, X // 8, 8).any(axis=(2, 4, 6))
+    assert np.array_equal(y.astype(bool), exp)

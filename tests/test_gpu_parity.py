@@ -17,10 +17,11 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def _grow_gpu(inst, tile_t=None, device_inputs=True, crit=None, seeds=None, schedule=None):
+def _grow_gpu(inst, tile_t=None, device_inputs=True, crit=None, seeds=None, schedule=None,
+             admit=None):
     from paper_1903_12294_amd import Grower
     _need_gpu()
-    g = Grower(device=0, tile_t=tile_t, schedule=schedule)
+    g = Grower(device=0, tile_t=tile_t, schedule=schedule, admit=admit)
     try:
         if device_inputs:
             dev = torch.device("cuda:0")
@@ -59,11 +60,12 @@ def _assert_parity(inst, tag="", **kw):
     return st, ost
 
 
+@pytest.mark.parametrize("admit", ["tiles", "all"])
 @pytest.mark.parametrize("schedule", ["persistent", "launch"])
 @pytest.mark.parametrize("case", golden_io.all_cases(), ids=lambda c: c["name"])
-def test_golden_fixtures_on_gpu(case, schedule):
+def test_golden_fixtures_on_gpu(case, schedule, admit):
     inst = dict(case)
-    _assert_parity(inst, tag=case["name"], schedule=schedule)
+    _assert_parity(inst, tag=case["name"], schedule=schedule, admit=admit)
 
 
 @pytest.mark.parametrize("seed", range(24))
@@ -75,7 +77,8 @@ def test_random_small_ragged(seed):
     P = int(rng.integers(0, 300))
     inst = _random_instance(rng, X, Y, Z, T, P, 5)
     _assert_parity(inst, tag=f"random{seed}", tile_t=[4, 8, 16][seed % 3],
-                   schedule=["persistent", "launch"][(seed // 3) % 2])
+                   schedule=["persistent", "launch"][(seed // 3) % 2],
+                   admit=["tiles", "all"][(seed // 6) % 2])
 
 
 @pytest.mark.parametrize("schedule", ["persistent", "launch"])
@@ -102,11 +105,12 @@ def test_ragged_multi_tile(shape):
     _assert_parity(inst, tag=f"ragged{shape}")
 
 
+@pytest.mark.parametrize("admit", ["tiles", "all"])
 @pytest.mark.parametrize("schedule", ["persistent", "launch"])
 @pytest.mark.parametrize("variant", ["field", "noise"])
-def test_config2(variant, schedule):
+def test_config2(variant, schedule, admit):
     inst = synth.make_config(2, attr_mode=variant)
-    st, ost = _assert_parity(inst, tag=f"cfg2-{variant}", schedule=schedule)
+    st, ost = _assert_parity(inst, tag=f"cfg2-{variant}", schedule=schedule, admit=admit)
     print(f"[cfg2] rounds {st['rounds']} visits {st['tile_visits']} depth {ost['depth']}")
 
 
@@ -219,3 +223,26 @@ def test_repeat_grows_identical(schedule):
         g.close()
     for f, p in outs[1:]:
         assert np.array_equal(f, outs[0][0]) and np.array_equal(p, outs[0][1])
+
+
+def test_criteria_change_between_grows():
+    """Labels and admissibility of tiles that stop being candidates must not
+    leak into the next grow (tiles are skipped, not cleared)."""
+    from paper_1903_12294_amd import Grower
+    _need_gpu()
+    inst = synth.make_config(1, attr_mode="noise")
+    g = Grower(device=0)
+    try:
+        g.load_field(inst["field"])
+        g.load_particles(inst["xyz"], inst["attr"])
+        g.set_seeds(inst["seeds"])
+        for crit in ([0.1, np.inf, 0.1, np.inf], [0.5, np.inf, 0.5, np.inf],
+                     [0.3, 0.6, 0.2, 0.9], [0.05, np.inf, 0.05, np.inf], [0.3, np.inf, 0.3, np.inf]):
+            crit = np.array(crit, np.float32)
+            g.set_criteria(*crit)
+            g.grow()
+            fm, pm = g.read_field_mask(), g.read_particle_mask()
+            ofm, opm, _ = oracle_grow(inst["field"], inst["xyz"], inst["attr"], crit, inst["seeds"])
+            assert np.array_equal(fm, ofm) and np.array_equal(pm, opm), crit
+    finally:
+        g.close()
