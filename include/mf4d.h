@@ -192,6 +192,11 @@ int mf4d_read_particle_mask(mf4d_ctx *ctx, uint8_t *dst, size_t n, int where);
 int mf4d_set_queries(mf4d_ctx *ctx, int Q, const float *crit, const int32_t *qxyzt, int64_t S,
                      int where);
 
+/* Tile of the batched grower: bx * by * bz * bt = 512 voxel-steps, each a
+ * power of two (default 8 x 4 x 4 x 4); one thread per voxel-step of a tile.
+ * Errors: MF4D_ERR_ARG. */
+int mf4d_set_batched_tile(mf4d_ctx *ctx, int bx, int by, int bz, int bt);
+
 /* Grow every query and write the results: fplanes uint32 [X*Y*Z*T][8] in
  * canonical voxel order, query q in bit (q & 31) of word (q >> 5); pplanes
  * uint32 [T][P][8] likewise (NULL allowed when no particles are loaded).

@@ -75,6 +75,7 @@ SIGNATURES = {
     "mf4d_set_queries": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_int64, c_int]),
     "mf4d_grow_batched": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, c_int,
                                   POINTER(Stats)]),
+    "mf4d_set_batched_tile": (c_int, [c_void_p, c_int, c_int, c_int, c_int]),
     "mf4d_net_num_params": (c_int, []),
     "mf4d_net_create": (c_int, [POINTER(c_void_p), c_int, c_void_p]),
     "mf4d_net_destroy": (None, [c_void_p]),

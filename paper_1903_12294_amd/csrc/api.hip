@@ -133,6 +133,7 @@ struct mf4d_ctx {
     int64_t QS = 0, qseeds_cap = 0;
     uint32_t NTB = 0;
     int NXb = 0, NYb = 0, NZb = 0, NTb = 0;
+    int blog[4] = {3, 2, 2, 2};  // log2 of the batched tile extents (x, y, z, t)
     uint8_t* b_active = nullptr;
     uint32_t* b_dirty = nullptr;
     uint8_t* b_chg = nullptr;
@@ -796,6 +797,24 @@ int mf4d_set_queries(mf4d_ctx* c, int Q, const float* crit, const int32_t* qxyzt
     return MF4D_OK;
 }
 
+int mf4d_set_batched_tile(mf4d_ctx* c, int bx, int by, int bz, int bt) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    const int e[4] = {bx, by, bz, bt};
+    int lg[4];
+    for (int i = 0; i < 4; ++i) {
+        lg[i] = e[i] > 0 ? ilog2(e[i]) : -1;
+        if (lg[i] < 0 || e[i] > 64) return fail(MF4D_ERR_ARG, "tile extents must be powers of two <= 64");
+    }
+    if (bx * by * bz * bt != 512) return fail(MF4D_ERR_ARG, "a batched tile holds 512 voxel-steps");
+    for (int i = 0; i < 4; ++i) c->blog[i] = lg[i];
+    dev_free(c->b_active);
+    dev_free(c->b_dirty);
+    dev_free(c->b_chg);
+    dev_free(c->b_work);
+    c->NTB = 0;
+    return MF4D_OK;
+}
+
 int mf4d_grow_batched(mf4d_ctx* c, uint32_t* fplanes, size_t fwords, uint32_t* pplanes,
                       size_t pwords, int where, mf4d_stats* out) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
@@ -812,7 +831,10 @@ int mf4d_grow_batched(mf4d_ctx* c, uint32_t* fplanes, size_t fwords, uint32_t* p
         return fail(MF4D_ERR_ARG, "plane buffers must be 16-byte aligned");
     HIP_TRY(hipSetDevice(c->device));
     if (c->NTB == 0) {
-        const int NXb = (g.X + 7) / 8, NYb = (g.Y + 3) / 4, NZb = (g.Z + 3) / 4, NTb = (g.T + 3) / 4;
+        const int NXb = (g.X + (1 << c->blog[0]) - 1) >> c->blog[0];
+        const int NYb = (g.Y + (1 << c->blog[1]) - 1) >> c->blog[1];
+        const int NZb = (g.Z + (1 << c->blog[2]) - 1) >> c->blog[2];
+        const int NTb = (g.T + (1 << c->blog[3]) - 1) >> c->blog[3];
         const uint64_t ntb = (uint64_t)NXb * NYb * NZb * NTb;
         int rc = dev_alloc(&c->b_active, (size_t)ntb + 8);
         if (!rc) rc = dev_alloc(&c->b_dirty, 2 * (size_t)ntb);
@@ -842,6 +864,7 @@ int mf4d_grow_batched(mf4d_ctx* c, uint32_t* fplanes, size_t fwords, uint32_t* p
     d.g = g;
     d.X = g.X; d.Y = g.Y; d.Z = g.Z; d.T = g.T;
     d.NXb = c->NXb; d.NYb = c->NYb; d.NZb = c->NZb; d.NTb = c->NTb;
+    d.lx = c->blog[0]; d.ly = c->blog[1]; d.lz = c->blog[2]; d.lt = c->blog[3];
     d.NTB = c->NTB;
     d.Q = c->Q;
     d.P = (int64_t)P;

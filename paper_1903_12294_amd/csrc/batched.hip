@@ -9,9 +9,10 @@
 //
 // Field labels are grown in place in the caller's [V][8] output (canonical
 // voxel order); particle labels in the caller's [T][P][8] output.  Work is
-// organised in tiles of 8 (x) x 4 (y) x 4 (z) x 4 (t) voxel-steps, one thread
-// per voxel-step, with the round protocol of the single-query grower: sweep,
-// pull, close/push, double-buffered work lists by round parity.
+// organised in 4D tiles of 512 voxel-steps (a power-of-two extent per axis,
+// chosen per context, e.g. 8 x 4 x 4 x 4), one thread per voxel-step, with
+// the round protocol of the single-query grower: sweep, pull, close/push,
+// double-buffered work lists by round parity.
 #include "mf4d_internal.h"
 #include "batched.h"
 
@@ -73,7 +74,7 @@ __device__ __forceinline__ BandTables particle_tables(const DevB& d) {
 }
 
 __device__ __forceinline__ uint32_t btile_of(const DevB& d, int x, int y, int z, int t) {
-    return ((uint32_t)((t >> 2) * d.NZb + (z >> 2)) * d.NYb + (y >> 2)) * d.NXb + (x >> 3);
+    return ((uint32_t)((t >> d.lt) * d.NZb + (z >> d.lz)) * d.NYb + (y >> d.ly)) * d.NXb + (x >> d.lx);
 }
 
 __device__ __forceinline__ void btile_coords(const DevB& d, uint32_t tile, int& bx, int& by, int& bz,
@@ -125,14 +126,15 @@ __device__ void bmark_voxel(const DevB& d, int x, int y, int z, int t, int par) 
     const uint32_t sy = d.NXb, sz = d.NXb * d.NYb, st = sz * d.NZb;
     uint32_t nb[8];
     int k = 0;
-    if ((x & 7) == 0 && x > 0) nb[k++] = tile - 1;
-    if ((x & 7) == 7 && x + 1 < d.X) nb[k++] = tile + 1;
-    if ((y & 3) == 0 && y > 0) nb[k++] = tile - sy;
-    if ((y & 3) == 3 && y + 1 < d.Y) nb[k++] = tile + sy;
-    if ((z & 3) == 0 && z > 0) nb[k++] = tile - sz;
-    if ((z & 3) == 3 && z + 1 < d.Z) nb[k++] = tile + sz;
-    if ((t & 3) == 0 && t > 0) nb[k++] = tile - st;
-    if ((t & 3) == 3 && t + 1 < d.T) nb[k++] = tile + st;
+    const int mx = (1 << d.lx) - 1, my = (1 << d.ly) - 1, mz = (1 << d.lz) - 1, mt = (1 << d.lt) - 1;
+    if ((x & mx) == 0 && x > 0) nb[k++] = tile - 1;
+    if ((x & mx) == mx && x + 1 < d.X) nb[k++] = tile + 1;
+    if ((y & my) == 0 && y > 0) nb[k++] = tile - sy;
+    if ((y & my) == my && y + 1 < d.Y) nb[k++] = tile + sy;
+    if ((z & mz) == 0 && z > 0) nb[k++] = tile - sz;
+    if ((z & mz) == mz && z + 1 < d.Z) nb[k++] = tile + sz;
+    if ((t & mt) == 0 && t > 0) nb[k++] = tile - st;
+    if ((t & mt) == mt && t + 1 < d.T) nb[k++] = tile + st;
     for (int i = 0; i < k; ++i)
         if (d.active[nb[i]]) bschedule(d, nb[i], par);
 }
@@ -252,8 +254,11 @@ __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_l
     int bx, by, bz, bt;
     btile_coords(d, tile, bx, by, bz, bt);
     const int tid = threadIdx.x;
-    const int xl = tid & 7, yl = (tid >> 3) & 3, zl = (tid >> 5) & 3, tl = tid >> 7;
-    const int x = bx * 8 + xl, y = by * 4 + yl, z = bz * 4 + zl, t = bt * 4 + tl;
+    const int mx = (1 << d.lx) - 1, my = (1 << d.ly) - 1, mz = (1 << d.lz) - 1, mt = (1 << d.lt) - 1;
+    const int sxl = 1, syl = 1 << d.lx, szl = 1 << (d.lx + d.ly), stl = 1 << (d.lx + d.ly + d.lz);
+    const int xl = tid & mx, yl = (tid >> d.lx) & my, zl = (tid >> (d.lx + d.ly)) & mz,
+              tl = tid >> (d.lx + d.ly + d.lz);
+    const int x = (bx << d.lx) + xl, y = (by << d.ly) + yl, z = (bz << d.lz) + zl, t = (bt << d.lt) + tl;
     const bool in = x < d.X && y < d.Y && z < d.Z && t < d.T;
     if (tid == 0) {
         d.dirty[par * d.NTB + tile] = 0u;
@@ -277,13 +282,13 @@ __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_l
         uint64_t hn[8];
         int nh = 0;
         if (xl == 0 && x > 0) hn[nh++] = v - sx;
-        if (xl == 7 && x + 1 < d.X) hn[nh++] = v + sx;
+        if (xl == mx && x + 1 < d.X) hn[nh++] = v + sx;
         if (yl == 0 && y > 0) hn[nh++] = v - sy;
-        if (yl == 3 && y + 1 < d.Y) hn[nh++] = v + sy;
+        if (yl == my && y + 1 < d.Y) hn[nh++] = v + sy;
         if (zl == 0 && z > 0) hn[nh++] = v - sz;
-        if (zl == 3 && z + 1 < d.Z) hn[nh++] = v + sz;
+        if (zl == mz && z + 1 < d.Z) hn[nh++] = v + sz;
         if (tl == 0 && t > 0) hn[nh++] = v - st;
-        if (tl == 3 && t + 1 < d.T) hn[nh++] = v + st;
+        if (tl == mt && t + 1 < d.T) hn[nh++] = v + st;
         for (int i = 0; i < nh; ++i) {
             const uint4* hp = reinterpret_cast<const uint4*>(d.fplanes + hn[i] * 8);
             const uint4 h01 = hp[0], h23 = hp[1];
@@ -297,10 +302,10 @@ __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_l
 #pragma unroll
     for (int k = 0; k < 8; ++k) l0[k] = l[k];
     // in-tile neighbour thread ids (or -1)
-    const int nx0 = xl > 0 ? tid - 1 : -1, nx1 = xl < 7 ? tid + 1 : -1;
-    const int ny0 = yl > 0 ? tid - 8 : -1, ny1 = yl < 3 ? tid + 8 : -1;
-    const int nz0 = zl > 0 ? tid - 32 : -1, nz1 = zl < 3 ? tid + 32 : -1;
-    const int nt0 = tl > 0 ? tid - 128 : -1, nt1 = tl < 3 ? tid + 128 : -1;
+    const int nx0 = xl > 0 ? tid - sxl : -1, nx1 = xl < mx ? tid + sxl : -1;
+    const int ny0 = yl > 0 ? tid - syl : -1, ny1 = yl < my ? tid + syl : -1;
+    const int nz0 = zl > 0 ? tid - szl : -1, nz1 = zl < mz ? tid + szl : -1;
+    const int nt0 = tl > 0 ? tid - stl : -1, nt1 = tl < mt ? tid + stl : -1;
     const int nbr[8] = {nx0, nx1, ny0, ny1, nz0, nz1, nt0, nt1};
     while (true) {
 #pragma unroll
@@ -331,13 +336,13 @@ __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_l
     if (any) {
         uint32_t faces = 1u << 8;  // bit 8: tile changed
         if (xl == 0) faces |= 1u << 0;
-        if (xl == 7) faces |= 1u << 1;
+        if (xl == mx) faces |= 1u << 1;
         if (yl == 0) faces |= 1u << 2;
-        if (yl == 3) faces |= 1u << 3;
+        if (yl == my) faces |= 1u << 3;
         if (zl == 0) faces |= 1u << 4;
-        if (zl == 3) faces |= 1u << 5;
+        if (zl == mz) faces |= 1u << 5;
         if (tl == 0) faces |= 1u << 6;
-        if (tl == 3) faces |= 1u << 7;
+        if (tl == mt) faces |= 1u << 7;
         atomicOr(&s_flags[0], faces);
     }
     __syncthreads();

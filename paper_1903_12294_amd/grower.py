@@ -184,6 +184,9 @@ class Grower:
                                               seeds.shape[0], MF4D_HOST))
         self.Q = crit.shape[0]
 
+    def set_batched_tile(self, bx: int, by: int, bz: int, bt: int):
+        self._check(self.lib.mf4d_set_batched_tile(self.ctx, bx, by, bz, bt))
+
     def grow_batched(self, fplanes=None, pplanes=None) -> tuple:
         """Grow all queries.  Outputs are device tensors (int32, grown in place)
         or, when None, numpy arrays: fplanes [V][8], pplanes [T][P][8] uint32."""
