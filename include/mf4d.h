@@ -96,6 +96,9 @@ typedef struct mf4d_stats {
     double ms_admit;          /* admissibility pass over field and particles */
     double ms_rounds;         /* seeding and all rounds */
     double ms_total;          /* the whole mf4d_grow call on the device */
+    int64_t tiles_tested;     /* single-query grow: tiles whose admissibility was read before the rounds
+                                 (every tile when admissibility is tested everywhere) */
+    int64_t tiles_deferred_read; /* deferred tiles whose admissibility a sweep read */
 } mf4d_stats;
 
 /* Library version string. */

@@ -47,6 +47,8 @@ class Stats(ctypes.Structure):
         ("ms_admit", c_double),
         ("ms_rounds", c_double),
         ("ms_total", c_double),
+        ("tiles_tested", c_int64),
+        ("tiles_deferred_read", c_int64),
     ]
 
     def as_dict(self) -> dict:

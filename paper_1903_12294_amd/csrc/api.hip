@@ -299,6 +299,8 @@ int finish_stats(mf4d_ctx* c, mf4d_stats* out, bool fresh, int64_t rounds) {
     s.tile_visits = (int64_t)c->h_stat[S_TILE_VISITS];
     s.particle_visits = (int64_t)c->h_stat[S_PART_VISITS];
     s.active_tiles = (int64_t)c->h_stat[S_ACTIVE_TILES];
+    if (fresh) s.tiles_tested = c->admit_all ? (int64_t)c->g.NT : (int64_t)c->h_stat[S_TILES_TESTED];
+    s.tiles_deferred_read = (int64_t)c->h_stat[S_DEFERRED_READ];
     s.seeds_dropped = (int64_t)c->h_counters[C_DROPPED];
     s.members_field = -1;
     s.members_particle = c->has_particles ? -1 : 0;

@@ -231,7 +231,10 @@ __device__ void sweep_tile(const Dev& d, uint32_t tile, int par) {
             any |= a[t];
         }
         const bool has = __ballot(any != 0) != 0;
-        if (lane == 0) d.active[tile] = has ? 1 : 0;
+        if (lane == 0) {
+            d.active[tile] = has ? 1 : 0;
+            atomicAdd(&d.stat64[S_DEFERRED_READ], 1ull);
+        }
     } else {
 #pragma unroll
         for (int t = 0; t < BT; ++t) a[t] = Ab[t * 64 + lane];
@@ -682,6 +685,7 @@ __global__ __launch_bounds__(256) void k_admit_tiles(Dev d) {
             }
             d.Lf[wi] = 0u;
         }
+        if (!defer && threadIdx.x == 0) atomicAdd(&d.stat64[S_TILES_TESTED], 1ull);
         if (defer) {
             if (threadIdx.x == 0) d.active[tile] = 2;
         } else if (__ballot(any != 0) != 0 && lane == 0) {

@@ -55,6 +55,8 @@ enum Stat64 : int {
     S_MEMBERS_F = 2,
     S_MEMBERS_P = 3,
     S_ACTIVE_TILES = 4,
+    S_TILES_TESTED = 5,
+    S_DEFERRED_READ = 6,
     S_NSTAT = 8
 };
 

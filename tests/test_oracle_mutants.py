@@ -5,10 +5,13 @@ edge, a wrong sign, a strict comparison, truncation instead of floor, a
 periodic wrap, a skipped criterion).  It is compiled to a temporary library
 and run against the hand-derived fixtures and the brute-force cross-checks;
 every mutant must fail at least one of them.  The mistakes live only in the
-temporary copies, on the CPU.
+temporary copies, on the CPU.  Some mistakes index out of bounds (an index
+past the grid edge), so each mutant runs the battery in a child process; a
+crash there also counts as the mistake being caught.
 """
 import os
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -18,6 +21,9 @@ from tests import golden_io
 from tests.test_oracle_pins import _random_instance
 
 SRC = os.path.join(os.path.dirname(bfs.__file__), "grow_bfs.c")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CHILD = ("import sys; from oracle import bfs; from tests.test_oracle_mutants import _battery; "
+         "r = _battery(bfs.load(sys.argv[1])); print('CAUGHT ' + r if r else 'SURVIVED')")
 
 MUTANTS = {
     "drop_plus_t_edge": ("if (t + 1 < (uint64_t)T) nb[k++] = v + XYZ;", ""),
@@ -85,5 +91,9 @@ def test_mutant_is_caught(name, tmp_path):
     so = str(tmp_path / f"lib{name}.so")
     subprocess.run(["gcc", "-O1", "-std=c99", "-fPIC", "-shared", "-o", so, str(path), "-lm"],
                    check=True)
-    lib = bfs.load(so)
-    assert _battery(lib) is not None, f"mutant {name} survived every pin"
+    res = subprocess.run([sys.executable, "-c", CHILD, so], cwd=ROOT, capture_output=True,
+                         text=True, timeout=600)
+    out = res.stdout.strip().splitlines()
+    crashed = res.returncode < 0
+    assert crashed or (res.returncode == 0 and out and out[-1].startswith("CAUGHT")), (
+        f"mutant {name} survived every pin: rc={res.returncode} {res.stdout[-300:]} {res.stderr[-300:]}")
