@@ -70,15 +70,33 @@ def sigmoid(z):
     return 1.0 / (1.0 + np.exp(-z))
 
 
-def forward(params, x):
-    """Returns (logits [N,D,H,W], cache)."""
+def bf16_round(a):
+    """Nearest bfloat16 value of each float32 value (ties to even), as float64;
+    NaN stays NaN.  bfloat16 keeps float32's sign, exponent and the top 7
+    mantissa bits, so rounding is integer arithmetic on the float32 bits."""
+    a32 = np.asarray(a, np.float32)
+    u = a32.view(np.uint32).astype(np.uint64)
+    r = (((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16).astype(np.uint32)
+    out = r.view(np.float32)
+    return np.where(np.isnan(a32), a32, out).astype(np.float64)
+
+
+def forward(params, x, bf16_storage: bool = False):
+    """Returns (logits [N,D,H,W], cache).
+
+    With bf16_storage the hidden activations are rounded to bfloat16 after the
+    ReLU and the logits to float32, as when they are stored in those types
+    between layers; the arithmetic itself stays fp64."""
     w1, b1, w2, b2, w3, b3 = params
+    rnd = bf16_round if bf16_storage else (lambda a: a)
     z1 = conv3d(x, w1, b1)
-    a1 = np.maximum(z1, 0)
+    a1 = rnd(np.maximum(z1, 0))
     z2 = conv3d(a1, w2, b2)
-    a2 = np.maximum(z2, 0)
-    z3 = conv3d(a2, w3, b3)
-    return z3[..., 0], (x, z1, a1, z2, a2)
+    a2 = rnd(np.maximum(z2, 0))
+    z3 = conv3d(a2, w3, b3)[..., 0]
+    if bf16_storage:
+        z3 = z3.astype(np.float32).astype(np.float64)
+    return z3, (x, z1, a1, z2, a2)
 
 
 def bce_loss(logits, y, pos_weight):
@@ -93,14 +111,17 @@ def bce_loss(logits, y, pos_weight):
     return loss.mean(), dz
 
 
-def backward(params, cache, dlogits):
+def backward(params, cache, dlogits, bf16_storage: bool = False):
+    """Parameter gradients; with bf16_storage each layer's output gradient is
+    rounded to bfloat16 before it is used (as when stored in that type)."""
     w1, b1, w2, b2, w3, b3 = params
     x, z1, a1, z2, a2 = cache
-    d3 = np.asarray(dlogits, np.float64)[..., None]
+    rnd = bf16_round if bf16_storage else (lambda a: a)
+    d3 = rnd(np.asarray(dlogits, np.float64))[..., None]
     da2, dw3, db3 = conv3d_backward(a2, w3, d3)
-    dz2 = da2 * (z2 > 0)
+    dz2 = rnd(da2 * (z2 > 0))
     da1, dw2, db2 = conv3d_backward(a1, w2, dz2)
-    dz1 = da1 * (z1 > 0)
+    dz1 = rnd(da1 * (z1 > 0))
     _, dw1, db1 = conv3d_backward(x, w1, dz1)
     return [dw1, db1, dw2, db2, dw3, db3]
 

@@ -201,7 +201,7 @@ __global__ void k_reduce_parts(const float* __restrict__ part, uint32_t nblk, ui
 }
 
 // Binary cross entropy with logits, positive weight pw, mean over n
-// positions: dz (bf16, channel 0 of 16) and per-block loss sums.
+// positions: dz (bf16, channel 0 of 16) and per-block shares of the mean loss.
 __global__ __launch_bounds__(256) void k_bce(const float* __restrict__ logits,
                                              const uint8_t* __restrict__ y, uint64_t n, float pw,
                                              uint16_t* __restrict__ dz, float* __restrict__ part_loss) {
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256) void k_bce(const float* __restrict__ logits,
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
     if (lane_id() == 0) s_sum[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) part_loss[blockIdx.x] = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
+    if (threadIdx.x == 0) part_loss[blockIdx.x] = (s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3]) * inv;
 }
 
 // Reference-layout fp32 parameters -> padded bf16 kernel weights:

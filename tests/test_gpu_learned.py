@@ -51,18 +51,31 @@ def test_forward_and_gradients_match_fp64_reference(shape):
         g = g.cpu().numpy().astype(np.float64)
     finally:
         net.close()
+    # Tight check: the fp64 reference with the kernels' storage points (hidden
+    # activations and layer gradients held in bf16, logits in fp32); what
+    # remains is fp32 accumulation order.
+    zq, cache_q = nn_ref.forward(ref_params, x_ref, bf16_storage=True)
+    loss_q, dz_q = nn_ref.bce_loss(zq, y, 2.5)
+    grads_q = join_params(nn_ref.backward(ref_params, cache_q, dz_q, bf16_storage=True)).astype(np.float64)
+    scale = np.abs(zq).max() + 1e-6
+    assert np.abs(logits - zq).max() < 1e-3 * scale, np.abs(logits - zq).max()
+    assert abs(loss - loss_q) < 1e-4 * abs(loss_q), (loss, loss_q)
+    # Loose check against pure fp64: bf16 storage alone moves the first
+    # layer's weight gradient by up to ~5% on these small ragged grids, where
+    # its sums over few positions cancel heavily.
     z, cache = nn_ref.forward(ref_params, x_ref)
     loss_ref, dz = nn_ref.bce_loss(z, y, 2.5)
     grads_ref = join_params(nn_ref.backward(ref_params, cache, dz)).astype(np.float64)
-    scale = np.abs(z).max() + 1e-6
-    assert np.abs(logits - z).max() < 2e-2 * scale, np.abs(logits - z).max()
+    assert np.abs(logits - z).max() < 2e-2 * scale
     assert abs(loss - loss_ref) < 1e-2 * abs(loss_ref)
     off = 0
     for cin, cout in [(8, 16), (16, 16), (16, 1)]:
         n = cout * cin * 27 + cout
-        a, b = g[off:off + n], grads_ref[off:off + n]
+        a, bq, b = g[off:off + n], grads_q[off:off + n], grads_ref[off:off + n]
+        rel_q = np.linalg.norm(a - bq) / (np.linalg.norm(bq) + 1e-12)
         rel = np.linalg.norm(a - b) / (np.linalg.norm(b) + 1e-12)
-        assert rel < 3e-2, (cin, cout, rel)
+        assert rel_q < 2e-3, (cin, cout, rel_q)
+        assert rel < 1e-1, (cin, cout, rel)
         off += n
 
 

@@ -93,3 +93,31 @@ def test_adam_first_step_is_signed_lr():
     v = [np.zeros(3)]
     p1, m1, v1 = nn_ref.adam_step(p, g, m, v, 1, lr=0.01, eps=0.0)
     assert np.allclose(p1[0], p[0] - 0.01 * np.sign(g[0]))
+
+
+def test_bf16_round_matches_torch_bfloat16():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(9)
+    a = np.concatenate([rng.normal(size=2000) * 10.0 ** rng.integers(-30, 30, 2000),
+                        [0.0, -0.0, np.inf, -np.inf, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8,
+                         3.3895313892515355e38, 1e-40, -1e-42]]).astype(np.float32)
+    exp = torch.from_numpy(a).to(torch.bfloat16).to(torch.float64).numpy()
+    got = nn_ref.bf16_round(a)
+    assert np.array_equal(got, exp)
+    assert np.isnan(nn_ref.bf16_round(np.array([np.nan], np.float32))[0])
+
+
+def test_bf16_storage_is_identity_on_representable_values():
+    # activations and gradients that are already bfloat16 values (small
+    # integers here) pass the storage rounding unchanged
+    rng = np.random.default_rng(4)
+    params = [np.round(p * 4) for p in nn_ref.init_params(rng, cin=2, hidden=2)]
+    params = [p * 0 + np.clip(p, -2, 2) for p in params]
+    x = rng.integers(-2, 3, size=(1, 3, 3, 3, 2)).astype(np.float64)
+    z, c = nn_ref.forward(params, x)
+    zb, cb = nn_ref.forward(params, x, bf16_storage=True)
+    assert np.array_equal(z, zb)
+    g = nn_ref.backward(params, c, np.sign(z))
+    gb = nn_ref.backward(params, cb, np.sign(z), bf16_storage=True)
+    for a, b in zip(g, gb):
+        assert np.array_equal(a, b)
