@@ -143,6 +143,7 @@ struct mf4d_ctx {
     // brick statistics and the activity predictor
     BrickDims bd{};
     float4* bstats = nullptr;   // [T][Db][Hb][Wb] (min, max, mean, particle-steps)
+    bool bstats_valid = false;  // computed on first use by the predictor
     uint16_t* feat = nullptr;   // bf16 [T][Db][Hb][Wb][16]
     float* blogits = nullptr;   // [T][Db][Hb][Wb]
     uint8_t* tpred = nullptr;   // NT
@@ -185,6 +186,7 @@ void free_particles(mf4d_ctx* c) {
     dev_free(c->psum);
     c->has_particles = false;
     c->pg = PGeom{};
+    c->bstats_valid = false;
 }
 
 int staging_for(mf4d_ctx* c, size_t bytes, void** out) {
@@ -447,7 +449,7 @@ int mf4d_load_field(mf4d_ctx* c, const float* field, int X, int Y, int Z, int T,
     launch_fill_u32(c->Af, 0, g.nwords, c->stream);
     launch_fill_u32(c->Lf, 0, g.nwords, c->stream);
     launch_summaries(g, c->field, c->tsum, c->stream);
-    launch_brick_stats(g, PGeom{}, bd, c->field, nullptr, c->bstats, c->stream);
+    c->bstats_valid = false;
     rc = sync(c);
     if (rc) {
         free_field(c);
@@ -522,7 +524,7 @@ int mf4d_load_particles(mf4d_ctx* c, const float* xyz, const float* attr, int64_
     }
     launch_bin_particles(c->g, pg, dx, da, c->bins, c->attr_t, c->stream);
     launch_particle_summaries(pg, c->attr_t, c->psum, c->stream);
-    launch_brick_stats(c->g, pg, c->bd, c->field, c->bins, c->bstats, c->stream);
+    c->bstats_valid = false;
     launch_fill_u32(c->pdirty, 0, (P + 31) / 32, c->stream);
     rc = sync(c);
     if (tmp) (void)hipFree(tmp);
@@ -624,6 +626,15 @@ int mf4d_set_schedule(mf4d_ctx* c, int mode) {
     return MF4D_OK;
 }
 
+// Brick statistics (network input) of the loaded field and particles, on the
+// context's stream; computed once per load, when first needed.
+void ensure_brick_stats(mf4d_ctx* c) {
+    if (c->bstats_valid) return;
+    launch_brick_stats(c->g, c->has_particles ? c->pg : PGeom{}, c->bd, c->field,
+                       c->has_particles ? c->bins : nullptr, c->bstats, c->stream);
+    c->bstats_valid = true;
+}
+
 int mf4d_grow(mf4d_ctx* c, mf4d_stats* out) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
     if (!c->has_field) return fail(MF4D_ERR_STATE, "no field loaded");
@@ -638,6 +649,7 @@ int mf4d_grow(mf4d_ctx* c, mf4d_stats* out) {
     Dev dp = d;
     if (c->net && !c->admit_all) {
         // the predictor marks the candidate tiles to test before the rounds
+        ensure_brick_stats(c);
         launch_features(c->bd, c->bstats, c->crit[0], c->feat, s);
         int rc = net_infer(c->net, c->feat, c->bd.T, c->bd.D, c->bd.H, c->bd.W, c->blogits, s);
         if (rc) return fail(rc, "predictor: %s", net_last_error());
@@ -945,6 +957,7 @@ int mf4d_features(mf4d_ctx* c, uint16_t* dst, size_t n, int where) {
     const size_t need = (size_t)c->bd.T * c->bd.D * c->bd.H * c->bd.W * 16;
     if (n < need) return fail(MF4D_ERR_ARG, "dst holds %zu elements, %zu needed", n, need);
     HIP_TRY(hipSetDevice(c->device));
+    ensure_brick_stats(c);
     launch_features(c->bd, c->bstats, c->crit[0], c->feat, c->stream);
     HIP_TRY(hipMemcpyAsync(dst, c->feat, need * sizeof(uint16_t),
                            where == MF4D_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,

@@ -440,14 +440,18 @@ __device__ bool grid_sync(const Dev& d, uint32_t& epoch) {
         __hip_atomic_fetch_add(d.bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         uint32_t ok = 1;
         uint32_t polls = 0;
-        while (__hip_atomic_load(d.bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
-            __builtin_amdgcn_s_sleep(1);
+        // Poll with relaxed loads: an acquire per poll would invalidate this
+        // XCD's L2 on every iteration and starve the waves still working.  One
+        // acquire fence after the wait makes the other blocks' writes visible.
+        while (__hip_atomic_load(d.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+            __builtin_amdgcn_s_sleep(2);
             if (++polls > (1u << 22)) {
                 atomicExch(&d.counters[C_ERR], 1u);
                 ok = 0;
                 break;
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (load_relaxed(&d.counters[C_ERR])) ok = 0;
         s_ok = ok;
     }
@@ -588,10 +592,19 @@ __global__ __launch_bounds__(256) void k_admit_field(Dev d) {
     }
 }
 
+__device__ __forceinline__ void minmax_skip_nan(float v, float& mn, float& mx) {
+    if (v == v) {
+        mn = fminf(mn, v);
+        mx = fmaxf(mx, v);
+    }
+}
+
 // Load time: (min, max) of each tile's non-NaN field values ((+inf, -inf)
 // when it has none).  A tile can hold a voxel with lo <= f <= hi only if
 // max >= lo and min <= hi, so these decide, exactly, which tiles a grow must
-// test at all.  Block = one tile; lane = (z_l, y_l) row, x by 16-byte loads.
+// test at all.  Block = one tile, wave = t-slices; when X is a multiple of 4
+// eight lanes read one 128-byte tile row with 16-byte loads, so a wave
+// instruction covers 8 whole rows.
 __global__ __launch_bounds__(256) void k_tile_summaries(Geom g, const float* __restrict__ f,
                                                         float2* __restrict__ tsum) {
     __shared__ float s_mn[4], s_mx[4];
@@ -599,19 +612,41 @@ __global__ __launch_bounds__(256) void k_tile_summaries(Geom g, const float* __r
     int tx, ty, tz, tt;
     tile_coords(g, tile, tx, ty, tz, tt);
     const int lane = lane_id(), wave = threadIdx.x >> 6;
-    const int y = ty * 8 + (lane & 7), z = tz * 8 + (lane >> 3);
     float mn = __builtin_inff(), mx = -__builtin_inff();
-    for (int tl = wave; tl < g.BT; tl += 4) {
-        const int t = (tt << g.logBT) + tl;
-        if (t >= g.T || y >= g.Y || z >= g.Z) continue;
-        const float* rp = f + ((size_t)(t * g.Z + z) * g.Y + y) * g.X;
-        for (int k = 0; k < 32; ++k) {
-            const int x = tx * 32 + k;
-            if (x >= g.X) break;
-            const float v = rp[x];
-            if (v == v) {
-                mn = fminf(mn, v);
-                mx = fmaxf(mx, v);
+    if ((g.X & 3) == 0) {
+        const int quad = lane & 7;
+        const int x = tx * 32 + quad * 4;
+        for (int tl = wave; tl < g.BT; tl += 4) {
+            const int t = (tt << g.logBT) + tl;
+            if (t >= g.T) break;
+            v4f v[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int row = i * 8 + (lane >> 3);  // (z_l, y_l) = (row >> 3, row & 7)
+                const int y = ty * 8 + (row & 7), z = tz * 8 + (row >> 3);
+                v[i] = (v4f){__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""), __builtin_nanf("")};
+                if (x < g.X && y < g.Y && z < g.Z)
+                    v[i] = __builtin_nontemporal_load(
+                        reinterpret_cast<const v4f*>(f + ((size_t)(t * g.Z + z) * g.Y + y) * g.X + x));
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                minmax_skip_nan(v[i].x, mn, mx);
+                minmax_skip_nan(v[i].y, mn, mx);
+                minmax_skip_nan(v[i].z, mn, mx);
+                minmax_skip_nan(v[i].w, mn, mx);
+            }
+        }
+    } else {
+        const int xl = lane & 31;
+        const int x = tx * 32 + xl;
+        for (int tl = wave; tl < g.BT; tl += 4) {
+            const int t = (tt << g.logBT) + tl;
+            if (t >= g.T) break;
+            for (int row = lane >> 5; row < 64; row += 2) {
+                const int y = ty * 8 + (row & 7), z = tz * 8 + (row >> 3);
+                if (x < g.X && y < g.Y && z < g.Z)
+                    minmax_skip_nan(f[((size_t)(t * g.Z + z) * g.Y + y) * g.X + x], mn, mx);
             }
         }
     }
@@ -629,19 +664,45 @@ __global__ __launch_bounds__(256) void k_tile_summaries(Geom g, const float* __r
                                  fmaxf(fmaxf(s_mx[0], s_mx[1]), fmaxf(s_mx[2], s_mx[3])));
 }
 
-// Load time: (min, max) of each particle's non-NaN values over its steps.
-__global__ void k_particle_summaries(PGeom pg, const float* __restrict__ at, float2* __restrict__ psum) {
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < pg.P;
-         p += (int64_t)gridDim.x * blockDim.x) {
+// Load time: (min, max) of each particle's non-NaN values over its steps
+// (padding steps hold NaN).  A group of G lanes reads one particle's row with
+// 16-byte loads (G = 16, or Tpad / 4 for short rows), so a wave instruction
+// covers whole rows.
+__global__ __launch_bounds__(256) void k_particle_summaries(PGeom pg, const float* __restrict__ at,
+                                                            float2* __restrict__ psum) {
+    if (pg.Tpad < 4) {
+        for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < pg.P;
+             p += (int64_t)gridDim.x * blockDim.x) {
+            float mn = __builtin_inff(), mx = -__builtin_inff();
+            for (int t = 0; t < pg.Tpad; ++t) minmax_skip_nan(at[p * pg.Tpad + t], mn, mx);
+            psum[p] = make_float2(mn, mx);
+        }
+        return;
+    }
+    const int G = pg.Tpad >= 64 ? 16 : (pg.Tpad >> 2);
+    const int per_wave = 64 / G;
+    const int lane = lane_id(), sub = lane & (G - 1);
+    const int64_t wave_id = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int nq = pg.Tpad >> 2;
+    for (int64_t p0 = wave_id * per_wave; p0 < pg.P; p0 += nwaves * per_wave) {
+        const int64_t p = p0 + lane / G;
         float mn = __builtin_inff(), mx = -__builtin_inff();
-        for (int t = 0; t < pg.T; ++t) {
-            const float v = at[p * pg.Tpad + t];
-            if (v == v) {
-                mn = fminf(mn, v);
-                mx = fmaxf(mx, v);
+        if (p < pg.P) {
+            const v4f* row = reinterpret_cast<const v4f*>(at + p * pg.Tpad);
+            for (int c = sub; c < nq; c += G) {
+                const v4f v = __builtin_nontemporal_load(row + c);
+                minmax_skip_nan(v.x, mn, mx);
+                minmax_skip_nan(v.y, mn, mx);
+                minmax_skip_nan(v.z, mn, mx);
+                minmax_skip_nan(v.w, mn, mx);
             }
         }
-        psum[p] = make_float2(mn, mx);
+        for (int o = 1; o < G; o <<= 1) {
+            mn = fminf(mn, __shfl_xor(mn, o));
+            mx = fmaxf(mx, __shfl_xor(mx, o));
+        }
+        if (p < pg.P && sub == 0) psum[p] = make_float2(mn, mx);
     }
 }
 
