@@ -1,10 +1,20 @@
 """Benchmark: voxel-timesteps segmented per second to the fixed point on one GPU.
 
 One step = one pass of the whole hot path over resident inputs: admissibility
-of every field and particle sample, seeding, rounds of tile sweeps and
+of the field and particle samples, seeding, rounds of tile sweeps and
 particle coupling until nothing changes, and the read-out of the uint32 field
-mask and the uint8 particle-step mask into device buffers.
+mask and the uint8 particle-step mask into device buffers.  The workload is
+the 256^3 x 64 field with 4,194,304 particles (64 crossing blobs, 32 seeds,
+thresholds 0.25 / 0.25); the single-query configuration (tile depth, round
+schedule, admissibility mode) is the autotuner's pick, every candidate
+checked to give identical masks.
 
+Beside the headline the bench reports, on the same GPU:
+  eager    - admissibility of every sample each step (the dense HBM pass);
+  learned  - the brick-activity predictor choosing the tiles tested up front,
+             trained (committed weights) and untrained, masks compared;
+  batched  - 256 queries as bit-planes on the 128^3 x 32 workload versus 256
+             single-query grows, sampled planes compared.
 Prints one JSON line (stdout).  Progress goes to stderr.
 """
 from __future__ import annotations
@@ -21,22 +31,150 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+PREDICTOR = os.path.join(ROOT, "paper_1903_12294_amd", "predictor.npy")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def field_kernel_bytes(V: int) -> int:
-    """Algorithmic bytes of one field-admissibility launch: read every fp32
-    sample once, write one bit per voxel-step."""
-    return 4 * V + V // 8
+def tile_voxels(bt: int) -> int:
+    return 32 * 8 * 8 * bt
 
 
-def grow_model_bytes(V: int, Q: int) -> int:
-    """Algorithmic bytes of one eager grow: read field (4 B) and particle values
-    (4 B) once, write admissibility bits, write both output masks."""
-    return 4 * V + 4 * Q + V // 8 + Q // 8 + V // 8 + Q
+def phase_bytes(V: int, Q: int, P: int, T: int, bt: int, st: dict, admit_all: bool) -> dict:
+    """Algorithmic bytes per launch of each phase's main kernel (the minimum
+    it must move): field admissibility reads 4 B per tested voxel-step and
+    writes its admissibility and label bits; the read-out writes the canonical
+    field bits and one byte per particle-step and reads the labels of active
+    tiles and particles."""
+    tv = tile_voxels(bt)
+    tested = V if admit_all else st["tiles_tested"] * tv
+    return {
+        "k_admit_field" if admit_all else "k_admit_tiles": int(tested * 4 + tested // 4),
+        "read_out": int(V // 8 + Q + st["active_tiles"] * tv // 8 + Q // 8),
+    }
+
+
+class Timer:
+    """HIP events on torch's current stream, which the library also uses."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.a = torch.cuda.Event(enable_timing=True)
+        self.b = torch.cuda.Event(enable_timing=True)
+
+    def start(self):
+        self.a.record()
+
+    def stop(self) -> float:
+        self.b.record()
+        self.b.synchronize()
+        return self.a.elapsed_time(self.b)
+
+
+def run_steps(g, fmask, pmask, steps: int, warmup: int, torch):
+    """Warm up, then time `steps` steps; per step: grow, field read, particle read."""
+    def step():
+        st = g.grow()
+        g.read_field_mask(fmask)
+        if pmask is not None:
+            g.read_particle_mask(pmask)
+        return st
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    rd = Timer(torch)
+    stats, reads = [], []
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    w0 = time.perf_counter()
+    for _ in range(steps):
+        st = g.grow()
+        rd.start()
+        g.read_field_mask(fmask)
+        if pmask is not None:
+            g.read_particle_mask(pmask)
+        reads.append(rd.stop())
+        stats.append(st)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - w0) * 1e3 / steps
+    ms = max(ev0.elapsed_time(ev1) / steps, wall)
+    last = g.stats()
+    mean = lambda k: float(np.mean([s[k] for s in stats]))
+    return dict(ms=ms, ms_admit_field=mean("ms_admit_field"), ms_admit=mean("ms_admit"),
+                ms_rounds=mean("ms_rounds"), ms_grow=mean("ms_total"),
+                ms_read=float(np.mean(reads)), stats=last)
+
+
+def bench_batched(args, torch, log):
+    """256 queries on the 128^3 x 32 workload: one batched grow (tile shape from
+    the autotuner) versus one single-query grow per query."""
+    from paper_1903_12294_amd import Grower, autotune, synth
+    dev = torch.device("cuda:0")
+    inst = synth.make_config(2)
+    crit, qseeds = synth.make_queries(inst, Q=256, seed=4)
+    X, Y, Z = inst["dims"]
+    T, P = inst["T"], inst["P"]
+    V = X * Y * Z * T
+    tune = autotune.tune_batched(inst, crit, qseeds, repeats=1, use_cache=False)
+    shape = tuple(tune["best"]["tile"])
+    log(f"[bench] batched tile {shape} from {len(tune['table'])} candidates")
+    g = Grower(device=0)
+    try:
+        g.load_field(torch.from_numpy(inst["field"]).to(dev))
+        g.load_particles(torch.from_numpy(inst["xyz"]).to(dev), torch.from_numpy(inst["attr"]).to(dev))
+        g.set_queries(crit, qseeds)
+        g.set_batched_tile(*shape)
+        fp = torch.empty((V, 8), dtype=torch.int32, device=dev)
+        pp = torch.empty((T, P, 8), dtype=torch.int32, device=dev)
+        g.grow_batched(fp, pp)
+        tm = Timer(torch)
+        times = []
+        for _ in range(args.batched_reps):
+            tm.start()
+            _, _, bst = g.grow_batched(fp, pp)
+            times.append(tm.stop())
+        ms_b = float(np.median(times))
+        # plain: one grow + read per query
+        fm = torch.empty((V + 31) // 32, dtype=torch.int32, device=dev)
+        pm = torch.empty((T, P), dtype=torch.uint8, device=dev)
+        per_q = [qseeds[qseeds[:, 4] == q][:, :4] for q in range(len(crit))]
+
+        def plain(q):
+            g.set_criteria(*crit[q])
+            g.set_seeds(per_q[q])
+            g.grow()
+            g.read_field_mask(fm)
+            g.read_particle_mask(pm)
+
+        for q in range(3):
+            plain(q)
+        tm.start()
+        for q in range(len(crit)):
+            plain(q)
+        ms_p = tm.stop()
+        bit = torch.arange(32, dtype=torch.int32, device=dev)
+        ok = True
+        for q in range(0, len(crit), len(crit) // 8):
+            plain(q)
+            plane_f = ((fp[:, q >> 5] >> (q & 31)) & 1).bool()
+            plain_f = ((fm.view(-1, 1) >> bit) & 1).bool().flatten()[:V]
+            plane_p = ((pp[..., q >> 5] >> (q & 31)) & 1).bool()
+            ok = ok and bool(torch.equal(plane_f, plain_f)) and bool(torch.equal(plane_p, pm.bool()))
+    finally:
+        g.close()
+    return {"workload": "128^3x32 field, 262144 particles x 32 steps, 256 queries "
+                        "(1-16 seeds each, thresholds U[0.15, 0.6])",
+            "tile": list(shape), "ms_batched": round(ms_b, 3), "ms_plain_256": round(ms_p, 3),
+            "speedup": round(ms_p / ms_b, 2),
+            "value": round(256 * V / (ms_b * 1e-3), 1), "unit": "query-voxel-steps/s",
+            "rounds": bst["rounds"], "sampled_planes_equal": ok,
+            "autotune": tune["table"]}
 
 
 def main():
@@ -45,19 +183,20 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3])
-    ap.add_argument("--tile-t", type=int, default=None)
+    ap.add_argument("--no-tune", action="store_true", help="default configuration, no autotuning")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip eager / learned / batched")
+    ap.add_argument("--batched-reps", type=int, default=3)
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              f"(the grower runs on a single MI355X; see DESIGN.md for how it would shard)",
-              file=sys.stderr)
+              f"(the grower runs on a single MI355X)", file=sys.stderr)
         sys.exit(2)
 
     import torch
 
-    from paper_1903_12294_amd import Grower, synth
+    from paper_1903_12294_amd import Grower, autotune, synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
@@ -69,58 +208,92 @@ def main():
     T, P = inst["T"], inst["P"]
     V, Q = X * Y * Z * T, P * T
 
-    g = Grower(device=0, tile_t=args.tile_t)
+    choice = dict(tile_t=8, schedule="persistent", admit="tiles")
+    tune = None
+    if not args.no_tune:
+        t0 = time.time()
+        tune = autotune.tune_plain(inst, repeats=3, use_cache=False)
+        choice = {k: tune["best"][k] for k in ("tile_t", "schedule", "admit")}
+        log(f"[bench] autotuned {choice} over {len(tune['table'])} candidates "
+            f"(identical masks) in {time.time() - t0:.1f}s")
+
+    g = Grower(device=0, tile_t=choice["tile_t"])
     t0 = time.time()
-    f_d = torch.from_numpy(inst["field"]).to(dev)
-    g.load_field(f_d)
-    del f_d
-    xyz_d = torch.from_numpy(inst["xyz"]).to(dev)
-    at_d = torch.from_numpy(inst["attr"]).to(dev)
-    g.load_particles(xyz_d, at_d)
-    del xyz_d, at_d
+    g.load_field(torch.from_numpy(inst["field"]).to(dev))
+    g.load_particles(torch.from_numpy(inst["xyz"]).to(dev), torch.from_numpy(inst["attr"]).to(dev))
     g.set_criteria(*inst["crit"])
     g.set_seeds(inst["seeds"])
+    g.set_schedule(choice["schedule"])
+    g.set_admit_mode(choice["admit"])
     torch.cuda.synchronize()
     log(f"[bench] loaded and binned in {time.time() - t0:.1f}s")
 
     fmask = torch.empty((V + 31) // 32, dtype=torch.int32, device=dev)
     pmask = torch.empty((T, P), dtype=torch.uint8, device=dev)
+    r = run_steps(g, fmask, pmask, args.steps, args.warmup, torch)
+    st = r["stats"]
+    ms = r["ms"]
+    log(f"[bench] {args.steps} steps, {ms:.3f} ms/step, rounds {st['rounds']}, "
+        f"tile visits {st['tile_visits']}, members {st['members_field']} / {st['members_particle']}")
 
-    def step():
-        st = g.grow()
-        g.read_field_mask(fmask)
-        g.read_particle_mask(pmask)
-        return st
+    admit_all = choice["admit"] == "all"
+    pb = phase_bytes(V, Q, P, T, choice["tile_t"], st, admit_all)
+    phases = {"admit_field": r["ms_admit_field"], "admit_particles": r["ms_admit"] - r["ms_admit_field"],
+              "rounds": r["ms_rounds"], "read_out": r["ms_read"]}
+    # roofline of the largest HBM-bound kernel with a live per-launch time
+    kname = "k_admit_field" if admit_all else "k_admit_tiles"
+    cands = {kname: (pb[kname], r["ms_admit_field"]), "read_out": (pb["read_out"], r["ms_read"])}
+    dom = max(cands, key=lambda k: cands[k][1])
+    b, t_ms = cands[dom]
+    achieved = b / (t_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": b, "ms_per_launch": round(t_ms, 4)}
 
-    for i in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    stats = []
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record()
-    w0 = time.perf_counter()
-    for i in range(args.steps):
-        stats.append(step())
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ms = ev0.elapsed_time(ev1) / args.steps
-    ms = max(ms, wall * 1e3 / args.steps)
-    last = g.stats()
-    log(f"[bench] {args.steps} steps, {ms:.3f} ms/step, rounds {last['rounds']}, "
-        f"tile visits {last['tile_visits']}, members {last['members_field']} / "
-        f"{last['members_particle']}")
+    ref_f = fmask.clone()
+    ref_p = pmask.clone()
+    forms = {}
+    if not args.no_forms:
+        # eager: every sample tested each step
+        g.set_admit_mode("all")
+        re_ = run_steps(g, fmask, pmask, args.steps, 2, torch)
+        eb = phase_bytes(V, Q, P, T, choice["tile_t"], re_["stats"], True)["k_admit_field"]
+        ea = eb / (re_["ms_admit_field"] * 1e-3) / 1e9
+        forms["eager"] = {"ms_per_step": round(re_["ms"], 4), "value": round(V / (re_["ms"] * 1e-3), 1),
+                          "masks_equal": bool(torch.equal(fmask, ref_f) and torch.equal(pmask, ref_p)),
+                          "k_admit_field": {"bytes_per_launch": eb, "ms_per_launch": round(re_["ms_admit_field"], 4),
+                                            "achieved_GBps": round(ea, 1), "frac": round(ea / HBM_PEAK_GBS, 4)}}
+        g.set_admit_mode("tiles")
+        # learned scheduling: trained and untrained predictor, tiles mode
+        from paper_1903_12294_amd.learned import Net, init_params, set_predictor
+        base = run_steps(g, fmask, pmask, args.steps, 2, torch)
+        lf = {"baseline_tiles_ms": round(base["ms"], 4), "baseline_tiles_tested": base["stats"]["tiles_tested"]}
+        net = Net(0)
+        try:
+            variants = [("untrained", init_params(0), 0.0)]
+            if os.path.exists(PREDICTOR):
+                meta = json.load(open(os.path.splitext(PREDICTOR)[0] + ".json"))
+                variants.insert(0, ("trained", np.load(PREDICTOR), float(meta["logit_threshold"])))
+            for name, params, thr in variants:
+                net.set_params(params)
+                set_predictor(g, net, thr)
+                rl = run_steps(g, fmask, pmask, args.steps, 2, torch)
+                lf[name] = {"ms_per_step": round(rl["ms"], 4), "speedup_vs_plain": round(base["ms"] / rl["ms"], 3),
+                            "tiles_tested": rl["stats"]["tiles_tested"],
+                            "tiles_deferred_read": rl["stats"]["tiles_deferred_read"],
+                            "rounds": rl["stats"]["rounds"], "logit_threshold": thr,
+                            "masks_equal": bool(torch.equal(fmask, ref_f) and torch.equal(pmask, ref_p))}
+                set_predictor(g, None)
+        finally:
+            net.close()
+        forms["learned"] = lf
+        g.set_admit_mode(choice["admit"])
+    g.close()
+    del g
+    torch.cuda.empty_cache()
 
-    ms_field = float(np.mean([s["ms_admit_field"] for s in stats]))
-    fbytes = field_kernel_bytes(V)
-    achieved = fbytes / (ms_field * 1e-3) / 1e9
-    traffic = None
-    roofline = {"bound": "hbm", "kernel": "k_admit_field", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "bytes_per_launch": fbytes,
-                "ms_per_launch": round(ms_field, 4)}
+    if not args.no_forms:
+        forms["batched"] = bench_batched(args, torch, log)
 
     cpu = None
     parity = None
@@ -131,15 +304,13 @@ def main():
                                     inst["seeds"])
         tc = time.perf_counter() - t0
         cpu = {"value": round(V / tc, 1), "unit": "voxel-steps/s", "cores": 1, "kind": "oracle",
-               "sample": f"full {cfg['name']} workload, single-thread C breadth-first oracle "
+               "sample": f"the full {cfg['name']} workload once, single-thread C breadth-first oracle "
                          f"({tc:.1f}s incl. binning and index build)",
                "host_cores_available": os.cpu_count()}
-        gm = fmask.cpu().numpy().view(np.uint32)
-        pm = pmask.cpu().numpy()
-        parity = bool(np.array_equal(gm, ofm) and np.array_equal(pm, opm))
+        parity = bool(np.array_equal(ref_f.cpu().numpy().view(np.uint32), ofm)
+                      and np.array_equal(ref_p.cpu().numpy(), opm))
         log(f"[bench] oracle {tc:.1f}s, parity {parity}")
 
-    mb = grow_model_bytes(V, Q)
     out = {
         "metric": "voxel-timesteps segmented/s to fixed point",
         "value": round(V / (ms * 1e-3), 1),
@@ -157,23 +328,23 @@ def main():
                                f"steps, {len(inst['seeds'])} seeds, thresholds "
                                f"{float(inst['crit'][0])}/{float(inst['crit'][2])}",
                    "voxel_steps": V, "particle_steps": Q,
-                   "tile": f"32x8x8x{args.tile_t or 8}"},
+                   "tile": f"32x8x8x{choice['tile_t']}", "schedule": choice["schedule"],
+                   "admissibility": choice["admit"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "detail": {
-            "rounds": last["rounds"], "tile_visits": last["tile_visits"],
-            "particle_visits": last["particle_visits"], "active_tiles": last["active_tiles"],
-            "members_field": last["members_field"], "members_particle": last["members_particle"],
-            "ms_admit": round(float(np.mean([s["ms_admit"] for s in stats])), 4),
-            "ms_rounds": round(float(np.mean([s["ms_rounds"] for s in stats])), 4),
-            "ms_grow": round(float(np.mean([s["ms_total"] for s in stats])), 4),
-            "model_bytes_per_step": mb,
-            "model_GBps": round(mb / (ms * 1e-3) / 1e9, 1),
+            "rounds": st["rounds"], "tile_visits": st["tile_visits"],
+            "particle_visits": st["particle_visits"], "active_tiles": st["active_tiles"],
+            "tiles_tested": st["tiles_tested"],
+            "members_field": st["members_field"], "members_particle": st["members_particle"],
+            "phases_ms": {k: round(v, 4) for k, v in phases.items()},
+            "ms_grow": round(r["ms_grow"], 4),
             "parity_vs_oracle": parity,
+            "autotune": tune["table"] if tune else None,
         },
+        "forms": forms,
     }
     print(json.dumps(out), flush=True)
-    g.close()
 
 
 if __name__ == "__main__":

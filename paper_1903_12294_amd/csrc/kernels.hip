@@ -764,10 +764,14 @@ __global__ void k_count_active(Dev d) {
     if (lane_id() == 0 && c) atomicAdd(&d.stat64[S_ACTIVE_TILES], (unsigned long long)c);
 }
 
-// Admissibility of every particle-step, and the labels cleared.  Lanes load 4
-// consecutive steps (16 bytes, non-temporal); the lanes covering one label
-// word (up to 64 steps) OR their nibbles together.  Requires Tpad >= 4.
+// Admissibility of every particle-step, the labels cleared, and the coupled
+// list: every admissible particle-step that lies in a voxel, as (flat index,
+// voxel bit).  Lanes load 4 consecutive steps (16 bytes, non-temporal); the
+// lanes covering one label word (up to 64 steps) OR their nibbles together; a
+// lane with an admissible step loads the 4 matching bins (16 bytes) and the
+// block appends its entries with one atomic.  Requires Tpad >= 4.
 __global__ __launch_bounds__(256) void k_admit_particles(Dev d) {
+    __shared__ uint32_t s_tmp[8];
     const PGeom& pg = d.pg;
     const float lo = d.crit[2], hi = d.crit[3];
     const uint64_t n4 = ((uint64_t)pg.P * pg.Tpad) >> 2;
@@ -775,13 +779,14 @@ __global__ __launch_bounds__(256) void k_admit_particles(Dev d) {
     const int lane = lane_id();
     const int sub = lane & (lanes_per_word - 1);
     const v4f* src = reinterpret_cast<const v4f*>(d.attr_t);
+    const uint4* bsrc = reinterpret_cast<const uint4*>(d.bins);
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t base0 = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~63u);
-    for (uint64_t base = base0; base < n4; base += 4 * stride) {
+    // block-uniform loop: every thread of the block reaches block_append256
+    for (uint64_t bb = blockIdx.x * (uint64_t)blockDim.x; bb < n4; bb += 4 * stride) {
         v4f v[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const uint64_t i = base + k * stride + lane;
+            const uint64_t i = bb + k * stride + threadIdx.x;
             const float nan = __builtin_nanf("");
             v[k] = (v4f){nan, nan, nan, nan};
             if (i < n4) {
@@ -791,9 +796,12 @@ __global__ __launch_bounds__(256) void k_admit_particles(Dev d) {
                 if (r.y >= lo && r.x <= hi) v[k] = __builtin_nontemporal_load(src + i);
             }
         }
+        uint32_t nibs[4];
+        uint4 bn[4];
+        uint32_t cnt = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const uint64_t i = base + k * stride + lane;
+            const uint64_t i = bb + k * stride + threadIdx.x;
             const uint32_t nib = (uint32_t)in_band(v[k].x, lo, hi) |
                                  ((uint32_t)in_band(v[k].y, lo, hi) << 1) |
                                  ((uint32_t)in_band(v[k].z, lo, hi) << 2) |
@@ -806,6 +814,25 @@ __global__ __launch_bounds__(256) void k_admit_particles(Dev d) {
                 d.Ap[wi] = x;
                 d.Lp[wi] = 0ull;
             }
+            bn[k] = make_uint4(kNoVoxel, kNoVoxel, kNoVoxel, kNoVoxel);
+            if (nib) bn[k] = bsrc[i];  // nib != 0 implies i < n4
+            uint32_t m = nib;
+            if (bn[k].x == kNoVoxel) m &= ~1u;
+            if (bn[k].y == kNoVoxel) m &= ~2u;
+            if (bn[k].z == kNoVoxel) m &= ~4u;
+            if (bn[k].w == kNoVoxel) m &= ~8u;
+            nibs[k] = m;
+            cnt += __popc(m);
+        }
+        uint32_t out = block_append256(cnt, &d.counters[C_NLIST], s_tmp);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (!nibs[k]) continue;
+            const uint32_t f0 = (uint32_t)((bb + k * stride + threadIdx.x) << 2);
+            if (nibs[k] & 1u) d.clist[out++] = make_uint2(f0, bn[k].x);
+            if (nibs[k] & 2u) d.clist[out++] = make_uint2(f0 + 1, bn[k].y);
+            if (nibs[k] & 4u) d.clist[out++] = make_uint2(f0 + 2, bn[k].z);
+            if (nibs[k] & 8u) d.clist[out++] = make_uint2(f0 + 3, bn[k].w);
         }
     }
 }
@@ -823,8 +850,9 @@ __global__ void k_admit_particles_short(Dev d) {
     }
 }
 
-// Coupled list: every admissible particle-step that lies in a voxel, as
-// (flat index, voxel bit); one thread per label word, one atomic per block.
+// Coupled list for short rows (Tpad < 4): every admissible particle-step that
+// lies in a voxel, as (flat index, voxel bit); one thread per label word, one
+// atomic per block.
 __global__ __launch_bounds__(256) void k_couple(Dev d) {
     __shared__ uint32_t s_tmp[8];
     const PGeom& pg = d.pg;
@@ -1131,9 +1159,9 @@ void launch_admit_particles(const Dev& d, hipStream_t s) {
     } else {
         hipLaunchKernelGGL(k_admit_particles_short, dim3(grid_for(pg.P, 256, 4096)), dim3(256), 0, s,
                            d);
+        hipLaunchKernelGGL(k_couple, dim3(grid_for((uint64_t)pg.P * pg.W, 256, 8192)), dim3(256), 0,
+                           s, d);
     }
-    hipLaunchKernelGGL(k_couple, dim3(grid_for((uint64_t)pg.P * pg.W, 256, 8192)), dim3(256), 0, s,
-                       d);
 }
 
 void launch_seeds(const Dev& d, const int32_t* seeds, int64_t S, hipStream_t s) {

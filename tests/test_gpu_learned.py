@@ -144,3 +144,54 @@ def test_labels_are_members_per_brick():
     T, Z, Y, X = Mf.shape
     exp = Mf.reshape(T, Z // 8, 8, Y // 8, 8, X // 8, 8).any(axis=(2, 4, 6))
     assert np.array_equal(y.astype(bool), exp)
+
+
+def test_trained_predictor_reads_fewer_tiles_and_stays_exact():
+    """What the trained network gains over the grower without it, on a
+    held-out variant (data seed 2000, not among the training seeds): fewer
+    field tiles read (up front plus deferred), identical masks."""
+    import json
+    import os
+    from paper_1903_12294_amd import Grower
+    from paper_1903_12294_amd.learned import Net, init_params, set_predictor
+    _need_gpu()
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    path = os.path.join(root, "paper_1903_12294_amd", "predictor.npy")
+    if not os.path.exists(path):
+        pytest.skip("no trained predictor weights in the tree")
+    meta = json.load(open(os.path.splitext(path)[0] + ".json"))
+    c = synth.CONFIGS[2]
+    inst = synth.make_instance(c["X"], c["Y"], c["Z"], c["T"], c["P"], n_blobs=c["n_blobs"],
+                               seed=2000, n_seeds=c["n_seeds"], tau_f=c["tau"], tau_p=c["tau"],
+                               crossing=c["crossing"])
+    ofm, opm, _ = oracle_grow(inst["field"], inst["xyz"], inst["attr"], inst["crit"], inst["seeds"])
+    net = Net(0)
+    g = Grower(device=0)
+    try:
+        g.load_field(inst["field"])
+        g.load_particles(inst["xyz"], inst["attr"])
+        g.set_criteria(*inst["crit"])
+        g.set_seeds(inst["seeds"])
+        g.set_admit_mode("tiles")
+        base = g.grow()
+        assert np.array_equal(g.read_field_mask(), ofm)
+        res = {}
+        for name, params, thr in [("trained", np.load(path), float(meta["logit_threshold"])),
+                                  ("untrained", init_params(0), 0.0)]:
+            net.set_params(params)
+            set_predictor(g, net, thr)
+            st = g.grow()
+            assert np.array_equal(g.read_field_mask(), ofm), name
+            assert np.array_equal(g.read_particle_mask(), opm), name
+            res[name] = st
+        set_predictor(g, None)
+    finally:
+        g.close()
+        net.close()
+    tr = res["trained"]
+    reads = tr["tiles_tested"] + tr["tiles_deferred_read"]
+    print(f"tiles read: without predictor {base['tiles_tested']}, trained {tr['tiles_tested']} up front "
+          f"+ {tr['tiles_deferred_read']} deferred, untrained {res['untrained']['tiles_tested']} + "
+          f"{res['untrained']['tiles_deferred_read']}")
+    assert tr["tiles_tested"] < base["tiles_tested"]
+    assert reads < base["tiles_tested"]
