@@ -972,7 +972,8 @@ __global__ __launch_bounds__(256) void k_rounds(Dev d, uint32_t round0, uint32_t
 // stages up to 8 x-consecutive tiles in LDS (rows padded by one word against
 // bank conflicts) and writes whole canonical rows.  Otherwise bit by bit.
 template <int BT>
-__global__ __launch_bounds__(256) void k_read_field_tiles(Dev d, uint32_t* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_read_field_tiles(Dev d, uint32_t* __restrict__ out, int vec) {
+    typedef unsigned int v4u __attribute__((ext_vector_type(4)));
     constexpr int WPT = 64 * BT;
     __shared__ uint32_t sl[8 * (WPT + 1)];
     const Geom& g = d.g;
@@ -981,20 +982,44 @@ __global__ __launch_bounds__(256) void k_read_field_tiles(Dev d, uint32_t* __res
     for (int tx0 = 0; tx0 < g.NXt; tx0 += 8) {
         const int ntx = min(8, g.NXt - tx0);
         const uint32_t tile0 = tile_of(g, tx0, ty, tz, tt);
-        const uint32_t* src = d.Lf + (size_t)tile0 * WPT;
-        for (int i = threadIdx.x; i < ntx * WPT; i += 256) {
-            const int txl = i / WPT, w = i - txl * WPT;
-            sl[txl * (WPT + 1) + w] = d.active[tile0 + txl] ? src[i] : 0u;
+        uint32_t act = 0;  // one bit per tile of this x-run; the same in every thread
+        for (int k = 0; k < ntx; ++k) act |= (d.active[tile0 + k] != 0 ? 1u : 0u) << k;
+        if (act) {
+            const uint32_t* src = d.Lf + (size_t)tile0 * WPT;
+            for (int i = threadIdx.x; i < ntx * WPT; i += 256) {
+                const int txl = i / WPT, w = i - txl * WPT;
+                sl[txl * (WPT + 1) + w] = (act >> txl) & 1u ? src[i] : 0u;
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        for (int i = threadIdx.x; i < ntx * WPT; i += 256) {
-            const int txl = i % ntx, w = i / ntx;
-            const int yl = w & 7, zl = (w >> 3) & 7, tl = w >> 6;
-            const int y = ty * 8 + yl, z = tz * 8 + zl, t = tt * BT + tl;
-            if (y < g.Y && z < g.Z && t < g.T) {
-                const uint32_t v = sl[txl * (WPT + 1) + w];
-                out[((size_t)(t * g.Z + z) * g.Y + y) * g.NXt + tx0 + txl] = v;
-                cnt += __popc(v);
+        if (vec) {
+            // a thread writes 4 x-consecutive words of one canonical row
+            const int nq = ntx >> 2;
+            for (int i = threadIdx.x; i < nq * WPT; i += 256) {
+                const int qx = i % nq, w = i / nq;
+                const int yl = w & 7, zl = (w >> 3) & 7, tl = w >> 6;
+                const int y = ty * 8 + yl, z = tz * 8 + zl, t = tt * BT + tl;
+                if (y < g.Y && z < g.Z && t < g.T) {
+                    v4u v = {0u, 0u, 0u, 0u};
+                    if (act) {
+                        const uint32_t* r = sl + (4 * qx) * (WPT + 1) + w;
+                        v = (v4u){r[0], r[WPT + 1], r[2 * (WPT + 1)], r[3 * (WPT + 1)]};
+                        cnt += __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
+                    }
+                    __builtin_nontemporal_store(
+                        v, reinterpret_cast<v4u*>(out + ((size_t)(t * g.Z + z) * g.Y + y) * g.NXt + tx0 + 4 * qx));
+                }
+            }
+        } else {
+            for (int i = threadIdx.x; i < ntx * WPT; i += 256) {
+                const int txl = i % ntx, w = i / ntx;
+                const int yl = w & 7, zl = (w >> 3) & 7, tl = w >> 6;
+                const int y = ty * 8 + yl, z = tz * 8 + zl, t = tt * BT + tl;
+                if (y < g.Y && z < g.Z && t < g.T) {
+                    const uint32_t v = act ? sl[txl * (WPT + 1) + w] : 0u;
+                    out[((size_t)(t * g.Z + z) * g.Y + y) * g.NXt + tx0 + txl] = v;
+                    cnt += __popc(v);
+                }
             }
         }
         __syncthreads();
@@ -1051,7 +1076,9 @@ __global__ __launch_bounds__(256) void k_read_particles16(Dev d, uint8_t* __rest
                 v[j] = (uint32_t)((lw[4 * j] >> t) & 1) | ((uint32_t)((lw[4 * j + 1] >> t) & 1) << 8) |
                        ((uint32_t)((lw[4 * j + 2] >> t) & 1) << 16) |
                        ((uint32_t)((lw[4 * j + 3] >> t) & 1) << 24);
-            *reinterpret_cast<uint4*>(out + (int64_t)t * pg.P + p0) = make_uint4(v[0], v[1], v[2], v[3]);
+            typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+            __builtin_nontemporal_store((v4u){v[0], v[1], v[2], v[3]},
+                                        reinterpret_cast<v4u*>(out + (int64_t)t * pg.P + p0));
         }
     }
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
@@ -1196,10 +1223,12 @@ void launch_read_field(const Dev& d, uint32_t* out, hipStream_t s) {
     const Geom& g = d.g;
     if ((g.X & 31) == 0) {
         const dim3 grid(g.NYt, g.NZt, g.NTt);
+        // 16-byte stores when every x-run of tiles is a multiple of 4 words
+        const int vec = (g.NXt & 3) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0;
         switch (g.BT) {
-            case 4: hipLaunchKernelGGL(k_read_field_tiles<4>, grid, dim3(256), 0, s, d, out); break;
-            case 8: hipLaunchKernelGGL(k_read_field_tiles<8>, grid, dim3(256), 0, s, d, out); break;
-            default: hipLaunchKernelGGL(k_read_field_tiles<16>, grid, dim3(256), 0, s, d, out); break;
+            case 4: hipLaunchKernelGGL(k_read_field_tiles<4>, grid, dim3(256), 0, s, d, out, vec); break;
+            case 8: hipLaunchKernelGGL(k_read_field_tiles<8>, grid, dim3(256), 0, s, d, out, vec); break;
+            default: hipLaunchKernelGGL(k_read_field_tiles<16>, grid, dim3(256), 0, s, d, out, vec); break;
         }
         return;
     }
