@@ -120,6 +120,46 @@ __device__ __forceinline__ uint32_t row_admissibility(const Dev& d, int tx, int 
     return w;
 }
 
+// Admissibility words of one t-slice of a tile (64 rows of 32 x), computed by
+// the whole wave: eight lanes read one 128-byte row with 16-byte loads, so an
+// instruction covers 8 whole rows; the eight nibble-words of a row are ORed
+// and handed to the lane that owns the row.  Returns the word of row `lane`
+// ((z_l, y_l) = (lane >> 3, lane & 7)).  Call with the whole wave.
+__device__ __forceinline__ uint32_t slice_admissibility(const Dev& d, int tx, int ty, int tz, int t) {
+    const Geom& g = d.g;
+    const int lane = lane_id();
+    if ((g.X & 3) != 0) return row_admissibility(d, tx, ty * 8 + (lane & 7), tz * 8 + (lane >> 3), t);
+    if (t >= g.T) return 0u;
+    typedef float v4f_ __attribute__((ext_vector_type(4)));
+    const float lo = d.crit[0], hi = d.crit[1];
+    const int quad = lane & 7, grp = lane >> 3;
+    const int x = tx * 32 + quad * 4;
+    v4f_ v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        // row i*8 + grp holds (z_l, y_l) = (i, grp)
+        const int y = ty * 8 + grp, z = tz * 8 + i;
+        const float nan = __builtin_nanf("");
+        v[i] = (v4f_){nan, nan, nan, nan};
+        if (x < g.X && y < g.Y && z < g.Z)
+            v[i] = __builtin_nontemporal_load(
+                reinterpret_cast<const v4f_*>(d.field + ((size_t)(t * g.Z + z) * g.Y + y) * g.X + x));
+    }
+    uint32_t mine = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        uint32_t w = ((uint32_t)in_band(v[i].x, lo, hi) | ((uint32_t)in_band(v[i].y, lo, hi) << 1) |
+                      ((uint32_t)in_band(v[i].z, lo, hi) << 2) | ((uint32_t)in_band(v[i].w, lo, hi) << 3))
+                     << (4 * quad);
+        w |= __shfl_xor(w, 1);
+        w |= __shfl_xor(w, 2);
+        w |= __shfl_xor(w, 4);
+        const uint32_t got = __shfl(w, (lane & 7) * 8);  // row i*8 + (lane & 7)
+        if ((lane >> 3) == i) mine = got;
+    }
+    return mine;
+}
+
 __device__ __forceinline__ uint32_t load_relaxed(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -226,7 +266,7 @@ __device__ void sweep_tile(const Dev& d, uint32_t tile, int par) {
         uint32_t any = 0;
 #pragma unroll
         for (int t = 0; t < BT; ++t) {
-            a[t] = row_admissibility(d, tx, ty * 8 + yl, tz * 8 + zl, (tt << g.logBT) + t);
+            a[t] = slice_admissibility(d, tx, ty, tz, (tt << g.logBT) + t);
             Ab[t * 64 + lane] = a[t];
             any |= a[t];
         }
@@ -735,12 +775,11 @@ __global__ __launch_bounds__(256) void k_admit_tiles(Dev d) {
         int tx, ty, tz, tt;
         tile_coords(g, tile, tx, ty, tz, tt);
         const bool defer = d.tpred && !d.tpred[tile];
-        const int y = ty * 8 + (lane & 7), z = tz * 8 + (lane >> 3);
         uint32_t any = 0;
         for (int tl = wave; tl < g.BT; tl += 4) {
             const size_t wi = (size_t)tile * g.WPT + tl * 64 + lane;
             if (!defer) {
-                const uint32_t w = row_admissibility(d, tx, y, z, (tt << g.logBT) + tl);
+                const uint32_t w = slice_admissibility(d, tx, ty, tz, (tt << g.logBT) + tl);
                 d.Af[wi] = w;
                 any |= w;
             }
