@@ -807,10 +807,24 @@ __global__ void k_count_active(Dev d) {
 // list: every admissible particle-step that lies in a voxel, as (flat index,
 // voxel bit).  Lanes load 4 consecutive steps (16 bytes, non-temporal); the
 // lanes covering one label word (up to 64 steps) OR their nibbles together; a
-// lane with an admissible step loads the 4 matching bins (16 bytes) and the
-// block appends its entries with one atomic.  Requires Tpad >= 4.
+// lane with an admissible step loads the 4 matching bins (16 bytes).  Entries
+// are staged in LDS and flushed to the global list with one atomic per flush
+// (one per block at config 3): appends to a single counter from every block
+// serialise, so their number, not the bytes, sets this kernel's time.
+// Requires Tpad >= 4.
+constexpr uint32_t kStage = 4096;  // >= the most entries one block iteration makes (256 x 4 x 4)
+__device__ __forceinline__ void flush_stage(const Dev& d, const uint2* s_buf, uint32_t n, uint32_t* s_tmp) {
+    if (threadIdx.x == 0) s_tmp[4] = atomicAdd(&d.counters[C_NLIST], n);
+    __syncthreads();
+    const uint32_t base = s_tmp[4];
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) d.clist[base + i] = s_buf[i];
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(256) void k_admit_particles(Dev d) {
     __shared__ uint32_t s_tmp[8];
+    __shared__ uint2 s_buf[kStage];
+    uint32_t nbuf = 0;  // entries staged; the same in every thread
     const PGeom& pg = d.pg;
     const float lo = d.crit[2], hi = d.crit[3];
     const uint64_t n4 = ((uint64_t)pg.P * pg.Tpad) >> 2;
@@ -863,17 +877,26 @@ __global__ __launch_bounds__(256) void k_admit_particles(Dev d) {
             nibs[k] = m;
             cnt += __popc(m);
         }
-        uint32_t out = block_append256(cnt, &d.counters[C_NLIST], s_tmp);
+        uint32_t total;
+        const uint32_t ex = block_exclusive_scan256(cnt, s_tmp, total);
+        if (nbuf + total > kStage) {  // block-uniform
+            flush_stage(d, s_buf, nbuf, s_tmp);
+            nbuf = 0;
+        }
+        uint32_t out = nbuf + ex;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             if (!nibs[k]) continue;
             const uint32_t f0 = (uint32_t)((bb + k * stride + threadIdx.x) << 2);
-            if (nibs[k] & 1u) d.clist[out++] = make_uint2(f0, bn[k].x);
-            if (nibs[k] & 2u) d.clist[out++] = make_uint2(f0 + 1, bn[k].y);
-            if (nibs[k] & 4u) d.clist[out++] = make_uint2(f0 + 2, bn[k].z);
-            if (nibs[k] & 8u) d.clist[out++] = make_uint2(f0 + 3, bn[k].w);
+            if (nibs[k] & 1u) s_buf[out++] = make_uint2(f0, bn[k].x);
+            if (nibs[k] & 2u) s_buf[out++] = make_uint2(f0 + 1, bn[k].y);
+            if (nibs[k] & 4u) s_buf[out++] = make_uint2(f0 + 2, bn[k].z);
+            if (nibs[k] & 8u) s_buf[out++] = make_uint2(f0 + 3, bn[k].w);
         }
+        nbuf += total;
     }
+    __syncthreads();
+    if (nbuf) flush_stage(d, s_buf, nbuf, s_tmp);
 }
 
 // Same for Tpad < 4 (T <= 2): one thread per particle.
@@ -935,12 +958,10 @@ __global__ __launch_bounds__(256) void k_round_sweep(Dev d, int par) {
     const uint32_t nwork = d.counters[C_NWORK0 + par];
     const uint32_t wave0 = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    uint32_t visits = 0;
-    for (uint32_t w = wave0; w < nwork; w += nwaves) {
-        sweep_tile<BT>(d, d.work[par * d.g.NT + w], par);
-        ++visits;
-    }
-    if (lane_id() == 0 && visits) atomicAdd(&d.stat64[S_TILE_VISITS], (unsigned long long)visits);
+    for (uint32_t w = wave0; w < nwork; w += nwaves) sweep_tile<BT>(d, d.work[par * d.g.NT + w], par);
+    // every listed tile is swept once: the visit count is the list length
+    if (blockIdx.x == 0 && threadIdx.x == 0 && nwork)
+        atomicAdd(&d.stat64[S_TILE_VISITS], (unsigned long long)nwork);
 }
 
 __global__ __launch_bounds__(256) void k_round_pull(Dev d, int par) {
@@ -977,10 +998,8 @@ __global__ __launch_bounds__(256) void k_rounds(Dev d, uint32_t round0, uint32_t
         if (nwork == 0 || (max_rounds && r - round0 >= max_rounds)) break;
         // sweep
         if (tid == 0) store_relaxed(&d.counters[C_NDIRTYP], 0u);
-        for (uint32_t w = wave0; w < nwork; w += nwaves) {
-            sweep_tile<BT>(d, d.work[par * d.g.NT + w], par);
-            ++visits;
-        }
+        for (uint32_t w = wave0; w < nwork; w += nwaves) sweep_tile<BT>(d, d.work[par * d.g.NT + w], par);
+        visits += nwork;  // the same in every thread; only thread 0 records it
         if (!grid_sync(d, epoch)) break;
         // pull
         if (tid == 0) store_relaxed(&d.counters[C_NWORK0 + par], 0u);
@@ -1000,7 +1019,7 @@ __global__ __launch_bounds__(256) void k_rounds(Dev d, uint32_t round0, uint32_t
         if (!grid_sync(d, epoch)) break;
         ++r;
     }
-    if (lane_id() == 0 && visits) atomicAdd(&d.stat64[S_TILE_VISITS], (unsigned long long)visits);
+    if (tid == 0 && visits) atomicAdd(&d.stat64[S_TILE_VISITS], (unsigned long long)visits);
     if (tid == 0) store_relaxed(&d.counters[C_ROUNDS], r - round0);
 }
 
@@ -1221,7 +1240,7 @@ void launch_admit_particles(const Dev& d, hipStream_t s) {
     if (pg.P == 0) return;
     if (pg.Tpad >= 4) {
         const uint64_t n4 = ((uint64_t)pg.P * pg.Tpad) >> 2;
-        hipLaunchKernelGGL(k_admit_particles, dim3(grid_for(n4 / 4, 256, 16384)), dim3(256), 0, s, d);
+        hipLaunchKernelGGL(k_admit_particles, dim3(grid_for(n4 / 4, 256, 2048)), dim3(256), 0, s, d);
     } else {
         hipLaunchKernelGGL(k_admit_particles_short, dim3(grid_for(pg.P, 256, 4096)), dim3(256), 0, s,
                            d);
