@@ -184,6 +184,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3])
     ap.add_argument("--no-tune", action="store_true", help="default configuration, no autotuning")
+    ap.add_argument("--schedule", choices=["persistent", "launch"], help="fix the schedule (no tuning)")
+    ap.add_argument("--admit", choices=["tiles", "all"], help="fix the admissibility mode (no tuning)")
+    ap.add_argument("--tile-t", type=int, choices=[4, 8, 16], help="fix the tile depth (no tuning)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip eager / learned / batched")
     ap.add_argument("--batched-reps", type=int, default=3)
@@ -209,8 +212,11 @@ def main():
     V, Q = X * Y * Z * T, P * T
 
     choice = dict(tile_t=8, schedule="persistent", admit="tiles")
+    fixed = {k: v for k, v in (("tile_t", args.tile_t), ("schedule", args.schedule),
+                               ("admit", args.admit)) if v is not None}
+    choice.update(fixed)
     tune = None
-    if not args.no_tune:
+    if not args.no_tune and not fixed:
         t0 = time.time()
         tune = autotune.tune_plain(inst, repeats=3, use_cache=False)
         choice = {k: tune["best"][k] for k in ("tile_t", "schedule", "admit")}

@@ -252,7 +252,7 @@ int run_rounds(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
     const uint32_t r0 = c->round;
     if (c->schedule == MF4D_SCHED_PERSISTENT) {
         launch_fill_u32(c->counters + C_ERR, 0, 2, c->stream);  // C_ERR, C_ROUNDS
-        launch_fill_u32(c->bar, 0, 4, c->stream);
+        launch_fill_u32(c->bar, 0, kBarWords, c->stream);
         if (launch_rounds_persistent(d, r0, cap, c->device, c->stream)) {
             int rc = read_counters(c);
             if (rc) return rc;
@@ -346,7 +346,7 @@ int mf4d_create(mf4d_ctx** out, int device, void* hip_stream) {
     c->stream = (hipStream_t)hip_stream;
     int rc = dev_alloc(&c->counters, C_NCOUNTERS);
     if (!rc) rc = dev_alloc(&c->stat64, S_NSTAT);
-    if (!rc) rc = dev_alloc(&c->bar, 64);
+    if (!rc) rc = dev_alloc(&c->bar, kBarWords);
     if (!rc) {
         const char* env = getenv("MF4D_SCHED");
         if (env && strcmp(env, "launch") == 0) c->schedule = MF4D_SCHED_LAUNCH;

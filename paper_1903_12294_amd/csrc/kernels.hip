@@ -13,6 +13,8 @@
 // and "changed" flags are double-buffered by round parity.  The phases run
 // either as three launches per round or inside one cooperative persistent
 // kernel separated by grid barriers.
+#include <algorithm>
+
 #include "mf4d_internal.h"
 
 namespace mf4d {
@@ -468,22 +470,45 @@ __device__ void close_particle(const Dev& d, uint32_t p, int par) {
 }
 
 // ---------------------------------------------------------------------------
-// Grid barrier for the persistent kernel: a monotone arrival counter; every
-// block waits until all blocks have arrived `epoch` times.  The wait is
-// bounded: after ~2^22 polls it records an error and returns false, so no wave
-// can hang; every block then leaves the round loop.
+// Grid barrier for the persistent kernel, in two levels so that no counter
+// takes an atomic from every block (same-address atomics serialise, ~12 ns
+// each here): block b arrives at sub-counter b % kBarSubs; the last arrival of
+// a sub-counter arrives at the top counter; the last top arrival publishes the
+// barrier's epoch in a flag that every block polls.  All counters are
+// monotone (epoch e expects e * n arrivals), so nothing is reset between
+// barriers.  Each lives on its own 128-byte line.  The wait is bounded: after
+// ~2^22 polls it records an error and returns false, so no wave can hang;
+// every block then leaves the round loop.
+constexpr int kBarSubs = 8;
+constexpr int kBarTop = 0, kBarGen = 32, kBarSub0 = 64;  // word offsets in d.bar (kBarWords)
+
 __device__ bool grid_sync(const Dev& d, uint32_t& epoch) {
     __shared__ uint32_t s_ok;
     __syncthreads();
     if (threadIdx.x == 0) {
-        epoch += gridDim.x;
-        __hip_atomic_fetch_add(d.bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t e = ++epoch;
+        const uint32_t j = blockIdx.x % kBarSubs;
+        const uint32_t nsub = gridDim.x / kBarSubs + (j < gridDim.x % kBarSubs ? 1u : 0u);
+        const uint32_t nact = gridDim.x < (uint32_t)kBarSubs ? gridDim.x : (uint32_t)kBarSubs;
+        // Arrivals release; only a last arrival needs to acquire what the
+        // others released before it passes them on (fence after the RMW).
+        const uint32_t old = __hip_atomic_fetch_add(d.bar + kBarSub0 + 32 * j, 1u, __ATOMIC_RELEASE,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1 == e * nsub) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            const uint32_t top = __hip_atomic_fetch_add(d.bar + kBarTop, 1u, __ATOMIC_RELEASE,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+            if (top + 1 == e * nact) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                __hip_atomic_store(d.bar + kBarGen, e, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
         uint32_t ok = 1;
         uint32_t polls = 0;
         // Poll with relaxed loads: an acquire per poll would invalidate this
         // XCD's L2 on every iteration and starve the waves still working.  One
         // acquire fence after the wait makes the other blocks' writes visible.
-        while (__hip_atomic_load(d.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+        while (__hip_atomic_load(d.bar + kBarGen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < e) {
             __builtin_amdgcn_s_sleep(2);
             if (++polls > (1u << 22)) {
                 atomicExch(&d.counters[C_ERR], 1u);
@@ -522,7 +547,7 @@ __global__ void k_reset(Dev d) {
     for (uint64_t i = tid; i < n_pd; i += stride) d.pdirty[i] = 0;
     if (tid < C_NCOUNTERS) d.counters[tid] = 0;
     if (tid < S_NSTAT) d.stat64[tid] = 0;
-    if (tid < 4) d.bar[tid] = 0;
+    for (uint64_t i = tid; i < (uint64_t)kBarWords; i += stride) d.bar[i] = 0;
 }
 
 // Load: bin every particle-step into the voxel covering it and transpose the
@@ -812,7 +837,7 @@ __global__ void k_count_active(Dev d) {
 // (one per block at config 3): appends to a single counter from every block
 // serialise, so their number, not the bytes, sets this kernel's time.
 // Requires Tpad >= 4.
-constexpr uint32_t kStage = 4096;  // >= the most entries one block iteration makes (256 x 4 x 4)
+constexpr uint32_t kStage = 1024;  // staged entries per block (8 KB of LDS)
 __device__ __forceinline__ void flush_stage(const Dev& d, const uint2* s_buf, uint32_t n, uint32_t* s_tmp) {
     if (threadIdx.x == 0) s_tmp[4] = atomicAdd(&d.counters[C_NLIST], n);
     __syncthreads();
@@ -821,34 +846,45 @@ __device__ __forceinline__ void flush_stage(const Dev& d, const uint2* s_buf, ui
     __syncthreads();
 }
 
+// Attribute values of the 4 float4 groups a thread handles in the block
+// iteration starting at bb (NaN where out of range or where the particle's
+// value range misses the band).
+__device__ __forceinline__ void load_attr4(const Dev& d, uint64_t bb, uint64_t stride, uint64_t n4,
+                                           float lo, float hi, v4f* v) {
+    const PGeom& pg = d.pg;
+    const v4f* src = reinterpret_cast<const v4f*>(d.attr_t);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint64_t i = bb + k * stride + threadIdx.x;
+        const float nan = __builtin_nanf("");
+        v[k] = (v4f){nan, nan, nan, nan};
+        if (i < n4) {
+            const uint64_t p = pg.logTpad >= 0 ? ((i << 2) >> pg.logTpad) : ((i << 2) / pg.Tpad);
+            const float2 r = d.psum[p];
+            if (r.y >= lo && r.x <= hi) v[k] = __builtin_nontemporal_load(src + i);
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_admit_particles(Dev d) {
     __shared__ uint32_t s_tmp[8];
     __shared__ uint2 s_buf[kStage];
-    uint32_t nbuf = 0;  // entries staged; the same in every thread
     const PGeom& pg = d.pg;
     const float lo = d.crit[2], hi = d.crit[3];
     const uint64_t n4 = ((uint64_t)pg.P * pg.Tpad) >> 2;
     const int lanes_per_word = (pg.Tpad >= 64 ? 64 : pg.Tpad) >> 2;
-    const int lane = lane_id();
-    const int sub = lane & (lanes_per_word - 1);
-    const v4f* src = reinterpret_cast<const v4f*>(d.attr_t);
+    const int sub = lane_id() & (lanes_per_word - 1);
     const uint4* bsrc = reinterpret_cast<const uint4*>(d.bins);
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    // block-uniform loop: every thread of the block reaches block_append256
-    for (uint64_t bb = blockIdx.x * (uint64_t)blockDim.x; bb < n4; bb += 4 * stride) {
-        v4f v[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint64_t i = bb + k * stride + threadIdx.x;
-            const float nan = __builtin_nanf("");
-            v[k] = (v4f){nan, nan, nan, nan};
-            if (i < n4) {
-                // skip particles none of whose values can meet the band
-                const uint64_t p = pg.logTpad >= 0 ? ((i << 2) >> pg.logTpad) : ((i << 2) / pg.Tpad);
-                const float2 r = d.psum[p];
-                if (r.y >= lo && r.x <= hi) v[k] = __builtin_nontemporal_load(src + i);
-            }
-        }
+    uint32_t nbuf = 0;  // entries staged; the same in every thread
+    v4f v[4];
+    uint64_t bb = blockIdx.x * (uint64_t)blockDim.x;
+    if (bb < n4) load_attr4(d, bb, stride, n4, lo, hi, v);
+    // block-uniform loop: every thread of the block reaches the scans
+    for (; bb < n4; bb += 4 * stride) {
+        v4f vn[4];
+        const uint64_t bnext = bb + 4 * stride;
+        if (bnext < n4) load_attr4(d, bnext, stride, n4, lo, hi, vn);  // in flight during this iteration
         uint32_t nibs[4];
         uint4 bn[4];
         uint32_t cnt = 0;
@@ -883,17 +919,30 @@ __global__ __launch_bounds__(256) void k_admit_particles(Dev d) {
             flush_stage(d, s_buf, nbuf, s_tmp);
             nbuf = 0;
         }
+        const bool direct = total > kStage;  // block-uniform; more than the stage holds
         uint32_t out = nbuf + ex;
+        if (direct) {
+            if (threadIdx.x == 0) s_tmp[4] = atomicAdd(&d.counters[C_NLIST], total);
+            __syncthreads();
+            out = s_tmp[4] + ex;
+            __syncthreads();
+        }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             if (!nibs[k]) continue;
             const uint32_t f0 = (uint32_t)((bb + k * stride + threadIdx.x) << 2);
-            if (nibs[k] & 1u) s_buf[out++] = make_uint2(f0, bn[k].x);
-            if (nibs[k] & 2u) s_buf[out++] = make_uint2(f0 + 1, bn[k].y);
-            if (nibs[k] & 4u) s_buf[out++] = make_uint2(f0 + 2, bn[k].z);
-            if (nibs[k] & 8u) s_buf[out++] = make_uint2(f0 + 3, bn[k].w);
+            const uint32_t bw[4] = {bn[k].x, bn[k].y, bn[k].z, bn[k].w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (!((nibs[k] >> j) & 1u)) continue;
+                const uint2 e = make_uint2(f0 + j, bw[j]);
+                if (direct) d.clist[out++] = e;
+                else s_buf[out++] = e;
+            }
         }
-        nbuf += total;
+        if (!direct) nbuf += total;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = vn[k];
     }
     __syncthreads();
     if (nbuf) flush_stage(d, s_buf, nbuf, s_tmp);
@@ -1188,7 +1237,9 @@ bool coop_rounds(const Dev& d, uint32_t round0, uint32_t max_rounds, int device,
     Dev dd = d;
     uint32_t r0 = round0, mr = max_rounds;
     void* args[] = {&dd, &r0, &mr};
-    const dim3 grid((unsigned)(per_cu * ncu));
+    // Two blocks (8 waves) per CU cover a round's work list at these sizes;
+    // more blocks only add barrier arrivals.
+    const dim3 grid((unsigned)(std::min(per_cu, 2) * ncu));
     return hipLaunchCooperativeKernel((const void*)k_rounds<BT>, grid, dim3(256), args, 0, s) ==
            hipSuccess;
 }
@@ -1240,7 +1291,7 @@ void launch_admit_particles(const Dev& d, hipStream_t s) {
     if (pg.P == 0) return;
     if (pg.Tpad >= 4) {
         const uint64_t n4 = ((uint64_t)pg.P * pg.Tpad) >> 2;
-        hipLaunchKernelGGL(k_admit_particles, dim3(grid_for(n4 / 4, 256, 2048)), dim3(256), 0, s, d);
+        hipLaunchKernelGGL(k_admit_particles, dim3(grid_for(n4 / 4, 256, 4096)), dim3(256), 0, s, d);
     } else {
         hipLaunchKernelGGL(k_admit_particles_short, dim3(grid_for(pg.P, 256, 4096)), dim3(256), 0, s,
                            d);

@@ -7,6 +7,7 @@
 namespace mf4d {
 
 constexpr uint32_t kNoVoxel = 0xFFFFFFFFu;
+constexpr int kBarWords = 64 + 32 * 8;  // grid-barrier counters (top, flag, 8 subs), one line each
 
 // Bit-packed tile layout of the field labels and admissibility.
 // A tile covers 32 (x) x 8 (y) x 8 (z) x BT (t) voxel-steps.  One 32-bit word

@@ -246,3 +246,15 @@ def test_criteria_change_between_grows():
             assert np.array_equal(fm, ofm) and np.array_equal(pm, opm), crit
     finally:
         g.close()
+
+
+@pytest.mark.parametrize("tau_p", [0.70, 0.75, 0.9])
+def test_coupled_list_staging_many_iterations(tau_p):
+    """Enough particle-steps (64 x 300,000) that each block of the particle
+    admissibility pass runs many iterations, with an independent-noise
+    attribute whose threshold puts an iteration's coupled entries near, above
+    and below what a block stages (flushes and direct writes mixed)."""
+    inst = synth.make_instance(64, 64, 64, 64, 300000, n_blobs=8, seed=17, n_seeds=8,
+                               tau_f=0.3, tau_p=tau_p, attr_mode="noise")
+    for schedule in ("persistent", "launch"):
+        _assert_parity(inst, tag=f"staging tau_p={tau_p} {schedule}", schedule=schedule)
