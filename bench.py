@@ -190,6 +190,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip eager / learned / batched")
     ap.add_argument("--batched-reps", type=int, default=3)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run three 1 GiB device copies (a plain copy kernel of known size, "
+                         "the scale for hardware byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -256,6 +259,13 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "bytes_per_launch": b, "ms_per_launch": round(t_ms, 4)}
 
+    if args.copy_probe:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     ref_f = fmask.clone()
     ref_p = pmask.clone()
     forms = {}

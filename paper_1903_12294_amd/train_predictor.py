@@ -93,7 +93,7 @@ def main():
     pos = sum(int(y.sum()) for _, y in data)
     tot = sum(y.numel() for _, y in data)
     rec = dict(workload="128^3 x 32, 16 blobs, 262144 particles, 8 seeds, thresholds 0.3/0.3",
-               seeds=[seeds[0], seeds[-1]], train=len(tr), val=len(va), epochs=args.epochs,
+               seeds=[seeds[0], seeds[-1]], n_train=len(tr), n_val=len(va), epochs=args.epochs,
                lr=args.lr, init_seed=args.init_seed, positive_fraction=pos / tot,
                loss_first=hist[0], loss_last=hist[-1], logit_threshold=thr,
                min_recall=args.min_recall, val=ev_val, train_metrics=ev_train,

@@ -49,3 +49,14 @@ def test_version_and_error_without_gpu():
 def test_missing_library_raises(tmp_path):
     with pytest.raises(_lib.LibraryMissing):
         _lib.load_library(str(tmp_path / "nope.so"))
+
+
+def test_every_package_module_imports():
+    import importlib
+    import pkgutil
+
+    import paper_1903_12294_amd as pkg
+    for m in pkgutil.iter_modules(pkg.__path__):
+        if m.name.startswith("lib"):  # the HIP shared library, not a Python module
+            continue
+        importlib.import_module(f"{pkg.__name__}.{m.name}")
