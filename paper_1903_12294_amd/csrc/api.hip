@@ -101,11 +101,15 @@ struct mf4d_ctx {
     unsigned long long* Lp = nullptr;
     uint2* clist = nullptr;
     uint32_t* pdirty = nullptr;
+    uint32_t* pcand = nullptr;      // candidate particles of the current grow
+    uint8_t* pflag = nullptr;       // P candidate flags
+    uint32_t* pblk = nullptr;       // candidate-pass block counts / offsets
     uint32_t* dlist = nullptr;
     float2* psum = nullptr;
 
     uint32_t* counters = nullptr;
     unsigned long long* stat64 = nullptr;
+    unsigned long long* slots = nullptr;  // per-block partial statistics
     uint32_t* bar = nullptr;
     uint32_t* h_counters = nullptr;
     unsigned long long* h_stat = nullptr;
@@ -182,6 +186,9 @@ void free_particles(mf4d_ctx* c) {
     dev_free(c->Lp);
     dev_free(c->clist);
     dev_free(c->pdirty);
+    dev_free(c->pcand);
+    dev_free(c->pflag);
+    dev_free(c->pblk);
     dev_free(c->dlist);
     dev_free(c->psum);
     c->has_particles = false;
@@ -231,7 +238,10 @@ Dev make_dev(mf4d_ctx* c) {
     d.Lp = c->Lp;
     d.clist = c->clist;
     d.pdirty = c->pdirty;
-    d.dlist = c->dlist;
+    d.pcand = c->pcand;
+    d.pflag = c->pflag;
+    d.pblk = c->pblk;
+    d.slots = c->slots;
     d.counters = c->counters;
     d.stat64 = c->stat64;
     d.bar = c->bar;
@@ -289,6 +299,7 @@ int run_rounds(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
 }
 
 int finish_stats(mf4d_ctx* c, mf4d_stats* out, bool fresh, int64_t rounds) {
+    launch_fold_slots(make_dev(c), SL_PART_VISITS, S_PART_VISITS, c->stream);
     HIP_TRY(hipMemcpyAsync(c->h_stat, c->stat64, S_NSTAT * sizeof(unsigned long long),
                            hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, C_NCOUNTERS * sizeof(uint32_t),
@@ -347,6 +358,8 @@ int mf4d_create(mf4d_ctx** out, int device, void* hip_stream) {
     int rc = dev_alloc(&c->counters, C_NCOUNTERS);
     if (!rc) rc = dev_alloc(&c->stat64, S_NSTAT);
     if (!rc) rc = dev_alloc(&c->bar, kBarWords);
+    if (!rc) rc = dev_alloc(&c->slots, (size_t)kSlotStats * kSlots);
+    if (!rc) launch_fill_u32((uint32_t*)c->slots, 0, 2ull * kSlotStats * kSlots, c->stream);
     if (!rc) {
         const char* env = getenv("MF4D_SCHED");
         if (env && strcmp(env, "launch") == 0) c->schedule = MF4D_SCHED_LAUNCH;
@@ -376,6 +389,7 @@ void mf4d_destroy(mf4d_ctx* c) {
     free_particles(c);
     dev_free(c->counters);
     dev_free(c->stat64);
+    dev_free(c->slots);
     dev_free(c->bar);
     dev_free(c->seeds);
     dev_free(c->btab);
@@ -495,6 +509,9 @@ int mf4d_load_particles(mf4d_ctx* c, const float* xyz, const float* attr, int64_
     if (!rc) rc = dev_alloc(&c->Lp, (size_t)P * pg.W);
     if (!rc) rc = dev_alloc(&c->clist, Q);
     if (!rc) rc = dev_alloc(&c->pdirty, (size_t)(P + 31) / 32);
+    if (!rc) rc = dev_alloc(&c->pcand, (size_t)P);
+    if (!rc) rc = dev_alloc(&c->pflag, (size_t)P);
+    if (!rc) rc = dev_alloc(&c->pblk, (size_t)kPBlocks + 1);
     if (!rc) rc = dev_alloc(&c->dlist, (size_t)P);
     if (!rc) rc = dev_alloc(&c->psum, (size_t)P);
     if (rc) {
@@ -705,6 +722,7 @@ int mf4d_read_field_mask(mf4d_ctx* c, uint32_t* dst, size_t nwords, int where) {
     }
     launch_fill_u32((uint32_t*)(c->stat64 + S_MEMBERS_F), 0, 2, c->stream);
     launch_read_field(make_dev(c), out, c->stream);
+    launch_fold_slots(make_dev(c), SL_MEMBERS_F, S_MEMBERS_F, c->stream);
     if (where == MF4D_HOST)
         HIP_TRY(hipMemcpyAsync(dst, out, need * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(c->h_stat + S_MEMBERS_F, c->stat64 + S_MEMBERS_F,
@@ -733,6 +751,7 @@ int mf4d_read_particle_mask(mf4d_ctx* c, uint8_t* dst, size_t n, int where) {
     }
     launch_fill_u32((uint32_t*)(c->stat64 + S_MEMBERS_P), 0, 2, c->stream);
     launch_read_particles(make_dev(c), out, c->stream);
+    launch_fold_slots(make_dev(c), SL_MEMBERS_P, S_MEMBERS_P, c->stream);
     if (where == MF4D_HOST)
         HIP_TRY(hipMemcpyAsync(dst, out, need, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(c->h_stat + S_MEMBERS_P, c->stat64 + S_MEMBERS_P,

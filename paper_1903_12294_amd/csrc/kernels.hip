@@ -364,30 +364,28 @@ __device__ void sweep_tile(const Dev& d, uint32_t tile, int par) {
     }
 }
 
-// Pull, block-level (every thread of the block calls it for the same chunk):
-// a coupled particle-step joins when the voxel holding it is a member.  Only
-// steps in tiles whose members changed since their last pull are tested.  A
-// particle that gains a step goes once on the dirty list.
-__device__ void pull_chunk(const Dev& d, uint32_t cb, uint32_t n, int par, uint32_t* s_tmp) {
+// Pull: a coupled particle-step joins when the voxel holding it is a member.
+// Only steps in tiles whose members changed since their last pull are tested.
+// A particle that gains a step is marked in pdirty for the close phase.
+// Thread-level: each thread takes list entries i0, i0 + stride, ... (4 at once).
+__device__ void pull_entries(const Dev& d, uint32_t i0, uint32_t stride, uint32_t n, int par) {
     const PGeom& pg = d.pg;
     const int tshift = 5 + 6 + d.g.logBT;
     const uint8_t* chg = d.chg + par * d.g.NT;
-    uint2 ent[4];
+    for (uint32_t i = i0; i < n; i += 4 * stride) {
+        uint2 ent[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const uint32_t i = cb + k * 256 + threadIdx.x;
-        ent[k] = i < n ? d.clist[i] : make_uint2(0u, kNoVoxel);
-    }
-    bool mem[4];
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t j = i + k * stride;
+            ent[k] = j < n ? d.clist[j] : make_uint2(0u, kNoVoxel);
+        }
+        bool mem[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-        mem[k] = ent[k].y != kNoVoxel && chg[ent[k].y >> tshift] && test_bit(d.Lf, ent[k].y);
-    uint32_t first[4];
-    uint32_t nfirst = 0;
+        for (int k = 0; k < 4; ++k)
+            mem[k] = ent[k].y != kNoVoxel && chg[ent[k].y >> tshift] && test_bit(d.Lf, ent[k].y);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        first[k] = kNoVoxel;
-        if (mem[k]) {
+        for (int k = 0; k < 4; ++k) {
+            if (!mem[k]) continue;
             uint32_t p, ts;
             if (pg.logTpad >= 0) {
                 p = ent[k].x >> pg.logTpad;
@@ -398,19 +396,10 @@ __device__ void pull_chunk(const Dev& d, uint32_t cb, uint32_t n, int par, uint3
             }
             const uint32_t wi = p * (uint32_t)pg.W + (ts >> 6);
             const unsigned long long bit = 1ull << (ts & 63);
-            if (!(d.Lp[wi] & bit) && !(atomicOr(&d.Lp[wi], bit) & bit)) {
-                const uint32_t pb = 1u << (p & 31);
-                if (!(atomicOr(&d.pdirty[p >> 5], pb) & pb)) {
-                    first[k] = p;
-                    ++nfirst;
-                }
-            }
+            if (!(d.Lp[wi] & bit) && !(atomicOr(&d.Lp[wi], bit) & bit))
+                atomicOr(&d.pdirty[p >> 5], 1u << (p & 31));
         }
     }
-    uint32_t base = block_append256(nfirst, &d.counters[C_NDIRTYP], s_tmp);
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-        if (first[k] != kNoVoxel) d.dlist[base++] = first[k];
 }
 
 __device__ __forceinline__ void push_steps(const Dev& d, uint32_t p, int w, unsigned long long nw,
@@ -426,23 +415,29 @@ __device__ __forceinline__ void push_steps(const Dev& d, uint32_t p, int w, unsi
     }
 }
 
-// Close and push one dirty particle: its member steps spread over each run of
-// admissible steps that holds them (its trajectory), and every step that joins
-// pushes its voxel in when that voxel is admissible, for round parity `par`.
-__device__ void close_particle(const Dev& d, uint32_t p, int par) {
-    atomicAnd(&d.pdirty[p >> 5], ~(1u << (p & 31)));
+// Push one particle-step that joined (flat index e = p * Tpad + t): its voxel
+// joins when admissible, for round parity `par`.
+__device__ __forceinline__ void push_one(const Dev& d, uint32_t e, int par) {
+    const uint32_t b = d.bins[e];
+    if (b != kNoVoxel && admissible_bit(d, b)) {
+        const uint32_t bit = 1u << (b & 31);
+        if (!(atomicOr(&d.Lf[b >> 5], bit) & bit)) mark_voxel(d, b, par);
+    }
+}
+
+// Close one dirty particle: its member steps spread over each run of
+// admissible steps that holds them (its trajectory).  With one label word
+// (W = 1) the new steps are returned for the caller to push; with more words
+// they are pushed here and 0 is returned.
+__device__ unsigned long long close_one(const Dev& d, uint32_t p, int par) {
     const int W = d.pg.W;
     unsigned long long* lw = d.Lp + (size_t)p * W;
     const unsigned long long* aw = d.Ap + (size_t)p * W;
     if (W == 1) {
         const unsigned long long a = aw[0], l0 = lw[0];
-        const unsigned long long l = fill_runs64(l0, a);
-        const unsigned long long nw = l & ~l0;
-        if (nw) {
-            atomicOr(&lw[0], nw);
-            push_steps(d, p, 0, nw, par);
-        }
-        return;
+        const unsigned long long nw = fill_runs64(l0, a) & ~l0;
+        if (nw) atomicOr(&lw[0], nw);
+        return nw;
     }
     // runs crossing word boundaries: carry upward, then downward
     unsigned long long carry = 0;
@@ -466,6 +461,99 @@ __device__ void close_particle(const Dev& d, uint32_t p, int par) {
             atomicOr(&lw[w], nw);
             push_steps(d, p, w, nw, par);
         }
+    }
+    return 0ull;
+}
+
+// Lanes of one wave exchanging through LDS: order the LDS accesses around it.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Exclusive prefix sum over the wave; `total` gets the wave's sum.
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t& total) {
+    const int lane = lane_id();
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    total = __shfl(x, 63);
+    return x - v;
+}
+
+// Close phase, wave-level: the wave takes 64 pdirty words at a time (clearing
+// them), gathers their dirty particles into LDS 64 at a time so that each
+// lane closes one, then gathers the new steps of all its lanes 64 at a time so
+// that each lane pushes one.  No lane walks a long chain alone.  Returns the
+// number of particles this wave closed (the same in every lane).
+__device__ uint32_t close_phase(const Dev& d, int par, uint32_t wave_id, uint32_t nwaves,
+                                uint32_t* s_list) {
+    const PGeom& pg = d.pg;
+    const uint32_t nw32 = (uint32_t)((pg.P + 31) / 32);
+    const int lane = lane_id();
+    uint32_t closed = 0;
+    for (uint32_t base = wave_id * 64; base < nw32; base += nwaves * 64) {
+        uint32_t wd = 0;
+        if (base + lane < nw32) {
+            wd = d.pdirty[base + lane];
+            if (wd) d.pdirty[base + lane] = 0u;  // no setter runs during this phase
+        }
+        while (__ballot(wd != 0)) {
+            uint32_t total;
+            uint32_t k = wave_excl_scan(__popc(wd), total);
+            while (wd && k < 64) {
+                const int b = __ffs(wd) - 1;
+                wd &= wd - 1;
+                s_list[k++] = (base + lane) * 32 + b;
+            }
+            wave_sync();
+            const uint32_t n = total < 64 ? total : 64;
+            closed += n;
+            uint32_t p = 0;
+            unsigned long long nw = 0;
+            if ((uint32_t)lane < n) {
+                p = s_list[lane];
+                nw = close_one(d, p, par);
+            }
+            wave_sync();
+            while (__ballot(nw != 0)) {
+                uint32_t tot2;
+                uint32_t k2 = wave_excl_scan(__popcll(nw), tot2);
+                while (nw && k2 < 64) {
+                    const int t = __builtin_ctzll(nw);
+                    nw &= nw - 1;
+                    s_list[k2++] = p * (uint32_t)pg.Tpad + t;
+                }
+                wave_sync();
+                if ((uint32_t)lane < (tot2 < 64 ? tot2 : 64)) push_one(d, s_list[lane], par);
+                wave_sync();
+            }
+        }
+    }
+    return closed;
+}
+
+// Add a per-block value to its slot of statistic `which` (thread 0 calls).
+__device__ __forceinline__ void slot_add(const Dev& d, int which, unsigned long long v) {
+    if (v) atomicAdd(&d.slots[which * kSlots + (blockIdx.x & (kSlots - 1))], v);
+}
+
+// Sum a per-thread count over the block (every thread calls; uses barriers)
+// and add it to the block's slot of statistic `which`.
+__device__ __forceinline__ void block_slot_sum(const Dev& d, int which, uint32_t v) {
+    __shared__ uint32_t s_w[16];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    __syncthreads();
+    if (lane_id() == 0) s_w[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (unsigned w = 0; w < (blockDim.x + 63) / 64; ++w) t += s_w[w];
+        slot_add(d, which, t);
     }
 }
 
@@ -527,6 +615,24 @@ __device__ bool grid_sync(const Dev& d, uint32_t& epoch) {
 // ---------------------------------------------------------------------------
 // kernels
 
+// stat64[dst] += the slots of statistic `which`; the slots are cleared.
+__global__ __launch_bounds__(1024) void k_fold_slots(Dev d, int which, int dst) {
+    __shared__ unsigned long long s_w[16];
+    unsigned long long v = 0;
+    for (int i = threadIdx.x; i < kSlots; i += blockDim.x) {
+        v += d.slots[which * kSlots + i];
+        d.slots[which * kSlots + i] = 0ull;
+    }
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane_id() == 0) s_w[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < 16; ++w) t += s_w[w];
+        d.stat64[dst] += t;
+    }
+}
+
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, uint64_t n) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x)
@@ -548,6 +654,7 @@ __global__ void k_reset(Dev d) {
     if (tid < C_NCOUNTERS) d.counters[tid] = 0;
     if (tid < S_NSTAT) d.stat64[tid] = 0;
     for (uint64_t i = tid; i < (uint64_t)kBarWords; i += stride) d.bar[i] = 0;
+    for (uint64_t i = tid; i < (uint64_t)kSlotStats * kSlots; i += stride) d.slots[i] = 0ull;
 }
 
 // Load: bin every particle-step into the voxel covering it and transpose the
@@ -846,65 +953,119 @@ __device__ __forceinline__ void flush_stage(const Dev& d, const uint2* s_buf, ui
     __syncthreads();
 }
 
-// Attribute values of the 4 float4 groups a thread handles in the block
-// iteration starting at bb (NaN where out of range or where the particle's
-// value range misses the band).
-__device__ __forceinline__ void load_attr4(const Dev& d, uint64_t bb, uint64_t stride, uint64_t n4,
-                                           float lo, float hi, v4f* v) {
-    const PGeom& pg = d.pg;
-    const v4f* src = reinterpret_cast<const v4f*>(d.attr_t);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const uint64_t i = bb + k * stride + threadIdx.x;
-        const float nan = __builtin_nanf("");
-        v[k] = (v4f){nan, nan, nan, nan};
-        if (i < n4) {
-            const uint64_t p = pg.logTpad >= 0 ? ((i << 2) >> pg.logTpad) : ((i << 2) / pg.Tpad);
-            const float2 r = d.psum[p];
-            if (r.y >= lo && r.x <= hi) v[k] = __builtin_nontemporal_load(src + i);
-        }
+// Candidate particles of a grow: those whose load-time value range meets the
+// band (the others hold no admissible step).  Three passes, no atomics: per
+// block of particles the flags and their count; one block scans the counts;
+// each block writes its candidates, in index order, at its offset.
+__global__ __launch_bounds__(256) void k_pcand_count(Dev d) {
+    __shared__ uint32_t s_tmp[8];
+    const int64_t P = d.pg.P;
+    const int64_t per = (P + kPBlocks - 1) / kPBlocks;
+    const int64_t p0 = blockIdx.x * per, p1 = min(P, p0 + per);
+    const float lo = d.crit[2], hi = d.crit[3];
+    uint32_t c = 0;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        const float2 r = d.psum[p];
+        const bool in = r.y >= lo && r.x <= hi;
+        d.pflag[p] = in ? 1 : 0;
+        c += in ? 1u : 0u;
+    }
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if (lane_id() == 0) s_tmp[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) d.pblk[blockIdx.x] = s_tmp[0] + s_tmp[1] + s_tmp[2] + s_tmp[3];
+}
+
+__global__ __launch_bounds__(1024) void k_pcand_scan(Dev d) {
+    __shared__ uint32_t s_w[16];
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const uint32_t v = threadIdx.x < (unsigned)kPBlocks ? d.pblk[threadIdx.x] : 0u;
+    uint32_t wt;
+    const uint32_t ex = wave_excl_scan(v, wt);
+    if (lane == 0) s_w[wave] = wt;
+    __syncthreads();
+    uint32_t base = 0, total = 0;
+    for (int w = 0; w < 16; ++w) {
+        if (w < wave) base += s_w[w];
+        total += s_w[w];
+    }
+    if (threadIdx.x < (unsigned)kPBlocks) d.pblk[threadIdx.x] = base + ex;
+    if (threadIdx.x == 0) d.counters[C_NPCAND] = total;
+}
+
+__global__ __launch_bounds__(256) void k_pcand_write(Dev d) {
+    __shared__ uint32_t s_tmp[8];
+    const int64_t P = d.pg.P;
+    const int64_t per = (P + kPBlocks - 1) / kPBlocks;
+    const int64_t p0 = blockIdx.x * per, p1 = min(P, p0 + per);
+    uint32_t off = d.pblk[blockIdx.x];
+    for (int64_t b0 = p0; b0 < p1; b0 += blockDim.x) {  // block-uniform
+        const int64_t p = b0 + threadIdx.x;
+        const uint32_t in = p < p1 && d.pflag[p] ? 1u : 0u;
+        uint32_t total;
+        const uint32_t ex = block_exclusive_scan256(in, s_tmp, total);
+        if (in) d.pcand[off + ex] = (uint32_t)p;
+        off += total;
     }
 }
 
+// Admissibility of the candidate particles' steps, their labels cleared, and
+// the coupled list: every admissible particle-step that lies in a voxel, as
+// (flat index, voxel bit).  A unit is one 64-step label word of a candidate
+// (or a whole row when Tpad < 64); G lanes read it with 16-byte loads and OR
+// their nibbles into the word.  A lane with an admissible step loads the 4
+// matching bins (16 bytes).  Entries are staged in LDS and flushed to the
+// global list with one atomic per flush (appends to one counter from every
+// block serialise).  Non-candidates are not touched: their pflag is 0.
+// Requires Tpad >= 4.
 __global__ __launch_bounds__(256) void k_admit_particles(Dev d) {
     __shared__ uint32_t s_tmp[8];
     __shared__ uint2 s_buf[kStage];
     const PGeom& pg = d.pg;
     const float lo = d.crit[2], hi = d.crit[3];
-    const uint64_t n4 = ((uint64_t)pg.P * pg.Tpad) >> 2;
-    const int lanes_per_word = (pg.Tpad >= 64 ? 64 : pg.Tpad) >> 2;
-    const int sub = lane_id() & (lanes_per_word - 1);
+    const int G = pg.Tpad >= 64 ? 16 : (pg.Tpad >> 2);  // lanes per unit (power of two)
+    const uint32_t upb = 256 / G;                       // units per block pass
+    const int W = pg.W;
+    const uint64_t nunits = (uint64_t)d.counters[C_NPCAND] * W;
+    const int sub = threadIdx.x & (G - 1);
+    const uint64_t gstride = (uint64_t)gridDim.x * upb;
+    const v4f* src = reinterpret_cast<const v4f*>(d.attr_t);
     const uint4* bsrc = reinterpret_cast<const uint4*>(d.bins);
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     uint32_t nbuf = 0;  // entries staged; the same in every thread
-    v4f v[4];
-    uint64_t bb = blockIdx.x * (uint64_t)blockDim.x;
-    if (bb < n4) load_attr4(d, bb, stride, n4, lo, hi, v);
-    // block-uniform loop: every thread of the block reaches the scans
-    for (; bb < n4; bb += 4 * stride) {
-        v4f vn[4];
-        const uint64_t bnext = bb + 4 * stride;
-        if (bnext < n4) load_attr4(d, bnext, stride, n4, lo, hi, vn);  // in flight during this iteration
+    for (uint64_t ub = blockIdx.x * (uint64_t)upb; ub < nunits; ub += 4 * gstride) {  // block-uniform
+        v4f v[4];
+        uint32_t e0[4], wi[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint64_t u = ub + k * gstride + threadIdx.x / G;
+            const float nan = __builtin_nanf("");
+            v[k] = (v4f){nan, nan, nan, nan};
+            e0[k] = 0xFFFFFFFFu;
+            if (u < nunits) {
+                const uint32_t p = d.pcand[W == 1 ? u : u / W];
+                const uint32_t w = W == 1 ? 0u : (uint32_t)(u % W);
+                e0[k] = p * (uint32_t)pg.Tpad + w * 64u + (uint32_t)sub * 4u;
+                wi[k] = p * (uint32_t)W + w;
+                v[k] = __builtin_nontemporal_load(src + (e0[k] >> 2));
+            }
+        }
         uint32_t nibs[4];
         uint4 bn[4];
         uint32_t cnt = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const uint64_t i = bb + k * stride + threadIdx.x;
             const uint32_t nib = (uint32_t)in_band(v[k].x, lo, hi) |
                                  ((uint32_t)in_band(v[k].y, lo, hi) << 1) |
                                  ((uint32_t)in_band(v[k].z, lo, hi) << 2) |
                                  ((uint32_t)in_band(v[k].w, lo, hi) << 3);
             unsigned long long x = (unsigned long long)nib << (4 * sub);
-            for (int o = 1; o < lanes_per_word; o <<= 1) x |= __shfl_xor(x, o);
-            if (sub == 0 && i < n4) {
-                // 64 steps per word (Tpad >= 64), else one word per particle
-                const uint64_t wi = pg.Tpad >= 64 ? (i >> 4) : (i / (uint64_t)lanes_per_word);
-                d.Ap[wi] = x;
-                d.Lp[wi] = 0ull;
+            for (int o = 1; o < G; o <<= 1) x |= __shfl_xor(x, o);
+            if (sub == 0 && e0[k] != 0xFFFFFFFFu) {
+                d.Ap[wi[k]] = x;
+                d.Lp[wi[k]] = 0ull;
             }
             bn[k] = make_uint4(kNoVoxel, kNoVoxel, kNoVoxel, kNoVoxel);
-            if (nib) bn[k] = bsrc[i];  // nib != 0 implies i < n4
+            if (nib) bn[k] = bsrc[e0[k] >> 2];  // nib != 0 implies a unit in range
             uint32_t m = nib;
             if (bn[k].x == kNoVoxel) m &= ~1u;
             if (bn[k].y == kNoVoxel) m &= ~2u;
@@ -930,19 +1091,16 @@ __global__ __launch_bounds__(256) void k_admit_particles(Dev d) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             if (!nibs[k]) continue;
-            const uint32_t f0 = (uint32_t)((bb + k * stride + threadIdx.x) << 2);
             const uint32_t bw[4] = {bn[k].x, bn[k].y, bn[k].z, bn[k].w};
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 if (!((nibs[k] >> j) & 1u)) continue;
-                const uint2 e = make_uint2(f0 + j, bw[j]);
+                const uint2 e = make_uint2(e0[k] + j, bw[j]);
                 if (direct) d.clist[out++] = e;
                 else s_buf[out++] = e;
             }
         }
         if (!direct) nbuf += total;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] = vn[k];
     }
     __syncthreads();
     if (nbuf) flush_stage(d, s_buf, nbuf, s_tmp);
@@ -958,6 +1116,7 @@ __global__ void k_admit_particles_short(Dev d) {
             if (in_band(d.attr_t[p * pg.Tpad + t], d.crit[2], d.crit[3])) x |= 1ull << t;
         d.Ap[p] = x;
         d.Lp[p] = 0ull;
+        d.pflag[p] = 1;
     }
 }
 
@@ -1003,7 +1162,6 @@ __global__ void k_seeds(Dev d, const int32_t* __restrict__ seeds, int64_t S) {
 
 template <int BT>
 __global__ __launch_bounds__(256) void k_round_sweep(Dev d, int par) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) d.counters[C_NDIRTYP] = 0;
     const uint32_t nwork = d.counters[C_NWORK0 + par];
     const uint32_t wave0 = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
@@ -1014,60 +1172,62 @@ __global__ __launch_bounds__(256) void k_round_sweep(Dev d, int par) {
 }
 
 __global__ __launch_bounds__(256) void k_round_pull(Dev d, int par) {
-    __shared__ uint32_t s_tmp[8];
     if (blockIdx.x == 0 && threadIdx.x == 0) d.counters[C_NWORK0 + par] = 0;
-    const uint32_t n = d.counters[C_NLIST];
-    for (uint32_t cb = blockIdx.x * 1024u; cb < n; cb += gridDim.x * 1024u)
-        pull_chunk(d, cb, n, par, s_tmp);
+    pull_entries(d, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x,
+                 d.counters[C_NLIST], par);
 }
 
 __global__ __launch_bounds__(256) void k_round_close(Dev d, int par) {
+    __shared__ uint32_t s_list[4 * 64];
+    __shared__ uint32_t s_cnt;
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t i = tid; i < d.g.NT; i += stride) d.chg[par * d.g.NT + i] = 0;
-    const uint32_t nd = d.counters[C_NDIRTYP];
-    if (tid == 0 && nd) atomicAdd(&d.stat64[S_PART_VISITS], (unsigned long long)nd);
-    for (uint32_t i = tid; i < nd; i += stride) close_particle(d, d.dlist[i], par ^ 1);
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    const uint32_t closed =
+        close_phase(d, par ^ 1, tid >> 6, stride >> 6, s_list + 64 * (threadIdx.x >> 6));
+    if (lane_id() == 0 && closed) atomicAdd(&s_cnt, closed);
+    __syncthreads();
+    if (threadIdx.x == 0) slot_add(d, SL_PART_VISITS, s_cnt);
 }
 
 // ---- all rounds in one cooperative launch ----
 template <int BT>
 __global__ __launch_bounds__(256) void k_rounds(Dev d, uint32_t round0, uint32_t max_rounds) {
-    __shared__ uint32_t s_tmp[8];
+    __shared__ uint32_t s_list[4 * 64];
+    __shared__ uint32_t s_cnt;
     uint32_t epoch = 0;
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t nthreads = gridDim.x * blockDim.x;
     const uint32_t wave0 = tid >> 6, nwaves = nthreads >> 6;
     const bool parts = d.pg.P > 0;
+    uint32_t* my_list = s_list + 64 * (threadIdx.x >> 6);
+    if (threadIdx.x == 0) s_cnt = 0;
     uint32_t r = round0;
-    uint32_t visits = 0;
+    uint32_t visits = 0, closed = 0;
     while (true) {
         const int par = r & 1;
         const uint32_t nwork = load_relaxed(&d.counters[C_NWORK0 + par]);
         if (nwork == 0 || (max_rounds && r - round0 >= max_rounds)) break;
         // sweep
-        if (tid == 0) store_relaxed(&d.counters[C_NDIRTYP], 0u);
         for (uint32_t w = wave0; w < nwork; w += nwaves) sweep_tile<BT>(d, d.work[par * d.g.NT + w], par);
         visits += nwork;  // the same in every thread; only thread 0 records it
         if (!grid_sync(d, epoch)) break;
         // pull
         if (tid == 0) store_relaxed(&d.counters[C_NWORK0 + par], 0u);
-        if (parts) {
-            const uint32_t n = load_relaxed(&d.counters[C_NLIST]);
-            for (uint32_t cb = blockIdx.x * 1024u; cb < n; cb += gridDim.x * 1024u)
-                pull_chunk(d, cb, n, par, s_tmp);
-        }
+        if (parts) pull_entries(d, tid, nthreads, load_relaxed(&d.counters[C_NLIST]), par);
         if (!grid_sync(d, epoch)) break;
         // close and push
         for (uint32_t i = tid; i < d.g.NT; i += nthreads) d.chg[par * d.g.NT + i] = 0;
-        if (parts) {
-            const uint32_t nd = load_relaxed(&d.counters[C_NDIRTYP]);
-            if (tid == 0 && nd) atomicAdd(&d.stat64[S_PART_VISITS], (unsigned long long)nd);
-            for (uint32_t i = tid; i < nd; i += nthreads) close_particle(d, d.dlist[i], par ^ 1);
-        }
+        if (parts) closed += close_phase(d, par ^ 1, wave0, nwaves, my_list);
         if (!grid_sync(d, epoch)) break;
         ++r;
     }
+    __syncthreads();
+    if (lane_id() == 0 && closed) atomicAdd(&s_cnt, closed);
+    __syncthreads();
+    if (threadIdx.x == 0) slot_add(d, SL_PART_VISITS, s_cnt);
     if (tid == 0 && visits) atomicAdd(&d.stat64[S_TILE_VISITS], (unsigned long long)visits);
     if (tid == 0) store_relaxed(&d.counters[C_ROUNDS], r - round0);
 }
@@ -1131,8 +1291,7 @@ __global__ __launch_bounds__(256) void k_read_field_tiles(Dev d, uint32_t* __res
         }
         __syncthreads();
     }
-    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-    if (lane_id() == 0 && cnt) atomicAdd(&d.stat64[S_MEMBERS_F], (unsigned long long)cnt);
+    block_slot_sum(d, SL_MEMBERS_F, cnt);
 }
 
 __global__ __launch_bounds__(256) void k_read_field_bits(Dev d, uint32_t* __restrict__ out) {
@@ -1157,8 +1316,7 @@ __global__ __launch_bounds__(256) void k_read_field_bits(Dev d, uint32_t* __rest
         out[i] = w;
         cnt += __popc(w);
     }
-    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-    if (lane_id() == 0 && cnt) atomicAdd(&d.stat64[S_MEMBERS_F], (unsigned long long)cnt);
+    block_slot_sum(d, SL_MEMBERS_F, cnt);
 }
 
 // Particle labels -> uint8 [T][P].  Fast path (one label word per particle,
@@ -1171,9 +1329,11 @@ __global__ __launch_bounds__(256) void k_read_particles16(Dev d, uint8_t* __rest
     uint32_t cnt = 0;
     if (p0 < pg.P) {
         unsigned long long lw[16];
+        const uint4 fl = *reinterpret_cast<const uint4*>(d.pflag + p0);  // 16 candidate flags
+        const uint32_t fw[4] = {fl.x, fl.y, fl.z, fl.w};
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            lw[k] = d.Lp[p0 + k];
+            lw[k] = (fw[k >> 2] >> (8 * (k & 3))) & 0xFFu ? d.Lp[p0 + k] : 0ull;
             cnt += __popcll(lw[k]);
         }
         for (int t = 0; t < pg.T; ++t) {
@@ -1188,8 +1348,7 @@ __global__ __launch_bounds__(256) void k_read_particles16(Dev d, uint8_t* __rest
                                         reinterpret_cast<v4u*>(out + (int64_t)t * pg.P + p0));
         }
     }
-    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-    if (lane_id() == 0 && cnt) atomicAdd(&d.stat64[S_MEMBERS_P], (unsigned long long)cnt);
+    block_slot_sum(d, SL_MEMBERS_P, cnt);
 }
 
 // General particle read-out: a thread owns 4 consecutive particles.
@@ -1203,7 +1362,7 @@ __global__ __launch_bounds__(256) void k_read_particles(Dev d, uint8_t* __restri
         for (int w = 0; w < pg.W; ++w) {
             unsigned long long lw[4] = {0, 0, 0, 0};
             for (int k = 0; k < np; ++k) {
-                lw[k] = d.Lp[(size_t)(p0 + k) * pg.W + w];
+                lw[k] = d.pflag[p0 + k] ? d.Lp[(size_t)(p0 + k) * pg.W + w] : 0ull;
                 cnt += __popcll(lw[k]);
             }
             const int tend = min(64, pg.T - w * 64);
@@ -1214,8 +1373,7 @@ __global__ __launch_bounds__(256) void k_read_particles(Dev d, uint8_t* __restri
             }
         }
     }
-    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-    if (lane_id() == 0 && cnt) atomicAdd(&d.stat64[S_MEMBERS_P], (unsigned long long)cnt);
+    block_slot_sum(d, SL_MEMBERS_P, cnt);
 }
 
 inline unsigned grid_for(uint64_t n, unsigned block, unsigned cap) {
@@ -1248,6 +1406,10 @@ bool coop_rounds(const Dev& d, uint32_t round0, uint32_t max_rounds, int device,
 
 // ---------------------------------------------------------------------------
 // launchers
+
+void launch_fold_slots(const Dev& d, int which, int dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(1024), 0, s, d, which, dst);
+}
 
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
     if (n == 0) return;
@@ -1291,7 +1453,13 @@ void launch_admit_particles(const Dev& d, hipStream_t s) {
     if (pg.P == 0) return;
     if (pg.Tpad >= 4) {
         const uint64_t n4 = ((uint64_t)pg.P * pg.Tpad) >> 2;
-        hipLaunchKernelGGL(k_admit_particles, dim3(grid_for(n4 / 4, 256, 4096)), dim3(256), 0, s, d);
+        (void)n4;
+        hipLaunchKernelGGL(k_pcand_count, dim3(kPBlocks), dim3(256), 0, s, d);
+        hipLaunchKernelGGL(k_pcand_scan, dim3(1), dim3(1024), 0, s, d);
+        hipLaunchKernelGGL(k_pcand_write, dim3(kPBlocks), dim3(256), 0, s, d);
+        const uint64_t units = (uint64_t)pg.P * pg.W;  // at most this many candidate words
+        const unsigned upb = 256 / (pg.Tpad >= 64 ? 16 : (pg.Tpad >> 2));
+        hipLaunchKernelGGL(k_admit_particles, dim3(grid_for(units, upb * 4, 2048)), dim3(256), 0, s, d);
     } else {
         hipLaunchKernelGGL(k_admit_particles_short, dim3(grid_for(pg.P, 256, 4096)), dim3(256), 0, s,
                            d);
@@ -1315,7 +1483,9 @@ void launch_round(const Dev& d, uint32_t round, uint32_t nwork_host, hipStream_t
     }
     const uint64_t Q = (uint64_t)d.pg.P * d.pg.Tpad;
     hipLaunchKernelGGL(k_round_pull, dim3(grid_for(Q / 4, 256, 2048)), dim3(256), 0, s, d, par);
-    const uint64_t nclose = (uint64_t)d.g.NT > (uint64_t)d.pg.P ? (uint64_t)d.g.NT : (uint64_t)d.pg.P;
+    // one thread per pdirty word (a wave takes 64), and enough to clear the tile flags
+    const uint64_t nw32 = (uint64_t)(d.pg.P + 31) / 32;
+    const uint64_t nclose = (uint64_t)d.g.NT > nw32 ? (uint64_t)d.g.NT : nw32;
     hipLaunchKernelGGL(k_round_close, dim3(grid_for(nclose, 256, 2048)), dim3(256), 0, s, d, par);
 }
 

@@ -8,6 +8,11 @@ namespace mf4d {
 
 constexpr uint32_t kNoVoxel = 0xFFFFFFFFu;
 constexpr int kBarWords = 64 + 32 * 8;  // grid-barrier counters (top, flag, 8 subs), one line each
+constexpr int kPBlocks = 1024;          // blocks of the candidate-particle passes
+// Statistics summed by many blocks go to per-block slots (distinct addresses)
+// and are folded into stat64 once, instead of one same-address atomic each.
+constexpr int kSlots = 1024;
+enum SlotStat : int { SL_PART_VISITS = 0, SL_MEMBERS_F = 1, SL_MEMBERS_P = 2, kSlotStats = 4 };
 
 // Bit-packed tile layout of the field labels and admissibility.
 // A tile covers 32 (x) x 8 (y) x 8 (z) x BT (t) voxel-steps.  One 32-bit word
@@ -41,7 +46,7 @@ struct PGeom {
 enum Counter : int {
     C_NWORK0 = 0,  // tiles on work list 0 (even rounds)
     C_NWORK1 = 1,  // tiles on work list 1 (odd rounds)
-    C_NDIRTYP = 2, // particles on the dirty list
+    C_NPCAND = 2,  // candidate particles of this grow (value range meets the band)
     C_NLIST = 3,   // coupled particle-steps on the flat list
     C_DROPPED = 4, // dropped seeds
     C_ERR = 5,     // set by the persistent kernel if a grid barrier timed out
@@ -78,8 +83,11 @@ struct Dev {
     unsigned long long* Ap;  // [P][W] admissibility bits
     unsigned long long* Lp;  // [P][W] label bits
     uint2* clist;            // coupled steps (flat index, voxel bit)
-    uint32_t* pdirty;        // P bits: particle on this round's dirty list
-    uint32_t* dlist;         // dirty particles
+    uint32_t* pdirty;        // P bits: particle gained a step this round (to close)
+    uint32_t* pcand;         // candidate particles of this grow, in index order
+    uint8_t* pflag;          // P: 1 if the particle is a candidate (its Ap / Lp are valid)
+    uint32_t* pblk;          // kPBlocks + 1: per-block candidate counts, then offsets
+    unsigned long long* slots;  // kSlotStats x kSlots partial sums of per-grow statistics
     uint32_t* counters;      // Counter
     unsigned long long* stat64;
     uint32_t* bar;           // grid barrier arrival counter
@@ -108,5 +116,7 @@ bool launch_rounds_persistent(const Dev& d, uint32_t round0, uint32_t max_rounds
                               hipStream_t s);
 void launch_read_field(const Dev& d, uint32_t* out, hipStream_t s);
 void launch_read_particles(const Dev& d, uint8_t* out, hipStream_t s);
+// stat64[dst] += sum of slot statistic `which`, and those slots cleared.
+void launch_fold_slots(const Dev& d, int which, int dst, hipStream_t s);
 
 }  // namespace mf4d
