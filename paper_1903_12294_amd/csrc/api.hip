@@ -100,6 +100,7 @@ struct mf4d_ctx {
     unsigned long long* Ap = nullptr;
     unsigned long long* Lp = nullptr;
     uint2* clist = nullptr;
+    uint32_t* wcnt = nullptr;       // work sub-list lengths
     uint32_t* pdirty = nullptr;
     uint32_t* pcand = nullptr;      // candidate particles of the current grow
     uint8_t* pflag = nullptr;       // P candidate flags
@@ -164,6 +165,7 @@ void free_field(mf4d_ctx* c) {
     dev_free(c->active);
     dev_free(c->dirty);
     dev_free(c->work);
+    dev_free(c->wcnt);
     dev_free(c->chg);
     dev_free(c->tsum);
     dev_free(c->cand);
@@ -232,6 +234,7 @@ Dev make_dev(mf4d_ctx* c) {
     d.dirty = c->dirty;
     d.chg = c->chg;
     d.work = c->work;
+    d.wcnt = c->wcnt;
     d.bins = c->bins;
     d.attr_t = c->attr_t;
     d.Ap = c->Ap;
@@ -433,6 +436,7 @@ int mf4d_load_field(mf4d_ctx* c, const float* field, int X, int Y, int Z, int T,
         return fail(MF4D_ERR_UNSUPPORTED, "grid of %llu voxel-steps (padded %llu) needs >= 2^32 bits",
                     (unsigned long long)X * Y * Z * T, (unsigned long long)g.nwords * 32ull);
     g.NT = (uint32_t)nt;
+    g.WCAP = (uint32_t)((nt + kWorkSubs - 1) / kWorkSubs);
     HIP_TRY(hipSetDevice(c->device));
     free_particles(c);
     free_field(c);
@@ -444,7 +448,8 @@ int mf4d_load_field(mf4d_ctx* c, const float* field, int X, int Y, int Z, int T,
     if (!rc) rc = dev_alloc(&c->active, (size_t)g.NT + 8);
     if (!rc) rc = dev_alloc(&c->dirty, 2 * (size_t)g.NT);
     if (!rc) rc = dev_alloc(&c->chg, 2 * (size_t)g.NT + 8);
-    if (!rc) rc = dev_alloc(&c->work, 2 * (size_t)g.NT);
+    if (!rc) rc = dev_alloc(&c->work, 2 * (size_t)kWorkSubs * g.WCAP);
+    if (!rc) rc = dev_alloc(&c->wcnt, 2 * (size_t)kWorkSubs * kWcntStride);
     if (!rc) rc = dev_alloc(&c->tsum, (size_t)g.NT);
     if (!rc) rc = dev_alloc(&c->cand, (size_t)g.NT);
     const BrickDims bd{T, (Z + 7) / 8, (Y + 7) / 8, (X + 7) / 8};

@@ -206,8 +206,9 @@ __device__ __forceinline__ uint32_t block_append256(uint32_t n, uint32_t* counte
 // Put a tile on the work list of round parity `par` (once per round).
 __device__ __forceinline__ void schedule(const Dev& d, uint32_t tile, int par) {
     if (atomicExch(&d.dirty[par * d.g.NT + tile], 1u) == 0u) {
-        const uint32_t k = atomicAdd(&d.counters[C_NWORK0 + par], 1u);
-        d.work[par * d.g.NT + k] = tile;
+        const uint32_t j = (uint32_t)(par * kWorkSubs) + (tile & (kWorkSubs - 1));
+        const uint32_t k = atomicAdd(&d.wcnt[j * kWcntStride], 1u);
+        d.work[(size_t)j * d.g.WCAP + k] = tile;
     }
 }
 
@@ -655,6 +656,7 @@ __global__ void k_reset(Dev d) {
     if (tid < S_NSTAT) d.stat64[tid] = 0;
     for (uint64_t i = tid; i < (uint64_t)kBarWords; i += stride) d.bar[i] = 0;
     for (uint64_t i = tid; i < (uint64_t)kSlotStats * kSlots; i += stride) d.slots[i] = 0ull;
+    for (uint64_t i = tid; i < 2ull * kWorkSubs; i += stride) d.wcnt[i * kWcntStride] = 0u;
 }
 
 // Load: bin every particle-step into the voxel covering it and transpose the
@@ -1158,21 +1160,47 @@ __global__ void k_seeds(Dev d, const int32_t* __restrict__ seeds, int64_t S) {
     }
 }
 
+// Sweep every tile on the work list of parity `par` (its kWorkSubs sub-lists
+// read as one list: lane j holds sub-list j's length and prefix, so a wave
+// finds the sub-list of flat index w with one ballot).  Returns the list's
+// length (the same in every lane).
+template <int BT>
+__device__ uint32_t sweep_phase(const Dev& d, int par, uint32_t wave0, uint32_t nwaves) {
+    const int lane = lane_id();
+    const uint32_t cj = load_relaxed(&d.wcnt[(par * kWorkSubs + lane) * kWcntStride]);
+    uint32_t total;
+    const uint32_t ex = wave_excl_scan(cj, total);
+    for (uint32_t w = wave0; w < total; w += nwaves) {
+        const uint32_t j = (uint32_t)__popcll(__ballot(ex + cj <= w));  // sub-lists wholly before w
+        const uint32_t k = w - (uint32_t)__shfl((int)ex, (int)j);
+        sweep_tile<BT>(d, d.work[(size_t)(par * kWorkSubs + j) * d.g.WCAP + k], par);
+    }
+    return total;
+}
+
+// Sum the sub-list lengths of parity `par` into the host-visible counter.
+__global__ void k_work_total(Dev d, int par) {
+    uint32_t total;
+    wave_excl_scan(d.wcnt[(par * kWorkSubs + lane_id()) * kWcntStride], total);
+    if (threadIdx.x == 0) d.counters[C_NWORK0 + par] = total;
+}
+
 // ---- one round as three launches ----
 
 template <int BT>
 __global__ __launch_bounds__(256) void k_round_sweep(Dev d, int par) {
-    const uint32_t nwork = d.counters[C_NWORK0 + par];
     const uint32_t wave0 = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    for (uint32_t w = wave0; w < nwork; w += nwaves) sweep_tile<BT>(d, d.work[par * d.g.NT + w], par);
+    const uint32_t nwork = sweep_phase<BT>(d, par, wave0, nwaves);
     // every listed tile is swept once: the visit count is the list length
     if (blockIdx.x == 0 && threadIdx.x == 0 && nwork)
         atomicAdd(&d.stat64[S_TILE_VISITS], (unsigned long long)nwork);
 }
 
 __global__ __launch_bounds__(256) void k_round_pull(Dev d, int par) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) d.counters[C_NWORK0 + par] = 0;
+    // the swept list is empty again (its dirty flags were cleared by the sweeps)
+    if (blockIdx.x == 0 && threadIdx.x < (unsigned)kWorkSubs)
+        d.wcnt[(par * kWorkSubs + threadIdx.x) * kWcntStride] = 0u;
     pull_entries(d, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x,
                  d.counters[C_NLIST], par);
 }
@@ -1206,16 +1234,21 @@ __global__ __launch_bounds__(256) void k_rounds(Dev d, uint32_t round0, uint32_t
     if (threadIdx.x == 0) s_cnt = 0;
     uint32_t r = round0;
     uint32_t visits = 0, closed = 0;
+    uint32_t nwork = 0;
     while (true) {
         const int par = r & 1;
-        const uint32_t nwork = load_relaxed(&d.counters[C_NWORK0 + par]);
+        {
+            uint32_t total;
+            wave_excl_scan(load_relaxed(&d.wcnt[(par * kWorkSubs + lane_id()) * kWcntStride]), total);
+            nwork = total;  // the same in every thread
+        }
         if (nwork == 0 || (max_rounds && r - round0 >= max_rounds)) break;
         // sweep
-        for (uint32_t w = wave0; w < nwork; w += nwaves) sweep_tile<BT>(d, d.work[par * d.g.NT + w], par);
-        visits += nwork;  // the same in every thread; only thread 0 records it
+        sweep_phase<BT>(d, par, wave0, nwaves);
+        visits += nwork;  // only thread 0 records it
         if (!grid_sync(d, epoch)) break;
         // pull
-        if (tid == 0) store_relaxed(&d.counters[C_NWORK0 + par], 0u);
+        if (tid < (unsigned)kWorkSubs) store_relaxed(&d.wcnt[(par * kWorkSubs + tid) * kWcntStride], 0u);
         if (parts) pull_entries(d, tid, nthreads, load_relaxed(&d.counters[C_NLIST]), par);
         if (!grid_sync(d, epoch)) break;
         // close and push
@@ -1229,7 +1262,10 @@ __global__ __launch_bounds__(256) void k_rounds(Dev d, uint32_t round0, uint32_t
     __syncthreads();
     if (threadIdx.x == 0) slot_add(d, SL_PART_VISITS, s_cnt);
     if (tid == 0 && visits) atomicAdd(&d.stat64[S_TILE_VISITS], (unsigned long long)visits);
-    if (tid == 0) store_relaxed(&d.counters[C_ROUNDS], r - round0);
+    if (tid == 0) {
+        store_relaxed(&d.counters[C_ROUNDS], r - round0);
+        store_relaxed(&d.counters[C_NWORK0 + (r & 1)], nwork);  // what remains (0 when converged)
+    }
 }
 
 // ---- read-out ----
@@ -1469,8 +1505,9 @@ void launch_admit_particles(const Dev& d, hipStream_t s) {
 }
 
 void launch_seeds(const Dev& d, const int32_t* seeds, int64_t S, hipStream_t s) {
-    if (S == 0) return;
-    hipLaunchKernelGGL(k_seeds, dim3(grid_for(S, 256, 1u << 20)), dim3(256), 0, s, d, seeds, S);
+    if (S > 0)
+        hipLaunchKernelGGL(k_seeds, dim3(grid_for(S, 256, 1u << 20)), dim3(256), 0, s, d, seeds, S);
+    hipLaunchKernelGGL(k_work_total, dim3(1), dim3(64), 0, s, d, 0);
 }
 
 void launch_round(const Dev& d, uint32_t round, uint32_t nwork_host, hipStream_t s) {
@@ -1487,6 +1524,7 @@ void launch_round(const Dev& d, uint32_t round, uint32_t nwork_host, hipStream_t
     const uint64_t nw32 = (uint64_t)(d.pg.P + 31) / 32;
     const uint64_t nclose = (uint64_t)d.g.NT > nw32 ? (uint64_t)d.g.NT : nw32;
     hipLaunchKernelGGL(k_round_close, dim3(grid_for(nclose, 256, 2048)), dim3(256), 0, s, d, par);
+    hipLaunchKernelGGL(k_work_total, dim3(1), dim3(64), 0, s, d, par ^ 1);
 }
 
 bool launch_rounds_persistent(const Dev& d, uint32_t round0, uint32_t max_rounds, int device,

@@ -9,6 +9,12 @@ namespace mf4d {
 constexpr uint32_t kNoVoxel = 0xFFFFFFFFu;
 constexpr int kBarWords = 64 + 32 * 8;  // grid-barrier counters (top, flag, 8 subs), one line each
 constexpr int kPBlocks = 1024;          // blocks of the candidate-particle passes
+// The tile work list of each round parity is split into kWorkSubs sub-lists
+// (tile % kWorkSubs), each with its own counter on its own 128-byte line:
+// appends to one counter from every wave serialise (~11 ns each), spread over
+// 64 counters they do not.
+constexpr int kWorkSubs = 64;
+constexpr int kWcntStride = 32;  // words between sub-list counters
 // Statistics summed by many blocks go to per-block slots (distinct addresses)
 // and are folded into stat64 once, instead of one same-address atomic each.
 constexpr int kSlots = 1024;
@@ -28,6 +34,7 @@ struct Geom {
     uint32_t NT;            // number of tiles
     uint32_t WPT;           // words per tile = 64 * BT
     uint64_t nwords;        // words in a padded bit array = NT * WPT
+    uint32_t WCAP;          // capacity of one work sub-list = ceil(NT / kWorkSubs)
 };
 
 // Particle-step layout: particle-major rows of Tpad steps (Tpad = next power
@@ -44,8 +51,8 @@ struct PGeom {
 
 // Counters kept in one small device array.
 enum Counter : int {
-    C_NWORK0 = 0,  // tiles on work list 0 (even rounds)
-    C_NWORK1 = 1,  // tiles on work list 1 (odd rounds)
+    C_NWORK0 = 0,  // tiles on work list 0 (even rounds), summed from its sub-lists for the host
+    C_NWORK1 = 1,  // tiles on work list 1 (odd rounds), likewise
     C_NPCAND = 2,  // candidate particles of this grow (value range meets the band)
     C_NLIST = 3,   // coupled particle-steps on the flat list
     C_DROPPED = 4, // dropped seeds
@@ -77,7 +84,8 @@ struct Dev {
                              // 2 deferred (labels cleared, admissibility not tested yet)
     uint32_t* dirty;         // 2 x NT: tile scheduled for round parity 0 / 1
     uint8_t* chg;            // 2 x NT: tile's members changed since its last pull
-    uint32_t* work;          // 2 x NT: work lists of round parity 0 / 1
+    uint32_t* work;          // [2][kWorkSubs][WCAP]: work sub-lists of round parity 0 / 1
+    uint32_t* wcnt;          // [2][kWorkSubs] sub-list lengths, kWcntStride words apart
     const uint32_t* bins;    // [P][Tpad] voxel bit of each particle-step, or kNoVoxel
     const float* attr_t;     // [P][Tpad] particle values (NaN padding)
     unsigned long long* Ap;  // [P][W] admissibility bits
