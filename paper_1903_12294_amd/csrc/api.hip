@@ -280,22 +280,30 @@ int run_rounds(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
         }
         (void)hipGetLastError();
     }
+    // Launches: rounds are queued kRoundChunk at a time (a round with an empty
+    // work list is a no-op on the device), and the host reads the counters once
+    // per chunk.  C_ROUNDS counts the rounds that had work.
+    constexpr int64_t kRoundChunk = 4;
+    launch_fill_u32(c->counters + C_ROUNDS, 0, 1, c->stream);
     int64_t r = 0;
     while (true) {
-        int rc = read_counters(c);
-        if (rc) return rc;
-        const uint32_t nwork = c->h_counters[C_NWORK0 + (c->round & 1)];
-        if (nwork == 0) {
-            c->state = 1;
-            break;
-        }
-        if (cap && r >= cap) {
+        int64_t chunk = kRoundChunk;
+        if (cap && cap - r < chunk) chunk = cap - r;
+        if (chunk <= 0) {  // cap reached with work left
             c->state = 2;
             break;
         }
-        launch_round(d, c->round, nwork, c->stream);
-        ++c->round;
-        ++r;
+        for (int64_t k = 0; k < chunk; ++k) launch_round(d, (uint32_t)(c->round + k), c->stream);
+        launch_work_total(d, (int)((c->round + chunk) & 1), c->stream);
+        int rc = read_counters(c);
+        if (rc) return rc;
+        const int64_t done = (int64_t)c->h_counters[C_ROUNDS] - r;
+        c->round += (uint32_t)done;
+        r += done;
+        if (done < chunk || c->h_counters[C_NWORK0 + (c->round & 1)] == 0) {
+            c->state = 1;
+            break;
+        }
     }
     *rounds_done = r;
     return MF4D_OK;

@@ -1192,12 +1192,18 @@ __global__ __launch_bounds__(256) void k_round_sweep(Dev d, int par) {
     const uint32_t wave0 = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
     const uint32_t nwork = sweep_phase<BT>(d, par, wave0, nwaves);
-    // every listed tile is swept once: the visit count is the list length
-    if (blockIdx.x == 0 && threadIdx.x == 0 && nwork)
-        atomicAdd(&d.stat64[S_TILE_VISITS], (unsigned long long)nwork);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        d.counters[C_RACT] = nwork ? 1u : 0u;  // pull and close of this round read it
+        if (nwork) {
+            d.counters[C_ROUNDS] += 1u;
+            // every listed tile is swept once: the visit count is the list length
+            atomicAdd(&d.stat64[S_TILE_VISITS], (unsigned long long)nwork);
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_round_pull(Dev d, int par) {
+    if (!d.counters[C_RACT]) return;
     // the swept list is empty again (its dirty flags were cleared by the sweeps)
     if (blockIdx.x == 0 && threadIdx.x < (unsigned)kWorkSubs)
         d.wcnt[(par * kWorkSubs + threadIdx.x) * kWcntStride] = 0u;
@@ -1208,6 +1214,7 @@ __global__ __launch_bounds__(256) void k_round_pull(Dev d, int par) {
 __global__ __launch_bounds__(256) void k_round_close(Dev d, int par) {
     __shared__ uint32_t s_list[4 * 64];
     __shared__ uint32_t s_cnt;
+    if (!d.counters[C_RACT]) return;
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t i = tid; i < d.g.NT; i += stride) d.chg[par * d.g.NT + i] = 0;
@@ -1431,9 +1438,9 @@ bool coop_rounds(const Dev& d, uint32_t round0, uint32_t max_rounds, int device,
     Dev dd = d;
     uint32_t r0 = round0, mr = max_rounds;
     void* args[] = {&dd, &r0, &mr};
-    // Two blocks (8 waves) per CU cover a round's work list at these sizes;
-    // more blocks only add barrier arrivals.
-    const dim3 grid((unsigned)(std::min(per_cu, 2) * ncu));
+    // Up to four blocks (16 waves) per CU: enough threads for the pull and
+    // close phases; more only add barrier arrivals.
+    const dim3 grid((unsigned)(std::min(per_cu, 4) * ncu));
     return hipLaunchCooperativeKernel((const void*)k_rounds<BT>, grid, dim3(256), args, 0, s) ==
            hipSuccess;
 }
@@ -1507,12 +1514,17 @@ void launch_admit_particles(const Dev& d, hipStream_t s) {
 void launch_seeds(const Dev& d, const int32_t* seeds, int64_t S, hipStream_t s) {
     if (S > 0)
         hipLaunchKernelGGL(k_seeds, dim3(grid_for(S, 256, 1u << 20)), dim3(256), 0, s, d, seeds, S);
-    hipLaunchKernelGGL(k_work_total, dim3(1), dim3(64), 0, s, d, 0);
 }
 
-void launch_round(const Dev& d, uint32_t round, uint32_t nwork_host, hipStream_t s) {
+void launch_work_total(const Dev& d, int par, hipStream_t s) {
+    hipLaunchKernelGGL(k_work_total, dim3(1), dim3(64), 0, s, d, par);
+}
+
+void launch_round(const Dev& d, uint32_t round, hipStream_t s) {
     const int par = round & 1;
-    const unsigned blocks = grid_for((uint64_t)nwork_host * 64, 256, 8192);
+    // one wave per listed tile, up to 8192 waves (the list length is on the device)
+    const uint64_t waves = d.g.NT < 8192u ? d.g.NT : 8192u;
+    const unsigned blocks = grid_for(waves * 64, 256, 2048);
     switch (d.g.BT) {
         case 4: hipLaunchKernelGGL(k_round_sweep<4>, dim3(blocks), dim3(256), 0, s, d, par); break;
         case 8: hipLaunchKernelGGL(k_round_sweep<8>, dim3(blocks), dim3(256), 0, s, d, par); break;
@@ -1524,7 +1536,6 @@ void launch_round(const Dev& d, uint32_t round, uint32_t nwork_host, hipStream_t
     const uint64_t nw32 = (uint64_t)(d.pg.P + 31) / 32;
     const uint64_t nclose = (uint64_t)d.g.NT > nw32 ? (uint64_t)d.g.NT : nw32;
     hipLaunchKernelGGL(k_round_close, dim3(grid_for(nclose, 256, 2048)), dim3(256), 0, s, d, par);
-    hipLaunchKernelGGL(k_work_total, dim3(1), dim3(64), 0, s, d, par ^ 1);
 }
 
 bool launch_rounds_persistent(const Dev& d, uint32_t round0, uint32_t max_rounds, int device,

@@ -59,7 +59,8 @@ enum Counter : int {
     C_ERR = 5,     // set by the persistent kernel if a grid barrier timed out
     C_ROUNDS = 6,  // rounds completed by the persistent kernel
     C_NCAND = 7,   // candidate tiles
-    C_NCOUNTERS = 8
+    C_RACT = 8,    // launched rounds: 1 if the current round has work (set by its sweep)
+    C_NCOUNTERS = 16
 };
 
 enum Stat64 : int {
@@ -117,8 +118,11 @@ void launch_particle_summaries(const PGeom& pg, const float* attr_t, float2* psu
 void launch_admit_field(const Dev& d, hipStream_t s);
 void launch_admit_particles(const Dev& d, hipStream_t s);
 void launch_seeds(const Dev& d, const int32_t* seeds, int64_t S, hipStream_t s);
-// One round as three launches (sweep, pull, close/push).
-void launch_round(const Dev& d, uint32_t round, uint32_t nwork_host, hipStream_t s);
+// One round as three launches (sweep, pull, close/push); a round whose work
+// list is empty does nothing, so rounds can be queued ahead of the host.
+void launch_round(const Dev& d, uint32_t round, hipStream_t s);
+// Sum of the work sub-list lengths of parity `par` into counters[C_NWORK0 + par].
+void launch_work_total(const Dev& d, int par, hipStream_t s);
 // Rounds in one cooperative persistent launch; false if it cannot be launched.
 bool launch_rounds_persistent(const Dev& d, uint32_t round0, uint32_t max_rounds, int device,
                               hipStream_t s);
