@@ -252,6 +252,32 @@ __device__ void mark_voxel(const Dev& d, uint32_t b, int par) {
 // passes along t.  Neighbour-tile words enter as fixed halos; when a face of
 // this tile gains bits, the tile across that face is scheduled for the next
 // round.  Every lane of the wave must call it.
+// Complete fill along one lane axis of a tile slice: lanes pos = 0..7 (lane
+// stride `stride`) hold the 32-bit rows of a line of 8; a bit spreads through
+// consecutive admissible rows in both directions.  Segmented Hillis-Steele
+// scans over (reached, all-admissible) pairs, up then down, 3 steps each.
+__device__ __forceinline__ uint32_t line_fill8(uint32_t s, uint32_t a, int pos, int stride) {
+    uint32_t P = a;
+#pragma unroll
+    for (int d = 1; d < 8; d <<= 1) {
+        const uint32_t sp = __shfl_up(s, d * stride), pp = __shfl_up(P, d * stride);
+        if (pos >= d) {
+            s |= P & sp;
+            P &= pp;
+        }
+    }
+    P = a;
+#pragma unroll
+    for (int d = 1; d < 8; d <<= 1) {
+        const uint32_t sn = __shfl_down(s, d * stride), pn = __shfl_down(P, d * stride);
+        if (pos + d <= 7) {
+            s |= P & sn;
+            P &= pn;
+        }
+    }
+    return s;
+}
+
 template <int BT>
 __device__ void sweep_tile(const Dev& d, uint32_t tile, int par) {
     const Geom& g = d.g;
@@ -310,12 +336,12 @@ __device__ void sweep_tile(const Dev& d, uint32_t tile, int par) {
         uint32_t s[BT];
 #pragma unroll
         for (int t = 0; t < BT; ++t) {
-            const uint32_t v = l[t];
-            const uint32_t ym = __shfl_up(v, 1), yp = __shfl_down(v, 1);
-            const uint32_t zm = __shfl_up(v, 8), zp = __shfl_down(v, 8);
-            uint32_t nb = v | (v << 1) | (v >> 1) | xin[t] | yh[t] | zh[t];
-            nb |= (yl > 0 ? ym : 0u) | (yl < 7 ? yp : 0u) | (zl > 0 ? zm : 0u) | (zl < 7 ? zp : 0u);
-            s[t] = fill_runs32(nb & a[t], a[t]);
+            // complete fills along x, y and z of this t-slice (halo bits seed the
+            // edge rows), then x again for runs the y/z fills opened
+            uint32_t v = fill_runs32((l[t] | xin[t] | yh[t] | zh[t]) & a[t], a[t]);
+            v = line_fill8(v, a[t], yl, 1);
+            v = line_fill8(v, a[t], zl, 8);
+            s[t] = fill_runs32(v, a[t]);
         }
         s[0] |= fill_runs32(tm & a[0], a[0]);
 #pragma unroll
@@ -1438,9 +1464,9 @@ bool coop_rounds(const Dev& d, uint32_t round0, uint32_t max_rounds, int device,
     Dev dd = d;
     uint32_t r0 = round0, mr = max_rounds;
     void* args[] = {&dd, &r0, &mr};
-    // Up to four blocks (16 waves) per CU: enough threads for the pull and
-    // close phases; more only add barrier arrivals.
-    const dim3 grid((unsigned)(std::min(per_cu, 4) * ncu));
+    // Two blocks (8 waves) per CU: measured faster than four at 256^3 x 64,
+    // where more blocks only add barrier arrivals.
+    const dim3 grid((unsigned)(std::min(per_cu, 2) * ncu));
     return hipLaunchCooperativeKernel((const void*)k_rounds<BT>, grid, dim3(256), args, 0, s) ==
            hipSuccess;
 }
