@@ -203,12 +203,33 @@ __device__ __forceinline__ uint32_t block_append256(uint32_t n, uint32_t* counte
 // ---------------------------------------------------------------------------
 // scheduling
 
-// Put a tile on the work list of round parity `par` (once per round).
-__device__ __forceinline__ void schedule(const Dev& d, uint32_t tile, int par) {
-    if (atomicExch(&d.dirty[par * d.g.NT + tile], 1u) == 0u) {
-        const uint32_t j = (uint32_t)(par * kWorkSubs) + (tile & (kWorkSubs - 1));
-        const uint32_t k = atomicAdd(&d.wcnt[j * kWcntStride], 1u);
-        d.work[(size_t)j * d.g.WCAP + k] = tile;
+// Put up to 8 tiles on the work list of round parity `par` (each once per
+// round), skipping tiles with no admissible voxel-step.  Each step is issued
+// for all tiles before the next (flag loads, then exchanges, then appends), so
+// the round trips of the tiles overlap instead of queueing.  A flag already
+// seen set needs no exchange: no one clears it during this phase.
+__device__ __forceinline__ void schedule_batch(const Dev& d, const uint32_t* nb, int k, int par) {
+    uint32_t* dirty = d.dirty + (size_t)par * d.g.NT;
+    uint32_t cur[8];
+    uint8_t act[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        act[i] = 0;
+        cur[i] = 1u;
+        if (i < k) {
+            act[i] = d.active[nb[i]];
+            cur[i] = dirty[nb[i]];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) cur[i] = (i < k && act[i] && cur[i] == 0u) ? atomicExch(&dirty[nb[i]], 1u) : 1u;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        if (cur[i] == 0u) {
+            const uint32_t j = (uint32_t)(par * kWorkSubs) + (nb[i] & (kWorkSubs - 1));
+            const uint32_t slot = atomicAdd(&d.wcnt[j * kWcntStride], 1u);
+            d.work[(size_t)j * d.g.WCAP + slot] = nb[i];
+        }
     }
 }
 
@@ -223,23 +244,22 @@ __device__ void mark_voxel(const Dev& d, uint32_t b, int par) {
     const uint32_t tile = word >> (6 + g.logBT);
     const uint32_t wi = word & (g.WPT - 1);
     const int yl = wi & 7, zl = (wi >> 3) & 7, tl = wi >> 6;
-    schedule(d, tile, par);
     d.chg[par * g.NT + tile] = 1;
     int tx, ty, tz, tt;
     tile_coords(g, tile, tx, ty, tz, tt);
     const uint32_t sy = g.NXt, sz = g.NXt * g.NYt, st = sz * g.NZt;
     uint32_t nb[8];
     int k = 0;
+    nb[k++] = tile;  // active: it holds an admissible voxel-step
     if (xb == 0 && tx > 0) nb[k++] = tile - 1;
-    if (xb == 31 && tx + 1 < g.NXt) nb[k++] = tile + 1;
+    else if (xb == 31 && tx + 1 < g.NXt) nb[k++] = tile + 1;
     if (yl == 0 && ty > 0) nb[k++] = tile - sy;
-    if (yl == 7 && ty + 1 < g.NYt) nb[k++] = tile + sy;
+    else if (yl == 7 && ty + 1 < g.NYt) nb[k++] = tile + sy;
     if (zl == 0 && tz > 0) nb[k++] = tile - sz;
-    if (zl == 7 && tz + 1 < g.NZt) nb[k++] = tile + sz;
+    else if (zl == 7 && tz + 1 < g.NZt) nb[k++] = tile + sz;
     if (tl == 0 && tt > 0) nb[k++] = tile - st;
-    if (tl == g.BT - 1 && tt + 1 < g.NTt) nb[k++] = tile + st;
-    for (int i = 0; i < k; ++i)
-        if (d.active[nb[i]]) schedule(d, nb[i], par);
+    else if (tl == g.BT - 1 && tt + 1 < g.NTt) nb[k++] = tile + st;
+    schedule_batch(d, nb, k, par);
 }
 
 // ---------------------------------------------------------------------------
@@ -385,8 +405,7 @@ __device__ void sweep_tile(const Dev& d, uint32_t tile, int par) {
             if (fzp && tz + 1 < g.NZt) nb[k++] = tile + sz;
             if (ftm && tt > 0) nb[k++] = tile - st;
             if (ftp && tt + 1 < g.NTt) nb[k++] = tile + st;
-            for (int i = 0; i < k; ++i)
-                if (d.active[nb[i]]) schedule(d, nb[i], nx);
+            schedule_batch(d, nb, k, nx);
         }
     }
 }
