@@ -272,32 +272,6 @@ __device__ void mark_voxel(const Dev& d, uint32_t b, int par) {
 // passes along t.  Neighbour-tile words enter as fixed halos; when a face of
 // this tile gains bits, the tile across that face is scheduled for the next
 // round.  Every lane of the wave must call it.
-// Complete fill along one lane axis of a tile slice: lanes pos = 0..7 (lane
-// stride `stride`) hold the 32-bit rows of a line of 8; a bit spreads through
-// consecutive admissible rows in both directions.  Segmented Hillis-Steele
-// scans over (reached, all-admissible) pairs, up then down, 3 steps each.
-__device__ __forceinline__ uint32_t line_fill8(uint32_t s, uint32_t a, int pos, int stride) {
-    uint32_t P = a;
-#pragma unroll
-    for (int d = 1; d < 8; d <<= 1) {
-        const uint32_t sp = __shfl_up(s, d * stride), pp = __shfl_up(P, d * stride);
-        if (pos >= d) {
-            s |= P & sp;
-            P &= pp;
-        }
-    }
-    P = a;
-#pragma unroll
-    for (int d = 1; d < 8; d <<= 1) {
-        const uint32_t sn = __shfl_down(s, d * stride), pn = __shfl_down(P, d * stride);
-        if (pos + d <= 7) {
-            s |= P & sn;
-            P &= pn;
-        }
-    }
-    return s;
-}
-
 template <int BT>
 __device__ void sweep_tile(const Dev& d, uint32_t tile, int par) {
     const Geom& g = d.g;
@@ -310,7 +284,51 @@ __device__ void sweep_tile(const Dev& d, uint32_t tile, int par) {
     uint32_t* Ab = d.Af + (size_t)tile * (64 * BT);
     uint32_t* Lb = d.Lf + (size_t)tile * (64 * BT);
     uint32_t a[BT], l[BT], l0[BT], xin[BT], yh[BT], zh[BT];
-    if (d.active[tile] == 2) {
+    // Every load of the visit is issued at once (one round trip): the activity
+    // of the tile and its neighbours, its admissibility and label words, and
+    // the halo words of every neighbour inside the grid.  Halos of inactive
+    // neighbours (stale labels, zero by definition) are masked afterwards; a
+    // neighbour outside the grid reads this tile's own words, masked too.
+    const bool hxm = tx > 0, hxp = tx + 1 < g.NXt;
+    const bool hym = yl == 0 && ty > 0, hyp = yl == 7 && ty + 1 < g.NYt;
+    const bool hzm = zl == 0 && tz > 0, hzp = zl == 7 && tz + 1 < g.NZt;
+    const bool htm = tt > 0, htp = tt + 1 < g.NTt;
+    const size_t w = 64 * BT;
+    const uint32_t* Lxm = hxm ? Lb - w : Lb;
+    const uint32_t* Lxp = hxp ? Lb + w : Lb;
+    const uint32_t* Ly = hym ? Lb - (size_t)sy * w : (hyp ? Lb + (size_t)sy * w : Lb);
+    const int yoff = hym ? 7 : (hyp ? -7 : 0);
+    const uint32_t* Lz = hzm ? Lb - (size_t)sz * w : (hzp ? Lb + (size_t)sz * w : Lb);
+    const int zoff = hzm ? 56 : (hzp ? -56 : 0);
+    const uint32_t* Ltm = htm ? Lb - (size_t)st * w : Lb;
+    const uint32_t* Ltp = htp ? Lb + (size_t)st * w : Lb;
+    const uint8_t act = d.active[tile];
+    const uint8_t axm = hxm ? d.active[tile - 1] : 0, axp = hxp ? d.active[tile + 1] : 0;
+    const uint8_t ay = hym ? d.active[tile - sy] : (hyp ? d.active[tile + sy] : 0);
+    const uint8_t az = hzm ? d.active[tile - sz] : (hzp ? d.active[tile + sz] : 0);
+    const uint8_t atm = htm ? d.active[tile - st] : 0, atp = htp ? d.active[tile + st] : 0;
+    uint32_t xm[BT], xp[BT];
+#pragma unroll
+    for (int t = 0; t < BT; ++t) {
+        a[t] = Ab[t * 64 + lane];
+        l[t] = Lb[t * 64 + lane];
+        xm[t] = Lxm[t * 64 + lane];
+        xp[t] = Lxp[t * 64 + lane];
+        yh[t] = Ly[t * 64 + lane + yoff];
+        zh[t] = Lz[t * 64 + lane + zoff];
+    }
+    uint32_t tm = Ltm[(BT - 1) * 64 + lane];
+    uint32_t tp = Ltp[lane];
+#pragma unroll
+    for (int t = 0; t < BT; ++t) {
+        xin[t] = (axm ? (xm[t] >> 31) : 0u) | (axp ? (xp[t] << 31) : 0u);
+        yh[t] = ay ? yh[t] : 0u;
+        zh[t] = az ? zh[t] : 0u;
+        l0[t] = l[t];
+    }
+    tm = atm ? tm : 0u;
+    tp = atp ? tp : 0u;
+    if (act == 2) {
         // deferred tile: test its admissibility now
         uint32_t any = 0;
 #pragma unroll
@@ -324,44 +342,20 @@ __device__ void sweep_tile(const Dev& d, uint32_t tile, int par) {
             d.active[tile] = has ? 1 : 0;
             atomicAdd(&d.stat64[S_DEFERRED_READ], 1ull);
         }
-    } else {
-#pragma unroll
-        for (int t = 0; t < BT; ++t) a[t] = Ab[t * 64 + lane];
     }
-#pragma unroll
-    for (int t = 0; t < BT; ++t) l[t] = Lb[t * 64 + lane];
-    // halos come only from active neighbours: an inactive tile's labels are
-    // stale (never cleared this grow) and all zero by definition
-    const uint32_t* Lxm = tx > 0 && d.active[tile - 1] ? Lb - 64 * BT : nullptr;
-    const uint32_t* Lxp = tx + 1 < g.NXt && d.active[tile + 1] ? Lb + 64 * BT : nullptr;
-    const uint32_t* Ly = nullptr;
-    int yoff = 0;
-    if (yl == 0 && ty > 0 && d.active[tile - sy]) { Ly = Lb - (size_t)sy * 64 * BT; yoff = 7; }
-    if (yl == 7 && ty + 1 < g.NYt && d.active[tile + sy]) { Ly = Lb + (size_t)sy * 64 * BT; yoff = -7; }
-    const uint32_t* Lz = nullptr;
-    int zoff = 0;
-    if (zl == 0 && tz > 0 && d.active[tile - sz]) { Lz = Lb - (size_t)sz * 64 * BT; zoff = 56; }
-    if (zl == 7 && tz + 1 < g.NZt && d.active[tile + sz]) { Lz = Lb + (size_t)sz * 64 * BT; zoff = -56; }
-#pragma unroll
-    for (int t = 0; t < BT; ++t) {
-        xin[t] = (Lxm ? (Lxm[t * 64 + lane] >> 31) : 0u) | (Lxp ? (Lxp[t * 64 + lane] << 31) : 0u);
-        yh[t] = Ly ? Ly[t * 64 + lane + yoff] : 0u;
-        zh[t] = Lz ? Lz[t * 64 + lane + zoff] : 0u;
-        l0[t] = l[t];
-    }
-    const uint32_t tm =
-        tt > 0 && d.active[tile - st] ? (Lb - (size_t)st * 64 * BT)[(BT - 1) * 64 + lane] : 0u;
-    const uint32_t tp = tt + 1 < g.NTt && d.active[tile + st] ? (Lb + (size_t)st * 64 * BT)[lane] : 0u;
     while (true) {
         uint32_t s[BT];
 #pragma unroll
         for (int t = 0; t < BT; ++t) {
-            // complete fills along x, y and z of this t-slice (halo bits seed the
-            // edge rows), then x again for runs the y/z fills opened
-            uint32_t v = fill_runs32((l[t] | xin[t] | yh[t] | zh[t]) & a[t], a[t]);
-            v = line_fill8(v, a[t], yl, 1);
-            v = line_fill8(v, a[t], zl, 8);
-            s[t] = fill_runs32(v, a[t]);
+            // one Jacobi step along y and z (lane shuffles; halos for edge
+            // lanes), complete along x (runs).  Measured faster than complete
+            // y/z line fills: those chain 12 dependent shuffles per word.
+            const uint32_t v = l[t];
+            const uint32_t ym = __shfl_up(v, 1), yp = __shfl_down(v, 1);
+            const uint32_t zm = __shfl_up(v, 8), zp = __shfl_down(v, 8);
+            uint32_t nb = v | xin[t] | yh[t] | zh[t];
+            nb |= (yl > 0 ? ym : 0u) | (yl < 7 ? yp : 0u) | (zl > 0 ? zm : 0u) | (zl < 7 ? zp : 0u);
+            s[t] = fill_runs32(nb & a[t], a[t]);
         }
         s[0] |= fill_runs32(tm & a[0], a[0]);
 #pragma unroll
@@ -1567,8 +1561,9 @@ void launch_work_total(const Dev& d, int par, hipStream_t s) {
 
 void launch_round(const Dev& d, uint32_t round, hipStream_t s) {
     const int par = round & 1;
-    // one wave per listed tile, up to 8192 waves (the list length is on the device)
-    const uint64_t waves = d.g.NT < 8192u ? d.g.NT : 8192u;
+    // one wave per listed tile, up to 2048 waves (8 per CU); the list length
+    // is on the device and longer lists are strided over the waves
+    const uint64_t waves = d.g.NT < 2048u ? d.g.NT : 2048u;
     const unsigned blocks = grid_for(waves * 64, 256, 2048);
     switch (d.g.BT) {
         case 4: hipLaunchKernelGGL(k_round_sweep<4>, dim3(blocks), dim3(256), 0, s, d, par); break;
