@@ -42,18 +42,41 @@ def tile_voxels(bt: int) -> int:
     return 32 * 8 * 8 * bt
 
 
-def phase_bytes(V: int, Q: int, P: int, T: int, bt: int, st: dict, admit_all: bool) -> dict:
-    """Algorithmic bytes per launch of each phase's main kernel (the minimum
-    it must move): field admissibility reads 4 B per tested voxel-step and
-    writes its admissibility and label bits; the read-out writes the canonical
-    field bits and one byte per particle-step and reads the labels of active
-    tiles and particles."""
+def visit_bytes(bt: int) -> int:
+    """Algorithmic bytes of one tile visit (a tile of 32x8x8xBT voxel-steps):
+    its label and admissibility bits (256*BT B each), the face halos it needs
+    (x: 2 x 8*BT B, y and z: 4 x 32*BT B, t: 2 x 256 B) and the label bits
+    written back (256*BT B)."""
+    return 912 * bt + 512
+
+
+def kernel_table(V: int, Q: int, bt: int, st: dict, r: dict, admit_all: bool, launch: bool) -> dict:
+    """Per kernel (or kernel group): algorithmic bytes per launch, measured
+    device time per launch (HIP events on the library's stream), launches per
+    step.  The unit counts come from the grow's statistics."""
     tv = tile_voxels(bt)
+    rounds = max(st["rounds"], 1)
     tested = V if admit_all else st["tiles_tested"] * tv
-    return {
-        "k_admit_field" if admit_all else "k_admit_tiles": int(tested * 4 + tested // 4),
-        "read_out": int(V // 8 + Q + st["active_tiles"] * tv // 8 + Q // 8),
-    }
+    rows = {}
+    rows["k_admit_field" if admit_all else "k_admit_tiles"] = (
+        int(tested * 4 + tested // 4), r["ms_admit_field"], 1)
+    rows["read-out (k_read_field_tiles + k_read_particles16)"] = (
+        int(V // 8 + Q + st["active_tiles"] * tv // 8 + Q // 8), r["ms_read"], 1)
+    sweep_b = int(st["tile_visits"] / rounds * visit_bytes(bt))
+    pull_b = int(8 * st["coupled_steps"])
+    if launch:
+        rows[f"k_round_sweep<{bt}>"] = (sweep_b, r["ms_sweep"] / rounds, rounds)
+        rows["k_round_pull"] = (pull_b, r["ms_pull"] / rounds, rounds)
+        rows["k_round_close"] = (int(st["particle_visits"] / rounds * 16), r["ms_close"] / rounds, rounds)
+    else:
+        rows[f"k_rounds<{bt}>"] = (sweep_b * rounds + pull_b * rounds, r["ms_rounds"], 1)
+    out = {}
+    for k, (b, ms, n) in rows.items():
+        gbs = b / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        out[k] = {"bytes_per_launch": b, "ms_per_launch": round(ms, 4), "launches_per_step": n,
+                  "ms_per_step": round(ms * n, 4), "achieved_GBps": round(gbs, 1),
+                  "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
 
 
 class Timer:
@@ -108,6 +131,7 @@ def run_steps(g, fmask, pmask, steps: int, warmup: int, torch):
     mean = lambda k: float(np.mean([s[k] for s in stats]))
     return dict(ms=ms, ms_admit_field=mean("ms_admit_field"), ms_admit=mean("ms_admit"),
                 ms_rounds=mean("ms_rounds"), ms_grow=mean("ms_total"),
+                ms_sweep=mean("ms_sweep"), ms_pull=mean("ms_pull"), ms_close=mean("ms_close"),
                 ms_read=float(np.mean(reads)), stats=last)
 
 
@@ -246,18 +270,16 @@ def main():
         f"tile visits {st['tile_visits']}, members {st['members_field']} / {st['members_particle']}")
 
     admit_all = choice["admit"] == "all"
-    pb = phase_bytes(V, Q, P, T, choice["tile_t"], st, admit_all)
+    launch = choice["schedule"] == "launch"
     phases = {"admit_field": r["ms_admit_field"], "admit_particles": r["ms_admit"] - r["ms_admit_field"],
               "rounds": r["ms_rounds"], "read_out": r["ms_read"]}
-    # roofline of the largest HBM-bound kernel with a live per-launch time
-    kname = "k_admit_field" if admit_all else "k_admit_tiles"
-    cands = {kname: (pb[kname], r["ms_admit_field"]), "read_out": (pb["read_out"], r["ms_read"])}
-    dom = max(cands, key=lambda k: cands[k][1])
-    b, t_ms = cands[dom]
-    achieved = b / (t_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "bytes_per_launch": b, "ms_per_launch": round(t_ms, 4)}
+    kt = kernel_table(V, Q, choice["tile_t"], st, r, admit_all, launch)
+    # the roofline object is the kernel with the most device time per step
+    dom = max(kt, key=lambda k: kt[k]["ms_per_step"])
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": kt[dom]["achieved_GBps"],
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kt[dom]["frac"], "traffic": None,
+                "bytes_per_launch": kt[dom]["bytes_per_launch"],
+                "ms_per_launch": kt[dom]["ms_per_launch"]}
 
     if args.copy_probe:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
@@ -273,7 +295,7 @@ def main():
         # eager: every sample tested each step
         g.set_admit_mode("all")
         re_ = run_steps(g, fmask, pmask, args.steps, 2, torch)
-        eb = phase_bytes(V, Q, P, T, choice["tile_t"], re_["stats"], True)["k_admit_field"]
+        eb = int(V * 4 + V // 4)
         ea = eb / (re_["ms_admit_field"] * 1e-3) / 1e9
         forms["eager"] = {"ms_per_step": round(re_["ms"], 4), "value": round(V / (re_["ms"] * 1e-3), 1),
                           "masks_equal": bool(torch.equal(fmask, ref_f) and torch.equal(pmask, ref_p)),
@@ -354,6 +376,7 @@ def main():
             "tiles_tested": st["tiles_tested"],
             "members_field": st["members_field"], "members_particle": st["members_particle"],
             "phases_ms": {k: round(v, 4) for k, v in phases.items()},
+            "kernels": kt, "coupled_steps": st["coupled_steps"],
             "ms_grow": round(r["ms_grow"], 4),
             "parity_vs_oracle": parity,
             "autotune": tune["table"] if tune else None,

@@ -99,6 +99,11 @@ typedef struct mf4d_stats {
     int64_t tiles_tested;     /* single-query grow: tiles whose admissibility was read before the rounds
                                  (every tile when admissibility is tested everywhere) */
     int64_t tiles_deferred_read; /* deferred tiles whose admissibility a sweep read */
+    double ms_sweep;          /* rounds as launches: device time of the sweep kernels (summed over
+                                 the rounds that had work; 0 for the persistent schedule) */
+    double ms_pull;           /* likewise for the pull kernels */
+    double ms_close;          /* likewise for the close/push kernels */
+    int64_t coupled_steps;    /* single-query grow: admissible particle-steps that lie in a voxel */
 } mf4d_stats;
 
 /* Library version string. */

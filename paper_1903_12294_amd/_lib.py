@@ -49,6 +49,10 @@ class Stats(ctypes.Structure):
         ("ms_total", c_double),
         ("tiles_tested", c_int64),
         ("tiles_deferred_read", c_int64),
+        ("ms_sweep", c_double),
+        ("ms_pull", c_double),
+        ("ms_close", c_double),
+        ("coupled_steps", c_int64),
     ]
 
     def as_dict(self) -> dict:

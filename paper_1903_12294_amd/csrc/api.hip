@@ -127,6 +127,8 @@ struct mf4d_ctx {
     uint32_t round = 0;  // index of the next round to run
     mf4d_stats stats{};
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t rev[4 * 4] = {};  // per launched round of a chunk: before sweep, pull, close, after
+    double ms_phase[3] = {0, 0, 0};  // sweep, pull, close of the current grow
 
     void* staging = nullptr;
     size_t staging_bytes = 0;
@@ -293,11 +295,17 @@ int run_rounds(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
             c->state = 2;
             break;
         }
-        for (int64_t k = 0; k < chunk; ++k) launch_round(d, (uint32_t)(c->round + k), c->stream);
+        for (int64_t k = 0; k < chunk; ++k) launch_round(d, (uint32_t)(c->round + k), c->stream, c->rev + 4 * k);
         launch_work_total(d, (int)((c->round + chunk) & 1), c->stream);
         int rc = read_counters(c);
         if (rc) return rc;
         const int64_t done = (int64_t)c->h_counters[C_ROUNDS] - r;
+        for (int64_t k = 0; k < done && k < chunk; ++k)
+            for (int ph = 0; ph < 3; ++ph) {
+                float ms = 0;
+                HIP_TRY(hipEventElapsedTime(&ms, c->rev[4 * k + ph], c->rev[4 * k + ph + 1]));
+                c->ms_phase[ph] += ms;
+            }
         c->round += (uint32_t)done;
         r += done;
         if (done < chunk || c->h_counters[C_NWORK0 + (c->round & 1)] == 0) {
@@ -325,6 +333,10 @@ int finish_stats(mf4d_ctx* c, mf4d_stats* out, bool fresh, int64_t rounds) {
     s.active_tiles = (int64_t)c->h_stat[S_ACTIVE_TILES];
     if (fresh) s.tiles_tested = c->admit_all ? (int64_t)c->g.NT : (int64_t)c->h_stat[S_TILES_TESTED];
     s.tiles_deferred_read = (int64_t)c->h_stat[S_DEFERRED_READ];
+    s.ms_sweep = c->ms_phase[0];
+    s.ms_pull = c->ms_phase[1];
+    s.ms_close = c->ms_phase[2];
+    if (fresh) s.coupled_steps = c->has_particles ? (int64_t)c->h_counters[C_NLIST] : 0;
     s.seeds_dropped = (int64_t)c->h_counters[C_DROPPED];
     s.members_field = -1;
     s.members_particle = c->has_particles ? -1 : 0;
@@ -383,6 +395,8 @@ int mf4d_create(mf4d_ctx** out, int device, void* hip_stream) {
         rc = fail(MF4D_ERR_OOM, "pinned host allocation failed");
     for (int i = 0; !rc && i < 4; ++i)
         if (hipEventCreate(&c->ev[i]) != hipSuccess) rc = fail(MF4D_ERR_HIP, "hipEventCreate failed");
+    for (int i = 0; !rc && i < 16; ++i)
+        if (hipEventCreate(&c->rev[i]) != hipSuccess) rc = fail(MF4D_ERR_HIP, "hipEventCreate failed");
     if (rc) {
         mf4d_destroy(c);
         return rc;
@@ -411,6 +425,8 @@ void mf4d_destroy(mf4d_ctx* c) {
     if (c->h_stat) (void)hipHostFree(c->h_stat);
     for (int i = 0; i < 4; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    for (int i = 0; i < 16; ++i)
+        if (c->rev[i]) (void)hipEventDestroy(c->rev[i]);
     delete c;
 }
 
@@ -674,6 +690,7 @@ int mf4d_grow(mf4d_ctx* c, mf4d_stats* out) {
     const Dev d = make_dev(c);
     c->state = 0;
     c->round = 0;
+    c->ms_phase[0] = c->ms_phase[1] = c->ms_phase[2] = 0;
     launch_reset(d, s);
     HIP_TRY(hipEventRecord(c->ev[0], s));
     Dev dp = d;

@@ -1559,7 +1559,8 @@ void launch_work_total(const Dev& d, int par, hipStream_t s) {
     hipLaunchKernelGGL(k_work_total, dim3(1), dim3(64), 0, s, d, par);
 }
 
-void launch_round(const Dev& d, uint32_t round, hipStream_t s) {
+void launch_round(const Dev& d, uint32_t round, hipStream_t s, hipEvent_t* ev) {
+    if (ev) (void)hipEventRecord(ev[0], s);
     const int par = round & 1;
     // one wave per listed tile, up to 2048 waves (8 per CU); the list length
     // is on the device and longer lists are strided over the waves
@@ -1571,11 +1572,14 @@ void launch_round(const Dev& d, uint32_t round, hipStream_t s) {
         default: hipLaunchKernelGGL(k_round_sweep<16>, dim3(blocks), dim3(256), 0, s, d, par); break;
     }
     const uint64_t Q = (uint64_t)d.pg.P * d.pg.Tpad;
+    if (ev) (void)hipEventRecord(ev[1], s);
     hipLaunchKernelGGL(k_round_pull, dim3(grid_for(Q / 4, 256, 2048)), dim3(256), 0, s, d, par);
+    if (ev) (void)hipEventRecord(ev[2], s);
     // one thread per pdirty word (a wave takes 64), and enough to clear the tile flags
     const uint64_t nw32 = (uint64_t)(d.pg.P + 31) / 32;
     const uint64_t nclose = (uint64_t)d.g.NT > nw32 ? (uint64_t)d.g.NT : nw32;
     hipLaunchKernelGGL(k_round_close, dim3(grid_for(nclose, 256, 2048)), dim3(256), 0, s, d, par);
+    if (ev) (void)hipEventRecord(ev[3], s);
 }
 
 bool launch_rounds_persistent(const Dev& d, uint32_t round0, uint32_t max_rounds, int device,

@@ -120,7 +120,7 @@ void launch_admit_particles(const Dev& d, hipStream_t s);
 void launch_seeds(const Dev& d, const int32_t* seeds, int64_t S, hipStream_t s);
 // One round as three launches (sweep, pull, close/push); a round whose work
 // list is empty does nothing, so rounds can be queued ahead of the host.
-void launch_round(const Dev& d, uint32_t round, hipStream_t s);
+void launch_round(const Dev& d, uint32_t round, hipStream_t s, hipEvent_t* ev = nullptr);  // ev: 4 events or null
 // Sum of the work sub-list lengths of parity `par` into counters[C_NWORK0 + par].
 void launch_work_total(const Dev& d, int par, hipStream_t s);
 // Rounds in one cooperative persistent launch; false if it cannot be launched.
