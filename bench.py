@@ -31,6 +31,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+# HBM bytes per launch read from the FETCH_SIZE / WRITE_SIZE counters (scaled by a
+# 1 GiB copy), per (kernel, library version); a kernel changed since then has none.
+# Source: profiles/cfg3_256x64_launch_bt16_hbm_counters.md.
+MEASURED_TRAFFIC = {("k_round_sweep<16>", "mf4d 0.2.0 (gfx950)"): 15.17e6 + 0.62e6}
 PREDICTOR = os.path.join(ROOT, "paper_1903_12294_amd", "predictor.npy")
 
 
@@ -276,8 +280,12 @@ def main():
     kt = kernel_table(V, Q, choice["tile_t"], st, r, admit_all, launch)
     # the roofline object is the kernel with the most device time per step
     dom = max(kt, key=lambda k: kt[k]["ms_per_step"])
+    from paper_1903_12294_amd import _lib
+    version = _lib.load_library().mf4d_version().decode()
+    traffic = MEASURED_TRAFFIC.get((dom, version)) if (X, Y, Z, T) == (256, 256, 256, 64) else None
     roofline = {"bound": "hbm", "kernel": dom, "achieved": kt[dom]["achieved_GBps"],
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kt[dom]["frac"], "traffic": None,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kt[dom]["frac"],
+                "traffic": int(traffic) if traffic else None,
                 "bytes_per_launch": kt[dom]["bytes_per_launch"],
                 "ms_per_launch": kt[dom]["ms_per_launch"]}
 

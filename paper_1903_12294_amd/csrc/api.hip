@@ -363,7 +363,9 @@ int finish_stats(mf4d_ctx* c, mf4d_stats* out, bool fresh, int64_t rounds) {
 
 extern "C" {
 
-const char* mf4d_version(void) { return "mf4d 0.1.0 (gfx950)"; }
+// Bumped whenever a kernel changes: autotuner caches and recorded hardware
+// counter figures are keyed by it.
+const char* mf4d_version(void) { return "mf4d 0.2.0 (gfx950)"; }
 
 const char* mf4d_last_error(void) { return g_err.c_str(); }
 
