@@ -577,6 +577,74 @@ __device__ uint32_t close_phase(const Dev& d, int par, uint32_t wave_id, uint32_
     return closed;
 }
 
+// Pull fused with close, for one 64-step label word per particle (W = 1).  A
+// wave takes 256 list entries at a time (4 per lane).  A coupled step whose
+// voxel is a member joins (atomicOr on its particle's label word); the thread
+// whose atomicOr sets the bit closes the particle's runs from the word it got
+// back plus its own bit.  Every bit set before that atomicOr is in the word it
+// returns, so the last setter of a word closes over all of them, and each bit
+// the closure adds is pushed by the thread that set it.  The new steps of the
+// wave are pushed 64 at a time through LDS, one per lane (pushes schedule for
+// parity par ^ 1).  Returns this lane's number of joins.
+__device__ uint32_t pull_close_wave(const Dev& d, int par, uint32_t wave_id, uint32_t nwaves,
+                                    uint32_t n, uint32_t* s_list) {
+    const PGeom& pg = d.pg;
+    const int tshift = 5 + 6 + d.g.logBT;
+    const uint8_t* chg = d.chg + par * d.g.NT;
+    const int lane = lane_id();
+    uint32_t joins = 0;
+    for (uint32_t base = wave_id * 256u; base < n; base += nwaves * 256u) {  // wave-uniform
+        uint2 ent[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t j = base + k * 64 + lane;
+            ent[k] = j < n ? d.clist[j] : make_uint2(0u, kNoVoxel);
+        }
+        bool mem[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            mem[k] = ent[k].y != kNoVoxel && chg[ent[k].y >> tshift] && test_bit(d.Lf, ent[k].y);
+        uint32_t pk[4];
+        unsigned long long nwk[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            pk[k] = 0;
+            nwk[k] = 0ull;
+            if (!mem[k]) continue;
+            const uint32_t p = pg.logTpad >= 0 ? ent[k].x >> pg.logTpad : ent[k].x / (uint32_t)pg.Tpad;
+            const uint32_t ts = ent[k].x - p * (uint32_t)pg.Tpad;
+            const unsigned long long bit = 1ull << ts;
+            if (d.Lp[p] & bit) continue;
+            const unsigned long long old = atomicOr(&d.Lp[p], bit);
+            if (old & bit) continue;
+            ++joins;
+            const unsigned long long known = old | bit;
+            const unsigned long long nw = fill_runs64(known, d.Ap[p]) & ~known;
+            if (nw) {
+                nwk[k] = nw & ~atomicOr(&d.Lp[p], nw);
+                pk[k] = p;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            unsigned long long nw = nwk[k];
+            while (__ballot(nw != 0)) {
+                uint32_t tot;
+                uint32_t kk = wave_excl_scan(__popcll(nw), tot);
+                while (nw && kk < 64) {
+                    const int t = __builtin_ctzll(nw);
+                    nw &= nw - 1;
+                    s_list[kk++] = pk[k] * (uint32_t)pg.Tpad + t;
+                }
+                wave_sync();
+                if ((uint32_t)lane < (tot < 64 ? tot : 64)) push_one(d, s_list[lane], par ^ 1);
+                wave_sync();
+            }
+        }
+    }
+    return joins;
+}
+
 // Add a per-block value to its slot of statistic `which` (thread 0 calls).
 __device__ __forceinline__ void slot_add(const Dev& d, int which, unsigned long long v) {
     if (v) atomicAdd(&d.slots[which * kSlots + (blockIdx.x & (kSlots - 1))], v);
@@ -1230,6 +1298,10 @@ template <int BT>
 __global__ __launch_bounds__(256) void k_round_sweep(Dev d, int par) {
     const uint32_t wave0 = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    // the other parity's changed-tile flags were consumed by the previous
+    // round's pull; clear them before this round's pull pushes set them again
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < d.g.NT; i += gridDim.x * blockDim.x)
+        d.chg[(par ^ 1) * d.g.NT + i] = 0;
     const uint32_t nwork = sweep_phase<BT>(d, par, wave0, nwaves);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         d.counters[C_RACT] = nwork ? 1u : 0u;  // pull and close of this round read it
@@ -1242,12 +1314,20 @@ __global__ __launch_bounds__(256) void k_round_sweep(Dev d, int par) {
 }
 
 __global__ __launch_bounds__(256) void k_round_pull(Dev d, int par) {
+    __shared__ uint32_t s_list[4 * 64];
     if (!d.counters[C_RACT]) return;
     // the swept list is empty again (its dirty flags were cleared by the sweeps)
     if (blockIdx.x == 0 && threadIdx.x < (unsigned)kWorkSubs)
         d.wcnt[(par * kWorkSubs + threadIdx.x) * kWcntStride] = 0u;
-    pull_entries(d, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x,
-                 d.counters[C_NLIST], par);
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t n = d.counters[C_NLIST];
+    if (d.pg.W == 1) {
+        const uint32_t joins =
+            pull_close_wave(d, par, tid >> 6, (gridDim.x * blockDim.x) >> 6, n, s_list + 64 * (threadIdx.x >> 6));
+        block_slot_sum(d, SL_PART_VISITS, joins);
+    } else {
+        pull_entries(d, tid, gridDim.x * blockDim.x, n, par);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_round_close(Dev d, int par) {
@@ -1256,7 +1336,6 @@ __global__ __launch_bounds__(256) void k_round_close(Dev d, int par) {
     if (!d.counters[C_RACT]) return;
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t i = tid; i < d.g.NT; i += stride) d.chg[par * d.g.NT + i] = 0;
     if (threadIdx.x == 0) s_cnt = 0;
     __syncthreads();
     const uint32_t closed =
@@ -1289,22 +1368,29 @@ __global__ __launch_bounds__(256) void k_rounds(Dev d, uint32_t round0, uint32_t
             nwork = total;  // the same in every thread
         }
         if (nwork == 0 || (max_rounds && r - round0 >= max_rounds)) break;
-        // sweep
+        // sweep (and clear the flags the previous round's pull consumed)
+        for (uint32_t i = tid; i < d.g.NT; i += nthreads) d.chg[(par ^ 1) * d.g.NT + i] = 0;
         sweep_phase<BT>(d, par, wave0, nwaves);
         visits += nwork;  // only thread 0 records it
         if (!grid_sync(d, epoch)) break;
-        // pull
+        // pull (fused with close and push for one label word per particle)
         if (tid < (unsigned)kWorkSubs) store_relaxed(&d.wcnt[(par * kWorkSubs + tid) * kWcntStride], 0u);
-        if (parts) pull_entries(d, tid, nthreads, load_relaxed(&d.counters[C_NLIST]), par);
+        if (parts) {
+            const uint32_t n = load_relaxed(&d.counters[C_NLIST]);
+            if (d.pg.W == 1) closed += pull_close_wave(d, par, wave0, nwaves, n, my_list);
+            else pull_entries(d, tid, nthreads, n, par);
+        }
         if (!grid_sync(d, epoch)) break;
-        // close and push
-        for (uint32_t i = tid; i < d.g.NT; i += nthreads) d.chg[par * d.g.NT + i] = 0;
-        if (parts) closed += close_phase(d, par ^ 1, wave0, nwaves, my_list);
-        if (!grid_sync(d, epoch)) break;
+        // close and push, for longer trajectories
+        if (parts && d.pg.W > 1) {
+            const uint32_t c = close_phase(d, par ^ 1, wave0, nwaves, my_list);  // same in every lane
+            if (lane_id() == 0) closed += c;
+            if (!grid_sync(d, epoch)) break;
+        }
         ++r;
     }
     __syncthreads();
-    if (lane_id() == 0 && closed) atomicAdd(&s_cnt, closed);
+    if (closed) atomicAdd(&s_cnt, closed);  // LDS; per-lane counts
     __syncthreads();
     if (threadIdx.x == 0) slot_add(d, SL_PART_VISITS, s_cnt);
     if (tid == 0 && visits) atomicAdd(&d.stat64[S_TILE_VISITS], (unsigned long long)visits);
@@ -1578,7 +1664,8 @@ void launch_round(const Dev& d, uint32_t round, hipStream_t s, hipEvent_t* ev) {
     // one thread per pdirty word (a wave takes 64), and enough to clear the tile flags
     const uint64_t nw32 = (uint64_t)(d.pg.P + 31) / 32;
     const uint64_t nclose = (uint64_t)d.g.NT > nw32 ? (uint64_t)d.g.NT : nw32;
-    hipLaunchKernelGGL(k_round_close, dim3(grid_for(nclose, 256, 2048)), dim3(256), 0, s, d, par);
+    if (d.pg.W > 1)  // one label word per particle: closed inside the pull
+        hipLaunchKernelGGL(k_round_close, dim3(grid_for(nclose, 256, 2048)), dim3(256), 0, s, d, par);
     if (ev) (void)hipEventRecord(ev[3], s);
 }
 

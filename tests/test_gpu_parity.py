@@ -258,3 +258,14 @@ def test_coupled_list_staging_many_iterations(tau_p):
                                tau_f=0.3, tau_p=tau_p, attr_mode="noise")
     for schedule in ("persistent", "launch"):
         _assert_parity(inst, tag=f"staging tau_p={tau_p} {schedule}", schedule=schedule)
+
+
+@pytest.mark.parametrize("schedule", ["persistent", "launch"])
+@pytest.mark.parametrize("T", [67, 130])
+def test_long_trajectories(T, schedule):
+    """More than 64 steps per particle (two or three label words): runs of
+    admissible steps cross word boundaries (independent-noise attribute, 85%
+    admissible), so the close phase carries across words."""
+    inst = synth.make_instance(40, 24, 16, T, 1500, n_blobs=4, seed=T, n_seeds=4, tau_f=0.3,
+                               tau_p=0.15, attr_mode="noise")
+    _assert_parity(inst, tag=f"long T={T} {schedule}", schedule=schedule)
