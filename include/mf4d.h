@@ -181,12 +181,16 @@ int mf4d_grow_resume(mf4d_ctx *ctx, mf4d_stats *out);
 
 /* Write the field part of the grown feature as canonical bit words (layout
  * above) to dst, which holds nwords >= ceil(X*Y*Z*T / 32) words.  Counts the
- * members into the statistics of the last grow (see mf4d_last_stats).
+ * members into the statistics of the last grow (see mf4d_last_stats).  With
+ * MF4D_DEVICE the call is ordered on the context's stream and returns without
+ * waiting for it (dst is ready for later work on that stream); the member
+ * count arrives with the stream (mf4d_last_stats waits for it).  With
+ * MF4D_HOST it returns when dst is written.
  * Errors: MF4D_ERR_STATE (nothing grown), MF4D_ERR_ARG (dst too small). */
 int mf4d_read_field_mask(mf4d_ctx *ctx, uint32_t *dst, size_t nwords, int where);
 
 /* Write the particle part of the grown feature as uint8 [T][P] to dst,
- * which holds n >= T*P bytes.
+ * which holds n >= T*P bytes.  Stream ordering as mf4d_read_field_mask.
  * Errors: MF4D_ERR_STATE (nothing grown or no particles), MF4D_ERR_ARG. */
 int mf4d_read_particle_mask(mf4d_ctx *ctx, uint8_t *dst, size_t n, int where);
 

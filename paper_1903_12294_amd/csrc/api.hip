@@ -129,6 +129,7 @@ struct mf4d_ctx {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     hipEvent_t rev[4 * 4] = {};  // per launched round of a chunk: before sweep, pull, close, after
     double ms_phase[3] = {0, 0, 0};  // sweep, pull, close of the current grow
+    bool members_pending[2] = {false, false};  // member counts in flight (field, particles)
 
     void* staging = nullptr;
     size_t staging_bytes = 0;
@@ -693,6 +694,7 @@ int mf4d_grow(mf4d_ctx* c, mf4d_stats* out) {
     c->state = 0;
     c->round = 0;
     c->ms_phase[0] = c->ms_phase[1] = c->ms_phase[2] = 0;
+    c->members_pending[0] = c->members_pending[1] = false;
     launch_reset(d, s);
     HIP_TRY(hipEventRecord(c->ev[0], s));
     Dev dp = d;
@@ -736,6 +738,17 @@ int mf4d_grow_resume(mf4d_ctx* c, mf4d_stats* out) {
     return MF4D_OK;
 }
 
+// Wait for member counts copied by stream-ordered reads and record them.
+int settle_members(mf4d_ctx* c) {
+    if (!c->members_pending[0] && !c->members_pending[1]) return MF4D_OK;
+    int rc = sync(c);
+    if (rc) return rc;
+    if (c->members_pending[0]) c->stats.members_field = (int64_t)c->h_stat[S_MEMBERS_F];
+    if (c->members_pending[1]) c->stats.members_particle = (int64_t)c->h_stat[S_MEMBERS_P];
+    c->members_pending[0] = c->members_pending[1] = false;
+    return MF4D_OK;
+}
+
 int mf4d_read_field_mask(mf4d_ctx* c, uint32_t* dst, size_t nwords, int where) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
     if (c->state == 0) return fail(MF4D_ERR_STATE, "nothing grown");
@@ -752,17 +765,15 @@ int mf4d_read_field_mask(mf4d_ctx* c, uint32_t* dst, size_t nwords, int where) {
         if (rc) return rc;
         out = (uint32_t*)st;
     }
-    launch_fill_u32((uint32_t*)(c->stat64 + S_MEMBERS_F), 0, 2, c->stream);
     launch_read_field(make_dev(c), out, c->stream);
-    launch_fold_slots(make_dev(c), SL_MEMBERS_F, S_MEMBERS_F, c->stream);
+    launch_fold_slots(make_dev(c), SL_MEMBERS_F, S_MEMBERS_F, c->stream, true);
     if (where == MF4D_HOST)
         HIP_TRY(hipMemcpyAsync(dst, out, need * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(c->h_stat + S_MEMBERS_F, c->stat64 + S_MEMBERS_F,
                            sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
-    int rc = sync(c);
-    if (rc) return rc;
-    c->stats.members_field = (int64_t)c->h_stat[S_MEMBERS_F];
-    return MF4D_OK;
+    c->members_pending[0] = true;
+    if (where == MF4D_DEVICE) return MF4D_OK;  // stream-ordered
+    return settle_members(c);
 }
 
 int mf4d_read_particle_mask(mf4d_ctx* c, uint8_t* dst, size_t n, int where) {
@@ -781,17 +792,15 @@ int mf4d_read_particle_mask(mf4d_ctx* c, uint8_t* dst, size_t n, int where) {
         if (rc) return rc;
         out = (uint8_t*)st;
     }
-    launch_fill_u32((uint32_t*)(c->stat64 + S_MEMBERS_P), 0, 2, c->stream);
     launch_read_particles(make_dev(c), out, c->stream);
-    launch_fold_slots(make_dev(c), SL_MEMBERS_P, S_MEMBERS_P, c->stream);
+    launch_fold_slots(make_dev(c), SL_MEMBERS_P, S_MEMBERS_P, c->stream, true);
     if (where == MF4D_HOST)
         HIP_TRY(hipMemcpyAsync(dst, out, need, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(c->h_stat + S_MEMBERS_P, c->stat64 + S_MEMBERS_P,
                            sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
-    int rc = sync(c);
-    if (rc) return rc;
-    c->stats.members_particle = (int64_t)c->h_stat[S_MEMBERS_P];
-    return MF4D_OK;
+    c->members_pending[1] = true;
+    if (where == MF4D_DEVICE) return MF4D_OK;  // stream-ordered
+    return settle_members(c);
 }
 
 int mf4d_set_queries(mf4d_ctx* c, int Q, const float* crit, const int32_t* qxyzt, int64_t S,
@@ -1048,6 +1057,8 @@ int mf4d_brick_dims(mf4d_ctx* c, int* dims4) {
 int mf4d_last_stats(mf4d_ctx* c, mf4d_stats* out) {
     if (!c || !out) return fail(MF4D_ERR_ARG, "NULL argument");
     if (c->state == 0) return fail(MF4D_ERR_STATE, "nothing grown");
+    int rc = settle_members(c);
+    if (rc) return rc;
     *out = c->stats;
     return MF4D_OK;
 }

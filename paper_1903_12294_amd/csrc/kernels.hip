@@ -724,7 +724,7 @@ __device__ bool grid_sync(const Dev& d, uint32_t& epoch) {
 // kernels
 
 // stat64[dst] += the slots of statistic `which`; the slots are cleared.
-__global__ __launch_bounds__(1024) void k_fold_slots(Dev d, int which, int dst) {
+__global__ __launch_bounds__(1024) void k_fold_slots(Dev d, int which, int dst, int assign) {
     __shared__ unsigned long long s_w[16];
     unsigned long long v = 0;
     for (int i = threadIdx.x; i < kSlots; i += blockDim.x) {
@@ -737,7 +737,7 @@ __global__ __launch_bounds__(1024) void k_fold_slots(Dev d, int which, int dst) 
     if (threadIdx.x == 0) {
         unsigned long long t = 0;
         for (int w = 0; w < 16; ++w) t += s_w[w];
-        d.stat64[dst] += t;
+        d.stat64[dst] = assign ? t : d.stat64[dst] + t;
     }
 }
 
@@ -1575,8 +1575,8 @@ bool coop_rounds(const Dev& d, uint32_t round0, uint32_t max_rounds, int device,
 // ---------------------------------------------------------------------------
 // launchers
 
-void launch_fold_slots(const Dev& d, int which, int dst, hipStream_t s) {
-    hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(1024), 0, s, d, which, dst);
+void launch_fold_slots(const Dev& d, int which, int dst, hipStream_t s, bool assign) {
+    hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(1024), 0, s, d, which, dst, assign ? 1 : 0);
 }
 
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
