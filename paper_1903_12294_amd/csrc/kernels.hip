@@ -91,8 +91,10 @@ __device__ __forceinline__ size_t voxel_of_bit(const Geom& g, uint32_t b) {
 // voxel (its bit words are not rewritten this grow); a deferred tile has not
 // been tested yet, so the field value itself is tested.
 __device__ __forceinline__ bool admissible_bit(const Dev& d, uint32_t b) {
+    // both loads issued together; the word is in bounds for any tile
     const uint8_t a = d.active[b >> (5 + 6 + d.g.logBT)];
-    if (a == 1) return test_bit(d.Af, b);
+    const uint32_t w = d.Af[b >> 5];
+    if (a == 1) return (w >> (b & 31)) & 1u;
     if (a == 2) return in_band(d.field[voxel_of_bit(d.g, b)], d.crit[0], d.crit[1]);
     return false;
 }
@@ -600,10 +602,15 @@ __device__ uint32_t pull_close_wave(const Dev& d, int par, uint32_t wave_id, uin
             const uint32_t j = base + k * 64 + lane;
             ent[k] = j < n ? d.clist[j] : make_uint2(0u, kNoVoxel);
         }
+        // the tile flag and the label word are loaded together
         bool mem[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            mem[k] = ent[k].y != kNoVoxel && chg[ent[k].y >> tshift] && test_bit(d.Lf, ent[k].y);
+        for (int k = 0; k < 4; ++k) {
+            const bool v = ent[k].y != kNoVoxel;
+            const uint8_t c = v ? chg[ent[k].y >> tshift] : 0;
+            const uint32_t lw = v ? d.Lf[ent[k].y >> 5] : 0u;
+            mem[k] = c && ((lw >> (ent[k].y & 31)) & 1u);
+        }
         uint32_t pk[4];
         unsigned long long nwk[4];
 #pragma unroll
@@ -614,14 +621,17 @@ __device__ uint32_t pull_close_wave(const Dev& d, int par, uint32_t wave_id, uin
             const uint32_t p = pg.logTpad >= 0 ? ent[k].x >> pg.logTpad : ent[k].x / (uint32_t)pg.Tpad;
             const uint32_t ts = ent[k].x - p * (uint32_t)pg.Tpad;
             const unsigned long long bit = 1ull << ts;
-            if (d.Lp[p] & bit) continue;
+            const unsigned long long a = d.Ap[p];  // issued beside the atomic
             const unsigned long long old = atomicOr(&d.Lp[p], bit);
             if (old & bit) continue;
             ++joins;
             const unsigned long long known = old | bit;
-            const unsigned long long nw = fill_runs64(known, d.Ap[p]) & ~known;
+            const unsigned long long nw = fill_runs64(known, a) & ~known;
             if (nw) {
-                nwk[k] = nw & ~atomicOr(&d.Lp[p], nw);
+                // No need to wait for the word back: a bit another closer set
+                // meanwhile is pushed twice, and pushes are idempotent.
+                atomicOr(&d.Lp[p], nw);
+                nwk[k] = nw;
                 pk[k] = p;
             }
         }
