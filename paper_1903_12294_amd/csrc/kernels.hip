@@ -602,15 +602,11 @@ __device__ uint32_t pull_close_wave(const Dev& d, int par, uint32_t wave_id, uin
             const uint32_t j = base + k * 64 + lane;
             ent[k] = j < n ? d.clist[j] : make_uint2(0u, kNoVoxel);
         }
-        // the tile flag and the label word are loaded together
+        // the label word is read only for steps in changed tiles (most are not)
         bool mem[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const bool v = ent[k].y != kNoVoxel;
-            const uint8_t c = v ? chg[ent[k].y >> tshift] : 0;
-            const uint32_t lw = v ? d.Lf[ent[k].y >> 5] : 0u;
-            mem[k] = c && ((lw >> (ent[k].y & 31)) & 1u);
-        }
+        for (int k = 0; k < 4; ++k)
+            mem[k] = ent[k].y != kNoVoxel && chg[ent[k].y >> tshift] && test_bit(d.Lf, ent[k].y);
         uint32_t pk[4];
         unsigned long long nwk[4];
 #pragma unroll
@@ -621,7 +617,8 @@ __device__ uint32_t pull_close_wave(const Dev& d, int par, uint32_t wave_id, uin
             const uint32_t p = pg.logTpad >= 0 ? ent[k].x >> pg.logTpad : ent[k].x / (uint32_t)pg.Tpad;
             const uint32_t ts = ent[k].x - p * (uint32_t)pg.Tpad;
             const unsigned long long bit = 1ull << ts;
-            const unsigned long long a = d.Ap[p];  // issued beside the atomic
+            const unsigned long long a = d.Ap[p];  // issued beside the label read
+            if (d.Lp[p] & bit) continue;  // joined already: no atomic
             const unsigned long long old = atomicOr(&d.Lp[p], bit);
             if (old & bit) continue;
             ++joins;
