@@ -617,18 +617,17 @@ __device__ uint32_t pull_close_wave(const Dev& d, int par, uint32_t wave_id, uin
             const uint32_t p = pg.logTpad >= 0 ? ent[k].x >> pg.logTpad : ent[k].x / (uint32_t)pg.Tpad;
             const uint32_t ts = ent[k].x - p * (uint32_t)pg.Tpad;
             const unsigned long long bit = 1ull << ts;
-            const unsigned long long a = d.Ap[p];  // issued beside the label read
             if (d.Lp[p] & bit) continue;  // joined already: no atomic
             const unsigned long long old = atomicOr(&d.Lp[p], bit);
             if (old & bit) continue;
             ++joins;
             const unsigned long long known = old | bit;
-            const unsigned long long nw = fill_runs64(known, a) & ~known;
+            const unsigned long long nw = fill_runs64(known, d.Ap[p]) & ~known;
             if (nw) {
-                // No need to wait for the word back: a bit another closer set
-                // meanwhile is pushed twice, and pushes are idempotent.
-                atomicOr(&d.Lp[p], nw);
-                nwk[k] = nw;
+                // push only the bits this closure set: a concurrent joiner of
+                // the same run closes it too, and pushing it twice would double
+                // the push work (measured)
+                nwk[k] = nw & ~atomicOr(&d.Lp[p], nw);
                 pk[k] = p;
             }
         }
