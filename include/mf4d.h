@@ -106,6 +106,13 @@ typedef struct mf4d_stats {
     int64_t coupled_steps;    /* single-query grow: admissible particle-steps that lie in a voxel */
 } mf4d_stats;
 
+/* Record HIP events in each grow (on = 1) so that the device times of
+ * mf4d_stats (ms_admit_field, ms_admit, ms_rounds, ms_total, and for rounds
+ * run as launches ms_sweep / ms_pull / ms_close) are filled; off (0, the
+ * default) records none and those times read 0: each event costs a few
+ * microseconds of device time.  Errors: MF4D_ERR_ARG. */
+int mf4d_set_phase_timing(mf4d_ctx *ctx, int on);
+
 /* Library version string. */
 const char *mf4d_version(void);
 

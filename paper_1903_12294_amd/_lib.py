@@ -66,6 +66,7 @@ SIGNATURES = {
     "mf4d_create": (c_int, [POINTER(c_void_p), c_int, c_void_p]),
     "mf4d_destroy": (None, [c_void_p]),
     "mf4d_set_tile": (c_int, [c_void_p, c_int]),
+    "mf4d_set_phase_timing": (c_int, [c_void_p, c_int]),
     "mf4d_load_field": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_int]),
     "mf4d_load_particles": (c_int, [c_void_p, c_void_p, c_void_p, c_int64, c_int, c_int]),
     "mf4d_set_criteria": (c_int, [c_void_p, c_float, c_float, c_float, c_float]),

@@ -130,6 +130,8 @@ struct mf4d_ctx {
     hipEvent_t rev[4 * 4] = {};  // per launched round of a chunk: before sweep, pull, close, after
     double ms_phase[3] = {0, 0, 0};  // sweep, pull, close of the current grow
     bool members_pending[2] = {false, false};  // member counts in flight (field, particles)
+    bool phase_timing = false;  // events around launched round kernels
+    bool timed = false;         // the current grow records its events
 
     void* staging = nullptr;
     size_t staging_bytes = 0;
@@ -296,12 +298,13 @@ int run_rounds(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
             c->state = 2;
             break;
         }
-        for (int64_t k = 0; k < chunk; ++k) launch_round(d, (uint32_t)(c->round + k), c->stream, c->rev + 4 * k);
+        for (int64_t k = 0; k < chunk; ++k)
+            launch_round(d, (uint32_t)(c->round + k), c->stream, c->timed ? c->rev + 4 * k : nullptr);
         launch_work_total(d, (int)((c->round + chunk) & 1), c->stream);
         int rc = read_counters(c);
         if (rc) return rc;
         const int64_t done = (int64_t)c->h_counters[C_ROUNDS] - r;
-        for (int64_t k = 0; k < done && k < chunk; ++k)
+        for (int64_t k = 0; c->timed && k < done && k < chunk; ++k)
             for (int ph = 0; ph < 3; ++ph) {
                 float ms = 0;
                 HIP_TRY(hipEventElapsedTime(&ms, c->rev[4 * k + ph], c->rev[4 * k + ph + 1]));
@@ -342,7 +345,9 @@ int finish_stats(mf4d_ctx* c, mf4d_stats* out, bool fresh, int64_t rounds) {
     s.members_field = -1;
     s.members_particle = c->has_particles ? -1 : 0;
     float ms = 0;
-    if (fresh) {
+    if (!c->timed) {
+        // no events were recorded: device times are reported only with phase timing on
+    } else if (fresh) {
         HIP_TRY(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
         s.ms_admit_field = ms;
         HIP_TRY(hipEventElapsedTime(&ms, c->ev[0], c->ev[2]));
@@ -667,6 +672,13 @@ int mf4d_set_admit_mode(mf4d_ctx* c, int mode) {
     return MF4D_OK;
 }
 
+int mf4d_set_phase_timing(mf4d_ctx* c, int on) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    if (on != 0 && on != 1) return fail(MF4D_ERR_ARG, "on must be 0 or 1");
+    c->phase_timing = on == 1;
+    return MF4D_OK;
+}
+
 int mf4d_set_schedule(mf4d_ctx* c, int mode) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
     if (mode != MF4D_SCHED_PERSISTENT && mode != MF4D_SCHED_LAUNCH)
@@ -696,7 +708,8 @@ int mf4d_grow(mf4d_ctx* c, mf4d_stats* out) {
     c->ms_phase[0] = c->ms_phase[1] = c->ms_phase[2] = 0;
     c->members_pending[0] = c->members_pending[1] = false;
     launch_reset(d, s);
-    HIP_TRY(hipEventRecord(c->ev[0], s));
+    c->timed = c->phase_timing;
+    if (c->timed) HIP_TRY(hipEventRecord(c->ev[0], s));
     Dev dp = d;
     if (c->net && !c->admit_all) {
         // the predictor marks the candidate tiles to test before the rounds
@@ -708,14 +721,14 @@ int mf4d_grow(mf4d_ctx* c, mf4d_stats* out) {
         dp.tpred = c->tpred;
     }
     launch_admit_field(dp, s);
-    HIP_TRY(hipEventRecord(c->ev[1], s));
+    if (c->timed) HIP_TRY(hipEventRecord(c->ev[1], s));
     launch_admit_particles(d, s);
-    HIP_TRY(hipEventRecord(c->ev[2], s));
+    if (c->timed) HIP_TRY(hipEventRecord(c->ev[2], s));
     launch_seeds(d, c->seeds, c->S, s);
     int64_t rounds = 0;
     int rc = run_rounds(c, d, &rounds);
     if (rc) return rc;
-    HIP_TRY(hipEventRecord(c->ev[3], s));
+    if (c->timed) HIP_TRY(hipEventRecord(c->ev[3], s));
     rc = finish_stats(c, out, true, rounds);
     if (rc) return rc;
     if (c->state == 2) return fail(MF4D_ERR_NOT_CONVERGED, "stopped after %lld rounds", (long long)rounds);
@@ -727,11 +740,11 @@ int mf4d_grow_resume(mf4d_ctx* c, mf4d_stats* out) {
     if (c->state != 2) return fail(MF4D_ERR_STATE, "nothing to resume");
     HIP_TRY(hipSetDevice(c->device));
     const Dev d = make_dev(c);
-    HIP_TRY(hipEventRecord(c->ev[2], c->stream));
+    if (c->timed) HIP_TRY(hipEventRecord(c->ev[2], c->stream));
     int64_t rounds = 0;
     int rc = run_rounds(c, d, &rounds);
     if (rc) return rc;
-    HIP_TRY(hipEventRecord(c->ev[3], c->stream));
+    if (c->timed) HIP_TRY(hipEventRecord(c->ev[3], c->stream));
     rc = finish_stats(c, out, false, rounds);
     if (rc) return rc;
     if (c->state == 2) return fail(MF4D_ERR_NOT_CONVERGED, "stopped after %lld more rounds", (long long)rounds);

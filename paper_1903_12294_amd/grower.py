@@ -121,6 +121,11 @@ class Grower:
         m = {"tiles": _lib.MF4D_ADMIT_TILES, "all": _lib.MF4D_ADMIT_ALL}[mode]
         self._check(self.lib.mf4d_set_admit_mode(self.ctx, m))
 
+    def set_phase_timing(self, on: bool):
+        """Device times of each launched round's kernels in the stats (costs a
+        few microseconds per event; off by default)."""
+        self._check(self.lib.mf4d_set_phase_timing(self.ctx, 1 if on else 0))
+
     def set_max_rounds(self, cap: int):
         self._check(self.lib.mf4d_set_max_rounds(self.ctx, int(cap)))
 
