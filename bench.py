@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # HBM bytes per launch read from the FETCH_SIZE / WRITE_SIZE counters (scaled by a
 # 1 GiB copy), per (kernel, library version); a kernel changed since then has none.
 # Source: profiles/cfg3_256x64_launch_bt16_hbm_counters.md.
-MEASURED_TRAFFIC = {("k_round_sweep<16>", "mf4d 0.2.0 (gfx950)"): 15.17e6 + 0.62e6}
+MEASURED_TRAFFIC = {}
 PREDICTOR = os.path.join(ROOT, "paper_1903_12294_amd", "predictor.npy")
 
 
@@ -54,7 +54,8 @@ def visit_bytes(bt: int) -> int:
     return 912 * bt + 512
 
 
-def kernel_table(V: int, Q: int, bt: int, st: dict, r: dict, admit_all: bool, launch: bool) -> dict:
+def kernel_table(V: int, Q: int, bt: int, st: dict, r: dict, admit_all: bool, launch: bool,
+                 T: int) -> dict:
     """Per kernel (or kernel group): algorithmic bytes per launch, measured
     device time per launch (HIP events on the library's stream), launches per
     step.  The unit counts come from the grow's statistics."""
@@ -71,7 +72,8 @@ def kernel_table(V: int, Q: int, bt: int, st: dict, r: dict, admit_all: bool, la
     if launch:
         rows[f"k_round_sweep<{bt}>"] = (sweep_b, r["ms_sweep"] / rounds, rounds)
         rows["k_round_pull"] = (pull_b, r["ms_pull"] / rounds, rounds)
-        rows["k_round_close"] = (int(st["particle_visits"] / rounds * 16), r["ms_close"] / rounds, rounds)
+        if T > 64:  # up to 64 steps the close is part of the pull kernel
+            rows["k_round_close"] = (int(st["particle_visits"] / rounds * 16), r["ms_close"] / rounds, rounds)
     else:
         rows[f"k_rounds<{bt}>"] = (sweep_b * rounds + pull_b * rounds, r["ms_rounds"], 1)
     out = {}
@@ -288,7 +290,7 @@ def main():
     launch = choice["schedule"] == "launch"
     phases = {"admit_field": r["ms_admit_field"], "admit_particles": r["ms_admit"] - r["ms_admit_field"],
               "rounds": r["ms_rounds"], "read_out": r["ms_read"]}
-    kt = kernel_table(V, Q, choice["tile_t"], st, r, admit_all, launch)
+    kt = kernel_table(V, Q, choice["tile_t"], st, r, admit_all, launch, T)
     # the roofline object is the kernel with the most device time per step
     dom = max(kt, key=lambda k: kt[k]["ms_per_step"])
     from paper_1903_12294_amd import _lib
