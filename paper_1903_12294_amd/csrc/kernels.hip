@@ -235,33 +235,32 @@ __device__ __forceinline__ void schedule_batch(const Dev& d, const uint32_t* nb,
     }
 }
 
-// A voxel bit set from outside a tile sweep (seed or particle push), before
-// round parity `par`: its own tile must be swept, and so must every tile whose
-// face it touches (the owning tile's sweep only reports bits new to that
-// sweep); the owning tile's coupled steps must be pulled.
-__device__ void mark_voxel(const Dev& d, uint32_t b, int par) {
+// Voxel bits set from outside a tile sweep (seeds, particle pushes), before
+// round parity `par`: each owning tile is flagged changed (its coupled steps
+// must be pulled) and scheduled.  Its sweep sees the flag and schedules every
+// tile across a face that holds members, since it cannot tell the bits set
+// here from older ones.  Up to 4 voxels (b = kNoVoxel: none), one round trip
+// per step for all of them.
+__device__ void mark_voxels(const Dev& d, const uint32_t* b, int par) {
     const Geom& g = d.g;
-    const uint32_t word = b >> 5;
-    const int xb = b & 31;
-    const uint32_t tile = word >> (6 + g.logBT);
-    const uint32_t wi = word & (g.WPT - 1);
-    const int yl = wi & 7, zl = (wi >> 3) & 7, tl = wi >> 6;
-    d.chg[par * g.NT + tile] = 1;
-    int tx, ty, tz, tt;
-    tile_coords(g, tile, tx, ty, tz, tt);
-    const uint32_t sy = g.NXt, sz = g.NXt * g.NYt, st = sz * g.NZt;
     uint32_t nb[8];
     int k = 0;
-    nb[k++] = tile;  // active: it holds an admissible voxel-step
-    if (xb == 0 && tx > 0) nb[k++] = tile - 1;
-    else if (xb == 31 && tx + 1 < g.NXt) nb[k++] = tile + 1;
-    if (yl == 0 && ty > 0) nb[k++] = tile - sy;
-    else if (yl == 7 && ty + 1 < g.NYt) nb[k++] = tile + sy;
-    if (zl == 0 && tz > 0) nb[k++] = tile - sz;
-    else if (zl == 7 && tz + 1 < g.NZt) nb[k++] = tile + sz;
-    if (tl == 0 && tt > 0) nb[k++] = tile - st;
-    else if (tl == g.BT - 1 && tt + 1 < g.NTt) nb[k++] = tile + st;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (b[i] == kNoVoxel) continue;
+        const uint32_t tile = b[i] >> (5 + 6 + g.logBT);
+        bool dup = false;
+        for (int j = 0; j < k; ++j) dup |= nb[j] == tile;
+        if (dup) continue;
+        d.chg[par * g.NT + tile] = 1;
+        nb[k++] = tile;
+    }
     schedule_batch(d, nb, k, par);
+}
+
+__device__ __forceinline__ void mark_voxel(const Dev& d, uint32_t b, int par) {
+    const uint32_t v[4] = {b, kNoVoxel, kNoVoxel, kNoVoxel};
+    mark_voxels(d, v, par);
 }
 
 // ---------------------------------------------------------------------------
@@ -305,6 +304,9 @@ __device__ void sweep_tile(const Dev& d, uint32_t tile, int par) {
     const uint32_t* Ltm = htm ? Lb - (size_t)st * w : Lb;
     const uint32_t* Ltp = htp ? Lb + (size_t)st * w : Lb;
     const uint8_t act = d.active[tile];
+    // set before this sweep only by pushes or seeds (the sweep that sets it
+    // for its own changes comes later; the previous round cleared it)
+    const bool pushed = d.chg[par * g.NT + tile] != 0;
     const uint8_t axm = hxm ? d.active[tile - 1] : 0, axp = hxp ? d.active[tile + 1] : 0;
     const uint8_t ay = hym ? d.active[tile - sy] : (hyp ? d.active[tile + sy] : 0);
     const uint8_t az = hzm ? d.active[tile - sz] : (hzp ? d.active[tile + sz] : 0);
@@ -373,23 +375,29 @@ __device__ void sweep_tile(const Dev& d, uint32_t tile, int par) {
         }
         if (__ballot(diff != 0) == 0) break;
     }
-    uint32_t any = 0, fx0 = 0, fx1 = 0;
+    // face bits that may be new to the tile across: those this sweep set, and
+    // after pushes every member (the pushed bits are not known apart)
+    uint32_t any = 0, fany = 0, fx0 = 0, fx1 = 0;
 #pragma unroll
     for (int t = 0; t < BT; ++t) {
         const uint32_t nw = l[t] & ~l0[t];
         if (nw) atomicOr(&Lb[t * 64 + lane], nw);
         any |= nw;
-        fx0 |= nw & 1u;
-        fx1 |= nw >> 31;
+        const uint32_t fb = pushed ? l[t] : nw;
+        fany |= fb;
+        fx0 |= fb & 1u;
+        fx1 |= fb >> 31;
     }
-    const uint32_t nt0 = l[0] & ~l0[0], nt1 = l[BT - 1] & ~l0[BT - 1];
-    if (__ballot(any != 0)) {
+    const uint32_t nt0 = pushed ? l[0] : l[0] & ~l0[0];
+    const uint32_t nt1 = pushed ? l[BT - 1] : l[BT - 1] & ~l0[BT - 1];
+    const bool changed = __ballot(any != 0) != 0;
+    if (changed || pushed) {
         const bool fxm = __ballot(fx0 != 0) != 0, fxp = __ballot(fx1 != 0) != 0;
-        const bool fym = __ballot(yl == 0 && any) != 0, fyp = __ballot(yl == 7 && any) != 0;
-        const bool fzm = __ballot(zl == 0 && any) != 0, fzp = __ballot(zl == 7 && any) != 0;
+        const bool fym = __ballot(yl == 0 && fany) != 0, fyp = __ballot(yl == 7 && fany) != 0;
+        const bool fzm = __ballot(zl == 0 && fany) != 0, fzp = __ballot(zl == 7 && fany) != 0;
         const bool ftm = __ballot(nt0 != 0) != 0, ftp = __ballot(nt1 != 0) != 0;
         if (lane == 0) {
-            d.chg[par * g.NT + tile] = 1;
+            if (changed) d.chg[par * g.NT + tile] = 1;
             const int nx = par ^ 1;
             uint32_t nb[8];
             int k = 0;
@@ -455,6 +463,42 @@ __device__ __forceinline__ void push_steps(const Dev& d, uint32_t p, int w, unsi
             if (!(atomicOr(&d.Lf[b >> 5], bit) & bit)) mark_voxel(d, b, par);
         }
     }
+}
+
+// Push up to 4 particle-steps per lane that joined (flat indices e = p * Tpad
+// + t; ~0u: none): each voxel joins when admissible, for round parity `par`.
+// Every step is issued for the 4 together (bins; activity, admissibility and
+// label words; atomics; marking), and a voxel already a member takes no
+// atomic.
+__device__ void push_four(const Dev& d, const uint32_t* e, int par) {
+    const Geom& g = d.g;
+    uint32_t b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b[i] = e[i] != 0xFFFFFFFFu ? d.bins[e[i]] : kNoVoxel;
+    uint8_t a[4];
+    uint32_t aw[4], lw[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        a[i] = 0;
+        aw[i] = lw[i] = 0;
+        if (b[i] != kNoVoxel) {
+            a[i] = d.active[b[i] >> (5 + 6 + g.logBT)];
+            aw[i] = d.Af[b[i] >> 5];
+            lw[i] = d.Lf[b[i] >> 5];
+        }
+    }
+    uint32_t got[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        got[i] = kNoVoxel;
+        if (b[i] == kNoVoxel) continue;
+        const uint32_t bit = 1u << (b[i] & 31);
+        if (lw[i] & bit) continue;
+        bool adm = a[i] == 1 && (aw[i] & bit);
+        if (a[i] == 2) adm = in_band(d.field[voxel_of_bit(g, b[i])], d.crit[0], d.crit[1]);
+        if (adm && !(atomicOr(&d.Lf[b[i] >> 5], bit) & bit)) got[i] = b[i];
+    }
+    if ((got[0] & got[1] & got[2] & got[3]) != kNoVoxel) mark_voxels(d, got, par);
 }
 
 // Push one particle-step that joined (flat index e = p * Tpad + t): its voxel
@@ -586,8 +630,9 @@ __device__ uint32_t close_phase(const Dev& d, int par, uint32_t wave_id, uint32_
 // back plus its own bit.  Every bit set before that atomicOr is in the word it
 // returns, so the last setter of a word closes over all of them, and each bit
 // the closure adds is pushed by the thread that set it.  The new steps of the
-// wave are pushed 64 at a time through LDS, one per lane (pushes schedule for
-// parity par ^ 1).  Returns this lane's number of joins.
+// wave are gathered in LDS (s_list: 256 words) and pushed 256 at a time, four
+// per lane (pushes schedule for parity par ^ 1).  Returns this lane's number
+// of joins.
 __device__ uint32_t pull_close_wave(const Dev& d, int par, uint32_t wave_id, uint32_t nwaves,
                                     uint32_t n, uint32_t* s_list) {
     const PGeom& pg = d.pg;
@@ -631,21 +676,26 @@ __device__ uint32_t pull_close_wave(const Dev& d, int par, uint32_t wave_id, uin
                 pk[k] = p;
             }
         }
+        while (__ballot((nwk[0] | nwk[1] | nwk[2] | nwk[3]) != 0)) {
+            uint32_t cnt = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            unsigned long long nw = nwk[k];
-            while (__ballot(nw != 0)) {
-                uint32_t tot;
-                uint32_t kk = wave_excl_scan(__popcll(nw), tot);
-                while (nw && kk < 64) {
-                    const int t = __builtin_ctzll(nw);
-                    nw &= nw - 1;
+            for (int k = 0; k < 4; ++k) cnt += __popcll(nwk[k]);
+            uint32_t tot;
+            uint32_t kk = wave_excl_scan(cnt, tot);
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                while (nwk[k] && kk < 256) {
+                    const int t = __builtin_ctzll(nwk[k]);
+                    nwk[k] &= nwk[k] - 1;
                     s_list[kk++] = pk[k] * (uint32_t)pg.Tpad + t;
                 }
-                wave_sync();
-                if ((uint32_t)lane < (tot < 64 ? tot : 64)) push_one(d, s_list[lane], par ^ 1);
-                wave_sync();
-            }
+            wave_sync();
+            const uint32_t m = tot < 256 ? tot : 256;
+            uint32_t e[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) e[i] = (uint32_t)lane + 64 * i < m ? s_list[lane + 64 * i] : 0xFFFFFFFFu;
+            wave_sync();
+            push_four(d, e, par ^ 1);
         }
     }
     return joins;
@@ -1320,7 +1370,7 @@ __global__ __launch_bounds__(256) void k_round_sweep(Dev d, int par) {
 }
 
 __global__ __launch_bounds__(256) void k_round_pull(Dev d, int par) {
-    __shared__ uint32_t s_list[4 * 64];
+    __shared__ uint32_t s_list[4 * 256];
     if (!d.counters[C_RACT]) return;
     // the swept list is empty again (its dirty flags were cleared by the sweeps)
     if (blockIdx.x == 0 && threadIdx.x < (unsigned)kWorkSubs)
@@ -1329,7 +1379,7 @@ __global__ __launch_bounds__(256) void k_round_pull(Dev d, int par) {
     const uint32_t n = d.counters[C_NLIST];
     if (d.pg.W == 1) {
         const uint32_t joins =
-            pull_close_wave(d, par, tid >> 6, (gridDim.x * blockDim.x) >> 6, n, s_list + 64 * (threadIdx.x >> 6));
+            pull_close_wave(d, par, tid >> 6, (gridDim.x * blockDim.x) >> 6, n, s_list + 256 * (threadIdx.x >> 6));
         block_slot_sum(d, SL_PART_VISITS, joins);
     } else {
         pull_entries(d, tid, gridDim.x * blockDim.x, n, par);
@@ -1354,14 +1404,14 @@ __global__ __launch_bounds__(256) void k_round_close(Dev d, int par) {
 // ---- all rounds in one cooperative launch ----
 template <int BT>
 __global__ __launch_bounds__(256) void k_rounds(Dev d, uint32_t round0, uint32_t max_rounds) {
-    __shared__ uint32_t s_list[4 * 64];
+    __shared__ uint32_t s_list[4 * 256];
     __shared__ uint32_t s_cnt;
     uint32_t epoch = 0;
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t nthreads = gridDim.x * blockDim.x;
     const uint32_t wave0 = tid >> 6, nwaves = nthreads >> 6;
     const bool parts = d.pg.P > 0;
-    uint32_t* my_list = s_list + 64 * (threadIdx.x >> 6);
+    uint32_t* my_list = s_list + 256 * (threadIdx.x >> 6);
     if (threadIdx.x == 0) s_cnt = 0;
     uint32_t r = round0;
     uint32_t visits = 0, closed = 0;
