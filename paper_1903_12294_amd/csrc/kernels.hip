@@ -347,23 +347,30 @@ __device__ void sweep_tile(const Dev& d, uint32_t tile, int par) {
             atomicAdd(&d.stat64[S_DEFERRED_READ], 1ull);
         }
     }
+    // Byte addresses of the lanes holding this lane's in-tile y / z
+    // neighbours.  An edge lane names itself: its own word is in the union
+    // anyway, and the halo word brings the neighbour tile's row.
+    const int iym = (yl > 0 ? lane - 1 : lane) << 2, iyp = (yl < 7 ? lane + 1 : lane) << 2;
+    const int izm = (zl > 0 ? lane - 8 : lane) << 2, izp = (zl < 7 ? lane + 8 : lane) << 2;
     while (true) {
         uint32_t s[BT];
 #pragma unroll
         for (int t = 0; t < BT; ++t) {
-            // one Jacobi step along y and z (lane shuffles; halos for edge
-            // lanes), complete along x (runs).  Measured faster than complete
-            // y/z line fills: those chain 12 dependent shuffles per word.
-            const uint32_t v = l[t];
-            const uint32_t ym = __shfl_up(v, 1), yp = __shfl_down(v, 1);
-            const uint32_t zm = __shfl_up(v, 8), zp = __shfl_down(v, 8);
-            uint32_t nb = v | xin[t] | yh[t] | zh[t];
-            nb |= (yl > 0 ? ym : 0u) | (yl < 7 ? yp : 0u) | (zl > 0 ? zm : 0u) | (zl < 7 ? zp : 0u);
-            s[t] = fill_runs32(nb & a[t], a[t]);
+            // one Jacobi step along y and z (lane permutes; halos for edge
+            // lanes).  Measured faster than complete y/z line fills: those
+            // chain 12 dependent shuffles per word.
+            const int v = (int)l[t];
+            const uint32_t ym = (uint32_t)__builtin_amdgcn_ds_bpermute(iym, v);
+            const uint32_t yp = (uint32_t)__builtin_amdgcn_ds_bpermute(iyp, v);
+            const uint32_t zm = (uint32_t)__builtin_amdgcn_ds_bpermute(izm, v);
+            const uint32_t zp = (uint32_t)__builtin_amdgcn_ds_bpermute(izp, v);
+            s[t] = (l[t] | xin[t] | yh[t] | zh[t] | ym | yp | zm | zp) & a[t];
         }
-        s[0] |= fill_runs32(tm & a[0], a[0]);
+        // forward along t; each slice's spatial inputs and what reaches it
+        // from the slice before are completed along x (runs) in one fill
+        s[0] = fill_runs32(s[0] | (tm & a[0]), a[0]);
 #pragma unroll
-        for (int t = 1; t < BT; ++t) s[t] |= fill_runs32(s[t - 1] & a[t], a[t]);
+        for (int t = 1; t < BT; ++t) s[t] = fill_runs32(s[t] | (s[t - 1] & a[t]), a[t]);
         s[BT - 1] |= fill_runs32(tp & a[BT - 1], a[BT - 1]);
 #pragma unroll
         for (int t = BT - 2; t >= 0; --t) s[t] |= fill_runs32(s[t + 1] & a[t], a[t]);
