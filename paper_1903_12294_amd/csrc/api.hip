@@ -121,6 +121,7 @@ struct mf4d_ctx {
     int64_t S = 0;
     int64_t seeds_cap = 0;
     int64_t max_rounds = 0;
+    int64_t last_rounds = 0;  // rounds of the last grow that converged (launch mode)
 
     // grow state: 0 nothing grown, 1 converged, 2 stopped by the round cap
     int state = 0;
@@ -285,14 +286,19 @@ int run_rounds(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
         }
         (void)hipGetLastError();
     }
-    // Launches: rounds are queued kRoundChunk at a time (a round with an empty
+    // Launches: rounds are queued a chunk at a time (a round with an empty
     // work list is a no-op on the device), and the host reads the counters once
-    // per chunk.  C_ROUNDS counts the rounds that had work.
-    constexpr int64_t kRoundChunk = 4;
+    // per chunk.  C_ROUNDS counts the rounds that had work.  Each host read
+    // costs about three queued empty rounds (measured), so the first chunk of a
+    // grow is as long as the context's last converged grow (4 to 16 rounds),
+    // the later ones kRoundChunk; with phase timing every chunk is kRoundChunk
+    // (one set of events per round).
+    constexpr int64_t kRoundChunk = 4, kMaxChunk = 16;
     launch_fill_u32(c->counters + C_ROUNDS, 0, 1, c->stream);
     int64_t r = 0;
     while (true) {
         int64_t chunk = kRoundChunk;
+        if (r == 0 && !c->timed) chunk = std::min(std::max(c->last_rounds, kRoundChunk), kMaxChunk);
         if (cap && cap - r < chunk) chunk = cap - r;
         if (chunk <= 0) {  // cap reached with work left
             c->state = 2;
@@ -728,6 +734,7 @@ int mf4d_grow(mf4d_ctx* c, mf4d_stats* out) {
     int64_t rounds = 0;
     int rc = run_rounds(c, d, &rounds);
     if (rc) return rc;
+    if (c->state == 1) c->last_rounds = rounds;
     if (c->timed) HIP_TRY(hipEventRecord(c->ev[3], s));
     rc = finish_stats(c, out, true, rounds);
     if (rc) return rc;
