@@ -33,8 +33,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # HBM bytes per launch read from the FETCH_SIZE / WRITE_SIZE counters (scaled by a
 # 1 GiB copy), per (kernel, library version); a kernel changed since then has none.
-# Source: profiles/cfg3_256x64_launch_bt16_hbm_counters.md.
-MEASURED_TRAFFIC = {}
+# Source: profiles/grow_256x256x256x64_bt16_launch_hbm_counters.md.
+MEASURED_TRAFFIC = {
+    ("k_round_pull", "mf4d 0.4.0 (gfx950)"): 54478452,
+    ("k_round_sweep<16>", "mf4d 0.4.0 (gfx950)"): 14043459,
+}
 PREDICTOR = os.path.join(ROOT, "paper_1903_12294_amd", "predictor.npy")
 
 
@@ -295,7 +298,9 @@ def main():
     dom = max(kt, key=lambda k: kt[k]["ms_per_step"])
     from paper_1903_12294_amd import _lib
     version = _lib.load_library().mf4d_version().decode()
-    traffic = MEASURED_TRAFFIC.get((dom, version)) if (X, Y, Z, T) == (256, 256, 256, 64) else None
+    # the counters were taken at 256^3 x 64 with tile depth 16 and launched rounds
+    measured_here = (X, Y, Z, T) == (256, 256, 256, 64) and choice["tile_t"] == 16 and launch
+    traffic = MEASURED_TRAFFIC.get((dom, version)) if measured_here else None
     roofline = {"bound": "hbm", "kernel": dom, "achieved": kt[dom]["achieved_GBps"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kt[dom]["frac"],
                 "traffic": int(traffic) if traffic else None,
