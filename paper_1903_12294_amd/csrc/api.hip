@@ -270,8 +270,10 @@ int run_rounds(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
     const uint32_t cap = (uint32_t)(c->max_rounds > 0 ? c->max_rounds : 0);
     const uint32_t r0 = c->round;
     if (c->schedule == MF4D_SCHED_PERSISTENT) {
-        launch_fill_u32(c->counters + C_ERR, 0, 2, c->stream);  // C_ERR, C_ROUNDS
-        launch_fill_u32(c->bar, 0, kBarWords, c->stream);
+        if (c->round != 0) {  // a fresh grow's reset cleared them
+            launch_fill_u32(c->counters + C_ERR, 0, 2, c->stream);  // C_ERR, C_ROUNDS
+            launch_fill_u32(c->bar, 0, kBarWords, c->stream);
+        }
         if (launch_rounds_persistent(d, r0, cap, c->device, c->stream)) {
             int rc = read_counters(c);
             if (rc) return rc;
@@ -294,7 +296,7 @@ int run_rounds(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
     // the later ones kRoundChunk; with phase timing every chunk is kRoundChunk
     // (one set of events per round).
     constexpr int64_t kRoundChunk = 4, kMaxChunk = 16;
-    launch_fill_u32(c->counters + C_ROUNDS, 0, 1, c->stream);
+    if (c->round != 0) launch_fill_u32(c->counters + C_ROUNDS, 0, 1, c->stream);  // fresh: reset cleared it
     int64_t r = 0;
     while (true) {
         int64_t chunk = kRoundChunk;
@@ -328,7 +330,7 @@ int run_rounds(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
 }
 
 int finish_stats(mf4d_ctx* c, mf4d_stats* out, bool fresh, int64_t rounds) {
-    launch_fold_slots(make_dev(c), SL_PART_VISITS, S_PART_VISITS, c->stream);
+    launch_fold_grow_slots(make_dev(c), c->stream);
     HIP_TRY(hipMemcpyAsync(c->h_stat, c->stat64, S_NSTAT * sizeof(unsigned long long),
                            hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, C_NCOUNTERS * sizeof(uint32_t),

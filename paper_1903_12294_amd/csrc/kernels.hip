@@ -787,20 +787,31 @@ __device__ bool grid_sync(const Dev& d, uint32_t& epoch) {
 // kernels
 
 // stat64[dst] += the slots of statistic `which`; the slots are cleared.
-__global__ __launch_bounds__(1024) void k_fold_slots(Dev d, int which, int dst, int assign) {
+// Fold up to 4 slot statistics: stat64[dst[k]] (+)= the sum of slots which[k].
+struct FoldList {
+    int n;
+    int which[4];
+    int dst[4];
+    int assign;
+};
+
+__global__ __launch_bounds__(1024) void k_fold_slots(Dev d, FoldList f) {
     __shared__ unsigned long long s_w[16];
-    unsigned long long v = 0;
-    for (int i = threadIdx.x; i < kSlots; i += blockDim.x) {
-        v += d.slots[which * kSlots + i];
-        d.slots[which * kSlots + i] = 0ull;
-    }
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if (lane_id() == 0) s_w[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (int w = 0; w < 16; ++w) t += s_w[w];
-        d.stat64[dst] = assign ? t : d.stat64[dst] + t;
+    for (int k = 0; k < f.n; ++k) {
+        unsigned long long v = 0;
+        for (int i = threadIdx.x; i < kSlots; i += blockDim.x) {
+            v += d.slots[f.which[k] * kSlots + i];
+            d.slots[f.which[k] * kSlots + i] = 0ull;
+        }
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane_id() == 0) s_w[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long t = 0;
+            for (int w = 0; w < 16; ++w) t += s_w[w];
+            d.stat64[f.dst[k]] = f.assign ? t : d.stat64[f.dst[k]] + t;
+        }
+        __syncthreads();
     }
 }
 
@@ -1074,6 +1085,7 @@ __global__ __launch_bounds__(256) void k_admit_tiles(Dev d) {
     const Geom& g = d.g;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
     const uint32_t n = d.counters[C_NCAND];
+    uint32_t tested = 0, active = 0;  // this block's counts (thread 0)
     for (uint32_t ci = blockIdx.x; ci < n; ci += gridDim.x) {
         const uint32_t tile = d.cand[ci];
         int tx, ty, tz, tt;
@@ -1089,22 +1101,38 @@ __global__ __launch_bounds__(256) void k_admit_tiles(Dev d) {
             }
             d.Lf[wi] = 0u;
         }
-        if (!defer && threadIdx.x == 0) atomicAdd(&d.stat64[S_TILES_TESTED], 1ull);
         if (defer) {
-            if (threadIdx.x == 0) d.active[tile] = 2;
-        } else if (__ballot(any != 0) != 0 && lane == 0) {
-            d.active[tile] = 1;
+            if (threadIdx.x == 0) {
+                d.active[tile] = 2;
+                ++active;
+            }
+            continue;
         }
+        const bool has = __ballot(any != 0) != 0;
+        if (has && lane == 0) d.active[tile] = 1;  // each wave's lane 0: the same value
+        // the block's waves may disagree: count the tile once, from all waves
+        __shared__ uint32_t s_any;
+        if (threadIdx.x == 0) s_any = 0;
+        __syncthreads();
+        if (has && lane == 0) s_any = 1;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            ++tested;
+            active += s_any;
+        }
+    }
+    if (threadIdx.x == 0) {
+        slot_add(d, SL_TESTED, tested);
+        slot_add(d, SL_ACTIVE, active);
     }
 }
 
-__global__ void k_count_active(Dev d) {
+__global__ __launch_bounds__(256) void k_count_active(Dev d) {
     uint32_t c = 0;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < d.g.NT;
          i += gridDim.x * blockDim.x)
         c += d.active[i] != 0;
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
-    if (lane_id() == 0 && c) atomicAdd(&d.stat64[S_ACTIVE_TILES], (unsigned long long)c);
+    block_slot_sum(d, SL_ACTIVE, c);
 }
 
 // Admissibility of every particle-step, the labels cleared, and the coupled
@@ -1149,11 +1177,18 @@ __global__ __launch_bounds__(256) void k_pcand_count(Dev d) {
 }
 
 __global__ __launch_bounds__(1024) void k_pcand_scan(Dev d) {
+    static_assert(kPBlocks % 1024 == 0, "each scan thread takes kPBlocks / 1024 counts");
+    constexpr int per = kPBlocks / 1024;
     __shared__ uint32_t s_w[16];
     const int lane = lane_id(), wave = threadIdx.x >> 6;
-    const uint32_t v = threadIdx.x < (unsigned)kPBlocks ? d.pblk[threadIdx.x] : 0u;
+    uint32_t v[per], sum = 0;
+#pragma unroll
+    for (int i = 0; i < per; ++i) {
+        v[i] = d.pblk[threadIdx.x * per + i];
+        sum += v[i];
+    }
     uint32_t wt;
-    const uint32_t ex = wave_excl_scan(v, wt);
+    const uint32_t ex = wave_excl_scan(sum, wt);
     if (lane == 0) s_w[wave] = wt;
     __syncthreads();
     uint32_t base = 0, total = 0;
@@ -1161,7 +1196,12 @@ __global__ __launch_bounds__(1024) void k_pcand_scan(Dev d) {
         if (w < wave) base += s_w[w];
         total += s_w[w];
     }
-    if (threadIdx.x < (unsigned)kPBlocks) d.pblk[threadIdx.x] = base + ex;
+    uint32_t at = base + ex;
+#pragma unroll
+    for (int i = 0; i < per; ++i) {
+        d.pblk[threadIdx.x * per + i] = at;
+        at += v[i];
+    }
     if (threadIdx.x == 0) d.counters[C_NPCAND] = total;
 }
 
@@ -1639,7 +1679,16 @@ bool coop_rounds(const Dev& d, uint32_t round0, uint32_t max_rounds, int device,
 // launchers
 
 void launch_fold_slots(const Dev& d, int which, int dst, hipStream_t s, bool assign) {
-    hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(1024), 0, s, d, which, dst, assign ? 1 : 0);
+    const FoldList f{1, {which, 0, 0, 0}, {dst, 0, 0, 0}, assign ? 1 : 0};
+    hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(1024), 0, s, d, f);
+}
+
+void launch_fold_grow_slots(const Dev& d, hipStream_t s) {
+    const FoldList f{3,
+                     {SL_PART_VISITS, SL_ACTIVE, SL_TESTED, 0},
+                     {S_PART_VISITS, S_ACTIVE_TILES, S_TILES_TESTED, 0},
+                     0};
+    hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(1024), 0, s, d, f);
 }
 
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
@@ -1672,11 +1721,12 @@ void launch_particle_summaries(const PGeom& pg, const float* attr_t, float2* psu
 void launch_admit_field(const Dev& d, hipStream_t s) {
     if (d.admit_all) {
         hipLaunchKernelGGL(k_admit_field, dim3(d.g.NYt, d.g.NZt, d.g.T), dim3(256), 0, s, d);
+        hipLaunchKernelGGL(k_count_active, dim3(grid_for(d.g.NT, 256, 1024)), dim3(256), 0, s, d);
     } else {
+        // counts its active and tested tiles itself
         hipLaunchKernelGGL(k_tile_candidates, dim3(grid_for(d.g.NT, 256, 1024)), dim3(256), 0, s, d);
         hipLaunchKernelGGL(k_admit_tiles, dim3(grid_for(d.g.NT, 1, 8192)), dim3(256), 0, s, d);
     }
-    hipLaunchKernelGGL(k_count_active, dim3(grid_for(d.g.NT, 256, 1024)), dim3(256), 0, s, d);
 }
 
 void launch_admit_particles(const Dev& d, hipStream_t s) {

@@ -8,7 +8,7 @@ namespace mf4d {
 
 constexpr uint32_t kNoVoxel = 0xFFFFFFFFu;
 constexpr int kBarWords = 64 + 32 * 8;  // grid-barrier counters (top, flag, 8 subs), one line each
-constexpr int kPBlocks = 1024;          // blocks of the candidate-particle passes
+constexpr int kPBlocks = 4096;          // blocks of the candidate-particle passes (4 per scan thread)
 // The tile work list of each round parity is split into kWorkSubs sub-lists
 // (tile % kWorkSubs), each with its own counter on its own 128-byte line:
 // appends to one counter from every wave serialise (~11 ns each), spread over
@@ -18,7 +18,14 @@ constexpr int kWcntStride = 32;  // words between sub-list counters
 // Statistics summed by many blocks go to per-block slots (distinct addresses)
 // and are folded into stat64 once, instead of one same-address atomic each.
 constexpr int kSlots = 1024;
-enum SlotStat : int { SL_PART_VISITS = 0, SL_MEMBERS_F = 1, SL_MEMBERS_P = 2, kSlotStats = 4 };
+enum SlotStat : int {
+    SL_PART_VISITS = 0,
+    SL_MEMBERS_F = 1,
+    SL_MEMBERS_P = 2,
+    SL_ACTIVE = 3,  // tiles holding an admissible voxel-step (or deferred)
+    SL_TESTED = 4,  // candidate tiles whose admissibility was read up front
+    kSlotStats = 5
+};
 
 // Bit-packed tile layout of the field labels and admissibility.
 // A tile covers 32 (x) x 8 (y) x 8 (z) x BT (t) voxel-steps.  One 32-bit word
@@ -130,5 +137,8 @@ void launch_read_field(const Dev& d, uint32_t* out, hipStream_t s);
 void launch_read_particles(const Dev& d, uint8_t* out, hipStream_t s);
 // stat64[dst] (+)= sum of slot statistic `which` (assign: =), and those slots cleared.
 void launch_fold_slots(const Dev& d, int which, int dst, hipStream_t s, bool assign = false);
+// The per-grow statistics (particle visits, active and tested tiles) folded
+// (added) in one launch.
+void launch_fold_grow_slots(const Dev& d, hipStream_t s);
 
 }  // namespace mf4d
