@@ -1,0 +1,244 @@
+"""4D SLIC clustering of point and field samples (Section 3.2), the oracle.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the product library.  Plain numpy,
+slow, written for a reader who checks it against the paper.
+
+What it computes (Section 3.2.1-3.2.3; the readings that fix what the paper
+leaves open are marked R and listed in the design notes):
+
+  samples   one field sample per voxel-step: position (x+0.5, y+0.5, z+0.5)
+            (R: the voxel centre), time t, value f; one point sample per
+            particle-step: its position, time t, value a.  A sample with a
+            non-finite position or value is not clustered (label -1) (R).
+  seeding   k = (kx, ky, kz, kt) centres on a 4D rectilinear grid, interval
+            C_d = E_d / k_d with E = (X, Y, Z, T) (Section 3.2.1), in fp32.
+            The seed cell of a sample is floor(pos_d / C_d) clamped to
+            [0, k_d - 1]; centre id = ((ct*kz + cz)*ky + cy)*kx + cx.
+            A seed centre sits at ((i + 0.5) C_d) with values 0 (R).
+  initial   every sample goes to the nearest seed centre, which on a
+            rectilinear grid under the (diagonal) space-time metric is its
+            seed cell's centre (Section 3.2.1).
+  update    a centre is the mean of its samples (Section 3.2.2): location over
+            both types, f_c over field samples, p_c over point samples.  R:
+            sums are exact integer sums of q(v) = rint(v * 2^20) (so the order
+            of summation cannot matter), and mean = dbl(sum) / n * 2^-20 with
+            dbl(s) = float64(s >> 32) * 2^32 + float64(s & 0xffffffff).  A
+            centre without samples keeps its previous location and values; one
+            without samples of a type keeps that type's previous value.
+  assign    a sample is compared with the centres whose window (Section
+            3.2.2: 2C_1 x 2C_2 x 2C_3 x 2C_4 around the centre) contains it,
+            |pos_d - c_d| <= C_d on every axis (R: among the centres seeded in
+            the 3^4 seed cells around the sample's own), by D_f or D_p
+            (Section 3.2.3) with S_st of Section 3.2.1:
+              S = sqrt(((dx*dx + dy*dy) + dz*dz) + (cf*dt)*(cf*dt))
+              D = w_v*|v - v_c| + w_d*S
+            in IEEE fp32, in that order (R), dx = x_s - x_c and so on.  The
+            smallest D wins, ties to the lowest id (R); a sample with no
+            candidate keeps its label (R).
+  converge  after the centres of an iteration are computed, the loop stops
+            when every one of the six values of every centre changed by at
+            most eps * |old| (R: the "percent change" of Section 3.2.2 read as
+            a relative change, in fp64) -- or after max_iter assignments.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+Q_BITS = 20
+Q_SCALE = float(1 << Q_BITS)
+F32 = np.float32
+
+
+def grid_interval(dims_xyzt, k):
+    """C_d = E_d / k_d in fp32 (Section 3.2.1)."""
+    return np.array([F32(e) / F32(kk) for e, kk in zip(dims_xyzt, k)], dtype=F32)
+
+
+def seed_cell(pos, C, kd):
+    """floor(pos / C) clamped to [0, kd - 1], fp32 division."""
+    c = np.floor((pos.astype(F32) / F32(C)).astype(F32))
+    return np.clip(c, 0, kd - 1).astype(np.int64)
+
+
+def centre_id(cx, cy, cz, ct, k):
+    kx, ky, kz, _ = k
+    return ((ct * kz + cz) * ky + cy) * kx + cx
+
+
+def quantise(v):
+    """q(v) = rint(v * 2^20) as an exact integer (v fp32 -> fp64 is exact)."""
+    return np.rint(np.asarray(v, np.float64) * Q_SCALE).astype(np.int64)
+
+
+def to_double(s):
+    """dbl(s) = float64(s >> 32) * 2^32 + float64(s & 0xffffffff)."""
+    s = np.asarray(s, np.int64)
+    hi = (s >> 32).astype(np.float64)
+    lo = (s & 0xFFFFFFFF).astype(np.float64)
+    return hi * 4294967296.0 + lo
+
+
+def samples(field, xyz, attr):
+    """Flatten both sample types: positions (fp32 [n][3]), times (int [n]),
+    values (fp32 [n]), type (0 field, 1 point), validity."""
+    T, Z, Y, X = field.shape
+    t, z, y, x = np.meshgrid(np.arange(T), np.arange(Z), np.arange(Y), np.arange(X), indexing="ij")
+    fpos = np.stack([x.ravel() + 0.5, y.ravel() + 0.5, z.ravel() + 0.5], 1).astype(F32)
+    ft = t.ravel().astype(np.int64)
+    fv = field.ravel().astype(F32)
+    P = attr.shape[1] if attr is not None else 0
+    if P:
+        ppos = xyz.reshape(T * P, 3).astype(F32)
+        pt = np.repeat(np.arange(T), P).astype(np.int64)
+        pv = attr.reshape(T * P).astype(F32)
+    else:
+        ppos = np.zeros((0, 3), F32)
+        pt = np.zeros(0, np.int64)
+        pv = np.zeros(0, F32)
+    pos = np.concatenate([fpos, ppos])
+    tt = np.concatenate([ft, pt])
+    val = np.concatenate([fv, pv])
+    typ = np.concatenate([np.zeros(len(fv), np.int64), np.ones(len(pv), np.int64)])
+    valid = np.isfinite(val) & np.all(np.isfinite(pos), axis=1)
+    return pos, tt, val, typ, valid
+
+
+def seed_centres(C, k):
+    """Seed centres: location ((i + 0.5) C_d), values 0; [K][6] fp64 as
+    (x, y, z, t, p, f)."""
+    kx, ky, kz, kt = k
+    K = kx * ky * kz * kt
+    cen = np.zeros((K, 6), np.float64)
+    for ct in range(kt):
+        for cz in range(kz):
+            for cy in range(ky):
+                for cx in range(kx):
+                    i = centre_id(cx, cy, cz, ct, k)
+                    cen[i, 0] = float(F32(cx + 0.5) * C[0])
+                    cen[i, 1] = float(F32(cy + 0.5) * C[1])
+                    cen[i, 2] = float(F32(cz + 0.5) * C[2])
+                    cen[i, 3] = float(F32(ct + 0.5) * C[3])
+    return cen
+
+
+def initial_labels(pos, tt, valid, C, k):
+    """Nearest seed centre = the seed cell's centre."""
+    cx = seed_cell(pos[:, 0], C[0], k[0])
+    cy = seed_cell(pos[:, 1], C[1], k[1])
+    cz = seed_cell(pos[:, 2], C[2], k[2])
+    ct = seed_cell(tt.astype(F32), C[3], k[3])
+    lab = centre_id(cx, cy, cz, ct, k)
+    return np.where(valid, lab, -1)
+
+
+def update_centres(pos, tt, val, typ, lab, prev, K):
+    """Means of the assigned samples from exact integer sums (see header).
+    Returns the new [K][6] centres and the counts [K][2] (field, point)."""
+    m = lab >= 0
+    ids = lab[m]
+    qx, qy, qz = quantise(pos[m, 0]), quantise(pos[m, 1]), quantise(pos[m, 2])
+    qt = tt[m].astype(np.int64) << Q_BITS
+    qv = quantise(val[m])
+    isf = typ[m] == 0
+
+    def isum(w, sel=None):
+        # exact in int64 while |sum| < 2^63, which the bounds on dimensions and
+        # values guarantee (fewer than 2^31 samples of |q| < 2^31)
+        idx = ids if sel is None else ids[sel]
+        ww = w if sel is None else w[sel]
+        acc = np.zeros(K, np.int64)
+        np.add.at(acc, idx, ww)
+        return acc
+
+    n_all = np.bincount(ids, minlength=K).astype(np.int64)
+    n_f = np.bincount(ids[isf], minlength=K).astype(np.int64)
+    n_p = n_all - n_f
+    sx, sy, sz, st = isum(qx), isum(qy), isum(qz), isum(qt)
+    sf = isum(qv, isf)
+    sp = isum(qv, ~isf)
+    cen = prev.copy()
+    for j, s in enumerate((sx, sy, sz, st)):
+        has = n_all > 0
+        cen[has, j] = to_double(s[has]) / n_all[has].astype(np.float64) / Q_SCALE
+    hp = n_p > 0
+    cen[hp, 4] = to_double(sp[hp]) / n_p[hp].astype(np.float64) / Q_SCALE
+    hf = n_f > 0
+    cen[hf, 5] = to_double(sf[hf]) / n_f[hf].astype(np.float64) / Q_SCALE
+    return cen, np.stack([n_f, n_p], 1)
+
+
+def assign(pos, tt, val, typ, lab, cen, C, k, w, cf):
+    """One assignment pass (Section 3.2.2-3.2.3, fp32 as in the header).
+    w = (w_d, w_f, w_p)."""
+    wd, wf, wp = F32(w[0]), F32(w[1]), F32(w[2])
+    cf = F32(cf)
+    c32 = cen.astype(F32)
+    n = len(val)
+    best_d = np.full(n, np.inf, F32)
+    best_i = np.full(n, np.iinfo(np.int64).max, np.int64)
+    scx = seed_cell(pos[:, 0], C[0], k[0])
+    scy = seed_cell(pos[:, 1], C[1], k[1])
+    scz = seed_cell(pos[:, 2], C[2], k[2])
+    sct = seed_cell(tt.astype(F32), C[3], k[3])
+    ts = tt.astype(F32)
+    wv = np.where(typ == 0, wf, wp).astype(F32)
+    for ot in (-1, 0, 1):
+        for oz in (-1, 0, 1):
+            for oy in (-1, 0, 1):
+                for ox in (-1, 0, 1):
+                    cx, cy, cz, ct = scx + ox, scy + oy, scz + oz, sct + ot
+                    ok = ((cx >= 0) & (cx < k[0]) & (cy >= 0) & (cy < k[1]) &
+                          (cz >= 0) & (cz < k[2]) & (ct >= 0) & (ct < k[3]))
+                    cid = np.where(ok, centre_id(cx, cy, cz, ct, k), 0)
+                    cc = c32[cid]
+                    dx = (pos[:, 0] - cc[:, 0]).astype(F32)
+                    dy = (pos[:, 1] - cc[:, 1]).astype(F32)
+                    dz = (pos[:, 2] - cc[:, 2]).astype(F32)
+                    dt = (ts - cc[:, 3]).astype(F32)
+                    inwin = (ok & (np.abs(dx) <= C[0]) & (np.abs(dy) <= C[1]) &
+                             (np.abs(dz) <= C[2]) & (np.abs(dt) <= C[3]))
+                    vc = np.where(typ == 0, cc[:, 5], cc[:, 4]).astype(F32)
+                    ctd = (cf * dt).astype(F32)
+                    sq = (((dx * dx + dy * dy).astype(F32) + dz * dz).astype(F32) + ctd * ctd).astype(F32)
+                    S = np.sqrt(sq).astype(F32)
+                    D = (wv * np.abs((val - vc).astype(F32)) + wd * S).astype(F32)
+                    better = inwin & ((D < best_d) | ((D == best_d) & (cid < best_i)))
+                    best_d = np.where(better, D, best_d)
+                    best_i = np.where(better, cid, best_i)
+    found = best_i != np.iinfo(np.int64).max
+    out = np.where(found, best_i, lab)
+    valid = lab >= 0
+    return np.where(valid, out, -1)
+
+
+def converged(new, old, eps):
+    """Every value changed by at most eps * |old| (fp64)."""
+    return bool(np.all(np.abs(new - old) <= eps * np.abs(old)))
+
+
+def slic(field, xyz, attr, k, w, cf, eps, max_iter):
+    """The whole clustering.  field fp32 [T][Z][Y][X]; xyz fp32 [T][P][3] and
+    attr fp32 [T][P] (or None); k = (kx, ky, kz, kt); w = (w_d, w_f, w_p).
+    Returns (field labels int64 [T][Z][Y][X], point labels int64 [T][P],
+    centres fp64 [K][6] as (x, y, z, t, p, f), counts [K][2], iterations)."""
+    T, Z, Y, X = field.shape
+    k = tuple(int(v) for v in k)
+    K = k[0] * k[1] * k[2] * k[3]
+    C = grid_interval((X, Y, Z, T), k)
+    pos, tt, val, typ, valid = samples(field, xyz, attr)
+    lab = initial_labels(pos, tt, valid, C, k)
+    prev = seed_centres(C, k)
+    it = 0
+    while True:
+        cen, counts = update_centres(pos, tt, val, typ, lab, prev, K)
+        if (it > 0 and converged(cen, prev, eps)) or it == max_iter:
+            break
+        lab = assign(pos, tt, val, typ, lab, cen, C, k, w, cf)
+        prev = cen
+        it += 1
+    V = X * Y * Z * T
+    fl = lab[:V].reshape(T, Z, Y, X)
+    P = attr.shape[1] if attr is not None else 0
+    pl = lab[V:].reshape(T, P)
+    return fl, pl, cen, counts, it
