@@ -289,6 +289,56 @@ int mf4d_set_predictor(mf4d_ctx *ctx, mf4d_net *net, float logit_threshold);
 /* Statistics of the last grow, including member counts of the last reads. */
 int mf4d_last_stats(mf4d_ctx *ctx, mf4d_stats *out);
 
+/* ---- 4D SLIC clustering of the loaded point and field samples (Section 3.2) ----
+ *
+ * Samples: one per voxel-step, at the voxel centre (x+0.5, y+0.5, z+0.5), time
+ * t, value f; one per loaded particle-step, at its position, time t, value a.
+ * A sample with a non-finite position or value is not clustered (label -1).
+ * Centres start on a kx x ky x kz x kt grid of intervals C_d = E_d / k_d with
+ * E = (X, Y, Z, T) (Section 3.2.1); every sample first joins its grid cell's
+ * centre (the nearest).  An iteration recomputes each centre as the mean
+ * location of its samples, the mean point value and the mean field value
+ * (Section 3.2.2), then assigns each sample to the centre with the smallest
+ * D_f = w_f |f - f_c| + w_d S_st or D_p = w_p |a - p_c| + w_d S_st (Section
+ * 3.2.3), S_st being the 4D distance with time scaled by c_f (Section 3.2.1),
+ * among the centres whose 2C_1 x 2C_2 x 2C_3 x 2C_4 window (Section 3.2.2)
+ * holds the sample -- searched among the centres seeded in the 3^4 grid cells
+ * around the sample's own; ties go to the lowest centre id, and a sample with
+ * no candidate keeps its centre.  Centre id = ((ct*kz + cz)*ky + cy)*kx + cx.
+ * Means come from exact integer sums of coordinates and values quantised to
+ * 2^-20 (so they do not depend on the order of additions); distances are IEEE
+ * fp32 operations in a fixed order.  The loop stops when no centre value
+ * changed by more than eps times its previous magnitude (the relative-change
+ * test of Section 3.2.2), or after max_iter assignment passes. */
+
+/* k4 = (kx, ky, kz, kt), each in [1, 4096], at most 2^24 centres; weights and
+ * c_f finite and >= 0; eps >= 0; max_iter in [0, 100000].
+ * Errors: MF4D_ERR_ARG, MF4D_ERR_OOM. */
+int mf4d_slic_set_params(mf4d_ctx *ctx, const int *k4, float w_d, float w_f, float w_p, float c_f,
+                         double eps, int max_iter);
+
+/* Cluster the loaded field (and particles, if loaded).  *iterations (nullable)
+ * receives the number of assignment passes.  Waits for the device.
+ * Errors: MF4D_ERR_STATE (no field or no parameters), MF4D_ERR_UNSUPPORTED (a
+ * dimension >= 2048, or 2^31 samples or more), MF4D_ERR_RANGE (a coordinate
+ * or value with magnitude >= 2048: the exact sums could overflow; the labels
+ * are then not defined), MF4D_ERR_OOM, MF4D_ERR_HIP. */
+int mf4d_slic_run(mf4d_ctx *ctx, int *iterations);
+
+/* Labels of the last run: field int32 [T][Z][Y][X] (nf >= X*Y*Z*T) and point
+ * int32 [T][P] (np >= T*P); either pointer may be NULL.  With MF4D_DEVICE the
+ * copies are ordered on the context's stream and the call returns at once.
+ * Errors: MF4D_ERR_STATE (no run), MF4D_ERR_ARG (too small). */
+int mf4d_slic_read_labels(mf4d_ctx *ctx, int32_t *field_labels, size_t nf, int32_t *point_labels,
+                          size_t np, int where);
+
+/* Centres of the last run: fp64 [K][6] as (x, y, z, t, p_c, f_c) and int64
+ * [K][2] sample counts (field, point); either pointer may be NULL; K >=
+ * kx*ky*kz*kt.  A centre that never had samples of a type keeps 0 for that
+ * type's value; one without samples keeps its seed location.
+ * Errors: MF4D_ERR_STATE (no run), MF4D_ERR_ARG. */
+int mf4d_slic_read_centres(mf4d_ctx *ctx, double *centres, int64_t *counts, size_t K, int where);
+
 #ifdef __cplusplus
 }
 #endif

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmf4d.so")
-SOURCES = ["api.hip", "kernels.hip", "batched.hip", "nn.hip", "nn_api.hip"]
+SOURCES = ["api.hip", "kernels.hip", "batched.hip", "nn.hip", "nn_api.hip", "slic.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

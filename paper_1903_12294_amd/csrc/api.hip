@@ -13,6 +13,7 @@
 #include "mf4d_internal.h"
 #include "batched.h"
 #include "nn.h"
+#include "slic.h"
 
 #include <algorithm>
 #include <vector>
@@ -160,11 +161,39 @@ struct mf4d_ctx {
     uint8_t* tpred = nullptr;   // NT
     mf4d_net* net = nullptr;
     float pred_thr = 0.0f;
+
+    // particles as loaded, for the clustering: xyz [T][P][3] then attr [T][P]
+    float* praw = nullptr;
+    // 4D SLIC clustering (Section 3.2)
+    bool slic_params = false;
+    int sk[4] = {1, 1, 1, 1};
+    float swd = 1.0f, swf = 1.0f, swp = 1.0f, scf = 1.0f;
+    double seps = 0.0;
+    int smax_iter = 10;
+    int sK = 0;
+    int32_t* slabels = nullptr;  // [V + T * P]
+    size_t slabels_n = 0;
+    unsigned long long* sacc = nullptr;
+    double* scen = nullptr;
+    float* scen32 = nullptr;
+    long long* scnt = nullptr;
+    uint32_t* scounters = nullptr;
+    uint32_t* h_scounters = nullptr;
+    bool slic_done = false;
+    int slic_iters = 0;
 };
 
 namespace {
 
+// Clustering labels (sized by the loaded samples); the centre buffers stay.
+void free_slic(mf4d_ctx* c) {
+    dev_free(c->slabels);
+    c->slabels_n = 0;
+    c->slic_done = false;
+}
+
 void free_field(mf4d_ctx* c) {
+    free_slic(c);
     dev_free(c->field);
     dev_free(c->Af);
     dev_free(c->Lf);
@@ -188,6 +217,8 @@ void free_field(mf4d_ctx* c) {
 }
 
 void free_particles(mf4d_ctx* c) {
+    dev_free(c->praw);
+    free_slic(c);
     dev_free(c->bins);
     dev_free(c->attr_t);
     dev_free(c->Ap);
@@ -436,6 +467,12 @@ void mf4d_destroy(mf4d_ctx* c) {
     dev_free(c->btab);
     dev_free(c->qseeds);
     dev_free(c->b_counters);
+    dev_free(c->sacc);
+    dev_free(c->scen);
+    dev_free(c->scen32);
+    dev_free(c->scnt);
+    dev_free(c->scounters);
+    if (c->h_scounters) (void)hipHostFree(c->h_scounters);
     if (c->staging) (void)hipFree(c->staging);
     if (c->h_counters) (void)hipHostFree(c->h_counters);
     if (c->h_stat) (void)hipHostFree(c->h_stat);
@@ -588,7 +625,22 @@ int mf4d_load_particles(mf4d_ctx* c, const float* xyz, const float* attr, int64_
     launch_particle_summaries(pg, c->attr_t, c->psum, c->stream);
     c->bstats_valid = false;
     launch_fill_u32(c->pdirty, 0, (P + 31) / 32, c->stream);
-    rc = sync(c);
+    // the clustering reads positions and values as loaded: keep the upload
+    // buffer, or copy device inputs into one laid out the same way
+    if (tmp) {
+        c->praw = tmp;
+        tmp = nullptr;
+    } else {
+        rc = dev_alloc(&c->praw, nxyz + nat);
+        if (!rc) {
+            hipError_t e = hipMemcpyAsync(c->praw, xyz, nxyz * sizeof(float), hipMemcpyDeviceToDevice, c->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(c->praw + nxyz, attr, nat * sizeof(float), hipMemcpyDeviceToDevice,
+                                   c->stream);
+            if (e != hipSuccess) rc = fail(MF4D_ERR_HIP, "particle copy failed: %s", hipGetErrorString(e));
+        }
+    }
+    if (!rc) rc = sync(c);
     if (tmp) (void)hipFree(tmp);
     if (rc) {
         free_particles(c);
@@ -1083,6 +1135,151 @@ int mf4d_last_stats(mf4d_ctx* c, mf4d_stats* out) {
     if (rc) return rc;
     *out = c->stats;
     return MF4D_OK;
+}
+
+// ---------------------------------------------------------------------------
+// 4D SLIC clustering (Section 3.2)
+
+int mf4d_slic_set_params(mf4d_ctx* c, const int* k4, float w_d, float w_f, float w_p, float c_f,
+                         double eps, int max_iter) {
+    if (!c || !k4) return fail(MF4D_ERR_ARG, "NULL argument");
+    int64_t K = 1;
+    for (int i = 0; i < 4; ++i) {
+        if (k4[i] < 1 || k4[i] > 4096) return fail(MF4D_ERR_ARG, "k[%d] = %d not in [1, 4096]", i, k4[i]);
+        K *= k4[i];
+    }
+    if (K > (1 << 24)) return fail(MF4D_ERR_ARG, "%lld centres exceed 2^24", (long long)K);
+    const float w[4] = {w_d, w_f, w_p, c_f};
+    for (int i = 0; i < 4; ++i)
+        if (!(w[i] >= 0.0f && w[i] <= 3.4e38f)) return fail(MF4D_ERR_ARG, "weights and c_f must be finite and >= 0");
+    if (!(eps >= 0.0 && eps <= 1.7e308)) return fail(MF4D_ERR_ARG, "eps must be finite and >= 0");
+    if (max_iter < 0 || max_iter > 100000) return fail(MF4D_ERR_ARG, "max_iter %d not in [0, 100000]", max_iter);
+    HIP_TRY(hipSetDevice(c->device));
+    if ((int)K != c->sK) {
+        dev_free(c->sacc);
+        dev_free(c->scen);
+        dev_free(c->scen32);
+        dev_free(c->scnt);
+        c->sK = 0;
+        int rc = dev_alloc(&c->sacc, (size_t)K * kSlicAcc);
+        if (!rc) rc = dev_alloc(&c->scen, (size_t)K * 6);
+        if (!rc) rc = dev_alloc(&c->scen32, (size_t)K * 8);
+        if (!rc) rc = dev_alloc(&c->scnt, (size_t)K * 2);
+        if (!rc && !c->scounters) rc = dev_alloc(&c->scounters, (size_t)kSlicCounters);
+        if (!rc && !c->h_scounters &&
+            hipHostMalloc((void**)&c->h_scounters, kSlicCounters * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess)
+            rc = fail(MF4D_ERR_OOM, "pinned counters");
+        if (rc) return rc;
+        c->sK = (int)K;
+    }
+    for (int i = 0; i < 4; ++i) c->sk[i] = k4[i];
+    c->swd = w_d;
+    c->swf = w_f;
+    c->swp = w_p;
+    c->scf = c_f;
+    c->seps = eps;
+    c->smax_iter = max_iter;
+    c->slic_params = true;
+    c->slic_done = false;
+    return MF4D_OK;
+}
+
+int mf4d_slic_run(mf4d_ctx* c, int* iterations) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    if (!c->has_field) return fail(MF4D_ERR_STATE, "no field loaded");
+    if (!c->slic_params) return fail(MF4D_ERR_STATE, "no clustering parameters set");
+    const Geom& g = c->g;
+    if (g.X >= 2048 || g.Y >= 2048 || g.Z >= 2048 || g.T >= 2048)
+        return fail(MF4D_ERR_UNSUPPORTED, "clustering needs every dimension below 2048");
+    const int64_t P = c->has_particles ? c->pg.P : 0;
+    const size_t V = (size_t)g.X * g.Y * g.Z * g.T, Qp = (size_t)g.T * P;
+    if (V + Qp >= (size_t)1 << 31) return fail(MF4D_ERR_UNSUPPORTED, "more than 2^31 samples");
+    HIP_TRY(hipSetDevice(c->device));
+    c->slic_done = false;
+    if (c->slabels_n != V + Qp) {
+        dev_free(c->slabels);
+        c->slabels_n = 0;
+        int rc = dev_alloc(&c->slabels, V + Qp);
+        if (rc) return rc;
+        c->slabels_n = V + Qp;
+    }
+    DevS s{};
+    s.X = g.X; s.Y = g.Y; s.Z = g.Z; s.T = g.T;
+    s.P = P;
+    for (int i = 0; i < 4; ++i) s.k[i] = c->sk[i];
+    s.K = c->sK;
+    const float E[4] = {(float)g.X, (float)g.Y, (float)g.Z, (float)g.T};
+    for (int i = 0; i < 4; ++i) s.C[i] = E[i] / (float)c->sk[i];
+    s.wd = c->swd; s.wf = c->swf; s.wp = c->swp; s.cf = c->scf;
+    s.eps = c->seps;
+    s.field = c->field;
+    s.xyz = P ? c->praw : nullptr;
+    s.attr = P ? c->praw + (size_t)3 * Qp : nullptr;
+    s.labels = c->slabels;
+    s.acc = c->sacc;
+    s.cen = c->scen;
+    s.cen32 = c->scen32;
+    s.cnt = c->scnt;
+    s.counters = c->scounters;
+    hipStream_t st = c->stream;
+    launch_fill_u32((uint32_t*)c->sacc, 0, (uint64_t)c->sK * kSlicAcc * 2, st);
+    launch_fill_u32(c->scounters, 0, kSlicCounters, st);
+    launch_slic_init(s, st);
+    launch_slic_update(s, 1, st);
+    int it = 0;
+    while (it < c->smax_iter) {
+        launch_fill_u32(c->scounters + SC_MOVED, 0, 1, st);
+        launch_slic_assign(s, st);
+        ++it;
+        launch_slic_update(s, 0, st);
+        HIP_TRY(hipMemcpyAsync(c->h_scounters, c->scounters, kSlicCounters * sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, st));
+        int rc = sync(c);
+        if (rc) return rc;
+        if (c->h_scounters[SC_RANGE]) break;
+        if (c->h_scounters[SC_MOVED] == 0) break;
+    }
+    HIP_TRY(hipMemcpyAsync(c->h_scounters, c->scounters, kSlicCounters * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, st));
+    int rc = sync(c);
+    if (rc) return rc;
+    if (c->h_scounters[SC_RANGE])
+        return fail(MF4D_ERR_RANGE, "a coordinate or value with |v| >= 2048: the clustering's exact sums could overflow");
+    c->slic_iters = it;
+    c->slic_done = true;
+    if (iterations) *iterations = it;
+    return MF4D_OK;
+}
+
+int mf4d_slic_read_labels(mf4d_ctx* c, int32_t* field_labels, size_t nf, int32_t* point_labels, size_t np,
+                          int where) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    if (!c->slic_done) return fail(MF4D_ERR_STATE, "no clustering run");
+    if (where != MF4D_HOST && where != MF4D_DEVICE) return fail(MF4D_ERR_ARG, "bad where");
+    const Geom& g = c->g;
+    const size_t V = (size_t)g.X * g.Y * g.Z * g.T, Qp = c->slabels_n - V;
+    if (field_labels && nf < V) return fail(MF4D_ERR_ARG, "field labels hold %zu, %zu needed", nf, V);
+    if (point_labels && np < Qp) return fail(MF4D_ERR_ARG, "point labels hold %zu, %zu needed", np, Qp);
+    HIP_TRY(hipSetDevice(c->device));
+    const hipMemcpyKind kind = where == MF4D_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    if (field_labels) HIP_TRY(hipMemcpyAsync(field_labels, c->slabels, V * sizeof(int32_t), kind, c->stream));
+    if (point_labels && Qp)
+        HIP_TRY(hipMemcpyAsync(point_labels, c->slabels + V, Qp * sizeof(int32_t), kind, c->stream));
+    if (where == MF4D_DEVICE) return MF4D_OK;  // stream-ordered
+    return sync(c);
+}
+
+int mf4d_slic_read_centres(mf4d_ctx* c, double* centres, int64_t* counts, size_t K, int where) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    if (!c->slic_done) return fail(MF4D_ERR_STATE, "no clustering run");
+    if (where != MF4D_HOST && where != MF4D_DEVICE) return fail(MF4D_ERR_ARG, "bad where");
+    if (K < (size_t)c->sK) return fail(MF4D_ERR_ARG, "room for %zu centres, %d needed", K, c->sK);
+    HIP_TRY(hipSetDevice(c->device));
+    const hipMemcpyKind kind = where == MF4D_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    if (centres) HIP_TRY(hipMemcpyAsync(centres, c->scen, (size_t)c->sK * 6 * sizeof(double), kind, c->stream));
+    if (counts) HIP_TRY(hipMemcpyAsync(counts, c->scnt, (size_t)c->sK * 2 * sizeof(int64_t), kind, c->stream));
+    if (where == MF4D_DEVICE) return MF4D_OK;  // stream-ordered
+    return sync(c);
 }
 
 }  // extern "C"

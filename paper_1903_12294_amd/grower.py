@@ -178,6 +178,54 @@ class Grower:
                 self.ctx, out.ctypes.data_as(ctypes.c_void_p), n, MF4D_HOST))
         return out
 
+    # -- 4D SLIC clustering (Section 3.2) ------------------------------------
+    def slic_set_params(self, k, w_d: float, w_f: float, w_p: float, c_f: float, eps: float,
+                        max_iter: int):
+        """k = (kx, ky, kz, kt) centres per axis; distance weights and the
+        time-to-space factor of Sections 3.2.1 and 3.2.3; relative-change
+        threshold and iteration cap of Section 3.2.2."""
+        k4 = (ctypes.c_int * 4)(*[int(v) for v in k])
+        self._check(self.lib.mf4d_slic_set_params(self.ctx, k4, float(w_d), float(w_f), float(w_p),
+                                                  float(c_f), float(eps), int(max_iter)))
+        self.slic_K = int(k[0]) * int(k[1]) * int(k[2]) * int(k[3])
+
+    def slic_run(self) -> int:
+        """Cluster the loaded samples; returns the number of assignment passes."""
+        it = ctypes.c_int(0)
+        self._check(self.lib.mf4d_slic_run(self.ctx, ctypes.byref(it)))
+        return int(it.value)
+
+    def slic_read_labels(self, field_out=None, point_out=None):
+        """(field int32 [T][Z][Y][X], point int32 [T][P]); outputs may be
+        device tensors (int32) or numpy arrays."""
+        X, Y, Z = self.dims
+        T, P = self.T, self.P
+        if field_out is None:
+            field_out = np.zeros((T, Z, Y, X), np.int32)
+        if point_out is None:
+            point_out = np.zeros((T, P), np.int32)
+        dev = _is_device_tensor(field_out)
+        if dev != _is_device_tensor(point_out):
+            raise ValueError("both outputs on the device or both on the host")
+
+        def ptr(a):
+            return ctypes.c_void_p(a.data_ptr()) if dev else a.ctypes.data_as(ctypes.c_void_p)
+        n_f = field_out.numel() if dev else field_out.size
+        n_p = point_out.numel() if dev else point_out.size
+        self._check(self.lib.mf4d_slic_read_labels(self.ctx, ptr(field_out), n_f,
+                                                   ptr(point_out) if n_p else None, n_p,
+                                                   MF4D_DEVICE if dev else MF4D_HOST))
+        return field_out, point_out
+
+    def slic_read_centres(self):
+        """(centres fp64 [K][6] as x, y, z, t, p_c, f_c; counts int64 [K][2])."""
+        K = self.slic_K
+        cen = np.zeros((K, 6), np.float64)
+        cnt = np.zeros((K, 2), np.int64)
+        self._check(self.lib.mf4d_slic_read_centres(self.ctx, cen.ctypes.data_as(ctypes.c_void_p),
+                                                    cnt.ctypes.data_as(ctypes.c_void_p), K, MF4D_HOST))
+        return cen, cnt
+
     # -- batched queries ----------------------------------------------------
     def set_queries(self, crit, seeds):
         """crit fp32 [Q][4] = (f_lo, f_hi, a_lo, a_hi); seeds int32 [S][5] = (x, y, z, t, q)."""

@@ -1,0 +1,158 @@
+"""GPU parity of the 4D SLIC clustering (Section 3.2): the HIP path, called
+through the C ABI, against the CPU oracle on the same seeded inputs -- labels
+and sample counts equal, centres bit-equal (exact integer sums, fp32
+distances in a fixed order on both sides), same number of iterations."""
+import numpy as np
+import pytest
+
+from oracle import slic as oslic
+from paper_1903_12294_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _case(seed, T, Z, Y, X, P, spread=1.0, nan=False):
+    rng = np.random.default_rng(seed)
+    field = rng.random((T, Z, Y, X), dtype=np.float32)
+    # a few smooth blobs so that clusters follow values, not only the grid
+    t, z, y, x = np.meshgrid(np.arange(T), np.arange(Z), np.arange(Y), np.arange(X), indexing="ij")
+    for _ in range(3):
+        c = rng.random(4) * np.array([X, Y, Z, T])
+        r2 = ((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2) / max(X, Y, Z) + (t - c[3]) ** 2 / max(T, 1)
+        field += (2.0 * np.exp(-r2)).astype(np.float32)
+    # particles, a few outside the domain (spread > 1)
+    lo = -(spread - 1) / 2
+    xyz = ((lo + spread * rng.random((T, P, 3))) * np.array([X, Y, Z])).astype(np.float32)
+    attr = rng.random((T, P), dtype=np.float32)
+    if nan and P:
+        field[0, 0, 0, 0] = np.nan
+        xyz[min(1, T - 1), 0, 1] = np.nan
+        attr[0, min(2, P - 1)] = np.inf
+    return field, xyz, attr
+
+
+def _run_gpu(field, xyz, attr, k, w, cf, eps, max_iter, device_inputs=True):
+    from paper_1903_12294_amd import Grower
+    _need_gpu()
+    g = Grower(device=0)
+    try:
+        dev = torch.device("cuda:0")
+        if device_inputs:
+            g.load_field(torch.from_numpy(np.ascontiguousarray(field)).to(dev))
+            if xyz is not None and xyz.shape[1] > 0:
+                g.load_particles(torch.from_numpy(np.ascontiguousarray(xyz)).to(dev),
+                                 torch.from_numpy(np.ascontiguousarray(attr)).to(dev))
+        else:
+            g.load_field(field)
+            if xyz is not None and xyz.shape[1] > 0:
+                g.load_particles(xyz, attr)
+        g.slic_set_params(k, w[0], w[1], w[2], cf, eps, max_iter)
+        it = g.slic_run()
+        fl, pl = g.slic_read_labels()
+        cen, cnt = g.slic_read_centres()
+    finally:
+        g.close()
+    return fl, pl, cen, cnt, it
+
+
+def _assert_parity(tag, field, xyz, attr, k, w=(1.0, 2.0, 2.0), cf=0.5, eps=1e-4, max_iter=8, **kw):
+    P = 0 if xyz is None else xyz.shape[1]
+    print(f"[slic] {tag} field {field.shape} P={P} k={k} w={w} cf={cf} eps={eps} it<={max_iter}", flush=True)
+    fl, pl, cen, cnt, it = _run_gpu(field, xyz, attr, k, w, cf, eps, max_iter, **kw)
+    ofl, opl, ocen, ocnt, oit = oslic.slic(field, xyz if P else None, attr if P else None, k, w, cf, eps,
+                                           max_iter)
+    assert it == oit, f"{tag}: {it} iterations vs {oit}"
+    assert np.array_equal(fl, ofl), f"{tag}: {int((fl != ofl).sum())} field labels differ"
+    if P:
+        assert np.array_equal(pl, opl), f"{tag}: {int((pl != opl).sum())} point labels differ"
+    assert np.array_equal(cnt, ocnt), f"{tag}: counts differ"
+    assert cen.tobytes() == ocen.tobytes(), f"{tag}: centres differ, max {np.abs(cen - ocen).max()}"
+    return it
+
+
+def test_field_only_small():
+    field, _, _ = _case(1, 4, 8, 8, 16, 0)
+    _assert_parity("field-only", field, None, None, (2, 2, 2, 2))
+
+
+def test_field_and_points():
+    field, xyz, attr = _case(2, 8, 8, 16, 16, 300)
+    it = _assert_parity("field+points", field, xyz, attr, (4, 2, 2, 2))
+    assert it >= 2
+
+
+def test_points_outside_and_non_finite():
+    field, xyz, attr = _case(3, 6, 8, 8, 8, 200, spread=1.4, nan=True)
+    _assert_parity("outside+nan", field, xyz, attr, (2, 2, 2, 3))
+
+
+def test_ragged_dims_and_unit_axes():
+    field, xyz, attr = _case(4, 3, 5, 7, 13, 57)
+    _assert_parity("ragged", field, xyz, attr, (3, 1, 2, 1), w=(0.5, 4.0, 1.0), cf=2.0)
+
+
+def test_host_inputs():
+    field, xyz, attr = _case(5, 4, 8, 8, 16, 64)
+    _assert_parity("host-inputs", field, xyz, attr, (2, 2, 2, 2), device_inputs=False)
+
+
+@pytest.mark.parametrize("max_iter", [0, 1, 2])
+def test_iteration_caps(max_iter):
+    field, xyz, attr = _case(6, 4, 8, 8, 8, 40)
+    assert _assert_parity(f"cap{max_iter}", field, xyz, attr, (2, 2, 2, 2), max_iter=max_iter) <= max_iter
+
+
+def test_value_only_and_space_only_weights():
+    field, xyz, attr = _case(7, 4, 8, 8, 16, 100)
+    _assert_parity("value-only", field, xyz, attr, (2, 2, 2, 2), w=(0.0, 1.0, 1.0))
+    _assert_parity("space-only", field, xyz, attr, (2, 2, 2, 2), w=(1.0, 0.0, 0.0), cf=0.0)
+
+
+def test_many_centres_per_block():
+    """A block of 1024 consecutive samples meets more centres than its LDS
+    table holds (64): the overflow path (direct global sums) must agree."""
+    field, xyz, attr = _case(8, 2, 2, 64, 16, 32)
+    _assert_parity("table-overflow", field, xyz, attr, (16, 64, 1, 1), w=(1.0, 0.5, 0.5), max_iter=3)
+
+
+def test_synthetic_32cube_workload():
+    """The 32^3 x 8 workload with 4,096 particles (the grower's small
+    configuration) clustered into 4 x 4 x 4 x 2 centres."""
+    inst = synth.make_config(1)
+    _assert_parity("32^3x8", inst["field"], inst["xyz"], inst["attr"], (4, 4, 4, 2), w=(1.0, 8.0, 8.0),
+                   cf=2.0, eps=1e-3, max_iter=10)
+
+
+def test_errors():
+    from paper_1903_12294_amd import Grower
+    from paper_1903_12294_amd._lib import MF4DError
+    _need_gpu()
+    g = Grower(device=0)
+    try:
+        field = np.zeros((2, 2, 2, 2), np.float32)
+        g.load_field(field)
+        with pytest.raises(MF4DError):
+            g.slic_run()  # no parameters
+        with pytest.raises(MF4DError):
+            g.slic_set_params((0, 1, 1, 1), 1, 1, 1, 1, 0, 5)
+        with pytest.raises(MF4DError):
+            g.slic_set_params((1, 1, 1, 1), -1, 1, 1, 1, 0, 5)
+        g.slic_set_params((1, 1, 1, 1), 1, 1, 1, 1, 0, 5)
+        field[1, 1, 1, 1] = 4096.0  # outside the exact-sum range
+        g.load_field(field)
+        with pytest.raises(MF4DError):
+            g.slic_run()
+        g.load_field(np.zeros((1, 1, 1, 2048), np.float32))
+        with pytest.raises(MF4DError):
+            g.slic_run()  # a dimension of 2048
+        with pytest.raises(MF4DError):
+            g.slic_read_labels()  # no successful run
+    finally:
+        g.close()
