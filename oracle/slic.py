@@ -58,6 +58,7 @@ def grid_interval(dims_xyzt, k):
 def seed_cell(pos, C, kd):
     """floor(pos / C) clamped to [0, kd - 1], fp32 division."""
     c = np.floor((pos.astype(F32) / F32(C)).astype(F32))
+    c = np.where(np.isnan(c), 0, c)  # non-finite samples are not clustered; any cell will do
     return np.clip(c, 0, kd - 1).astype(np.int64)
 
 
