@@ -164,6 +164,9 @@ struct mf4d_ctx {
 
     // particles as loaded, for the clustering: xyz [T][P][3] then attr [T][P]
     float* praw = nullptr;
+    uint32_t* porder = nullptr;  // point samples sorted by tile (built on the first clustering)
+    float4* spos = nullptr;      // their positions and times in that order
+    float* sattr = nullptr;      // their values in that order
     // 4D SLIC clustering (Section 3.2)
     bool slic_params = false;
     int sk[4] = {1, 1, 1, 1};
@@ -179,6 +182,7 @@ struct mf4d_ctx {
     long long* scnt = nullptr;
     uint32_t* scounters = nullptr;
     uint32_t* h_scounters = nullptr;
+    uint32_t* sslab = nullptr;  // 8 x 4096 slab bounds (k_d <= 4096)
     bool slic_done = false;
     int slic_iters = 0;
 };
@@ -218,6 +222,9 @@ void free_field(mf4d_ctx* c) {
 
 void free_particles(mf4d_ctx* c) {
     dev_free(c->praw);
+    dev_free(c->porder);
+    dev_free(c->spos);
+    dev_free(c->sattr);
     free_slic(c);
     dev_free(c->bins);
     dev_free(c->attr_t);
@@ -472,6 +479,7 @@ void mf4d_destroy(mf4d_ctx* c) {
     dev_free(c->scen32);
     dev_free(c->scnt);
     dev_free(c->scounters);
+    dev_free(c->sslab);
     if (c->h_scounters) (void)hipHostFree(c->h_scounters);
     if (c->staging) (void)hipFree(c->staging);
     if (c->h_counters) (void)hipHostFree(c->h_counters);
@@ -1166,6 +1174,7 @@ int mf4d_slic_set_params(mf4d_ctx* c, const int* k4, float w_d, float w_f, float
         if (!rc) rc = dev_alloc(&c->scen32, (size_t)K * 8);
         if (!rc) rc = dev_alloc(&c->scnt, (size_t)K * 2);
         if (!rc && !c->scounters) rc = dev_alloc(&c->scounters, (size_t)kSlicCounters);
+        if (!rc && !c->sslab) rc = dev_alloc(&c->sslab, (size_t)8 * 4096);
         if (!rc && !c->h_scounters &&
             hipHostMalloc((void**)&c->h_scounters, kSlicCounters * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess)
             rc = fail(MF4D_ERR_OOM, "pinned counters");
@@ -1203,6 +1212,28 @@ int mf4d_slic_run(mf4d_ctx* c, int* iterations) {
         if (rc) return rc;
         c->slabels_n = V + Qp;
     }
+    if (P > 0 && !c->porder) {
+        // point samples in tile order, so that a block of them meets few centres
+        int rc = dev_alloc(&c->porder, Qp);
+        if (!rc) rc = dev_alloc(&c->spos, Qp);
+        if (!rc) rc = dev_alloc(&c->sattr, Qp);
+        uint32_t* scratch = nullptr;
+        if (!rc) rc = dev_alloc(&scratch, (size_t)g.NT + 1 + 1 + 1025);
+        if (!rc) {
+            const int e = launch_slic_order(c->bins, c->praw, c->praw + (size_t)3 * Qp, P, c->pg.Tpad, c->pg.T,
+                                            5 + 6 + g.logBT, g.NT, scratch, c->porder, c->spos, c->sattr,
+                                            c->stream);
+            if (e != hipSuccess) rc = fail(MF4D_ERR_HIP, "clustering order: %s", hipGetErrorString((hipError_t)e));
+        }
+        if (!rc) rc = sync(c);
+        if (scratch) (void)hipFree(scratch);
+        if (rc) {
+            dev_free(c->porder);
+            dev_free(c->spos);
+            dev_free(c->sattr);
+            return rc;
+        }
+    }
     DevS s{};
     s.X = g.X; s.Y = g.Y; s.Z = g.Z; s.T = g.T;
     s.P = P;
@@ -1213,14 +1244,16 @@ int mf4d_slic_run(mf4d_ctx* c, int* iterations) {
     s.wd = c->swd; s.wf = c->swf; s.wp = c->swp; s.cf = c->scf;
     s.eps = c->seps;
     s.field = c->field;
-    s.xyz = P ? c->praw : nullptr;
-    s.attr = P ? c->praw + (size_t)3 * Qp : nullptr;
+    s.spos = P ? c->spos : nullptr;
+    s.sattr = P ? c->sattr : nullptr;
     s.labels = c->slabels;
     s.acc = c->sacc;
     s.cen = c->scen;
     s.cen32 = c->scen32;
     s.cnt = c->scnt;
     s.counters = c->scounters;
+    s.slab = c->sslab;
+    s.kmax = std::max(std::max(c->sk[0], c->sk[1]), std::max(c->sk[2], c->sk[3]));
     hipStream_t st = c->stream;
     launch_fill_u32((uint32_t*)c->sacc, 0, (uint64_t)c->sK * kSlicAcc * 2, st);
     launch_fill_u32(c->scounters, 0, kSlicCounters, st);
@@ -1263,8 +1296,19 @@ int mf4d_slic_read_labels(mf4d_ctx* c, int32_t* field_labels, size_t nf, int32_t
     HIP_TRY(hipSetDevice(c->device));
     const hipMemcpyKind kind = where == MF4D_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
     if (field_labels) HIP_TRY(hipMemcpyAsync(field_labels, c->slabels, V * sizeof(int32_t), kind, c->stream));
-    if (point_labels && Qp)
-        HIP_TRY(hipMemcpyAsync(point_labels, c->slabels + V, Qp * sizeof(int32_t), kind, c->stream));
+    if (point_labels && Qp) {
+        // point labels are kept in visiting order: put them back in [T][P]
+        int32_t* out = point_labels;
+        if (where == MF4D_HOST) {
+            void* st = nullptr;
+            int rc = staging_for(c, Qp * sizeof(int32_t), &st);
+            if (rc) return rc;
+            out = (int32_t*)st;
+        }
+        launch_slic_unsort(c->slabels + V, c->porder, Qp, out, c->stream);
+        if (where == MF4D_HOST)
+            HIP_TRY(hipMemcpyAsync(point_labels, out, Qp * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    }
     if (where == MF4D_DEVICE) return MF4D_OK;  // stream-ordered
     return sync(c);
 }

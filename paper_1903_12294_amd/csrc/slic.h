@@ -26,22 +26,40 @@ struct DevS {
     float wd, wf, wp, cf;
     double eps;
     const float* field;  // [T][Z][Y][X]
-    const float* xyz;    // [T][P][3]
-    const float* attr;   // [T][P]
-    int32_t* labels;     // [V + T * P]: field samples, then point samples [T][P]
+    const float4* spos;  // [T * P]: point samples in visiting order, (x, y, z, t)
+    const float* sattr;  // [T * P]: their values, same order
+    int32_t* labels;     // [V + T * P]: field samples [T][Z][Y][X], then point samples in
+                         // visiting order
     unsigned long long* acc;  // [K][kSlicAcc]
     double* cen;         // [K][6]: x, y, z, t, p, f
     float* cen32;        // [K][8]: the same rounded to fp32, then 2 unused
     long long* cnt;      // [K][2]: field and point samples of each centre
+    // Per axis d and seed-grid slab i (centres with cell index i on axis d):
+    // the least and greatest centre coordinate, as order-preserving keys,
+    // at [(0 * 4 + d) * kmax + i] (least) and [(1 * 4 + d) * kmax + i].
+    uint32_t* slab;
+    int kmax;            // max(k[0..3])
     uint32_t* counters;  // SlicCounter
 };
 
+// Visiting order of the point samples: particle-steps sorted by the tile
+// holding them (tile = voxel bit >> shift), steps in no voxel last; order[j]
+// = t * P + p of the j-th.  Their positions and times (spos) and values
+// (sattr) are copied in that order from xyz [T][P][3] and attr [T][P].  bins:
+// [P][Tpad] voxel bits (~0u: none); scratch: nb + 1 + 1025 words, nb = number
+// of tiles + 1.  Errors as a HIP result.
+int launch_slic_order(const uint32_t* bins, const float* xyz, const float* attr, int64_t P, int Tpad,
+                      int T, int shift, uint32_t ntiles, uint32_t* scratch, uint32_t* order, float4* spos,
+                      float* sattr, hipStream_t st);
+// Point labels from visiting order back to [T][P]: out[order[j]] = in[j].
+void launch_slic_unsort(const int32_t* in, const uint32_t* order, uint64_t Q, int32_t* out, hipStream_t st);
 // Labels from the seed cells, and their sums.
 void launch_slic_init(const DevS& s, hipStream_t st);
 // One assignment pass over both sample types, with the sums of the new labels.
 void launch_slic_assign(const DevS& s, hipStream_t st);
-// Centres from the sums (the sums cleared), compared with the previous ones.
-// seed: 1 to write the seed centres first (before the first update).
+// Centres from the sums (the sums cleared), compared with the previous ones,
+// and the slab bounds of the new centres.  seed: 1 to write the seed centres
+// first (before the first update).
 void launch_slic_update(const DevS& s, int seed, hipStream_t st);
 
 }  // namespace mf4d

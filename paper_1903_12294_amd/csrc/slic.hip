@@ -18,6 +18,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace mf4d {
 namespace {
 
@@ -45,20 +47,47 @@ __device__ __forceinline__ double to_double(long long s) {
     return hi * 4294967296.0 + lo;
 }
 
+// Order-preserving map of fp32 to uint32 (and back), for atomic min / max.
+__device__ __forceinline__ uint32_t float_key(float f) {
+    const uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float key_float(uint32_t k) {
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
+// The slabs c0 - 1 .. c0 + 1 of axis d (inside the grid) that can hold a
+// centre within C of p, as bits 0..2 for offsets -1, 0, +1.  Rounding of
+// p - c is monotone in c, so a centre of the slab that passes the window
+// test passes this one too: no candidate is lost.
+__device__ __forceinline__ unsigned slab_mask(const DevS& s, int d, int c0, float p) {
+    unsigned m = 0;
+    for (int o = -1; o <= 1; ++o) {
+        const int i = c0 + o;
+        if (i < 0 || i >= s.k[d]) continue;
+        const float lo = key_float(s.slab[(0 * 4 + d) * s.kmax + i]);
+        const float hi = key_float(s.slab[(1 * 4 + d) * s.kmax + i]);
+        if (__fsub_rn(p, hi) <= s.C[d] && __fsub_rn(p, lo) >= -s.C[d]) m |= 1u << (o + 1);
+    }
+    return m;
+}
+
 // Centre with the smallest distance among those seeded in the 3^4 cells
-// around the sample's seed cell whose window holds the sample; ties go to the
-// lowest id; none: `prev`.
-__device__ int assign_one(const DevS& s, float px, float py, float pz, float pt, float v, bool field,
-                          int prev) {
-    const int cx0 = seed_cell(px, s.C[0], s.k[0]), cy0 = seed_cell(py, s.C[1], s.k[1]);
-    const int cz0 = seed_cell(pz, s.C[2], s.k[2]), ct0 = seed_cell(pt, s.C[3], s.k[3]);
+// around the sample's seed cell (cx0 .. ct0) whose window holds the sample;
+// ties go to the lowest id; none: `prev`.  Only the slabs in the masks mx ..
+// mt (slab_mask) are visited: the others hold no centre near enough.
+__device__ int assign_cands(const DevS& s, float px, float py, float pz, float pt, float v, bool field,
+                            int prev, int cx0, int cy0, int cz0, int ct0, unsigned mx, unsigned my,
+                            unsigned mz, unsigned mt) {
     const float wv = field ? s.wf : s.wp;
     float best_d = INFINITY;
     int best = 0x7FFFFFFF;
-    for (int ct = max(ct0 - 1, 0); ct <= min(ct0 + 1, s.k[3] - 1); ++ct)
-        for (int cz = max(cz0 - 1, 0); cz <= min(cz0 + 1, s.k[2] - 1); ++cz)
-            for (int cy = max(cy0 - 1, 0); cy <= min(cy0 + 1, s.k[1] - 1); ++cy)
-                for (int cx = max(cx0 - 1, 0); cx <= min(cx0 + 1, s.k[0] - 1); ++cx) {
+    for (unsigned bt = mt; bt; bt &= bt - 1)
+        for (unsigned bz = mz; bz; bz &= bz - 1)
+            for (unsigned by = my; by; by &= by - 1)
+                for (unsigned bx = mx; bx; bx &= bx - 1) {
+                    const int ct = ct0 + __builtin_ctz(bt) - 1, cz = cz0 + __builtin_ctz(bz) - 1;
+                    const int cy = cy0 + __builtin_ctz(by) - 1, cx = cx0 + __builtin_ctz(bx) - 1;
                     const int id = ((ct * s.k[2] + cz) * s.k[1] + cy) * s.k[0] + cx;
                     const float4 c = reinterpret_cast<const float4*>(s.cen32)[2 * id];
                     const float2 cv = reinterpret_cast<const float2*>(s.cen32)[4 * id + 2];
@@ -67,19 +96,31 @@ __device__ int assign_one(const DevS& s, float px, float py, float pz, float pt,
                     if (!(fabsf(dx) <= s.C[0] && fabsf(dy) <= s.C[1] && fabsf(dz) <= s.C[2] &&
                           fabsf(dt) <= s.C[3]))
                         continue;
+                    const float vc = field ? cv.y : cv.x;
+                    const float A = __fmul_rn(wv, fabsf(__fsub_rn(v, vc)));
+                    // D = A + (w_d S) rounded is >= A: a value term above the
+                    // best distance cannot win (nor tie), so skip the rest
+                    if (A > best_d) continue;
                     const float ctd = __fmul_rn(s.cf, dt);
                     const float sq = __fadd_rn(
                         __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz)),
                         __fmul_rn(ctd, ctd));
                     const float S = __fsqrt_rn(sq);
-                    const float vc = field ? cv.y : cv.x;
-                    const float D = __fadd_rn(__fmul_rn(wv, fabsf(__fsub_rn(v, vc))), __fmul_rn(s.wd, S));
+                    const float D = __fadd_rn(A, __fmul_rn(s.wd, S));
                     if (D < best_d || (D == best_d && id < best)) {
                         best_d = D;
                         best = id;
                     }
                 }
     return best == 0x7FFFFFFF ? prev : best;
+}
+
+__device__ __forceinline__ int assign_one(const DevS& s, float px, float py, float pz, float pt, float v,
+                                          bool field, int prev) {
+    const int cx0 = seed_cell(px, s.C[0], s.k[0]), cy0 = seed_cell(py, s.C[1], s.k[1]);
+    const int cz0 = seed_cell(pz, s.C[2], s.k[2]), ct0 = seed_cell(pt, s.C[3], s.k[3]);
+    return assign_cands(s, px, py, pz, pt, v, field, prev, cx0, cy0, cz0, ct0, slab_mask(s, 0, cx0, px),
+                        slab_mask(s, 1, cy0, py), slab_mask(s, 2, cz0, pz), slab_mask(s, 3, ct0, pt));
 }
 
 // Block-local sums keyed by centre id (open addressing).  A sample whose
@@ -95,8 +136,16 @@ __device__ __forceinline__ void table_init(Table& tb) {
     __syncthreads();
 }
 
-__device__ __forceinline__ void add_sample(const DevS& s, Table& tb, int id, const long long* q,
-                                           bool field) {
+// One thread's running sums for the centre of its last samples.
+struct Run {
+    int id;  // -1: none
+    long long q[5];
+    long long n;
+};
+
+__device__ __forceinline__ void add_run(const DevS& s, Table& tb, const Run& r, bool field) {
+    if (r.id < 0) return;
+    const int id = r.id;
     unsigned long long* dst = nullptr;
     const unsigned h = ((unsigned)id * 2654435761u) >> 26;
     for (int k = 0; k < kTab; ++k) {
@@ -108,12 +157,26 @@ __device__ __forceinline__ void add_sample(const DevS& s, Table& tb, int id, con
         }
     }
     if (!dst) dst = s.acc + (size_t)id * kSlicAcc;  // table full: global (device-scope) atomics
-    atomicAdd(&dst[SA_X], (unsigned long long)q[0]);
-    atomicAdd(&dst[SA_Y], (unsigned long long)q[1]);
-    atomicAdd(&dst[SA_Z], (unsigned long long)q[2]);
-    atomicAdd(&dst[SA_T], (unsigned long long)q[3]);
-    atomicAdd(&dst[field ? SA_F : SA_P], (unsigned long long)q[4]);
-    atomicAdd(&dst[field ? SA_NF : SA_NP], 1ull);
+    atomicAdd(&dst[SA_X], (unsigned long long)r.q[0]);
+    atomicAdd(&dst[SA_Y], (unsigned long long)r.q[1]);
+    atomicAdd(&dst[SA_Z], (unsigned long long)r.q[2]);
+    atomicAdd(&dst[SA_T], (unsigned long long)r.q[3]);
+    atomicAdd(&dst[field ? SA_F : SA_P], (unsigned long long)r.q[4]);
+    atomicAdd(&dst[field ? SA_NF : SA_NP], (unsigned long long)r.n);
+}
+
+// Add one sample to the thread's run; a sample of another centre first adds
+// the run to the block's sums.
+__device__ __forceinline__ void run_sample(const DevS& s, Table& tb, Run& r, int id, const long long* q,
+                                           bool field) {
+    if (id != r.id) {
+        add_run(s, tb, r, field);
+        r.id = id;
+        r.n = 0;
+        for (int k = 0; k < 5; ++k) r.q[k] = 0;
+    }
+    for (int k = 0; k < 5; ++k) r.q[k] += q[k];
+    ++r.n;
 }
 
 __device__ __forceinline__ void table_flush(const DevS& s, Table& tb) {
@@ -127,66 +190,110 @@ __device__ __forceinline__ void table_flush(const DevS& s, Table& tb) {
 }
 
 // Field samples: block b takes samples [b * 1024, (b + 1) * 1024) in
-// [T][Z][Y][X] order.  assign = 0: labels from the seed cells.
+// [T][Z][Y][X] order, 4 consecutive ones per thread (mostly of one centre:
+// the thread sums them before touching the block's table).  assign = 0:
+// labels from the seed cells.
 __global__ __launch_bounds__(kBlock) void k_slic_field(DevS s, int assign) {
     __shared__ Table tb;
     table_init(tb);
-    const uint64_t V = (uint64_t)s.X * s.Y * s.Z * s.T;
-    const uint64_t base = (uint64_t)blockIdx.x * (kBlock * kPer);
+    const uint32_t V = (uint32_t)s.X * s.Y * s.Z * s.T;  // < 2^31 (checked by the host)
+    const uint32_t i0 = blockIdx.x * (uint32_t)(kBlock * kPer) + threadIdx.x * kPer;
+    Run run;
+    run.id = -1;
+    // coordinates of the thread's first sample (32-bit arithmetic), then
+    // stepped along x; what depends only on (y, z, t) is computed per row
+    int x = 0, y = 0, z = 0, t = 0;
+    if (i0 < V) {
+        uint32_t r = i0;
+        x = (int)(r % (uint32_t)s.X);
+        r /= (uint32_t)s.X;
+        y = (int)(r % (uint32_t)s.Y);
+        r /= (uint32_t)s.Y;
+        z = (int)(r % (uint32_t)s.Z);
+        t = (int)(r / (uint32_t)s.Z);
+    }
+    float py = 0.f, pz = 0.f, pt = 0.f;
+    int cy0 = 0, cz0 = 0, ct0 = 0;
+    unsigned my = 0, mz = 0, mt = 0;
+    bool row = false;  // row values current
     for (int j = 0; j < kPer; ++j) {
-        const uint64_t i = base + (uint64_t)j * kBlock + threadIdx.x;
+        const uint32_t i = i0 + j;
         if (i >= V) break;
+        if (j > 0 && ++x == s.X) {  // next row
+            x = 0;
+            row = false;
+            if (++y == s.Y) {
+                y = 0;
+                if (++z == s.Z) {
+                    z = 0;
+                    ++t;
+                }
+            }
+        }
         const float v = s.field[i];
         if (!isfinite(v)) {
             s.labels[i] = -1;
             continue;
         }
         if (!(fabsf(v) < kMaxAbs)) s.counters[SC_RANGE] = 1u;
-        uint64_t r = i;
-        const int x = (int)(r % s.X);
-        r /= s.X;
-        const int y = (int)(r % s.Y);
-        r /= s.Y;
-        const int z = (int)(r % s.Z);
-        const int t = (int)(r / s.Z);
-        const float px = (float)x + 0.5f, py = (float)y + 0.5f, pz = (float)z + 0.5f, pt = (float)t;
+        if (!row) {
+            py = (float)y + 0.5f;
+            pz = (float)z + 0.5f;
+            pt = (float)t;
+            cy0 = seed_cell(py, s.C[1], s.k[1]);
+            cz0 = seed_cell(pz, s.C[2], s.k[2]);
+            ct0 = seed_cell(pt, s.C[3], s.k[3]);
+            if (assign) {
+                my = slab_mask(s, 1, cy0, py);
+                mz = slab_mask(s, 2, cz0, pz);
+                mt = slab_mask(s, 3, ct0, pt);
+            }
+            row = true;
+        }
+        const float px = (float)x + 0.5f;
+        const int cx0 = seed_cell(px, s.C[0], s.k[0]);
         int id;
         if (assign) {
-            id = assign_one(s, px, py, pz, pt, v, true, s.labels[i]);
+            id = assign_cands(s, px, py, pz, pt, v, true, s.labels[i], cx0, cy0, cz0, ct0,
+                              slab_mask(s, 0, cx0, px), my, mz, mt);
         } else {
-            const int cx = seed_cell(px, s.C[0], s.k[0]), cy = seed_cell(py, s.C[1], s.k[1]);
-            const int cz = seed_cell(pz, s.C[2], s.k[2]), ct = seed_cell(pt, s.C[3], s.k[3]);
-            id = ((ct * s.k[2] + cz) * s.k[1] + cy) * s.k[0] + cx;
+            id = ((ct0 * s.k[2] + cz0) * s.k[1] + cy0) * s.k[0] + cx0;
         }
         s.labels[i] = id;
         const long long q[5] = {quantise(px), quantise(py), quantise(pz), (long long)t << 20, quantise(v)};
-        add_sample(s, tb, id, q, true);
+        run_sample(s, tb, run, id, q, true);
     }
+    add_run(s, tb, run, true);
     table_flush(s, tb);
 }
 
-// Point samples: block b takes particle-steps [b * 1024, (b + 1) * 1024) in
-// [T][P] order; their labels follow the field's.
+// Point samples in visiting order (particle-steps sorted by the tile holding
+// them, so that a block meets few centres, with positions, times and values
+// copied in that order): block b takes positions [b * 1024, (b + 1) * 1024),
+// 4 consecutive ones per thread.  Their labels follow the field's, in the
+// same order.
 __global__ __launch_bounds__(kBlock) void k_slic_points(DevS s, int assign) {
     __shared__ Table tb;
     table_init(tb);
     const uint64_t V = (uint64_t)s.X * s.Y * s.Z * s.T;
     const uint64_t Q = (uint64_t)s.T * s.P;
-    const uint64_t base = (uint64_t)blockIdx.x * (kBlock * kPer);
+    const uint64_t base = (uint64_t)blockIdx.x * (kBlock * kPer) + (uint64_t)threadIdx.x * kPer;
+    Run run;
+    run.id = -1;
     for (int j = 0; j < kPer; ++j) {
-        const uint64_t i = base + (uint64_t)j * kBlock + threadIdx.x;
-        if (i >= Q) break;
-        const float v = s.attr[i];
-        const float px = s.xyz[3 * i], py = s.xyz[3 * i + 1], pz = s.xyz[3 * i + 2];
-        int32_t* lab = s.labels + V + i;
+        const uint64_t o = base + j;
+        if (o >= Q) break;
+        const float4 pp = s.spos[o];
+        const float v = s.sattr[o];
+        const float px = pp.x, py = pp.y, pz = pp.z, pt = pp.w;
+        int32_t* lab = s.labels + V + o;
         if (!(isfinite(v) && isfinite(px) && isfinite(py) && isfinite(pz))) {
             *lab = -1;
             continue;
         }
         if (!(fabsf(v) < kMaxAbs && fabsf(px) < kMaxAbs && fabsf(py) < kMaxAbs && fabsf(pz) < kMaxAbs))
             s.counters[SC_RANGE] = 1u;
-        const int t = (int)(i / (uint64_t)s.P);
-        const float pt = (float)t;
+        const int t = (int)pt;
         int id;
         if (assign) {
             id = assign_one(s, px, py, pz, pt, v, false, *lab);
@@ -197,8 +304,9 @@ __global__ __launch_bounds__(kBlock) void k_slic_points(DevS s, int assign) {
         }
         *lab = id;
         const long long q[5] = {quantise(px), quantise(py), quantise(pz), (long long)t << 20, quantise(v)};
-        add_sample(s, tb, id, q, false);
+        run_sample(s, tb, run, id, q, false);
     }
+    add_run(s, tb, run, false);
     table_flush(s, tb);
 }
 
@@ -249,6 +357,16 @@ __global__ __launch_bounds__(256) void k_slic_update(DevS s, int seed) {
         }
         s.cnt[(size_t)i * 2] = nf;
         s.cnt[(size_t)i * 2 + 1] = np;
+        // slab bounds of the new centre, on each axis (from the fp32 copy the
+        // assignment compares with)
+        int r = i;
+        for (int d = 0; d < 4; ++d) {
+            const int cell = d < 3 ? r % s.k[d] : r;
+            r /= s.k[d];
+            const uint32_t key = float_key((float)nw[d]);
+            atomicMin(&s.slab[(0 * 4 + d) * s.kmax + cell], key);
+            atomicMax(&s.slab[(1 * 4 + d) * s.kmax + cell], key);
+        }
     }
     const unsigned long long m = __ballot(moved);
     if ((threadIdx.x & 63) == 0 && m) atomicAdd(&s.counters[SC_MOVED], (unsigned)__popcll(m));
@@ -256,7 +374,173 @@ __global__ __launch_bounds__(256) void k_slic_update(DevS s, int seed) {
 
 inline unsigned blocks_for(uint64_t n, uint64_t per) { return (unsigned)((n + per - 1) / per); }
 
+// ---- visiting order of the point samples (counting sort by tile) ----------
+
+constexpr uint32_t kSkip = 0xFFFFFFFFu;  // a padding step (t >= T): not a sample
+constexpr int kScanBlocks = 1024;
+
+// Sort key of particle-step e = p * Tpad + t.
+__device__ __forceinline__ uint32_t order_key(const uint32_t* bins, uint64_t e, uint64_t Qpad, int Tpad,
+                                              int T, int shift, uint32_t none) {
+    if (e >= Qpad) return kSkip;
+    const uint64_t p = e / (uint64_t)Tpad;
+    if ((int)(e - p * Tpad) >= T) return kSkip;
+    const uint32_t b = bins[e];
+    return b == 0xFFFFFFFFu ? none : b >> shift;
+}
+
+// A wave holds 64 consecutive steps; consecutive steps of a trajectory mostly
+// share a tile, so lanes split into runs of one key and only a run's first
+// lane (head) touches the key's counter.
+struct KeyRun {
+    int head, len;
+};
+
+__device__ __forceinline__ KeyRun key_run(uint32_t key) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t prev = (uint32_t)__shfl_up((int)key, 1);
+    const unsigned long long starts = __ballot(lane == 0 || prev != key);
+    const unsigned long long later = lane == 63 ? 0ull : starts >> (lane + 1);
+    KeyRun r;
+    r.len = later ? __builtin_ctzll(later) + 1 : 64 - lane;
+    const unsigned long long upto = lane == 63 ? starts : starts & ((2ull << lane) - 1);
+    r.head = 63 - __builtin_clzll(upto);  // lane 0 always starts a run
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_order_count(const uint32_t* __restrict__ bins, uint64_t Qpad,
+                                                     int Tpad, int T, int shift, uint32_t none,
+                                                     uint32_t* __restrict__ cnt) {
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t w = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6; w * 64 < Qpad; w += nwaves) {
+        const uint32_t key = order_key(bins, w * 64 + (threadIdx.x & 63), Qpad, Tpad, T, shift, none);
+        const KeyRun r = key_run(key);
+        if (key != kSkip && r.head == (int)(threadIdx.x & 63)) atomicAdd(&cnt[key], (uint32_t)r.len);
+    }
+}
+
+// Exclusive prefix of the 256 values of a block; `total` gets their sum.
+__device__ __forceinline__ uint32_t block_scan256(uint32_t v, uint32_t* s_w, uint32_t& total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[wave] = x;
+    __syncthreads();
+    uint32_t base = 0;
+    for (int i = 0; i < wave; ++i) base += s_w[i];
+    total = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+    __syncthreads();
+    return base + x - v;
+}
+
+// Counts -> exclusive offsets, in place, over n buckets: per-block sums of
+// consecutive ranges, one block scans them, each block writes its offsets.
+__global__ __launch_bounds__(256) void k_order_sums(const uint32_t* __restrict__ cnt, uint32_t n,
+                                                    uint32_t* __restrict__ bsum) {
+    const uint32_t per = (n + kScanBlocks - 1) / kScanBlocks;
+    const uint32_t i0 = blockIdx.x * per, i1 = min(n, i0 + per);
+    uint32_t c = 0;
+    for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) c += cnt[i];
+    for (int o = 32; o > 0; o >>= 1) c += (uint32_t)__shfl_xor((int)c, o);
+    __shared__ uint32_t s_w[4];
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) bsum[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+}
+
+__global__ __launch_bounds__(1024) void k_order_top(uint32_t* __restrict__ bsum) {
+    __shared__ uint32_t s_w[16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t v = bsum[threadIdx.x];
+    uint32_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[wave] = x;
+    __syncthreads();
+    uint32_t base = 0;
+    for (int i = 0; i < wave; ++i) base += s_w[i];
+    bsum[threadIdx.x] = base + x - v;
+}
+
+__global__ __launch_bounds__(256) void k_order_offsets(uint32_t* __restrict__ cnt, uint32_t n,
+                                                       const uint32_t* __restrict__ bsum) {
+    __shared__ uint32_t s_w[4];
+    const uint32_t per = (n + kScanBlocks - 1) / kScanBlocks;
+    const uint32_t i0 = blockIdx.x * per, i1 = min(n, i0 + per);
+    uint32_t base = bsum[blockIdx.x];
+    for (uint32_t b0 = i0; b0 < i1; b0 += blockDim.x) {  // block-uniform
+        const uint32_t i = b0 + threadIdx.x;
+        const uint32_t v = i < i1 ? cnt[i] : 0u;
+        uint32_t total;
+        const uint32_t ex = block_scan256(v, s_w, total);
+        if (i < i1) cnt[i] = base + ex;
+        base += total;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_order_scatter(const uint32_t* __restrict__ bins, uint64_t Qpad,
+                                                       int Tpad, int T, int shift, uint32_t none, int64_t P,
+                                                       uint32_t* __restrict__ cur, uint32_t* __restrict__ order,
+                                                       const float* __restrict__ xyz,
+                                                       const float* __restrict__ attr,
+                                                       float4* __restrict__ spos, float* __restrict__ sattr) {
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    for (uint64_t w = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6; w * 64 < Qpad; w += nwaves) {
+        const uint64_t e = w * 64 + lane;
+        const uint32_t key = order_key(bins, e, Qpad, Tpad, T, shift, none);
+        const KeyRun r = key_run(key);
+        uint32_t at = 0;
+        if (key != kSkip && r.head == lane) at = atomicAdd(&cur[key], (uint32_t)r.len);
+        at = (uint32_t)__shfl((int)at, r.head) + (uint32_t)(lane - r.head);
+        if (key != kSkip) {
+            const uint64_t p = e / (uint64_t)Tpad;
+            const uint64_t t = e - p * Tpad;
+            const uint64_t i = t * (uint64_t)P + p;
+            order[at] = (uint32_t)i;
+            spos[at] = make_float4(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], (float)t);
+            sattr[at] = attr[i];
+        }
+    }
+}
+
 }  // namespace
+
+__global__ __launch_bounds__(256) void k_slic_unsort(const int32_t* __restrict__ in,
+                                                     const uint32_t* __restrict__ order, uint64_t Q,
+                                                     int32_t* __restrict__ out) {
+    for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < Q; j += (uint64_t)gridDim.x * blockDim.x)
+        out[order[j]] = in[j];
+}
+
+void launch_slic_unsort(const int32_t* in, const uint32_t* order, uint64_t Q, int32_t* out, hipStream_t st) {
+    if (Q == 0) return;
+    const unsigned g = (unsigned)std::min<uint64_t>((Q + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_slic_unsort, dim3(g), dim3(256), 0, st, in, order, Q, out);
+}
+
+int launch_slic_order(const uint32_t* bins, const float* xyz, const float* attr, int64_t P, int Tpad,
+                      int T, int shift, uint32_t ntiles, uint32_t* scratch, uint32_t* order, float4* spos,
+                      float* sattr, hipStream_t st) {
+    const uint64_t Qpad = (uint64_t)P * Tpad;
+    const uint32_t nb = ntiles + 1;  // the last bucket: steps in no voxel
+    uint32_t* cnt = scratch;
+    uint32_t* bsum = scratch + nb + 1;
+    if (hipMemsetAsync(cnt, 0, (size_t)nb * sizeof(uint32_t), st) != hipSuccess) return (int)hipGetLastError();
+    const unsigned g = (unsigned)std::min<uint64_t>((Qpad + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_order_count, dim3(g), dim3(256), 0, st, bins, Qpad, Tpad, T, shift, ntiles, cnt);
+    hipLaunchKernelGGL(k_order_sums, dim3(kScanBlocks), dim3(256), 0, st, cnt, nb, bsum);
+    hipLaunchKernelGGL(k_order_top, dim3(1), dim3(kScanBlocks), 0, st, bsum);
+    hipLaunchKernelGGL(k_order_offsets, dim3(kScanBlocks), dim3(256), 0, st, cnt, nb, bsum);
+    hipLaunchKernelGGL(k_order_scatter, dim3(g), dim3(256), 0, st, bins, Qpad, Tpad, T, shift, ntiles, P, cnt,
+                       order, xyz, attr, spos, sattr);
+    return (int)hipGetLastError();
+}
 
 void launch_slic_init(const DevS& s, hipStream_t st) {
     const uint64_t V = (uint64_t)s.X * s.Y * s.Z * s.T, Q = (uint64_t)s.T * s.P;
@@ -270,7 +554,13 @@ void launch_slic_assign(const DevS& s, hipStream_t st) {
     if (Q) hipLaunchKernelGGL(k_slic_points, dim3(blocks_for(Q, kBlock * kPer)), dim3(kBlock), 0, st, s, 1);
 }
 
+__global__ void k_slic_slab_reset(DevS s) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 8 * s.kmax) s.slab[i] = i < 4 * s.kmax ? 0xFFFFFFFFu : 0u;
+}
+
 void launch_slic_update(const DevS& s, int seed, hipStream_t st) {
+    hipLaunchKernelGGL(k_slic_slab_reset, dim3(blocks_for((uint64_t)8 * s.kmax, 256)), dim3(256), 0, st, s);
     hipLaunchKernelGGL(k_slic_update, dim3(blocks_for((uint64_t)s.K, 256)), dim3(256), 0, st, s, seed);
 }
 
