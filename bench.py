@@ -153,6 +153,103 @@ def run_steps(g, fmask, pmask, steps: int, warmup: int, torch, instrumented: boo
                 ms_read=float(np.mean(reads)) if reads else 0.0, stats=last)
 
 
+SLIC_K = (16, 16, 16, 4)     # centres per axis (x, y, z, t): 16,384 centres
+SLIC_W = (1.0, 8.0, 8.0)     # w_d, w_f, w_p
+SLIC_CF = 2.0                # time-to-space factor
+SLIC_ITERS = 5
+
+
+def bench_slic(torch, log, inst, name):
+    """4D SLIC clustering (Section 3.2) of the same workload's 1.07e9 field and
+    2.7e8 point samples: time per iteration (runs of 1 and 1 + SLIC_ITERS
+    iterations with eps = 0, the difference), HBM bytes of an iteration
+    against peak, parity at full size on 20,000 sampled labels (the oracle
+    assigns them from the GPU's centres of the iteration before), and the
+    oracle's own speed on the 32^3 x 8 workload."""
+    from oracle import slic as oslic
+    from paper_1903_12294_amd import Grower, synth
+    dev = torch.device("cuda:0")
+    X, Y, Z = inst["dims"]
+    T, P = inst["T"], inst["P"]
+    V, Qs = X * Y * Z * T, T * P
+    g = Grower(device=0)
+    try:
+        g.load_field(torch.from_numpy(inst["field"]).to(dev))
+        g.load_particles(torch.from_numpy(inst["xyz"]).to(dev), torch.from_numpy(inst["attr"]).to(dev))
+
+        def run(m):
+            g.slic_set_params(SLIC_K, *SLIC_W, SLIC_CF, 0.0, m)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            it = g.slic_run()
+            torch.cuda.synchronize()
+            return it, time.perf_counter() - t0
+
+        run(1)  # builds the point samples' visiting order (once per particle load)
+        t1 = min(run(1)[1] for _ in range(2))
+        tn, itn = None, None
+        for _ in range(2):
+            itn, t = run(1 + SLIC_ITERS)
+            tn = t if tn is None else min(tn, t)
+        ms_iter = (tn - t1) / SLIC_ITERS * 1e3
+        # sampled parity at full size
+        m = 3
+        rng = np.random.default_rng(11)
+        fi = np.sort(rng.integers(0, V, 10000))
+        pi = np.sort(rng.integers(0, Qs, 10000))
+        fl = torch.empty((T, Z, Y, X), dtype=torch.int32, device=dev)
+        pl = torch.empty((T, P), dtype=torch.int32, device=dev)
+        fi_d, pi_d = torch.from_numpy(fi).to(dev), torch.from_numpy(pi).to(dev)
+        g.slic_set_params(SLIC_K, *SLIC_W, SLIC_CF, 0.0, m - 1)
+        g.slic_run()
+        cen_prev, _ = g.slic_read_centres()
+        g.slic_read_labels(fl, pl)
+        prev = np.concatenate([fl.view(-1)[fi_d].cpu().numpy(), pl.view(-1)[pi_d].cpu().numpy()])
+        g.slic_set_params(SLIC_K, *SLIC_W, SLIC_CF, 0.0, m)
+        it_m = g.slic_run()
+        g.slic_read_labels(fl, pl)
+        got = np.concatenate([fl.view(-1)[fi_d].cpu().numpy(), pl.view(-1)[pi_d].cpu().numpy()])
+        tt_f = fi // (X * Y * Z)
+        r = fi % (X * Y * Z)
+        z, r = r // (X * Y), r % (X * Y)
+        y, x = r // X, r % X
+        tp, pp = pi // P, pi % P
+        pos = np.concatenate([np.stack([x + 0.5, y + 0.5, z + 0.5], 1).astype(np.float32),
+                              inst["xyz"][tp, pp].astype(np.float32)])
+        tt = np.concatenate([tt_f, tp]).astype(np.int64)
+        val = np.concatenate([inst["field"].reshape(-1)[fi], inst["attr"][tp, pp]]).astype(np.float32)
+        typ = np.concatenate([np.zeros(len(fi), np.int64), np.ones(len(pi), np.int64)])
+        C = oslic.grid_interval((X, Y, Z, T), SLIC_K)
+        want = oslic.assign(pos, tt, val, typ, prev.astype(np.int64), cen_prev, C, SLIC_K, SLIC_W, SLIC_CF)
+        parity = bool(it_m == m and np.array_equal(want, got))
+    finally:
+        g.close()
+    # the oracle on the small workload, for a CPU reference
+    small = synth.make_config(1)
+    sX, sY, sZ = small["dims"]
+    sN = sX * sY * sZ * small["T"] + small["T"] * small["P"]
+    t0 = time.perf_counter()
+    oslic.slic(small["field"], small["xyz"], small["attr"], (4, 4, 4, 2), SLIC_W, SLIC_CF, 0.0, 3)
+    tc = time.perf_counter() - t0
+    N = V + Qs
+    # HBM bytes of an iteration: field value, label read and write (12 B); point
+    # position and time (16 B), value, label read and write (28 B)
+    b = 12 * V + 28 * Qs
+    gbs = b / (ms_iter * 1e-3) / 1e9
+    log(f"[bench] slic {ms_iter:.2f} ms/iteration, {N / (ms_iter * 1e-3):.3e} samples/s, parity {parity}")
+    return {"workload": f"{name}: {V} field + {Qs} point samples, k = {SLIC_K} "
+                        f"({SLIC_K[0] * SLIC_K[1] * SLIC_K[2] * SLIC_K[3]} centres), w_d/w_f/w_p = {SLIC_W}, "
+                        f"c_f = {SLIC_CF}",
+            "ms_per_iteration": round(ms_iter, 3), "value": round(N / (ms_iter * 1e-3), 1),
+            "unit": "samples/s per iteration",
+            "roofline": {"bound": "alu (distance evaluation)", "hbm_bytes_per_iteration": b,
+                         "achieved_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)},
+            "parity_sampled": parity, "parity_samples": int(len(got)),
+            "cpu_oracle": {"value": round(sN * 4 / tc, 1), "unit": "samples/s per iteration", "cores": 1,
+                           "sample": f"the 32^3 x 8 workload ({sN} samples), initial pass and 3 iterations, "
+                                     f"numpy ({tc:.1f}s)"}}
+
+
 def bench_batched(args, torch, log):
     """256 queries on the 128^3 x 32 workload: one batched grow (tile shape from
     the autotuner) versus one single-query grow per query."""
@@ -359,6 +456,8 @@ def main():
 
     if not args.no_forms:
         forms["batched"] = bench_batched(args, torch, log)
+        forms["slic"] = bench_slic(torch, log, inst, cfg["name"])
+        torch.cuda.empty_cache()
 
     cpu = None
     parity = None
