@@ -243,3 +243,88 @@ def slic(field, xyz, attr, k, w, cf, eps, max_iter):
     P = attr.shape[1] if attr is not None else 0
     pl = lab[V:].reshape(T, P)
     return fl, pl, cen, counts, it
+
+
+# ---- cluster merging and feature statistics (Section 3.3) -------------------
+#
+#   match     two centres match when, for each sample type, either neither has
+#             samples of it or both do and their means differ by at most
+#             eps_m * max(|a|, |b|) (R: the "percent difference" of Section
+#             3.3, relative to the larger magnitude); a centre without samples
+#             matches nothing (R).  Location is ignored (Section 3.3).
+#   merge     features are the connected components of "match" (R: merging is
+#             transitive), each named by its lowest centre id.
+#   stats     per feature: field and point sample counts; mean field and point
+#             values from the exact integer sums of the update (same formula);
+#             population standard deviations of the field and point values
+#             (fp64); extent: least and greatest x, y, z, t of its samples.
+
+
+def _matches(a, b, eps):
+    return np.abs(a - b) <= eps * np.maximum(np.abs(a), np.abs(b))
+
+
+def merge_centres(cen, counts, eps_m):
+    """Feature id (lowest centre id of its component) of every centre; -1 for
+    a centre without samples."""
+    K = len(cen)
+    nf, npt = counts[:, 0], counts[:, 1]
+    has = (nf + npt) > 0
+    parent = list(range(K))
+
+    def find(i):
+        while parent[i] != i:
+            parent[i] = parent[parent[i]]
+            i = parent[i]
+        return i
+
+    for i in range(K):
+        if not has[i]:
+            continue
+        j = np.arange(i + 1, K)
+        ok = has[j]
+        for col, n in ((5, nf), (4, npt)):
+            both = (n[i] > 0) & (n[j] > 0)
+            none = (n[i] == 0) & (n[j] == 0)
+            ok &= none | (both & _matches(cen[i, col], cen[j, col], eps_m))
+        for jj in j[ok]:
+            ri, rj = find(i), find(int(jj))
+            if ri != rj:
+                parent[max(ri, rj)] = min(ri, rj)
+    return np.array([find(i) if has[i] else -1 for i in range(K)], np.int64)
+
+
+def feature_stats(field, xyz, attr, fl, pl, feat):
+    """Per feature id (indexed by its lowest centre id, [K] rows; rows of
+    non-features are zero): n_f, n_p, mean f, mean p, std f, std p, then
+    x min, x max, y min, y max, z min, z max, t min, t max.  fp64 [K][14]."""
+    K = len(feat)
+    pos, tt, val, typ, valid = samples(field, xyz, attr)
+    lab = np.concatenate([fl.ravel(), pl.ravel()]) if pl is not None else fl.ravel()
+    m = lab >= 0
+    F = feat[lab[m]]
+    pos, tt, val, typ = pos[m], tt[m], val[m], typ[m]
+    out = np.zeros((K, 14), np.float64)
+    qv = quantise(val)
+    for ty, (cn, cm, cs) in ((0, (0, 2, 4)), (1, (1, 3, 5))):
+        sel = typ == ty
+        n = np.bincount(F[sel], minlength=K).astype(np.int64)
+        s = np.zeros(K, np.int64)
+        np.add.at(s, F[sel], qv[sel])
+        mean = np.where(n > 0, to_double(s) / np.maximum(n, 1).astype(np.float64) / Q_SCALE, 0.0)
+        dev = val[sel].astype(np.float64) - mean[F[sel]]
+        ss = np.zeros(K, np.float64)
+        np.add.at(ss, F[sel], dev * dev)
+        out[:, cn] = n
+        out[:, cm] = mean
+        out[:, cs] = np.where(n > 0, np.sqrt(ss / np.maximum(n, 1)), 0.0)
+    coords = [pos[:, 0], pos[:, 1], pos[:, 2], tt.astype(np.float32)]
+    for d, c in enumerate(coords):
+        lo = np.full(K, np.inf)
+        hi = np.full(K, -np.inf)
+        np.minimum.at(lo, F, c.astype(np.float64))
+        np.maximum.at(hi, F, c.astype(np.float64))
+        has = (out[:, 0] + out[:, 1]) > 0
+        out[:, 6 + 2 * d] = np.where(has, lo, 0.0)
+        out[:, 7 + 2 * d] = np.where(has, hi, 0.0)
+    return out

@@ -199,3 +199,55 @@ def test_empty_centre_keeps_its_values():
     assert (cen[0] == prev[0]).all()  # no samples
     assert cen[1, 4] == 2.0           # no point samples: p_c kept
     assert cen[1, 5] == 0.5 and cen[1, 0] == 1.0 and cen[1, 3] == 2.0
+
+
+# ---- cluster merging and feature statistics (Section 3.3) ----
+
+def _cen(rows):
+    """centres from (f, p, n_f, n_p) rows"""
+    cen = np.zeros((len(rows), 6))
+    cnt = np.zeros((len(rows), 2), np.int64)
+    for i, (f, p, nf, np_) in enumerate(rows):
+        cen[i, 5], cen[i, 4], cnt[i] = f, p, (nf, np_)
+    return cen, cnt
+
+
+def test_merge_is_transitive_and_named_by_lowest_id():
+    """1.00 ~ 1.09 ~ 1.18 at eps 0.1 (relative to the larger value), 1.00 and
+    1.18 do not match directly but share a feature; 5.0 stays alone."""
+    cen, cnt = _cen([(1.18, 0.0, 4, 0), (5.0, 0.0, 4, 0), (1.00, 0.0, 4, 0), (1.09, 0.0, 4, 0)])
+    assert S.merge_centres(cen, cnt, 0.1).tolist() == [0, 1, 0, 0]
+    assert S.merge_centres(cen, cnt, 0.0).tolist() == [0, 1, 2, 3]
+
+
+def test_merge_needs_both_types_to_match():
+    """Same field mean, point means apart: no merge; a centre with no point
+    samples never merges with one that has them; empty centres never merge."""
+    cen, cnt = _cen([(1.0, 0.2, 3, 3), (1.0, 0.9, 3, 3), (1.0, 0.2, 3, 0), (1.0, 0.2, 0, 0), (1.0, 0.21, 2, 2)])
+    assert S.merge_centres(cen, cnt, 0.1).tolist() == [0, 1, 2, -1, 0]
+
+
+def test_feature_stats_match_numpy_per_feature():
+    field, xyz, attr = rand_case(12, P=25)
+    fl, pl, cen, cnt, it = S.slic(field, xyz, attr, (2, 2, 2, 2), (1.0, 2.0, 2.0), 0.5, 1e-6, 4)
+    feat = S.merge_centres(cen, cnt, 0.15)
+    st = S.feature_stats(field, xyz, attr, fl, pl, feat)
+    T, Z, Y, X = field.shape
+    t, z, y, x = np.meshgrid(np.arange(T), np.arange(Z), np.arange(Y), np.arange(X), indexing="ij")
+    ff = feat[fl.ravel()]
+    fp = feat[pl.ravel()]
+    for F in np.unique(feat[feat >= 0]):
+        mf = ff == F
+        mp = fp == F
+        assert st[F, 0] == mf.sum() and st[F, 1] == mp.sum()
+        if mf.any():
+            fv = field.ravel()[mf].astype(np.float64)
+            assert abs(st[F, 2] - fv.mean()) < 1e-6 and abs(st[F, 4] - fv.std()) < 1e-6
+        if mp.any():
+            pv = attr.ravel()[mp].astype(np.float64)
+            assert abs(st[F, 3] - pv.mean()) < 1e-6 and abs(st[F, 5] - pv.std()) < 1e-6
+        xs = np.concatenate([(x + 0.5).ravel()[mf], xyz[..., 0].ravel()[mp]])
+        ts = np.concatenate([t.ravel()[mf], np.repeat(np.arange(T), xyz.shape[1])[mp]])
+        assert st[F, 6] == xs.min() and st[F, 7] == xs.max()
+        assert st[F, 12] == ts.min() and st[F, 13] == ts.max()
+    assert st[:, 0].sum() == field.size and st[:, 1].sum() == attr.size
