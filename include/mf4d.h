@@ -339,6 +339,27 @@ int mf4d_slic_read_labels(mf4d_ctx *ctx, int32_t *field_labels, size_t nf, int32
  * Errors: MF4D_ERR_STATE (no run), MF4D_ERR_ARG. */
 int mf4d_slic_read_centres(mf4d_ctx *ctx, double *centres, int64_t *counts, size_t K, int where);
 
+/* Merge the centres of the last run into features (Section 3.3): two centres
+ * match when, for each sample type, neither has samples of it or both do and
+ * their means differ by at most eps_m times the larger magnitude (location is
+ * ignored); a centre without samples matches nothing.  Features are the
+ * transitive groups of matching centres, each named by its lowest centre id
+ * (a background "supercluster" is simply the group its centres form).
+ * *n_features (nullable) receives their number.  Waits for the device.
+ * Errors: MF4D_ERR_STATE (no run), MF4D_ERR_ARG (eps_m not finite or < 0). */
+int mf4d_slic_merge(mf4d_ctx *ctx, double eps_m, int *n_features);
+
+/* Result of the last merge: the feature of each centre, int32 [K] (-1: a
+ * centre without samples), and per feature id fp64 [K][14]: field and point
+ * sample counts, mean field and point values (from the exact sums of the
+ * clustering), population standard deviations of the field and point values,
+ * then the least and greatest x, y, z and t of its samples (the extent of
+ * Section 3.3's feature list); rows of ids that name no feature hold zeros.
+ * Either pointer may be NULL.  Errors: MF4D_ERR_STATE (no merge since the
+ * last run), MF4D_ERR_ARG (K too small). */
+int mf4d_slic_read_features(mf4d_ctx *ctx, int32_t *feature_of_centre, double *stats, size_t K,
+                            int where);
+
 #ifdef __cplusplus
 }
 #endif

@@ -83,6 +83,8 @@ SIGNATURES = {
     "mf4d_slic_run": (c_int, [c_void_p, c_void_p]),
     "mf4d_slic_read_labels": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, c_int]),
     "mf4d_slic_read_centres": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_int]),
+    "mf4d_slic_merge": (c_int, [c_void_p, c_double, c_void_p]),
+    "mf4d_slic_read_features": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_int]),
     "mf4d_set_queries": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_int64, c_int]),
     "mf4d_grow_batched": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, c_int,
                                   POINTER(Stats)]),

@@ -183,6 +183,11 @@ struct mf4d_ctx {
     uint32_t* scounters = nullptr;
     uint32_t* h_scounters = nullptr;
     uint32_t* sslab = nullptr;  // 8 x 4096 slab bounds (k_d <= 4096)
+    unsigned long long* slsum = nullptr;  // [K][8] sums of the last update
+    // cluster merging (Section 3.3), sized by K
+    char* mbuf = nullptr;
+    DevM m{};
+    bool merged = false;
     bool slic_done = false;
     int slic_iters = 0;
 };
@@ -480,6 +485,8 @@ void mf4d_destroy(mf4d_ctx* c) {
     dev_free(c->scnt);
     dev_free(c->scounters);
     dev_free(c->sslab);
+    dev_free(c->slsum);
+    dev_free(c->mbuf);
     if (c->h_scounters) (void)hipHostFree(c->h_scounters);
     if (c->staging) (void)hipFree(c->staging);
     if (c->h_counters) (void)hipHostFree(c->h_counters);
@@ -1168,11 +1175,15 @@ int mf4d_slic_set_params(mf4d_ctx* c, const int* k4, float w_d, float w_f, float
         dev_free(c->scen);
         dev_free(c->scen32);
         dev_free(c->scnt);
+        dev_free(c->slsum);
+        dev_free(c->mbuf);
+        c->merged = false;
         c->sK = 0;
         int rc = dev_alloc(&c->sacc, (size_t)K * kSlicAcc);
         if (!rc) rc = dev_alloc(&c->scen, (size_t)K * 6);
         if (!rc) rc = dev_alloc(&c->scen32, (size_t)K * 8);
         if (!rc) rc = dev_alloc(&c->scnt, (size_t)K * 2);
+        if (!rc) rc = dev_alloc(&c->slsum, (size_t)K * kSlicAcc);
         if (!rc && !c->scounters) rc = dev_alloc(&c->scounters, (size_t)kSlicCounters);
         if (!rc && !c->sslab) rc = dev_alloc(&c->sslab, (size_t)8 * 4096);
         if (!rc && !c->h_scounters &&
@@ -1253,6 +1264,7 @@ int mf4d_slic_run(mf4d_ctx* c, int* iterations) {
     s.cnt = c->scnt;
     s.counters = c->scounters;
     s.slab = c->sslab;
+    s.lsum = c->slsum;
     s.kmax = std::max(std::max(c->sk[0], c->sk[1]), std::max(c->sk[2], c->sk[3]));
     hipStream_t st = c->stream;
     launch_fill_u32((uint32_t*)c->sacc, 0, (uint64_t)c->sK * kSlicAcc * 2, st);
@@ -1280,6 +1292,7 @@ int mf4d_slic_run(mf4d_ctx* c, int* iterations) {
         return fail(MF4D_ERR_RANGE, "a coordinate or value with |v| >= 2048: the clustering's exact sums could overflow");
     c->slic_iters = it;
     c->slic_done = true;
+    c->merged = false;
     if (iterations) *iterations = it;
     return MF4D_OK;
 }
@@ -1322,6 +1335,89 @@ int mf4d_slic_read_centres(mf4d_ctx* c, double* centres, int64_t* counts, size_t
     const hipMemcpyKind kind = where == MF4D_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
     if (centres) HIP_TRY(hipMemcpyAsync(centres, c->scen, (size_t)c->sK * 6 * sizeof(double), kind, c->stream));
     if (counts) HIP_TRY(hipMemcpyAsync(counts, c->scnt, (size_t)c->sK * 2 * sizeof(int64_t), kind, c->stream));
+    if (where == MF4D_DEVICE) return MF4D_OK;  // stream-ordered
+    return sync(c);
+}
+
+// The clustering's device state for the merge (the last run's buffers).
+static DevS slic_state(mf4d_ctx* c) {
+    const Geom& g = c->g;
+    DevS s{};
+    s.X = g.X; s.Y = g.Y; s.Z = g.Z; s.T = g.T;
+    s.P = c->has_particles ? c->pg.P : 0;
+    for (int i = 0; i < 4; ++i) s.k[i] = c->sk[i];
+    s.K = c->sK;
+    s.field = c->field;
+    s.spos = s.P ? c->spos : nullptr;
+    s.sattr = s.P ? c->sattr : nullptr;
+    s.labels = c->slabels;
+    s.cen = c->scen;
+    s.cnt = c->scnt;
+    s.lsum = c->slsum;
+    return s;
+}
+
+int mf4d_slic_merge(mf4d_ctx* c, double eps_m, int* n_features) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    if (!c->slic_done) return fail(MF4D_ERR_STATE, "no clustering run");
+    if (!(eps_m >= 0.0 && eps_m <= 1.7e308)) return fail(MF4D_ERR_ARG, "eps_m must be finite and >= 0");
+    HIP_TRY(hipSetDevice(c->device));
+    const size_t K = (size_t)c->sK;
+    if (!c->mbuf) {
+        // parent, feat (int), fsum (8 x u64), fmean (2 x f64), cext, fext (8 x u32),
+        // css, fss (2 x f64), out (kFeatStats x f64), err
+        // ten arrays, each started on a 256-byte boundary
+        const size_t bytes = K * (4 + 4 + 64 + 16 + 32 + 32 + 16 + 16 + 8 * kFeatStats) + 10 * 256;
+        int rc = dev_alloc(&c->mbuf, bytes);
+        if (rc) return rc;
+        char* p = c->mbuf;
+        auto take = [&](size_t n) { char* q = p; p += (n + 255) / 256 * 256; return q; };
+        DevM& m = c->m;
+        m.K = (int)K;
+        m.fsum = (unsigned long long*)take(K * 64);
+        m.fmean = (double*)take(K * 16);
+        m.css = (double*)take(K * 16);
+        m.fss = (double*)take(K * 16);
+        m.out = (double*)take(K * 8 * kFeatStats);
+        m.cext = (uint32_t*)take(K * 32);
+        m.fext = (uint32_t*)take(K * 32);
+        m.parent = (int*)take(K * 4);
+        m.feat = (int32_t*)take(K * 4);
+        m.err = (uint32_t*)take(4);
+        if ((size_t)(p - c->mbuf) > bytes) {
+            dev_free(c->mbuf);
+            return fail(MF4D_ERR_HIP, "internal error: merge buffer layout");
+        }
+    }
+    c->m.eps = eps_m;
+    launch_fill_u32(c->m.err, 0, 1, c->stream);
+    const int e = launch_slic_merge(slic_state(c), c->m, c->stream);
+    if (e != hipSuccess) return fail(MF4D_ERR_HIP, "merge: %s", hipGetErrorString((hipError_t)e));
+    std::vector<int32_t> feat(K);
+    uint32_t err = 0;
+    HIP_TRY(hipMemcpyAsync(feat.data(), c->m.feat, K * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(&err, c->m.err, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+    int rc = sync(c);
+    if (rc) return rc;
+    if (err) return fail(MF4D_ERR_HIP, "internal error: a union-find walk did not end");
+    int n = 0;
+    for (size_t i = 0; i < K; ++i) n += feat[i] == (int32_t)i;
+    if (n_features) *n_features = n;
+    c->merged = true;
+    return MF4D_OK;
+}
+
+int mf4d_slic_read_features(mf4d_ctx* c, int32_t* feature_of_centre, double* stats, size_t K, int where) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    if (!c->merged) return fail(MF4D_ERR_STATE, "no merge since the last clustering run");
+    if (where != MF4D_HOST && where != MF4D_DEVICE) return fail(MF4D_ERR_ARG, "bad where");
+    if (K < (size_t)c->sK) return fail(MF4D_ERR_ARG, "room for %zu centres, %d needed", K, c->sK);
+    HIP_TRY(hipSetDevice(c->device));
+    const hipMemcpyKind kind = where == MF4D_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    if (feature_of_centre)
+        HIP_TRY(hipMemcpyAsync(feature_of_centre, c->m.feat, (size_t)c->sK * sizeof(int32_t), kind, c->stream));
+    if (stats)
+        HIP_TRY(hipMemcpyAsync(stats, c->m.out, (size_t)c->sK * kFeatStats * sizeof(double), kind, c->stream));
     if (where == MF4D_DEVICE) return MF4D_OK;  // stream-ordered
     return sync(c);
 }

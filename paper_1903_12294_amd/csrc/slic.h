@@ -40,7 +40,34 @@ struct DevS {
     uint32_t* slab;
     int kmax;            // max(k[0..3])
     uint32_t* counters;  // SlicCounter
+    unsigned long long* lsum;  // [K][kSlicAcc]: the sums of the last update (for the features)
 };
+
+// Cluster merging and feature statistics (Section 3.3).  Feature ids are
+// centre ids (the lowest of each merged group).
+enum FeatStat : int {
+    FS_NF = 0, FS_NP, FS_MEAN_F, FS_MEAN_P, FS_STD_F, FS_STD_P,
+    FS_XMIN, FS_XMAX, FS_YMIN, FS_YMAX, FS_ZMIN, FS_ZMAX, FS_TMIN, FS_TMAX, kFeatStats
+};
+
+struct DevM {
+    int K;
+    double eps;
+    int* parent;             // [K] union-find links
+    int32_t* feat;           // [K] feature of each centre (-1: no samples)
+    unsigned long long* fsum;  // [K][kSlicAcc] integer sums per feature
+    double* fmean;           // [K][2] mean field, point value per feature
+    uint32_t* cext;          // [K][8] per centre: least x, y, z, t keys, then greatest
+    double* css;             // [K][2] per centre: squared deviations from its feature's means
+    uint32_t* fext;          // [K][8] per feature, the same
+    double* fss;             // [K][2] per feature
+    double* out;             // [K][kFeatStats]
+    uint32_t* err;           // set if a union-find wait ran out (never expected)
+};
+
+// Merge the centres of the last run (labels, centres, counts, sums in s) and
+// compute the features' statistics into m.out.  Errors as a HIP result.
+int launch_slic_merge(const DevS& s, const DevM& m, hipStream_t st);
 
 // Visiting order of the point samples: particle-steps sorted by the tile
 // holding them (tile = voxel bit >> shift), steps in no voxel last; order[j]

@@ -339,6 +339,7 @@ __global__ __launch_bounds__(256) void k_slic_update(DevS s, int seed) {
 #pragma unroll
         for (int j = 0; j < kSlicAcc; ++j) {
             sum[j] = (long long)a[j];
+            s.lsum[(size_t)i * kSlicAcc + j] = a[j];  // kept for the features (Section 3.3)
             a[j] = 0ull;
         }
         const long long nf = sum[SA_NF], np = sum[SA_NP], n = nf + np;
@@ -373,6 +374,266 @@ __global__ __launch_bounds__(256) void k_slic_update(DevS s, int seed) {
 }
 
 inline unsigned blocks_for(uint64_t n, uint64_t per) { return (unsigned)((n + per - 1) / per); }
+
+// ---- cluster merging and feature statistics (Section 3.3) ------------------
+//
+// Centres i < j match when, per sample type, neither has samples of it or
+// both do and their means differ by at most eps * max(|a|, |b|); centres
+// without samples match nothing.  Features are the connected components of
+// "match" (a lock-free union-find: a root is only ever linked to a smaller
+// root, so every component ends rooted at its lowest centre id, whatever the
+// order of the unions).  Per feature: exact means from the integer sums of
+// its centres, extents and squared deviations from one pass over the samples
+// keyed by centre (spatially coherent, like the clustering passes), folded
+// into the features.
+
+// Links are read with agent-scope atomic loads: a stale cached link could
+// keep a compare-and-swap loop failing.
+__device__ __forceinline__ int load_link(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Root of i; links strictly decrease, so the walk is at most K steps (the
+// bound only guards against the impossible).
+__device__ __forceinline__ int find_root(const int* parent, int i, int K) {
+    for (int k = 0; k <= K; ++k) {
+        const int p = load_link(&parent[i]);
+        if (p == i) return i;
+        i = p;
+    }
+    return -1;
+}
+
+__device__ bool unite(int* parent, int i, int j, int K) {
+    for (int k = 0; k <= K + 1; ++k) {  // every failed swap means another union succeeded
+        int a = find_root(parent, i, K), b = find_root(parent, j, K);
+        if (a < 0 || b < 0) return false;
+        if (a == b) return true;
+        if (a > b) {
+            const int t = a;
+            a = b;
+            b = t;
+        }
+        if (atomicCAS(&parent[b], b, a) == b) return true;
+    }
+    return false;
+}
+
+__device__ __forceinline__ bool centres_match(const DevS& s, double eps, int i, int j) {
+    for (int ty = 0; ty < 2; ++ty) {  // 0: field (value column 5), 1: points (column 4)
+        const bool hi = s.cnt[2 * (size_t)i + ty] > 0, hj = s.cnt[2 * (size_t)j + ty] > 0;
+        if (hi != hj) return false;
+        if (hi) {
+            const int col = ty == 0 ? 5 : 4;
+            const double a = s.cen[6 * (size_t)i + col], b = s.cen[6 * (size_t)j + col];
+            if (!(fabs(__dsub_rn(a, b)) <= __dmul_rn(eps, fmax(fabs(a), fabs(b))))) return false;
+        }
+    }
+    return true;
+}
+
+__device__ __forceinline__ bool has_samples(const DevS& s, int i) {
+    return s.cnt[2 * (size_t)i] + s.cnt[2 * (size_t)i + 1] > 0;
+}
+
+__global__ __launch_bounds__(256) void k_merge_init(DevS s, DevM m) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.K) return;
+    m.parent[i] = i;
+    for (int d = 0; d < 8; ++d) {
+        m.cext[8 * (size_t)i + d] = d < 4 ? 0xFFFFFFFFu : 0u;
+        m.fext[8 * (size_t)i + d] = d < 4 ? 0xFFFFFFFFu : 0u;
+        m.fsum[8 * (size_t)i + d] = 0ull;
+    }
+    for (int t = 0; t < 2; ++t) {
+        m.css[2 * (size_t)i + t] = 0.0;
+        m.fss[2 * (size_t)i + t] = 0.0;
+    }
+}
+
+// Thread i compares centre i with every later centre (K^2 / 2 tests).
+__global__ __launch_bounds__(256) void k_merge_pairs(DevS s, DevM m) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.K || !has_samples(s, i)) return;
+    for (int j = i + 1; j < m.K; ++j)
+        if (has_samples(s, j) && centres_match(s, m.eps, i, j) && !unite(m.parent, i, j, m.K)) m.err[0] = 1u;
+}
+
+__global__ __launch_bounds__(256) void k_merge_flatten(DevS s, DevM m) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.K) return;
+    int f = -1;
+    if (has_samples(s, i)) {
+        f = find_root(m.parent, i, m.K);
+        if (f < 0) m.err[0] = 1u;
+    }
+    m.feat[i] = f;
+}
+
+__global__ __launch_bounds__(256) void k_feature_sums(DevS s, DevM m) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.K || m.feat[i] < 0) return;
+    const int F = m.feat[i];
+    for (int j = 0; j < kSlicAcc; ++j) atomicAdd(&m.fsum[8 * (size_t)F + j], s.lsum[8 * (size_t)i + j]);
+}
+
+__global__ __launch_bounds__(256) void k_feature_means(DevS s, DevM m) {
+    const int F = blockIdx.x * blockDim.x + threadIdx.x;
+    if (F >= m.K || m.feat[F] != F) return;
+    const unsigned long long* a = m.fsum + 8 * (size_t)F;
+    const long long nf = (long long)a[SA_NF], np = (long long)a[SA_NP];
+    m.fmean[2 * (size_t)F] = nf > 0 ? __ddiv_rn(to_double((long long)a[SA_F]), (double)nf) * kQInv : 0.0;
+    m.fmean[2 * (size_t)F + 1] = np > 0 ? __ddiv_rn(to_double((long long)a[SA_P]), (double)np) * kQInv : 0.0;
+}
+
+// Block-local extents and squared deviations keyed by centre.
+struct StatTable {
+    int key[kTab];
+    uint32_t ext[kTab][8];
+    double ss[kTab];
+};
+
+struct StatRun {
+    int id;
+    uint32_t ext[8];
+    double ss;
+};
+
+__device__ __forceinline__ void stat_init(StatTable& tb) {
+    for (int i = threadIdx.x; i < kTab; i += blockDim.x) {
+        tb.key[i] = -1;
+        tb.ss[i] = 0.0;
+        for (int d = 0; d < 8; ++d) tb.ext[i][d] = d < 4 ? 0xFFFFFFFFu : 0u;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void stat_add(const DevM& m, StatTable& tb, const StatRun& r, int ty) {
+    if (r.id < 0) return;
+    uint32_t* ext = nullptr;
+    double* ss = nullptr;
+    const unsigned h = ((unsigned)r.id * 2654435761u) >> 26;
+    for (int k = 0; k < kTab; ++k) {
+        const int slot = (h + k) & (kTab - 1);
+        const int was = atomicCAS(&tb.key[slot], -1, r.id);
+        if (was == -1 || was == r.id) {
+            ext = tb.ext[slot];
+            ss = &tb.ss[slot];
+            break;
+        }
+    }
+    if (!ext) {  // table full: straight to the centre's accumulators
+        ext = m.cext + 8 * (size_t)r.id;
+        ss = m.css + 2 * (size_t)r.id + ty;
+    }
+    for (int d = 0; d < 4; ++d) {
+        atomicMin(&ext[d], r.ext[d]);
+        atomicMax(&ext[4 + d], r.ext[4 + d]);
+    }
+    atomicAdd(ss, r.ss);
+}
+
+__device__ __forceinline__ void stat_sample(const DevM& m, StatTable& tb, StatRun& r, int id, const float* c,
+                                            double dev, int ty) {
+    if (id != r.id) {
+        stat_add(m, tb, r, ty);
+        r.id = id;
+        r.ss = 0.0;
+        for (int d = 0; d < 4; ++d) {
+            r.ext[d] = 0xFFFFFFFFu;
+            r.ext[4 + d] = 0u;
+        }
+    }
+    for (int d = 0; d < 4; ++d) {
+        const uint32_t k = float_key(c[d]);
+        r.ext[d] = min(r.ext[d], k);
+        r.ext[4 + d] = max(r.ext[4 + d], k);
+    }
+    r.ss += dev * dev;
+}
+
+__device__ __forceinline__ void stat_flush(const DevM& m, StatTable& tb, int ty) {
+    __syncthreads();
+    for (int slot = threadIdx.x; slot < kTab; slot += blockDim.x) {
+        const int id = tb.key[slot];
+        if (id < 0) continue;
+        for (int d = 0; d < 4; ++d) {
+            atomicMin(&m.cext[8 * (size_t)id + d], tb.ext[slot][d]);
+            atomicMax(&m.cext[8 * (size_t)id + 4 + d], tb.ext[slot][4 + d]);
+        }
+        atomicAdd(&m.css[2 * (size_t)id + ty], tb.ss[slot]);
+    }
+}
+
+// ty 0: field samples [T][Z][Y][X]; ty 1: point samples in visiting order.
+__global__ __launch_bounds__(kBlock) void k_feature_pass(DevS s, DevM m, int ty) {
+    __shared__ StatTable tb;
+    stat_init(tb);
+    const uint64_t V = (uint64_t)s.X * s.Y * s.Z * s.T;
+    const uint64_t N = ty == 0 ? V : (uint64_t)s.T * s.P;
+    const uint64_t base = (uint64_t)blockIdx.x * (kBlock * kPer) + (uint64_t)threadIdx.x * kPer;
+    StatRun run;
+    run.id = -1;
+    for (int j = 0; j < kPer; ++j) {
+        const uint64_t i = base + j;
+        if (i >= N) break;
+        const int L = s.labels[(ty == 0 ? 0 : V) + i];
+        if (L < 0) continue;
+        float c[4], v;
+        if (ty == 0) {
+            uint32_t r = (uint32_t)i;
+            c[0] = (float)(r % (uint32_t)s.X) + 0.5f;
+            r /= (uint32_t)s.X;
+            c[1] = (float)(r % (uint32_t)s.Y) + 0.5f;
+            r /= (uint32_t)s.Y;
+            c[2] = (float)(r % (uint32_t)s.Z) + 0.5f;
+            c[3] = (float)(r / (uint32_t)s.Z);
+            v = s.field[i];
+        } else {
+            const float4 pp = s.spos[i];
+            c[0] = pp.x;
+            c[1] = pp.y;
+            c[2] = pp.z;
+            c[3] = pp.w;
+            v = s.sattr[i];
+        }
+        const double dev = (double)v - m.fmean[2 * (size_t)m.feat[L] + ty];
+        stat_sample(m, tb, run, L, c, dev, ty);
+    }
+    stat_add(m, tb, run, ty);
+    stat_flush(m, tb, ty);
+}
+
+__global__ __launch_bounds__(256) void k_feature_fold(DevM m) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.K || m.feat[i] < 0) return;
+    const int F = m.feat[i];
+    for (int d = 0; d < 4; ++d) {
+        atomicMin(&m.fext[8 * (size_t)F + d], m.cext[8 * (size_t)i + d]);
+        atomicMax(&m.fext[8 * (size_t)F + 4 + d], m.cext[8 * (size_t)i + 4 + d]);
+    }
+    for (int t = 0; t < 2; ++t) atomicAdd(&m.fss[2 * (size_t)F + t], m.css[2 * (size_t)i + t]);
+}
+
+__global__ __launch_bounds__(256) void k_feature_write(DevM m) {
+    const int F = blockIdx.x * blockDim.x + threadIdx.x;
+    if (F >= m.K) return;
+    double* o = m.out + (size_t)F * kFeatStats;
+    for (int k = 0; k < kFeatStats; ++k) o[k] = 0.0;
+    if (m.feat[F] != F) return;
+    const unsigned long long* a = m.fsum + 8 * (size_t)F;
+    const double nf = (double)(long long)a[SA_NF], np = (double)(long long)a[SA_NP];
+    o[FS_NF] = nf;
+    o[FS_NP] = np;
+    o[FS_MEAN_F] = m.fmean[2 * (size_t)F];
+    o[FS_MEAN_P] = m.fmean[2 * (size_t)F + 1];
+    o[FS_STD_F] = nf > 0 ? sqrt(m.fss[2 * (size_t)F] / nf) : 0.0;
+    o[FS_STD_P] = np > 0 ? sqrt(m.fss[2 * (size_t)F + 1] / np) : 0.0;
+    for (int d = 0; d < 4; ++d) {
+        o[FS_XMIN + 2 * d] = (double)key_float(m.fext[8 * (size_t)F + d]);
+        o[FS_XMIN + 2 * d + 1] = (double)key_float(m.fext[8 * (size_t)F + 4 + d]);
+    }
+}
 
 // ---- visiting order of the point samples (counting sort by tile) ----------
 
@@ -562,6 +823,21 @@ __global__ void k_slic_slab_reset(DevS s) {
 void launch_slic_update(const DevS& s, int seed, hipStream_t st) {
     hipLaunchKernelGGL(k_slic_slab_reset, dim3(blocks_for((uint64_t)8 * s.kmax, 256)), dim3(256), 0, st, s);
     hipLaunchKernelGGL(k_slic_update, dim3(blocks_for((uint64_t)s.K, 256)), dim3(256), 0, st, s, seed);
+}
+
+int launch_slic_merge(const DevS& s, const DevM& m, hipStream_t st) {
+    const dim3 gk(blocks_for((uint64_t)m.K, 256)), b256(256);
+    const uint64_t V = (uint64_t)s.X * s.Y * s.Z * s.T, Q = (uint64_t)s.T * s.P;
+    hipLaunchKernelGGL(k_merge_init, gk, b256, 0, st, s, m);
+    hipLaunchKernelGGL(k_merge_pairs, gk, b256, 0, st, s, m);
+    hipLaunchKernelGGL(k_merge_flatten, gk, b256, 0, st, s, m);
+    hipLaunchKernelGGL(k_feature_sums, gk, b256, 0, st, s, m);
+    hipLaunchKernelGGL(k_feature_means, gk, b256, 0, st, s, m);
+    if (V) hipLaunchKernelGGL(k_feature_pass, dim3(blocks_for(V, kBlock * kPer)), dim3(kBlock), 0, st, s, m, 0);
+    if (Q) hipLaunchKernelGGL(k_feature_pass, dim3(blocks_for(Q, kBlock * kPer)), dim3(kBlock), 0, st, s, m, 1);
+    hipLaunchKernelGGL(k_feature_fold, gk, b256, 0, st, m);
+    hipLaunchKernelGGL(k_feature_write, gk, b256, 0, st, m);
+    return (int)hipGetLastError();
 }
 
 }  // namespace mf4d

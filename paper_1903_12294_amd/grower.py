@@ -226,6 +226,23 @@ class Grower:
                                                     cnt.ctypes.data_as(ctypes.c_void_p), K, MF4D_HOST))
         return cen, cnt
 
+    def slic_merge(self, eps_m: float) -> int:
+        """Merge the last run's centres into features (Section 3.3); returns
+        the number of features."""
+        n = ctypes.c_int(0)
+        self._check(self.lib.mf4d_slic_merge(self.ctx, float(eps_m), ctypes.byref(n)))
+        return int(n.value)
+
+    def slic_read_features(self):
+        """(feature id of each centre int32 [K], per feature id fp64 [K][14]:
+        n_f, n_p, mean f, mean p, std f, std p, x/y/z/t min and max)."""
+        K = self.slic_K
+        feat = np.zeros(K, np.int32)
+        st = np.zeros((K, 14), np.float64)
+        self._check(self.lib.mf4d_slic_read_features(self.ctx, feat.ctypes.data_as(ctypes.c_void_p),
+                                                     st.ctypes.data_as(ctypes.c_void_p), K, MF4D_HOST))
+        return feat, st
+
     # -- batched queries ----------------------------------------------------
     def set_queries(self, crit, seeds):
         """crit fp32 [Q][4] = (f_lo, f_hi, a_lo, a_hi); seeds int32 [S][5] = (x, y, z, t, q)."""

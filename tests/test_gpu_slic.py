@@ -156,3 +156,60 @@ def test_errors():
             g.slic_read_labels()  # no successful run
     finally:
         g.close()
+
+
+# ---- cluster merging and feature statistics (Section 3.3) ----
+
+def _merge_gpu(field, xyz, attr, k, w, cf, eps, max_iter, eps_m):
+    from paper_1903_12294_amd import Grower
+    _need_gpu()
+    g = Grower(device=0)
+    try:
+        dev = torch.device("cuda:0")
+        g.load_field(torch.from_numpy(np.ascontiguousarray(field)).to(dev))
+        if xyz is not None and xyz.shape[1] > 0:
+            g.load_particles(torch.from_numpy(np.ascontiguousarray(xyz)).to(dev),
+                             torch.from_numpy(np.ascontiguousarray(attr)).to(dev))
+        g.slic_set_params(k, w[0], w[1], w[2], cf, eps, max_iter)
+        g.slic_run()
+        out = []
+        for e in eps_m:
+            n = g.slic_merge(e)
+            feat, st = g.slic_read_features()
+            out.append((n, feat, st))
+    finally:
+        g.close()
+    return out
+
+
+def _assert_merge(tag, field, xyz, attr, k, eps_m=(0.0, 0.05, 0.3), w=(1.0, 2.0, 2.0), cf=0.5, eps=1e-4,
+                  max_iter=6):
+    P = 0 if xyz is None else xyz.shape[1]
+    print(f"[merge] {tag} field {field.shape} P={P} k={k} eps_m={eps_m}", flush=True)
+    res = _merge_gpu(field, xyz, attr, k, w, cf, eps, max_iter, eps_m)
+    fl, pl, cen, cnt, it = oslic.slic(field, xyz if P else None, attr if P else None, k, w, cf, eps, max_iter)
+    for e, (n, feat, st) in zip(eps_m, res):
+        ofeat = oslic.merge_centres(cen, cnt, e)
+        assert np.array_equal(feat, ofeat), f"{tag} eps_m={e}: features differ"
+        assert n == int((ofeat == np.arange(len(ofeat))).sum())
+        ost = oslic.feature_stats(field, xyz if P else None, attr if P else None, fl, pl if P else None, ofeat)
+        exact = [0, 1, 2, 3] + list(range(6, 14))  # counts, means, extents
+        assert st[:, exact].tobytes() == ost[:, exact].tobytes(), f"{tag} eps_m={e}: stats differ"
+        assert np.allclose(st[:, 4:6], ost[:, 4:6], rtol=1e-9, atol=1e-12), f"{tag} eps_m={e}: std differs"
+
+
+def test_merge_field_and_points():
+    field, xyz, attr = _case(20, 4, 8, 8, 16, 120)
+    _assert_merge("merge", field, xyz, attr, (4, 2, 2, 2))
+
+
+def test_merge_field_only_and_non_finite():
+    field, xyz, attr = _case(21, 6, 8, 8, 8, 60, spread=1.4, nan=True)
+    _assert_merge("merge-nan", field, xyz, attr, (2, 2, 2, 3))
+    _assert_merge("merge-field-only", field, None, None, (2, 2, 2, 2), eps_m=(0.1, 1e9))
+
+
+def test_merge_32cube_workload():
+    inst = synth.make_config(1)
+    _assert_merge("merge-32^3x8", inst["field"], inst["xyz"], inst["attr"], (4, 4, 4, 2), w=(1.0, 8.0, 8.0),
+                  cf=2.0, eps=1e-3, max_iter=8, eps_m=(0.02, 0.1))
