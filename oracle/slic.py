@@ -266,32 +266,32 @@ def _matches(a, b, eps):
 
 def merge_centres(cen, counts, eps_m):
     """Feature id (lowest centre id of its component) of every centre; -1 for
-    a centre without samples."""
+    a centre without samples.  The match relation is evaluated row block by
+    row block; its transitive closure is scipy's connected components."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
     K = len(cen)
     nf, npt = counts[:, 0], counts[:, 1]
     has = (nf + npt) > 0
-    parent = list(range(K))
-
-    def find(i):
-        while parent[i] != i:
-            parent[i] = parent[parent[i]]
-            i = parent[i]
-        return i
-
-    for i in range(K):
-        if not has[i]:
-            continue
-        j = np.arange(i + 1, K)
-        ok = has[j]
+    rows, cols = [], []
+    for i0 in range(0, K, 1024):
+        i = np.arange(i0, min(K, i0 + 1024))[:, None]
+        j = np.arange(K)[None, :]
+        ok = has[i] & has[j] & (j > i)
         for col, n in ((5, nf), (4, npt)):
             both = (n[i] > 0) & (n[j] > 0)
             none = (n[i] == 0) & (n[j] == 0)
             ok &= none | (both & _matches(cen[i, col], cen[j, col], eps_m))
-        for jj in j[ok]:
-            ri, rj = find(i), find(int(jj))
-            if ri != rj:
-                parent[max(ri, rj)] = min(ri, rj)
-    return np.array([find(i) if has[i] else -1 for i in range(K)], np.int64)
+        r, c = np.nonzero(ok)
+        rows.append(r + i0)
+        cols.append(c)
+    r = np.concatenate(rows) if rows else np.zeros(0, np.int64)
+    c = np.concatenate(cols) if cols else np.zeros(0, np.int64)
+    g = coo_matrix((np.ones(len(r), np.int8), (r, c)), shape=(K, K))
+    _, comp = connected_components(g, directed=False)
+    low = np.full(comp.max() + 1 if K else 0, K, np.int64)
+    np.minimum.at(low, comp, np.arange(K))
+    return np.where(has, low[comp], -1).astype(np.int64)
 
 
 def feature_stats(field, xyz, attr, fl, pl, feat):
