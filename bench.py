@@ -157,6 +157,7 @@ SLIC_K = (16, 16, 16, 4)     # centres per axis (x, y, z, t): 16,384 centres
 SLIC_W = (1.0, 8.0, 8.0)     # w_d, w_f, w_p
 SLIC_CF = 2.0                # time-to-space factor
 SLIC_ITERS = 5
+SLIC_EPS_M = 0.05            # merging threshold (relative difference of both means)
 
 
 def bench_slic(torch, log, inst, name):
@@ -222,6 +223,17 @@ def bench_slic(torch, log, inst, name):
         C = oslic.grid_interval((X, Y, Z, T), SLIC_K)
         want = oslic.assign(pos, tt, val, typ, prev.astype(np.int64), cen_prev, C, SLIC_K, SLIC_W, SLIC_CF)
         parity = bool(it_m == m and np.array_equal(want, got))
+        # merging into features (Section 3.3) at full size; the oracle merges
+        # the same centres
+        cen_m, cnt_m = g.slic_read_centres()
+        g.slic_merge(SLIC_EPS_M)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n_feat = g.slic_merge(SLIC_EPS_M)
+        ms_merge = (time.perf_counter() - t0) * 1e3
+        feat, fst = g.slic_read_features()
+        merge_parity = bool(np.array_equal(feat, oslic.merge_centres(cen_m, cnt_m, SLIC_EPS_M)))
+        big = int(fst[:, 0:2].sum(1).max())
     finally:
         g.close()
     # the oracle on the small workload, for a CPU reference
@@ -236,7 +248,8 @@ def bench_slic(torch, log, inst, name):
     # position and time (16 B), value, label read and write (28 B)
     b = 12 * V + 28 * Qs
     gbs = b / (ms_iter * 1e-3) / 1e9
-    log(f"[bench] slic {ms_iter:.2f} ms/iteration, {N / (ms_iter * 1e-3):.3e} samples/s, parity {parity}")
+    log(f"[bench] slic {ms_iter:.2f} ms/iteration, {N / (ms_iter * 1e-3):.3e} samples/s, parity {parity}; "
+        f"merge {ms_merge:.2f} ms, {n_feat} features, parity {merge_parity}")
     return {"workload": f"{name}: {V} field + {Qs} point samples, k = {SLIC_K} "
                         f"({SLIC_K[0] * SLIC_K[1] * SLIC_K[2] * SLIC_K[3]} centres), w_d/w_f/w_p = {SLIC_W}, "
                         f"c_f = {SLIC_CF}",
@@ -245,6 +258,8 @@ def bench_slic(torch, log, inst, name):
             "roofline": {"bound": "alu (distance evaluation)", "hbm_bytes_per_iteration": b,
                          "achieved_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)},
             "parity_sampled": parity, "parity_samples": int(len(got)),
+            "merge": {"eps_m": SLIC_EPS_M, "ms": round(ms_merge, 3), "features": n_feat,
+                      "largest_feature_samples": big, "parity_feature_ids": merge_parity},
             "cpu_oracle": {"value": round(sN * 4 / tc, 1), "unit": "samples/s per iteration", "cores": 1,
                            "sample": f"the 32^3 x 8 workload ({sN} samples), initial pass and 3 iterations, "
                                      f"numpy ({tc:.1f}s)"}}
