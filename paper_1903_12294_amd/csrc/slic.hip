@@ -393,13 +393,17 @@ __device__ __forceinline__ int load_link(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Root of i; links strictly decrease, so the walk is at most K steps (the
+// Root of i, halving the path on the way (i's link moves to its grandparent:
+// still an ancestor, and only a non-root's link moves, which no union
+// touches).  Links strictly decrease, so the walk is at most K steps (the
 // bound only guards against the impossible).
-__device__ __forceinline__ int find_root(const int* parent, int i, int K) {
+__device__ __forceinline__ int find_root(int* parent, int i, int K) {
     for (int k = 0; k <= K; ++k) {
         const int p = load_link(&parent[i]);
         if (p == i) return i;
-        i = p;
+        const int gp = load_link(&parent[p]);
+        if (gp != p) __hip_atomic_store(&parent[i], gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        i = gp;
     }
     return -1;
 }
