@@ -12,6 +12,9 @@ Contents
             sweeps F(X) = S_adm ∪ (Adm ∩ N(X)) in numpy until nothing changes.
   check  -- the invariants that single out the result, and an explicit edge
             list of the coupled graph for library connected-components.
+  slic   -- the 4D clustering, cluster merging and feature statistics.
+  segments -- the trajectory segment rule: runs of >= 2 consecutive steps
+            of a particle in one feature.
 """
 from .bfs import build_oracle, oracle_grow, oracle_grow_queries  # noqa: F401
 from .sweep import sweep_grow  # noqa: F401
