@@ -201,6 +201,15 @@ int mf4d_read_field_mask(mf4d_ctx *ctx, uint32_t *dst, size_t nwords, int where)
  * Errors: MF4D_ERR_STATE (nothing grown or no particles), MF4D_ERR_ARG. */
 int mf4d_read_particle_mask(mf4d_ctx *ctx, uint8_t *dst, size_t n, int where);
 
+/* Trajectory segments of the grown feature (Section 3.4, visual
+ * representation): a trajectory is split where it leaves the feature, and
+ * only pieces of at least two consecutive member steps are kept.  Writes
+ * uint8 [T][P] to dst (n >= T*P bytes): 1 where particle p is a member at
+ * step t and also at t - 1 or t + 1, else 0.  Reads the labels of the last
+ * grow; stream ordering as mf4d_read_particle_mask.
+ * Errors: MF4D_ERR_STATE (nothing grown or no particles), MF4D_ERR_ARG. */
+int mf4d_read_particle_segments(mf4d_ctx *ctx, uint8_t *dst, size_t n, int where);
+
 /* Batched queries (up to 256, each with its own criteria and seeds), grown
  * together as the bit-planes of one 256-bit label per node.  crit fp32
  * [Q][4] = (f_lo, f_hi, a_lo, a_hi) per query; seeds int32 [S][5] =
@@ -359,6 +368,16 @@ int mf4d_slic_merge(mf4d_ctx *ctx, double eps_m, int *n_features);
  * last run), MF4D_ERR_ARG (K too small). */
 int mf4d_slic_read_features(mf4d_ctx *ctx, int32_t *feature_of_centre, double *stats, size_t K,
                             int where);
+
+/* Trajectory segments of the merged features (Section 3.4): the feature id
+ * of point sample (t, p) where the same particle has that feature at t - 1
+ * or t + 1, else -1, as int32 [T][P] in dst (n >= T*P).  A trajectory that
+ * passes through several features is thereby split into pieces of two or
+ * more consecutive steps each.  Uses the labels of the last run and the
+ * features of the last merge.  Stream ordering as mf4d_slic_read_labels.
+ * Errors: MF4D_ERR_STATE (no merge since the last run, or a run without
+ * point samples), MF4D_ERR_ARG (dst NULL or too small). */
+int mf4d_slic_read_segments(mf4d_ctx *ctx, int32_t *dst, size_t n, int where);
 
 #ifdef __cplusplus
 }

@@ -199,6 +199,7 @@ void free_slic(mf4d_ctx* c) {
     dev_free(c->slabels);
     c->slabels_n = 0;
     c->slic_done = false;
+    c->merged = false;
 }
 
 void free_field(mf4d_ctx* c) {
@@ -892,6 +893,29 @@ int mf4d_read_particle_mask(mf4d_ctx* c, uint8_t* dst, size_t n, int where) {
     return settle_members(c);
 }
 
+int mf4d_read_particle_segments(mf4d_ctx* c, uint8_t* dst, size_t n, int where) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    if (c->state == 0) return fail(MF4D_ERR_STATE, "nothing grown");
+    if (!c->has_particles) return fail(MF4D_ERR_STATE, "no particles loaded");
+    if (!dst) return fail(MF4D_ERR_ARG, "dst is NULL");
+    if (where != MF4D_HOST && where != MF4D_DEVICE) return fail(MF4D_ERR_ARG, "bad where");
+    const size_t need = (size_t)c->pg.P * c->pg.T;
+    if (n < need) return fail(MF4D_ERR_ARG, "dst holds %zu bytes, %zu needed", n, need);
+    HIP_TRY(hipSetDevice(c->device));
+    uint8_t* out = dst;
+    if (where == MF4D_HOST) {
+        void* st = nullptr;
+        int rc = staging_for(c, need, &st);
+        if (rc) return rc;
+        out = (uint8_t*)st;
+    }
+    launch_particle_segments(make_dev(c), out, c->stream);
+    if (where == MF4D_HOST)
+        HIP_TRY(hipMemcpyAsync(dst, out, need, hipMemcpyDeviceToHost, c->stream));
+    if (where == MF4D_DEVICE) return MF4D_OK;  // stream-ordered
+    return sync(c);
+}
+
 int mf4d_set_queries(mf4d_ctx* c, int Q, const float* crit, const int32_t* qxyzt, int64_t S,
                      int where) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
@@ -1409,7 +1433,7 @@ int mf4d_slic_merge(mf4d_ctx* c, double eps_m, int* n_features) {
 
 int mf4d_slic_read_features(mf4d_ctx* c, int32_t* feature_of_centre, double* stats, size_t K, int where) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
-    if (!c->merged) return fail(MF4D_ERR_STATE, "no merge since the last clustering run");
+    if (!c->slic_done || !c->merged) return fail(MF4D_ERR_STATE, "no merge since the last clustering run");
     if (where != MF4D_HOST && where != MF4D_DEVICE) return fail(MF4D_ERR_ARG, "bad where");
     if (K < (size_t)c->sK) return fail(MF4D_ERR_ARG, "room for %zu centres, %d needed", K, c->sK);
     HIP_TRY(hipSetDevice(c->device));
@@ -1418,6 +1442,31 @@ int mf4d_slic_read_features(mf4d_ctx* c, int32_t* feature_of_centre, double* sta
         HIP_TRY(hipMemcpyAsync(feature_of_centre, c->m.feat, (size_t)c->sK * sizeof(int32_t), kind, c->stream));
     if (stats)
         HIP_TRY(hipMemcpyAsync(stats, c->m.out, (size_t)c->sK * kFeatStats * sizeof(double), kind, c->stream));
+    if (where == MF4D_DEVICE) return MF4D_OK;  // stream-ordered
+    return sync(c);
+}
+
+int mf4d_slic_read_segments(mf4d_ctx* c, int32_t* dst, size_t n, int where) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    if (!c->slic_done || !c->merged) return fail(MF4D_ERR_STATE, "no merge since the last clustering run");
+    if (!dst) return fail(MF4D_ERR_ARG, "dst is NULL");
+    if (where != MF4D_HOST && where != MF4D_DEVICE) return fail(MF4D_ERR_ARG, "bad where");
+    const Geom& g = c->g;
+    const size_t V = (size_t)g.X * g.Y * g.Z * g.T, Qp = c->slabels_n - V;
+    if (Qp == 0) return fail(MF4D_ERR_STATE, "the last clustering run had no point samples");
+    if (n < Qp) return fail(MF4D_ERR_ARG, "dst holds %zu, %zu needed", n, Qp);
+    HIP_TRY(hipSetDevice(c->device));
+    int32_t* out = dst;
+    if (where == MF4D_HOST) {
+        void* st = nullptr;
+        int rc = staging_for(c, Qp * sizeof(int32_t), &st);
+        if (rc) return rc;
+        out = (int32_t*)st;
+    }
+    launch_slic_unsort(c->slabels + V, c->porder, Qp, out, c->stream);
+    launch_slic_segments(out, c->m.feat, g.T, (int64_t)(Qp / g.T), c->stream);
+    if (where == MF4D_HOST)
+        HIP_TRY(hipMemcpyAsync(dst, out, Qp * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     if (where == MF4D_DEVICE) return MF4D_OK;  // stream-ordered
     return sync(c);
 }

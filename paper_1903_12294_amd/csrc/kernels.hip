@@ -1647,6 +1647,51 @@ __global__ __launch_bounds__(256) void k_read_particles(Dev d, uint8_t* __restri
     block_slot_sum(d, SL_MEMBERS_P, cnt);
 }
 
+// Trajectory segments of the grown feature (Section 3.4): a member step stays
+// when the same particle is a member at t - 1 or t + 1, so that only runs of
+// two or more consecutive member steps are drawn.  On a label word L (bit t =
+// step t) that is L & ((L << 1) | (L >> 1)), with the neighbouring words'
+// edge bits carried in.  A thread owns 4 consecutive particles; out is uint8
+// [T][P], written 4 bytes per step when the 4 are whole and aligned.
+__global__ __launch_bounds__(256) void k_particle_segments(Dev d, uint8_t* __restrict__ out) {
+    const PGeom& pg = d.pg;
+    const int nw = (pg.T + 63) >> 6;  // words holding real steps
+    const bool wide = (pg.P & 3) == 0 && (reinterpret_cast<uintptr_t>(out) & 3) == 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
+    for (int64_t p0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) * 4; p0 < pg.P; p0 += stride) {
+        const int np = (int)min((int64_t)4, pg.P - p0);
+        bool cand[4];
+        for (int k = 0; k < 4; ++k) cand[k] = k < np && d.pflag[p0 + k];
+        auto word = [&](int k, int w) -> unsigned long long {
+            if (w < 0 || w >= nw || !cand[k]) return 0ull;
+            const int valid = min(64, pg.T - w * 64);
+            const unsigned long long vm = valid >= 64 ? ~0ull : ((1ull << valid) - 1);
+            return d.Lp[(size_t)(p0 + k) * pg.W + w] & vm;
+        };
+        for (int w = 0; w < nw; ++w) {
+            unsigned long long keep[4];
+            for (int k = 0; k < 4; ++k) {
+                const unsigned long long L = word(k, w);
+                const unsigned long long nb = (L << 1) | (word(k, w - 1) >> 63) | (L >> 1) |
+                                              (word(k, w + 1) << 63);
+                keep[k] = L & nb;
+            }
+            const int tend = min(64, pg.T - w * 64);
+            for (int tl = 0; tl < tend; ++tl) {
+                uint8_t* o = out + (int64_t)(w * 64 + tl) * pg.P + p0;
+                if (wide) {
+                    const uint32_t v = (uint32_t)((keep[0] >> tl) & 1) | ((uint32_t)((keep[1] >> tl) & 1) << 8) |
+                                       ((uint32_t)((keep[2] >> tl) & 1) << 16) |
+                                       ((uint32_t)((keep[3] >> tl) & 1) << 24);
+                    *reinterpret_cast<uint32_t*>(o) = v;
+                } else {
+                    for (int k = 0; k < np; ++k) o[k] = (uint8_t)((keep[k] >> tl) & 1);
+                }
+            }
+        }
+    }
+}
+
 inline unsigned grid_for(uint64_t n, unsigned block, unsigned cap) {
     uint64_t b = (n + block - 1) / block;
     if (b < 1) b = 1;
@@ -1819,6 +1864,13 @@ void launch_read_particles(const Dev& d, uint8_t* out, hipStream_t s) {
     }
     hipLaunchKernelGGL(k_read_particles, dim3(grid_for((pg.P + 3) / 4, 256, 1u << 20)), dim3(256),
                        0, s, d, out);
+}
+
+void launch_particle_segments(const Dev& d, uint8_t* out, hipStream_t s) {
+    const PGeom& pg = d.pg;
+    if (pg.P == 0 || pg.T == 0) return;
+    hipLaunchKernelGGL(k_particle_segments, dim3(grid_for((pg.P + 3) / 4, 256, 1u << 16)), dim3(256), 0,
+                       s, d, out);
 }
 
 }  // namespace mf4d

@@ -135,6 +135,8 @@ bool launch_rounds_persistent(const Dev& d, uint32_t round0, uint32_t max_rounds
                               hipStream_t s);
 void launch_read_field(const Dev& d, uint32_t* out, hipStream_t s);
 void launch_read_particles(const Dev& d, uint8_t* out, hipStream_t s);
+// Trajectory segments of the grown feature as uint8 [T][P] (Section 3.4).
+void launch_particle_segments(const Dev& d, uint8_t* out, hipStream_t s);
 // stat64[dst] (+)= sum of slot statistic `which` (assign: =), and those slots cleared.
 void launch_fold_slots(const Dev& d, int which, int dst, hipStream_t s, bool assign = false);
 // The per-grow statistics (particle visits, active and tested tiles) folded

@@ -80,6 +80,10 @@ int launch_slic_order(const uint32_t* bins, const float* xyz, const float* attr,
                       float* sattr, hipStream_t st);
 // Point labels from visiting order back to [T][P]: out[order[j]] = in[j].
 void launch_slic_unsort(const int32_t* in, const uint32_t* order, uint64_t Q, int32_t* out, hipStream_t st);
+// Trajectory segments (Section 3.4), in place on point labels [T][P]: the
+// feature id (feat[label]) where the particle has that feature at t - 1 or
+// t + 1, else -1.
+void launch_slic_segments(int32_t* lab, const int32_t* feat, int T, int64_t P, hipStream_t st);
 // Labels from the seed cells, and their sums.
 void launch_slic_init(const DevS& s, hipStream_t st);
 // One assignment pass over both sample types, with the sums of the new labels.

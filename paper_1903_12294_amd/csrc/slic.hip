@@ -783,6 +783,35 @@ __global__ __launch_bounds__(256) void k_slic_unsort(const int32_t* __restrict__
         out[order[j]] = in[j];
 }
 
+// Trajectory segments of the features (Section 3.4): a particle-step keeps
+// its feature id when the same particle lies in that feature at t - 1 or
+// t + 1 (so that runs of two or more consecutive steps are drawn), else -1.
+// In place on point labels [T][P]: a thread owns one particle and reads its
+// step t + 1 before it writes step t.  feat[centre] -> feature id.
+__global__ __launch_bounds__(256) void k_slic_segments(int32_t* __restrict__ lab, const int32_t* __restrict__ feat,
+                                                      int T, int64_t P) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P; p += stride) {
+        auto fid = [&](int t) -> int32_t {
+            const int32_t l = lab[(int64_t)t * P + p];
+            return l >= 0 ? feat[l] : -1;
+        };
+        int32_t prev = -1, cur = fid(0);
+        for (int t = 0; t < T; ++t) {
+            const int32_t next = t + 1 < T ? fid(t + 1) : -1;
+            lab[(int64_t)t * P + p] = cur >= 0 && (cur == prev || cur == next) ? cur : -1;
+            prev = cur;
+            cur = next;
+        }
+    }
+}
+
+void launch_slic_segments(int32_t* lab, const int32_t* feat, int T, int64_t P, hipStream_t st) {
+    if (T <= 0 || P <= 0) return;
+    const unsigned g = (unsigned)std::min<int64_t>((P + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_slic_segments, dim3(g), dim3(256), 0, st, lab, feat, T, P);
+}
+
 void launch_slic_unsort(const int32_t* in, const uint32_t* order, uint64_t Q, int32_t* out, hipStream_t st) {
     if (Q == 0) return;
     const unsigned g = (unsigned)std::min<uint64_t>((Q + 255) / 256, 16384);

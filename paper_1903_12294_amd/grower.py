@@ -178,6 +178,21 @@ class Grower:
                 self.ctx, out.ctypes.data_as(ctypes.c_void_p), n, MF4D_HOST))
         return out
 
+    def read_particle_segments(self, out=None):
+        """Trajectory segments of the grown feature (Section 3.4): uint8
+        [T][P], members with a member neighbour step.  `out` may be a device
+        tensor (uint8)."""
+        n = self.T * self.P
+        if out is None:
+            out = np.zeros((self.T, self.P), np.uint8)
+        if _is_device_tensor(out):
+            self._check(self.lib.mf4d_read_particle_segments(
+                self.ctx, ctypes.c_void_p(out.data_ptr()), out.numel(), MF4D_DEVICE))
+        else:
+            self._check(self.lib.mf4d_read_particle_segments(
+                self.ctx, out.ctypes.data_as(ctypes.c_void_p), n, MF4D_HOST))
+        return out
+
     # -- 4D SLIC clustering (Section 3.2) ------------------------------------
     def slic_set_params(self, k, w_d: float, w_f: float, w_p: float, c_f: float, eps: float,
                         max_iter: int):
@@ -242,6 +257,21 @@ class Grower:
         self._check(self.lib.mf4d_slic_read_features(self.ctx, feat.ctypes.data_as(ctypes.c_void_p),
                                                      st.ctypes.data_as(ctypes.c_void_p), K, MF4D_HOST))
         return feat, st
+
+    def slic_read_segments(self, out=None):
+        """Trajectory segments of the merged features (Section 3.4): int32
+        [T][P], the feature id where the particle keeps it at a neighbouring
+        step, else -1.  `out` may be a device tensor (int32)."""
+        n = self.T * self.P
+        if out is None:
+            out = np.zeros((self.T, self.P), np.int32)
+        if _is_device_tensor(out):
+            self._check(self.lib.mf4d_slic_read_segments(
+                self.ctx, ctypes.c_void_p(out.data_ptr()), out.numel(), MF4D_DEVICE))
+        else:
+            self._check(self.lib.mf4d_slic_read_segments(
+                self.ctx, out.ctypes.data_as(ctypes.c_void_p), n, MF4D_HOST))
+        return out
 
     # -- batched queries ----------------------------------------------------
     def set_queries(self, crit, seeds):
