@@ -10,6 +10,9 @@ schedule, admissibility mode) is the autotuner's pick, every candidate
 checked to give identical masks.
 
 Beside the headline the bench reports, on the same GPU:
+  segments - the trajectory segments of the grown feature (runs of >= 2
+             member steps), timed as a read-out pass, sampled particles
+             compared with the oracle's rule on the oracle's mask;
   eager    - admissibility of every sample each step (the dense HBM pass);
   learned  - the brick-activity predictor choosing the tiles tested up front,
              trained (committed weights) and untrained, masks compared;
@@ -160,6 +163,20 @@ SLIC_ITERS = 5
 SLIC_EPS_M = 0.05            # merging threshold (relative difference of both means)
 
 
+def time_call(fn, torch, reps: int = 5) -> float:
+    """Least wall time of fn over reps calls, each bracketed by device
+    synchronisation, in ms."""
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) * 1e3
+        best = t if best is None else min(best, t)
+    return best
+
+
 def bench_slic(torch, log, inst, name):
     """4D SLIC clustering (Section 3.2) of the same workload's 1.07e9 field and
     2.7e8 point samples: time per iteration (runs of 1 and 1 + SLIC_ITERS
@@ -167,6 +184,7 @@ def bench_slic(torch, log, inst, name):
     against peak, parity at full size on 20,000 sampled labels (the oracle
     assigns them from the GPU's centres of the iteration before), and the
     oracle's own speed on the 32^3 x 8 workload."""
+    from oracle import segments as oseg
     from oracle import slic as oslic
     from paper_1903_12294_amd import Grower, synth
     dev = torch.device("cuda:0")
@@ -234,6 +252,17 @@ def bench_slic(torch, log, inst, name):
         feat, fst = g.slic_read_features()
         merge_parity = bool(np.array_equal(feat, oslic.merge_centres(cen_m, cnt_m, SLIC_EPS_M)))
         big = int(fst[:, 0:2].sum(1).max())
+        # trajectory segments of the merged features (Section 3.4); the
+        # oracle's rule applied to the same particles' labels and features
+        sseg = torch.empty((T, P), dtype=torch.int32, device=dev)
+        ms_sseg = time_call(lambda: g.slic_read_segments(sseg), torch)
+        sel = np.sort(np.random.default_rng(13).choice(P, min(P, 4096), replace=False))
+        sel_d = torch.from_numpy(sel).to(dev)
+        got_s = sseg[:, sel_d].cpu().numpy()
+        want_s = oseg.feature_segments(oseg.point_features(pl[:, sel_d].cpu().numpy(), feat))
+        seg_parity = bool(np.array_equal(got_s, want_s))
+        seg_kept = int((sseg >= 0).sum().item())
+        del sseg
     finally:
         g.close()
     # the oracle on the small workload, for a CPU reference
@@ -249,7 +278,8 @@ def bench_slic(torch, log, inst, name):
     b = 12 * V + 28 * Qs
     gbs = b / (ms_iter * 1e-3) / 1e9
     log(f"[bench] slic {ms_iter:.2f} ms/iteration, {N / (ms_iter * 1e-3):.3e} samples/s, parity {parity}; "
-        f"merge {ms_merge:.2f} ms, {n_feat} features, parity {merge_parity}")
+        f"merge {ms_merge:.2f} ms, {n_feat} features, parity {merge_parity}; "
+        f"segments {ms_sseg:.3f} ms, parity {seg_parity}")
     return {"workload": f"{name}: {V} field + {Qs} point samples, k = {SLIC_K} "
                         f"({SLIC_K[0] * SLIC_K[1] * SLIC_K[2] * SLIC_K[3]} centres), w_d/w_f/w_p = {SLIC_W}, "
                         f"c_f = {SLIC_CF}",
@@ -260,6 +290,9 @@ def bench_slic(torch, log, inst, name):
             "parity_sampled": parity, "parity_samples": int(len(got)),
             "merge": {"eps_m": SLIC_EPS_M, "ms": round(ms_merge, 3), "features": n_feat,
                       "largest_feature_samples": big, "parity_feature_ids": merge_parity},
+            "segments": {"ms": round(ms_sseg, 3), "kept_point_samples": seg_kept,
+                         "hbm_bytes": 20 * Qs, "achieved_GBps": round(20 * Qs / (ms_sseg * 1e-3) / 1e9, 1),
+                         "parity_sampled_particles": seg_parity, "particles_checked": int(len(sel))},
             "cpu_oracle": {"value": round(sN * 4 / tc, 1), "unit": "samples/s per iteration", "cores": 1,
                            "sample": f"the 32^3 x 8 workload ({sN} samples), initial pass and 3 iterations, "
                                      f"numpy ({tc:.1f}s)"}}
@@ -419,6 +452,19 @@ def main():
                 "bytes_per_launch": kt[dom]["bytes_per_launch"],
                 "ms_per_launch": kt[dom]["ms_per_launch"]}
 
+    # trajectory segments of the grown feature (Section 3.4): a read-out pass
+    seg = torch.empty((T, P), dtype=torch.uint8, device=dev)
+    ms_seg = time_call(lambda: g.read_particle_segments(seg), torch)
+    seg_sel = np.sort(np.random.default_rng(12).choice(P, min(P, 4096), replace=False))
+    seg_cols = seg[:, torch.from_numpy(seg_sel).to(dev)].cpu().numpy()
+    seg_kept = int(seg.sum(dtype=torch.int64).item())
+    del seg
+    # label words, candidate flags, output bytes
+    seg_bytes = 8 * max(1, (T + 63) // 64) * P + P + T * P
+    forms_seg = {"ms": round(ms_seg, 4), "kept_particle_steps": seg_kept, "hbm_bytes": seg_bytes,
+                 "achieved_GBps": round(seg_bytes / (ms_seg * 1e-3) / 1e9, 1),
+                 "frac": round(seg_bytes / (ms_seg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
     if args.copy_probe:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
@@ -428,7 +474,7 @@ def main():
         del a, b
     ref_f = fmask.clone()
     ref_p = pmask.clone()
-    forms = {}
+    forms = {"segments": forms_seg}
     if not args.no_forms:
         # eager: every sample tested each step
         g.set_admit_mode("all")
@@ -488,7 +534,10 @@ def main():
                "host_cores_available": os.cpu_count()}
         parity = bool(np.array_equal(ref_f.cpu().numpy().view(np.uint32), ofm)
                       and np.array_equal(ref_p.cpu().numpy(), opm))
-        log(f"[bench] oracle {tc:.1f}s, parity {parity}")
+        from oracle import segments as oseg
+        forms_seg["parity_sampled_particles"] = bool(np.array_equal(seg_cols, oseg.mask_segments(opm[:, seg_sel])))
+        forms_seg["particles_checked"] = int(len(seg_sel))
+        log(f"[bench] oracle {tc:.1f}s, parity {parity}, segments parity {forms_seg['parity_sampled_particles']}")
 
     out = {
         "metric": "voxel-timesteps segmented/s to fixed point",
