@@ -18,4 +18,4 @@ Contents
 """
 from .bfs import build_oracle, oracle_grow, oracle_grow_queries  # noqa: F401
 from .sweep import sweep_grow  # noqa: F401
-from .check import check_invariants, edge_list, components_grow  # noqa: F401
+from .check import check_invariants, edge_list, components_grow, reach_grow  # noqa: F401

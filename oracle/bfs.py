@@ -40,6 +40,9 @@ def load(path: str = _LIB):
     i64 = ctypes.c_int64
     flt = ctypes.c_float
     f.argtypes = [P, i64, i64, i64, i64, P, P, i64, flt, flt, flt, flt, P, i64, P, P, P]
+    g = lib.oracle_grow_dir
+    g.restype = ctypes.c_int
+    g.argtypes = [P, i64, i64, i64, i64, P, P, i64, flt, flt, flt, flt, P, i64, ctypes.c_int, P, P, P]
     if path == _LIB:
         _lib = lib
     return lib
@@ -50,9 +53,10 @@ def _ptr(a):
 
 
 def oracle_grow(field: np.ndarray, xyz: np.ndarray | None, attr: np.ndarray | None,
-                crit, seeds: np.ndarray, lib=None):
+                crit, seeds: np.ndarray, lib=None, forward_only: bool = False):
     """Grow from seeds.  field fp32 [T][Z][Y][X]; xyz fp32 [T][P][3];
     attr fp32 [T][P]; crit = (f_lo, f_hi, a_lo, a_hi); seeds int32 [S][4].
+    forward_only: trajectory edges lead from t to t + 1 only (causal).
     Returns (field mask uint32 words, particle mask uint8 [T][P], stats dict)."""
     lib = lib or load()
     field = np.ascontiguousarray(field, np.float32)
@@ -72,9 +76,9 @@ def oracle_grow(field: np.ndarray, xyz: np.ndarray | None, attr: np.ndarray | No
     fmask = np.zeros((V + 31) // 32, np.uint32)
     stats = np.zeros(5, np.int64)
     c = [float(np.float32(v)) for v in crit]
-    rc = lib.oracle_grow(_ptr(field), X, Y, Z, T, _ptr(xyz), _ptr(attr), P,
-                         c[0], c[1], c[2], c[3], _ptr(seeds), len(seeds),
-                         _ptr(fmask), _ptr(pmask) if P else None, _ptr(stats))
+    rc = lib.oracle_grow_dir(_ptr(field), X, Y, Z, T, _ptr(xyz), _ptr(attr), P,
+                             c[0], c[1], c[2], c[3], _ptr(seeds), len(seeds), int(bool(forward_only)),
+                             _ptr(fmask), _ptr(pmask) if P else None, _ptr(stats))
     if rc != 0:
         raise OracleError(rc, ERRORS.get(rc, str(rc)))
     st = dict(members_field=int(stats[0]), members_particle=int(stats[1]),
@@ -83,7 +87,7 @@ def oracle_grow(field: np.ndarray, xyz: np.ndarray | None, attr: np.ndarray | No
 
 
 def oracle_grow_queries(field, xyz, attr, crit_q: np.ndarray, qseeds: np.ndarray,
-                        queries=None, threads: int | None = None):
+                        queries=None, threads: int | None = None, forward_only: bool = False):
     """One independent oracle grow per query (thread pool over queries).
     crit_q fp32 [Q][4]; qseeds int32 [S][5] = (x, y, z, t, q).
     Returns {q: (fmask, pmask, stats)} for the requested queries."""
@@ -93,7 +97,7 @@ def oracle_grow_queries(field, xyz, attr, crit_q: np.ndarray, qseeds: np.ndarray
 
     def one(q):
         s = qseeds[qseeds[:, 4] == q][:, :4]
-        return q, oracle_grow(field, xyz, attr, crit_q[q], s, lib=lib)
+        return q, oracle_grow(field, xyz, attr, crit_q[q], s, lib=lib, forward_only=forward_only)
 
     with ThreadPoolExecutor(threads or max(1, min(16, os.cpu_count() or 1))) as ex:
         return dict(ex.map(one, qs))

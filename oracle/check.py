@@ -32,10 +32,12 @@ def admissible(field, attr, crit):
     return Af, Ap
 
 
-def edge_list(field, xyz, attr, crit, restrict_f=None, restrict_p=None):
+def edge_list(field, xyz, attr, crit, restrict_f=None, restrict_p=None, trajectories=True):
     """Edges (a, b) between admissible nodes.  Voxel node id = canonical index
     ((t*Z+z)*Y+y)*X+x; particle node id = V + t*P + i.  Optional boolean
-    restrict_* masks further limit the node set (used for I4)."""
+    restrict_* masks further limit the node set (used for I4).  Trajectory
+    edges (i, t) - (i, t+1) come in the order (earlier, later); trajectories
+    = False leaves them out."""
     field = np.asarray(field, np.float32)
     T, Z, Y, X = field.shape
     V = field.size
@@ -58,9 +60,10 @@ def edge_list(field, xyz, attr, crit, restrict_f=None, restrict_p=None):
         if restrict_p is not None:
             Ap = Ap & restrict_p
         pid = V + np.arange(T * P, dtype=np.int64).reshape(T, P)
-        m = Ap[:-1] & Ap[1:]
-        A.append(pid[:-1][m])
-        B.append(pid[1:][m])
+        if trajectories:
+            m = Ap[:-1] & Ap[1:]
+            A.append(pid[:-1][m])
+            B.append(pid[1:][m])
         ok, cx, cy, cz = particle_voxels(np.asarray(xyz, np.float32), (X, Y, Z))
         tt = np.broadcast_to(np.arange(T)[:, None], (T, P))
         vox = idx[tt, cz, cy, cx]
@@ -86,6 +89,40 @@ def components_grow(field, xyz, attr, crit, seeds):
     member = np.isin(lab, np.fromiter(keep, np.int64, len(keep)))
     P = 0 if xyz is None else xyz.shape[1]
     return member[:V].reshape(T, Z, Y, X), member[V:].reshape(T, P)
+
+
+def reach_grow(field, xyz, attr, crit, seeds, forward_only=True):
+    """M as the nodes reachable from the admissible seeds in the directed
+    graph: every non-trajectory edge both ways, trajectory edges from t to
+    t + 1 only (forward_only) or both ways; scipy's breadth-first order from
+    a virtual source linked to the admissible seeds."""
+    from scipy.sparse.csgraph import breadth_first_order
+    field = np.asarray(field, np.float32)
+    T, Z, Y, X = field.shape
+    a, b, V, Q = edge_list(field, xyz, attr, crit, trajectories=False)
+    src, dst = [a, b], [b, a]
+    P = 0 if xyz is None else xyz.shape[1]
+    if P:
+        _, Ap = admissible(field, attr, crit)
+        pid = V + np.arange(T * P, dtype=np.int64).reshape(T, P)
+        m = Ap[:-1] & Ap[1:]
+        src.append(pid[:-1][m])
+        dst.append(pid[1:][m])
+        if not forward_only:
+            src.append(pid[1:][m])
+            dst.append(pid[:-1][m])
+    Af, _ = admissible(field, attr, crit)
+    N = V + Q
+    sd = [((t * Z + z) * Y + y) * X + x for x, y, z, t in np.asarray(seeds, np.int64).reshape(-1, 4)
+          if Af[t, z, y, x]]
+    src.append(np.full(len(sd), N, np.int64))
+    dst.append(np.asarray(sd, np.int64))
+    s, d = np.concatenate(src), np.concatenate(dst)
+    g = sp.coo_matrix((np.ones(len(s), np.int8), (s, d)), shape=(N + 1, N + 1)).tocsr()
+    order = breadth_first_order(g, N, directed=True, return_predecessors=False)
+    member = np.zeros(N + 1, bool)
+    member[order] = True
+    return member[:V].reshape(T, Z, Y, X), member[V:N].reshape(T, P)
 
 
 def check_invariants(field, xyz, attr, crit, seeds, Mf, Mp):

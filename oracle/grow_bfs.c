@@ -27,6 +27,10 @@
  *   Result M = the nodes reachable from the admissible seeds inside the
  *   subgraph induced on admissible nodes.  Seeds that are not admissible are
  *   dropped and counted.
+ *   Forward-only (causal) coupling, oracle_grow_dir with forward_only = 1:
+ *   the trajectory edge leads only from (i, t) to (i, t+1), so membership
+ *   travels along a trajectory forward in time; every other edge stays
+ *   undirected, and M is the set reachable along the directed edges.
  *
  * Algorithm: textbook FIFO breadth-first search.  The voxel -> particle-step
  * index is a counting sort of particle-steps by voxel id (CSR).
@@ -91,11 +95,11 @@ static int test_and_set(uint64_t *bits, uint64_t i)
  * stats[4] = number of admissible seed entries.
  * Returns 0, OR_ERR_ARG, OR_ERR_RANGE (a seed outside the grid) or OR_ERR_OOM.
  */
-int oracle_grow(const float *field, int64_t X, int64_t Y, int64_t Z, int64_t T,
-                const float *xyz, const float *attr, int64_t P,
-                float f_lo, float f_hi, float a_lo, float a_hi,
-                const int32_t *seeds, int64_t S,
-                uint32_t *fmask, uint8_t *pmask, int64_t *stats)
+int oracle_grow_dir(const float *field, int64_t X, int64_t Y, int64_t Z, int64_t T,
+                    const float *xyz, const float *attr, int64_t P,
+                    float f_lo, float f_hi, float a_lo, float a_hi,
+                    const int32_t *seeds, int64_t S, int forward_only,
+                    uint32_t *fmask, uint8_t *pmask, int64_t *stats)
 {
     if (X <= 0 || Y <= 0 || Z <= 0 || T <= 0 || P < 0 || S < 0) return OR_ERR_ARG;
     if (!field || !fmask || !stats || (S > 0 && !seeds)) return OR_ERR_ARG;
@@ -186,7 +190,8 @@ int oracle_grow(const float *field, int64_t X, int64_t Y, int64_t Z, int64_t T,
                 if (bin[q] != NO_VOXEL && in_band(field[bin[q]], f_lo, f_hi) &&
                     test_and_set(visF, bin[q]))
                     if (fifo_push(&fifo, bin[q])) goto done;
-                if (t > 0 && in_band(attr[q - P], a_lo, a_hi) && test_and_set(visP, q - P))
+                if (!forward_only && t > 0 && in_band(attr[q - P], a_lo, a_hi) &&
+                    test_and_set(visP, q - P))
                     if (fifo_push(&fifo, V + q - P)) goto done;
                 if (t + 1 < (uint64_t)T && in_band(attr[q + P], a_lo, a_hi) &&
                     test_and_set(visP, q + P))
@@ -221,4 +226,15 @@ done:
     free(visF);
     free(visP);
     return rc;
+}
+
+/* Both trajectory directions (undirected coupling). */
+int oracle_grow(const float *field, int64_t X, int64_t Y, int64_t Z, int64_t T,
+                const float *xyz, const float *attr, int64_t P,
+                float f_lo, float f_hi, float a_lo, float a_hi,
+                const int32_t *seeds, int64_t S,
+                uint32_t *fmask, uint8_t *pmask, int64_t *stats)
+{
+    return oracle_grow_dir(field, X, Y, Z, T, xyz, attr, P, f_lo, f_hi, a_lo, a_hi, seeds, S, 0,
+                           fmask, pmask, stats);
 }

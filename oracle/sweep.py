@@ -10,6 +10,10 @@ and the trajectory coupling motivated in Section 1).  Starting from
 X_0 = S_adm, synchronous full sweeps X_{k+1} = F(X_k) are repeated until a
 sweep changes nothing; the number of sweeps, counting that last one, is
 D + 1 where D is the largest breadth-first level.
+
+With forward_only (causal coupling) a particle-step is a neighbour of the
+same particle's previous step only: N(X) gains (i, t+1) from (i, t) in X, not
+(i, t-1).
 """
 from __future__ import annotations
 
@@ -33,7 +37,8 @@ def particle_voxels(xyz: np.ndarray, dims):
     return ok, ci[..., 0], ci[..., 1], ci[..., 2]
 
 
-def sweep_grow(field, xyz, attr, crit, seeds, max_sweeps: int | None = None):
+def sweep_grow(field, xyz, attr, crit, seeds, max_sweeps: int | None = None,
+               forward_only: bool = False):
     """Returns (Mf bool [T][Z][Y][X], Mp bool [T][P], sweeps, dropped)."""
     field = np.asarray(field, np.float32)
     T, Z, Y, X = field.shape
@@ -74,7 +79,8 @@ def sweep_grow(field, xyz, attr, crit, seeds, max_sweeps: int | None = None):
         Np = Mp.copy()
         if P:
             Np[1:] |= Mp[:-1]
-            Np[:-1] |= Mp[1:]
+            if not forward_only:
+                Np[:-1] |= Mp[1:]
             from_p = Mp[tt, pp]
             Nf[tt[from_p], bz[from_p], by[from_p], bx[from_p]] = True
             Np[tt, pp] |= Mf[tt, bz, by, bx]
