@@ -16,7 +16,7 @@ import sys
 import numpy as np
 import pytest
 
-from oracle import bfs, components_grow, oracle_grow, sweep_grow
+from oracle import bfs, components_grow, oracle_grow, reach_grow, sweep_grow
 from tests import golden_io
 from tests.test_oracle_pins import _random_instance
 
@@ -37,8 +37,12 @@ MUTANTS = {
                                 "if (test_and_set(visP, q))"),
     "skip_field_check_on_bin": ("if (bin[q] != NO_VOXEL && in_band(field[bin[q]], f_lo, f_hi) &&",
                                 "if (bin[q] != NO_VOXEL &&"),
-    "drop_trajectory_back": ("if (t > 0 && in_band(attr[q - P], a_lo, a_hi) && test_and_set(visP, q - P))",
-                             "if (0)"),
+    "drop_trajectory_back": ("if (!forward_only && t > 0 && in_band(attr[q - P], a_lo, a_hi) &&",
+                             "if (0 &&"),
+    "forward_only_ignored": ("if (!forward_only && t > 0 && in_band(attr[q - P], a_lo, a_hi) &&",
+                             "if (t > 0 && in_band(attr[q - P], a_lo, a_hi) &&"),
+    "forward_only_reversed": ("if (t + 1 < (uint64_t)T && in_band(attr[q + P], a_lo, a_hi) &&",
+                              "if (!forward_only && t + 1 < (uint64_t)T && in_band(attr[q + P], a_lo, a_hi) &&"),
     "seed_unchecked": ("if (!in_band(field[v], f_lo, f_hi)) { dropped++; continue; }", ""),
     "upper_bin_inclusive": ("if (!(cx >= 0.0f && cx < (float)X)) return -1;",
                             "if (!(cx >= 0.0f && cx <= (float)X)) return -1;"),
@@ -74,6 +78,18 @@ def _battery(lib):
         if not (np.array_equal(Mf, sf) and np.array_equal(pm.astype(bool), sp_)
                 and np.array_equal(Mf, cf) and sweeps == st_["depth"] + 1):
             return "random"
+    # forward-only coupling against the directed sweeps and scipy reachability
+    for _ in range(40):
+        X, Y, Z, T = (int(v) for v in rng.integers(1, 6, 4))
+        inst = _random_instance(rng, X, Y, Z, T, int(rng.integers(1, 30)), 3)
+        args = (inst["field"], inst["xyz"], inst["attr"], inst["crit"], inst["seeds"])
+        fm, pm, st_ = oracle_grow(*args, lib=lib, forward_only=True)
+        sf, sp_, sweeps, _ = sweep_grow(*args, forward_only=True)
+        rf, rp = reach_grow(*args, forward_only=True)
+        Mf = golden_io.unpack_field(fm, inst["field"].shape)
+        if not (np.array_equal(Mf, sf) and np.array_equal(pm.astype(bool), sp_)
+                and np.array_equal(Mf, rf) and np.array_equal(sp_, rp) and sweeps == st_["depth"] + 1):
+            return "random-forward"
     return None
 
 
