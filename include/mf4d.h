@@ -77,6 +77,9 @@ enum { MF4D_HOST = 0, MF4D_DEVICE = 1 };
 /* Admissibility modes (mf4d_set_admit_mode). */
 enum { MF4D_ADMIT_TILES = 0, MF4D_ADMIT_ALL = 1 };
 
+/* Trajectory coupling (mf4d_set_trajectory_mode). */
+enum { MF4D_TRAJ_BOTH = 0, MF4D_TRAJ_FORWARD = 1 };
+
 /* How the rounds of a grow are scheduled (both give the same result). */
 enum {
     MF4D_SCHED_PERSISTENT = 0, /* one cooperative kernel runs every round (default) */
@@ -170,6 +173,18 @@ int mf4d_set_schedule(mf4d_ctx *ctx, int mode);
  * The environment variable MF4D_ADMIT=all selects the latter at creation.
  * Errors: MF4D_ERR_ARG (unknown mode). */
 int mf4d_set_admit_mode(mf4d_ctx *ctx, int mode);
+
+/* Direction of the trajectory edges (a particle-step and the same particle
+ * at the next step; trajectories carry a feature between timesteps, Section
+ * 1).  MF4D_TRAJ_BOTH (default): membership spreads both ways along a run of
+ * admissible steps.  MF4D_TRAJ_FORWARD (causal coupling): only from t to
+ * t + 1, so a particle joins at the first step that touches the feature and
+ * keeps its later admissible steps; the field's t - 1 / t + 1 edges and the
+ * particle-voxel coupling stay undirected, and the result is the set that the
+ * seeds reach along the directed edges.  Applies to mf4d_grow and
+ * mf4d_grow_batched; it invalidates the labels of an earlier grow.
+ * Errors: MF4D_ERR_ARG (unknown mode). */
+int mf4d_set_trajectory_mode(mf4d_ctx *ctx, int mode);
 
 /* Cap on rounds per mf4d_grow / mf4d_grow_resume call (0 = no cap). */
 int mf4d_set_max_rounds(mf4d_ctx *ctx, int64_t cap);

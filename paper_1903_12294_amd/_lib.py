@@ -24,6 +24,8 @@ MF4D_HOST = 0
 MF4D_DEVICE = 1
 MF4D_ADMIT_TILES = 0
 MF4D_ADMIT_ALL = 1
+MF4D_TRAJ_BOTH = 0
+MF4D_TRAJ_FORWARD = 1
 MF4D_SCHED_PERSISTENT = 0
 MF4D_SCHED_LAUNCH = 1
 
@@ -74,6 +76,7 @@ SIGNATURES = {
     "mf4d_set_schedule": (c_int, [c_void_p, c_int]),
     "mf4d_set_admit_mode": (c_int, [c_void_p, c_int]),
     "mf4d_set_max_rounds": (c_int, [c_void_p, c_int64]),
+    "mf4d_set_trajectory_mode": (c_int, [c_void_p, c_int]),
     "mf4d_grow": (c_int, [c_void_p, POINTER(Stats)]),
     "mf4d_grow_resume": (c_int, [c_void_p, POINTER(Stats)]),
     "mf4d_read_field_mask": (c_int, [c_void_p, c_void_p, c_size_t, c_int]),

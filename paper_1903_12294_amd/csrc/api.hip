@@ -93,6 +93,7 @@ struct mf4d_ctx {
     float2* tsum = nullptr;
     uint32_t* cand = nullptr;
     int admit_all = 0;
+    int forward_only = 0;  // trajectory coupling from t to t + 1 only
 
     bool has_particles = false;
     PGeom pg{};
@@ -303,6 +304,7 @@ Dev make_dev(mf4d_ctx* c) {
     d.cand = c->cand;
     d.tpred = nullptr;
     d.admit_all = c->admit_all;
+    d.forward_only = c->forward_only;
     for (int i = 0; i < 4; ++i) d.crit[i] = c->crit[i];
     return d;
 }
@@ -748,6 +750,15 @@ int mf4d_set_admit_mode(mf4d_ctx* c, int mode) {
     return MF4D_OK;
 }
 
+int mf4d_set_trajectory_mode(mf4d_ctx* c, int mode) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    if (mode != MF4D_TRAJ_BOTH && mode != MF4D_TRAJ_FORWARD)
+        return fail(MF4D_ERR_ARG, "unknown trajectory mode %d", mode);
+    c->forward_only = mode == MF4D_TRAJ_FORWARD;
+    c->state = 0;  // labels of an earlier grow no longer describe this mode
+    return MF4D_OK;
+}
+
 int mf4d_set_phase_timing(mf4d_ctx* c, int on) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
     if (on != 0 && on != 1) return fail(MF4D_ERR_ARG, "on must be 0 or 1");
@@ -1071,6 +1082,7 @@ int mf4d_grow_batched(mf4d_ctx* c, uint32_t* fplanes, size_t fwords, uint32_t* p
     d.dlist = c->dlist;
     d.counters = c->b_counters;
     d.stat64 = c->stat64;
+    d.forward_only = c->forward_only;
     hipStream_t s = c->stream;
     HIP_TRY(hipEventRecord(c->ev[0], s));
     launch_b_prepare(d, c->qseeds, c->QS, s);

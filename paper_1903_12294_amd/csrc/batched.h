@@ -43,6 +43,7 @@ struct DevB {
     uint32_t* dlist;         // P
     uint32_t* counters;      // BCounter
     unsigned long long* stat64;
+    int forward_only;        // 1: membership runs along a trajectory from t to t + 1 only
 };
 
 void launch_b_prepare(const DevB& d, const int32_t* seeds, int64_t S, hipStream_t s);

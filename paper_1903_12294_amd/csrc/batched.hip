@@ -434,13 +434,15 @@ __global__ __launch_bounds__(256) void kb_pull(DevB d, int par) {
 }
 
 // Close and push one particle for every query plane: forward and backward
-// passes along its steps spread members over admissible runs; each step that
-// gains queries pushes them into its voxel where the voxel is admissible.
+// passes along its steps spread members over admissible runs (the forward
+// pass alone with forward-only coupling); each step that gains queries pushes
+// them into its voxel where the voxel is admissible.
 __device__ void bclose_particle(const DevB& d, uint32_t p, int par) {
     atomicAnd(&d.pdirty[p >> 5], ~(1u << (p & 31)));
     const BandTables tp = particle_tables(d);
     const BandTables tf = field_tables(d);
-    for (int dir = 0; dir < 2; ++dir) {
+    const int ndir = d.forward_only ? 1 : 2;
+    for (int dir = 0; dir < ndir; ++dir) {
         uint32_t carry[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         for (int i = 0; i < d.T; ++i) {
             const int t = dir == 0 ? i : d.T - 1 - i;

@@ -49,6 +49,11 @@ __device__ __forceinline__ uint64_t fill_runs64(uint64_t l, uint64_t a) {
         fill_up64(__builtin_bitreverse64(l), __builtin_bitreverse64(a)));
     return up | dn;
 }
+// Trajectory closure of a label word: whole runs, or with forward-only
+// coupling the part of each run at or after its first member step.
+__device__ __forceinline__ uint64_t close_word(uint64_t l, uint64_t a, int forward_only) {
+    return forward_only ? fill_up64(l, a) : fill_runs64(l, a);
+}
 
 __device__ __forceinline__ uint32_t tile_of(const Geom& g, int tx, int ty, int tz, int tt) {
     return ((uint32_t)(tt * g.NZt + tz) * g.NYt + ty) * g.NXt + tx;
@@ -519,16 +524,17 @@ __device__ __forceinline__ void push_one(const Dev& d, uint32_t e, int par) {
 }
 
 // Close one dirty particle: its member steps spread over each run of
-// admissible steps that holds them (its trajectory).  With one label word
-// (W = 1) the new steps are returned for the caller to push; with more words
-// they are pushed here and 0 is returned.
+// admissible steps that holds them (its trajectory; forward in time only with
+// forward-only coupling).  With one label word (W = 1) the new steps are
+// returned for the caller to push; with more words they are pushed here and 0
+// is returned.
 __device__ unsigned long long close_one(const Dev& d, uint32_t p, int par) {
     const int W = d.pg.W;
     unsigned long long* lw = d.Lp + (size_t)p * W;
     const unsigned long long* aw = d.Ap + (size_t)p * W;
     if (W == 1) {
         const unsigned long long a = aw[0], l0 = lw[0];
-        const unsigned long long nw = fill_runs64(l0, a) & ~l0;
+        const unsigned long long nw = close_word(l0, a, d.forward_only) & ~l0;
         if (nw) atomicOr(&lw[0], nw);
         return nw;
     }
@@ -536,7 +542,7 @@ __device__ unsigned long long close_one(const Dev& d, uint32_t p, int par) {
     unsigned long long carry = 0;
     for (int w = 0; w < W; ++w) {
         const unsigned long long a = aw[w], l0 = lw[w];
-        unsigned long long l = fill_runs64(l0 | (carry & a & 1ull), a);
+        unsigned long long l = close_word(l0 | (carry & a & 1ull), a, d.forward_only);
         carry = l >> 63;
         const unsigned long long nw = l & ~l0;
         if (nw) {
@@ -544,6 +550,7 @@ __device__ unsigned long long close_one(const Dev& d, uint32_t p, int par) {
             push_steps(d, p, w, nw, par);
         }
     }
+    if (d.forward_only) return 0ull;
     carry = 0;
     for (int w = W - 1; w >= 0; --w) {
         const unsigned long long a = aw[w], l0 = lw[w];
@@ -674,7 +681,7 @@ __device__ uint32_t pull_close_wave(const Dev& d, int par, uint32_t wave_id, uin
             if (old & bit) continue;
             ++joins;
             const unsigned long long known = old | bit;
-            const unsigned long long nw = fill_runs64(known, d.Ap[p]) & ~known;
+            const unsigned long long nw = close_word(known, d.Ap[p], d.forward_only) & ~known;
             if (nw) {
                 // push only the bits this closure set: a concurrent joiner of
                 // the same run closes it too, and pushing it twice would double

@@ -113,6 +113,7 @@ struct Dev {
     const uint8_t* tpred;    // NT or null: candidate tiles to test before the rounds
     float crit[4];
     int admit_all;           // 1: test every voxel-step; 0: only candidate tiles
+    int forward_only;        // 1: membership runs along a trajectory from t to t + 1 only
 };
 
 // ---- launchers (kernels.hip) ----

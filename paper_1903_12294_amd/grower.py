@@ -121,6 +121,12 @@ class Grower:
         m = {"tiles": _lib.MF4D_ADMIT_TILES, "all": _lib.MF4D_ADMIT_ALL}[mode]
         self._check(self.lib.mf4d_set_admit_mode(self.ctx, m))
 
+    def set_trajectory_mode(self, mode):
+        """"both" (membership spreads both ways along a trajectory) or
+        "forward" (causal: from t to t + 1 only)."""
+        m = {"both": _lib.MF4D_TRAJ_BOTH, "forward": _lib.MF4D_TRAJ_FORWARD}[mode]
+        self._check(self.lib.mf4d_set_trajectory_mode(self.ctx, m))
+
     def set_phase_timing(self, on: bool):
         """Device times of each launched round's kernels in the stats (costs a
         few microseconds per event; off by default)."""
