@@ -16,6 +16,6 @@ Contents
   segments -- the trajectory segment rule: runs of >= 2 consecutive steps
             of a particle in one feature.
 """
-from .bfs import build_oracle, oracle_grow, oracle_grow_queries  # noqa: F401
+from .bfs import build_oracle, oracle_grow, oracle_grow_queries, oracle_seed_ids  # noqa: F401
 from .sweep import sweep_grow  # noqa: F401
 from .check import check_invariants, edge_list, components_grow, reach_grow  # noqa: F401

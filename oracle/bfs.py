@@ -103,6 +103,26 @@ def oracle_grow_queries(field, xyz, attr, crit_q: np.ndarray, qseeds: np.ndarray
         return dict(ex.map(one, qs))
 
 
+def oracle_seed_ids(field, xyz, attr, crit, seeds, forward_only: bool = False):
+    """Per-seed component ids: every node gets the index of the lowest seed
+    whose own grown region (a grow from that seed alone) holds it, -1 where no
+    seed reaches.  Returns (field ids int32 [T][Z][Y][X], particle ids int32
+    [T][P]).  One oracle grow per seed, in index order."""
+    field = np.ascontiguousarray(field, np.float32)
+    T, Z, Y, X = field.shape
+    P = 0 if xyz is None else xyz.shape[1]
+    fid = np.full(field.size, -1, np.int32)
+    pid = np.full((T, P), -1, np.int32)
+    seeds = np.asarray(seeds, np.int32).reshape(-1, 4)
+    for i, s in enumerate(seeds):
+        fm, pm, _ = oracle_grow(field, xyz, attr, crit, s[None], forward_only=forward_only)
+        bits = np.unpackbits(fm.view(np.uint8), bitorder="little")[:field.size].astype(bool)
+        fid[bits & (fid < 0)] = i
+        if P:
+            pid[(pm != 0) & (pid < 0)] = i
+    return fid.reshape(T, Z, Y, X), pid
+
+
 class OracleError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"oracle error {code}: {msg}")
