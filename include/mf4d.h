@@ -225,6 +225,24 @@ int mf4d_read_particle_mask(mf4d_ctx *ctx, uint8_t *dst, size_t n, int where);
  * Errors: MF4D_ERR_STATE (nothing grown or no particles), MF4D_ERR_ARG. */
 int mf4d_read_particle_segments(mf4d_ctx *ctx, uint8_t *dst, size_t n, int where);
 
+/* Per-seed component ids: which seed a grown node belongs to.  Every node gets
+ * the index (in the context's seed list) of the lowest seed whose own region
+ * -- a grow from that seed alone, with the context's criteria and trajectory
+ * mode -- holds it, or -1.  With undirected coupling the regions are the
+ * connected components that hold seeds, so each carries its lowest seed; with
+ * forward-only coupling regions may overlap and the lowest index wins.  The
+ * labelled nodes are exactly those of mf4d_grow.  Runs one grow per seed not
+ * already inside an earlier seed's region (*grows, nullable, receives their
+ * number), in index order.  field_ids: int32 [T][Z][Y][X], nf >= X*Y*Z*T;
+ * particle_ids: int32 [T][P], np >= T*P, or NULL.  Allocates a scratch of
+ * 2 bits per voxel-step and 1 bit per particle-step for the call.  Leaves the
+ * context with no grown labels (mf4d_grow again before reading masks).
+ * Waits for the device.
+ * Errors: MF4D_ERR_STATE (no field or no criteria), MF4D_ERR_ARG,
+ * MF4D_ERR_NOT_CONVERGED (a round cap stopped a grow), MF4D_ERR_OOM. */
+int mf4d_grow_seed_ids(mf4d_ctx *ctx, int32_t *field_ids, size_t nf, int32_t *particle_ids, size_t np,
+                       int where, int64_t *grows);
+
 /* Batched queries (up to 256, each with its own criteria and seeds), grown
  * together as the bit-planes of one 256-bit label per node.  crit fp32
  * [Q][4] = (f_lo, f_hi, a_lo, a_hi) per query; seeds int32 [S][5] =

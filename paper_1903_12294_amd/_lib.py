@@ -82,6 +82,7 @@ SIGNATURES = {
     "mf4d_read_field_mask": (c_int, [c_void_p, c_void_p, c_size_t, c_int]),
     "mf4d_read_particle_mask": (c_int, [c_void_p, c_void_p, c_size_t, c_int]),
     "mf4d_read_particle_segments": (c_int, [c_void_p, c_void_p, c_size_t, c_int]),
+    "mf4d_grow_seed_ids": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, c_int, c_void_p]),
     "mf4d_last_stats": (c_int, [c_void_p, POINTER(Stats)]),
     "mf4d_slic_set_params": (c_int, [c_void_p, c_void_p, c_float, c_float, c_float, c_float, c_double, c_int]),
     "mf4d_slic_run": (c_int, [c_void_p, c_void_p]),

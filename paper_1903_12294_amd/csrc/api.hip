@@ -927,6 +927,90 @@ int mf4d_read_particle_segments(mf4d_ctx* c, uint8_t* dst, size_t n, int where) 
     return sync(c);
 }
 
+int mf4d_grow_seed_ids(mf4d_ctx* c, int32_t* field_ids, size_t nf, int32_t* particle_ids, size_t np,
+                       int where, int64_t* grows) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    if (!c->has_field) return fail(MF4D_ERR_STATE, "no field loaded");
+    if (!c->has_crit) return fail(MF4D_ERR_STATE, "no criteria set");
+    if (where != MF4D_HOST && where != MF4D_DEVICE) return fail(MF4D_ERR_ARG, "bad where");
+    const Geom& g = c->g;
+    const size_t V = (size_t)g.X * g.Y * g.Z * g.T;
+    const int64_t P = c->has_particles ? c->pg.P : 0;
+    const size_t Qp = (size_t)P * g.T;
+    if (!field_ids || nf < V) return fail(MF4D_ERR_ARG, "field ids need %zu elements", V);
+    const bool want_p = P > 0 && particle_ids;
+    if (want_p && np < Qp) return fail(MF4D_ERR_ARG, "particle ids need %zu elements", Qp);
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    const int64_t S = c->S;
+    std::vector<int32_t> hs((size_t)S * 4);
+    if (S > 0) HIP_TRY(hipMemcpy(hs.data(), c->seeds, hs.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    int32_t* fo = field_ids;
+    int32_t* po = want_p ? particle_ids : nullptr;
+    if (where == MF4D_HOST) {
+        void* st = nullptr;
+        int rc = staging_for(c, (V + (want_p ? Qp : 0)) * sizeof(int32_t), &st);
+        if (rc) return rc;
+        fo = (int32_t*)st;
+        po = want_p ? fo + V : nullptr;
+    }
+    // canonical member words of one grow, and the members seen so far
+    struct Scratch {
+        uint32_t* words = nullptr;
+        uint32_t* seen_f = nullptr;
+        unsigned long long* seen_p = nullptr;
+        ~Scratch() { dev_free(words); dev_free(seen_f); dev_free(seen_p); }
+    } sc;
+    const size_t nw = (V + 31) / 32, pw = (size_t)(g.T + 63) / 64;
+    int rc = dev_alloc(&sc.words, nw);
+    if (!rc) rc = dev_alloc(&sc.seen_f, nw);
+    if (!rc && po) rc = dev_alloc(&sc.seen_p, (size_t)P * pw);
+    if (rc) return rc;
+    launch_fill_u32((uint32_t*)fo, 0xFFFFFFFFu, V, s);
+    launch_fill_u32(sc.seen_f, 0u, nw, s);
+    if (po) {
+        launch_fill_u32((uint32_t*)po, 0xFFFFFFFFu, Qp, s);
+        launch_fill_u32((uint32_t*)sc.seen_p, 0u, 2 * (size_t)P * pw, s);
+    }
+    int32_t* const all_seeds = c->seeds;
+    int64_t ngrow = 0;
+    for (int64_t i = 0; i < S; ++i) {
+        const int32_t* sd = &hs[(size_t)i * 4];
+        const size_t v = (((size_t)sd[3] * g.Z + sd[2]) * g.Y + sd[1]) * g.X + sd[0];
+        // a seed inside an earlier seed's region reaches nothing new (every
+        // node it reaches, that region reaches); an inadmissible one is dropped
+        int32_t cur = 0;
+        float fv = 0.0f;
+        HIP_TRY(hipMemcpyAsync(&cur, fo + v, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&fv, c->field + v, sizeof(float), hipMemcpyDeviceToHost, s));
+        rc = sync(c);
+        if (rc) return rc;
+        if (cur != -1 || !(c->crit[0] <= fv && fv <= c->crit[1])) continue;
+        c->seeds = all_seeds + 4 * i;
+        c->S = 1;
+        rc = mf4d_grow(c, nullptr);
+        c->seeds = all_seeds;
+        c->S = S;
+        if (rc) {
+            c->state = 0;
+            return rc;
+        }
+        ++ngrow;
+        const Dev d = make_dev(c);
+        launch_read_field(d, sc.words, s);
+        launch_seed_ids(d, sc.words, sc.seen_f, sc.seen_p, (int32_t)i, fo, po, s);
+    }
+    c->state = 0;  // the labels hold the last single-seed grow, not the seeds' union
+    if (where == MF4D_HOST) {
+        HIP_TRY(hipMemcpyAsync(field_ids, fo, V * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        if (po) HIP_TRY(hipMemcpyAsync(particle_ids, po, Qp * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    }
+    rc = sync(c);
+    if (rc) return rc;
+    if (grows) *grows = ngrow;
+    return MF4D_OK;
+}
+
 int mf4d_set_queries(mf4d_ctx* c, int Q, const float* crit, const int32_t* qxyzt, int64_t S,
                      int where) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");

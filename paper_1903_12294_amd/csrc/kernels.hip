@@ -1699,6 +1699,57 @@ __global__ __launch_bounds__(256) void k_particle_segments(Dev d, uint8_t* __res
     }
 }
 
+// Per-seed component ids, field part.  words: canonical member bits of a grow
+// from one seed; seen: the members of the earlier seeds' grows.  A member no
+// earlier grow reached takes `id` (seeds run in index order, so each node
+// keeps the lowest index whose region holds it).  A thread owns whole words.
+__global__ __launch_bounds__(256) void k_seed_ids_field(const uint32_t* __restrict__ words,
+                                                        uint32_t* __restrict__ seen, uint64_t V, int32_t id,
+                                                        int32_t* __restrict__ out) {
+    const uint64_t nw = (V + 31) >> 5;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nw; i += stride) {
+        const uint32_t w = words[i];
+        if (!w) continue;
+        const uint32_t s = seen[i];
+        uint32_t n = w & ~s;
+        if (!n) continue;
+        seen[i] = s | n;
+        while (n) {
+            const uint64_t v = i * 32 + (uint64_t)(__ffs(n) - 1);
+            n &= n - 1;
+            if (v < V) out[v] = id;
+        }
+    }
+}
+
+// Per-seed component ids, particle part: the same over each particle's label
+// words (seen: [P][ceil(T / 64)] words); out is int32 [T][P].
+__global__ __launch_bounds__(256) void k_seed_ids_particles(Dev d, unsigned long long* __restrict__ seen,
+                                                            int32_t id, int32_t* __restrict__ out) {
+    const PGeom& pg = d.pg;
+    const int nw = (pg.T + 63) >> 6;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < pg.P; p += stride) {
+        if (!d.pflag[p]) continue;
+        for (int w = 0; w < nw; ++w) {
+            const int valid = min(64, pg.T - w * 64);
+            const unsigned long long vm = valid >= 64 ? ~0ull : ((1ull << valid) - 1);
+            const unsigned long long L = d.Lp[(size_t)p * pg.W + w] & vm;
+            if (!L) continue;
+            const unsigned long long s = seen[(size_t)p * nw + w];
+            unsigned long long n = L & ~s;
+            if (!n) continue;
+            seen[(size_t)p * nw + w] = s | n;
+            while (n) {
+                const int64_t t = w * 64 + __builtin_ctzll(n);
+                n &= n - 1;
+                out[t * pg.P + p] = id;
+            }
+        }
+    }
+}
+
 inline unsigned grid_for(uint64_t n, unsigned block, unsigned cap) {
     uint64_t b = (n + block - 1) / block;
     if (b < 1) b = 1;
@@ -1878,6 +1929,16 @@ void launch_particle_segments(const Dev& d, uint8_t* out, hipStream_t s) {
     if (pg.P == 0 || pg.T == 0) return;
     hipLaunchKernelGGL(k_particle_segments, dim3(grid_for((pg.P + 3) / 4, 256, 1u << 16)), dim3(256), 0,
                        s, d, out);
+}
+
+void launch_seed_ids(const Dev& d, const uint32_t* words, uint32_t* seen_f, unsigned long long* seen_p,
+                     int32_t id, int32_t* field_ids, int32_t* particle_ids, hipStream_t s) {
+    const uint64_t V = (uint64_t)d.g.X * d.g.Y * d.g.Z * d.g.T;
+    hipLaunchKernelGGL(k_seed_ids_field, dim3(grid_for((V + 31) / 32, 256, 16384)), dim3(256), 0, s, words,
+                       seen_f, V, id, field_ids);
+    if (particle_ids && d.pg.P > 0)
+        hipLaunchKernelGGL(k_seed_ids_particles, dim3(grid_for((uint64_t)d.pg.P, 256, 16384)), dim3(256), 0, s,
+                           d, seen_p, id, particle_ids);
 }
 
 }  // namespace mf4d

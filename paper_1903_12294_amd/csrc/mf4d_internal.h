@@ -138,6 +138,12 @@ void launch_read_field(const Dev& d, uint32_t* out, hipStream_t s);
 void launch_read_particles(const Dev& d, uint8_t* out, hipStream_t s);
 // Trajectory segments of the grown feature as uint8 [T][P] (Section 3.4).
 void launch_particle_segments(const Dev& d, uint8_t* out, hipStream_t s);
+// Fold one single-seed grow into per-seed ids: members of the canonical field
+// words and of the particle labels that no earlier grow reached (seen_f: one
+// bit per voxel-step, seen_p: [P][ceil(T / 64)] words) take id.  particle_ids
+// may be null.
+void launch_seed_ids(const Dev& d, const uint32_t* words, uint32_t* seen_f, unsigned long long* seen_p,
+                     int32_t id, int32_t* field_ids, int32_t* particle_ids, hipStream_t s);
 // stat64[dst] (+)= sum of slot statistic `which` (assign: =), and those slots cleared.
 void launch_fold_slots(const Dev& d, int which, int dst, hipStream_t s, bool assign = false);
 // The per-grow statistics (particle visits, active and tested tiles) folded

@@ -199,6 +199,32 @@ class Grower:
                 self.ctx, out.ctypes.data_as(ctypes.c_void_p), n, MF4D_HOST))
         return out
 
+    def grow_seed_ids(self, field_out=None, particle_out=None):
+        """Per-seed component ids: (field int32 [T][Z][Y][X], particle int32
+        [T][P], number of grows run); each grown node carries the lowest seed
+        index whose own region holds it, others -1.  Outputs may be device
+        tensors (int32) or numpy arrays; the context holds no grown labels
+        afterwards."""
+        X, Y, Z = self.dims
+        T, P = self.T, self.P
+        if field_out is None:
+            field_out = np.zeros((T, Z, Y, X), np.int32)
+        if particle_out is None:
+            particle_out = np.zeros((T, P), np.int32)
+        dev = _is_device_tensor(field_out)
+        if dev != _is_device_tensor(particle_out):
+            raise ValueError("both outputs on the device or both on the host")
+
+        def ptr(a):
+            return ctypes.c_void_p(a.data_ptr()) if dev else a.ctypes.data_as(ctypes.c_void_p)
+        n_f = field_out.numel() if dev else field_out.size
+        n_p = particle_out.numel() if dev else particle_out.size
+        grows = ctypes.c_int64(0)
+        self._check(self.lib.mf4d_grow_seed_ids(self.ctx, ptr(field_out), n_f,
+                                                ptr(particle_out) if n_p else None, n_p,
+                                                MF4D_DEVICE if dev else MF4D_HOST, ctypes.byref(grows)))
+        return field_out, particle_out, int(grows.value)
+
     # -- 4D SLIC clustering (Section 3.2) ------------------------------------
     def slic_set_params(self, k, w_d: float, w_f: float, w_p: float, c_f: float, eps: float,
                         max_iter: int):
