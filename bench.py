@@ -10,6 +10,10 @@ schedule, admissibility mode) is the autotuner's pick, every candidate
 checked to give identical masks.
 
 Beside the headline the bench reports, on the same GPU:
+  forward_only - the same grow with causal trajectory coupling (t -> t+1
+             only), its masks compared with the directed oracle;
+  seed_ids - per-seed component ids of the same grow (lowest seed index
+             per node), labelled nodes compared with the oracle's union grow;
   segments - the trajectory segments of the grown feature (runs of >= 2
              member steps), timed as a read-out pass, sampled particles
              compared with the oracle's rule on the oracle's mask;
@@ -38,8 +42,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # 1 GiB copy), per (kernel, library version); a kernel changed since then has none.
 # Source: profiles/grow_256x256x256x64_bt16_launch_hbm_counters.md.
 MEASURED_TRAFFIC = {
-    ("k_round_pull", "mf4d 0.4.0 (gfx950)"): 54478452,
-    ("k_round_sweep<16>", "mf4d 0.4.0 (gfx950)"): 14043459,
+    ("k_round_pull", "mf4d 0.5.0 (gfx950)"): 54470937,
+    ("k_round_sweep<16>", "mf4d 0.5.0 (gfx950)"): 14022865,
 }
 PREDICTOR = os.path.join(ROOT, "paper_1903_12294_amd", "predictor.npy")
 
@@ -364,6 +368,64 @@ def bench_batched(args, torch, log):
             "autotune": tune["table"]}
 
 
+def bench_adjacent(g, inst, fmask, pmask, args, torch, forms):
+    """Adjacent outputs of the grower on the headline workload, on the same
+    context: the trajectory segment read-out, the grow with forward-only
+    coupling, and the per-seed component ids.  Fills `forms`; returns what the
+    oracle checks afterwards."""
+    dev = torch.device("cuda:0")
+    X, Y, Z = inst["dims"]
+    T, P = inst["T"], inst["P"]
+    V = X * Y * Z * T
+    # trajectory segments of the grown feature (Section 3.4): a read-out pass
+    seg = torch.empty((T, P), dtype=torch.uint8, device=dev)
+    ms_seg = time_call(lambda: g.read_particle_segments(seg), torch)
+    seg_sel = np.sort(np.random.default_rng(12).choice(P, min(P, 4096), replace=False))
+    seg_cols = seg[:, torch.from_numpy(seg_sel).to(dev)].cpu().numpy()
+    seg_kept = int(seg.sum(dtype=torch.int64).item())
+    del seg
+    # label words, candidate flags, output bytes
+    seg_bytes = 8 * max(1, (T + 63) // 64) * P + P + T * P
+    forms_seg = {"ms": round(ms_seg, 4), "kept_particle_steps": seg_kept, "hbm_bytes": seg_bytes,
+                 "achieved_GBps": round(seg_bytes / (ms_seg * 1e-3) / 1e9, 1),
+                 "frac": round(seg_bytes / (ms_seg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    forms["segments"] = forms_seg
+    # forward-only (causal) trajectory coupling: the same workload and
+    # configuration, a different fixed point
+    g.set_trajectory_mode("forward")
+    rf = run_steps(g, fmask, pmask, args.steps, 2, torch)
+    fwd_f, fwd_p = fmask.clone(), pmask.clone()
+    forms["forward_only"] = {"ms_per_step": round(rf["ms"], 4), "value": round(V / (rf["ms"] * 1e-3), 1),
+                             "rounds": rf["stats"]["rounds"],
+                             "members_field": rf["stats"]["members_field"],
+                             "members_particle": rf["stats"]["members_particle"]}
+    g.set_trajectory_mode("both")
+    # per-seed component ids: one grow per seed outside the earlier seeds'
+    # regions, folded into int32 ids
+    fid = torch.empty((T, Z, Y, X), dtype=torch.int32, device=dev)
+    pid = torch.empty((T, P), dtype=torch.int32, device=dev)
+    g.grow_seed_ids(fid, pid)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, n_grows = g.grow_seed_ids(fid, pid)
+    ms_ids = (time.perf_counter() - t0) * 1e3
+    sd = np.asarray(inst["seeds"], np.int64).reshape(-1, 4)
+    sd_d = torch.from_numpy(((sd[:, 3] * Z + sd[:, 2]) * Y + sd[:, 1]) * X + sd[:, 0]).to(dev)
+    seed_id = fid.view(-1)[sd_d].cpu().numpy()
+    # labelled field nodes as canonical bit words, to compare with the masks
+    lab = np.packbits(fid.view(-1).cpu().numpy() >= 0, bitorder="little")
+    ids_words = np.zeros((V + 31) // 32, np.uint32)
+    ids_words.view(np.uint8)[:len(lab)] = lab
+    del lab
+    ids_pl = (pid >= 0).cpu().numpy()
+    forms["seed_ids"] = {"ms": round(ms_ids, 3), "seeds": int(len(sd)), "grows": n_grows,
+                         "ids_in_use": int(torch.unique(fid[fid >= 0]).numel()),
+                         "seed_ids": [int(v) for v in seed_id]}
+    del fid, pid
+    return dict(seg_sel=seg_sel, seg_cols=seg_cols, fwd_f=fwd_f, fwd_p=fwd_p, ids_words=ids_words,
+                ids_pl=ids_pl, sd=sd)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -375,7 +437,9 @@ def main():
     ap.add_argument("--admit", choices=["tiles", "all"], help="fix the admissibility mode (no tuning)")
     ap.add_argument("--tile-t", type=int, choices=[4, 8, 16], help="fix the tile depth (no tuning)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-forms", action="store_true", help="skip eager / learned / batched")
+    ap.add_argument("--no-forms", action="store_true", help="the headline grow only (no other form)")
+    ap.add_argument("--slic-only", action="store_true",
+                    help="only the clustering form (for profiling its kernels); prints its JSON object")
     ap.add_argument("--batched-reps", type=int, default=3)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run three 1 GiB device copies (a plain copy kernel of known size, "
@@ -397,6 +461,9 @@ def main():
     t0 = time.time()
     inst = synth.make_config(args.config)
     log(f"[bench] generated {cfg['name']} in {time.time() - t0:.1f}s")
+    if args.slic_only:
+        print(json.dumps(bench_slic(torch, log, inst, cfg["name"])), flush=True)
+        return
     X, Y, Z = inst["dims"]
     T, P = inst["T"], inst["P"]
     V, Q = X * Y * Z * T, P * T
@@ -452,19 +519,6 @@ def main():
                 "bytes_per_launch": kt[dom]["bytes_per_launch"],
                 "ms_per_launch": kt[dom]["ms_per_launch"]}
 
-    # trajectory segments of the grown feature (Section 3.4): a read-out pass
-    seg = torch.empty((T, P), dtype=torch.uint8, device=dev)
-    ms_seg = time_call(lambda: g.read_particle_segments(seg), torch)
-    seg_sel = np.sort(np.random.default_rng(12).choice(P, min(P, 4096), replace=False))
-    seg_cols = seg[:, torch.from_numpy(seg_sel).to(dev)].cpu().numpy()
-    seg_kept = int(seg.sum(dtype=torch.int64).item())
-    del seg
-    # label words, candidate flags, output bytes
-    seg_bytes = 8 * max(1, (T + 63) // 64) * P + P + T * P
-    forms_seg = {"ms": round(ms_seg, 4), "kept_particle_steps": seg_kept, "hbm_bytes": seg_bytes,
-                 "achieved_GBps": round(seg_bytes / (ms_seg * 1e-3) / 1e9, 1),
-                 "frac": round(seg_bytes / (ms_seg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-
     if args.copy_probe:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
@@ -474,7 +528,10 @@ def main():
         del a, b
     ref_f = fmask.clone()
     ref_p = pmask.clone()
-    forms = {"segments": forms_seg}
+    forms = {}
+    checks = None
+    if not args.no_forms:
+        checks = bench_adjacent(g, inst, fmask, pmask, args, torch, forms)
     if not args.no_forms:
         # eager: every sample tested each step
         g.set_admit_mode("all")
@@ -534,10 +591,31 @@ def main():
                "host_cores_available": os.cpu_count()}
         parity = bool(np.array_equal(ref_f.cpu().numpy().view(np.uint32), ofm)
                       and np.array_equal(ref_p.cpu().numpy(), opm))
-        from oracle import segments as oseg
-        forms_seg["parity_sampled_particles"] = bool(np.array_equal(seg_cols, oseg.mask_segments(opm[:, seg_sel])))
-        forms_seg["particles_checked"] = int(len(seg_sel))
-        log(f"[bench] oracle {tc:.1f}s, parity {parity}, segments parity {forms_seg['parity_sampled_particles']}")
+        if checks:
+            t0 = time.perf_counter()
+            ffm, fpm, _ = oracle_grow(inst["field"], inst["xyz"], inst["attr"], inst["crit"], inst["seeds"],
+                                      forward_only=True)
+            fo = forms["forward_only"]
+            fo["oracle_s"] = round(time.perf_counter() - t0, 1)
+            fo["parity_vs_oracle"] = bool(np.array_equal(checks["fwd_f"].cpu().numpy().view(np.uint32), ffm)
+                                          and np.array_equal(checks["fwd_p"].cpu().numpy(), fpm))
+            # per-seed ids: labelled nodes are the union grow; a seed's own
+            # voxel holds an id no larger than its index
+            si = forms["seed_ids"]
+            adm = [bool(inst["crit"][0] <= inst["field"][t, z, y, x] <= inst["crit"][1])
+                   for x, y, z, t in checks["sd"]]
+            si["labelled_equal_oracle_union"] = bool(
+                np.array_equal(checks["ids_words"], ofm) and np.array_equal(checks["ids_pl"], opm != 0))
+            si["seed_voxels_consistent"] = bool(all(
+                (0 <= s_id <= j) if a else True for j, (s_id, a) in enumerate(zip(si["seed_ids"], adm))))
+            from oracle import segments as oseg
+            sg = forms["segments"]
+            sg["parity_sampled_particles"] = bool(
+                np.array_equal(checks["seg_cols"], oseg.mask_segments(opm[:, checks["seg_sel"]])))
+            sg["particles_checked"] = int(len(checks["seg_sel"]))
+            log(f"[bench] forward-only parity {fo['parity_vs_oracle']}, seed ids {si['labelled_equal_oracle_union']}"
+                f"/{si['seed_voxels_consistent']}, segments parity {sg['parity_sampled_particles']}")
+        log(f"[bench] oracle {tc:.1f}s, parity {parity}")
 
     out = {
         "metric": "voxel-timesteps segmented/s to fixed point",
