@@ -32,12 +32,13 @@ def admissible(field, attr, crit):
     return Af, Ap
 
 
-def edge_list(field, xyz, attr, crit, restrict_f=None, restrict_p=None, trajectories=True):
+def edge_list(field, xyz, attr, crit, restrict_f=None, restrict_p=None, trajectories=True, rate=1):
     """Edges (a, b) between admissible nodes.  Voxel node id = canonical index
     ((t*Z+z)*Y+y)*X+x; particle node id = V + t*P + i.  Optional boolean
     restrict_* masks further limit the node set (used for I4).  Trajectory
     edges (i, t) - (i, t+1) come in the order (earlier, later); trajectories
-    = False leaves them out."""
+    = False leaves them out.  rate: particle steps per field step (particle
+    step tau lies in field step tau // rate); particle node id = V + tau*P + i."""
     field = np.asarray(field, np.float32)
     T, Z, Y, X = field.shape
     V = field.size
@@ -59,18 +60,19 @@ def edge_list(field, xyz, attr, crit, restrict_f=None, restrict_p=None, trajecto
     if P:
         if restrict_p is not None:
             Ap = Ap & restrict_p
-        pid = V + np.arange(T * P, dtype=np.int64).reshape(T, P)
+        Tp = xyz.shape[0]
+        pid = V + np.arange(Tp * P, dtype=np.int64).reshape(Tp, P)
         if trajectories:
             m = Ap[:-1] & Ap[1:]
             A.append(pid[:-1][m])
             B.append(pid[1:][m])
         ok, cx, cy, cz = particle_voxels(np.asarray(xyz, np.float32), (X, Y, Z))
-        tt = np.broadcast_to(np.arange(T)[:, None], (T, P))
+        tt = np.broadcast_to((np.arange(Tp) // rate)[:, None], (Tp, P))
         vox = idx[tt, cz, cy, cx]
         m = ok & Ap & Af[tt, cz, cy, cx]
         A.append(pid[m])
         B.append(vox[m])
-    return np.concatenate(A), np.concatenate(B), V, T * P
+    return np.concatenate(A), np.concatenate(B), V, (xyz.shape[0] * P if P else 0)
 
 
 def components_grow(field, xyz, attr, crit, seeds):
@@ -91,7 +93,7 @@ def components_grow(field, xyz, attr, crit, seeds):
     return member[:V].reshape(T, Z, Y, X), member[V:].reshape(T, P)
 
 
-def reach_grow(field, xyz, attr, crit, seeds, forward_only=True):
+def reach_grow(field, xyz, attr, crit, seeds, forward_only=True, rate=1):
     """M as the nodes reachable from the admissible seeds in the directed
     graph: every non-trajectory edge both ways, trajectory edges from t to
     t + 1 only (forward_only) or both ways; scipy's breadth-first order from
@@ -99,12 +101,13 @@ def reach_grow(field, xyz, attr, crit, seeds, forward_only=True):
     from scipy.sparse.csgraph import breadth_first_order
     field = np.asarray(field, np.float32)
     T, Z, Y, X = field.shape
-    a, b, V, Q = edge_list(field, xyz, attr, crit, trajectories=False)
+    a, b, V, Q = edge_list(field, xyz, attr, crit, trajectories=False, rate=rate)
     src, dst = [a, b], [b, a]
     P = 0 if xyz is None else xyz.shape[1]
     if P:
         _, Ap = admissible(field, attr, crit)
-        pid = V + np.arange(T * P, dtype=np.int64).reshape(T, P)
+        Tp = xyz.shape[0]
+        pid = V + np.arange(Tp * P, dtype=np.int64).reshape(Tp, P)
         m = Ap[:-1] & Ap[1:]
         src.append(pid[:-1][m])
         dst.append(pid[1:][m])
@@ -122,7 +125,8 @@ def reach_grow(field, xyz, attr, crit, seeds, forward_only=True):
     order = breadth_first_order(g, N, directed=True, return_predecessors=False)
     member = np.zeros(N + 1, bool)
     member[order] = True
-    return member[:V].reshape(T, Z, Y, X), member[V:N].reshape(T, P)
+    return member[:V].reshape(T, Z, Y, X), member[V:N].reshape(-1, P) if P else np.zeros(
+        (T if xyz is None else xyz.shape[0], 0), bool)
 
 
 def check_invariants(field, xyz, attr, crit, seeds, Mf, Mp):

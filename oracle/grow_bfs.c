@@ -27,7 +27,12 @@
  *   Result M = the nodes reachable from the admissible seeds inside the
  *   subgraph induced on admissible nodes.  Seeds that are not admissible are
  *   dropped and counted.
- *   Forward-only (causal) coupling, oracle_grow_dir with forward_only = 1:
+ *   Particles at their own temporal rate (oracle_grow_rate): the particles
+ *   hold Tp steps, r per field step; particle step tau lies at time tau / r
+ *   in field steps and couples with a voxel of field step floor(tau / r),
+ *   the step whose interval [t, t+1) holds that time.  Trajectory edges join
+ *   consecutive particle steps.  r = 1 and Tp = T is the plain case.
+ *   Forward-only (causal) coupling, forward_only = 1:
  *   the trajectory edge leads only from (i, t) to (i, t+1), so membership
  *   travels along a trajectory forward in time; every other edge stays
  *   undirected, and M is the set reachable along the directed edges.
@@ -36,7 +41,7 @@
  * index is a counting sort of particle-steps by voxel id (CSR).
  *
  * Output layouts: field mask bit ((t*Z + z)*Y + y)*X + x, word = bit >> 5,
- * LSB first; particle mask uint8 [T][P].
+ * LSB first; particle mask uint8 [Tp][P].
  */
 #include <math.h>
 #include <stdint.h>
@@ -95,17 +100,18 @@ static int test_and_set(uint64_t *bits, uint64_t i)
  * stats[4] = number of admissible seed entries.
  * Returns 0, OR_ERR_ARG, OR_ERR_RANGE (a seed outside the grid) or OR_ERR_OOM.
  */
-int oracle_grow_dir(const float *field, int64_t X, int64_t Y, int64_t Z, int64_t T,
-                    const float *xyz, const float *attr, int64_t P,
-                    float f_lo, float f_hi, float a_lo, float a_hi,
-                    const int32_t *seeds, int64_t S, int forward_only,
-                    uint32_t *fmask, uint8_t *pmask, int64_t *stats)
+int oracle_grow_rate(const float *field, int64_t X, int64_t Y, int64_t Z, int64_t T,
+                     const float *xyz, const float *attr, int64_t P, int64_t Tp, int64_t r,
+                     float f_lo, float f_hi, float a_lo, float a_hi,
+                     const int32_t *seeds, int64_t S, int forward_only,
+                     uint32_t *fmask, uint8_t *pmask, int64_t *stats)
 {
     if (X <= 0 || Y <= 0 || Z <= 0 || T <= 0 || P < 0 || S < 0) return OR_ERR_ARG;
+    if (r < 1 || Tp < 1 || Tp > r * T) return OR_ERR_ARG;
     if (!field || !fmask || !stats || (S > 0 && !seeds)) return OR_ERR_ARG;
     if (P > 0 && (!xyz || !attr || !pmask)) return OR_ERR_ARG;
     const uint64_t XY = (uint64_t)X * Y, XYZ = XY * Z, V = XYZ * T;
-    const uint64_t Q = (uint64_t)P * T;
+    const uint64_t Q = (uint64_t)P * Tp;
     if (V >= (uint64_t)UINT32_MAX || Q >= (uint64_t)UINT32_MAX) return OR_ERR_ARG;
     for (int64_t s = 0; s < S; ++s) {
         const int32_t *sd = seeds + 4 * s;
@@ -129,11 +135,12 @@ int oracle_grow_dir(const float *field, int64_t X, int64_t Y, int64_t Z, int64_t
         start = (uint32_t *)calloc(V + 1, sizeof(uint32_t));
         order = (uint32_t *)malloc(Q * sizeof(uint32_t));
         if (!bin || !start || !order) goto done;
-        for (uint64_t t = 0; t < (uint64_t)T; ++t)
+        for (uint64_t t = 0; t < (uint64_t)Tp; ++t)
             for (uint64_t i = 0; i < (uint64_t)P; ++i) {
                 uint64_t q = t * P + i;
                 int64_t s = voxel_of(xyz + 3 * q, X, Y, Z);
-                bin[q] = s < 0 ? NO_VOXEL : (uint32_t)(t * XYZ + (uint64_t)s);
+                uint64_t tf = t / (uint64_t)r; /* the field step holding time t / r */
+                bin[q] = s < 0 ? NO_VOXEL : (uint32_t)(tf * XYZ + (uint64_t)s);
             }
         /* Counting sort of particle-steps by voxel: start[v]..start[v+1]. */
         for (uint64_t q = 0; q < Q; ++q)
@@ -193,7 +200,7 @@ int oracle_grow_dir(const float *field, int64_t X, int64_t Y, int64_t Z, int64_t
                 if (!forward_only && t > 0 && in_band(attr[q - P], a_lo, a_hi) &&
                     test_and_set(visP, q - P))
                     if (fifo_push(&fifo, V + q - P)) goto done;
-                if (t + 1 < (uint64_t)T && in_band(attr[q + P], a_lo, a_hi) &&
+                if (t + 1 < (uint64_t)Tp && in_band(attr[q + P], a_lo, a_hi) &&
                     test_and_set(visP, q + P))
                     if (fifo_push(&fifo, V + q + P)) goto done;
             }
@@ -226,6 +233,17 @@ done:
     free(visF);
     free(visP);
     return rc;
+}
+
+/* Particles at the field's rate (Tp = T, r = 1). */
+int oracle_grow_dir(const float *field, int64_t X, int64_t Y, int64_t Z, int64_t T,
+                    const float *xyz, const float *attr, int64_t P,
+                    float f_lo, float f_hi, float a_lo, float a_hi,
+                    const int32_t *seeds, int64_t S, int forward_only,
+                    uint32_t *fmask, uint8_t *pmask, int64_t *stats)
+{
+    return oracle_grow_rate(field, X, Y, Z, T, xyz, attr, P, T, 1, f_lo, f_hi, a_lo, a_hi, seeds, S,
+                            forward_only, fmask, pmask, stats);
 }
 
 /* Both trajectory directions (undirected coupling). */

@@ -9,7 +9,9 @@ leaves open are marked R and listed in the design notes):
 
   samples   one field sample per voxel-step: position (x+0.5, y+0.5, z+0.5)
             (R: the voxel centre), time t, value f; one point sample per
-            particle-step: its position, time t, value a.  A sample with a
+            particle-step: its position, time tau / r in field steps (fp32;
+            r particle steps per field step, Section 3.4 on different
+            temporal resolutions; r = 1: time t), value a.  A sample with a
             non-finite position or value is not clustered (label -1) (R).
   seeding   k = (kx, ky, kz, kt) centres on a 4D rectilinear grid, interval
             C_d = E_d / k_d with E = (X, Y, Z, T) (Section 3.2.1), in fp32.
@@ -80,22 +82,23 @@ def to_double(s):
     return hi * 4294967296.0 + lo
 
 
-def samples(field, xyz, attr):
-    """Flatten both sample types: positions (fp32 [n][3]), times (int [n]),
-    values (fp32 [n]), type (0 field, 1 point), validity."""
+def samples(field, xyz, attr, rate=1):
+    """Flatten both sample types: positions (fp32 [n][3]), times (fp32 [n],
+    in field steps), values (fp32 [n]), type (0 field, 1 point), validity."""
     T, Z, Y, X = field.shape
     t, z, y, x = np.meshgrid(np.arange(T), np.arange(Z), np.arange(Y), np.arange(X), indexing="ij")
     fpos = np.stack([x.ravel() + 0.5, y.ravel() + 0.5, z.ravel() + 0.5], 1).astype(F32)
-    ft = t.ravel().astype(np.int64)
+    ft = t.ravel().astype(F32)
     fv = field.ravel().astype(F32)
     P = attr.shape[1] if attr is not None else 0
     if P:
-        ppos = xyz.reshape(T * P, 3).astype(F32)
-        pt = np.repeat(np.arange(T), P).astype(np.int64)
-        pv = attr.reshape(T * P).astype(F32)
+        Tp = attr.shape[0]
+        ppos = xyz.reshape(Tp * P, 3).astype(F32)
+        pt = np.repeat((np.arange(Tp, dtype=F32) / F32(rate)).astype(F32), P)
+        pv = attr.reshape(Tp * P).astype(F32)
     else:
         ppos = np.zeros((0, 3), F32)
-        pt = np.zeros(0, np.int64)
+        pt = np.zeros(0, F32)
         pv = np.zeros(0, F32)
     pos = np.concatenate([fpos, ppos])
     tt = np.concatenate([ft, pt])
@@ -139,7 +142,7 @@ def update_centres(pos, tt, val, typ, lab, prev, K):
     m = lab >= 0
     ids = lab[m]
     qx, qy, qz = quantise(pos[m, 0]), quantise(pos[m, 1]), quantise(pos[m, 2])
-    qt = tt[m].astype(np.int64) << Q_BITS
+    qt = quantise(tt[m])
     qv = quantise(val[m])
     isf = typ[m] == 0
 
@@ -218,16 +221,17 @@ def converged(new, old, eps):
     return bool(np.all(np.abs(new - old) <= eps * np.abs(old)))
 
 
-def slic(field, xyz, attr, k, w, cf, eps, max_iter):
-    """The whole clustering.  field fp32 [T][Z][Y][X]; xyz fp32 [T][P][3] and
-    attr fp32 [T][P] (or None); k = (kx, ky, kz, kt); w = (w_d, w_f, w_p).
-    Returns (field labels int64 [T][Z][Y][X], point labels int64 [T][P],
-    centres fp64 [K][6] as (x, y, z, t, p, f), counts [K][2], iterations)."""
+def slic(field, xyz, attr, k, w, cf, eps, max_iter, rate=1):
+    """The whole clustering.  field fp32 [T][Z][Y][X]; xyz fp32 [Tp][P][3] and
+    attr fp32 [Tp][P] (or None), rate particle steps per field step; k = (kx,
+    ky, kz, kt); w = (w_d, w_f, w_p).  Returns (field labels int64
+    [T][Z][Y][X], point labels int64 [Tp][P], centres fp64 [K][6] as (x, y,
+    z, t, p, f), counts [K][2], iterations)."""
     T, Z, Y, X = field.shape
     k = tuple(int(v) for v in k)
     K = k[0] * k[1] * k[2] * k[3]
     C = grid_interval((X, Y, Z, T), k)
-    pos, tt, val, typ, valid = samples(field, xyz, attr)
+    pos, tt, val, typ, valid = samples(field, xyz, attr, rate)
     lab = initial_labels(pos, tt, valid, C, k)
     prev = seed_centres(C, k)
     it = 0
@@ -241,7 +245,7 @@ def slic(field, xyz, attr, k, w, cf, eps, max_iter):
     V = X * Y * Z * T
     fl = lab[:V].reshape(T, Z, Y, X)
     P = attr.shape[1] if attr is not None else 0
-    pl = lab[V:].reshape(T, P)
+    pl = lab[V:].reshape(attr.shape[0] if attr is not None else T, P)
     return fl, pl, cen, counts, it
 
 
@@ -294,12 +298,12 @@ def merge_centres(cen, counts, eps_m):
     return np.where(has, low[comp], -1).astype(np.int64)
 
 
-def feature_stats(field, xyz, attr, fl, pl, feat):
+def feature_stats(field, xyz, attr, fl, pl, feat, rate=1):
     """Per feature id (indexed by its lowest centre id, [K] rows; rows of
     non-features are zero): n_f, n_p, mean f, mean p, std f, std p, then
     x min, x max, y min, y max, z min, z max, t min, t max.  fp64 [K][14]."""
     K = len(feat)
-    pos, tt, val, typ, valid = samples(field, xyz, attr)
+    pos, tt, val, typ, valid = samples(field, xyz, attr, rate)
     lab = np.concatenate([fl.ravel(), pl.ravel()]) if pl is not None else fl.ravel()
     m = lab >= 0
     F = feat[lab[m]]

@@ -13,7 +13,8 @@ D + 1 where D is the largest breadth-first level.
 
 With forward_only (causal coupling) a particle-step is a neighbour of the
 same particle's previous step only: N(X) gains (i, t+1) from (i, t) in X, not
-(i, t-1).
+(i, t-1).  With rate r the particles hold their own steps, r per field step;
+particle step tau couples with a voxel of field step tau // r.
 """
 from __future__ import annotations
 
@@ -38,8 +39,8 @@ def particle_voxels(xyz: np.ndarray, dims):
 
 
 def sweep_grow(field, xyz, attr, crit, seeds, max_sweeps: int | None = None,
-               forward_only: bool = False):
-    """Returns (Mf bool [T][Z][Y][X], Mp bool [T][P], sweeps, dropped)."""
+               forward_only: bool = False, rate: int = 1):
+    """Returns (Mf bool [T][Z][Y][X], Mp bool [Tp][P], sweeps, dropped)."""
     field = np.asarray(field, np.float32)
     T, Z, Y, X = field.shape
     f_lo, f_hi, a_lo, a_hi = (np.float32(v) for v in crit)
@@ -52,8 +53,9 @@ def sweep_grow(field, xyz, attr, crit, seeds, max_sweeps: int | None = None,
         ok, cx, cy, cz = particle_voxels(np.asarray(xyz, np.float32), (X, Y, Z))
         tt, pp = np.nonzero(ok)
         bx, by, bz = cx[tt, pp], cy[tt, pp], cz[tt, pp]
+        tf = tt // rate  # field step of each particle step
     else:
-        Ap = np.zeros((T, 0), bool)
+        Ap = np.zeros((T if xyz is None else xyz.shape[0], 0), bool)
     Mf = np.zeros_like(Af)
     Mp = np.zeros_like(Ap)
     dropped = 0
@@ -82,8 +84,8 @@ def sweep_grow(field, xyz, attr, crit, seeds, max_sweeps: int | None = None,
             if not forward_only:
                 Np[:-1] |= Mp[1:]
             from_p = Mp[tt, pp]
-            Nf[tt[from_p], bz[from_p], by[from_p], bx[from_p]] = True
-            Np[tt, pp] |= Mf[tt, bz, by, bx]
+            Nf[tf[from_p], bz[from_p], by[from_p], bx[from_p]] = True
+            Np[tt, pp] |= Mf[tf, bz, by, bx]
         nMf = Af & Nf
         nMp = Ap & Np
         if np.array_equal(nMf, Mf) and np.array_equal(nMp, Mp):

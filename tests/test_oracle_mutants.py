@@ -41,8 +41,8 @@ MUTANTS = {
                              "if (0 &&"),
     "forward_only_ignored": ("if (!forward_only && t > 0 && in_band(attr[q - P], a_lo, a_hi) &&",
                              "if (t > 0 && in_band(attr[q - P], a_lo, a_hi) &&"),
-    "forward_only_reversed": ("if (t + 1 < (uint64_t)T && in_band(attr[q + P], a_lo, a_hi) &&",
-                              "if (!forward_only && t + 1 < (uint64_t)T && in_band(attr[q + P], a_lo, a_hi) &&"),
+    "forward_only_reversed": ("if (t + 1 < (uint64_t)Tp && in_band(attr[q + P], a_lo, a_hi) &&",
+                              "if (!forward_only && t + 1 < (uint64_t)Tp && in_band(attr[q + P], a_lo, a_hi) &&"),
     "seed_unchecked": ("if (!in_band(field[v], f_lo, f_hi)) { dropped++; continue; }", ""),
     "upper_bin_inclusive": ("if (!(cx >= 0.0f && cx < (float)X)) return -1;",
                             "if (!(cx >= 0.0f && cx <= (float)X)) return -1;"),
