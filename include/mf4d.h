@@ -151,6 +151,21 @@ int mf4d_load_field(mf4d_ctx *ctx, const float *field, int X, int Y, int Z, int 
 int mf4d_load_particles(mf4d_ctx *ctx, const float *xyz, const float *attr, int64_t P, int T,
                         int where);
 
+/* Load point samples stored at their own temporal rate (Section 3.4: point
+ * and field data need not share a temporal resolution; particles are often
+ * saved more frequently than the field): positions xyz fp32 [Tp][P][3] and
+ * values attr fp32 [Tp][P], with r = steps_per_field_step particle steps per
+ * field step (1 <= r <= 1024, 1 <= Tp <= r * T).  Particle step tau lies at
+ * time tau / r in field steps: it couples with the voxel covering its
+ * position at field step floor(tau / r), the step whose interval [t, t + 1)
+ * holds that time, and the clustering gives its point sample the time tau / r
+ * (fp32).  Trajectory edges join consecutive particle steps.  Every particle
+ * output (masks, segments, ids, point labels, batched planes) is then
+ * [Tp][P].  r = 1 with Tp = T is mf4d_load_particles.
+ * Errors: as mf4d_load_particles; MF4D_ERR_ARG (r or Tp out of range). */
+int mf4d_load_particles_rate(mf4d_ctx *ctx, const float *xyz, const float *attr, int64_t P, int Tp,
+                             int steps_per_field_step, int where);
+
 /* Membership criteria: inclusive fp32 bands for field and particle values.
  * Errors: MF4D_ERR_ARG (a NaN bound). */
 int mf4d_set_criteria(mf4d_ctx *ctx, float f_lo, float f_hi, float a_lo, float a_hi);

@@ -71,6 +71,7 @@ SIGNATURES = {
     "mf4d_set_phase_timing": (c_int, [c_void_p, c_int]),
     "mf4d_load_field": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_int]),
     "mf4d_load_particles": (c_int, [c_void_p, c_void_p, c_void_p, c_int64, c_int, c_int]),
+    "mf4d_load_particles_rate": (c_int, [c_void_p, c_void_p, c_void_p, c_int64, c_int, c_int, c_int]),
     "mf4d_set_criteria": (c_int, [c_void_p, c_float, c_float, c_float, c_float]),
     "mf4d_set_seeds": (c_int, [c_void_p, c_void_p, c_int64, c_int]),
     "mf4d_set_schedule": (c_int, [c_void_p, c_int]),

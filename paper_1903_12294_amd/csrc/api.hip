@@ -579,13 +579,26 @@ int mf4d_load_particles(mf4d_ctx* c, const float* xyz, const float* attr, int64_
                         int where) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
     if (!c->has_field) return fail(MF4D_ERR_STATE, "load the field before the particles");
+    if (P > 0 && T != c->g.T) return fail(MF4D_ERR_ARG, "particle T %d differs from field T %d", T, c->g.T);
+    return mf4d_load_particles_rate(c, xyz, attr, P, c->g.T, 1, where);
+}
+
+int mf4d_load_particles_rate(mf4d_ctx* c, const float* xyz, const float* attr, int64_t P, int Tp,
+                             int steps_per_field_step, int where) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    if (!c->has_field) return fail(MF4D_ERR_STATE, "load the field before the particles");
     if (P < 0) return fail(MF4D_ERR_ARG, "P < 0");
     if (where != MF4D_HOST && where != MF4D_DEVICE) return fail(MF4D_ERR_ARG, "bad where");
     if (P > 0 && (!xyz || !attr)) return fail(MF4D_ERR_ARG, "xyz or attr is NULL");
-    if (P > 0 && T != c->g.T) return fail(MF4D_ERR_ARG, "particle T %d differs from field T %d", T, c->g.T);
+    const int r = steps_per_field_step;
+    if (r < 1 || r > 1024) return fail(MF4D_ERR_ARG, "steps per field step %d not in 1..1024", r);
+    if (P > 0 && (Tp < 1 || (int64_t)Tp > (int64_t)r * c->g.T))
+        return fail(MF4D_ERR_ARG, "%d particle steps at %d per field step do not fit %d field steps", Tp, r,
+                    c->g.T);
     PGeom pg{};
     pg.P = P;
-    pg.T = c->g.T;
+    pg.T = Tp;
+    pg.tr = r;
     if (pg.T <= 64) {
         int tp = 1;
         while (tp < pg.T) tp <<= 1;
@@ -936,7 +949,7 @@ int mf4d_grow_seed_ids(mf4d_ctx* c, int32_t* field_ids, size_t nf, int32_t* part
     const Geom& g = c->g;
     const size_t V = (size_t)g.X * g.Y * g.Z * g.T;
     const int64_t P = c->has_particles ? c->pg.P : 0;
-    const size_t Qp = (size_t)P * g.T;
+    const size_t Qp = P > 0 ? (size_t)P * c->pg.T : 0;
     if (!field_ids || nf < V) return fail(MF4D_ERR_ARG, "field ids need %zu elements", V);
     const bool want_p = P > 0 && particle_ids;
     if (want_p && np < Qp) return fail(MF4D_ERR_ARG, "particle ids need %zu elements", Qp);
@@ -961,7 +974,7 @@ int mf4d_grow_seed_ids(mf4d_ctx* c, int32_t* field_ids, size_t nf, int32_t* part
         unsigned long long* seen_p = nullptr;
         ~Scratch() { dev_free(words); dev_free(seen_f); dev_free(seen_p); }
     } sc;
-    const size_t nw = (V + 31) / 32, pw = (size_t)(g.T + 63) / 64;
+    const size_t nw = (V + 31) / 32, pw = P > 0 ? (size_t)(c->pg.T + 63) / 64 : 0;
     int rc = dev_alloc(&sc.words, nw);
     if (!rc) rc = dev_alloc(&sc.seen_f, nw);
     if (!rc && po) rc = dev_alloc(&sc.seen_p, (size_t)P * pw);
@@ -1107,8 +1120,9 @@ int mf4d_grow_batched(mf4d_ctx* c, uint32_t* fplanes, size_t fwords, uint32_t* p
     const uint64_t V = (uint64_t)g.X * g.Y * g.Z * g.T;
     const uint64_t P = c->has_particles ? (uint64_t)c->pg.P : 0;
     if (!fplanes || fwords < 8 * V) return fail(MF4D_ERR_ARG, "field planes need %llu words", (unsigned long long)(8 * V));
-    if (P > 0 && (!pplanes || pwords < 8 * P * g.T))
-        return fail(MF4D_ERR_ARG, "particle planes need %llu words", (unsigned long long)(8 * P * g.T));
+    const uint64_t Tp = P > 0 ? (uint64_t)c->pg.T : 0;
+    if (P > 0 && (!pplanes || pwords < 8 * P * Tp))
+        return fail(MF4D_ERR_ARG, "particle planes need %llu words", (unsigned long long)(8 * P * Tp));
     if ((reinterpret_cast<uintptr_t>(fplanes) & 15) || (reinterpret_cast<uintptr_t>(pplanes) & 15))
         return fail(MF4D_ERR_ARG, "plane buffers must be 16-byte aligned");
     HIP_TRY(hipSetDevice(c->device));
@@ -1137,7 +1151,7 @@ int mf4d_grow_batched(mf4d_ctx* c, uint32_t* fplanes, size_t fwords, uint32_t* p
     uint32_t* po = pplanes;
     if (where == MF4D_HOST) {
         void* st = nullptr;
-        int rc = staging_for(c, (size_t)(8 * V + 8 * P * g.T) * sizeof(uint32_t), &st);
+        int rc = staging_for(c, (size_t)(8 * V + 8 * P * Tp) * sizeof(uint32_t), &st);
         if (rc) return rc;
         fo = (uint32_t*)st;
         po = fo + 8 * V;
@@ -1145,6 +1159,7 @@ int mf4d_grow_batched(mf4d_ctx* c, uint32_t* fplanes, size_t fwords, uint32_t* p
     DevB d{};
     d.g = g;
     d.X = g.X; d.Y = g.Y; d.Z = g.Z; d.T = g.T;
+    d.Tp = (int)Tp;
     d.NXb = c->NXb; d.NYb = c->NYb; d.NZb = c->NZb; d.NTb = c->NTb;
     d.lx = c->blog[0]; d.ly = c->blog[1]; d.lz = c->blog[2]; d.lt = c->blog[3];
     d.NTB = c->NTB;
@@ -1204,7 +1219,7 @@ int mf4d_grow_batched(mf4d_ctx* c, uint32_t* fplanes, size_t fwords, uint32_t* p
     if (where == MF4D_HOST) {
         HIP_TRY(hipMemcpyAsync(fplanes, fo, 8 * V * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         if (P > 0)
-            HIP_TRY(hipMemcpyAsync(pplanes, po, 8 * P * g.T * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(pplanes, po, 8 * P * Tp * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         rc = sync(c);
         if (rc) return rc;
     }
@@ -1332,7 +1347,7 @@ int mf4d_slic_run(mf4d_ctx* c, int* iterations) {
     if (g.X >= 2048 || g.Y >= 2048 || g.Z >= 2048 || g.T >= 2048)
         return fail(MF4D_ERR_UNSUPPORTED, "clustering needs every dimension below 2048");
     const int64_t P = c->has_particles ? c->pg.P : 0;
-    const size_t V = (size_t)g.X * g.Y * g.Z * g.T, Qp = (size_t)g.T * P;
+    const size_t V = (size_t)g.X * g.Y * g.Z * g.T, Qp = P > 0 ? (size_t)c->pg.T * P : 0;
     if (V + Qp >= (size_t)1 << 31) return fail(MF4D_ERR_UNSUPPORTED, "more than 2^31 samples");
     HIP_TRY(hipSetDevice(c->device));
     c->slic_done = false;
@@ -1352,8 +1367,8 @@ int mf4d_slic_run(mf4d_ctx* c, int* iterations) {
         if (!rc) rc = dev_alloc(&scratch, (size_t)g.NT + 1 + 1 + 1025);
         if (!rc) {
             const int e = launch_slic_order(c->bins, c->praw, c->praw + (size_t)3 * Qp, P, c->pg.Tpad, c->pg.T,
-                                            5 + 6 + g.logBT, g.NT, scratch, c->porder, c->spos, c->sattr,
-                                            c->stream);
+                                            c->pg.tr, 5 + 6 + g.logBT, g.NT, scratch, c->porder, c->spos,
+                                            c->sattr, c->stream);
             if (e != hipSuccess) rc = fail(MF4D_ERR_HIP, "clustering order: %s", hipGetErrorString((hipError_t)e));
         }
         if (!rc) rc = sync(c);
@@ -1368,6 +1383,7 @@ int mf4d_slic_run(mf4d_ctx* c, int* iterations) {
     DevS s{};
     s.X = g.X; s.Y = g.Y; s.Z = g.Z; s.T = g.T;
     s.P = P;
+    s.Tp = P > 0 ? c->pg.T : 0;
     for (int i = 0; i < 4; ++i) s.k[i] = c->sk[i];
     s.K = c->sK;
     const float E[4] = {(float)g.X, (float)g.Y, (float)g.Z, (float)g.T};
@@ -1465,6 +1481,7 @@ static DevS slic_state(mf4d_ctx* c) {
     DevS s{};
     s.X = g.X; s.Y = g.Y; s.Z = g.Z; s.T = g.T;
     s.P = c->has_particles ? c->pg.P : 0;
+    s.Tp = s.P > 0 ? c->pg.T : 0;
     for (int i = 0; i < 4; ++i) s.k[i] = c->sk[i];
     s.K = c->sK;
     s.field = c->field;
@@ -1560,7 +1577,7 @@ int mf4d_slic_read_segments(mf4d_ctx* c, int32_t* dst, size_t n, int where) {
         out = (int32_t*)st;
     }
     launch_slic_unsort(c->slabels + V, c->porder, Qp, out, c->stream);
-    launch_slic_segments(out, c->m.feat, g.T, (int64_t)(Qp / g.T), c->stream);
+    launch_slic_segments(out, c->m.feat, c->pg.T, (int64_t)(Qp / c->pg.T), c->stream);
     if (where == MF4D_HOST)
         HIP_TRY(hipMemcpyAsync(dst, out, Qp * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     if (where == MF4D_DEVICE) return MF4D_OK;  // stream-ordered

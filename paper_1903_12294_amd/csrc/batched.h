@@ -22,6 +22,7 @@ constexpr int kTabWords = 1024 + 4 * 257 * 8;
 struct DevB {
     Geom g;  // tile geometry of the single-query binning (decodes particle bins)
     int X, Y, Z, T;
+    int Tp;                  // particle steps (r per field step)
     int NXb, NYb, NZb, NTb;  // tiles of (1 << lx) x (1 << ly) x (1 << lz) x (1 << lt) voxel-steps
     int lx, ly, lz, lt;      // log2 of the tile extents, lx + ly + lz + lt = 9 (512 per tile)
     uint32_t NTB;

@@ -205,7 +205,7 @@ __global__ __launch_bounds__(256) void kb_admit_particles(DevB d) {
     const BandTables tb = particle_tables(d);
     const uint64_t n = (uint64_t)d.P * d.Tpad;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t np = (uint64_t)d.T * d.P * 2;  // uint4 per particle-step: 2
+    const uint64_t np = (uint64_t)d.Tp * d.P * 2;  // uint4 per particle-step: 2
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < np; i += stride)
         reinterpret_cast<uint4*>(d.pplanes)[i] = make_uint4(0, 0, 0, 0);
     for (uint64_t b0 = blockIdx.x * (uint64_t)blockDim.x; b0 < n; b0 += stride) {
@@ -444,8 +444,8 @@ __device__ void bclose_particle(const DevB& d, uint32_t p, int par) {
     const int ndir = d.forward_only ? 1 : 2;
     for (int dir = 0; dir < ndir; ++dir) {
         uint32_t carry[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (int i = 0; i < d.T; ++i) {
-            const int t = dir == 0 ? i : d.T - 1 - i;
+        for (int i = 0; i < d.Tp; ++i) {
+            const int t = dir == 0 ? i : d.Tp - 1 - i;
             uint32_t* lp = d.pplanes + ((uint64_t)t * d.P + p) * 8;
             const Mask8 am = band_mask(tp, d.Q, d.attr_t[(uint64_t)p * d.Tpad + t]);
             uint32_t nw[8];
@@ -503,7 +503,7 @@ __global__ void kb_reset(DevB d) {
 
 __global__ void kb_count(DevB d) {
     const uint64_t nf = (uint64_t)d.X * d.Y * d.Z * d.T * 8;
-    const uint64_t np = (uint64_t)d.T * d.P * 8;
+    const uint64_t np = (uint64_t)d.Tp * d.P * 8;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     unsigned long long cf = 0, cp = 0;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nf; i += stride)

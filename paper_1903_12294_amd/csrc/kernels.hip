@@ -847,8 +847,9 @@ __global__ void k_reset(Dev d) {
     for (uint64_t i = tid; i < 2ull * kWorkSubs; i += stride) d.wcnt[i * kWcntStride] = 0u;
 }
 
-// Load: bin every particle-step into the voxel covering it and transpose the
-// values to particle-major rows.  Block = 64 particles; LDS tile [64][65].
+// Load: bin every particle-step into the voxel covering it (at the field step
+// holding the step's time, t / tr) and transpose the values to particle-major
+// rows.  Block = 64 particles; LDS tile [64][65].
 __global__ __launch_bounds__(256) void k_bin_particles(Geom g, PGeom pg,
                                                        const float* __restrict__ xyz,
                                                        const float* __restrict__ attr,
@@ -870,7 +871,7 @@ __global__ __launch_bounds__(256) void k_bin_particles(Geom g, PGeom pg,
                 const float cx = floorf(q[0]), cy = floorf(q[1]), cz = floorf(q[2]);
                 if (cx >= 0.0f && cx < (float)g.X && cy >= 0.0f && cy < (float)g.Y &&
                     cz >= 0.0f && cz < (float)g.Z)
-                    b = bit_index(g, (int)cx, (int)cy, (int)cz, t);
+                    b = bit_index(g, (int)cx, (int)cy, (int)cz, t / pg.tr);
                 a = attr[(int64_t)t * pg.P + p];
             }
             sb[pl][tl] = b;

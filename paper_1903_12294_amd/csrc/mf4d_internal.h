@@ -54,6 +54,7 @@ struct PGeom {
     int Tpad;
     int W;
     int logTpad;  // log2(Tpad) when Tpad is a power of two, else -1
+    int tr;       // particle steps per field step: step t lies in field step t / tr
 };
 
 // Counters kept in one small device array.

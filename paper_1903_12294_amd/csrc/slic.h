@@ -20,15 +20,16 @@ enum SlicCounter : int {
 struct DevS {
     int X, Y, Z, T;
     int64_t P;
+    int Tp;              // particle steps (point sample tau at time tau / r)
     int k[4];            // centres per axis (x, y, z, t)
     int K;               // k[0] * k[1] * k[2] * k[3]
     float C[4];          // grid intervals E_d / k_d (fp32)
     float wd, wf, wp, cf;
     double eps;
     const float* field;  // [T][Z][Y][X]
-    const float4* spos;  // [T * P]: point samples in visiting order, (x, y, z, t)
-    const float* sattr;  // [T * P]: their values, same order
-    int32_t* labels;     // [V + T * P]: field samples [T][Z][Y][X], then point samples in
+    const float4* spos;  // [Tp * P]: point samples in visiting order, (x, y, z, t)
+    const float* sattr;  // [Tp * P]: their values, same order
+    int32_t* labels;     // [V + Tp * P]: field samples [T][Z][Y][X], then point samples in
                          // visiting order
     unsigned long long* acc;  // [K][kSlicAcc]
     double* cen;         // [K][6]: x, y, z, t, p, f
@@ -71,13 +72,14 @@ int launch_slic_merge(const DevS& s, const DevM& m, hipStream_t st);
 
 // Visiting order of the point samples: particle-steps sorted by the tile
 // holding them (tile = voxel bit >> shift), steps in no voxel last; order[j]
-// = t * P + p of the j-th.  Their positions and times (spos) and values
-// (sattr) are copied in that order from xyz [T][P][3] and attr [T][P].  bins:
+// = t * P + p of the j-th.  Their positions and times (spos; time t / r in
+// field steps, r particle steps per field step) and values (sattr) are copied
+// in that order from xyz [T][P][3] and attr [T][P] (T particle steps).  bins:
 // [P][Tpad] voxel bits (~0u: none); scratch: nb + 1 + 1025 words, nb = number
 // of tiles + 1.  Errors as a HIP result.
 int launch_slic_order(const uint32_t* bins, const float* xyz, const float* attr, int64_t P, int Tpad,
-                      int T, int shift, uint32_t ntiles, uint32_t* scratch, uint32_t* order, float4* spos,
-                      float* sattr, hipStream_t st);
+                      int T, int r, int shift, uint32_t ntiles, uint32_t* scratch, uint32_t* order,
+                      float4* spos, float* sattr, hipStream_t st);
 // Point labels from visiting order back to [T][P]: out[order[j]] = in[j].
 void launch_slic_unsort(const int32_t* in, const uint32_t* order, uint64_t Q, int32_t* out, hipStream_t st);
 // Trajectory segments (Section 3.4), in place on point labels [T][P]: the

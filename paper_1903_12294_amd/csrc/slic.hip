@@ -276,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_slic_points(DevS s, int assign) {
     __shared__ Table tb;
     table_init(tb);
     const uint64_t V = (uint64_t)s.X * s.Y * s.Z * s.T;
-    const uint64_t Q = (uint64_t)s.T * s.P;
+    const uint64_t Q = (uint64_t)s.Tp * s.P;
     const uint64_t base = (uint64_t)blockIdx.x * (kBlock * kPer) + (uint64_t)threadIdx.x * kPer;
     Run run;
     run.id = -1;
@@ -293,7 +293,6 @@ __global__ __launch_bounds__(kBlock) void k_slic_points(DevS s, int assign) {
         }
         if (!(fabsf(v) < kMaxAbs && fabsf(px) < kMaxAbs && fabsf(py) < kMaxAbs && fabsf(pz) < kMaxAbs))
             s.counters[SC_RANGE] = 1u;
-        const int t = (int)pt;
         int id;
         if (assign) {
             id = assign_one(s, px, py, pz, pt, v, false, *lab);
@@ -303,7 +302,7 @@ __global__ __launch_bounds__(kBlock) void k_slic_points(DevS s, int assign) {
             id = ((ct * s.k[2] + cz) * s.k[1] + cy) * s.k[0] + cx;
         }
         *lab = id;
-        const long long q[5] = {quantise(px), quantise(py), quantise(pz), (long long)t << 20, quantise(v)};
+        const long long q[5] = {quantise(px), quantise(py), quantise(pz), quantise(pt), quantise(v)};
         run_sample(s, tb, run, id, q, false);
     }
     add_run(s, tb, run, false);
@@ -574,7 +573,7 @@ __global__ __launch_bounds__(kBlock) void k_feature_pass(DevS s, DevM m, int ty)
     __shared__ StatTable tb;
     stat_init(tb);
     const uint64_t V = (uint64_t)s.X * s.Y * s.Z * s.T;
-    const uint64_t N = ty == 0 ? V : (uint64_t)s.T * s.P;
+    const uint64_t N = ty == 0 ? V : (uint64_t)s.Tp * s.P;
     const uint64_t base = (uint64_t)blockIdx.x * (kBlock * kPer) + (uint64_t)threadIdx.x * kPer;
     StatRun run;
     run.id = -1;
@@ -749,7 +748,7 @@ __global__ __launch_bounds__(256) void k_order_offsets(uint32_t* __restrict__ cn
 }
 
 __global__ __launch_bounds__(256) void k_order_scatter(const uint32_t* __restrict__ bins, uint64_t Qpad,
-                                                       int Tpad, int T, int shift, uint32_t none, int64_t P,
+                                                       int Tpad, int T, int rate, int shift, uint32_t none, int64_t P,
                                                        uint32_t* __restrict__ cur, uint32_t* __restrict__ order,
                                                        const float* __restrict__ xyz,
                                                        const float* __restrict__ attr,
@@ -768,7 +767,7 @@ __global__ __launch_bounds__(256) void k_order_scatter(const uint32_t* __restric
             const uint64_t t = e - p * Tpad;
             const uint64_t i = t * (uint64_t)P + p;
             order[at] = (uint32_t)i;
-            spos[at] = make_float4(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], (float)t);
+            spos[at] = make_float4(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], __fdiv_rn((float)t, (float)rate));
             sattr[at] = attr[i];
         }
     }
@@ -819,7 +818,7 @@ void launch_slic_unsort(const int32_t* in, const uint32_t* order, uint64_t Q, in
 }
 
 int launch_slic_order(const uint32_t* bins, const float* xyz, const float* attr, int64_t P, int Tpad,
-                      int T, int shift, uint32_t ntiles, uint32_t* scratch, uint32_t* order, float4* spos,
+                      int T, int r, int shift, uint32_t ntiles, uint32_t* scratch, uint32_t* order, float4* spos,
                       float* sattr, hipStream_t st) {
     const uint64_t Qpad = (uint64_t)P * Tpad;
     const uint32_t nb = ntiles + 1;  // the last bucket: steps in no voxel
@@ -831,19 +830,19 @@ int launch_slic_order(const uint32_t* bins, const float* xyz, const float* attr,
     hipLaunchKernelGGL(k_order_sums, dim3(kScanBlocks), dim3(256), 0, st, cnt, nb, bsum);
     hipLaunchKernelGGL(k_order_top, dim3(1), dim3(kScanBlocks), 0, st, bsum);
     hipLaunchKernelGGL(k_order_offsets, dim3(kScanBlocks), dim3(256), 0, st, cnt, nb, bsum);
-    hipLaunchKernelGGL(k_order_scatter, dim3(g), dim3(256), 0, st, bins, Qpad, Tpad, T, shift, ntiles, P, cnt,
+    hipLaunchKernelGGL(k_order_scatter, dim3(g), dim3(256), 0, st, bins, Qpad, Tpad, T, r, shift, ntiles, P, cnt,
                        order, xyz, attr, spos, sattr);
     return (int)hipGetLastError();
 }
 
 void launch_slic_init(const DevS& s, hipStream_t st) {
-    const uint64_t V = (uint64_t)s.X * s.Y * s.Z * s.T, Q = (uint64_t)s.T * s.P;
+    const uint64_t V = (uint64_t)s.X * s.Y * s.Z * s.T, Q = (uint64_t)s.Tp * s.P;
     if (V) hipLaunchKernelGGL(k_slic_field, dim3(blocks_for(V, kBlock * kPer)), dim3(kBlock), 0, st, s, 0);
     if (Q) hipLaunchKernelGGL(k_slic_points, dim3(blocks_for(Q, kBlock * kPer)), dim3(kBlock), 0, st, s, 0);
 }
 
 void launch_slic_assign(const DevS& s, hipStream_t st) {
-    const uint64_t V = (uint64_t)s.X * s.Y * s.Z * s.T, Q = (uint64_t)s.T * s.P;
+    const uint64_t V = (uint64_t)s.X * s.Y * s.Z * s.T, Q = (uint64_t)s.Tp * s.P;
     if (V) hipLaunchKernelGGL(k_slic_field, dim3(blocks_for(V, kBlock * kPer)), dim3(kBlock), 0, st, s, 1);
     if (Q) hipLaunchKernelGGL(k_slic_points, dim3(blocks_for(Q, kBlock * kPer)), dim3(kBlock), 0, st, s, 1);
 }
@@ -860,7 +859,7 @@ void launch_slic_update(const DevS& s, int seed, hipStream_t st) {
 
 int launch_slic_merge(const DevS& s, const DevM& m, hipStream_t st) {
     const dim3 gk(blocks_for((uint64_t)m.K, 256)), b256(256);
-    const uint64_t V = (uint64_t)s.X * s.Y * s.Z * s.T, Q = (uint64_t)s.T * s.P;
+    const uint64_t V = (uint64_t)s.X * s.Y * s.Z * s.T, Q = (uint64_t)s.Tp * s.P;
     hipLaunchKernelGGL(k_merge_init, gk, b256, 0, st, s, m);
     hipLaunchKernelGGL(k_merge_pairs, gk, b256, 0, st, s, m);
     hipLaunchKernelGGL(k_merge_flatten, gk, b256, 0, st, s, m);

@@ -52,6 +52,7 @@ class Grower:
         self.device = device
         self.dims = None
         self.T = None
+        self.Tp = None  # particle steps (the field's T unless loaded at another rate)
         self.P = 0
         if tile_t is not None:
             self._check(self.lib.mf4d_set_tile(self.ctx, tile_t))
@@ -85,10 +86,13 @@ class Grower:
         T, Z, Y, X = field.shape
         p, where, keep = _arg(field, np.float32)
         self._check(self.lib.mf4d_load_field(self.ctx, p, X, Y, Z, T, where))
-        self.dims, self.T, self.P = (X, Y, Z), T, 0
+        self.dims, self.T, self.P, self.Tp = (X, Y, Z), T, 0, T
         del keep
 
-    def load_particles(self, xyz, attr):
+    def load_particles(self, xyz, attr, rate: int = 1):
+        """xyz [Tp][P][3], attr [Tp][P]; rate = particle steps per field step
+        (step tau couples with field step tau // rate; Tp == T when rate is
+        1)."""
         T, P = attr.shape[0], attr.shape[1]
         if tuple(xyz.shape) != (T, P, 3):
             raise ValueError("xyz must be [T][P][3] matching attr [T][P]")
@@ -96,8 +100,12 @@ class Grower:
         pa, wa, ka = _arg(attr, np.float32)
         if wx != wa:
             raise ValueError("xyz and attr must both live on the host or both on the device")
-        self._check(self.lib.mf4d_load_particles(self.ctx, px, pa, P, T, wx))
+        if rate == 1:
+            self._check(self.lib.mf4d_load_particles(self.ctx, px, pa, P, T, wx))
+        else:
+            self._check(self.lib.mf4d_load_particles_rate(self.ctx, px, pa, P, T, int(rate), wx))
         self.P = P
+        self.Tp = T if P else self.T
         del kx, ka
 
     def set_criteria(self, f_lo, f_hi=np.inf, a_lo=-np.inf, a_hi=np.inf):
@@ -173,9 +181,9 @@ class Grower:
 
     def read_particle_mask(self, out=None):
         """uint8 [T][P].  `out` may be a device tensor (uint8)."""
-        n = self.T * self.P
+        n = self.Tp * self.P
         if out is None:
-            out = np.zeros((self.T, self.P), np.uint8)
+            out = np.zeros((self.Tp, self.P), np.uint8)
         if _is_device_tensor(out):
             self._check(self.lib.mf4d_read_particle_mask(
                 self.ctx, ctypes.c_void_p(out.data_ptr()), out.numel(), MF4D_DEVICE))
@@ -188,9 +196,9 @@ class Grower:
         """Trajectory segments of the grown feature (Section 3.4): uint8
         [T][P], members with a member neighbour step.  `out` may be a device
         tensor (uint8)."""
-        n = self.T * self.P
+        n = self.Tp * self.P
         if out is None:
-            out = np.zeros((self.T, self.P), np.uint8)
+            out = np.zeros((self.Tp, self.P), np.uint8)
         if _is_device_tensor(out):
             self._check(self.lib.mf4d_read_particle_segments(
                 self.ctx, ctypes.c_void_p(out.data_ptr()), out.numel(), MF4D_DEVICE))
@@ -210,7 +218,7 @@ class Grower:
         if field_out is None:
             field_out = np.zeros((T, Z, Y, X), np.int32)
         if particle_out is None:
-            particle_out = np.zeros((T, P), np.int32)
+            particle_out = np.zeros((self.Tp, P), np.int32)
         dev = _is_device_tensor(field_out)
         if dev != _is_device_tensor(particle_out):
             raise ValueError("both outputs on the device or both on the host")
@@ -250,7 +258,7 @@ class Grower:
         if field_out is None:
             field_out = np.zeros((T, Z, Y, X), np.int32)
         if point_out is None:
-            point_out = np.zeros((T, P), np.int32)
+            point_out = np.zeros((self.Tp, P), np.int32)
         dev = _is_device_tensor(field_out)
         if dev != _is_device_tensor(point_out):
             raise ValueError("both outputs on the device or both on the host")
@@ -294,9 +302,9 @@ class Grower:
         """Trajectory segments of the merged features (Section 3.4): int32
         [T][P], the feature id where the particle keeps it at a neighbouring
         step, else -1.  `out` may be a device tensor (int32)."""
-        n = self.T * self.P
+        n = self.Tp * self.P
         if out is None:
-            out = np.zeros((self.T, self.P), np.int32)
+            out = np.zeros((self.Tp, self.P), np.int32)
         if _is_device_tensor(out):
             self._check(self.lib.mf4d_slic_read_segments(
                 self.ctx, ctypes.c_void_p(out.data_ptr()), out.numel(), MF4D_DEVICE))
@@ -327,7 +335,7 @@ class Grower:
         st = Stats()
         if fplanes is None:
             fplanes = np.zeros((V, 8), np.uint32)
-            pplanes = np.zeros((self.T, self.P, 8), np.uint32)
+            pplanes = np.zeros((self.Tp, self.P, 8), np.uint32)
             self._check(self.lib.mf4d_grow_batched(
                 self.ctx, fplanes.ctypes.data_as(ctypes.c_void_p), fplanes.size,
                 pplanes.ctypes.data_as(ctypes.c_void_p) if self.P else None, pplanes.size,

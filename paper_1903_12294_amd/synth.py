@@ -34,6 +34,12 @@ Attribute: trilinear sample of the fp32 field at timestep t at the stored
   position minus 0.5 (voxel centres), clamp-to-edge, float64, cast to fp32.
   Mode "noise": an independent U[0, 1) value instead (decouples the particle
   criterion from the field criterion).
+Particle rate r (the paper's particles are saved more often than the field):
+  r * T stored particle steps, one RK4 step of dt = 0.05 / r each (the same
+  motion per field step), the attribute of step tau sampled from field step
+  tau // r.  r = 1 is the recipe above, unchanged.
+Planar (2D + t) instances are Z = 1 grids: stored z lies in [0, 1), so every
+  particle moves in the one layer, and the blobs are evaluated at z = 0.5.
 """
 from __future__ import annotations
 
@@ -208,8 +214,9 @@ def _trilinear(ft: np.ndarray, q: np.ndarray) -> np.ndarray:
     return acc
 
 
-def sample_attribute(field: np.ndarray, xyz: np.ndarray) -> np.ndarray:
-    """fp32 [T][P]: the field at each stored particle position (trilinear)."""
+def sample_attribute(field: np.ndarray, xyz: np.ndarray, rate: int = 1) -> np.ndarray:
+    """fp32 [Tp][P]: the field at each stored particle position (trilinear),
+    step tau sampled from field step tau // rate."""
     T, P = xyz.shape[0], xyz.shape[1]
     out = np.empty((T, P), np.float32)
     if P == 0:
@@ -218,7 +225,7 @@ def sample_attribute(field: np.ndarray, xyz: np.ndarray) -> np.ndarray:
     def one(t):
         for a in range(0, P, 1 << 20):
             b = min(P, a + (1 << 20))
-            out[t, a:b] = _trilinear(field[t], xyz[t, a:b]).astype(np.float32)
+            out[t, a:b] = _trilinear(field[t // rate], xyz[t, a:b]).astype(np.float32)
 
     with ThreadPoolExecutor(_workers()) as ex:
         list(ex.map(one, range(T)))
@@ -247,19 +254,20 @@ def blob_seeds(rng: np.random.Generator, blobs: BlobSet, dims, T: int, S: int,
 def make_instance(X: int, Y: int, Z: int, T: int, P: int, *, n_blobs: int = 4,
                   seed: int = 0, n_seeds: int = 1, tau_f: float = 0.3,
                   tau_p: float = 0.3, attr_mode: str = "field",
-                  crossing: bool = False, first_seed_blob0_t0: bool = False) -> dict:
-    """A generic instance of the recipe above, for any grid shape."""
+                  crossing: bool = False, first_seed_blob0_t0: bool = False, rate: int = 1) -> dict:
+    """A generic instance of the recipe above, for any grid shape; rate =
+    particle steps per field step (the particles hold rate * T steps)."""
     ss = np.random.SeedSequence(seed)
     s_blob, s_noise, s_part, s_seed, s_attr = ss.spawn(5)
     dims = (X, Y, Z)
     blobs = make_blobs(np.random.Generator(np.random.PCG64(s_blob)), n_blobs, dims, T,
                        crossing=crossing)
     field = make_field(blobs, dims, T, s_noise)
-    xyz = make_particles(P, dims, T, s_part)
+    xyz = make_particles(P, dims, rate * T, s_part, dt=0.05 / rate)
     if attr_mode == "field":
-        attr = sample_attribute(field, xyz)
+        attr = sample_attribute(field, xyz, rate)
     elif attr_mode == "noise":
-        attr = np.random.Generator(np.random.PCG64(s_attr)).random((T, P)).astype(np.float32)
+        attr = np.random.Generator(np.random.PCG64(s_attr)).random((rate * T, P)).astype(np.float32)
     else:
         raise ValueError(attr_mode)
     rng = np.random.Generator(np.random.PCG64(s_seed))
@@ -271,7 +279,7 @@ def make_instance(X: int, Y: int, Z: int, T: int, P: int, *, n_blobs: int = 4,
         seeds = blob_seeds(rng, blobs, dims, T, n_seeds)
     crit = np.array([tau_f, np.inf, tau_p, np.inf], np.float32)
     return dict(dims=dims, T=T, P=P, field=field, xyz=xyz, attr=attr, seeds=seeds,
-                crit=crit, blobs=blobs, seed=seed)
+                crit=crit, blobs=blobs, seed=seed, rate=rate)
 
 
 # name -> (X, Y, Z, T, P, blobs, seeds, tau, crossing, data seed)
