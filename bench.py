@@ -10,6 +10,9 @@ schedule, admissibility mode) is the autotuner's pick, every candidate
 checked to give identical masks.
 
 Beside the headline the bench reports, on the same GPU:
+  city_2d  - a planar 2D + t city-like workload with particles at 4 steps
+             per field step: grow (masks compared with the oracle) and
+             clustering;
   forward_only - the same grow with causal trajectory coupling (t -> t+1
              only), its masks compared with the directed oracle;
   seed_ids - per-seed component ids of the same grow (lowest seed index
@@ -181,27 +184,31 @@ def time_call(fn, torch, reps: int = 5) -> float:
     return best
 
 
-def bench_slic(torch, log, inst, name):
-    """4D SLIC clustering (Section 3.2) of the same workload's 1.07e9 field and
-    2.7e8 point samples: time per iteration (runs of 1 and 1 + SLIC_ITERS
-    iterations with eps = 0, the difference), HBM bytes of an iteration
-    against peak, parity at full size on 20,000 sampled labels (the oracle
-    assigns them from the GPU's centres of the iteration before), and the
-    oracle's own speed on the 32^3 x 8 workload."""
+def bench_slic(torch, log, inst, name, k=SLIC_K, cpu_leg=True):
+    """4D SLIC clustering (Section 3.2) of a workload (the headline one: 1.07e9
+    field and 2.7e8 point samples): time per iteration (runs of 1 and 1 +
+    SLIC_ITERS iterations with eps = 0, the difference), HBM bytes of an
+    iteration against peak, parity at full size on 20,000 sampled labels (the
+    oracle assigns them from the GPU's centres of the iteration before), the
+    merge and the segment read-out, and (cpu_leg) the oracle's own speed on
+    the 32^3 x 8 workload.  Particles load at the instance's rate."""
     from oracle import segments as oseg
     from oracle import slic as oslic
     from paper_1903_12294_amd import Grower, synth
     dev = torch.device("cuda:0")
     X, Y, Z = inst["dims"]
     T, P = inst["T"], inst["P"]
-    V, Qs = X * Y * Z * T, T * P
+    rate = inst.get("rate", 1)
+    Tp = inst["xyz"].shape[0]
+    V, Qs = X * Y * Z * T, Tp * P
     g = Grower(device=0)
     try:
         g.load_field(torch.from_numpy(inst["field"]).to(dev))
-        g.load_particles(torch.from_numpy(inst["xyz"]).to(dev), torch.from_numpy(inst["attr"]).to(dev))
+        g.load_particles(torch.from_numpy(inst["xyz"]).to(dev), torch.from_numpy(inst["attr"]).to(dev),
+                         rate=rate)
 
         def run(m):
-            g.slic_set_params(SLIC_K, *SLIC_W, SLIC_CF, 0.0, m)
+            g.slic_set_params(k, *SLIC_W, SLIC_CF, 0.0, m)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             it = g.slic_run()
@@ -221,14 +228,14 @@ def bench_slic(torch, log, inst, name):
         fi = np.sort(rng.integers(0, V, 10000))
         pi = np.sort(rng.integers(0, Qs, 10000))
         fl = torch.empty((T, Z, Y, X), dtype=torch.int32, device=dev)
-        pl = torch.empty((T, P), dtype=torch.int32, device=dev)
+        pl = torch.empty((Tp, P), dtype=torch.int32, device=dev)
         fi_d, pi_d = torch.from_numpy(fi).to(dev), torch.from_numpy(pi).to(dev)
-        g.slic_set_params(SLIC_K, *SLIC_W, SLIC_CF, 0.0, m - 1)
+        g.slic_set_params(k, *SLIC_W, SLIC_CF, 0.0, m - 1)
         g.slic_run()
         cen_prev, _ = g.slic_read_centres()
         g.slic_read_labels(fl, pl)
         prev = np.concatenate([fl.view(-1)[fi_d].cpu().numpy(), pl.view(-1)[pi_d].cpu().numpy()])
-        g.slic_set_params(SLIC_K, *SLIC_W, SLIC_CF, 0.0, m)
+        g.slic_set_params(k, *SLIC_W, SLIC_CF, 0.0, m)
         it_m = g.slic_run()
         g.slic_read_labels(fl, pl)
         got = np.concatenate([fl.view(-1)[fi_d].cpu().numpy(), pl.view(-1)[pi_d].cpu().numpy()])
@@ -239,11 +246,12 @@ def bench_slic(torch, log, inst, name):
         tp, pp = pi // P, pi % P
         pos = np.concatenate([np.stack([x + 0.5, y + 0.5, z + 0.5], 1).astype(np.float32),
                               inst["xyz"][tp, pp].astype(np.float32)])
-        tt = np.concatenate([tt_f, tp]).astype(np.int64)
+        # point times tau / rate in field steps (fp32), field times t
+        tt = np.concatenate([tt_f.astype(np.float32), (tp.astype(np.float32) / np.float32(rate)).astype(np.float32)])
         val = np.concatenate([inst["field"].reshape(-1)[fi], inst["attr"][tp, pp]]).astype(np.float32)
         typ = np.concatenate([np.zeros(len(fi), np.int64), np.ones(len(pi), np.int64)])
-        C = oslic.grid_interval((X, Y, Z, T), SLIC_K)
-        want = oslic.assign(pos, tt, val, typ, prev.astype(np.int64), cen_prev, C, SLIC_K, SLIC_W, SLIC_CF)
+        C = oslic.grid_interval((X, Y, Z, T), k)
+        want = oslic.assign(pos, tt, val, typ, prev.astype(np.int64), cen_prev, C, k, SLIC_W, SLIC_CF)
         parity = bool(it_m == m and np.array_equal(want, got))
         # merging into features (Section 3.3) at full size; the oracle merges
         # the same centres
@@ -258,7 +266,7 @@ def bench_slic(torch, log, inst, name):
         big = int(fst[:, 0:2].sum(1).max())
         # trajectory segments of the merged features (Section 3.4); the
         # oracle's rule applied to the same particles' labels and features
-        sseg = torch.empty((T, P), dtype=torch.int32, device=dev)
+        sseg = torch.empty((Tp, P), dtype=torch.int32, device=dev)
         ms_sseg = time_call(lambda: g.slic_read_segments(sseg), torch)
         sel = np.sort(np.random.default_rng(13).choice(P, min(P, 4096), replace=False))
         sel_d = torch.from_numpy(sel).to(dev)
@@ -269,13 +277,14 @@ def bench_slic(torch, log, inst, name):
         del sseg
     finally:
         g.close()
-    # the oracle on the small workload, for a CPU reference
-    small = synth.make_config(1)
-    sX, sY, sZ = small["dims"]
-    sN = sX * sY * sZ * small["T"] + small["T"] * small["P"]
-    t0 = time.perf_counter()
-    oslic.slic(small["field"], small["xyz"], small["attr"], (4, 4, 4, 2), SLIC_W, SLIC_CF, 0.0, 3)
-    tc = time.perf_counter() - t0
+    if cpu_leg:
+        # the oracle on the small workload, for a CPU reference
+        small = synth.make_config(1)
+        sX, sY, sZ = small["dims"]
+        sN = sX * sY * sZ * small["T"] + small["T"] * small["P"]
+        t0 = time.perf_counter()
+        oslic.slic(small["field"], small["xyz"], small["attr"], (4, 4, 4, 2), SLIC_W, SLIC_CF, 0.0, 3)
+        tc = time.perf_counter() - t0
     N = V + Qs
     # HBM bytes of an iteration: field value, label read and write (12 B); point
     # position and time (16 B), value, label read and write (28 B)
@@ -284,9 +293,9 @@ def bench_slic(torch, log, inst, name):
     log(f"[bench] slic {ms_iter:.2f} ms/iteration, {N / (ms_iter * 1e-3):.3e} samples/s, parity {parity}; "
         f"merge {ms_merge:.2f} ms, {n_feat} features, parity {merge_parity}; "
         f"segments {ms_sseg:.3f} ms, parity {seg_parity}")
-    return {"workload": f"{name}: {V} field + {Qs} point samples, k = {SLIC_K} "
-                        f"({SLIC_K[0] * SLIC_K[1] * SLIC_K[2] * SLIC_K[3]} centres), w_d/w_f/w_p = {SLIC_W}, "
-                        f"c_f = {SLIC_CF}",
+    out = {"workload": f"{name}: {V} field + {Qs} point samples, k = {k} "
+                       f"({k[0] * k[1] * k[2] * k[3]} centres), w_d/w_f/w_p = {SLIC_W}, "
+                       f"c_f = {SLIC_CF}",
             "ms_per_iteration": round(ms_iter, 3), "value": round(N / (ms_iter * 1e-3), 1),
             "unit": "samples/s per iteration",
             "roofline": {"bound": "alu (distance evaluation)", "hbm_bytes_per_iteration": b,
@@ -297,9 +306,12 @@ def bench_slic(torch, log, inst, name):
             "segments": {"ms": round(ms_sseg, 3), "kept_point_samples": seg_kept,
                          "hbm_bytes": 20 * Qs, "achieved_GBps": round(20 * Qs / (ms_sseg * 1e-3) / 1e9, 1),
                          "parity_sampled_particles": seg_parity, "particles_checked": int(len(sel))},
-            "cpu_oracle": {"value": round(sN * 4 / tc, 1), "unit": "samples/s per iteration", "cores": 1,
-                           "sample": f"the 32^3 x 8 workload ({sN} samples), initial pass and 3 iterations, "
-                                     f"numpy ({tc:.1f}s)"}}
+            }
+    if cpu_leg:
+        out["cpu_oracle"] = {"value": round(sN * 4 / tc, 1), "unit": "samples/s per iteration", "cores": 1,
+                             "sample": f"the 32^3 x 8 workload ({sN} samples), initial pass and 3 iterations, "
+                                       f"numpy ({tc:.1f}s)"}
+    return out
 
 
 def bench_batched(args, torch, log):
@@ -366,6 +378,59 @@ def bench_batched(args, torch, log):
             "value": round(256 * V / (ms_b * 1e-3), 1), "unit": "query-voxel-steps/s",
             "rounds": bst["rounds"], "sampled_planes_equal": ok,
             "autotune": tune["table"]}
+
+
+def bench_city(args, torch, log):
+    """The planar 2D + t city-like workload (1024 x 1024 x 1 cells x 48 field
+    steps, 28,672 particles at 4 steps per field step): the grow under both
+    round schedules, masks compared with the oracle at the same rate (unless
+    --no-cpu-baseline), and the clustering with 32 x 32 x 1 x 4 centres."""
+    from paper_1903_12294_amd import Grower, synth
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    inst = synth.make_city()
+    name = synth.CITY["name"]
+    log(f"[bench] generated {name} in {time.time() - t0:.1f}s")
+    X, Y, Z = inst["dims"]
+    T, P, r = inst["T"], inst["P"], inst["rate"]
+    Tp = inst["xyz"].shape[0]
+    V = X * Y * Z * T
+    fmask = torch.empty((V + 31) // 32, dtype=torch.int32, device=dev)
+    pmask = torch.empty((Tp, P), dtype=torch.uint8, device=dev)
+    res = {}
+    for sched in ("persistent", "launch"):
+        g = Grower(device=0, schedule=sched)
+        try:
+            g.load_field(torch.from_numpy(inst["field"]).to(dev))
+            g.load_particles(torch.from_numpy(inst["xyz"]).to(dev), torch.from_numpy(inst["attr"]).to(dev),
+                             rate=r)
+            g.set_criteria(*inst["crit"])
+            g.set_seeds(inst["seeds"])
+            rs = run_steps(g, fmask, pmask, args.steps, args.warmup, torch)
+            res[sched] = (rs, fmask.cpu().numpy().view(np.uint32).copy(), pmask.cpu().numpy().copy())
+        finally:
+            g.close()
+    best = min(res, key=lambda k: res[k][0]["ms"])
+    st = res[best][0]["stats"]
+    out = {"workload": f"{name}: field {X}x{Y}x{Z}x{T} fp32, {P} particles x {Tp} steps ({r} per field "
+                       f"step), {len(inst['seeds'])} seeds, thresholds {float(inst['crit'][0])}"
+                       f"/{float(inst['crit'][2])}",
+           "ms_per_step": {s: round(v[0]["ms"], 4) for s, v in res.items()}, "schedule": best,
+           "value": round(V / (res[best][0]["ms"] * 1e-3), 1), "unit": "voxel-steps/s",
+           "rounds": st["rounds"], "members_field": st["members_field"],
+           "members_particle": st["members_particle"]}
+    if not args.no_cpu_baseline:
+        from oracle import oracle_grow
+        t0 = time.perf_counter()
+        ofm, opm, _ = oracle_grow(inst["field"], inst["xyz"], inst["attr"], inst["crit"], inst["seeds"], rate=r)
+        out["oracle_s"] = round(time.perf_counter() - t0, 2)
+        out["parity_vs_oracle"] = bool(all(np.array_equal(f, ofm) and np.array_equal(p, opm)
+                                           for _, f, p in res.values()))
+    log(f"[bench] city {out['ms_per_step']} ms/step, parity {out.get('parity_vs_oracle')}")
+    del fmask, pmask
+    torch.cuda.empty_cache()
+    out["slic"] = bench_slic(torch, log, inst, name, k=(32, 32, 1, 4), cpu_leg=False)
+    return out
 
 
 def bench_adjacent(g, inst, fmask, pmask, args, torch, forms):
@@ -440,6 +505,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="the headline grow only (no other form)")
     ap.add_argument("--slic-only", action="store_true",
                     help="only the clustering form (for profiling its kernels); prints its JSON object")
+    ap.add_argument("--city-only", action="store_true",
+                    help="only the planar city-like form (for profiling); prints its JSON object")
     ap.add_argument("--batched-reps", type=int, default=3)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run three 1 GiB device copies (a plain copy kernel of known size, "
@@ -457,6 +524,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.city_only:
+        print(json.dumps(bench_city(args, torch, log)), flush=True)
+        return
     cfg = synth.CONFIGS[args.config]
     t0 = time.time()
     inst = synth.make_config(args.config)
@@ -575,6 +645,7 @@ def main():
     if not args.no_forms:
         forms["batched"] = bench_batched(args, torch, log)
         forms["slic"] = bench_slic(torch, log, inst, cfg["name"])
+        forms["city_2d"] = bench_city(args, torch, log)
         torch.cuda.empty_cache()
 
     cpu = None

@@ -464,19 +464,6 @@ __device__ void pull_entries(const Dev& d, uint32_t i0, uint32_t stride, uint32_
     }
 }
 
-__device__ __forceinline__ void push_steps(const Dev& d, uint32_t p, int w, unsigned long long nw,
-                                           int par) {
-    while (nw) {
-        const int t = __builtin_ctzll(nw);
-        nw &= nw - 1;
-        const uint32_t b = d.bins[(size_t)p * d.pg.Tpad + w * 64 + t];
-        if (b != kNoVoxel && admissible_bit(d, b)) {
-            const uint32_t bit = 1u << (b & 31);
-            if (!(atomicOr(&d.Lf[b >> 5], bit) & bit)) mark_voxel(d, b, par);
-        }
-    }
-}
-
 // Push up to 4 particle-steps per lane that joined (flat indices e = p * Tpad
 // + t; ~0u: none): each voxel joins when admissible, for round parity `par`.
 // Every step is issued for the 4 together (bins; activity, admissibility and
@@ -523,46 +510,15 @@ __device__ __forceinline__ void push_one(const Dev& d, uint32_t e, int par) {
     }
 }
 
-// Close one dirty particle: its member steps spread over each run of
-// admissible steps that holds them (its trajectory; forward in time only with
-// forward-only coupling).  With one label word (W = 1) the new steps are
-// returned for the caller to push; with more words they are pushed here and 0
-// is returned.
-__device__ unsigned long long close_one(const Dev& d, uint32_t p, int par) {
-    const int W = d.pg.W;
-    unsigned long long* lw = d.Lp + (size_t)p * W;
-    const unsigned long long* aw = d.Ap + (size_t)p * W;
-    if (W == 1) {
-        const unsigned long long a = aw[0], l0 = lw[0];
-        const unsigned long long nw = close_word(l0, a, d.forward_only) & ~l0;
-        if (nw) atomicOr(&lw[0], nw);
-        return nw;
-    }
-    // runs crossing word boundaries: carry upward, then downward
-    unsigned long long carry = 0;
-    for (int w = 0; w < W; ++w) {
-        const unsigned long long a = aw[w], l0 = lw[w];
-        unsigned long long l = close_word(l0 | (carry & a & 1ull), a, d.forward_only);
-        carry = l >> 63;
-        const unsigned long long nw = l & ~l0;
-        if (nw) {
-            atomicOr(&lw[w], nw);
-            push_steps(d, p, w, nw, par);
-        }
-    }
-    if (d.forward_only) return 0ull;
-    carry = 0;
-    for (int w = W - 1; w >= 0; --w) {
-        const unsigned long long a = aw[w], l0 = lw[w];
-        unsigned long long l = fill_runs64(l0 | ((carry << 63) & a), a);
-        carry = l & 1ull;
-        const unsigned long long nw = l & ~l0;
-        if (nw) {
-            atomicOr(&lw[w], nw);
-            push_steps(d, p, w, nw, par);
-        }
-    }
-    return 0ull;
+// Close one dirty particle with one label word (W = 1): its member steps
+// spread over each run of admissible steps that holds them (its trajectory;
+// forward in time only with forward-only coupling).  The new steps are
+// returned for the caller to push.
+__device__ unsigned long long close_one(const Dev& d, uint32_t p) {
+    const unsigned long long a = d.Ap[p], l0 = d.Lp[p];
+    const unsigned long long nw = close_word(l0, a, d.forward_only) & ~l0;
+    if (nw) atomicOr(&d.Lp[p], nw);
+    return nw;
 }
 
 // Lanes of one wave exchanging through LDS: order the LDS accesses around it.
@@ -585,11 +541,71 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t& total) 
     return x - v;
 }
 
+// Push the new steps of every lane of the wave (nw: new bits of label word w
+// of particle p; p * Tpad + w * 64 + t is a step's flat index), 256 at a time,
+// four per lane with their loads issued together.  s_list: 256 words.
+__device__ void push_wave_word(const Dev& d, uint32_t p, int w, unsigned long long nw, int par,
+                               uint32_t* s_list) {
+    const int lane = lane_id();
+    const uint32_t base = p * (uint32_t)d.pg.Tpad + (uint32_t)w * 64u;
+    while (__ballot(nw != 0)) {
+        uint32_t tot;
+        uint32_t k = wave_excl_scan(__popcll(nw), tot);
+        while (nw && k < 256) {
+            s_list[k++] = base + (uint32_t)__builtin_ctzll(nw);
+            nw &= nw - 1;
+        }
+        wave_sync();
+        const uint32_t m = tot < 256 ? tot : 256;
+        uint32_t e[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) e[i] = (uint32_t)lane + 64 * i < m ? s_list[lane + 64 * i] : 0xFFFFFFFFu;
+        wave_sync();
+        push_four(d, e, par);
+    }
+}
+
+// Close the dirty particles held by a wave's lanes (lane holds p when `has`)
+// whose trajectories span several label words (W > 1).  Runs cross word
+// boundaries, so every lane walks its words upward, carrying a run's
+// membership into the next word, then downward (not with forward-only
+// coupling), in step with the other lanes; after each word the wave pushes
+// the steps all its lanes added, instead of each lane pushing its own steps
+// one after another.
+__device__ void close_words_wave(const Dev& d, uint32_t p, bool has, int par, uint32_t* s_list) {
+    const int W = d.pg.W;
+    unsigned long long* lw = d.Lp + (size_t)p * W;
+    const unsigned long long* aw = d.Ap + (size_t)p * W;
+    const int ndir = d.forward_only ? 1 : 2;
+    for (int dir = 0; dir < ndir; ++dir) {
+        unsigned long long carry = 0;
+        for (int i = 0; i < W; ++i) {
+            const int w = dir == 0 ? i : W - 1 - i;
+            unsigned long long nw = 0;
+            if (has) {
+                const unsigned long long a = aw[w], l0 = lw[w];
+                unsigned long long l;
+                if (dir == 0) {
+                    l = close_word(l0 | (carry & a & 1ull), a, d.forward_only);
+                    carry = l >> 63;
+                } else {
+                    l = fill_runs64(l0 | ((carry << 63) & a), a);
+                    carry = l & 1ull;
+                }
+                nw = l & ~l0;
+                if (nw) atomicOr(&lw[w], nw);
+            }
+            push_wave_word(d, p, w, nw, par, s_list);
+        }
+    }
+}
+
 // Close phase, wave-level: the wave takes 64 pdirty words at a time (clearing
 // them), gathers their dirty particles into LDS 64 at a time so that each
-// lane closes one, then gathers the new steps of all its lanes 64 at a time so
-// that each lane pushes one.  No lane walks a long chain alone.  Returns the
-// number of particles this wave closed (the same in every lane).
+// lane closes one, then gathers the new steps of all its lanes so that each
+// lane pushes one (several label words: word by word, four per lane).  No lane
+// walks a long chain alone.  s_list: 256 words.  Returns the number of
+// particles this wave closed (the same in every lane).
 __device__ uint32_t close_phase(const Dev& d, int par, uint32_t wave_id, uint32_t nwaves,
                                 uint32_t* s_list) {
     const PGeom& pg = d.pg;
@@ -614,12 +630,14 @@ __device__ uint32_t close_phase(const Dev& d, int par, uint32_t wave_id, uint32_
             const uint32_t n = total < 64 ? total : 64;
             closed += n;
             uint32_t p = 0;
-            unsigned long long nw = 0;
-            if ((uint32_t)lane < n) {
-                p = s_list[lane];
-                nw = close_one(d, p, par);
-            }
+            const bool has = (uint32_t)lane < n;
+            if (has) p = s_list[lane];
             wave_sync();
+            if (pg.W > 1) {  // wave-uniform
+                close_words_wave(d, p, has, par, s_list);
+                continue;
+            }
+            unsigned long long nw = has ? close_one(d, p) : 0ull;
             while (__ballot(nw != 0)) {
                 uint32_t tot2;
                 uint32_t k2 = wave_excl_scan(__popcll(nw), tot2);
@@ -1442,7 +1460,7 @@ __global__ __launch_bounds__(256) void k_round_pull(Dev d, int par) {
 }
 
 __global__ __launch_bounds__(256) void k_round_close(Dev d, int par) {
-    __shared__ uint32_t s_list[4 * 64];
+    __shared__ uint32_t s_list[4 * 256];
     __shared__ uint32_t s_cnt;
     if (!d.counters[C_RACT]) return;
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1450,7 +1468,7 @@ __global__ __launch_bounds__(256) void k_round_close(Dev d, int par) {
     if (threadIdx.x == 0) s_cnt = 0;
     __syncthreads();
     const uint32_t closed =
-        close_phase(d, par ^ 1, tid >> 6, stride >> 6, s_list + 64 * (threadIdx.x >> 6));
+        close_phase(d, par ^ 1, tid >> 6, stride >> 6, s_list + 256 * (threadIdx.x >> 6));
     if (lane_id() == 0 && closed) atomicAdd(&s_cnt, closed);
     __syncthreads();
     if (threadIdx.x == 0) slot_add(d, SL_PART_VISITS, s_cnt);

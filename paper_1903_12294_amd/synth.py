@@ -58,6 +58,7 @@ __all__ = [
     "sample_attribute",
     "make_instance",
     "make_config",
+    "make_city",
     "blob_seeds",
     "make_queries",
 ]
@@ -291,6 +292,24 @@ CONFIGS = {
     3: dict(name="scale-256^3x64", X=256, Y=256, Z=256, T=64, P=4194304, n_blobs=64,
             n_seeds=32, tau=0.25, crossing=True, seed=3),
 }
+
+
+# A planar (2D + t) city-like workload in the shape of the paper's taxi case
+# (about a million grid locations per timestep, tens of thousands of
+# vehicles, positions saved more often than the traffic field): 1024 x 1024
+# x 1 cells, 48 field steps, 28,672 particles at 4 steps per field step; 1,024
+# crossing blobs stand in for congestion, threshold 0.2 (about 10% of the
+# cells), 32 seeds.
+CITY = dict(name="city-2d-1024^2x48-r4", X=1024, Y=1024, Z=1, T=48, rate=4, P=28672, n_blobs=1024,
+            n_seeds=32, tau=0.2, crossing=True, seed=4)
+
+
+def make_city(**kw) -> dict:
+    """The planar city-like workload above (keyword arguments override)."""
+    c = dict(CITY, **kw)
+    return make_instance(c["X"], c["Y"], c["Z"], c["T"], c["P"], n_blobs=c["n_blobs"], seed=c["seed"],
+                         n_seeds=c["n_seeds"], tau_f=c["tau"], tau_p=c["tau"], crossing=c["crossing"],
+                         rate=c["rate"])
 
 
 def make_config(k: int, *, attr_mode: str = "field", tau_p_offset: float = 0.0,
