@@ -600,21 +600,26 @@ __device__ void close_words_wave(const Dev& d, uint32_t p, bool has, int par, ui
     }
 }
 
-// Close phase, wave-level: the wave takes 64 pdirty words at a time (clearing
-// them), gathers their dirty particles into LDS 64 at a time so that each
-// lane closes one, then gathers the new steps of all its lanes so that each
-// lane pushes one (several label words: word by word, four per lane).  No lane
-// walks a long chain alone.  s_list: 256 words.  Returns the number of
-// particles this wave closed (the same in every lane).
+// Close phase, wave-level: the wave takes up to 64 pdirty words at a time
+// (clearing them; fewer when the grid has more waves than that needs), gathers
+// their dirty particles into LDS 64 at a time so that each lane closes one,
+// then gathers the new steps of all its lanes so that each lane pushes one
+// (several label words: word by word, four per lane).  No lane walks a long
+// chain alone.  s_list: 256 words.  Returns the number of particles this wave
+// closed (the same in every lane).
 __device__ uint32_t close_phase(const Dev& d, int par, uint32_t wave_id, uint32_t nwaves,
                                 uint32_t* s_list) {
     const PGeom& pg = d.pg;
     const uint32_t nw32 = (uint32_t)((pg.P + 31) / 32);
     const int lane = lane_id();
+    // pdirty words per wave visit: up to 64, fewer when there are few words
+    // per wave, so that every wave of the grid gets dirty particles
+    uint32_t per = (nw32 + nwaves - 1) / nwaves;
+    per = per < 1 ? 1 : (per > 64 ? 64 : per);
     uint32_t closed = 0;
-    for (uint32_t base = wave_id * 64; base < nw32; base += nwaves * 64) {
+    for (uint32_t base = wave_id * per; base < nw32; base += nwaves * per) {
         uint32_t wd = 0;
-        if (base + lane < nw32) {
+        if ((uint32_t)lane < per && base + lane < nw32) {
             wd = d.pdirty[base + lane];
             if (wd) d.pdirty[base + lane] = 0u;  // no setter runs during this phase
         }
@@ -1616,33 +1621,37 @@ __global__ __launch_bounds__(256) void k_read_field_bits(Dev d, uint32_t* __rest
     block_slot_sum(d, SL_MEMBERS_F, cnt);
 }
 
-// Particle labels -> uint8 [T][P].  Fast path (one label word per particle,
-// P a multiple of 16): a thread owns 16 consecutive particles and writes their
-// 16 bytes of each timestep as one 16-byte store.
+// Particle labels -> uint8 [T][P].  Fast path (P a multiple of 16): a thread
+// owns 16 consecutive particles and, label word by label word, writes their 16
+// bytes of each step as one 16-byte store.
 __global__ __launch_bounds__(256) void k_read_particles16(Dev d, uint8_t* __restrict__ out) {
     const PGeom& pg = d.pg;
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t p0 = q * 16;
     uint32_t cnt = 0;
     if (p0 < pg.P) {
-        unsigned long long lw[16];
         const uint4 fl = *reinterpret_cast<const uint4*>(d.pflag + p0);  // 16 candidate flags
         const uint32_t fw[4] = {fl.x, fl.y, fl.z, fl.w};
+        const int nw = (pg.T + 63) >> 6;  // words holding real steps
+        for (int w = 0; w < nw; ++w) {
+            unsigned long long lw[16];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            lw[k] = (fw[k >> 2] >> (8 * (k & 3))) & 0xFFu ? d.Lp[p0 + k] : 0ull;
-            cnt += __popcll(lw[k]);
-        }
-        for (int t = 0; t < pg.T; ++t) {
-            uint32_t v[4];
+            for (int k = 0; k < 16; ++k) {
+                lw[k] = (fw[k >> 2] >> (8 * (k & 3))) & 0xFFu ? d.Lp[(size_t)(p0 + k) * pg.W + w] : 0ull;
+                cnt += __popcll(lw[k]);
+            }
+            const int tend = min(64, pg.T - w * 64);
+            for (int t = 0; t < tend; ++t) {
+                uint32_t v[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                v[j] = (uint32_t)((lw[4 * j] >> t) & 1) | ((uint32_t)((lw[4 * j + 1] >> t) & 1) << 8) |
-                       ((uint32_t)((lw[4 * j + 2] >> t) & 1) << 16) |
-                       ((uint32_t)((lw[4 * j + 3] >> t) & 1) << 24);
-            typedef unsigned int v4u __attribute__((ext_vector_type(4)));
-            __builtin_nontemporal_store((v4u){v[0], v[1], v[2], v[3]},
-                                        reinterpret_cast<v4u*>(out + (int64_t)t * pg.P + p0));
+                for (int j = 0; j < 4; ++j)
+                    v[j] = (uint32_t)((lw[4 * j] >> t) & 1) | ((uint32_t)((lw[4 * j + 1] >> t) & 1) << 8) |
+                           ((uint32_t)((lw[4 * j + 2] >> t) & 1) << 16) |
+                           ((uint32_t)((lw[4 * j + 3] >> t) & 1) << 24);
+                typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+                __builtin_nontemporal_store((v4u){v[0], v[1], v[2], v[3]},
+                                            reinterpret_cast<v4u*>(out + (int64_t)(w * 64 + t) * pg.P + p0));
+            }
         }
     }
     block_slot_sum(d, SL_MEMBERS_P, cnt);
@@ -1934,7 +1943,7 @@ void launch_read_field(const Dev& d, uint32_t* out, hipStream_t s) {
 void launch_read_particles(const Dev& d, uint8_t* out, hipStream_t s) {
     const PGeom& pg = d.pg;
     if (pg.P == 0) return;
-    if (pg.W == 1 && (pg.P & 15) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
+    if ((pg.P & 15) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
         hipLaunchKernelGGL(k_read_particles16, dim3(grid_for(pg.P / 16, 256, 1u << 20)), dim3(256),
                            0, s, d, out);
         return;
