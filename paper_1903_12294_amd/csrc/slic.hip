@@ -422,19 +422,6 @@ __device__ bool unite(int* parent, int i, int j, int K) {
     return false;
 }
 
-__device__ __forceinline__ bool centres_match(const DevS& s, double eps, int i, int j) {
-    for (int ty = 0; ty < 2; ++ty) {  // 0: field (value column 5), 1: points (column 4)
-        const bool hi = s.cnt[2 * (size_t)i + ty] > 0, hj = s.cnt[2 * (size_t)j + ty] > 0;
-        if (hi != hj) return false;
-        if (hi) {
-            const int col = ty == 0 ? 5 : 4;
-            const double a = s.cen[6 * (size_t)i + col], b = s.cen[6 * (size_t)j + col];
-            if (!(fabs(__dsub_rn(a, b)) <= __dmul_rn(eps, fmax(fabs(a), fabs(b))))) return false;
-        }
-    }
-    return true;
-}
-
 __device__ __forceinline__ bool has_samples(const DevS& s, int i) {
     return s.cnt[2 * (size_t)i] + s.cnt[2 * (size_t)i + 1] > 0;
 }
@@ -454,12 +441,51 @@ __global__ __launch_bounds__(256) void k_merge_init(DevS s, DevM m) {
     }
 }
 
-// Thread i compares centre i with every later centre (K^2 / 2 tests).
-__global__ __launch_bounds__(256) void k_merge_pairs(DevS s, DevM m) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m.K || !has_samples(s, i)) return;
-    for (int j = i + 1; j < m.K; ++j)
-        if (has_samples(s, j) && centres_match(s, m.eps, i, j) && !unite(m.parent, i, j, m.K)) m.err[0] = 1u;
+// Pair tests in tiles of 256 x 256 centres, so that every block does the same
+// work (K^2 / 2 tests in all): block (bx, by >= bx) compares the centres of
+// tile bx, one per thread, with the later centres of tile by, held in LDS.  Two
+// centres match when they have the same sample types and, per type, means
+// within eps of the larger magnitude (Section 3.3).
+constexpr int kMergeTile = 256;
+__global__ __launch_bounds__(kMergeTile) void k_merge_pairs(DevS s, DevM m) {
+    if (blockIdx.y < blockIdx.x) return;  // block-uniform: lower triangle
+    __shared__ double sv[2][kMergeTile];  // field mean, point mean
+    __shared__ unsigned sh[kMergeTile];   // bit 0: has field samples, bit 1: has point samples
+    const int j0 = blockIdx.y * kMergeTile;
+    {
+        const int j = j0 + threadIdx.x;
+        unsigned h = 0;
+        double vf = 0.0, vp = 0.0;
+        if (j < m.K) {
+            h = (s.cnt[2 * (size_t)j] > 0 ? 1u : 0u) | (s.cnt[2 * (size_t)j + 1] > 0 ? 2u : 0u);
+            vf = s.cen[6 * (size_t)j + 5];
+            vp = s.cen[6 * (size_t)j + 4];
+        }
+        sh[threadIdx.x] = h;
+        sv[0][threadIdx.x] = vf;
+        sv[1][threadIdx.x] = vp;
+    }
+    __syncthreads();
+    const int i = blockIdx.x * kMergeTile + threadIdx.x;
+    if (i >= m.K) return;
+    const unsigned hi = (s.cnt[2 * (size_t)i] > 0 ? 1u : 0u) | (s.cnt[2 * (size_t)i + 1] > 0 ? 2u : 0u);
+    if (!hi) return;  // no samples: merges with nothing
+    const double af = s.cen[6 * (size_t)i + 5], ap = s.cen[6 * (size_t)i + 4];
+    const int jn = min(kMergeTile, m.K - j0);
+    for (int jj = 0; jj < jn; ++jj) {
+        const int j = j0 + jj;
+        if (j <= i || sh[jj] != hi) continue;  // a type only one has: different phenomena
+        bool ok = true;
+        if (hi & 1u) {
+            const double b = sv[0][jj];
+            ok = fabs(__dsub_rn(af, b)) <= __dmul_rn(m.eps, fmax(fabs(af), fabs(b)));
+        }
+        if (ok && (hi & 2u)) {
+            const double b = sv[1][jj];
+            ok = fabs(__dsub_rn(ap, b)) <= __dmul_rn(m.eps, fmax(fabs(ap), fabs(b)));
+        }
+        if (ok && !unite(m.parent, i, j, m.K)) m.err[0] = 1u;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_merge_flatten(DevS s, DevM m) {
@@ -861,7 +887,8 @@ int launch_slic_merge(const DevS& s, const DevM& m, hipStream_t st) {
     const dim3 gk(blocks_for((uint64_t)m.K, 256)), b256(256);
     const uint64_t V = (uint64_t)s.X * s.Y * s.Z * s.T, Q = (uint64_t)s.Tp * s.P;
     hipLaunchKernelGGL(k_merge_init, gk, b256, 0, st, s, m);
-    hipLaunchKernelGGL(k_merge_pairs, gk, b256, 0, st, s, m);
+    const unsigned nt = (unsigned)((m.K + kMergeTile - 1) / kMergeTile);
+    hipLaunchKernelGGL(k_merge_pairs, dim3(nt, nt), dim3(kMergeTile), 0, st, s, m);
     hipLaunchKernelGGL(k_merge_flatten, gk, b256, 0, st, s, m);
     hipLaunchKernelGGL(k_feature_sums, gk, b256, 0, st, s, m);
     hipLaunchKernelGGL(k_feature_means, gk, b256, 0, st, s, m);
