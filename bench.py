@@ -13,6 +13,8 @@ Beside the headline the bench reports, on the same GPU:
   city_2d  - a planar 2D + t city-like workload with particles at 4 steps
              per field step: grow (masks compared with the oracle) and
              clustering;
+  rate4_3d - the 128^3 x 32 workload with particles saved 4 times per field
+             step: grow, masks compared with the oracle;
   forward_only - the same grow with causal trajectory coupling (t -> t+1
              only), its masks compared with the directed oracle;
   seed_ids - per-seed component ids of the same grow (lowest seed index
@@ -380,19 +382,14 @@ def bench_batched(args, torch, log):
             "autotune": tune["table"]}
 
 
-def bench_city(args, torch, log):
-    """The planar 2D + t city-like workload (1024 x 1024 x 1 cells x 48 field
-    steps, 28,672 particles at 4 steps per field step): the grow under both
-    round schedules, masks compared with the oracle at the same rate (unless
-    --no-cpu-baseline), and the clustering with 32 x 32 x 1 x 4 centres."""
-    from paper_1903_12294_amd import Grower, synth
+def bench_grow_form(args, torch, log, inst, name, slic_k=None):
+    """A grow workload beside the headline: the grow under both round
+    schedules, masks compared with the oracle at the instance's particle rate
+    (unless --no-cpu-baseline), and (slic_k) the clustering."""
+    from paper_1903_12294_amd import Grower
     dev = torch.device("cuda:0")
-    t0 = time.time()
-    inst = synth.make_city()
-    name = synth.CITY["name"]
-    log(f"[bench] generated {name} in {time.time() - t0:.1f}s")
     X, Y, Z = inst["dims"]
-    T, P, r = inst["T"], inst["P"], inst["rate"]
+    T, P, r = inst["T"], inst["P"], inst.get("rate", 1)
     Tp = inst["xyz"].shape[0]
     V = X * Y * Z * T
     fmask = torch.empty((V + 31) // 32, dtype=torch.int32, device=dev)
@@ -426,11 +423,38 @@ def bench_city(args, torch, log):
         out["oracle_s"] = round(time.perf_counter() - t0, 2)
         out["parity_vs_oracle"] = bool(all(np.array_equal(f, ofm) and np.array_equal(p, opm)
                                            for _, f, p in res.values()))
-    log(f"[bench] city {out['ms_per_step']} ms/step, parity {out.get('parity_vs_oracle')}")
+    log(f"[bench] {name} {out['ms_per_step']} ms/step, parity {out.get('parity_vs_oracle')}")
     del fmask, pmask
     torch.cuda.empty_cache()
-    out["slic"] = bench_slic(torch, log, inst, name, k=(32, 32, 1, 4), cpu_leg=False)
+    if slic_k is not None:
+        out["slic"] = bench_slic(torch, log, inst, name, k=slic_k, cpu_leg=False)
     return out
+
+
+def bench_city(args, torch, log):
+    """The planar 2D + t city-like workload (1024 x 1024 x 1 cells x 48 field
+    steps, 28,672 particles at 4 steps per field step): grow and clustering
+    with 32 x 32 x 1 x 4 centres."""
+    from paper_1903_12294_amd import synth
+    t0 = time.time()
+    inst = synth.make_city()
+    log(f"[bench] generated {synth.CITY['name']} in {time.time() - t0:.1f}s")
+    return bench_grow_form(args, torch, log, inst, synth.CITY["name"], slic_k=(32, 32, 1, 4))
+
+
+def bench_rate3d(args, torch, log):
+    """The 128^3 x 32 workload with its 262,144 particles saved 4 times per
+    field step (128 steps, two label words each), as the paper's combustion
+    particles are saved more often than the field: the grow."""
+    from paper_1903_12294_amd import synth
+    c = synth.CONFIGS[2]
+    t0 = time.time()
+    inst = synth.make_instance(c["X"], c["Y"], c["Z"], c["T"], c["P"], n_blobs=c["n_blobs"], seed=c["seed"],
+                               n_seeds=c["n_seeds"], tau_f=c["tau"], tau_p=c["tau"], crossing=c["crossing"],
+                               rate=4)
+    name = "single-128^3x32-r4"
+    log(f"[bench] generated {name} in {time.time() - t0:.1f}s")
+    return bench_grow_form(args, torch, log, inst, name)
 
 
 def bench_adjacent(g, inst, fmask, pmask, args, torch, forms):
@@ -646,6 +670,7 @@ def main():
         forms["batched"] = bench_batched(args, torch, log)
         forms["slic"] = bench_slic(torch, log, inst, cfg["name"])
         forms["city_2d"] = bench_city(args, torch, log)
+        forms["rate4_3d"] = bench_rate3d(args, torch, log)
         torch.cuda.empty_cache()
 
     cpu = None
