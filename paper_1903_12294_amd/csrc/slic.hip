@@ -499,11 +499,39 @@ __global__ __launch_bounds__(256) void k_merge_flatten(DevS s, DevM m) {
     m.feat[i] = f;
 }
 
+// The lanes of a wave that hold centres of one feature combine their values
+// first, so that one lane per (wave, feature) updates the feature (most
+// centres of a wave usually share one).  Visits each distinct feature of the
+// wave in turn: fn(feature, this lane holds it, this lane updates it); F < 0:
+// no centre.
+template <typename Fn>
+__device__ __forceinline__ void per_wave_feature(int F, Fn&& fn) {
+    unsigned long long pending = __ballot(F >= 0);
+    while (pending) {  // wave-uniform
+        const int leader = __ffsll((long long)pending) - 1;
+        const int FL = __shfl(F, leader);
+        const bool mine = F == FL;
+        pending &= ~__ballot(mine);
+        fn(FL, mine, (int)__lane_id() == leader);
+    }
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
 __global__ __launch_bounds__(256) void k_feature_sums(DevS s, DevM m) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m.K || m.feat[i] < 0) return;
-    const int F = m.feat[i];
-    for (int j = 0; j < kSlicAcc; ++j) atomicAdd(&m.fsum[8 * (size_t)F + j], s.lsum[8 * (size_t)i + j]);
+    const int F = i < m.K ? m.feat[i] : -1;
+    unsigned long long v[kSlicAcc];
+    for (int j = 0; j < kSlicAcc; ++j) v[j] = F >= 0 ? s.lsum[8 * (size_t)i + j] : 0ull;
+    per_wave_feature(F, [&](int FL, bool mine, bool lead) {
+        for (int j = 0; j < kSlicAcc; ++j) {
+            const unsigned long long x = wave_sum_u64(mine ? v[j] : 0ull);
+            if (lead) atomicAdd(&m.fsum[8 * (size_t)FL + j], x);
+        }
+    });
 }
 
 __global__ __launch_bounds__(256) void k_feature_means(DevS s, DevM m) {
@@ -633,15 +661,33 @@ __global__ __launch_bounds__(kBlock) void k_feature_pass(DevS s, DevM m, int ty)
     stat_flush(m, tb, ty);
 }
 
+// Per-centre extents and squared deviations folded into their features, one
+// update per (wave, feature).
 __global__ __launch_bounds__(256) void k_feature_fold(DevM m) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m.K || m.feat[i] < 0) return;
-    const int F = m.feat[i];
-    for (int d = 0; d < 4; ++d) {
-        atomicMin(&m.fext[8 * (size_t)F + d], m.cext[8 * (size_t)i + d]);
-        atomicMax(&m.fext[8 * (size_t)F + 4 + d], m.cext[8 * (size_t)i + 4 + d]);
-    }
-    for (int t = 0; t < 2; ++t) atomicAdd(&m.fss[2 * (size_t)F + t], m.css[2 * (size_t)i + t]);
+    const int F = i < m.K ? m.feat[i] : -1;
+    uint32_t e[8];
+    double q[2];
+    for (int d = 0; d < 8; ++d) e[d] = F >= 0 ? m.cext[8 * (size_t)i + d] : (d < 4 ? 0xFFFFFFFFu : 0u);
+    for (int t = 0; t < 2; ++t) q[t] = F >= 0 ? m.css[2 * (size_t)i + t] : 0.0;
+    per_wave_feature(F, [&](int FL, bool mine, bool lead) {
+        for (int d = 0; d < 8; ++d) {
+            uint32_t x = mine ? e[d] : (d < 4 ? 0xFFFFFFFFu : 0u);
+            for (int o = 32; o > 0; o >>= 1) {
+                const uint32_t y = __shfl_xor(x, o);
+                x = d < 4 ? min(x, y) : max(x, y);
+            }
+            if (lead) {
+                if (d < 4) atomicMin(&m.fext[8 * (size_t)FL + d], x);
+                else atomicMax(&m.fext[8 * (size_t)FL + d], x);
+            }
+        }
+        for (int t = 0; t < 2; ++t) {
+            double x = mine ? q[t] : 0.0;
+            for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+            if (lead) atomicAdd(&m.fss[2 * (size_t)FL + t], x);
+        }
+    });
 }
 
 __global__ __launch_bounds__(256) void k_feature_write(DevM m) {
