@@ -305,11 +305,17 @@ CITY = dict(name="city-2d-1024^2x48-r4", X=1024, Y=1024, Z=1, T=48, rate=4, P=28
 
 
 def make_city(**kw) -> dict:
-    """The planar city-like workload above (keyword arguments override)."""
+    """The planar city-like workload above (keyword arguments override).
+    Particles lie on the layer's mid-plane (z = 0.5, like the field samples'
+    voxel centres), so the clustering's z differences vanish, as in a 2D + t
+    method without a z coordinate."""
     c = dict(CITY, **kw)
-    return make_instance(c["X"], c["Y"], c["Z"], c["T"], c["P"], n_blobs=c["n_blobs"], seed=c["seed"],
+    inst = make_instance(c["X"], c["Y"], c["Z"], c["T"], c["P"], n_blobs=c["n_blobs"], seed=c["seed"],
                          n_seeds=c["n_seeds"], tau_f=c["tau"], tau_p=c["tau"], crossing=c["crossing"],
                          rate=c["rate"])
+    if c["Z"] == 1:
+        inst["xyz"][..., 2] = np.float32(0.5)
+    return inst
 
 
 def make_config(k: int, *, attr_mode: str = "field", tau_p_offset: float = 0.0,
