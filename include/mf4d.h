@@ -69,7 +69,7 @@ enum {
     MF4D_ERR_HIP = -4,           /* a HIP runtime call failed */
     MF4D_ERR_STATE = -5,         /* call out of order (e.g. grow before load) */
     MF4D_ERR_NOT_CONVERGED = -6, /* round cap reached; masks hold a valid subset */
-    MF4D_ERR_UNSUPPORTED = -7    /* shape outside what this build supports */
+    MF4D_ERR_UNSUPPORTED = -7    /* shape outside what the library supports */
 };
 
 enum { MF4D_HOST = 0, MF4D_DEVICE = 1 };

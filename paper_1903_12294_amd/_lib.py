@@ -134,7 +134,7 @@ def load_library(path: str = LIB_PATH):
     if _lib is not None and path == LIB_PATH:
         return _lib
     if not os.path.exists(path):
-        raise LibraryMissing(f"{path} is not built; run __graft_entry__.build() first")
+        raise LibraryMissing(f"{path} is not built; run paper_1903_12294_amd.build.build_library() first")
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
