@@ -71,16 +71,18 @@ struct DevM {
 int launch_slic_merge(const DevS& s, const DevM& m, hipStream_t st);
 
 // Visiting order of the point samples: particle-steps sorted by the tile
-// holding them (tile = voxel bit >> shift), steps in no voxel last; order[j]
-// = t * P + p of the j-th.  Their positions and times (spos; time t / r in
-// field steps, r particle steps per field step) and values (sattr) are copied
-// in that order from xyz [T][P][3] and attr [T][P] (T particle steps).  bins:
-// [P][Tpad] voxel bits (~0u: none); scratch: nb + 1 + 1025 words, nb = number
-// of tiles + 1.  Errors as a HIP result.
+// holding them (tile = voxel bit >> shift), steps in no voxel last; order[t *
+// P + p] = the position of that step in the visiting order.  Their positions
+// and times (spos; time t / r in field steps, r particle steps per field step)
+// and values (sattr) are copied in that order from xyz [T][P][3] and attr
+// [T][P] (T particle steps).  bins: [P][Tpad] voxel bits (~0u: none);
+// scratch: nb + 1 + 1025 words, nb = number of tiles + 1.  Errors as a HIP
+// result.
 int launch_slic_order(const uint32_t* bins, const float* xyz, const float* attr, int64_t P, int Tpad,
                       int T, int r, int shift, uint32_t ntiles, uint32_t* scratch, uint32_t* order,
                       float4* spos, float* sattr, hipStream_t st);
-// Point labels from visiting order back to [T][P]: out[order[j]] = in[j].
+// Point labels from visiting order back to [T][P]: out[q] = in[order[q]]
+// (order as written by launch_slic_order).
 void launch_slic_unsort(const int32_t* in, const uint32_t* order, uint64_t Q, int32_t* out, hipStream_t st);
 // Trajectory segments (Section 3.4), in place on point labels [T][P]: the
 // feature id (feat[label]) where the particle has that feature at t - 1 or

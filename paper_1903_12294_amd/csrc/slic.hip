@@ -838,7 +838,7 @@ __global__ __launch_bounds__(256) void k_order_scatter(const uint32_t* __restric
             const uint64_t p = e / (uint64_t)Tpad;
             const uint64_t t = e - p * Tpad;
             const uint64_t i = t * (uint64_t)P + p;
-            order[at] = (uint32_t)i;
+            order[i] = at;  // position of step i in the visiting order
             spos[at] = make_float4(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], __fdiv_rn((float)t, (float)rate));
             sattr[at] = attr[i];
         }
@@ -847,11 +847,12 @@ __global__ __launch_bounds__(256) void k_order_scatter(const uint32_t* __restric
 
 }  // namespace
 
+// Gathers, so that the writes of [T][P] are coalesced: out[q] = in[pos[q]].
 __global__ __launch_bounds__(256) void k_slic_unsort(const int32_t* __restrict__ in,
-                                                     const uint32_t* __restrict__ order, uint64_t Q,
+                                                     const uint32_t* __restrict__ pos, uint64_t Q,
                                                      int32_t* __restrict__ out) {
-    for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < Q; j += (uint64_t)gridDim.x * blockDim.x)
-        out[order[j]] = in[j];
+    for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < Q; q += (uint64_t)gridDim.x * blockDim.x)
+        out[q] = in[pos[q]];
 }
 
 // Trajectory segments of the features (Section 3.4): a particle-step keeps
