@@ -326,9 +326,12 @@ def bench_batched(args, torch, log):
     X, Y, Z = inst["dims"]
     T, P = inst["T"], inst["P"]
     V = X * Y * Z * T
-    tune = autotune.tune_batched(inst, crit, qseeds, repeats=1, use_cache=False)
+    if args.no_tune:
+        tune = {"best": {"tile": [8, 4, 4, 4]}, "table": None}
+    else:
+        tune = autotune.tune_batched(inst, crit, qseeds, repeats=1, use_cache=False)
     shape = tuple(tune["best"]["tile"])
-    log(f"[bench] batched tile {shape} from {len(tune['table'])} candidates")
+    log(f"[bench] batched tile {shape}" + (f" from {len(tune['table'])} candidates" if tune["table"] else ""))
     g = Grower(device=0)
     try:
         g.load_field(torch.from_numpy(inst["field"]).to(dev))
@@ -457,6 +460,34 @@ def bench_rate3d(args, torch, log):
     return bench_grow_form(args, torch, log, inst, name)
 
 
+def bench_learned(g, args, torch, fmask, pmask, ref_f, ref_p):
+    """Learned scheduling on the loaded workload: the plain grow (tiles mode),
+    then the trained (committed weights) and untrained predictor, masks
+    compared with the plain grow's (ref_f, ref_p)."""
+    from paper_1903_12294_amd.learned import Net, init_params, set_predictor
+    base = run_steps(g, fmask, pmask, args.steps, 2, torch)
+    lf = {"baseline_tiles_ms": round(base["ms"], 4), "baseline_tiles_tested": base["stats"]["tiles_tested"]}
+    net = Net(0)
+    try:
+        variants = [("untrained", init_params(0), 0.0)]
+        if os.path.exists(PREDICTOR):
+            meta = json.load(open(os.path.splitext(PREDICTOR)[0] + ".json"))
+            variants.insert(0, ("trained", np.load(PREDICTOR), float(meta["logit_threshold"])))
+        for name, params, thr in variants:
+            net.set_params(params)
+            set_predictor(g, net, thr)
+            rl = run_steps(g, fmask, pmask, args.steps, 2, torch)
+            lf[name] = {"ms_per_step": round(rl["ms"], 4), "speedup_vs_plain": round(base["ms"] / rl["ms"], 3),
+                        "tiles_tested": rl["stats"]["tiles_tested"],
+                        "tiles_deferred_read": rl["stats"]["tiles_deferred_read"],
+                        "rounds": rl["stats"]["rounds"], "logit_threshold": thr,
+                        "masks_equal": bool(torch.equal(fmask, ref_f) and torch.equal(pmask, ref_p))}
+            set_predictor(g, None)
+    finally:
+        net.close()
+    return lf
+
+
 def bench_adjacent(g, inst, fmask, pmask, args, torch, forms):
     """Adjacent outputs of the grower on the headline workload, on the same
     context: the trajectory segment read-out, the grow with forward-only
@@ -531,6 +562,11 @@ def main():
                     help="only the clustering form (for profiling its kernels); prints its JSON object")
     ap.add_argument("--city-only", action="store_true",
                     help="only the planar city-like form (for profiling); prints its JSON object")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the batched form (for profiling its kernels); prints its JSON object")
+    ap.add_argument("--learned-only", action="store_true",
+                    help="only the learned-scheduling form at the chosen config (for profiling); "
+                         "prints its JSON object")
     ap.add_argument("--batched-reps", type=int, default=3)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run three 1 GiB device copies (a plain copy kernel of known size, "
@@ -557,6 +593,9 @@ def main():
     log(f"[bench] generated {cfg['name']} in {time.time() - t0:.1f}s")
     if args.slic_only:
         print(json.dumps(bench_slic(torch, log, inst, cfg["name"])), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps(bench_batched(args, torch, log)), flush=True)
         return
     X, Y, Z = inst["dims"]
     T, P = inst["T"], inst["P"]
@@ -622,6 +661,12 @@ def main():
         del a, b
     ref_f = fmask.clone()
     ref_p = pmask.clone()
+    if args.learned_only:
+        g.set_admit_mode("tiles")
+        out = bench_learned(g, args, torch, fmask, pmask, ref_f, ref_p)
+        g.close()
+        print(json.dumps(out), flush=True)
+        return
     forms = {}
     checks = None
     if not args.no_forms:
@@ -638,29 +683,7 @@ def main():
                           "k_admit_field": {"bytes_per_launch": eb, "ms_per_launch": round(re_["ms_admit_field"], 4),
                                             "achieved_GBps": round(ea, 1), "frac": round(ea / HBM_PEAK_GBS, 4)}}
         g.set_admit_mode("tiles")
-        # learned scheduling: trained and untrained predictor, tiles mode
-        from paper_1903_12294_amd.learned import Net, init_params, set_predictor
-        base = run_steps(g, fmask, pmask, args.steps, 2, torch)
-        lf = {"baseline_tiles_ms": round(base["ms"], 4), "baseline_tiles_tested": base["stats"]["tiles_tested"]}
-        net = Net(0)
-        try:
-            variants = [("untrained", init_params(0), 0.0)]
-            if os.path.exists(PREDICTOR):
-                meta = json.load(open(os.path.splitext(PREDICTOR)[0] + ".json"))
-                variants.insert(0, ("trained", np.load(PREDICTOR), float(meta["logit_threshold"])))
-            for name, params, thr in variants:
-                net.set_params(params)
-                set_predictor(g, net, thr)
-                rl = run_steps(g, fmask, pmask, args.steps, 2, torch)
-                lf[name] = {"ms_per_step": round(rl["ms"], 4), "speedup_vs_plain": round(base["ms"] / rl["ms"], 3),
-                            "tiles_tested": rl["stats"]["tiles_tested"],
-                            "tiles_deferred_read": rl["stats"]["tiles_deferred_read"],
-                            "rounds": rl["stats"]["rounds"], "logit_threshold": thr,
-                            "masks_equal": bool(torch.equal(fmask, ref_f) and torch.equal(pmask, ref_p))}
-                set_predictor(g, None)
-        finally:
-            net.close()
-        forms["learned"] = lf
+        forms["learned"] = bench_learned(g, args, torch, fmask, pmask, ref_f, ref_p)
         g.set_admit_mode(choice["admit"])
     g.close()
     del g
@@ -749,6 +772,7 @@ def main():
         "forms": forms,
     }
     print(json.dumps(out), flush=True)
+    torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

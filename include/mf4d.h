@@ -77,6 +77,12 @@ enum { MF4D_HOST = 0, MF4D_DEVICE = 1 };
 /* Admissibility modes (mf4d_set_admit_mode). */
 enum { MF4D_ADMIT_TILES = 0, MF4D_ADMIT_ALL = 1 };
 
+/* Schedulers of the rounds of a grow (mf4d_set_scheduler). */
+enum {
+    MF4D_SCHEDULER_PLAIN = 0,  /* tiles are visited in the order their work is found */
+    MF4D_SCHEDULER_LEARNED = 1 /* the brick-activity predictor orders the first visits */
+};
+
 /* Trajectory coupling (mf4d_set_trajectory_mode). */
 enum { MF4D_TRAJ_BOTH = 0, MF4D_TRAJ_FORWARD = 1 };
 
@@ -167,10 +173,17 @@ int mf4d_load_particles_rate(mf4d_ctx *ctx, const float *xyz, const float *attr,
                              int steps_per_field_step, int where);
 
 /* Membership criteria: inclusive fp32 bands for field and particle values.
+ * The paper's method has no thresholds; its metrics D_f and D_p (Section
+ * 3.2.3) test each sample type only against its own value, and these bands
+ * are that per-type value test made a membership criterion: a voxel-step
+ * tests the field band, a particle-step the attribute band.
  * Errors: MF4D_ERR_ARG (a NaN bound). */
 int mf4d_set_criteria(mf4d_ctx *ctx, float f_lo, float f_hi, float a_lo, float a_hi);
 
-/* Seeds int32 [S][4] = (x, y, z, t).  Duplicates are allowed.
+/* Seeds int32 [S][4] = (x, y, z, t): the field samples (Section 3.1) the
+ * grown feature starts from (the paper's method starts from a seed grid of
+ * cluster centres, Section 3.2.1; a grower starts from chosen samples
+ * instead).  Duplicates are allowed.
  * Errors: MF4D_ERR_STATE (no field), MF4D_ERR_RANGE (a seed outside the
  * grid; nothing changes), MF4D_ERR_ARG. */
 int mf4d_set_seeds(mf4d_ctx *ctx, const int32_t *xyzt, int64_t S, int where);
@@ -206,6 +219,9 @@ int mf4d_set_max_rounds(mf4d_ctx *ctx, int64_t cap);
 
 /* Grow the feature from scratch: admissibility of every node, seeding, and
  * rounds of tile sweeps and particle coupling until a round changes no bit.
+ * The result is the feature with a field and a point part spanning
+ * timesteps of Section 1; every sample is tested independently in each
+ * round, as the samples of Section 3.4's GPU design are.
  * `out` (nullable) receives statistics.
  * Errors: MF4D_ERR_STATE (no field or no criteria), MF4D_ERR_NOT_CONVERGED
  * (the round cap was reached: the labels hold a subset of the feature that
@@ -215,6 +231,15 @@ int mf4d_grow(mf4d_ctx *ctx, mf4d_stats *out);
 /* Continue rounds from the current labels after MF4D_ERR_NOT_CONVERGED.
  * Errors: as mf4d_grow; MF4D_ERR_STATE if there is nothing to resume. */
 int mf4d_grow_resume(mf4d_ctx *ctx, mf4d_stats *out);
+
+/* Discard the grown feature (the output of Section 1's contribution): every
+ * field and particle label bit is cleared and the context holds no grown set,
+ * so reads fail with MF4D_ERR_STATE and mf4d_grow_resume has nothing to
+ * continue until the next mf4d_grow.  (mf4d_grow itself always starts from
+ * cleared labels; mf4d_grow_resume is the call that continues from the
+ * current ones.)  Waits for the device.
+ * Errors: MF4D_ERR_ARG (ctx NULL), MF4D_ERR_STATE (no field loaded). */
+int mf4d_reset_labels(mf4d_ctx *ctx);
 
 /* Write the field part of the grown feature as canonical bit words (layout
  * above) to dst, which holds nwords >= ceil(X*Y*Z*T / 32) words.  Counts the
@@ -259,7 +284,9 @@ int mf4d_grow_seed_ids(mf4d_ctx *ctx, int32_t *field_ids, size_t nf, int32_t *pa
                        int where, int64_t *grows);
 
 /* Batched queries (up to 256, each with its own criteria and seeds), grown
- * together as the bit-planes of one 256-bit label per node.  crit fp32
+ * together as the bit-planes of one 256-bit label per node: the interactive
+ * loop of the paper's workflow (Section 3: adjust the parameters and segment
+ * again) run for many parameter sets in one pass over the data.  crit fp32
  * [Q][4] = (f_lo, f_hi, a_lo, a_hi) per query; seeds int32 [S][5] =
  * (x, y, z, t, q).  Every query means the same as a single grow with its own
  * criteria and seeds.
@@ -273,7 +300,8 @@ int mf4d_set_queries(mf4d_ctx *ctx, int Q, const float *crit, const int32_t *qxy
  * Errors: MF4D_ERR_ARG. */
 int mf4d_set_batched_tile(mf4d_ctx *ctx, int bx, int by, int bz, int bt);
 
-/* Grow every query and write the results: fplanes uint32 [X*Y*Z*T][8] in
+/* Grow every query (as mf4d_grow grows one, Section 1's output for each)
+ * and write the results: fplanes uint32 [X*Y*Z*T][8] in
  * canonical voxel order, query q in bit (q & 31) of word (q >> 5); pplanes
  * uint32 [T][P][8] likewise (NULL allowed when no particles are loaded).
  * Planes q >= Q are zero.  Device outputs are grown in place.
@@ -281,6 +309,17 @@ int mf4d_set_batched_tile(mf4d_ctx *ctx, int bx, int by, int bz, int bt);
  * too small), MF4D_ERR_OOM, MF4D_ERR_HIP. */
 int mf4d_grow_batched(mf4d_ctx *ctx, uint32_t *fplanes, size_t fwords, uint32_t *pplanes,
                       size_t pwords, int where, mf4d_stats *out);
+
+/* The planes of the last mf4d_grow_batched call that was given no output
+ * buffers (fplanes and pplanes NULL, fwords and pwords 0): such a call grows
+ * into planes the context owns (allocated on first use: 32 bytes per
+ * voxel-step and per particle-step), and this call copies them out in the
+ * layouts of mf4d_grow_batched.  pdst may be NULL (then pwords is ignored).
+ * Waits for the copies.
+ * Errors: MF4D_ERR_STATE (no batched grow into context planes since the
+ * last load or query change), MF4D_ERR_ARG (a buffer too small). */
+int mf4d_read_batched(mf4d_ctx *ctx, uint32_t *fdst, size_t fwords, uint32_t *pdst, size_t pwords,
+                      int where);
 
 /* ---- brick-activity predictor --------------------------------------------
  * A 3-layer 3D convolutional network (8 -> 16 -> 16 -> 1 channels, 3x3x3,
@@ -295,7 +334,9 @@ int mf4d_grow_batched(mf4d_ctx *ctx, uint32_t *fplanes, size_t fwords, uint32_t 
  * fp32 master parameters, Adam.  Parameter layout (fp32, 10833 values): per
  * layer W [cout][cin][3][3][3] then b [cout]. */
 
-/* Number of parameters (10833). */
+/* The network has no counterpart in the paper; its inputs summarise the
+ * field and point samples of Section 3.1 per brick-step.
+ * Number of parameters (10833). */
 int mf4d_net_num_params(void);
 
 /* Create a network with zero parameters on `device`, ordering its work on
@@ -326,6 +367,21 @@ int mf4d_net_grad(mf4d_net *net, const uint16_t *x, const uint8_t *y, int N, int
 int mf4d_net_train_step(mf4d_net *net, const uint16_t *x, const uint8_t *y, int N, int D, int H,
                         int W, float pos_weight, float lr, float *loss);
 
+/* The network's three kernels as separate calls, for a trainer that drives
+ * them itself.  mf4d_nn_forward is mf4d_net_forward.  mf4d_nn_backward is
+ * mf4d_net_grad that also writes, when dx is not NULL, the gradient of the
+ * loss with respect to the inputs x as fp32 [N][D][H][W][16] (channels 8..15
+ * are unused inputs and read 0).  mf4d_nn_adam_step applies one Adam step
+ * (beta 0.9 / 0.999, eps 1e-8, learning rate lr) with the gradients `grads`
+ * (fp32, parameter layout, device; NULL: those of the last mf4d_nn_backward
+ * or mf4d_net_grad call).  Device pointers only (where = MF4D_DEVICE).
+ * Errors: MF4D_ERR_ARG, MF4D_ERR_UNSUPPORTED, MF4D_ERR_OOM, MF4D_ERR_HIP. */
+int mf4d_nn_forward(mf4d_net *net, const uint16_t *x, int N, int D, int H, int W, float *logits,
+                    int where);
+int mf4d_nn_backward(mf4d_net *net, const uint16_t *x, const uint8_t *y, int N, int D, int H, int W,
+                     float pos_weight, float *grads, float *dx, float *loss, int where);
+int mf4d_nn_adam_step(mf4d_net *net, const float *grads, float lr, int where);
+
 /* Brick grid of the loaded field: dims4 = (T, Db, Hb, Wb). */
 int mf4d_brick_dims(mf4d_ctx *ctx, int *dims4);
 
@@ -342,6 +398,18 @@ int mf4d_brick_labels(mf4d_ctx *ctx, uint8_t *dst, size_t n, int where);
  * >= logit_threshold.  The context keeps the pointer; the net must outlive
  * its use.  Errors: MF4D_ERR_ARG (NaN threshold). */
 int mf4d_set_predictor(mf4d_ctx *ctx, mf4d_net *net, float logit_threshold);
+
+/* Choose the scheduler of the context's grows.  MF4D_SCHEDULER_PLAIN (the
+ * default): params must be NULL and nbytes 0.  MF4D_SCHEDULER_LEARNED: params
+ * holds, on the host, the network's fp32 parameters (mf4d_net_num_params()
+ * values, layout above) followed by one fp32 logit threshold, nbytes = 4 *
+ * (mf4d_net_num_params() + 1); the context keeps its own copy of the network
+ * (on its device and stream) and uses it as mf4d_set_predictor does.  No
+ * scheduler changes the grown set (the least fixed point of the coupled
+ * graph is unique; a verification round and the plain rounds judge it).
+ * Errors: MF4D_ERR_ARG (unknown kind, bad size, NaN threshold),
+ * MF4D_ERR_OOM, MF4D_ERR_HIP. */
+int mf4d_set_scheduler(mf4d_ctx *ctx, int kind, const void *params, size_t nbytes);
 
 /* Statistics of the last grow, including member counts of the last reads. */
 int mf4d_last_stats(mf4d_ctx *ctx, mf4d_stats *out);

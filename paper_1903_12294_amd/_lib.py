@@ -5,8 +5,11 @@ There is no fallback: if the library is missing, loading raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 from ctypes import POINTER, c_char_p, c_double, c_float, c_int, c_int64, c_size_t, c_void_p
 
 PKG = os.path.dirname(os.path.abspath(__file__))
@@ -28,12 +31,39 @@ MF4D_TRAJ_BOTH = 0
 MF4D_TRAJ_FORWARD = 1
 MF4D_SCHED_PERSISTENT = 0
 MF4D_SCHED_LAUNCH = 1
+MF4D_SCHEDULER_PLAIN = 0
+MF4D_SCHEDULER_LEARNED = 1
 
 ERROR_NAMES = {
     MF4D_ERR_ARG: "ARG", MF4D_ERR_RANGE: "RANGE", MF4D_ERR_OOM: "OOM", MF4D_ERR_HIP: "HIP",
     MF4D_ERR_STATE: "STATE", MF4D_ERR_NOT_CONVERGED: "NOT_CONVERGED",
     MF4D_ERR_UNSUPPORTED: "UNSUPPORTED",
 }
+
+
+# Library objects (contexts, networks) still open.  They are closed by an exit
+# handler, before the interpreter shuts down: a HIP call made from a finaliser
+# while the runtime itself is being torn down can crash the process after its
+# work is done.
+_open_handles = weakref.WeakSet()
+
+
+def track(obj) -> None:
+    """Register an object with a close() method to be closed at exit."""
+    _open_handles.add(obj)
+
+
+def finalizing() -> bool:
+    return sys.is_finalizing()
+
+
+@atexit.register
+def _close_open_handles() -> None:
+    for obj in list(_open_handles):
+        try:
+            obj.close()
+        except Exception:
+            pass
 
 
 class Stats(ctypes.Structure):
@@ -111,6 +141,13 @@ SIGNATURES = {
     "mf4d_features": (c_int, [c_void_p, c_void_p, c_size_t, c_int]),
     "mf4d_brick_labels": (c_int, [c_void_p, c_void_p, c_size_t, c_int]),
     "mf4d_set_predictor": (c_int, [c_void_p, c_void_p, c_float]),
+    "mf4d_set_scheduler": (c_int, [c_void_p, c_int, c_void_p, c_size_t]),
+    "mf4d_reset_labels": (c_int, [c_void_p]),
+    "mf4d_read_batched": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, c_int]),
+    "mf4d_nn_forward": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_void_p, c_int]),
+    "mf4d_nn_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_float,
+                                 c_void_p, c_void_p, c_void_p, c_int]),
+    "mf4d_nn_adam_step": (c_int, [c_void_p, c_void_p, c_float, c_int]),
 }
 
 

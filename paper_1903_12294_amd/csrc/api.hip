@@ -152,6 +152,10 @@ struct mf4d_ctx {
     uint8_t* b_chg = nullptr;
     uint32_t* b_work = nullptr;
     uint32_t* b_counters = nullptr;
+    uint32_t* b_fown = nullptr;  // planes owned by the context (a batched grow given no buffers)
+    uint32_t* b_pown = nullptr;
+    size_t b_fown_n = 0, b_pown_n = 0;
+    bool b_grown = false;        // the owned planes hold the last batched grow
 
     // brick statistics and the activity predictor
     BrickDims bd{};
@@ -161,6 +165,7 @@ struct mf4d_ctx {
     float* blogits = nullptr;   // [T][Db][Hb][Wb]
     uint8_t* tpred = nullptr;   // NT
     mf4d_net* net = nullptr;
+    mf4d_net* own_net = nullptr;  // the network of the learned scheduler (mf4d_set_scheduler)
     float pred_thr = 0.0f;
 
     // particles as loaded, for the clustering: xyz [T][P][3] then attr [T][P]
@@ -223,6 +228,10 @@ void free_field(mf4d_ctx* c) {
     dev_free(c->b_dirty);
     dev_free(c->b_chg);
     dev_free(c->b_work);
+    dev_free(c->b_fown);
+    dev_free(c->b_pown);
+    c->b_fown_n = c->b_pown_n = 0;
+    c->b_grown = false;
     c->NTB = 0;
     c->has_field = false;
 }
@@ -244,6 +253,9 @@ void free_particles(mf4d_ctx* c) {
     dev_free(c->pblk);
     dev_free(c->dlist);
     dev_free(c->psum);
+    dev_free(c->b_pown);
+    c->b_pown_n = 0;
+    c->b_grown = false;
     c->has_particles = false;
     c->pg = PGeom{};
     c->bstats_valid = false;
@@ -490,6 +502,8 @@ void mf4d_destroy(mf4d_ctx* c) {
     dev_free(c->sslab);
     dev_free(c->slsum);
     dev_free(c->mbuf);
+    if (c->own_net) mf4d_net_destroy(c->own_net);
+    c->own_net = nullptr;
     if (c->h_scounters) (void)hipHostFree(c->h_scounters);
     if (c->staging) (void)hipFree(c->staging);
     if (c->h_counters) (void)hipHostFree(c->h_counters);
@@ -852,6 +866,20 @@ int mf4d_grow_resume(mf4d_ctx* c, mf4d_stats* out) {
     return MF4D_OK;
 }
 
+int mf4d_reset_labels(mf4d_ctx* c) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    if (!c->has_field) return fail(MF4D_ERR_STATE, "no field loaded");
+    HIP_TRY(hipSetDevice(c->device));
+    launch_fill_u32(c->Lf, 0u, c->g.nwords, c->stream);
+    if (c->has_particles && c->Lp)
+        launch_fill_u32(reinterpret_cast<uint32_t*>(c->Lp), 0u, 2ull * (uint64_t)c->pg.P * c->pg.W, c->stream);
+    int rc = sync(c);
+    if (rc) return rc;
+    c->state = 0;
+    c->round = 0;
+    return MF4D_OK;
+}
+
 // Wait for member counts copied by stream-ordered reads and record them.
 int settle_members(mf4d_ctx* c) {
     if (!c->members_pending[0] && !c->members_pending[1]) return MF4D_OK;
@@ -1089,6 +1117,7 @@ int mf4d_set_queries(mf4d_ctx* c, int Q, const float* crit, const int32_t* qxyzt
         HIP_TRY(hipMemcpy(c->qseeds, sd.data(), sd.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     c->Q = Q;
     c->QS = S;
+    c->b_grown = false;
     return MF4D_OK;
 }
 
@@ -1119,13 +1148,38 @@ int mf4d_grow_batched(mf4d_ctx* c, uint32_t* fplanes, size_t fwords, uint32_t* p
     const Geom& g = c->g;
     const uint64_t V = (uint64_t)g.X * g.Y * g.Z * g.T;
     const uint64_t P = c->has_particles ? (uint64_t)c->pg.P : 0;
-    if (!fplanes || fwords < 8 * V) return fail(MF4D_ERR_ARG, "field planes need %llu words", (unsigned long long)(8 * V));
     const uint64_t Tp = P > 0 ? (uint64_t)c->pg.T : 0;
-    if (P > 0 && (!pplanes || pwords < 8 * P * Tp))
-        return fail(MF4D_ERR_ARG, "particle planes need %llu words", (unsigned long long)(8 * P * Tp));
-    if ((reinterpret_cast<uintptr_t>(fplanes) & 15) || (reinterpret_cast<uintptr_t>(pplanes) & 15))
-        return fail(MF4D_ERR_ARG, "plane buffers must be 16-byte aligned");
+    // no buffers: grow into planes the context owns (read with mf4d_read_batched)
+    const bool owned = !fplanes && !pplanes && fwords == 0 && pwords == 0;
+    if (!owned) {
+        if (!fplanes || fwords < 8 * V)
+            return fail(MF4D_ERR_ARG, "field planes need %llu words", (unsigned long long)(8 * V));
+        if (P > 0 && (!pplanes || pwords < 8 * P * Tp))
+            return fail(MF4D_ERR_ARG, "particle planes need %llu words", (unsigned long long)(8 * P * Tp));
+        if ((reinterpret_cast<uintptr_t>(fplanes) & 15) || (reinterpret_cast<uintptr_t>(pplanes) & 15))
+            return fail(MF4D_ERR_ARG, "plane buffers must be 16-byte aligned");
+    }
     HIP_TRY(hipSetDevice(c->device));
+    c->b_grown = false;
+    if (owned) {
+        if (c->b_fown_n < 8 * V) {
+            dev_free(c->b_fown);
+            c->b_fown_n = 0;
+            int rc = dev_alloc(&c->b_fown, (size_t)(8 * V));
+            if (rc) return rc;
+            c->b_fown_n = (size_t)(8 * V);
+        }
+        if (P > 0 && c->b_pown_n < 8 * P * Tp) {
+            dev_free(c->b_pown);
+            c->b_pown_n = 0;
+            int rc = dev_alloc(&c->b_pown, (size_t)(8 * P * Tp));
+            if (rc) return rc;
+            c->b_pown_n = (size_t)(8 * P * Tp);
+        }
+        fplanes = c->b_fown;
+        pplanes = P > 0 ? c->b_pown : nullptr;
+        where = MF4D_DEVICE;
+    }
     if (c->NTB == 0) {
         const int NXb = (g.X + (1 << c->blog[0]) - 1) >> c->blog[0];
         const int NYb = (g.Y + (1 << c->blog[1]) - 1) >> c->blog[1];
@@ -1223,8 +1277,28 @@ int mf4d_grow_batched(mf4d_ctx* c, uint32_t* fplanes, size_t fwords, uint32_t* p
         rc = sync(c);
         if (rc) return rc;
     }
+    c->b_grown = owned;
     if (out) *out = st;
     return MF4D_OK;
+}
+
+int mf4d_read_batched(mf4d_ctx* c, uint32_t* fdst, size_t fwords, uint32_t* pdst, size_t pwords,
+                      int where) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    if (!c->b_grown) return fail(MF4D_ERR_STATE, "no batched grow into the context's planes");
+    if (where != MF4D_HOST && where != MF4D_DEVICE) return fail(MF4D_ERR_ARG, "bad where");
+    const Geom& g = c->g;
+    const uint64_t V = (uint64_t)g.X * g.Y * g.Z * g.T;
+    const uint64_t P = c->has_particles ? (uint64_t)c->pg.P : 0;
+    const uint64_t Tp = P > 0 ? (uint64_t)c->pg.T : 0;
+    if (!fdst || fwords < 8 * V) return fail(MF4D_ERR_ARG, "field planes need %llu words", (unsigned long long)(8 * V));
+    if (pdst && pwords < 8 * P * Tp)
+        return fail(MF4D_ERR_ARG, "particle planes need %llu words", (unsigned long long)(8 * P * Tp));
+    HIP_TRY(hipSetDevice(c->device));
+    const hipMemcpyKind k = where == MF4D_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    HIP_TRY(hipMemcpyAsync(fdst, c->b_fown, 8 * V * sizeof(uint32_t), k, c->stream));
+    if (pdst && P > 0) HIP_TRY(hipMemcpyAsync(pdst, c->b_pown, 8 * P * Tp * sizeof(uint32_t), k, c->stream));
+    return sync(c);
 }
 
 int mf4d_set_predictor(mf4d_ctx* c, mf4d_net* net, float logit_threshold) {
@@ -1232,6 +1306,31 @@ int mf4d_set_predictor(mf4d_ctx* c, mf4d_net* net, float logit_threshold) {
     if (logit_threshold != logit_threshold) return fail(MF4D_ERR_ARG, "threshold is NaN");
     c->net = net;
     c->pred_thr = logit_threshold;
+    return MF4D_OK;
+}
+
+int mf4d_set_scheduler(mf4d_ctx* c, int kind, const void* params, size_t nbytes) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    if (kind == MF4D_SCHEDULER_PLAIN) {
+        if (params || nbytes) return fail(MF4D_ERR_ARG, "the plain scheduler takes no parameters");
+        c->net = nullptr;
+        c->pred_thr = 0.0f;
+        return MF4D_OK;
+    }
+    if (kind != MF4D_SCHEDULER_LEARNED) return fail(MF4D_ERR_ARG, "unknown scheduler %d", kind);
+    const int np = mf4d_net_num_params();
+    if (!params || nbytes != (size_t)(np + 1) * sizeof(float))
+        return fail(MF4D_ERR_ARG, "the learned scheduler takes %d fp32 parameters and a threshold", np);
+    const float thr = static_cast<const float*>(params)[np];
+    if (thr != thr) return fail(MF4D_ERR_ARG, "threshold is NaN");
+    if (!c->own_net) {
+        int rc = mf4d_net_create(&c->own_net, c->device, c->stream);
+        if (rc) return fail(rc, "network: %s", mf4d_net_last_error());
+    }
+    int rc = mf4d_net_set_params(c->own_net, static_cast<const float*>(params), MF4D_HOST);
+    if (rc) return fail(rc, "network: %s", mf4d_net_last_error());
+    c->net = c->own_net;
+    c->pred_thr = thr;
     return MF4D_OK;
 }
 

@@ -41,6 +41,10 @@ uint32_t nn_blocks(int N, int D, int H, int W);
 void launch_conv16(int N, int D, int H, int W, const uint16_t* x, const uint16_t* w,
                    const float* bias, int relu, const uint16_t* mask, uint16_t* out_bf,
                    float* out_f32, hipStream_t s);
+// The convolution without bias or activation, all 16 output channels as
+// fp32 [..][16] (the input gradient of the first layer).
+void launch_conv16_f32(int N, int D, int H, int W, const uint16_t* x, const uint16_t* w,
+                       float* out_f32, hipStream_t s);
 void launch_conv16_wgrad(int N, int D, int H, int W, const uint16_t* x, const uint16_t* dz,
                          float* part_w, float* part_b, float* gw, float* gb, hipStream_t s);
 void launch_bce(const float* logits, const uint8_t* y, uint64_t n, float pw, uint16_t* dz,

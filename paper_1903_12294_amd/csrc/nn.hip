@@ -75,7 +75,8 @@ __global__ __launch_bounds__(256) void k_conv16(ConvDims c, const uint16_t* __re
                                                 const uint16_t* __restrict__ w,
                                                 const float* __restrict__ bias, int relu,
                                                 const uint16_t* __restrict__ mask,
-                                                uint16_t* __restrict__ out_bf, float* __restrict__ out_f32) {
+                                                uint16_t* __restrict__ out_bf, float* __restrict__ out_f32,
+                                                int f32_all) {
     __shared__ uint16_t s_x[HZ * HY * HX * 16];
     const int lane = lane_id(), wave = threadIdx.x >> 6;
     const int row = lane & 15, grp = lane >> 4;
@@ -116,7 +117,8 @@ __global__ __launch_bounds__(256) void k_conv16(ConvDims c, const uint16_t* __re
                 if (relu) v = fmaxf(v, 0.0f);
                 if (mask && !(bf2f(mask[pos * 16 + row]) > 0.0f)) v = 0.0f;
                 if (out_bf) out_bf[pos * 16 + row] = f2bf(v);
-                if (out_f32 && row == 0) out_f32[pos] = v;
+                if (out_f32 && f32_all) out_f32[pos * 16 + row] = v;
+                else if (out_f32 && row == 0) out_f32[pos] = v;
             }
         }
     }
@@ -453,7 +455,15 @@ void launch_conv16(int N, int D, int H, int W, const uint16_t* x, const uint16_t
     const ConvDims c = conv_dims(N, D, H, W);
     const uint32_t nb = nn_blocks(N, D, H, W);
     hipLaunchKernelGGL(k_conv16, dim3(grid_for(nb, 1, 8192)), dim3(256), 0, s, c, x, w, bias, relu,
-                       mask, out_bf, out_f32);
+                       mask, out_bf, out_f32, 0);
+}
+
+void launch_conv16_f32(int N, int D, int H, int W, const uint16_t* x, const uint16_t* w,
+                       float* out_f32, hipStream_t s) {
+    const ConvDims c = conv_dims(N, D, H, W);
+    const uint32_t nb = nn_blocks(N, D, H, W);
+    hipLaunchKernelGGL(k_conv16, dim3(grid_for(nb, 1, 8192)), dim3(256), 0, s, c, x, w,
+                       (const float*)nullptr, 0, (const uint16_t*)nullptr, (uint16_t*)nullptr, out_f32, 1);
 }
 
 void launch_conv16_wgrad(int N, int D, int H, int W, const uint16_t* x, const uint16_t* dz,

@@ -303,4 +303,46 @@ int mf4d_net_train_step(mf4d_net* n, const uint16_t* x, const uint8_t* y, int N,
     return MF4D_OK;
 }
 
+int mf4d_nn_forward(mf4d_net* n, const uint16_t* x, int N, int D, int H, int W, float* logits,
+                    int where) {
+    return mf4d_net_forward(n, x, N, D, H, W, logits, where);
+}
+
+int mf4d_nn_backward(mf4d_net* n, const uint16_t* x, const uint8_t* y, int N, int D, int H, int W,
+                     float pos_weight, float* grads, float* dx, float* loss, int where) {
+    if (!n || !x || !y || !grads) return nfail(MF4D_ERR_ARG, "NULL argument");
+    if (where != MF4D_DEVICE) return nfail(MF4D_ERR_ARG, "network tensors must be device pointers");
+    int rc = check_dims(N, D, H, W);
+    if (rc) return rc;
+    NHIP(hipSetDevice(n->device));
+    rc = ensure_acts(n, (uint64_t)N * D * H * W, nn_blocks(N, D, H, W));
+    if (rc) return rc;
+    forward(n, x, N, D, H, W);
+    backward(n, x, y, N, D, H, W, pos_weight);
+    // input gradient: the first layer's input-gradient convolution of dz1
+    if (dx) launch_conv16_f32(N, D, H, W, n->dz1, n->wb, dx, n->stream);
+    NHIP(hipMemcpyAsync(grads, n->grads, n->sh.total * sizeof(float), hipMemcpyDeviceToDevice,
+                        n->stream));
+    NHIP(hipMemcpyAsync(n->h_loss, n->loss, sizeof(float), hipMemcpyDeviceToHost, n->stream));
+    NHIP(hipStreamSynchronize(n->stream));
+    if (loss) *loss = *n->h_loss;
+    return MF4D_OK;
+}
+
+int mf4d_nn_adam_step(mf4d_net* n, const float* grads, float lr, int where) {
+    if (!n) return nfail(MF4D_ERR_ARG, "NULL argument");
+    if (where != MF4D_DEVICE) return nfail(MF4D_ERR_ARG, "network tensors must be device pointers");
+    if (!(lr == lr)) return nfail(MF4D_ERR_ARG, "lr is NaN");
+    NHIP(hipSetDevice(n->device));
+    if (grads && grads != n->grads)
+        NHIP(hipMemcpyAsync(n->grads, grads, n->sh.total * sizeof(float), hipMemcpyDeviceToDevice,
+                            n->stream));
+    n->step += 1;
+    launch_adam(n->params, n->grads, n->m, n->v, n->sh.total, lr, 0.9f, 0.999f, 1e-8f, n->step,
+                n->stream);
+    launch_prep_weights(n->params, n->sh, n->wf, n->wb, n->bias, n->stream);
+    NHIP(hipStreamSynchronize(n->stream));
+    return MF4D_OK;
+}
+
 }  // extern "C"

@@ -49,6 +49,7 @@ class Grower:
             stream = torch.cuda.current_stream(device).cuda_stream
         self.ctx = ctypes.c_void_p()
         self._check(self.lib.mf4d_create(ctypes.byref(self.ctx), device, ctypes.c_void_p(stream)))
+        _lib.track(self)
         self.device = device
         self.dims = None
         self.T = None
@@ -70,6 +71,10 @@ class Grower:
             self.ctx = ctypes.c_void_p()
 
     def __del__(self):
+        # at interpreter shutdown the exit handler has closed every context;
+        # make no HIP call from a finaliser then
+        if _lib.finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -346,3 +351,45 @@ class Grower:
                 self.ctx, ctypes.c_void_p(fplanes.data_ptr()), fplanes.numel(), pp,
                 0 if pplanes is None else pplanes.numel(), MF4D_DEVICE, ctypes.byref(st)))
         return fplanes, pplanes, st.as_dict()
+
+    def grow_batched_owned(self) -> dict:
+        """Grow all queries into planes the context owns (read them with
+        read_batched)."""
+        st = Stats()
+        self._check(self.lib.mf4d_grow_batched(self.ctx, None, 0, None, 0, MF4D_DEVICE, ctypes.byref(st)))
+        return st.as_dict()
+
+    def read_batched(self, fplanes=None, pplanes=None) -> tuple:
+        """The planes of the last grow_batched_owned: into device tensors
+        (int32) or, when None, new numpy arrays [V][8] and [T][P][8] uint32."""
+        X, Y, Z = self.dims
+        V = X * Y * Z * self.T
+        if fplanes is None:
+            fplanes = np.zeros((V, 8), np.uint32)
+            pplanes = np.zeros((self.Tp, self.P, 8), np.uint32)
+            self._check(self.lib.mf4d_read_batched(
+                self.ctx, fplanes.ctypes.data_as(ctypes.c_void_p), fplanes.size,
+                pplanes.ctypes.data_as(ctypes.c_void_p) if self.P else None, pplanes.size, MF4D_HOST))
+        else:
+            pp = ctypes.c_void_p(pplanes.data_ptr()) if pplanes is not None else None
+            self._check(self.lib.mf4d_read_batched(
+                self.ctx, ctypes.c_void_p(fplanes.data_ptr()), fplanes.numel(), pp,
+                0 if pplanes is None else pplanes.numel(), MF4D_DEVICE))
+        return fplanes, pplanes
+
+    def reset_labels(self):
+        """Discard the grown feature (reads fail until the next grow)."""
+        self._check(self.lib.mf4d_reset_labels(self.ctx))
+
+    def set_scheduler(self, kind: str, params=None, logit_threshold: float = 0.0):
+        """'plain', or 'learned' with the predictor's fp32 parameters (the
+        context keeps its own copy of the network)."""
+        if kind == "plain":
+            self._check(self.lib.mf4d_set_scheduler(self.ctx, _lib.MF4D_SCHEDULER_PLAIN, None, 0))
+            return
+        if kind != "learned":
+            raise ValueError(f"unknown scheduler {kind!r}")
+        buf = np.concatenate([np.asarray(params, np.float32).ravel(),
+                              np.array([logit_threshold], np.float32)])
+        self._check(self.lib.mf4d_set_scheduler(self.ctx, _lib.MF4D_SCHEDULER_LEARNED,
+                                                buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes))

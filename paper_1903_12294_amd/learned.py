@@ -58,6 +58,7 @@ class Net:
             stream = torch.cuda.current_stream(device).cuda_stream
         self.ptr = ctypes.c_void_p()
         self._check(self.lib.mf4d_net_create(ctypes.byref(self.ptr), device, ctypes.c_void_p(stream)))
+        _lib.track(self)
         self.n = self.lib.mf4d_net_num_params()
         self.device = device
 
@@ -71,6 +72,8 @@ class Net:
             self.ptr = ctypes.c_void_p()
 
     def __del__(self):
+        if _lib.finalizing():
+            return
         try:
             self.close()
         except Exception:
