@@ -28,16 +28,19 @@ leaves open are marked R and listed in the design notes):
             dbl(s) = float64(s >> 32) * 2^32 + float64(s & 0xffffffff).  A
             centre without samples keeps its previous location and values; one
             without samples of a type keeps that type's previous value.
-  assign    a sample is compared with the centres whose window (Section
-            3.2.2: 2C_1 x 2C_2 x 2C_3 x 2C_4 around the centre) contains it,
-            |pos_d - c_d| <= C_d on every axis (R: among the centres seeded in
-            the 3^4 seed cells around the sample's own), by D_f or D_p
-            (Section 3.2.3) with S_st of Section 3.2.1:
+  assign    each centre searches the 2C_1 x 2C_2 x 2C_3 x 2C_4 window around
+            itself (Section 3.2.2), the samples with |pos_d - c_d| <= C_d on
+            every axis (fp32 difference, c_d the centre rounded to fp32), and
+            rates them by D_f or D_p (Section 3.2.3) with S_st of Section
+            3.2.1:
               S = sqrt(((dx*dx + dy*dy) + dz*dz) + (cf*dt)*(cf*dt))
               D = w_v*|v - v_c| + w_d*S
-            in IEEE fp32, in that order (R), dx = x_s - x_c and so on.  The
-            smallest D wins, ties to the lowest id (R); a sample with no
-            candidate keeps its label (R).
+            in IEEE fp32, in that order (R), dx = x_s - x_c and so on.  A
+            sample takes the centre with the smallest D among those whose
+            window holds it, ties to the lowest id (R); a sample no window
+            holds keeps its label (R).  Every centre is searched: a centre
+            that drifted far from its seed cell still claims the samples of
+            its window.
   converge  after the centres of an iteration are computed, the loop stops
             when every one of the six values of every centre changed by at
             most eps * |old| (R: the "percent change" of Section 3.2.2 read as
@@ -172,48 +175,96 @@ def update_centres(pos, tt, val, typ, lab, prev, K):
     return cen, np.stack([n_f, n_p], 1)
 
 
+def _distance(pos, ts, val, typ, cc, wv, wd, cf):
+    """D of samples against one centre cc (fp32 [6] as x, y, z, t, p, f), in
+    the fixed fp32 order of the header; also the window test."""
+    dx = (pos[:, 0] - cc[0]).astype(F32)
+    dy = (pos[:, 1] - cc[1]).astype(F32)
+    dz = (pos[:, 2] - cc[2]).astype(F32)
+    dt = (ts - cc[3]).astype(F32)
+    vc = np.where(typ == 0, cc[5], cc[4]).astype(F32)
+    ctd = (cf * dt).astype(F32)
+    sq = (((dx * dx + dy * dy).astype(F32) + dz * dz).astype(F32) + ctd * ctd).astype(F32)
+    S = np.sqrt(sq).astype(F32)
+    D = (wv * np.abs((val - vc).astype(F32)) + wd * S).astype(F32)
+    return dx, dy, dz, dt, D
+
+
 def assign(pos, tt, val, typ, lab, cen, C, k, w, cf):
-    """One assignment pass (Section 3.2.2-3.2.3, fp32 as in the header).
-    w = (w_d, w_f, w_p)."""
+    """One assignment pass (Section 3.2.2-3.2.3, fp32 as in the header),
+    centre by centre as the paper describes it: centre i, in id order, rates
+    every sample inside its window and takes those it rates strictly better
+    than any earlier centre did (so ties stay with the lowest id).  Samples
+    are indexed by x so that a centre only looks at the slab of samples its
+    window can reach; the window test itself is the exact fp32 one.
+    w = (w_d, w_f, w_p); k is unused (the search does not depend on the seed
+    grid)."""
     wd, wf, wp = F32(w[0]), F32(w[1]), F32(w[2])
     cf = F32(cf)
     c32 = cen.astype(F32)
+    C = np.asarray(C, F32)
     n = len(val)
     best_d = np.full(n, np.inf, F32)
-    best_i = np.full(n, np.iinfo(np.int64).max, np.int64)
-    scx = seed_cell(pos[:, 0], C[0], k[0])
-    scy = seed_cell(pos[:, 1], C[1], k[1])
-    scz = seed_cell(pos[:, 2], C[2], k[2])
-    sct = seed_cell(tt.astype(F32), C[3], k[3])
+    best_i = np.full(n, -1, np.int64)
     ts = tt.astype(F32)
     wv = np.where(typ == 0, wf, wp).astype(F32)
-    for ot in (-1, 0, 1):
-        for oz in (-1, 0, 1):
-            for oy in (-1, 0, 1):
-                for ox in (-1, 0, 1):
-                    cx, cy, cz, ct = scx + ox, scy + oy, scz + oz, sct + ot
-                    ok = ((cx >= 0) & (cx < k[0]) & (cy >= 0) & (cy < k[1]) &
-                          (cz >= 0) & (cz < k[2]) & (ct >= 0) & (ct < k[3]))
-                    cid = np.where(ok, centre_id(cx, cy, cz, ct, k), 0)
-                    cc = c32[cid]
-                    dx = (pos[:, 0] - cc[:, 0]).astype(F32)
-                    dy = (pos[:, 1] - cc[:, 1]).astype(F32)
-                    dz = (pos[:, 2] - cc[:, 2]).astype(F32)
-                    dt = (ts - cc[:, 3]).astype(F32)
-                    inwin = (ok & (np.abs(dx) <= C[0]) & (np.abs(dy) <= C[1]) &
-                             (np.abs(dz) <= C[2]) & (np.abs(dt) <= C[3]))
-                    vc = np.where(typ == 0, cc[:, 5], cc[:, 4]).astype(F32)
-                    ctd = (cf * dt).astype(F32)
-                    sq = (((dx * dx + dy * dy).astype(F32) + dz * dz).astype(F32) + ctd * ctd).astype(F32)
-                    S = np.sqrt(sq).astype(F32)
-                    D = (wv * np.abs((val - vc).astype(F32)) + wd * S).astype(F32)
-                    better = inwin & ((D < best_d) | ((D == best_d) & (cid < best_i)))
-                    best_d = np.where(better, D, best_d)
-                    best_i = np.where(better, cid, best_i)
-    found = best_i != np.iinfo(np.int64).max
-    out = np.where(found, best_i, lab)
-    valid = lab >= 0
-    return np.where(valid, out, -1)
+    live = lab >= 0
+    order = np.argsort(np.where(live, pos[:, 0], np.inf).astype(np.float64), kind="stable")
+    xs = np.where(live, pos[:, 0], np.inf).astype(np.float64)[order]
+    for i in range(len(cen)):
+        cc = c32[i]
+        # every sample with |fl(x - c_x)| <= C_x lies within C_x (1 + 2^-23)
+        # of c_x, so this slab holds them all; the exact test follows
+        r = float(C[0]) * (1.0 + 2.0 ** -20) + 2.0 ** -20 * abs(float(cc[0]))
+        a = np.searchsorted(xs, float(cc[0]) - r, side="left")
+        b = np.searchsorted(xs, float(cc[0]) + r, side="right")
+        if a >= b:
+            continue
+        idx = order[a:b]
+        # the window test on y, z, t first (the same fp32 differences), then
+        # the distances of the samples inside
+        idx = idx[(np.abs((pos[idx, 1] - cc[1]).astype(F32)) <= C[1]) &
+                  (np.abs((pos[idx, 2] - cc[2]).astype(F32)) <= C[2]) &
+                  (np.abs((ts[idx] - cc[3]).astype(F32)) <= C[3])]
+        dx, dy, dz, dt, D = _distance(pos[idx], ts[idx], val[idx], typ[idx], cc, wv[idx], wd, cf)
+        inwin = ((np.abs(dx) <= C[0]) & (np.abs(dy) <= C[1]) & (np.abs(dz) <= C[2]) &
+                 (np.abs(dt) <= C[3]))
+        better = inwin & (D < best_d[idx])
+        sel = idx[better]
+        best_d[sel] = D[better]
+        best_i[sel] = i
+    out = np.where(best_i >= 0, best_i, lab)
+    return np.where(live, out, -1)
+
+
+def assign_brute(pos, tt, val, typ, lab, cen, C, w, cf, chunk=256):
+    """The same pass sample by sample: every sample against every centre
+    (brute force over K, numpy argmin takes the lowest id among equal D).
+    An independent formulation of `assign`, used to pin it and to check
+    sampled labels at sizes where `assign` would take long."""
+    wd, wf, wp = F32(w[0]), F32(w[1]), F32(w[2])
+    cf = F32(cf)
+    c32 = cen.astype(F32)
+    C = np.asarray(C, F32)
+    out = np.array(lab, np.int64, copy=True)
+    ts = tt.astype(F32)
+    for s0 in range(0, len(val), chunk):
+        sl = slice(s0, min(len(val), s0 + chunk))
+        p = pos[sl].astype(F32)[:, None, :]
+        d = (p - c32[None, :, :3]).astype(F32)
+        dt = (ts[sl][:, None] - c32[None, :, 3]).astype(F32)
+        inwin = (np.all(np.abs(d) <= C[None, None, :3], axis=2) & (np.abs(dt) <= C[3]))
+        vc = np.where((typ[sl] == 0)[:, None], c32[None, :, 5], c32[None, :, 4]).astype(F32)
+        wv = np.where(typ[sl] == 0, wf, wp).astype(F32)[:, None]
+        ctd = (cf * dt).astype(F32)
+        sq = (((d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]).astype(F32) + d[..., 2] * d[..., 2]).astype(F32)
+              + ctd * ctd).astype(F32)
+        D = (wv * np.abs((val[sl][:, None] - vc).astype(F32)) + wd * np.sqrt(sq).astype(F32)).astype(F32)
+        D = np.where(inwin, D, np.inf).astype(F32)
+        j = np.argmin(D, axis=1)
+        has = inwin.any(axis=1)
+        out[sl] = np.where(has & (out[sl] >= 0), j, out[sl])
+    return out
 
 
 def converged(new, old, eps):

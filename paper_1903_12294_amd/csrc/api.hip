@@ -188,7 +188,7 @@ struct mf4d_ctx {
     long long* scnt = nullptr;
     uint32_t* scounters = nullptr;
     uint32_t* h_scounters = nullptr;
-    uint32_t* sslab = nullptr;  // 8 x 4096 slab bounds (k_d <= 4096)
+    uint32_t* sslab = nullptr;  // 8 x 4096 slab bounds, then 8 x 4096 reach ranges (k_d <= 4096)
     unsigned long long* slsum = nullptr;  // [K][8] sums of the last update
     // cluster merging (Section 3.3), sized by K
     char* mbuf = nullptr;
@@ -1419,7 +1419,7 @@ int mf4d_slic_set_params(mf4d_ctx* c, const int* k4, float w_d, float w_f, float
         if (!rc) rc = dev_alloc(&c->scnt, (size_t)K * 2);
         if (!rc) rc = dev_alloc(&c->slsum, (size_t)K * kSlicAcc);
         if (!rc && !c->scounters) rc = dev_alloc(&c->scounters, (size_t)kSlicCounters);
-        if (!rc && !c->sslab) rc = dev_alloc(&c->sslab, (size_t)8 * 4096);
+        if (!rc && !c->sslab) rc = dev_alloc(&c->sslab, (size_t)16 * 4096);
         if (!rc && !c->h_scounters &&
             hipHostMalloc((void**)&c->h_scounters, kSlicCounters * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess)
             rc = fail(MF4D_ERR_OOM, "pinned counters");
@@ -1499,6 +1499,11 @@ int mf4d_slic_run(mf4d_ctx* c, int* iterations) {
     s.cnt = c->scnt;
     s.counters = c->scounters;
     s.slab = c->sslab;
+    s.reach = reinterpret_cast<int*>(c->sslab + 8 * 4096);
+    // debug switch: MF4D_SLIC_MASK_SLABS = 0 sends every sample through the
+    // general candidate loop (the tests compare both paths)
+    s.mask_slabs = 32;
+    if (const char* e = getenv("MF4D_SLIC_MASK_SLABS")) s.mask_slabs = std::min(32, std::max(0, atoi(e)));
     s.lsum = c->slsum;
     s.kmax = std::max(std::max(c->sk[0], c->sk[1]), std::max(c->sk[2], c->sk[3]));
     hipStream_t st = c->stream;

@@ -39,6 +39,12 @@ struct DevS {
     // the least and greatest centre coordinate, as order-preserving keys,
     // at [(0 * 4 + d) * kmax + i] (least) and [(1 * 4 + d) * kmax + i].
     uint32_t* slab;
+    // Per axis d and seed cell j: the least and greatest slab index whose
+    // centres can reach a sample of cell j, at [(d * kmax + j) * 2] and + 1
+    // (empty: least > greatest).
+    int* reach;
+    int mask_slabs;      // widest reach range searched through bit masks (0..32); wider ranges
+                         // take the general loop
     int kmax;            // max(k[0..3])
     uint32_t* counters;  // SlicCounter
     unsigned long long* lsum;  // [K][kSlicAcc]: the sums of the last update (for the features)

@@ -56,28 +56,68 @@ __device__ __forceinline__ float key_float(uint32_t k) {
     return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
 }
 
-// The slabs c0 - 1 .. c0 + 1 of axis d (inside the grid) that can hold a
-// centre within C of p, as bits 0..2 for offsets -1, 0, +1.  Rounding of
-// p - c is monotone in c, so a centre of the slab that passes the window
-// test passes this one too: no candidate is lost.
-__device__ __forceinline__ unsigned slab_mask(const DevS& s, int d, int c0, float p) {
-    unsigned m = 0;
-    for (int o = -1; o <= 1; ++o) {
-        const int i = c0 + o;
-        if (i < 0 || i >= s.k[d]) continue;
-        const float lo = key_float(s.slab[(0 * 4 + d) * s.kmax + i]);
-        const float hi = key_float(s.slab[(1 * 4 + d) * s.kmax + i]);
-        if (__fsub_rn(p, hi) <= s.C[d] && __fsub_rn(p, lo) >= -s.C[d]) m |= 1u << (o + 1);
+// Candidate search.  A centre's window holds a sample when |p_d - c_d| <=
+// C_d on every axis (Section 3.2.2).  A centre may drift any distance from
+// its seed cell, so no fixed neighbourhood of seed cells is assumed: after
+// each update, per axis d, every slab i (the centres with cell index i on
+// axis d) records the least and greatest coordinate of its centres, and every
+// seed cell j the range reach[d][j] of slabs whose [least - C, greatest + C]
+// meets cell j.  A sample of cell j then tests exactly those slabs.  Rounding
+// of p - c is monotone in c, so a centre that passes the window test lies in
+// a slab that passes the slab test: no candidate is lost.
+
+__device__ __forceinline__ bool slab_holds(const DevS& s, int d, int i, float p) {
+    const float lo = key_float(s.slab[(0 * 4 + d) * s.kmax + i]);
+    const float hi = key_float(s.slab[(1 * 4 + d) * s.kmax + i]);
+    return __fsub_rn(p, hi) <= s.C[d] && __fsub_rn(p, lo) >= -s.C[d];
+}
+
+// The slabs of axis d that can hold a centre within C of p (seed cell c), as
+// bits i - base.  A reach range of more than s.mask_slabs (<= 32) slabs
+// (centres drifted by many cells) sets `wide`: the caller then takes
+// assign_wide.
+__device__ __forceinline__ unsigned axis_mask(const DevS& s, int d, int c, float p, int& base, bool& wide) {
+    const int lo = s.reach[(d * s.kmax + c) * 2], hi = s.reach[(d * s.kmax + c) * 2 + 1];
+    base = lo;
+    if (hi < lo) return 0u;
+    if (hi - lo >= s.mask_slabs) {
+        wide = true;
+        return 0u;
     }
+    unsigned m = 0;
+    for (int i = lo; i <= hi; ++i)
+        if (slab_holds(s, d, i, p)) m |= 1u << (i - lo);
     return m;
 }
 
-// Centre with the smallest distance among those seeded in the 3^4 cells
-// around the sample's seed cell (cx0 .. ct0) whose window holds the sample;
-// ties go to the lowest id; none: `prev`.  Only the slabs in the masks mx ..
-// mt (slab_mask) are visited: the others hold no centre near enough.
+// Rate centre id for the sample if its window holds it; keep the smallest D,
+// ties to the lowest id.
+__device__ __forceinline__ void consider(const DevS& s, int id, float px, float py, float pz, float pt, float v,
+                                         bool field, float wv, float& best_d, int& best) {
+    const float4 c = reinterpret_cast<const float4*>(s.cen32)[2 * id];
+    const float2 cv = reinterpret_cast<const float2*>(s.cen32)[4 * id + 2];
+    const float dx = __fsub_rn(px, c.x), dy = __fsub_rn(py, c.y);
+    const float dz = __fsub_rn(pz, c.z), dt = __fsub_rn(pt, c.w);
+    if (!(fabsf(dx) <= s.C[0] && fabsf(dy) <= s.C[1] && fabsf(dz) <= s.C[2] && fabsf(dt) <= s.C[3])) return;
+    const float vc = field ? cv.y : cv.x;
+    const float A = __fmul_rn(wv, fabsf(__fsub_rn(v, vc)));
+    // D = A + (w_d S) rounded is >= A: a value term above the best distance
+    // cannot win (nor tie), so skip the rest
+    if (A > best_d) return;
+    const float ctd = __fmul_rn(s.cf, dt);
+    const float sq = __fadd_rn(__fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz)),
+                               __fmul_rn(ctd, ctd));
+    const float D = __fadd_rn(A, __fmul_rn(s.wd, __fsqrt_rn(sq)));
+    if (D < best_d || (D == best_d && id < best)) {
+        best_d = D;
+        best = id;
+    }
+}
+
+// Centre with the smallest distance among the centres of the slabs in the
+// masks (bit b of mx: slab bx0 + b on x, and so on); none: `prev`.
 __device__ int assign_cands(const DevS& s, float px, float py, float pz, float pt, float v, bool field,
-                            int prev, int cx0, int cy0, int cz0, int ct0, unsigned mx, unsigned my,
+                            int prev, int bx0, int by0, int bz0, int bt0, unsigned mx, unsigned my,
                             unsigned mz, unsigned mt) {
     const float wv = field ? s.wf : s.wp;
     float best_d = INFINITY;
@@ -86,41 +126,54 @@ __device__ int assign_cands(const DevS& s, float px, float py, float pz, float p
         for (unsigned bz = mz; bz; bz &= bz - 1)
             for (unsigned by = my; by; by &= by - 1)
                 for (unsigned bx = mx; bx; bx &= bx - 1) {
-                    const int ct = ct0 + __builtin_ctz(bt) - 1, cz = cz0 + __builtin_ctz(bz) - 1;
-                    const int cy = cy0 + __builtin_ctz(by) - 1, cx = cx0 + __builtin_ctz(bx) - 1;
-                    const int id = ((ct * s.k[2] + cz) * s.k[1] + cy) * s.k[0] + cx;
-                    const float4 c = reinterpret_cast<const float4*>(s.cen32)[2 * id];
-                    const float2 cv = reinterpret_cast<const float2*>(s.cen32)[4 * id + 2];
-                    const float dx = __fsub_rn(px, c.x), dy = __fsub_rn(py, c.y);
-                    const float dz = __fsub_rn(pz, c.z), dt = __fsub_rn(pt, c.w);
-                    if (!(fabsf(dx) <= s.C[0] && fabsf(dy) <= s.C[1] && fabsf(dz) <= s.C[2] &&
-                          fabsf(dt) <= s.C[3]))
-                        continue;
-                    const float vc = field ? cv.y : cv.x;
-                    const float A = __fmul_rn(wv, fabsf(__fsub_rn(v, vc)));
-                    // D = A + (w_d S) rounded is >= A: a value term above the
-                    // best distance cannot win (nor tie), so skip the rest
-                    if (A > best_d) continue;
-                    const float ctd = __fmul_rn(s.cf, dt);
-                    const float sq = __fadd_rn(
-                        __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz)),
-                        __fmul_rn(ctd, ctd));
-                    const float S = __fsqrt_rn(sq);
-                    const float D = __fadd_rn(A, __fmul_rn(s.wd, S));
-                    if (D < best_d || (D == best_d && id < best)) {
-                        best_d = D;
-                        best = id;
-                    }
+                    const int ct = bt0 + __builtin_ctz(bt), cz = bz0 + __builtin_ctz(bz);
+                    const int cy = by0 + __builtin_ctz(by), cx = bx0 + __builtin_ctz(bx);
+                    consider(s, ((ct * s.k[2] + cz) * s.k[1] + cy) * s.k[0] + cx, px, py, pz, pt, v, field, wv,
+                             best_d, best);
                 }
+    return best == 0x7FFFFFFF ? prev : best;
+}
+
+// The same search over reach ranges of any width (the slab test inline).
+__device__ __noinline__ int assign_wide(const DevS& s, float px, float py, float pz, float pt, float v,
+                                        bool field, int prev) {
+    const float p[4] = {px, py, pz, pt};
+    int lo[4], hi[4];
+    for (int d = 0; d < 4; ++d) {
+        const int c = seed_cell(p[d], s.C[d], s.k[d]);
+        lo[d] = s.reach[(d * s.kmax + c) * 2];
+        hi[d] = s.reach[(d * s.kmax + c) * 2 + 1];
+    }
+    const float wv = field ? s.wf : s.wp;
+    float best_d = INFINITY;
+    int best = 0x7FFFFFFF;
+    for (int ct = lo[3]; ct <= hi[3]; ++ct) {
+        if (!slab_holds(s, 3, ct, pt)) continue;
+        for (int cz = lo[2]; cz <= hi[2]; ++cz) {
+            if (!slab_holds(s, 2, cz, pz)) continue;
+            for (int cy = lo[1]; cy <= hi[1]; ++cy) {
+                if (!slab_holds(s, 1, cy, py)) continue;
+                for (int cx = lo[0]; cx <= hi[0]; ++cx) {
+                    if (!slab_holds(s, 0, cx, px)) continue;
+                    consider(s, ((ct * s.k[2] + cz) * s.k[1] + cy) * s.k[0] + cx, px, py, pz, pt, v, field, wv,
+                             best_d, best);
+                }
+            }
+        }
+    }
     return best == 0x7FFFFFFF ? prev : best;
 }
 
 __device__ __forceinline__ int assign_one(const DevS& s, float px, float py, float pz, float pt, float v,
                                           bool field, int prev) {
-    const int cx0 = seed_cell(px, s.C[0], s.k[0]), cy0 = seed_cell(py, s.C[1], s.k[1]);
-    const int cz0 = seed_cell(pz, s.C[2], s.k[2]), ct0 = seed_cell(pt, s.C[3], s.k[3]);
-    return assign_cands(s, px, py, pz, pt, v, field, prev, cx0, cy0, cz0, ct0, slab_mask(s, 0, cx0, px),
-                        slab_mask(s, 1, cy0, py), slab_mask(s, 2, cz0, pz), slab_mask(s, 3, ct0, pt));
+    int b[4];
+    bool wide = false;
+    const unsigned mx = axis_mask(s, 0, seed_cell(px, s.C[0], s.k[0]), px, b[0], wide);
+    const unsigned my = axis_mask(s, 1, seed_cell(py, s.C[1], s.k[1]), py, b[1], wide);
+    const unsigned mz = axis_mask(s, 2, seed_cell(pz, s.C[2], s.k[2]), pz, b[2], wide);
+    const unsigned mt = axis_mask(s, 3, seed_cell(pt, s.C[3], s.k[3]), pt, b[3], wide);
+    if (wide) return assign_wide(s, px, py, pz, pt, v, field, prev);
+    return assign_cands(s, px, py, pz, pt, v, field, prev, b[0], b[1], b[2], b[3], mx, my, mz, mt);
 }
 
 // Block-local sums keyed by centre id (open addressing).  A sample whose
@@ -214,8 +267,10 @@ __global__ __launch_bounds__(kBlock) void k_slic_field(DevS s, int assign) {
     }
     float py = 0.f, pz = 0.f, pt = 0.f;
     int cy0 = 0, cz0 = 0, ct0 = 0;
+    int by0 = 0, bz0 = 0, bt0 = 0;
     unsigned my = 0, mz = 0, mt = 0;
-    bool row = false;  // row values current
+    bool row = false;       // row values current
+    bool row_wide = false;  // a reach range of the row wider than 32 slabs
     for (int j = 0; j < kPer; ++j) {
         const uint32_t i = i0 + j;
         if (i >= V) break;
@@ -244,9 +299,10 @@ __global__ __launch_bounds__(kBlock) void k_slic_field(DevS s, int assign) {
             cz0 = seed_cell(pz, s.C[2], s.k[2]);
             ct0 = seed_cell(pt, s.C[3], s.k[3]);
             if (assign) {
-                my = slab_mask(s, 1, cy0, py);
-                mz = slab_mask(s, 2, cz0, pz);
-                mt = slab_mask(s, 3, ct0, pt);
+                row_wide = false;
+                my = axis_mask(s, 1, cy0, py, by0, row_wide);
+                mz = axis_mask(s, 2, cz0, pz, bz0, row_wide);
+                mt = axis_mask(s, 3, ct0, pt, bt0, row_wide);
             }
             row = true;
         }
@@ -254,8 +310,12 @@ __global__ __launch_bounds__(kBlock) void k_slic_field(DevS s, int assign) {
         const int cx0 = seed_cell(px, s.C[0], s.k[0]);
         int id;
         if (assign) {
-            id = assign_cands(s, px, py, pz, pt, v, true, s.labels[i], cx0, cy0, cz0, ct0,
-                              slab_mask(s, 0, cx0, px), my, mz, mt);
+            int bx0;
+            bool wide = row_wide;
+            const unsigned mx = axis_mask(s, 0, cx0, px, bx0, wide);
+            id = wide ? assign_wide(s, px, py, pz, pt, v, true, s.labels[i])
+                      : assign_cands(s, px, py, pz, pt, v, true, s.labels[i], bx0, by0, bz0, bt0, mx, my, mz,
+                                     mt);
         } else {
             id = ((ct0 * s.k[2] + cz0) * s.k[1] + cy0) * s.k[0] + cx0;
         }
@@ -922,12 +982,40 @@ void launch_slic_assign(const DevS& s, hipStream_t st) {
 
 __global__ void k_slic_slab_reset(DevS s) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < 8 * s.kmax) s.slab[i] = i < 4 * s.kmax ? 0xFFFFFFFFu : 0u;
+    if (i < 8 * s.kmax) {
+        s.slab[i] = i < 4 * s.kmax ? 0xFFFFFFFFu : 0u;
+        s.reach[i] = (i & 1) ? -1 : 0x7FFFFFFF;
+    }
+}
+
+// Slab i of axis d (bounds lo, hi from the update) can hold a centre within
+// C of any p in [lo - C, hi + C], widened by C 2^-20 for the rounding of the
+// window test's difference.  Those p fall in the seed cells from floor of
+// the lower end / C to floor of the upper end / C (clamped like seed_cell),
+// widened by 10^-3 of a cell for the rounding of the division (below 2.5e-4
+// of a cell wherever the cell index is below 4096).  Each of those cells
+// takes i into its reach range.
+__global__ void k_slic_reach(DevS s) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int d = g / s.kmax, i = g - d * s.kmax;
+    if (d >= 4 || i >= s.k[d]) return;
+    const double C = s.C[d];
+    const double lo = key_float(s.slab[(0 * 4 + d) * s.kmax + i]);
+    const double hi = key_float(s.slab[(1 * 4 + d) * s.kmax + i]);
+    const double m = C * (1.0 + 0x1p-20);
+    const double kd = s.k[d] - 1;
+    const int j0 = (int)fmin(fmax(floor((lo - m) / C - 1e-3), 0.0), kd);
+    const int j1 = (int)fmin(fmax(floor((hi + m) / C + 1e-3), 0.0), kd);
+    for (int j = j0; j <= j1; ++j) {
+        atomicMin(&s.reach[(d * s.kmax + j) * 2], i);
+        atomicMax(&s.reach[(d * s.kmax + j) * 2 + 1], i);
+    }
 }
 
 void launch_slic_update(const DevS& s, int seed, hipStream_t st) {
     hipLaunchKernelGGL(k_slic_slab_reset, dim3(blocks_for((uint64_t)8 * s.kmax, 256)), dim3(256), 0, st, s);
     hipLaunchKernelGGL(k_slic_update, dim3(blocks_for((uint64_t)s.K, 256)), dim3(256), 0, st, s, seed);
+    hipLaunchKernelGGL(k_slic_reach, dim3(blocks_for((uint64_t)4 * s.kmax, 256)), dim3(256), 0, st, s);
 }
 
 int launch_slic_merge(const DevS& s, const DevM& m, hipStream_t st) {

@@ -213,3 +213,31 @@ def test_merge_32cube_workload():
     inst = synth.make_config(1)
     _assert_merge("merge-32^3x8", inst["field"], inst["xyz"], inst["attr"], (4, 4, 4, 2), w=(1.0, 8.0, 8.0),
                   cf=2.0, eps=1e-3, max_iter=8, eps_m=(0.02, 0.1))
+
+
+@pytest.mark.parametrize("mask_slabs", ["32", "0"])
+def test_drifting_centres_exact_window_search(mask_slabs, monkeypatch):
+    """Section 3.2.2: every centre searches its own 2C window, wherever it has
+    drifted.  On the swarm inputs the centres wander about a cell from their
+    seeds and many samples take a centre seeded two or more cells away; the
+    GPU's slab-range search must find exactly the oracle's centres.
+    mask_slabs = 0 sends every sample through the general candidate loop."""
+    from tests.slic_cases import SWARM_CF, SWARM_K, SWARM_W, swarm_case
+    monkeypatch.setenv("MF4D_SLIC_MASK_SLABS", mask_slabs)
+    field, xyz, attr = swarm_case(0)
+    T, Z, Y, X = field.shape
+    it = _assert_parity(f"drift-mask{mask_slabs}", field, xyz, attr, SWARM_K, w=SWARM_W, cf=SWARM_CF, eps=0.0,
+                        max_iter=6)
+    assert it == 6
+    _, _, cen, _, _ = oslic.slic(field, xyz, attr, SWARM_K, SWARM_W, SWARM_CF, 0.0, 6)
+    C = oslic.grid_interval((X, Y, Z, T), SWARM_K).astype(np.float64)
+    seeds = oslic.seed_centres(oslic.grid_interval((X, Y, Z, T), SWARM_K), SWARM_K)
+    assert np.max(np.abs(cen[:, :4] - seeds[:, :4]) / C) > 0.5
+
+
+def test_general_candidate_loop_matches_on_ragged_case(monkeypatch):
+    """The general loop (every sample) on a ragged case with points outside
+    the grid and non-finite samples."""
+    monkeypatch.setenv("MF4D_SLIC_MASK_SLABS", "0")
+    field, xyz, attr = _case(3, 6, 8, 8, 8, 200, spread=1.4, nan=True)
+    _assert_parity("general-loop", field, xyz, attr, (2, 2, 2, 3))

@@ -251,3 +251,66 @@ def test_feature_stats_match_numpy_per_feature():
         assert st[F, 6] == xs.min() and st[F, 7] == xs.max()
         assert st[F, 12] == ts.min() and st[F, 13] == ts.max()
     assert st[:, 0].sum() == field.size and st[:, 1].sum() == attr.size
+
+
+def test_every_centre_is_searched_hand_placed():
+    """Section 3.2.2: a centre searches the 2C window around itself wherever
+    it has moved.  Four centres along x (C_x = 2); centre 3, seeded in the
+    last cell, has drifted into the first cells, where a sample of cell 0
+    lies within C_x of it.  Its value matches the sample's, so with a large
+    value weight it wins over the near centres 0 and 1 -- although its seed
+    cell is three cells from the sample's."""
+    C = (2.0, 8.0, 8.0, 8.0)
+    k = (4, 1, 1, 1)
+    cen = [[1.0, 4.0, 4.0, 4.0, 0.0, 0.0], [3.0, 4.0, 4.0, 4.0, 0.2, 0.0],
+           [5.0, 4.0, 4.0, 4.0, 0.3, 0.0], [2.5, 4.0, 4.0, 4.0, 0.9, 0.0]]
+    w = (0.1, 0.0, 10.0)
+    pts = [(1.5, 4.0, 4.0, 4), (1.5, 4.0, 4.0, 4), (6.9, 4.0, 4.0, 4)]
+    vals = [0.9, 0.0, 0.9]
+    # sample 3 lies 4.4 from centre 3: outside its window; centre 2 wins
+    assert _assign_oracle(pts, vals, cen, C, k, w, 1.0) == [3, 0, 2]
+    assert _assign_by_hand(pts, vals, cen, C, k, w, 1.0) == [3, 0, 2]
+    pos = np.asarray([p[:3] for p in pts], F32)
+    brute = S.assign_brute(pos, np.asarray([p[3] for p in pts], np.int64), np.asarray(vals, F32),
+                           np.ones(3, np.int64), np.zeros(3, np.int64), np.asarray(cen, np.float64),
+                           np.asarray(C, F32), w, 1.0)
+    assert brute.tolist() == [3, 0, 2]
+
+
+def test_drifting_centres_centre_search_equals_brute_force():
+    """k = (4, 4, 4, 2), six iterations on the swarm inputs: the centres
+    drift by more than half a cell (so that centres seeded two cells away
+    from a sample can hold it in their window), many samples take such a
+    centre, and at every iteration the centre-by-centre search equals the
+    sample-by-sample brute force over all centres."""
+    from tests.slic_cases import SWARM_CF, SWARM_K, SWARM_W, swarm_case
+    field, xyz, attr = swarm_case(0)
+    T, Z, Y, X = field.shape
+    k, w, cf = SWARM_K, SWARM_W, SWARM_CF
+    K = int(np.prod(k))
+    C = S.grid_interval((X, Y, Z, T), k)
+    pos, tt, val, typ, valid = S.samples(field, xyz, attr)
+    lab = S.initial_labels(pos, tt, valid, C, k)
+    seeds = S.seed_centres(C, k)
+    prev = seeds
+    cells = [S.seed_cell(pos[:, d], C[d], k[d]) for d in range(3)] + [S.seed_cell(tt.astype(F32), C[3], k[3])]
+    far_total = 0
+    max_drift = 0.0
+    for _ in range(6):
+        cen, _ = S.update_centres(pos, tt, val, typ, lab, prev, K)
+        max_drift = max(max_drift, float(np.max(np.abs(cen[:, :4] - seeds[:, :4]) / C.astype(np.float64))))
+        new = S.assign(pos, tt, val, typ, lab, cen, C, k, w, cf)
+        assert np.array_equal(new, S.assign_brute(pos, tt, val, typ, lab, cen, C, w, cf))
+        r = new.copy()
+        own = []
+        for d in range(3):
+            own.append(r % k[d])
+            r //= k[d]
+        own.append(r)
+        far = np.zeros(len(new), bool)
+        for d in range(4):
+            far |= np.abs(own[d] - cells[d]) > 1
+        far_total += int((far & (new >= 0)).sum())
+        lab, prev = new, cen
+    assert max_drift > 0.5
+    assert far_total > 100
