@@ -382,6 +382,21 @@ int mf4d_nn_backward(mf4d_net *net, const uint16_t *x, const uint8_t *y, int N, 
                      float pos_weight, float *grads, float *dx, float *loss, int where);
 int mf4d_nn_adam_step(mf4d_net *net, const float *grads, float lr, int where);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * logits as mf4d_nn_forward, from the same kernels, with the two hidden
+ * activations in a static per-GPU scratch array of 16 MiB instead of buffers
+ * the network allocates, so the call allocates and frees nothing.  At most
+ * 2^18 positions (N*D*H*W <= 262144).  Stream-ordered on the network's
+ * stream; returns without waiting.  Every call on one GPU shares that GPU's
+ * scratch, so calls that overlap on one GPU (another stream, another thread,
+ * another network on the same device) race and must be serialised by the
+ * caller.  Device pointers only.
+ * Errors: MF4D_ERR_ARG, MF4D_ERR_RANGE (more positions than the scratch
+ * holds), MF4D_ERR_UNSUPPORTED, MF4D_ERR_STATE, MF4D_ERR_HIP. */
+int mf4d_nn_forward_noalloc(mf4d_net *net, const uint16_t *x, int N, int D, int H, int W, float *logits,
+                            int where);
+
 /* Brick grid of the loaded field: dims4 = (T, Db, Hb, Wb). */
 int mf4d_brick_dims(mf4d_ctx *ctx, int *dims4);
 

@@ -148,6 +148,7 @@ SIGNATURES = {
     "mf4d_nn_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_float,
                                  c_void_p, c_void_p, c_void_p, c_int]),
     "mf4d_nn_adam_step": (c_int, [c_void_p, c_void_p, c_float, c_int]),
+    "mf4d_nn_forward_noalloc": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_void_p, c_int]),
 }
 
 

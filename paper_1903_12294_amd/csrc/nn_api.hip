@@ -5,6 +5,7 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -15,6 +16,7 @@ using namespace mf4d;
 struct mf4d_net {
     int device = 0;
     hipStream_t stream = nullptr;
+    uint16_t* noalloc = nullptr;  // this device's copy of `scratch` (device address)
     NetShapes sh{};
     float* params = nullptr;  // fp32 masters, reference layout
     float* grads = nullptr;
@@ -33,6 +35,16 @@ struct mf4d_net {
     float *part_loss = nullptr, *loss = nullptr;
     float* h_loss = nullptr;
 };
+
+// Scratch of the allocation-free forward (mf4d_nn_forward_noalloc): the two
+// hidden activations, bf16 [positions][16] each, for at most
+// kNoAllocPositions positions: 16 MiB per GPU, held until the process ends.
+// Every call on one GPU uses that GPU's copy, so calls that overlap on one
+// GPU race.  Host code never passes the array's name to a kernel (on the host
+// it is only a stand-in); it uses the device address that
+// hipGetSymbolAddress returns for the current device, kept per device.
+constexpr uint64_t kNoAllocPositions = 1ull << 18;
+static __device__ __align__(256) uint16_t scratch[2 * kNoAllocPositions * 16];
 
 namespace {
 
@@ -107,6 +119,29 @@ int ensure_acts(mf4d_net* n, uint64_t pos, uint32_t blocks) {
     return MF4D_OK;
 }
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint16_t* g_scratch[kMaxDevices] = {};
+
+// The device address of `scratch` on `device` (current), looked up once.
+int noalloc_scratch(int device, uint16_t** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices)
+        return nfail(MF4D_ERR_UNSUPPORTED, "device index %d not below %d", device, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return nfail(MF4D_ERR_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        }
+        g_scratch[device] = static_cast<uint16_t*>(ptr);
+    }
+    *out = g_scratch[device];
+    return MF4D_OK;
+}
+
 int check_dims(int N, int D, int H, int W) {
     if (N <= 0 || D <= 0 || H <= 0 || W <= 0) return nfail(MF4D_ERR_ARG, "dims must be positive");
     if ((uint64_t)N * D * H * W >= (1ull << 31)) return nfail(MF4D_ERR_UNSUPPORTED, "too many positions");
@@ -172,7 +207,8 @@ int mf4d_net_create(mf4d_net** out, int device, void* stream) {
     n->stream = (hipStream_t)stream;
     n->sh = net_shapes();
     const int P = n->sh.total;
-    int rc = nalloc(&n->params, P);
+    int rc = noalloc_scratch(device, &n->noalloc);
+    if (!rc) rc = nalloc(&n->params, P);
     if (!rc) rc = nalloc(&n->grads, P);
     if (!rc) rc = nalloc(&n->m, P);
     if (!rc) rc = nalloc(&n->v, P);
@@ -326,6 +362,28 @@ int mf4d_nn_backward(mf4d_net* n, const uint16_t* x, const uint8_t* y, int N, in
     NHIP(hipMemcpyAsync(n->h_loss, n->loss, sizeof(float), hipMemcpyDeviceToHost, n->stream));
     NHIP(hipStreamSynchronize(n->stream));
     if (loss) *loss = *n->h_loss;
+    return MF4D_OK;
+}
+
+int mf4d_nn_forward_noalloc(mf4d_net* n, const uint16_t* x, int N, int D, int H, int W, float* logits,
+                            int where) {
+    if (!n || !x || !logits) return nfail(MF4D_ERR_ARG, "NULL argument");
+    if (where != MF4D_DEVICE) return nfail(MF4D_ERR_ARG, "network tensors must be device pointers");
+    int rc = check_dims(N, D, H, W);
+    if (rc) return rc;
+    const uint64_t pos = (uint64_t)N * D * H * W;
+    if (pos > kNoAllocPositions)
+        return nfail(MF4D_ERR_RANGE, "%llu positions exceed the %llu of the static scratch",
+                     (unsigned long long)pos, (unsigned long long)kNoAllocPositions);
+    if (!n->noalloc) return nfail(MF4D_ERR_STATE, "no scratch address for device %d", n->device);
+    NHIP(hipSetDevice(n->device));
+    const size_t L = 27 * 256;
+    uint16_t* a1 = n->noalloc;
+    uint16_t* a2 = n->noalloc + pos * 16;
+    launch_conv16(N, D, H, W, x, n->wf, n->bias, 1, nullptr, a1, nullptr, n->stream);
+    launch_conv16(N, D, H, W, a1, n->wf + L, n->bias + 16, 1, nullptr, a2, nullptr, n->stream);
+    launch_conv16(N, D, H, W, a2, n->wf + 2 * L, n->bias + 32, 0, nullptr, nullptr, logits, n->stream);
+    NHIP(hipGetLastError());
     return MF4D_OK;
 }
 
