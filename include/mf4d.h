@@ -330,8 +330,9 @@ int mf4d_read_batched(mf4d_ctx *ctx, uint32_t *fdst, size_t fwords, uint32_t *pd
  * whether a brick-step will hold a member of the grown feature; the grower
  * uses it only to choose which candidate tiles to test before the rounds (the
  * rest are tested by the first sweep that reaches them), so the result never
- * depends on it.  Weights bf16 on the matrix cores with fp32 accumulation;
- * fp32 master parameters, Adam.  Parameter layout (fp32, 10833 values): per
+ * depends on it.  Weights bf16 on the matrix cores with fp32 accumulation
+ * (bf16 hidden activations for inference, fp32 ones for training); fp32
+ * master parameters, Adam.  Parameter layout (fp32, 10833 values): per
  * layer W [cout][cin][3][3][3] then b [cout]. */
 
 /* The network has no counterpart in the paper; its inputs summarise the
@@ -350,15 +351,18 @@ const char *mf4d_net_last_error(void);
 int mf4d_net_set_params(mf4d_net *net, const float *params, int where);
 int mf4d_net_get_params(mf4d_net *net, float *params, int where);
 
-/* Logits fp32 [N][D][H][W] of inputs x bf16 [N][D][H][W][16]; device
- * pointers only.  Errors: MF4D_ERR_ARG, MF4D_ERR_UNSUPPORTED (>= 2^31
- * positions). */
+/* Logits fp32 [N][D][H][W] of inputs x bf16 [N][D][H][W][16] (channels 0..7
+ * are the network's inputs, 8..15 are ignored) at inference precision: bf16
+ * hidden activations; device pointers only.  Errors: MF4D_ERR_ARG,
+ * MF4D_ERR_UNSUPPORTED (>= 2^31 positions). */
 int mf4d_net_forward(mf4d_net *net, const uint16_t *x, int N, int D, int H, int W, float *logits,
                      int where);
 
 /* Gradients (fp32, parameter layout, device) of the mean binary cross entropy
  * with positive weight `pos_weight` against labels y uint8 [N][D][H][W];
- * *loss receives the loss.  Device pointers only. */
+ * *loss receives the loss.  Training precision: fp32 hidden activations and
+ * layer gradients (operands split into bf16 pieces on the matrix cores).
+ * Device pointers only. */
 int mf4d_net_grad(mf4d_net *net, const uint16_t *x, const uint8_t *y, int N, int D, int H, int W,
                   float pos_weight, float *grads, float *loss, int where);
 

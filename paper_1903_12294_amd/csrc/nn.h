@@ -35,24 +35,30 @@ struct BrickDims {
 };
 
 constexpr int kLossBlocks = 256;
+// Packed B operands of one convolution: up to 14 instruction steps x 64 lanes,
+// 16 bytes (8 bf16) each.
+constexpr int kPackSlot = 14 * 64;
 
 const char* net_last_error();
 uint32_t nn_blocks(int N, int D, int H, int W);
-void launch_conv16(int N, int D, int H, int W, const uint16_t* x, const uint16_t* w,
-                   const float* bias, int relu, const uint16_t* mask, uint16_t* out_bf,
-                   float* out_f32, hipStream_t s);
-// The convolution without bias or activation, all 16 output channels as
-// fp32 [..][16] (the input gradient of the first layer).
-void launch_conv16_f32(int N, int D, int H, int W, const uint16_t* x, const uint16_t* w,
-                       float* out_f32, hipStream_t s);
-void launch_conv16_wgrad(int N, int D, int H, int W, const uint16_t* x, const uint16_t* dz,
-                         float* part_w, float* part_b, float* gw, float* gb, hipStream_t s);
-void launch_bce(const float* logits, const uint8_t* y, uint64_t n, float pw, uint16_t* dz,
-                float* part_loss, float* loss, hipStream_t s);
-void launch_prep_weights(const float* params, const NetShapes& sh, uint16_t* wf, uint16_t* wb,
-                         float* bias, hipStream_t s);
-void launch_gather_grads(const float* gw, const float* gb, const NetShapes& sh, int layer,
-                         float* grads, hipStream_t s);
+// Inference: bf16 activations a1, a2 ([pos][16]), logits fp32 [pos].  x: bf16
+// [pos][16] (channels 0..7 read).  wpk: [6][kPackSlot] packed weights.
+void launch_infer(int N, int D, int H, int W, const uint16_t* x, const uint4* wpk, const float* bias,
+                  uint16_t* a1, uint16_t* a2, float* logits, hipStream_t s);
+// Training forward: fp32 activations a1, a2 ([pos][16]) and logits.
+void launch_train_forward(int N, int D, int H, int W, const uint16_t* x, const uint4* wpk, const float* bias,
+                          float* a1, float* a2, float* logits, hipStream_t s);
+// Loss (mean BCE, positive weight pw, into *loss on the device), layer
+// gradients dz1..dz3 (fp32 [pos][16]), every parameter's gradient into grads
+// (reference layout), and with dx non-null the input gradient (fp32
+// [pos][16]).  part_w / part_b: per-block partials (nn_blocks of them).
+void launch_train_backward(int N, int D, int H, int W, const uint16_t* x, const uint4* wpk, const float* logits,
+                           const uint8_t* y, float pw, const float* a1, const float* a2, float* dz1, float* dz2,
+                           float* dz3, float* dx, float* part_w, float* part_b, float* gw, float* gb,
+                           float* part_loss, float* loss, const NetShapes& sh, float* grads, hipStream_t s);
+// fp32 parameters -> packed bf16 operands (forward and input gradient of each
+// layer) and biases [3][16].
+void launch_pack_weights(const float* params, const NetShapes& sh, uint4* wpk, float* bias, hipStream_t s);
 void launch_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1, float b2,
                  float eps, int step, hipStream_t s);
 void launch_brick_stats(const Geom& g, const PGeom& pg, const BrickDims& bd, const float* field,

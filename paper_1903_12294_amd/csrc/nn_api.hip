@@ -22,15 +22,18 @@ struct mf4d_net {
     float* grads = nullptr;
     float* m = nullptr;
     float* v = nullptr;
-    uint16_t* wf = nullptr;   // bf16 [3][27][16][16] forward weights
-    uint16_t* wb = nullptr;   // bf16 [3][27][16][16] input-gradient weights
+    uint4* wpk = nullptr;     // packed bf16 B operands: [6][kPackSlot] (forward and input
+                              // gradient of each layer)
     float* bias = nullptr;    // fp32 [3][16]
     int step = 0;
-    // activation buffers (grown on demand)
+    // activation buffers (grown on demand): inference (bf16 activations)
     uint64_t cap_pos = 0;
-    uint32_t cap_blocks = 0;
-    uint16_t *a1 = nullptr, *a2 = nullptr, *dz1 = nullptr, *dz2 = nullptr, *dz3 = nullptr;
+    uint16_t *a1 = nullptr, *a2 = nullptr;
     float* logits = nullptr;
+    // training (fp32 activations and layer gradients)
+    uint64_t cap_tpos = 0;
+    uint32_t cap_blocks = 0;
+    float *t1 = nullptr, *t2 = nullptr, *dz1 = nullptr, *dz2 = nullptr, *dz3 = nullptr, *tlogits = nullptr;
     float *part_w = nullptr, *part_b = nullptr, *gw = nullptr, *gb = nullptr;
     float *part_loss = nullptr, *loss = nullptr;
     float* h_loss = nullptr;
@@ -86,35 +89,56 @@ void nfree(T*& p) {
     p = nullptr;
 }
 
-void free_acts(mf4d_net* n) {
+void free_infer(mf4d_net* n) {
     nfree(n->a1);
     nfree(n->a2);
+    nfree(n->logits);
+    n->cap_pos = 0;
+}
+
+void free_train(mf4d_net* n) {
+    nfree(n->t1);
+    nfree(n->t2);
     nfree(n->dz1);
     nfree(n->dz2);
     nfree(n->dz3);
-    nfree(n->logits);
+    nfree(n->tlogits);
     nfree(n->part_w);
     nfree(n->part_b);
-    n->cap_pos = 0;
+    n->cap_tpos = 0;
     n->cap_blocks = 0;
 }
 
-int ensure_acts(mf4d_net* n, uint64_t pos, uint32_t blocks) {
-    if (pos <= n->cap_pos && blocks <= n->cap_blocks) return MF4D_OK;
-    free_acts(n);
+int ensure_infer(mf4d_net* n, uint64_t pos) {
+    if (pos <= n->cap_pos) return MF4D_OK;
+    free_infer(n);
     int rc = nalloc(&n->a1, pos * 16);
     if (!rc) rc = nalloc(&n->a2, pos * 16);
-    if (!rc) rc = nalloc(&n->dz1, pos * 16);
-    if (!rc) rc = nalloc(&n->dz2, pos * 16);
-    if (!rc) rc = nalloc(&n->dz3, pos * 16);
     if (!rc) rc = nalloc(&n->logits, pos);
-    if (!rc) rc = nalloc(&n->part_w, (size_t)blocks * 27 * 256);
-    if (!rc) rc = nalloc(&n->part_b, (size_t)blocks * 16);
     if (rc) {
-        free_acts(n);
+        free_infer(n);
         return rc;
     }
     n->cap_pos = pos;
+    return MF4D_OK;
+}
+
+int ensure_train(mf4d_net* n, uint64_t pos, uint32_t blocks) {
+    if (pos <= n->cap_tpos && blocks <= n->cap_blocks) return MF4D_OK;
+    free_train(n);
+    int rc = nalloc(&n->t1, pos * 16);
+    if (!rc) rc = nalloc(&n->t2, pos * 16);
+    if (!rc) rc = nalloc(&n->dz1, pos * 16);
+    if (!rc) rc = nalloc(&n->dz2, pos * 16);
+    if (!rc) rc = nalloc(&n->dz3, pos * 16);
+    if (!rc) rc = nalloc(&n->tlogits, pos);
+    if (!rc) rc = nalloc(&n->part_w, (size_t)blocks * 27 * 256);
+    if (!rc) rc = nalloc(&n->part_b, (size_t)blocks * 16);
+    if (rc) {
+        free_train(n);
+        return rc;
+    }
+    n->cap_tpos = pos;
     n->cap_blocks = blocks;
     return MF4D_OK;
 }
@@ -148,28 +172,12 @@ int check_dims(int N, int D, int H, int W) {
     return MF4D_OK;
 }
 
-void forward(mf4d_net* n, const uint16_t* x, int N, int D, int H, int W) {
-    const size_t L = 27 * 256;
-    launch_conv16(N, D, H, W, x, n->wf, n->bias, 1, nullptr, n->a1, nullptr, n->stream);
-    launch_conv16(N, D, H, W, n->a1, n->wf + L, n->bias + 16, 1, nullptr, n->a2, nullptr, n->stream);
-    launch_conv16(N, D, H, W, n->a2, n->wf + 2 * L, n->bias + 32, 0, nullptr, nullptr, n->logits,
-                  n->stream);
-}
-
-// Loss and gradients of every parameter (into n->grads), from device x, y.
-void backward(mf4d_net* n, const uint16_t* x, const uint8_t* y, int N, int D, int H, int W, float pw) {
-    const size_t L = 27 * 256;
-    const uint64_t pos = (uint64_t)N * D * H * W;
-    hipStream_t s = n->stream;
-    launch_bce(n->logits, y, pos, pw, n->dz3, n->part_loss, n->loss, s);
-    launch_conv16_wgrad(N, D, H, W, n->a2, n->dz3, n->part_w, n->part_b, n->gw, n->gb, s);
-    launch_gather_grads(n->gw, n->gb, n->sh, 2, n->grads, s);
-    launch_conv16(N, D, H, W, n->dz3, n->wb + 2 * L, nullptr, 0, n->a2, n->dz2, nullptr, s);
-    launch_conv16_wgrad(N, D, H, W, n->a1, n->dz2, n->part_w, n->part_b, n->gw, n->gb, s);
-    launch_gather_grads(n->gw, n->gb, n->sh, 1, n->grads, s);
-    launch_conv16(N, D, H, W, n->dz2, n->wb + L, nullptr, 0, n->a1, n->dz1, nullptr, s);
-    launch_conv16_wgrad(N, D, H, W, x, n->dz1, n->part_w, n->part_b, n->gw, n->gb, s);
-    launch_gather_grads(n->gw, n->gb, n->sh, 0, n->grads, s);
+// Loss and gradients of every parameter (into n->grads) at training
+// precision, from device x, y; dx (nullable): the input gradient.
+void train_pass(mf4d_net* n, const uint16_t* x, const uint8_t* y, int N, int D, int H, int W, float pw, float* dx) {
+    launch_train_forward(N, D, H, W, x, n->wpk, n->bias, n->t1, n->t2, n->tlogits, n->stream);
+    launch_train_backward(N, D, H, W, x, n->wpk, n->tlogits, y, pw, n->t1, n->t2, n->dz1, n->dz2, n->dz3, dx,
+                          n->part_w, n->part_b, n->gw, n->gb, n->part_loss, n->loss, n->sh, n->grads, n->stream);
 }
 
 }  // namespace
@@ -182,12 +190,9 @@ int net_infer(mf4d_net* n, const uint16_t* x, int N, int D, int H, int W, float*
     int rc = check_dims(N, D, H, W);
     if (rc) return rc;
     const uint64_t pos = (uint64_t)N * D * H * W;
-    rc = ensure_acts(n, pos, nn_blocks(N, D, H, W));
+    rc = ensure_infer(n, pos);
     if (rc) return rc;
-    const size_t L = 27 * 256;
-    launch_conv16(N, D, H, W, x, n->wf, n->bias, 1, nullptr, n->a1, nullptr, s);
-    launch_conv16(N, D, H, W, n->a1, n->wf + L, n->bias + 16, 1, nullptr, n->a2, nullptr, s);
-    launch_conv16(N, D, H, W, n->a2, n->wf + 2 * L, n->bias + 32, 0, nullptr, nullptr, logits, s);
+    launch_infer(N, D, H, W, x, n->wpk, n->bias, n->a1, n->a2, logits, s);
     return MF4D_OK;
 }
 const char* net_last_error() { return n_err.c_str(); }
@@ -212,8 +217,7 @@ int mf4d_net_create(mf4d_net** out, int device, void* stream) {
     if (!rc) rc = nalloc(&n->grads, P);
     if (!rc) rc = nalloc(&n->m, P);
     if (!rc) rc = nalloc(&n->v, P);
-    if (!rc) rc = nalloc(&n->wf, 3 * 27 * 256);
-    if (!rc) rc = nalloc(&n->wb, 3 * 27 * 256);
+    if (!rc) rc = nalloc(&n->wpk, 6 * kPackSlot);
     if (!rc) rc = nalloc(&n->bias, 48);
     if (!rc) rc = nalloc(&n->gw, 27 * 256);
     if (!rc) rc = nalloc(&n->gb, 16);
@@ -225,7 +229,7 @@ int mf4d_net_create(mf4d_net** out, int device, void* stream) {
         launch_fill_u32((uint32_t*)n->params, 0, P, n->stream);
         launch_fill_u32((uint32_t*)n->m, 0, P, n->stream);
         launch_fill_u32((uint32_t*)n->v, 0, P, n->stream);
-        launch_prep_weights(n->params, n->sh, n->wf, n->wb, n->bias, n->stream);
+        launch_pack_weights(n->params, n->sh, n->wpk, n->bias, n->stream);
         if (hipStreamSynchronize(n->stream) != hipSuccess) rc = nfail(MF4D_ERR_HIP, "init failed");
     }
     if (rc) {
@@ -240,13 +244,13 @@ void mf4d_net_destroy(mf4d_net* n) {
     if (!n) return;
     (void)hipSetDevice(n->device);
     (void)hipStreamSynchronize(n->stream);
-    free_acts(n);
+    free_infer(n);
+    free_train(n);
     nfree(n->params);
     nfree(n->grads);
     nfree(n->m);
     nfree(n->v);
-    nfree(n->wf);
-    nfree(n->wb);
+    nfree(n->wpk);
     nfree(n->bias);
     nfree(n->gw);
     nfree(n->gb);
@@ -266,7 +270,7 @@ int mf4d_net_set_params(mf4d_net* n, const float* params, int where) {
                         n->stream));
     launch_fill_u32((uint32_t*)n->m, 0, n->sh.total, n->stream);
     launch_fill_u32((uint32_t*)n->v, 0, n->sh.total, n->stream);
-    launch_prep_weights(n->params, n->sh, n->wf, n->wb, n->bias, n->stream);
+    launch_pack_weights(n->params, n->sh, n->wpk, n->bias, n->stream);
     n->step = 0;
     NHIP(hipStreamSynchronize(n->stream));
     return MF4D_OK;
@@ -289,11 +293,9 @@ int mf4d_net_forward(mf4d_net* n, const uint16_t* x, int N, int D, int H, int W,
     int rc = check_dims(N, D, H, W);
     if (rc) return rc;
     NHIP(hipSetDevice(n->device));
-    rc = ensure_acts(n, (uint64_t)N * D * H * W, nn_blocks(N, D, H, W));
+    rc = ensure_infer(n, (uint64_t)N * D * H * W);
     if (rc) return rc;
-    forward(n, x, N, D, H, W);
-    NHIP(hipMemcpyAsync(logits, n->logits, (size_t)N * D * H * W * sizeof(float),
-                        hipMemcpyDeviceToDevice, n->stream));
+    launch_infer(N, D, H, W, x, n->wpk, n->bias, n->a1, n->a2, logits, n->stream);
     NHIP(hipStreamSynchronize(n->stream));
     return MF4D_OK;
 }
@@ -305,10 +307,9 @@ int mf4d_net_grad(mf4d_net* n, const uint16_t* x, const uint8_t* y, int N, int D
     int rc = check_dims(N, D, H, W);
     if (rc) return rc;
     NHIP(hipSetDevice(n->device));
-    rc = ensure_acts(n, (uint64_t)N * D * H * W, nn_blocks(N, D, H, W));
+    rc = ensure_train(n, (uint64_t)N * D * H * W, nn_blocks(N, D, H, W));
     if (rc) return rc;
-    forward(n, x, N, D, H, W);
-    backward(n, x, y, N, D, H, W, pos_weight);
+    train_pass(n, x, y, N, D, H, W, pos_weight, nullptr);
     NHIP(hipMemcpyAsync(grads, n->grads, n->sh.total * sizeof(float), hipMemcpyDeviceToDevice,
                         n->stream));
     NHIP(hipMemcpyAsync(n->h_loss, n->loss, sizeof(float), hipMemcpyDeviceToHost, n->stream));
@@ -323,14 +324,13 @@ int mf4d_net_train_step(mf4d_net* n, const uint16_t* x, const uint8_t* y, int N,
     int rc = check_dims(N, D, H, W);
     if (rc) return rc;
     NHIP(hipSetDevice(n->device));
-    rc = ensure_acts(n, (uint64_t)N * D * H * W, nn_blocks(N, D, H, W));
+    rc = ensure_train(n, (uint64_t)N * D * H * W, nn_blocks(N, D, H, W));
     if (rc) return rc;
-    forward(n, x, N, D, H, W);
-    backward(n, x, y, N, D, H, W, pos_weight);
+    train_pass(n, x, y, N, D, H, W, pos_weight, nullptr);
     n->step += 1;
     launch_adam(n->params, n->grads, n->m, n->v, n->sh.total, lr, 0.9f, 0.999f, 1e-8f, n->step,
                 n->stream);
-    launch_prep_weights(n->params, n->sh, n->wf, n->wb, n->bias, n->stream);
+    launch_pack_weights(n->params, n->sh, n->wpk, n->bias, n->stream);
     if (loss) {
         NHIP(hipMemcpyAsync(n->h_loss, n->loss, sizeof(float), hipMemcpyDeviceToHost, n->stream));
         NHIP(hipStreamSynchronize(n->stream));
@@ -351,12 +351,9 @@ int mf4d_nn_backward(mf4d_net* n, const uint16_t* x, const uint8_t* y, int N, in
     int rc = check_dims(N, D, H, W);
     if (rc) return rc;
     NHIP(hipSetDevice(n->device));
-    rc = ensure_acts(n, (uint64_t)N * D * H * W, nn_blocks(N, D, H, W));
+    rc = ensure_train(n, (uint64_t)N * D * H * W, nn_blocks(N, D, H, W));
     if (rc) return rc;
-    forward(n, x, N, D, H, W);
-    backward(n, x, y, N, D, H, W, pos_weight);
-    // input gradient: the first layer's input-gradient convolution of dz1
-    if (dx) launch_conv16_f32(N, D, H, W, n->dz1, n->wb, dx, n->stream);
+    train_pass(n, x, y, N, D, H, W, pos_weight, dx);
     NHIP(hipMemcpyAsync(grads, n->grads, n->sh.total * sizeof(float), hipMemcpyDeviceToDevice,
                         n->stream));
     NHIP(hipMemcpyAsync(n->h_loss, n->loss, sizeof(float), hipMemcpyDeviceToHost, n->stream));
@@ -377,12 +374,7 @@ int mf4d_nn_forward_noalloc(mf4d_net* n, const uint16_t* x, int N, int D, int H,
                      (unsigned long long)pos, (unsigned long long)kNoAllocPositions);
     if (!n->noalloc) return nfail(MF4D_ERR_STATE, "no scratch address for device %d", n->device);
     NHIP(hipSetDevice(n->device));
-    const size_t L = 27 * 256;
-    uint16_t* a1 = n->noalloc;
-    uint16_t* a2 = n->noalloc + pos * 16;
-    launch_conv16(N, D, H, W, x, n->wf, n->bias, 1, nullptr, a1, nullptr, n->stream);
-    launch_conv16(N, D, H, W, a1, n->wf + L, n->bias + 16, 1, nullptr, a2, nullptr, n->stream);
-    launch_conv16(N, D, H, W, a2, n->wf + 2 * L, n->bias + 32, 0, nullptr, nullptr, logits, n->stream);
+    launch_infer(N, D, H, W, x, n->wpk, n->bias, n->noalloc, n->noalloc + pos * 16, logits, n->stream);
     NHIP(hipGetLastError());
     return MF4D_OK;
 }
@@ -398,7 +390,7 @@ int mf4d_nn_adam_step(mf4d_net* n, const float* grads, float lr, int where) {
     n->step += 1;
     launch_adam(n->params, n->grads, n->m, n->v, n->sh.total, lr, 0.9f, 0.999f, 1e-8f, n->step,
                 n->stream);
-    launch_prep_weights(n->params, n->sh, n->wf, n->wb, n->bias, n->stream);
+    launch_pack_weights(n->params, n->sh, n->wpk, n->bias, n->stream);
     NHIP(hipStreamSynchronize(n->stream));
     return MF4D_OK;
 }

@@ -111,6 +111,21 @@ class Net:
                                            ctypes.byref(loss), MF4D_DEVICE))
         return g, loss.value
 
+    def backward(self, x, y, pos_weight: float):
+        """Parameter gradients, input gradient (fp32 [N][D][H][W][16]) and
+        loss of the training path (mf4d_nn_backward)."""
+        torch = _torch()
+        N, D, H, W, _ = x.shape
+        g = torch.empty(self.n, dtype=torch.float32, device=x.device)
+        dx = torch.empty((N, D, H, W, 16), dtype=torch.float32, device=x.device)
+        loss = ctypes.c_float()
+        self._check(self.lib.mf4d_nn_backward(self.ptr, ctypes.c_void_p(x.data_ptr()),
+                                              ctypes.c_void_p(y.data_ptr()), N, D, H, W,
+                                              float(pos_weight), ctypes.c_void_p(g.data_ptr()),
+                                              ctypes.c_void_p(dx.data_ptr()), ctypes.byref(loss),
+                                              MF4D_DEVICE))
+        return g, dx, loss.value
+
     def train_step(self, x, y, pos_weight: float, lr: float) -> float:
         N, D, H, W, _ = x.shape
         loss = ctypes.c_float()

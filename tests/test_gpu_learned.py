@@ -20,63 +20,102 @@ def _bf16_round(a):
     return torch.from_numpy(np.asarray(a, np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
 
 
-def _inputs(rng, shape):
+# A kernel's pre-activation carries the rounding of fp32 accumulation over at
+# most 43 terms (7 or 14 matrix instructions of 32 products, three operand
+# pieces each): at most 43 * 2^-24 = 2.6e-6 of the sum of the terms'
+# magnitudes.  A ReLU decision on a pre-activation closer to zero than that
+# could go either way, so the inputs are chosen (seeded, on the CPU, in fp64)
+# with every hidden pre-activation further from zero than 3e-6 of its
+# magnitude sum; then both sides take every ReLU decision alike and the
+# gradients are compared element by element.
+RELU_MARGIN = 3e-6
+
+
+def _make_case(shape, seed):
+    from paper_1903_12294_amd.learned import init_params, split_params
+    rng = np.random.default_rng(seed)
+    flat = (init_params(seed) + 0.02 * rng.normal(size=10833)).astype(np.float32)
+    parts = split_params(flat)
+    ref_params = [(_bf16_round(p) if i % 2 == 0 else np.asarray(p, np.float64)) for i, p in enumerate(parts)]
     N, D, H, W = shape
     x8 = rng.normal(size=(N, D, H, W, 8)).astype(np.float32)
-    x = np.zeros((N, D, H, W, 16), np.float32)
+    y = (rng.random(shape) < 0.3).astype(np.uint8)
+    return flat, ref_params, x8, y
+
+
+def _relu_margin(ref_params, x):
+    """Smallest |z| / sum |terms| over the hidden pre-activations (fp64)."""
+    w1, b1, w2, b2, _, _ = ref_params
+    z1 = nn_ref.conv3d(x, w1, b1)
+    s1 = nn_ref.conv3d(np.abs(x), np.abs(w1), np.abs(b1))
+    a1 = np.maximum(z1, 0)
+    z2 = nn_ref.conv3d(a1, w2, b2)
+    s2 = nn_ref.conv3d(a1, np.abs(w2), np.abs(b2))
+    return min(float((np.abs(z1) / s1).min()), float((np.abs(z2) / s2).min()))
+
+
+def _well_posed_case(shape):
+    for seed in range(200):
+        flat, ref_params, x8, y = _make_case(shape, seed)
+        x_ref = _bf16_round(x8)
+        if _relu_margin(ref_params, x_ref) > RELU_MARGIN:
+            return flat, ref_params, x8, x_ref, y
+    raise AssertionError(f"no seed below 200 gives a ReLU margin above {RELU_MARGIN} at {shape}")
+
+
+@pytest.mark.parametrize("shape", [(4, 8, 8, 8), (4, 9, 10, 19), (5, 8, 12, 8), (6, 8, 8, 16)])
+def test_forward_and_gradients_match_fp64_reference(shape):
+    """Logits (the inference path: bf16 activations) within 2e-2 of the
+    logit scale; loss, every weight and bias gradient and the input gradient
+    (the training path: fp32 activations and layer gradients) element by
+    element within 2e-2 of the pure fp64 reference (oracle/nn_ref.py) plus
+    1e-4 of the tensor's largest magnitude, on grids of at least 8 x 8 x 8 x 4
+    brick-steps.  The reference keeps every intermediate in fp64; weights and
+    inputs are the bf16 values both sides use."""
+    from paper_1903_12294_amd.learned import Net, join_params
+    _need_gpu()
+    flat, ref_params, x8, x_ref, y = _well_posed_case(shape)
+    print(f"[grad] {shape}", flush=True)
+    x = np.zeros(shape + (16,), np.float32)
     x[..., :8] = x8
     xt = torch.from_numpy(x).to(torch.bfloat16).to("cuda:0").contiguous()
-    return xt, _bf16_round(x8)
-
-
-@pytest.mark.parametrize("shape", [(2, 5, 6, 19), (1, 4, 4, 16), (3, 3, 9, 5)])
-def test_forward_and_gradients_match_fp64_reference(shape):
-    from paper_1903_12294_amd.learned import Net, init_params, join_params, split_params
-    _need_gpu()
-    rng = np.random.default_rng(sum(shape))
-    flat = init_params(7) + 0.02 * rng.normal(size=10833).astype(np.float32)
-    flat = flat.astype(np.float32)
-    parts = split_params(flat)
-    ref_params = [(_bf16_round(p) if i % 2 == 0 else np.asarray(p, np.float64))
-                  for i, p in enumerate(parts)]
-    xt, x_ref = _inputs(rng, shape)
-    y = (rng.random(shape) < 0.3).astype(np.uint8)
     yt = torch.from_numpy(y).to("cuda:0")
     net = Net(0)
     try:
         net.set_params(flat)
         assert np.array_equal(net.get_params(), flat)
         logits = net.forward(xt).cpu().numpy().astype(np.float64)
-        g, loss = net.grad(xt, yt, 2.5)
+        g, dx, loss = net.backward(xt, yt, 2.5)
         g = g.cpu().numpy().astype(np.float64)
+        dx = dx.cpu().numpy().astype(np.float64)
     finally:
         net.close()
-    # Tight check: the fp64 reference with the kernels' storage points (hidden
-    # activations and layer gradients held in bf16, logits in fp32); what
-    # remains is fp32 accumulation order.
-    zq, cache_q = nn_ref.forward(ref_params, x_ref, bf16_storage=True)
-    loss_q, dz_q = nn_ref.bce_loss(zq, y, 2.5)
-    grads_q = join_params(nn_ref.backward(ref_params, cache_q, dz_q, bf16_storage=True)).astype(np.float64)
-    scale = np.abs(zq).max() + 1e-6
-    assert np.abs(logits - zq).max() < 1e-3 * scale, np.abs(logits - zq).max()
-    assert abs(loss - loss_q) < 1e-4 * abs(loss_q), (loss, loss_q)
-    # Loose check against pure fp64: bf16 storage alone moves the first
-    # layer's weight gradient by up to ~5% on these small ragged grids, where
-    # its sums over few positions cancel heavily.
     z, cache = nn_ref.forward(ref_params, x_ref)
     loss_ref, dz = nn_ref.bce_loss(z, y, 2.5)
-    grads_ref = join_params(nn_ref.backward(ref_params, cache, dz)).astype(np.float64)
-    assert np.abs(logits - z).max() < 2e-2 * scale
-    assert abs(loss - loss_ref) < 1e-2 * abs(loss_ref)
-    off = 0
-    for cin, cout in [(8, 16), (16, 16), (16, 1)]:
-        n = cout * cin * 27 + cout
-        a, bq, b = g[off:off + n], grads_q[off:off + n], grads_ref[off:off + n]
-        rel_q = np.linalg.norm(a - bq) / (np.linalg.norm(bq) + 1e-12)
-        rel = np.linalg.norm(a - b) / (np.linalg.norm(b) + 1e-12)
-        assert rel_q < 2e-3, (cin, cout, rel_q)
-        assert rel < 1e-1, (cin, cout, rel)
-        off += n
+    grads_ref = nn_ref.backward(ref_params, cache, dz)
+    # the input gradient: the first layer's input-gradient convolution of the
+    # first layer's output gradient
+    xr, z1, a1, z2, a2 = cache
+    w1, _, w2, _, w3, _ = ref_params
+    da2, _, _ = nn_ref.conv3d_backward(a2, w3, dz[..., None])
+    da1, _, _ = nn_ref.conv3d_backward(a1, w2, da2 * (z2 > 0))
+    dx_ref, _, _ = nn_ref.conv3d_backward(xr, w1, da1 * (z1 > 0))
+    assert np.abs(logits - z).max() < 2e-2 * (np.abs(z).max() + 1e-6)
+    assert abs(loss - loss_ref) < 1e-4 * abs(loss_ref), (loss, loss_ref)
+    got = [gg for gg in _split_flat(g)] + [dx[..., :8]]
+    want = [np.asarray(r, np.float64) for r in grads_ref] + [dx_ref]
+    names = ["dW1", "db1", "dW2", "db2", "dW3", "db3", "dX"]
+    for name, a, b in zip(names, got, want):
+        a = a.reshape(b.shape)
+        tol = 2e-2 * np.abs(b) + 1e-4 * np.abs(b).max()
+        bad = np.abs(a - b) > tol
+        assert not bad.any(), (name, int(bad.sum()), float((np.abs(a - b) / (tol + 1e-300)).max()))
+    assert not dx[..., 8:].any()
+
+
+def _split_flat(g):
+    from paper_1903_12294_amd.learned import split_params
+    return [np.asarray(p, np.float64) for p in split_params(g)]
 
 
 def test_training_reduces_loss():
