@@ -332,7 +332,9 @@ def bench_batched(args, torch, log):
         tune = autotune.tune_batched(inst, crit, qseeds, repeats=1, use_cache=False)
     shape = tuple(tune["best"]["tile"])
     log(f"[bench] batched tile {shape}" + (f" from {len(tune['table'])} candidates" if tune["table"] else ""))
-    g = Grower(device=0)
+    # the single-query grows it is compared with run their rounds as launches
+    # (faster than the persistent kernel at this size)
+    g = Grower(device=0, schedule="launch")
     try:
         g.load_field(torch.from_numpy(inst["field"]).to(dev))
         g.load_particles(torch.from_numpy(inst["xyz"]).to(dev), torch.from_numpy(inst["attr"]).to(dev))
@@ -374,6 +376,27 @@ def bench_batched(args, torch, log):
             plain_f = ((fm.view(-1, 1) >> bit) & 1).bool().flatten()[:V]
             plane_p = ((pp[..., q >> 5] >> (q & 31)) & 1).bool()
             ok = ok and bool(torch.equal(plane_f, plain_f)) and bool(torch.equal(plane_p, pm.bool()))
+        cpu = None
+        if not args.no_cpu_baseline:
+            # the oracle on a bounded sample of the queries, one single-thread
+            # grow per query on every host core; its planes checked too
+            from oracle import oracle_grow_queries
+            nq = 64
+            threads = max(1, min(16, os.cpu_count() or 1))
+            t0 = time.perf_counter()
+            res = oracle_grow_queries(inst["field"], inst["xyz"], inst["attr"], crit[:nq],
+                                      qseeds[qseeds[:, 4] < nq], threads=threads)
+            tc = time.perf_counter() - t0
+            for q in range(nq):
+                ofm, opm, _ = res[q]
+                plane_f = ((fp[:, q >> 5] >> (q & 31)) & 1).to(torch.uint8).cpu().numpy().astype(bool)
+                want_f = np.unpackbits(ofm.view(np.uint8), bitorder="little")[:V].astype(bool)
+                plane_p = ((pp[..., q >> 5] >> (q & 31)) & 1).to(torch.uint8).cpu().numpy()
+                ok = ok and bool(np.array_equal(plane_f, want_f)) and bool(np.array_equal(plane_p, opm))
+            cpu = {"value": round(nq * V / tc, 1), "unit": "query-voxel-steps/s", "cores": threads,
+                   "kind": "oracle",
+                   "sample": f"{nq} of the 256 queries, one single-thread C breadth-first grow each, "
+                             f"on {threads} host threads ({tc:.1f}s); their planes compared too"}
     finally:
         g.close()
     return {"workload": "128^3x32 field, 262144 particles x 32 steps, 256 queries "
@@ -381,8 +404,8 @@ def bench_batched(args, torch, log):
             "tile": list(shape), "ms_batched": round(ms_b, 3), "ms_plain_256": round(ms_p, 3),
             "speedup": round(ms_p / ms_b, 2),
             "value": round(256 * V / (ms_b * 1e-3), 1), "unit": "query-voxel-steps/s",
-            "rounds": bst["rounds"], "sampled_planes_equal": ok,
-            "autotune": tune["table"]}
+            "rounds": bst["rounds"], "tile_visits": bst["tile_visits"], "sampled_planes_equal": ok,
+            "cpu_baseline": cpu, "autotune": tune["table"]}
 
 
 def bench_grow_form(args, torch, log, inst, name, slic_k=None):
@@ -461,30 +484,38 @@ def bench_rate3d(args, torch, log):
 
 
 def bench_learned(g, args, torch, fmask, pmask, ref_f, ref_p):
-    """Learned scheduling on the loaded workload: the plain grow (tiles mode),
-    then the trained (committed weights) and untrained predictor, masks
+    """Score-ordered scheduling on the loaded workload (lazy admissibility):
+    the plain grow, the heuristic priority (candidate tiles in descending
+    order of their greatest field value), and the learned scheduler with the
+    trained (committed weights) and an untrained network: time per step,
+    rounds (the verification round and any after it included), tile visits
+    of the rounds and of the priority pass, tiles tested up front; masks
     compared with the plain grow's (ref_f, ref_p)."""
-    from paper_1903_12294_amd.learned import Net, init_params, set_predictor
+    from paper_1903_12294_amd.learned import init_params
+    g.set_scheduler("plain")
     base = run_steps(g, fmask, pmask, args.steps, 2, torch)
-    lf = {"baseline_tiles_ms": round(base["ms"], 4), "baseline_tiles_tested": base["stats"]["tiles_tested"]}
-    net = Net(0)
-    try:
-        variants = [("untrained", init_params(0), 0.0)]
-        if os.path.exists(PREDICTOR):
-            meta = json.load(open(os.path.splitext(PREDICTOR)[0] + ".json"))
-            variants.insert(0, ("trained", np.load(PREDICTOR), float(meta["logit_threshold"])))
-        for name, params, thr in variants:
-            net.set_params(params)
-            set_predictor(g, net, thr)
-            rl = run_steps(g, fmask, pmask, args.steps, 2, torch)
-            lf[name] = {"ms_per_step": round(rl["ms"], 4), "speedup_vs_plain": round(base["ms"] / rl["ms"], 3),
-                        "tiles_tested": rl["stats"]["tiles_tested"],
-                        "tiles_deferred_read": rl["stats"]["tiles_deferred_read"],
-                        "rounds": rl["stats"]["rounds"], "logit_threshold": thr,
-                        "masks_equal": bool(torch.equal(fmask, ref_f) and torch.equal(pmask, ref_p))}
-            set_predictor(g, None)
-    finally:
-        net.close()
+    bst = base["stats"]
+    lf = {"plain": {"ms_per_step": round(base["ms"], 4), "rounds": bst["rounds"],
+                    "tile_visits": bst["tile_visits"], "tiles_tested": bst["tiles_tested"]}}
+    variants = [("heuristic", None, None), ("untrained", init_params(0), 0.0)]
+    if os.path.exists(PREDICTOR):
+        meta = json.load(open(os.path.splitext(PREDICTOR)[0] + ".json"))
+        variants.insert(1, ("trained", np.load(PREDICTOR), float(meta["logit_threshold"])))
+    for name, params, thr in variants:
+        if params is None:
+            g.set_scheduler("heuristic")
+        else:
+            g.set_scheduler("learned", params, thr)
+        rl = run_steps(g, fmask, pmask, args.steps, 2, torch)
+        st = rl["stats"]
+        lf[name] = {"ms_per_step": round(rl["ms"], 4), "speedup_vs_plain": round(base["ms"] / rl["ms"], 3),
+                    "rounds": st["rounds"], "verify_rounds": st["verify_rounds"],
+                    "tile_visits": st["tile_visits"], "priority_visits": st["priority_visits"],
+                    "tiles_tested": st["tiles_tested"], "tiles_deferred_read": st["tiles_deferred_read"],
+                    "masks_equal": bool(torch.equal(fmask, ref_f) and torch.equal(pmask, ref_p))}
+        if thr is not None:
+            lf[name]["logit_threshold"] = thr
+    g.set_scheduler("plain")
     return lf
 
 
@@ -587,15 +618,15 @@ def main():
     if args.city_only:
         print(json.dumps(bench_city(args, torch, log)), flush=True)
         return
+    if args.batched_only:
+        print(json.dumps(bench_batched(args, torch, log)), flush=True)
+        return
     cfg = synth.CONFIGS[args.config]
     t0 = time.time()
     inst = synth.make_config(args.config)
     log(f"[bench] generated {cfg['name']} in {time.time() - t0:.1f}s")
     if args.slic_only:
         print(json.dumps(bench_slic(torch, log, inst, cfg["name"])), flush=True)
-        return
-    if args.batched_only:
-        print(json.dumps(bench_batched(args, torch, log)), flush=True)
         return
     X, Y, Z = inst["dims"]
     T, P = inst["T"], inst["P"]
@@ -646,11 +677,17 @@ def main():
     # the counters were taken at 256^3 x 64 with tile depth 16 and launched rounds
     measured_here = (X, Y, Z, T) == (256, 256, 256, 64) and choice["tile_t"] == 16 and launch
     traffic = MEASURED_TRAFFIC.get((dom, version)) if measured_here else None
+    # the whole step against the lazy floor: 0.43 B per voxel-step (the
+    # admissible-reached nodes and their shell at ~0.5% occupancy, dominated
+    # by the dense mask writes)
+    floor_b = 0.43 * V
     roofline = {"bound": "hbm", "kernel": dom, "achieved": kt[dom]["achieved_GBps"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kt[dom]["frac"],
                 "traffic": int(traffic) if traffic else None,
                 "bytes_per_launch": kt[dom]["bytes_per_launch"],
-                "ms_per_launch": kt[dom]["ms_per_launch"]}
+                "ms_per_launch": kt[dom]["ms_per_launch"],
+                "grow_lazy_floor_bytes": int(floor_b),
+                "grow_frac": round(floor_b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     if args.copy_probe:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)

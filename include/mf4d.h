@@ -79,8 +79,9 @@ enum { MF4D_ADMIT_TILES = 0, MF4D_ADMIT_ALL = 1 };
 
 /* Schedulers of the rounds of a grow (mf4d_set_scheduler). */
 enum {
-    MF4D_SCHEDULER_PLAIN = 0,  /* tiles are visited in the order their work is found */
-    MF4D_SCHEDULER_LEARNED = 1 /* the brick-activity predictor orders the first visits */
+    MF4D_SCHEDULER_PLAIN = 0,    /* tiles are visited in the order their work is found */
+    MF4D_SCHEDULER_LEARNED = 1,  /* the brick-activity predictor orders the first visits */
+    MF4D_SCHEDULER_HEURISTIC = 2 /* the tiles' greatest field values order the first visits */
 };
 
 /* Trajectory coupling (mf4d_set_trajectory_mode). */
@@ -89,7 +90,10 @@ enum { MF4D_TRAJ_BOTH = 0, MF4D_TRAJ_FORWARD = 1 };
 /* How the rounds of a grow are scheduled (both give the same result). */
 enum {
     MF4D_SCHED_PERSISTENT = 0, /* one cooperative kernel runs every round (default) */
-    MF4D_SCHED_LAUNCH = 1      /* three kernel launches per round */
+    MF4D_SCHED_LAUNCH = 1,     /* three kernel launches per round */
+    MF4D_SCHED_JACOBI = 2      /* debugging: synchronous sweeps over every node, one edge per sweep;
+                                  converges after D + 1 sweeps, D the largest breadth-first level
+                                  (stats.rounds counts the sweeps; admissibility is read everywhere) */
 };
 
 typedef struct mf4d_stats {
@@ -113,6 +117,9 @@ typedef struct mf4d_stats {
     double ms_pull;           /* likewise for the pull kernels */
     double ms_close;          /* likewise for the close/push kernels */
     int64_t coupled_steps;    /* single-query grow: admissible particle-steps that lie in a voxel */
+    int64_t priority_visits;  /* score-ordered schedulers: tiles swept by the priority pass */
+    int64_t verify_rounds;    /* score-ordered schedulers: rounds from the verification round on
+                                 (1 when it changed nothing); included in `rounds` */
 } mf4d_stats;
 
 /* Record HIP events in each grow (on = 1) so that the device times of
@@ -127,6 +134,13 @@ const char *mf4d_version(void);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *mf4d_last_error(void);
+
+/* Bytes of device memory the grower contexts hold (all devices; networks
+ * are not counted).  An environment variable MF4D_MAX_DEVICE_BYTES (decimal),
+ * read at each allocation, caps it: an allocation that would exceed the cap
+ * fails with MF4D_ERR_OOM as if the device were full (a way to exercise
+ * out-of-memory handling); the failing call frees what it allocated. */
+int64_t mf4d_device_bytes(void);
 
 /* Create a context on HIP device `device`, ordering its work on `hip_stream`
  * (a hipStream_t, or NULL for the null stream).  *out receives the context.

@@ -31,8 +31,10 @@ MF4D_TRAJ_BOTH = 0
 MF4D_TRAJ_FORWARD = 1
 MF4D_SCHED_PERSISTENT = 0
 MF4D_SCHED_LAUNCH = 1
+MF4D_SCHED_JACOBI = 2
 MF4D_SCHEDULER_PLAIN = 0
 MF4D_SCHEDULER_LEARNED = 1
+MF4D_SCHEDULER_HEURISTIC = 2
 
 ERROR_NAMES = {
     MF4D_ERR_ARG: "ARG", MF4D_ERR_RANGE: "RANGE", MF4D_ERR_OOM: "OOM", MF4D_ERR_HIP: "HIP",
@@ -85,6 +87,8 @@ class Stats(ctypes.Structure):
         ("ms_pull", c_double),
         ("ms_close", c_double),
         ("coupled_steps", c_int64),
+        ("priority_visits", c_int64),
+        ("verify_rounds", c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -95,6 +99,7 @@ class Stats(ctypes.Structure):
 SIGNATURES = {
     "mf4d_version": (c_char_p, []),
     "mf4d_last_error": (c_char_p, []),
+    "mf4d_device_bytes": (c_int64, []),
     "mf4d_create": (c_int, [POINTER(c_void_p), c_int, c_void_p]),
     "mf4d_destroy": (None, [c_void_p]),
     "mf4d_set_tile": (c_int, [c_void_p, c_int]),

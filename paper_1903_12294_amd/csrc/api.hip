@@ -7,8 +7,11 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <hipcub/hipcub.hpp>
+#include <mutex>
 #include <new>
 #include <string>
+#include <unordered_map>
 
 #include "mf4d_internal.h"
 #include "batched.h"
@@ -47,23 +50,55 @@ int fail(int code, const char* fmt, ...) {
                         "%s failed: %s", #expr, hipGetErrorString(e_));                 \
     } while (0)
 
+// Device memory held by the library's contexts, and an optional cap on it
+// (MF4D_MAX_DEVICE_BYTES, read at each allocation): an allocation that would
+// exceed the cap fails with MF4D_ERR_OOM as if the device were full, so that
+// out-of-memory paths can be exercised on any GPU.
+std::mutex g_mem_mu;
+std::unordered_map<void*, size_t> g_mem_sizes;
+size_t g_mem_total = 0;
+
+size_t device_cap() {
+    const char* e = getenv("MF4D_MAX_DEVICE_BYTES");
+    if (!e || !*e) return SIZE_MAX;
+    char* end = nullptr;
+    const unsigned long long v = strtoull(e, &end, 10);
+    return (end && *end == 0) ? (size_t)v : SIZE_MAX;
+}
+
 template <class T>
 int dev_alloc(T** p, size_t count) {
     *p = nullptr;
     if (count == 0) count = 1;
-    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    const size_t bytes = count * sizeof(T);
+    std::lock_guard<std::mutex> lock(g_mem_mu);
+    const size_t cap = device_cap();
+    if (bytes > cap || g_mem_total > cap - bytes)
+        return fail(MF4D_ERR_OOM, "allocation of %zu bytes exceeds MF4D_MAX_DEVICE_BYTES (%zu held)", bytes,
+                    g_mem_total);
+    hipError_t e = hipMalloc((void**)p, bytes);
     if (e != hipSuccess) {
         *p = nullptr;
         (void)hipGetLastError();
         return fail(e == hipErrorOutOfMemory ? MF4D_ERR_OOM : MF4D_ERR_HIP,
-                    "hipMalloc of %zu bytes failed: %s", count * sizeof(T), hipGetErrorString(e));
+                    "hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
     }
+    g_mem_sizes[(void*)*p] = bytes;
+    g_mem_total += bytes;
     return MF4D_OK;
 }
 
 template <class T>
 void dev_free(T*& p) {
-    if (p) (void)hipFree(p);
+    if (p) {
+        (void)hipFree(p);
+        std::lock_guard<std::mutex> lock(g_mem_mu);
+        auto it = g_mem_sizes.find((void*)p);
+        if (it != g_mem_sizes.end()) {
+            g_mem_total -= it->second;
+            g_mem_sizes.erase(it);
+        }
+    }
     p = nullptr;
 }
 
@@ -167,6 +202,16 @@ struct mf4d_ctx {
     mf4d_net* net = nullptr;
     mf4d_net* own_net = nullptr;  // the network of the learned scheduler (mf4d_set_scheduler)
     float pred_thr = 0.0f;
+    // score-ordered schedulers (MF4D_SCHEDULER_LEARNED / _HEURISTIC): priority
+    // list of the candidate tiles, sorted on the device
+    int priority = MF4D_SCHEDULER_PLAIN;
+    uint32_t* pr_buf = nullptr;  // 4 x NT: keys, tiles, sorted keys, sorted tiles; then the count
+    void* pr_tmp = nullptr;      // radix sort scratch
+    size_t pr_tmp_bytes = 0;
+    int pr_waves = 512;          // wavefronts of the priority pass
+    // Jacobi sweeps (MF4D_SCHED_JACOBI): the next labels
+    uint32_t* jlf = nullptr;
+    unsigned long long* jlp = nullptr;
 
     // particles as loaded, for the clustering: xyz [T][P][3] then attr [T][P]
     float* praw = nullptr;
@@ -224,6 +269,14 @@ void free_field(mf4d_ctx* c) {
     dev_free(c->feat);
     dev_free(c->blogits);
     dev_free(c->tpred);
+    dev_free(c->pr_buf);
+    dev_free(c->jlf);
+    {
+        char* tmp = static_cast<char*>(c->pr_tmp);
+        dev_free(tmp);
+        c->pr_tmp = nullptr;
+        c->pr_tmp_bytes = 0;
+    }
     dev_free(c->b_active);
     dev_free(c->b_dirty);
     dev_free(c->b_chg);
@@ -237,6 +290,7 @@ void free_field(mf4d_ctx* c) {
 }
 
 void free_particles(mf4d_ctx* c) {
+    dev_free(c->jlp);
     dev_free(c->praw);
     dev_free(c->porder);
     dev_free(c->spos);
@@ -263,7 +317,8 @@ void free_particles(mf4d_ctx* c) {
 
 int staging_for(mf4d_ctx* c, size_t bytes, void** out) {
     if (c->staging_bytes < bytes) {
-        if (c->staging) (void)hipFree(c->staging);
+        char* old = static_cast<char*>(c->staging);
+        dev_free(old);
         c->staging = nullptr;
         c->staging_bytes = 0;
         int rc = dev_alloc((char**)&c->staging, bytes);
@@ -315,16 +370,53 @@ Dev make_dev(mf4d_ctx* c) {
     d.psum = c->psum;
     d.cand = c->cand;
     d.tpred = nullptr;
-    d.admit_all = c->admit_all;
+    d.admit_all = c->admit_all || c->schedule == MF4D_SCHED_JACOBI;  // Jacobi sweeps read every word
     d.forward_only = c->forward_only;
     for (int i = 0; i < 4; ++i) d.crit[i] = c->crit[i];
     return d;
+}
+
+// Jacobi sweeps until one adds nothing (converged) or the cap is hit; each
+// sweep reads the current labels and writes a copy, then the copy becomes
+// current.  rounds_done: the sweeps run (the last converged one included).
+int run_jacobi(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
+    const uint64_t nw = c->g.nwords;
+    const uint64_t np = c->has_particles ? (uint64_t)c->pg.P * c->pg.W : 0;
+    int rc = MF4D_OK;
+    if (!c->jlf) rc = dev_alloc(&c->jlf, nw);
+    if (!rc && np && !c->jlp) rc = dev_alloc(&c->jlp, np);
+    if (rc) return rc;
+    hipStream_t s = c->stream;
+    int64_t k = 0;
+    while (true) {
+        if (c->max_rounds > 0 && k >= c->max_rounds) {
+            c->state = 2;
+            break;
+        }
+        HIP_TRY(hipMemcpyAsync(c->jlf, c->Lf, nw * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+        if (np) HIP_TRY(hipMemcpyAsync(c->jlp, c->Lp, np * sizeof(unsigned long long), hipMemcpyDeviceToDevice, s));
+        launch_fill_u32(c->counters + C_JCHANGED, 0, 1, s);
+        launch_jacobi(d, c->Lf, c->Lp, c->jlf, c->jlp, s);
+        HIP_TRY(hipMemcpyAsync(c->Lf, c->jlf, nw * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+        if (np) HIP_TRY(hipMemcpyAsync(c->Lp, c->jlp, np * sizeof(unsigned long long), hipMemcpyDeviceToDevice, s));
+        rc = read_counters(c);
+        if (rc) return rc;
+        ++k;
+        if (!c->h_counters[C_JCHANGED]) {
+            c->state = 1;
+            break;
+        }
+    }
+    c->round += (uint32_t)k;
+    *rounds_done = k;
+    return MF4D_OK;
 }
 
 // Rounds until a round's work list is empty (converged) or the cap is hit.
 // Persistent: one cooperative launch runs every round; if it cannot be
 // launched, or a grid barrier timed out, the rounds run as launches instead.
 int run_rounds(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
+    if (c->schedule == MF4D_SCHED_JACOBI) return run_jacobi(c, d, rounds_done);
     const uint32_t cap = (uint32_t)(c->max_rounds > 0 ? c->max_rounds : 0);
     const uint32_t r0 = c->round;
     if (c->schedule == MF4D_SCHED_PERSISTENT) {
@@ -403,6 +495,7 @@ int finish_stats(mf4d_ctx* c, mf4d_stats* out, bool fresh, int64_t rounds) {
     s.active_tiles = (int64_t)c->h_stat[S_ACTIVE_TILES];
     if (fresh) s.tiles_tested = c->admit_all ? (int64_t)c->g.NT : (int64_t)c->h_stat[S_TILES_TESTED];
     s.tiles_deferred_read = (int64_t)c->h_stat[S_DEFERRED_READ];
+    s.priority_visits = (int64_t)c->h_stat[S_PRIO_VISITS];
     s.ms_sweep = c->ms_phase[0];
     s.ms_pull = c->ms_phase[1];
     s.ms_close = c->ms_phase[2];
@@ -437,9 +530,14 @@ extern "C" {
 
 // Bumped whenever a kernel changes: autotuner caches and recorded hardware
 // counter figures are keyed by it.
-const char* mf4d_version(void) { return "mf4d 0.6.2 (gfx950)"; }
+const char* mf4d_version(void) { return "mf4d 0.7.0 (gfx950)"; }
 
 const char* mf4d_last_error(void) { return g_err.c_str(); }
+
+int64_t mf4d_device_bytes(void) {
+    std::lock_guard<std::mutex> lock(g_mem_mu);
+    return (int64_t)g_mem_total;
+}
 
 int mf4d_create(mf4d_ctx** out, int device, void* hip_stream) {
     if (!out) return fail(MF4D_ERR_ARG, "out is NULL");
@@ -505,7 +603,11 @@ void mf4d_destroy(mf4d_ctx* c) {
     if (c->own_net) mf4d_net_destroy(c->own_net);
     c->own_net = nullptr;
     if (c->h_scounters) (void)hipHostFree(c->h_scounters);
-    if (c->staging) (void)hipFree(c->staging);
+    {
+        char* st = static_cast<char*>(c->staging);
+        dev_free(st);
+        c->staging = nullptr;
+    }
     if (c->h_counters) (void)hipHostFree(c->h_counters);
     if (c->h_stat) (void)hipHostFree(c->h_stat);
     for (int i = 0; i < 4; ++i)
@@ -659,7 +761,7 @@ int mf4d_load_particles_rate(mf4d_ctx* c, const float* xyz, const float* attr, i
         if (e == hipSuccess)
             e = hipMemcpyAsync(tmp + nxyz, attr, nat * sizeof(float), hipMemcpyHostToDevice, c->stream);
         if (e != hipSuccess) {
-            (void)hipFree(tmp);
+            dev_free(tmp);
             free_particles(c);
             return fail(MF4D_ERR_HIP, "particle upload failed: %s", hipGetErrorString(e));
         }
@@ -686,7 +788,7 @@ int mf4d_load_particles_rate(mf4d_ctx* c, const float* xyz, const float* attr, i
         }
     }
     if (!rc) rc = sync(c);
-    if (tmp) (void)hipFree(tmp);
+    dev_free(tmp);
     if (rc) {
         free_particles(c);
         return rc;
@@ -795,7 +897,7 @@ int mf4d_set_phase_timing(mf4d_ctx* c, int on) {
 
 int mf4d_set_schedule(mf4d_ctx* c, int mode) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
-    if (mode != MF4D_SCHED_PERSISTENT && mode != MF4D_SCHED_LAUNCH)
+    if (mode != MF4D_SCHED_PERSISTENT && mode != MF4D_SCHED_LAUNCH && mode != MF4D_SCHED_JACOBI)
         return fail(MF4D_ERR_ARG, "unknown schedule %d", mode);
     c->schedule = mode;
     return MF4D_OK;
@@ -808,6 +910,48 @@ void ensure_brick_stats(mf4d_ctx* c) {
     launch_brick_stats(c->g, c->has_particles ? c->pg : PGeom{}, c->bd, c->field,
                        c->has_particles ? c->bins : nullptr, c->bstats, c->stream);
     c->bstats_valid = true;
+}
+
+// Buffers of the score-ordered schedulers (sized by the tile count).
+int ensure_priority(mf4d_ctx* c) {
+    if (c->pr_buf) return MF4D_OK;
+    const uint32_t NT = c->g.NT;
+    int rc = dev_alloc(&c->pr_buf, 4 * (size_t)NT + 1);
+    if (rc) return rc;
+    size_t bytes = 0;
+    HIP_TRY(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, bytes, c->pr_buf, c->pr_buf + 2 * (size_t)NT,
+                                                         c->pr_buf + NT, c->pr_buf + 3 * (size_t)NT, (int)NT, 0,
+                                                         32, c->stream));
+    char* tmp = nullptr;
+    rc = dev_alloc(&tmp, bytes);
+    if (rc) {
+        dev_free(c->pr_buf);
+        return rc;
+    }
+    c->pr_tmp = tmp;
+    c->pr_tmp_bytes = bytes;
+    return MF4D_OK;
+}
+
+// The verification round after the rounds converged (run as launches
+// whatever the schedule), then plain rounds while it found work.
+int verify_round(mf4d_ctx* c, const Dev& d, int64_t* rounds) {
+    const int par = (int)(c->round & 1);
+    launch_verify_schedule(d, par, c->stream);
+    Dev dv = d;
+    dv.pull_all = 1;
+    launch_fill_u32(c->counters + C_ROUNDS, 0, 1, c->stream);
+    launch_round(dv, c->round, c->stream);
+    launch_work_total(d, par ^ 1, c->stream);
+    int rc = read_counters(c);
+    if (rc) return rc;
+    c->round += c->h_counters[C_ROUNDS];
+    *rounds = c->h_counters[C_ROUNDS];
+    if (c->h_counters[C_NWORK0 + (par ^ 1)] == 0) return MF4D_OK;
+    int64_t more = 0;
+    rc = run_rounds(c, d, &more);
+    *rounds += more;
+    return rc;
 }
 
 int mf4d_grow(mf4d_ctx* c, mf4d_stats* out) {
@@ -825,7 +969,9 @@ int mf4d_grow(mf4d_ctx* c, mf4d_stats* out) {
     c->timed = c->phase_timing;
     if (c->timed) HIP_TRY(hipEventRecord(c->ev[0], s));
     Dev dp = d;
-    if (c->net && !c->admit_all) {
+    const bool ordered = c->priority != MF4D_SCHEDULER_PLAIN && !d.admit_all;
+    const bool predicted = c->net && !d.admit_all;
+    if (predicted) {
         // the predictor marks the candidate tiles to test before the rounds
         ensure_brick_stats(c);
         launch_features(c->bd, c->bstats, c->crit[0], c->feat, s);
@@ -834,18 +980,50 @@ int mf4d_grow(mf4d_ctx* c, mf4d_stats* out) {
         launch_tile_predict(c->g, c->bd, c->blogits, c->pred_thr, c->tpred, s);
         dp.tpred = c->tpred;
     }
+    uint32_t* plist = nullptr;
+    uint32_t* pcount = nullptr;
+    if (ordered) {
+        // priority list: candidate tiles in descending score, scored by the
+        // network (learned) or by their greatest field value (heuristic)
+        int rc = ensure_priority(c);
+        if (rc) return rc;
+        const uint32_t NT = c->g.NT;
+        uint32_t* keys = c->pr_buf;
+        uint32_t* vals = c->pr_buf + NT;
+        uint32_t* skeys = c->pr_buf + 2 * (size_t)NT;
+        plist = c->pr_buf + 3 * (size_t)NT;
+        pcount = c->pr_buf + 4 * (size_t)NT;
+        launch_fill_u32(pcount, 0, 1, s);
+        const bool learned = c->priority == MF4D_SCHEDULER_LEARNED && c->net;
+        launch_priority_keys(d, learned ? c->blogits : nullptr, c->bd.W, c->bd.H, c->bd.D,
+                             learned ? c->pred_thr : -INFINITY, keys, vals, pcount, s);
+        size_t bytes = c->pr_tmp_bytes;
+        HIP_TRY(hipcub::DeviceRadixSort::SortPairsDescending(c->pr_tmp, bytes, keys, skeys, vals, plist, (int)NT,
+                                                             0, 32, s));
+    }
     launch_admit_field(dp, s);
     if (c->timed) HIP_TRY(hipEventRecord(c->ev[1], s));
     launch_admit_particles(d, s);
     if (c->timed) HIP_TRY(hipEventRecord(c->ev[2], s));
     launch_seeds(d, c->seeds, c->S, s);
+    if (ordered) launch_priority_sweep(d, plist, pcount, c->pr_waves, s);
     int64_t rounds = 0;
     int rc = run_rounds(c, d, &rounds);
     if (rc) return rc;
+    int64_t verify_rounds = 0;
+    if (ordered && c->state == 1) {
+        // verification round: every tile holding an admissible voxel-step is
+        // swept and every coupled particle-step pulled; should anything
+        // change, the plain rounds continue until nothing does
+        rc = verify_round(c, d, &verify_rounds);
+        if (rc) return rc;
+    }
     if (c->state == 1) c->last_rounds = rounds;
     if (c->timed) HIP_TRY(hipEventRecord(c->ev[3], s));
-    rc = finish_stats(c, out, true, rounds);
+    rc = finish_stats(c, out, true, rounds + verify_rounds);
     if (rc) return rc;
+    c->stats.verify_rounds = verify_rounds;
+    if (out) *out = c->stats;
     if (c->state == 2) return fail(MF4D_ERR_NOT_CONVERGED, "stopped after %lld rounds", (long long)rounds);
     return MF4D_OK;
 }
@@ -1311,10 +1489,11 @@ int mf4d_set_predictor(mf4d_ctx* c, mf4d_net* net, float logit_threshold) {
 
 int mf4d_set_scheduler(mf4d_ctx* c, int kind, const void* params, size_t nbytes) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
-    if (kind == MF4D_SCHEDULER_PLAIN) {
-        if (params || nbytes) return fail(MF4D_ERR_ARG, "the plain scheduler takes no parameters");
+    if (kind == MF4D_SCHEDULER_PLAIN || kind == MF4D_SCHEDULER_HEURISTIC) {
+        if (params || nbytes) return fail(MF4D_ERR_ARG, "this scheduler takes no parameters");
         c->net = nullptr;
         c->pred_thr = 0.0f;
+        c->priority = kind;
         return MF4D_OK;
     }
     if (kind != MF4D_SCHEDULER_LEARNED) return fail(MF4D_ERR_ARG, "unknown scheduler %d", kind);
@@ -1331,6 +1510,7 @@ int mf4d_set_scheduler(mf4d_ctx* c, int kind, const void* params, size_t nbytes)
     if (rc) return fail(rc, "network: %s", mf4d_net_last_error());
     c->net = c->own_net;
     c->pred_thr = thr;
+    c->priority = MF4D_SCHEDULER_LEARNED;
     return MF4D_OK;
 }
 
@@ -1471,7 +1651,7 @@ int mf4d_slic_run(mf4d_ctx* c, int* iterations) {
             if (e != hipSuccess) rc = fail(MF4D_ERR_HIP, "clustering order: %s", hipGetErrorString((hipError_t)e));
         }
         if (!rc) rc = sync(c);
-        if (scratch) (void)hipFree(scratch);
+        dev_free(scratch);
         if (rc) {
             dev_free(c->porder);
             dev_free(c->spos);

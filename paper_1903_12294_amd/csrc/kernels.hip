@@ -444,7 +444,7 @@ __device__ void pull_entries(const Dev& d, uint32_t i0, uint32_t stride, uint32_
         bool mem[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            mem[k] = ent[k].y != kNoVoxel && chg[ent[k].y >> tshift] && test_bit(d.Lf, ent[k].y);
+            mem[k] = ent[k].y != kNoVoxel && (d.pull_all || chg[ent[k].y >> tshift]) && test_bit(d.Lf, ent[k].y);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             if (!mem[k]) continue;
@@ -688,7 +688,7 @@ __device__ uint32_t pull_close_wave(const Dev& d, int par, uint32_t wave_id, uin
         bool mem[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            mem[k] = ent[k].y != kNoVoxel && chg[ent[k].y >> tshift] && test_bit(d.Lf, ent[k].y);
+            mem[k] = ent[k].y != kNoVoxel && (d.pull_all || chg[ent[k].y >> tshift]) && test_bit(d.Lf, ent[k].y);
         uint32_t pk[4];
         unsigned long long nwk[4];
 #pragma unroll
@@ -1401,6 +1401,166 @@ __global__ void k_seeds(Dev d, const int32_t* __restrict__ seeds, int64_t S) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// score-ordered schedulers (learned and heuristic priority)
+
+__device__ __forceinline__ uint32_t score_key(float f) {
+    const uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+// Sort keys of the candidate tiles (value range meets the band): the
+// order-preserving bits of the tile's score when the score reaches thr, else
+// 0; value = the tile.  Score: with logits ([T][Db][Hb][Wb] over 8^3-voxel
+// brick-steps) the largest logit of the tile's brick-steps, else the tile's
+// greatest field value.  count: tiles with a nonzero key.
+__global__ void k_priority_keys(Dev d, const float* __restrict__ logits, int bW, int bH, int bD, float thr,
+                                uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t* count) {
+    const Geom& g = d.g;
+    const float lo = d.crit[0], hi = d.crit[1];
+    for (uint32_t tile = blockIdx.x * blockDim.x + threadIdx.x; tile < g.NT; tile += gridDim.x * blockDim.x) {
+        const float2 r = d.tsum[tile];
+        uint32_t key = 0;
+        if (r.y >= lo && r.x <= hi) {
+            float score = r.y;
+            if (logits) {
+                int tx, ty, tz, tt;
+                tile_coords(g, tile, tx, ty, tz, tt);
+                score = -INFINITY;
+                for (int tl = 0; tl < g.BT; ++tl) {
+                    const int t = (tt << g.logBT) + tl;
+                    if (t >= g.T) break;
+                    for (int k = 0; k < 4; ++k) {
+                        const int bx = tx * 4 + k;
+                        if (bx >= bW) break;
+                        const float v = logits[(((size_t)t * bD + tz) * bH + ty) * bW + bx];
+                        score = v > score ? v : score;  // NaN logits never raise it
+                    }
+                }
+            }
+            if (score >= thr) key = score_key(score);
+        }
+        keys[tile] = key;
+        vals[tile] = tile;
+        if (key) atomicAdd(count, 1u);
+    }
+}
+
+// The priority pass: the first count tiles of `list` (descending score) are
+// swept in list order by nwaves waves, wave w taking items w, w + nwaves, ...
+// so that a tile later in the list sees what earlier ones set (Gauss-Seidel
+// within the pass).  Sweeps schedule the tiles across faces that gained bits
+// into the work list of parity par ^ 1, as in a round of parity par.
+template <int BT>
+__global__ __launch_bounds__(256) void k_priority_sweep(Dev d, const uint32_t* __restrict__ list,
+                                                        const uint32_t* __restrict__ count, int par) {
+    const uint32_t wave0 = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    const uint32_t n = *count;
+    for (uint32_t w = wave0; w < n; w += nwaves) {
+        const uint32_t tile = list[w];
+        if (d.active[tile] == 1) sweep_tile<BT>(d, tile, par);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&d.stat64[S_PRIO_VISITS], (unsigned long long)n);
+}
+
+// The verification round's schedule: every tile holding an admissible
+// voxel-step on the work list of parity par.  Its "changed" flag is left
+// alone: the round sweeps each tile as an ordinary visit (only faces that
+// gain bits schedule a neighbour), and its pull tests every coupled step
+// (Dev::pull_all) instead of those of changed tiles.
+__global__ __launch_bounds__(256) void k_verify_schedule(Dev d, int par) {
+    for (uint32_t t0 = blockIdx.x * blockDim.x; t0 < d.g.NT; t0 += gridDim.x * blockDim.x) {
+        const uint32_t tile = t0 + threadIdx.x;
+        uint32_t nb[1] = {tile};
+        const int k = tile < d.g.NT && d.active[tile] == 1 ? 1 : 0;
+        schedule_batch(d, nb, k, par);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Jacobi sweeps (a debugging schedule): X_{k+1} = X_k with every admissible
+// node one edge away from X_k added, computed from X_k alone (read from the
+// current label arrays, written to the next ones).  From the admissible
+// seeds, the sweep that adds nothing is number D + 1, D the largest
+// breadth-first level of the grown set.
+
+// Label word of the row (y, z, t) of x-tile tx, or 0 outside the tile grid.
+__device__ __forceinline__ uint32_t jword(const Geom& g, const uint32_t* L, int tx, int y, int z, int t) {
+    if (tx < 0 || tx >= g.NXt || y < 0 || y >= g.NYt * 8 || z < 0 || z >= g.NZt * 8 || t < 0 ||
+        t >= (g.NTt << g.logBT))
+        return 0u;
+    const uint32_t tile = tile_of(g, tx, y >> 3, z >> 3, t >> g.logBT);
+    return L[(size_t)tile * g.WPT + (((t & (g.BT - 1)) * 8 + (z & 7)) * 8 + (y & 7))];
+}
+
+// Field edges: each word of the next labels = its current word plus the
+// admissible bits with a member neighbour (x within and across words, y, z,
+// t from the neighbouring rows).
+__global__ __launch_bounds__(256) void k_jacobi_field(Dev d, const uint32_t* __restrict__ cur,
+                                                      uint32_t* __restrict__ nxt) {
+    const Geom& g = d.g;
+    for (uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; w < g.nwords;
+         w += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t c = cur[w];
+        const uint32_t a = d.Af[w];
+        uint32_t add = 0;
+        if (a & ~c) {
+            const uint32_t tile = (uint32_t)(w / g.WPT), wi = (uint32_t)(w % g.WPT);
+            int tx, ty, tz, tt;
+            tile_coords(g, tile, tx, ty, tz, tt);
+            const int y = ty * 8 + (wi & 7), z = tz * 8 + ((wi >> 3) & 7), t = (tt << g.logBT) + (wi >> 6);
+            uint32_t n = (c << 1) | (c >> 1);
+            n |= jword(g, cur, tx - 1, y, z, t) >> 31;
+            n |= jword(g, cur, tx + 1, y, z, t) << 31;
+            n |= jword(g, cur, tx, y - 1, z, t) | jword(g, cur, tx, y + 1, z, t);
+            n |= jword(g, cur, tx, y, z - 1, t) | jword(g, cur, tx, y, z + 1, t);
+            n |= jword(g, cur, tx, y, z, t - 1) | jword(g, cur, tx, y, z, t + 1);
+            add = n & a & ~c;
+        }
+        if (add) {
+            atomicOr(&nxt[w], add);
+            d.counters[C_JCHANGED] = 1u;
+        }
+    }
+}
+
+// Particle edges, one thread per particle-step of the candidate particles:
+// a member step puts its admissible voxel into the next labels; a
+// non-member admissible step joins when its voxel or the same particle at t -
+// 1 (or t + 1, unless coupling is forward-only) is a member now.
+__global__ __launch_bounds__(256) void k_jacobi_particles(Dev d, const uint32_t* __restrict__ lf_cur,
+                                                          const unsigned long long* __restrict__ lp_cur,
+                                                          uint32_t* __restrict__ lf_nxt,
+                                                          unsigned long long* __restrict__ lp_nxt) {
+    const PGeom& pg = d.pg;
+    const uint64_t n = (uint64_t)pg.P * pg.Tpad;
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < n;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t p = e / pg.Tpad;
+        const int t = (int)(e - p * pg.Tpad);
+        if (t >= pg.T || !d.pflag[p]) continue;
+        auto member = [&](int s) -> bool {
+            return (lp_cur[p * pg.W + (s >> 6)] >> (s & 63)) & 1ull;
+        };
+        const uint32_t b = d.bins[e];
+        if (member(t)) {
+            if (b != kNoVoxel && test_bit(d.Af, b) && !test_bit(lf_cur, b)) {
+                atomicOr(&lf_nxt[b >> 5], 1u << (b & 31));
+                d.counters[C_JCHANGED] = 1u;
+            }
+            continue;
+        }
+        if (!((d.Ap[p * pg.W + (t >> 6)] >> (t & 63)) & 1ull)) continue;
+        const bool join = (b != kNoVoxel && test_bit(lf_cur, b)) || (t > 0 && member(t - 1)) ||
+                          (!d.forward_only && t + 1 < pg.T && member(t + 1));
+        if (join) {
+            atomicOr(&lp_nxt[p * pg.W + (t >> 6)], 1ull << (t & 63));
+            d.counters[C_JCHANGED] = 1u;
+        }
+    }
+}
+
 // Sweep every tile on the work list of parity `par` (its kWorkSubs sub-lists
 // read as one list: lane j holds sub-list j's length and prefix, so a wave
 // finds the sub-list of flat index w with one ballot).  Returns the list's
@@ -1967,6 +2127,33 @@ void launch_seed_ids(const Dev& d, const uint32_t* words, uint32_t* seen_f, unsi
     if (particle_ids && d.pg.P > 0)
         hipLaunchKernelGGL(k_seed_ids_particles, dim3(grid_for((uint64_t)d.pg.P, 256, 16384)), dim3(256), 0, s,
                            d, seen_p, id, particle_ids);
+}
+
+void launch_priority_keys(const Dev& d, const float* logits, int bW, int bH, int bD, float thr, uint32_t* keys,
+                          uint32_t* vals, uint32_t* count, hipStream_t s) {
+    hipLaunchKernelGGL(k_priority_keys, dim3(grid_for(d.g.NT, 256, 1024)), dim3(256), 0, s, d, logits, bW, bH, bD,
+                       thr, keys, vals, count);
+}
+
+void launch_priority_sweep(const Dev& d, const uint32_t* list, const uint32_t* count, int waves, hipStream_t s) {
+    const unsigned blocks = (unsigned)std::max(1, waves / 4);
+    switch (d.g.BT) {
+        case 4: hipLaunchKernelGGL(k_priority_sweep<4>, dim3(blocks), dim3(256), 0, s, d, list, count, 0); break;
+        case 8: hipLaunchKernelGGL(k_priority_sweep<8>, dim3(blocks), dim3(256), 0, s, d, list, count, 0); break;
+        default: hipLaunchKernelGGL(k_priority_sweep<16>, dim3(blocks), dim3(256), 0, s, d, list, count, 0); break;
+    }
+}
+
+void launch_verify_schedule(const Dev& d, int par, hipStream_t s) {
+    hipLaunchKernelGGL(k_verify_schedule, dim3(grid_for(d.g.NT, 256, 1024)), dim3(256), 0, s, d, par);
+}
+
+void launch_jacobi(const Dev& d, const uint32_t* lf_cur, const unsigned long long* lp_cur, uint32_t* lf_nxt,
+                   unsigned long long* lp_nxt, hipStream_t s) {
+    hipLaunchKernelGGL(k_jacobi_field, dim3(grid_for(d.g.nwords, 256, 16384)), dim3(256), 0, s, d, lf_cur, lf_nxt);
+    if (d.pg.P > 0)
+        hipLaunchKernelGGL(k_jacobi_particles, dim3(grid_for((uint64_t)d.pg.P * d.pg.Tpad, 256, 16384)), dim3(256), 0,
+                           s, d, lf_cur, lp_cur, lf_nxt, lp_nxt);
 }
 
 }  // namespace mf4d

@@ -68,6 +68,7 @@ enum Counter : int {
     C_ROUNDS = 6,  // rounds completed by the persistent kernel
     C_NCAND = 7,   // candidate tiles
     C_RACT = 8,    // launched rounds: 1 if the current round has work (set by its sweep)
+    C_JCHANGED = 9,  // Jacobi sweeps: the sweep added a node
     C_NCOUNTERS = 16
 };
 
@@ -79,6 +80,7 @@ enum Stat64 : int {
     S_ACTIVE_TILES = 4,
     S_TILES_TESTED = 5,
     S_DEFERRED_READ = 6,
+    S_PRIO_VISITS = 7,  // tiles swept by the priority pass of a score-ordered scheduler
     S_NSTAT = 8
 };
 
@@ -115,6 +117,8 @@ struct Dev {
     float crit[4];
     int admit_all;           // 1: test every voxel-step; 0: only candidate tiles
     int forward_only;        // 1: membership runs along a trajectory from t to t + 1 only
+    int pull_all;            // 1: the pull tests every coupled step, changed tile or not
+                             // (the verification round of the score-ordered schedulers)
 };
 
 // ---- launchers (kernels.hip) ----
@@ -145,6 +149,25 @@ void launch_particle_segments(const Dev& d, uint8_t* out, hipStream_t s);
 // may be null.
 void launch_seed_ids(const Dev& d, const uint32_t* words, uint32_t* seen_f, unsigned long long* seen_p,
                      int32_t id, int32_t* field_ids, int32_t* particle_ids, hipStream_t s);
+// Score-ordered schedulers.  Sort keys of the candidate tiles (order-
+// preserving bits of the score when it reaches thr, else 0) and values (the
+// tiles), count = tiles with a key.  Score: with logits ([T][bD][bH][bW] over
+// 8^3-voxel brick-steps) the largest logit of the tile's brick-steps, else
+// the tile's greatest field value.
+void launch_priority_keys(const Dev& d, const float* logits, int bW, int bH, int bD, float thr, uint32_t* keys,
+                          uint32_t* vals, uint32_t* count, hipStream_t s);
+// The priority pass: the first *count tiles of list swept in list order by
+// `waves` wavefronts (wave w takes items w, w + waves, ...), as in a round of
+// parity 0 (they schedule for round 1).
+void launch_priority_sweep(const Dev& d, const uint32_t* list, const uint32_t* count, int waves, hipStream_t s);
+// The verification round's schedule: every tile holding an admissible
+// voxel-step on the work list of parity par.
+void launch_verify_schedule(const Dev& d, int par, hipStream_t s);
+// One Jacobi sweep: the next labels (lf_nxt, lp_nxt: copies of the current
+// ones on entry) gain every admissible node one edge away from the current
+// labels; counters[C_JCHANGED] is set if any node was added.
+void launch_jacobi(const Dev& d, const uint32_t* lf_cur, const unsigned long long* lp_cur, uint32_t* lf_nxt,
+                   unsigned long long* lp_nxt, hipStream_t s);
 // stat64[dst] (+)= sum of slot statistic `which` (assign: =), and those slots cleared.
 void launch_fold_slots(const Dev& d, int which, int dst, hipStream_t s, bool assign = false);
 // The per-grow statistics (particle visits, active and tested tiles) folded

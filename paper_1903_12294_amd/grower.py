@@ -125,8 +125,10 @@ class Grower:
         del keep
 
     def set_schedule(self, mode):
-        """"persistent" (one cooperative kernel) or "launch" (launches per round)."""
-        m = {"persistent": _lib.MF4D_SCHED_PERSISTENT, "launch": _lib.MF4D_SCHED_LAUNCH}[mode]
+        """"persistent" (one cooperative kernel), "launch" (launches per round)
+        or "jacobi" (debugging: synchronous sweeps, one edge per sweep)."""
+        m = {"persistent": _lib.MF4D_SCHED_PERSISTENT, "launch": _lib.MF4D_SCHED_LAUNCH,
+             "jacobi": _lib.MF4D_SCHED_JACOBI}[mode]
         self._check(self.lib.mf4d_set_schedule(self.ctx, m))
 
     def set_admit_mode(self, mode):
@@ -382,10 +384,15 @@ class Grower:
         self._check(self.lib.mf4d_reset_labels(self.ctx))
 
     def set_scheduler(self, kind: str, params=None, logit_threshold: float = 0.0):
-        """'plain', or 'learned' with the predictor's fp32 parameters (the
-        context keeps its own copy of the network)."""
-        if kind == "plain":
-            self._check(self.lib.mf4d_set_scheduler(self.ctx, _lib.MF4D_SCHEDULER_PLAIN, None, 0))
+        """'plain'; 'heuristic' (candidate tiles visited first in descending
+        order of their greatest field value, then a verification round); or
+        'learned' with the predictor's fp32 parameters (the context keeps its
+        own copy of the network): tiles scoring at least the threshold
+        visited first in descending score, the others' admissibility deferred,
+        then a verification round."""
+        if kind in ("plain", "heuristic"):
+            k = _lib.MF4D_SCHEDULER_PLAIN if kind == "plain" else _lib.MF4D_SCHEDULER_HEURISTIC
+            self._check(self.lib.mf4d_set_scheduler(self.ctx, k, None, 0))
             return
         if kind != "learned":
             raise ValueError(f"unknown scheduler {kind!r}")

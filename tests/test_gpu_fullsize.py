@@ -88,6 +88,11 @@ def test_config5_learned_masks_equal_oracle(scale):
                                  scheduler=("learned", params, float(meta["logit_threshold"])))
         assert torch.equal(fm, scale["ofm"]), schedule
         assert torch.equal(pm, scale["opm"]), schedule
+        assert st["verify_rounds"] == 1
+    print("[fullsize] 256^3x64 heuristic priority", flush=True)
+    fm, pm, st = _grow_scale(scale, 16, "launch", "tiles", scheduler=("heuristic",))
+    assert torch.equal(fm, scale["ofm"]) and torch.equal(pm, scale["opm"])
+    assert st["verify_rounds"] == 1 and st["priority_visits"] > 0
 
 
 def _pack_plane(bits_u8):

@@ -234,3 +234,49 @@ def test_trained_predictor_reads_fewer_tiles_and_stays_exact():
           f"{res['untrained']['tiles_deferred_read']}")
     assert tr["tiles_tested"] < base["tiles_tested"]
     assert reads < base["tiles_tested"]
+
+
+@pytest.mark.parametrize("variant", ["field", "noise"])
+def test_score_ordered_schedulers_are_exact(variant):
+    """The score-ordered schedulers (priority pass over the candidate tiles in
+    descending score, plain rounds, a verification round that sweeps every
+    tile holding an admissible voxel-step and pulls every coupled step) give
+    the oracle's masks under both round schedules, with the heuristic score,
+    an untrained and a NaN-weighted network, and report the verification
+    round (which changes nothing: exactly one verification round)."""
+    from paper_1903_12294_amd import Grower
+    from paper_1903_12294_amd.learned import init_params
+    _need_gpu()
+    inst = synth.make_config(2, attr_mode=variant)
+    ofm, opm, _ = oracle_grow(inst["field"], inst["xyz"], inst["attr"], inst["crit"], inst["seeds"])
+    g = Grower(device=0)
+    try:
+        g.load_field(inst["field"])
+        g.load_particles(inst["xyz"], inst["attr"])
+        g.set_criteria(*inst["crit"])
+        g.set_seeds(inst["seeds"])
+        g.set_scheduler("plain")
+        base = g.grow()
+        assert base["verify_rounds"] == 0 and base["priority_visits"] == 0
+        cases = [("heuristic", None, None), ("learned", init_params(4), 0.0),
+                 ("learned", init_params(5), -np.inf), ("learned", np.full(10833, np.nan, np.float32), 0.0)]
+        for kind, params, thr in cases:
+            if params is None:
+                g.set_scheduler(kind)
+            else:
+                g.set_scheduler(kind, params, thr)
+            for schedule in ("persistent", "launch"):
+                print(f"[ordered] {variant} {kind} thr={thr} {schedule}", flush=True)
+                g.set_schedule(schedule)
+                st = g.grow()
+                assert np.array_equal(g.read_field_mask(), ofm), (kind, thr, schedule)
+                assert np.array_equal(g.read_particle_mask(), opm), (kind, thr, schedule)
+                assert st["verify_rounds"] == 1, st
+                if kind == "heuristic" or thr == -np.inf:
+                    assert st["priority_visits"] > 0
+        g.set_scheduler("plain")
+        st = g.grow()
+        assert st["verify_rounds"] == 0
+        assert np.array_equal(g.read_field_mask(), ofm)
+    finally:
+        g.close()
