@@ -174,6 +174,15 @@ struct mf4d_ctx {
     void* staging = nullptr;
     size_t staging_bytes = 0;
 
+    // A second stream for the particle read-out, beside the field read-out
+    // on the context stream; joined back into the context stream with an
+    // event, so every call stays ordered on it.
+    hipStream_t side = nullptr;
+    hipEvent_t ev_labels = nullptr;   // recorded after the last work that changed the labels
+    bool labels_marked = false;
+    hipEvent_t ev_pread = nullptr;    // the particle read-out on the side stream is done
+    bool stats_ready = false;         // h_stat / h_counters already hold this grow's statistics
+
     // batched queries
     int Q = 0;
     float* btab = nullptr;
@@ -183,9 +192,13 @@ struct mf4d_ctx {
     int NXb = 0, NYb = 0, NZb = 0, NTb = 0;
     int blog[4] = {3, 2, 2, 2};  // log2 of the batched tile extents (x, y, z, t)
     uint8_t* b_active = nullptr;
+    uint32_t* b_vrank = nullptr;  // [V] ranks of the voxel-steps under the query bands
+    uint32_t* b_prank = nullptr;  // [P][Tpad] ranks of the particle-steps
     uint32_t* b_dirty = nullptr;
     uint8_t* b_chg = nullptr;
     uint32_t* b_work = nullptr;
+    uint32_t* b_wcnt = nullptr;
+    uint32_t b_wcap = 0;
     uint32_t* b_counters = nullptr;
     uint32_t* b_fown = nullptr;  // planes owned by the context (a batched grow given no buffers)
     uint32_t* b_pown = nullptr;
@@ -253,7 +266,19 @@ void free_slic(mf4d_ctx* c) {
     c->merged = false;
 }
 
+void quiesce_side(mf4d_ctx* c) {
+    if (c->side) (void)hipStreamSynchronize(c->side);
+    c->labels_marked = false;
+}
+
+// Record that the labels are final up to here on the context stream: a
+// read-out on the side stream waits for this event only.
+void mark_labels(mf4d_ctx* c) {
+    c->labels_marked = hipEventRecord(c->ev_labels, c->stream) == hipSuccess;
+}
+
 void free_field(mf4d_ctx* c) {
+    quiesce_side(c);
     free_slic(c);
     dev_free(c->field);
     dev_free(c->Af);
@@ -278,9 +303,11 @@ void free_field(mf4d_ctx* c) {
         c->pr_tmp_bytes = 0;
     }
     dev_free(c->b_active);
+    dev_free(c->b_vrank);
     dev_free(c->b_dirty);
     dev_free(c->b_chg);
     dev_free(c->b_work);
+    dev_free(c->b_wcnt);
     dev_free(c->b_fown);
     dev_free(c->b_pown);
     c->b_fown_n = c->b_pown_n = 0;
@@ -290,7 +317,9 @@ void free_field(mf4d_ctx* c) {
 }
 
 void free_particles(mf4d_ctx* c) {
+    quiesce_side(c);
     dev_free(c->jlp);
+    dev_free(c->b_prank);
     dev_free(c->praw);
     dev_free(c->porder);
     dev_free(c->spos);
@@ -380,6 +409,7 @@ Dev make_dev(mf4d_ctx* c) {
 // sweep reads the current labels and writes a copy, then the copy becomes
 // current.  rounds_done: the sweeps run (the last converged one included).
 int run_jacobi(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
+    c->stats_ready = false;
     const uint64_t nw = c->g.nwords;
     const uint64_t np = c->has_particles ? (uint64_t)c->pg.P * c->pg.W : 0;
     int rc = MF4D_OK;
@@ -425,8 +455,12 @@ int run_rounds(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
             launch_fill_u32(c->bar, 0, kBarWords, c->stream);
         }
         if (launch_rounds_persistent(d, r0, cap, c->device, c->stream)) {
+            launch_fold_grow_slots(d, c->stream);
+            HIP_TRY(hipMemcpyAsync(c->h_stat, c->stat64, S_NSTAT * sizeof(unsigned long long),
+                                   hipMemcpyDeviceToHost, c->stream));
             int rc = read_counters(c);
             if (rc) return rc;
+            c->stats_ready = true;
             if (c->h_counters[C_ERR] == 0) {
                 const uint32_t done = c->h_counters[C_ROUNDS];
                 c->round = r0 + done;
@@ -459,8 +493,14 @@ int run_rounds(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
         for (int64_t k = 0; k < chunk; ++k)
             launch_round(d, (uint32_t)(c->round + k), c->stream, c->timed ? c->rev + 4 * k : nullptr);
         launch_work_total(d, (int)((c->round + chunk) & 1), c->stream);
+        // the grow's statistics come back with the same read, so that
+        // finish_stats needs no wait of its own after the last chunk
+        launch_fold_grow_slots(d, c->stream);
+        HIP_TRY(hipMemcpyAsync(c->h_stat, c->stat64, S_NSTAT * sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, c->stream));
         int rc = read_counters(c);
         if (rc) return rc;
+        c->stats_ready = true;
         const int64_t done = (int64_t)c->h_counters[C_ROUNDS] - r;
         for (int64_t k = 0; c->timed && k < done && k < chunk; ++k)
             for (int ph = 0; ph < 3; ++ph) {
@@ -480,13 +520,18 @@ int run_rounds(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
 }
 
 int finish_stats(mf4d_ctx* c, mf4d_stats* out, bool fresh, int64_t rounds) {
-    launch_fold_grow_slots(make_dev(c), c->stream);
-    HIP_TRY(hipMemcpyAsync(c->h_stat, c->stat64, S_NSTAT * sizeof(unsigned long long),
-                           hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, C_NCOUNTERS * sizeof(uint32_t),
-                           hipMemcpyDeviceToHost, c->stream));
-    int rc = sync(c);
-    if (rc) return rc;
+    if (!c->stats_ready) {  // else the last read of the rounds brought them
+        launch_fold_grow_slots(make_dev(c), c->stream);
+        HIP_TRY(hipMemcpyAsync(c->h_stat, c->stat64, S_NSTAT * sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, C_NCOUNTERS * sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, c->stream));
+        int rc = sync(c);
+        if (rc) return rc;
+    }
+    c->stats_ready = false;
+    // with phase timing the events after the last read must have completed
+    if (c->timed) HIP_TRY(hipEventSynchronize(c->ev[3]));
     mf4d_stats& s = c->stats;
     if (fresh) s = mf4d_stats{};
     s.rounds += rounds;
@@ -569,6 +614,11 @@ int mf4d_create(mf4d_ctx** out, int device, void* hip_stream) {
         if (hipEventCreate(&c->ev[i]) != hipSuccess) rc = fail(MF4D_ERR_HIP, "hipEventCreate failed");
     for (int i = 0; !rc && i < 16; ++i)
         if (hipEventCreate(&c->rev[i]) != hipSuccess) rc = fail(MF4D_ERR_HIP, "hipEventCreate failed");
+    if (!rc && hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess)
+        rc = fail(MF4D_ERR_HIP, "hipStreamCreateWithFlags failed");
+    for (hipEvent_t* e : {&c->ev_labels, &c->ev_pread})
+        if (!rc && hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess)
+            rc = fail(MF4D_ERR_HIP, "hipEventCreate failed");
     if (rc) {
         mf4d_destroy(c);
         return rc;
@@ -582,6 +632,7 @@ void mf4d_destroy(mf4d_ctx* c) {
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
+    if (c->side) (void)hipStreamSynchronize(c->side);
     free_field(c);
     free_particles(c);
     dev_free(c->counters);
@@ -608,6 +659,9 @@ void mf4d_destroy(mf4d_ctx* c) {
         dev_free(st);
         c->staging = nullptr;
     }
+    if (c->side) (void)hipStreamDestroy(c->side);
+    for (hipEvent_t e : {c->ev_labels, c->ev_pread})
+        if (e) (void)hipEventDestroy(e);
     if (c->h_counters) (void)hipHostFree(c->h_counters);
     if (c->h_stat) (void)hipHostFree(c->h_stat);
     for (int i = 0; i < 4; ++i)
@@ -936,6 +990,7 @@ int ensure_priority(mf4d_ctx* c) {
 // The verification round after the rounds converged (run as launches
 // whatever the schedule), then plain rounds while it found work.
 int verify_round(mf4d_ctx* c, const Dev& d, int64_t* rounds) {
+    c->stats_ready = false;
     const int par = (int)(c->round & 1);
     launch_verify_schedule(d, par, c->stream);
     Dev dv = d;
@@ -1024,6 +1079,7 @@ int mf4d_grow(mf4d_ctx* c, mf4d_stats* out) {
     if (rc) return rc;
     c->stats.verify_rounds = verify_rounds;
     if (out) *out = c->stats;
+    mark_labels(c);
     if (c->state == 2) return fail(MF4D_ERR_NOT_CONVERGED, "stopped after %lld rounds", (long long)rounds);
     return MF4D_OK;
 }
@@ -1040,6 +1096,7 @@ int mf4d_grow_resume(mf4d_ctx* c, mf4d_stats* out) {
     if (c->timed) HIP_TRY(hipEventRecord(c->ev[3], c->stream));
     rc = finish_stats(c, out, false, rounds);
     if (rc) return rc;
+    mark_labels(c);
     if (c->state == 2) return fail(MF4D_ERR_NOT_CONVERGED, "stopped after %lld more rounds", (long long)rounds);
     return MF4D_OK;
 }
@@ -1055,12 +1112,16 @@ int mf4d_reset_labels(mf4d_ctx* c) {
     if (rc) return rc;
     c->state = 0;
     c->round = 0;
+    mark_labels(c);
     return MF4D_OK;
 }
 
-// Wait for member counts copied by stream-ordered reads and record them.
+// Member counts folded on the device by stream-ordered reads: copy them to
+// the host (once, when asked for) and record them.
 int settle_members(mf4d_ctx* c) {
     if (!c->members_pending[0] && !c->members_pending[1]) return MF4D_OK;
+    HIP_TRY(hipMemcpyAsync(c->h_stat + S_MEMBERS_F, c->stat64 + S_MEMBERS_F, 2 * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, c->stream));
     int rc = sync(c);
     if (rc) return rc;
     if (c->members_pending[0]) c->stats.members_field = (int64_t)c->h_stat[S_MEMBERS_F];
@@ -1089,9 +1150,7 @@ int mf4d_read_field_mask(mf4d_ctx* c, uint32_t* dst, size_t nwords, int where) {
     launch_fold_slots(make_dev(c), SL_MEMBERS_F, S_MEMBERS_F, c->stream, true);
     if (where == MF4D_HOST)
         HIP_TRY(hipMemcpyAsync(dst, out, need * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->h_stat + S_MEMBERS_F, c->stat64 + S_MEMBERS_F,
-                           sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
-    c->members_pending[0] = true;
+    c->members_pending[0] = true;  // the count stays on the device until asked for
     if (where == MF4D_DEVICE) return MF4D_OK;  // stream-ordered
     return settle_members(c);
 }
@@ -1112,13 +1171,22 @@ int mf4d_read_particle_mask(mf4d_ctx* c, uint8_t* dst, size_t n, int where) {
         if (rc) return rc;
         out = (uint8_t*)st;
     }
-    launch_read_particles(make_dev(c), out, c->stream);
-    launch_fold_slots(make_dev(c), SL_MEMBERS_P, S_MEMBERS_P, c->stream, true);
+    // Into a device buffer the read-out runs on the side stream, after the
+    // last work that changed the labels and beside whatever the context
+    // stream does meanwhile (the field read-out); the context stream then
+    // waits for it, so the call stays ordered on that stream.
+    const bool side = where == MF4D_DEVICE && c->labels_marked;
+    hipStream_t rs = side ? c->side : c->stream;
+    if (side) HIP_TRY(hipStreamWaitEvent(c->side, c->ev_labels, 0));
+    launch_read_particles(make_dev(c), out, rs);
+    launch_fold_slots(make_dev(c), SL_MEMBERS_P, S_MEMBERS_P, rs, true);
     if (where == MF4D_HOST)
         HIP_TRY(hipMemcpyAsync(dst, out, need, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->h_stat + S_MEMBERS_P, c->stat64 + S_MEMBERS_P,
-                           sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
-    c->members_pending[1] = true;
+    if (side) {
+        HIP_TRY(hipEventRecord(c->ev_pread, c->side));
+        HIP_TRY(hipStreamWaitEvent(c->stream, c->ev_pread, 0));
+    }
+    c->members_pending[1] = true;  // the count stays on the device until asked for
     if (where == MF4D_DEVICE) return MF4D_OK;  // stream-ordered
     return settle_members(c);
 }
@@ -1367,17 +1435,29 @@ int mf4d_grow_batched(mf4d_ctx* c, uint32_t* fplanes, size_t fwords, uint32_t* p
         int rc = dev_alloc(&c->b_active, (size_t)ntb + 8);
         if (!rc) rc = dev_alloc(&c->b_dirty, 2 * (size_t)ntb);
         if (!rc) rc = dev_alloc(&c->b_chg, 2 * (size_t)ntb + 8);
-        if (!rc) rc = dev_alloc(&c->b_work, 2 * (size_t)ntb);
+        const uint32_t wcap = (uint32_t)((ntb + kBSubs - 1) / kBSubs);
+        if (!rc) rc = dev_alloc(&c->b_work, 2 * (size_t)kBSubs * wcap);
+        if (!rc && !c->b_wcnt) rc = dev_alloc(&c->b_wcnt, 2 * (size_t)kBSubs * kBCntStride);
         if (!rc && !c->b_counters) rc = dev_alloc(&c->b_counters, BC_NCOUNTERS);
         if (rc) {
             dev_free(c->b_active);
             dev_free(c->b_dirty);
             dev_free(c->b_chg);
             dev_free(c->b_work);
+            dev_free(c->b_wcnt);
             return rc;
         }
+        c->b_wcap = wcap;
         c->NXb = NXb; c->NYb = NYb; c->NZb = NZb; c->NTb = NTb;
         c->NTB = (uint32_t)ntb;
+    }
+    if (!c->b_vrank) {
+        int rc = dev_alloc(&c->b_vrank, (size_t)V);
+        if (rc) return rc;
+    }
+    if (P > 0 && !c->b_prank) {
+        int rc = dev_alloc(&c->b_prank, (size_t)P * c->pg.Tpad);
+        if (rc) return rc;
     }
     uint32_t* fo = fplanes;
     uint32_t* po = pplanes;
@@ -1400,6 +1480,8 @@ int mf4d_grow_batched(mf4d_ctx* c, uint32_t* fplanes, size_t fwords, uint32_t* p
     d.Tpad = c->has_particles ? c->pg.Tpad : 1;
     d.field = c->field;
     d.attr_t = c->attr_t;
+    d.vrank = c->b_vrank;
+    d.prank = P > 0 ? c->b_prank : nullptr;
     d.bins = c->bins;
     d.fplanes = fo;
     d.pplanes = P > 0 ? po : nullptr;
@@ -1408,6 +1490,8 @@ int mf4d_grow_batched(mf4d_ctx* c, uint32_t* fplanes, size_t fwords, uint32_t* p
     d.dirty = c->b_dirty;
     d.chg = c->b_chg;
     d.work = c->b_work;
+    d.wcnt = c->b_wcnt;
+    d.WCAPB = c->b_wcap;
     d.clist = c->clist;
     d.pdirty = c->pdirty;
     d.dlist = c->dlist;
@@ -1418,16 +1502,23 @@ int mf4d_grow_batched(mf4d_ctx* c, uint32_t* fplanes, size_t fwords, uint32_t* p
     HIP_TRY(hipEventRecord(c->ev[0], s));
     launch_b_prepare(d, c->qseeds, c->QS, s);
     HIP_TRY(hipEventRecord(c->ev[1], s));
+    // rounds are queued a chunk at a time (a round with an empty work list is
+    // a no-op on the device, and every round after it is one too); the host
+    // reads the counters once per chunk
+    constexpr uint32_t kChunk = 8;
     uint32_t r = 0;
     while (true) {
+        launch_fill_u32(c->b_counters + BC_ROUNDS, 0, 1, s);
+        for (uint32_t k = 0; k < kChunk; ++k) launch_b_round(d, r + k, s);
+        launch_b_work_total(d, 0, s);
+        launch_b_work_total(d, 1, s);
         HIP_TRY(hipMemcpyAsync(c->h_counters, c->b_counters, BC_NCOUNTERS * sizeof(uint32_t),
                                hipMemcpyDeviceToHost, s));
         int rc = sync(c);
         if (rc) return rc;
-        const uint32_t nwork = c->h_counters[BC_NWORK0 + (r & 1)];
-        if (nwork == 0) break;
-        launch_b_round(d, r, nwork, s);
-        ++r;
+        const uint32_t done = c->h_counters[BC_ROUNDS];
+        r += done;
+        if (done < kChunk || c->h_counters[BC_NWORK0 + (r & 1)] == 0) break;
     }
     HIP_TRY(hipEventRecord(c->ev[3], s));
     HIP_TRY(hipMemcpyAsync(c->h_stat, c->stat64, S_NSTAT * sizeof(unsigned long long),

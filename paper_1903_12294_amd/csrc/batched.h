@@ -11,8 +11,14 @@ enum BCounter : int {
     BC_NDIRTYP = 2,
     BC_NLIST = 3,
     BC_DROPPED = 4,
+    BC_RACT = 5,    // the current round has work (set by its sweep)
+    BC_ROUNDS = 6,  // rounds that had work (since last cleared by the host)
     BC_NCOUNTERS = 8
 };
+
+// Work sub-lists per round parity, and the words between their counters.
+constexpr int kBSubs = 64;
+constexpr int kBCntStride = 32;
 
 // Float offsets inside the table buffer: sorted bounds (256 each), then the
 // four prefix-mask tables of 257 x 8 words (field lo, field hi, particle lo,
@@ -31,6 +37,8 @@ struct DevB {
     int Tpad;
     const float* field;      // fp32 [T][Z][Y][X]
     const float* attr_t;     // fp32 [P][Tpad]
+    uint32_t* vrank;         // [V] ranks of each voxel-step: rank_lo | rank_hi << 16
+    uint32_t* prank;         // [P][Tpad] ranks of each particle-step, likewise
     const uint32_t* bins;    // [P][Tpad] tile-layout bit position or kNoVoxel
     uint32_t* fplanes;       // [V][8] labels = output
     uint32_t* pplanes;       // [T][P][8] labels = output
@@ -38,7 +46,9 @@ struct DevB {
     uint8_t* active;         // NTB (+8)
     uint32_t* dirty;         // 2 x NTB
     uint8_t* chg;            // 2 x NTB (+8)
-    uint32_t* work;          // 2 x NTB
+    uint32_t* work;          // [2][kBSubs][WCAPB] work sub-lists of round parity 0 / 1
+    uint32_t* wcnt;          // [2][kBSubs] sub-list lengths, kBCntStride words apart
+    uint32_t WCAPB;          // capacity of one sub-list = ceil(NTB / kBSubs)
     uint2* clist;            // coupled steps (flat step index, canonical voxel index)
     uint32_t* pdirty;        // P bits
     uint32_t* dlist;         // P
@@ -48,7 +58,11 @@ struct DevB {
 };
 
 void launch_b_prepare(const DevB& d, const int32_t* seeds, int64_t S, hipStream_t s);
-void launch_b_round(const DevB& d, uint32_t round, uint32_t nwork_host, hipStream_t s);
+// One round (sweep, pull, close); a round whose work list is empty does
+// nothing, so rounds are queued ahead of the host.
+void launch_b_round(const DevB& d, uint32_t round, hipStream_t s);
+// Total length of the work list of parity par into counters[BC_NWORK0 + par].
+void launch_b_work_total(const DevB& d, int par, hipStream_t s);
 void launch_b_count(const DevB& d, hipStream_t s);
 
 }  // namespace mf4d

@@ -7,6 +7,11 @@
 // order, a prefix mask read from a table; likewise for the upper bounds sorted
 // descending.  The node's 256-bit mask is the AND of the two table rows.
 //
+// The two ranks of every voxel-step and particle-step (rank_lo | rank_hi <<
+// 16) are computed once per grow, when its admissibility is first read, and
+// kept: sweeps, pulls and closes rebuild a node's 256-bit mask from them with
+// two rows of the prefix tables (staged in LDS), no search.
+//
 // Field labels are grown in place in the caller's [V][8] output (canonical
 // voxel order); particle labels in the caller's [T][P][8] output.  Work is
 // organised in 4D tiles of 512 voxel-steps (a power-of-two extent per axis,
@@ -63,14 +68,23 @@ __device__ __forceinline__ Mask8 band_mask(const BandTables& tb, int Q, float v)
     return m;
 }
 
+// Prefix-mask tables of one sample type staged in LDS: lo rows then hi rows,
+// [257][8] words each.
+constexpr int kLdsTab = 2 * 257 * 8;
+
+__device__ __forceinline__ void stage_tables(const DevB& d, int type, uint32_t* s_tab) {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(d.tab + 1024) + (size_t)type * 2 * 257 * 8;
+    for (int i = threadIdx.x; i < kLdsTab; i += blockDim.x) s_tab[i] = src[i];
+}
+
+// Word k of the mask of a node with packed ranks r, from staged tables.
+__device__ __forceinline__ uint32_t rank_word(const uint32_t* s_tab, uint32_t r, int k) {
+    return s_tab[(r & 0xFFFFu) * 8 + k] & s_tab[257 * 8 + (r >> 16) * 8 + k];
+}
+
 __device__ __forceinline__ BandTables field_tables(const DevB& d) {
     return BandTables{d.tab, d.tab + 256, reinterpret_cast<const uint32_t*>(d.tab + 1024),
                       reinterpret_cast<const uint32_t*>(d.tab + 1024) + 257 * 8};
-}
-__device__ __forceinline__ BandTables particle_tables(const DevB& d) {
-    return BandTables{d.tab + 512, d.tab + 768,
-                      reinterpret_cast<const uint32_t*>(d.tab + 1024) + 2 * 257 * 8,
-                      reinterpret_cast<const uint32_t*>(d.tab + 1024) + 3 * 257 * 8};
 }
 
 __device__ __forceinline__ uint32_t btile_of(const DevB& d, int x, int y, int z, int t) {
@@ -110,10 +124,14 @@ __device__ __forceinline__ void bit_to_xyzt(const Geom& g, uint32_t b, int& x, i
     t = (tt << g.logBT) + (wi >> 6);
 }
 
+// The work list of a round parity is kBSubs sub-lists (tile % kBSubs), each
+// with its own counter on its own cache line: appends from every wave to one
+// counter would serialise.
 __device__ __forceinline__ void bschedule(const DevB& d, uint32_t tile, int par) {
     if (atomicExch(&d.dirty[par * d.NTB + tile], 1u) == 0u) {
-        const uint32_t k = atomicAdd(&d.counters[BC_NWORK0 + par], 1u);
-        d.work[par * d.NTB + k] = tile;
+        const uint32_t j = (uint32_t)par * kBSubs + (tile & (kBSubs - 1));
+        const uint32_t k = atomicAdd(&d.wcnt[j * kBCntStride], 1u);
+        d.work[(size_t)j * d.WCAPB + k] = tile;
     }
 }
 
@@ -172,21 +190,34 @@ __device__ __forceinline__ uint32_t block_append(uint32_t n, uint32_t* counter, 
 
 // ---------------------------------------------------------------------------
 
-// Clear both output planes, mark tiles that hold a node admissible for some
-// query.  One thread per voxel-step (canonical order).
+// The sorted bounds of one sample type staged in LDS (lo ascending, then hi
+// descending, 256 each), for the rank searches of a whole block.
+__device__ __forceinline__ void stage_bounds(const DevB& d, int type, float* s_b) {
+    for (int i = threadIdx.x; i < 512; i += blockDim.x) s_b[i] = d.tab[512 * type + i];
+}
+
+// Clear both output planes, record every voxel-step's ranks, mark tiles that
+// hold a node admissible for some query.  One thread per voxel-step
+// (canonical order), a grid-stride loop.
 __global__ __launch_bounds__(256) void kb_admit_field(DevB d) {
-    const BandTables tb = field_tables(d);
+    __shared__ float s_b[512];
+    stage_bounds(d, 0, s_b);
+    __syncthreads();
+    const uint32_t* ftab = reinterpret_cast<const uint32_t*>(d.tab + 1024);
     const uint64_t V = (uint64_t)d.X * d.Y * d.Z * d.T;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < V; v += stride) {
         const float f = __builtin_nontemporal_load(d.field + v);
-        const Mask8 m = band_mask(tb, d.Q, f);
+        const uint32_t r = (uint32_t)rank_le(s_b, d.Q, f) | ((uint32_t)rank_ge(s_b + 256, d.Q, f) << 16);
+        d.vrank[v] = r;
         uint4* o = reinterpret_cast<uint4*>(d.fplanes + v * 8);
         o[0] = make_uint4(0, 0, 0, 0);
         o[1] = make_uint4(0, 0, 0, 0);
         uint32_t any = 0;
+        if ((r & 0xFFFFu) && (r >> 16)) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) any |= m.w[k];
+            for (int k = 0; k < 8; ++k) any |= rank_word(ftab, r, k);
+        }
         if (any) {
             const int x = (int)(v % d.X);
             const uint64_t r = v / d.X;
@@ -202,7 +233,10 @@ __global__ __launch_bounds__(256) void kb_admit_field(DevB d) {
 // query and lying in a voxel, as (flat step index, canonical voxel index).
 __global__ __launch_bounds__(256) void kb_admit_particles(DevB d) {
     __shared__ uint32_t s_tmp[20];
-    const BandTables tb = particle_tables(d);
+    __shared__ float s_b[512];
+    stage_bounds(d, 1, s_b);
+    __syncthreads();
+    const uint32_t* ptab = reinterpret_cast<const uint32_t*>(d.tab + 1024) + 2 * 257 * 8;
     const uint64_t n = (uint64_t)d.P * d.Tpad;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t np = (uint64_t)d.Tp * d.P * 2;  // uint4 per particle-step: 2
@@ -214,10 +248,13 @@ __global__ __launch_bounds__(256) void kb_admit_particles(DevB d) {
         uint32_t vox = 0;
         if (e < n) {
             const float a = d.attr_t[e];
-            const Mask8 m = band_mask(tb, d.Q, a);
+            const uint32_t r = (uint32_t)rank_le(s_b, d.Q, a) | ((uint32_t)rank_ge(s_b + 256, d.Q, a) << 16);
+            d.prank[e] = r;
             uint32_t any = 0;
+            if ((r & 0xFFFFu) && (r >> 16)) {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) any |= m.w[k];
+                for (int k = 0; k < 8; ++k) any |= rank_word(ptab, r, k);
+            }
             const uint32_t b = d.bins[e];
             if (any && b != kNoVoxel) {
                 int x, y, z, t;
@@ -250,7 +287,7 @@ __global__ void kb_seeds(DevB d, const int32_t* __restrict__ seeds, int64_t S) {
 // point: Jacobi steps through LDS over the 8 in-tile neighbours, the out-of-
 // tile neighbours entering as fixed halos.
 __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_lab,
-                            uint32_t* s_flags) {
+                            uint32_t* s_flags, const uint32_t* s_ftab) {
     int bx, by, bz, bt;
     btile_coords(d, tile, bx, by, bz, bt);
     const int tid = threadIdx.x;
@@ -263,38 +300,41 @@ __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_l
     if (tid == 0) {
         d.dirty[par * d.NTB + tile] = 0u;
         s_flags[0] = 0;
+        s_flags[1] = 0;
+        s_flags[2] = 0;
     }
     uint32_t a[8], l[8], l0[8], h[8];
     const uint64_t v = in ? vindex(d, x, y, z, t) : 0;
     if (in) {
-        const Mask8 m = band_mask(field_tables(d), d.Q, d.field[v]);
+        const uint32_t rv = d.vrank[v];
         const uint4* lp = reinterpret_cast<const uint4*>(d.fplanes + v * 8);
         const uint4 l01 = lp[0], l23 = lp[1];
         l[0] = l01.x; l[1] = l01.y; l[2] = l01.z; l[3] = l01.w;
         l[4] = l23.x; l[5] = l23.y; l[6] = l23.z; l[7] = l23.w;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            a[k] = m.w[k];
+            a[k] = rank_word(s_ftab, rv, k);
             h[k] = 0;
         }
-        // halos: neighbours outside the tile (inside the grid)
+        // halos: neighbours outside the tile (inside the grid), each load
+        // issued on its own condition (no indexed list: it would live in
+        // scratch memory)
         const uint64_t sx = 1, sy = d.X, sz = (uint64_t)d.X * d.Y, st = sz * d.Z;
-        uint64_t hn[8];
-        int nh = 0;
-        if (xl == 0 && x > 0) hn[nh++] = v - sx;
-        if (xl == mx && x + 1 < d.X) hn[nh++] = v + sx;
-        if (yl == 0 && y > 0) hn[nh++] = v - sy;
-        if (yl == my && y + 1 < d.Y) hn[nh++] = v + sy;
-        if (zl == 0 && z > 0) hn[nh++] = v - sz;
-        if (zl == mz && z + 1 < d.Z) hn[nh++] = v + sz;
-        if (tl == 0 && t > 0) hn[nh++] = v - st;
-        if (tl == mt && t + 1 < d.T) hn[nh++] = v + st;
-        for (int i = 0; i < nh; ++i) {
-            const uint4* hp = reinterpret_cast<const uint4*>(d.fplanes + hn[i] * 8);
+        auto halo = [&](bool has, uint64_t nv) {
+            if (!has) return;
+            const uint4* hp = reinterpret_cast<const uint4*>(d.fplanes + nv * 8);
             const uint4 h01 = hp[0], h23 = hp[1];
             h[0] |= h01.x; h[1] |= h01.y; h[2] |= h01.z; h[3] |= h01.w;
             h[4] |= h23.x; h[5] |= h23.y; h[6] |= h23.z; h[7] |= h23.w;
-        }
+        };
+        halo(xl == 0 && x > 0, v - sx);
+        halo(xl == mx && x + 1 < d.X, v + sx);
+        halo(yl == 0 && y > 0, v - sy);
+        halo(yl == my && y + 1 < d.Y, v + sy);
+        halo(zl == 0 && z > 0, v - sz);
+        halo(zl == mz && z + 1 < d.Z, v + sz);
+        halo(tl == 0 && t > 0, v - st);
+        halo(tl == mt && t + 1 < d.T, v + st);
     } else {
 #pragma unroll
         for (int k = 0; k < 8; ++k) a[k] = l[k] = h[k] = 0;
@@ -307,23 +347,47 @@ __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_l
     const int nz0 = zl > 0 ? tid - szl : -1, nz1 = zl < mz ? tid + szl : -1;
     const int nt0 = tl > 0 ? tid - stl : -1, nt1 = tl < mt ? tid + stl : -1;
     const int nbr[8] = {nx0, nx1, ny0, ny1, nz0, nz1, nt0, nt1};
-    while (true) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) s_lab[k * 512 + tid] = l[k];
-        __syncthreads();
-        uint32_t diff = 0;
+    // Words that can change in this visit: some voxel has room to grow in the
+    // word (admissible, not a member) and some voxel or halo holds members of
+    // it.  Most tiles carry few of the 8 words' queries; the others are left
+    // out of the Jacobi steps (block-uniform).
+    {
+        uint32_t room = 0, src = 0;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            uint32_t nbv = l[k] | h[k];
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                if (nbr[j] >= 0) nbv |= s_lab[k * 512 + nbr[j]];
-            const uint32_t s = nbv & a[k];
-            diff |= s ^ l[k];
-            l[k] = s;
+            room |= (a[k] & ~l[k]) ? 1u << k : 0u;
+            src |= (l[k] | h[k]) ? 1u << k : 0u;
         }
+        __syncthreads();  // the flags were cleared
+        if (room) atomicOr(&s_flags[1], room);
+        if (src) atomicOr(&s_flags[2], src);
+        __syncthreads();
+    }
+    const uint32_t need = s_flags[1] & s_flags[2];
+    // The eight words are written out one by one (the register arrays stay
+    // in registers only with constant indices).
+#define MF4D_STORE_WORD(k) \
+    if ((need >> (k)) & 1u) s_lab[(k) * 512 + tid] = l[k];
+#define MF4D_STEP_WORD(k)                                                   \
+    if ((need >> (k)) & 1u) {                                               \
+        uint32_t nbv = l[k] | h[k];                                         \
+        _Pragma("unroll") for (int j = 0; j < 8; ++j)                       \
+            if (nbr[j] >= 0) nbv |= s_lab[(k) * 512 + nbr[j]];              \
+        const uint32_t sv = nbv & a[k];                                     \
+        diff |= sv ^ l[k];                                                  \
+        l[k] = sv;                                                          \
+    }
+    while (need) {
+        MF4D_STORE_WORD(0) MF4D_STORE_WORD(1) MF4D_STORE_WORD(2) MF4D_STORE_WORD(3)
+        MF4D_STORE_WORD(4) MF4D_STORE_WORD(5) MF4D_STORE_WORD(6) MF4D_STORE_WORD(7)
+        __syncthreads();
+        uint32_t diff = 0;
+        MF4D_STEP_WORD(0) MF4D_STEP_WORD(1) MF4D_STEP_WORD(2) MF4D_STEP_WORD(3)
+        MF4D_STEP_WORD(4) MF4D_STEP_WORD(5) MF4D_STEP_WORD(6) MF4D_STEP_WORD(7)
         if (!__syncthreads_or(diff != 0)) break;
     }
+#undef MF4D_STORE_WORD
+#undef MF4D_STEP_WORD
     uint32_t any = 0;
     if (in) {
 #pragma unroll
@@ -369,14 +433,46 @@ __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_l
     __syncthreads();
 }
 
+// A round's sweep.  Rounds are queued ahead of the host: a round whose work
+// list is empty does nothing (its sweep records that for the round's pull and
+// close), and BC_ROUNDS counts the rounds that had work.
 __global__ __launch_bounds__(512) void kb_sweep(DevB d, int par) {
     __shared__ uint32_t s_lab[8 * 512];
     __shared__ uint32_t s_flags[4];
-    if (blockIdx.x == 0 && threadIdx.x == 0) d.counters[BC_NDIRTYP] = 0;
-    const uint32_t nwork = d.counters[BC_NWORK0 + par];
+    __shared__ uint32_t s_ftab[kLdsTab];
+    __shared__ uint32_t s_pref[kBSubs + 1];  // sub-list prefix sums
+    if (threadIdx.x < kBSubs) {
+        // the first wave scans the sub-list lengths
+        const uint32_t c = d.wcnt[((uint32_t)par * kBSubs + threadIdx.x) * kBCntStride];
+        uint32_t x = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o);
+            if ((int)threadIdx.x >= o) x += y;
+        }
+        s_pref[threadIdx.x + 1] = x;
+        if (threadIdx.x == 0) s_pref[0] = 0;
+    }
+    __syncthreads();
+    const uint32_t nwork = s_pref[kBSubs];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        d.counters[BC_NDIRTYP] = 0;
+        d.counters[BC_RACT] = nwork ? 1u : 0u;
+        if (nwork) d.counters[BC_ROUNDS] += 1u;
+    }
+    if (blockIdx.x >= nwork) return;  // block-uniform
+    stage_tables(d, 0, s_ftab);
+    __syncthreads();
     uint32_t visits = 0;
     for (uint32_t w = blockIdx.x; w < nwork; w += gridDim.x) {
-        bsweep_tile(d, d.work[par * d.NTB + w], par, s_lab, s_flags);
+        // the sub-list holding flat item w: the last j with s_pref[j] <= w
+        int lo = 0, hi = kBSubs;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (s_pref[mid] <= w) lo = mid; else hi = mid;
+        }
+        const uint32_t tile = d.work[((size_t)par * kBSubs + lo) * d.WCAPB + (w - s_pref[lo])];
+        bsweep_tile(d, tile, par, s_lab, s_flags, s_ftab);
         ++visits;
     }
     if (threadIdx.x == 0 && visits) atomicAdd(&d.stat64[S_TILE_VISITS], (unsigned long long)visits);
@@ -386,8 +482,10 @@ __global__ __launch_bounds__(512) void kb_sweep(DevB d, int par) {
 // it is admissible.
 __global__ __launch_bounds__(256) void kb_pull(DevB d, int par) {
     __shared__ uint32_t s_tmp[20];
-    if (blockIdx.x == 0 && threadIdx.x == 0) d.counters[BC_NWORK0 + par] = 0;
-    const BandTables tb = particle_tables(d);
+    if (!d.counters[BC_RACT]) return;
+    // the swept list is empty again (its dirty flags were cleared by the sweeps)
+    if (blockIdx.x == 0 && threadIdx.x < kBSubs) d.wcnt[((uint32_t)par * kBSubs + threadIdx.x) * kBCntStride] = 0u;
+    const uint32_t* ptab = reinterpret_cast<const uint32_t*>(d.tab + 1024) + 2 * 257 * 8;
     const uint32_t n = d.counters[BC_NLIST];
     for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < n; b0 += gridDim.x * blockDim.x) {
         const uint32_t i = b0 + threadIdx.x;
@@ -415,10 +513,10 @@ __global__ __launch_bounds__(256) void kb_pull(DevB d, int par) {
                     any |= m.w[k] != 0;
                 }
                 if (any) {
-                    const Mask8 am = band_mask(tb, d.Q, d.attr_t[ent.x]);
+                    const uint32_t rp = d.prank[ent.x];
 #pragma unroll
                     for (int k = 0; k < 8; ++k) {
-                        const uint32_t nw = m.w[k] & am.w[k];
+                        const uint32_t nw = m.w[k] & rank_word(ptab, rp, k);
                         if (nw && (~atomicOr(&lp[k], nw) & nw)) got = true;
                     }
                 }
@@ -433,59 +531,116 @@ __global__ __launch_bounds__(256) void kb_pull(DevB d, int par) {
     }
 }
 
-// Close and push one particle for every query plane: forward and backward
-// passes along its steps spread members over admissible runs (the forward
-// pass alone with forward-only coupling); each step that gains queries pushes
-// them into its voxel where the voxel is admissible.
-__device__ void bclose_particle(const DevB& d, uint32_t p, int par) {
-    atomicAnd(&d.pdirty[p >> 5], ~(1u << (p & 31)));
-    const BandTables tp = particle_tables(d);
-    const BandTables tf = field_tables(d);
+// Close and push the dirty particles for every query plane, eight lanes per
+// particle: lane k of a group of eight carries word k (queries 32k .. 32k +
+// 31) along the particle's steps.  A forward and a backward pass spread the
+// members over admissible runs (the forward pass alone with forward-only
+// coupling); a step that gains queries pushes them into its voxel where the
+// voxel is admissible, and one lane of the group marks the voxel when any
+// word of it was gained.  The steps go in chunks of kChunk: every load of a
+// chunk (labels, ranks, bins; then the pushed voxels' ranks; then their
+// atomics) is issued together, so a chunk costs a few round trips instead of
+// a few per step.  Every lane runs every chunk (ballots).
+constexpr int kChunk = 16;
+
+__global__ __launch_bounds__(256) void kb_close(DevB d, int par) {
+    __shared__ uint32_t s_ptab[kLdsTab];
+    __shared__ uint32_t s_ftab[kLdsTab];
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    if (!d.counters[BC_RACT]) return;
+    for (uint32_t i = tid; i < d.NTB; i += stride) d.chg[par * d.NTB + i] = 0;
+    const uint32_t nd = d.counters[BC_NDIRTYP];
+    if (tid == 0 && nd) atomicAdd(&d.stat64[S_PART_VISITS], (unsigned long long)nd);
+    const uint32_t per_block = (blockDim.x >> 6) * 8;
+    if ((uint64_t)blockIdx.x * per_block >= nd) return;  // block-uniform
+    stage_tables(d, 1, s_ptab);
+    stage_tables(d, 0, s_ftab);
+    __syncthreads();
+    const int lane = lane_id(), k = lane & 7, grp = lane >> 3;
+    const int npar = par ^ 1;
     const int ndir = d.forward_only ? 1 : 2;
-    for (int dir = 0; dir < ndir; ++dir) {
-        uint32_t carry[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (int i = 0; i < d.Tp; ++i) {
-            const int t = dir == 0 ? i : d.Tp - 1 - i;
-            uint32_t* lp = d.pplanes + ((uint64_t)t * d.P + p) * 8;
-            const Mask8 am = band_mask(tp, d.Q, d.attr_t[(uint64_t)p * d.Tpad + t]);
-            uint32_t nw[8];
-            uint32_t anynew = 0;
+    const int nch = (d.Tp + kChunk - 1) / kChunk;
+    const uint32_t wave = tid >> 6, nwaves = stride >> 6;
+    for (uint32_t base = wave * 8; base < nd; base += nwaves * 8) {  // wave-uniform
+        const uint32_t i = base + grp;
+        const bool valid = i < nd;
+        const uint32_t p = valid ? d.dlist[i] : 0u;
+        if (valid && k == 0) atomicAnd(&d.pdirty[p >> 5], ~(1u << (p & 31)));
+        for (int dir = 0; dir < ndir; ++dir) {
+            uint32_t carry = 0;
+            for (int ci = 0; ci < nch; ++ci) {
+                const int c0 = (dir == 0 ? ci : nch - 1 - ci) * kChunk;
+                const int cn = d.Tp - c0 < kChunk ? d.Tp - c0 : kChunk;
+                uint32_t cur[kChunk], rk[kChunk], bb[kChunk];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const uint32_t cur = lp[k];
-                const uint32_t l = cur | (carry[k] & am.w[k]);
-                nw[k] = l & ~cur;
-                anynew |= nw[k];
-                carry[k] = l;
+                for (int j = 0; j < kChunk; ++j) {
+                    cur[j] = 0;
+                    rk[j] = 0;
+                    bb[j] = kNoVoxel;
+                    if (valid && j < cn) {
+                        const uint64_t e = (uint64_t)p * d.Tpad + c0 + j;
+                        cur[j] = d.pplanes[((uint64_t)(c0 + j) * d.P + p) * 8 + k];
+                        rk[j] = d.prank[e];
+                        bb[j] = d.bins[e];
+                    }
+                }
+                uint32_t nw[kChunk];
+#pragma unroll
+                for (int jj = 0; jj < kChunk; ++jj) {
+                    const int j = dir == 0 ? jj : kChunk - 1 - jj;
+                    nw[j] = 0;
+                    if (j < cn) {
+                        const uint32_t l = cur[j] | (carry & rank_word(s_ptab, rk[j], k));
+                        nw[j] = l & ~cur[j];
+                        carry = l;
+                    }
+                }
+                // new bits: the labels, then the pushed voxels' ranks, then
+                // their label atomics, each for the whole chunk at once
+                uint64_t vv[kChunk];
+#pragma unroll
+                for (int j = 0; j < kChunk; ++j) {
+                    if (nw[j]) atomicOr(&d.pplanes[((uint64_t)(c0 + j) * d.P + p) * 8 + k], nw[j]);
+                    const bool gnew = ((__ballot(nw[j] != 0) >> (8 * grp)) & 0xFFull) != 0;
+                    vv[j] = ~0ull;
+                    if (gnew && bb[j] != kNoVoxel) {
+                        int x, y, z, tt;
+                        bit_to_xyzt(d.g, bb[j], x, y, z, tt);
+                        vv[j] = vindex(d, x, y, z, tt);
+                    }
+                }
+                uint32_t rv[kChunk];
+#pragma unroll
+                for (int j = 0; j < kChunk; ++j) rv[j] = vv[j] != ~0ull && nw[j] ? d.vrank[vv[j]] : 0u;
+                uint32_t got[kChunk];
+#pragma unroll
+                for (int j = 0; j < kChunk; ++j) {
+                    got[j] = 0;
+                    if (vv[j] != ~0ull && nw[j]) {
+                        const uint32_t pw = nw[j] & rank_word(s_ftab, rv[j], k);
+                        if (pw) got[j] = ~atomicOr(&d.fplanes[vv[j] * 8 + k], pw) & pw;
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < kChunk; ++j) {
+                    const uint32_t gg = (uint32_t)(__ballot(got[j] != 0) >> (8 * grp)) & 0xFFu;
+                    if (got[j] && k == __builtin_ctz(gg)) {
+                        int x, y, z, tt;
+                        bit_to_xyzt(d.g, bb[j], x, y, z, tt);
+                        bmark_voxel(d, x, y, z, tt, npar);
+                    }
+                }
             }
-            if (!anynew) continue;
-#pragma unroll
-            for (int k = 0; k < 8; ++k)
-                if (nw[k]) atomicOr(&lp[k], nw[k]);
-            const uint32_t b = d.bins[(uint64_t)p * d.Tpad + t];
-            if (b == kNoVoxel) continue;
-            int x, y, z, tt;
-            bit_to_xyzt(d.g, b, x, y, z, tt);
-            const uint64_t v = vindex(d, x, y, z, tt);
-            const Mask8 af = band_mask(tf, d.Q, d.field[v]);
-            bool gained = false;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const uint32_t pw = nw[k] & af.w[k];
-                if (pw && (~atomicOr(&d.fplanes[v * 8 + k], pw) & pw)) gained = true;
-            }
-            if (gained) bmark_voxel(d, x, y, z, tt, par);
         }
     }
 }
 
-__global__ __launch_bounds__(256) void kb_close(DevB d, int par) {
-    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t i = tid; i < d.NTB; i += stride) d.chg[par * d.NTB + i] = 0;
-    const uint32_t nd = d.counters[BC_NDIRTYP];
-    if (tid == 0 && nd) atomicAdd(&d.stat64[S_PART_VISITS], (unsigned long long)nd);
-    for (uint32_t i = tid; i < nd; i += stride) bclose_particle(d, d.dlist[i], par ^ 1);
+// Total length of the work list of parity par, for the host.
+__global__ void kb_work_total(DevB d, int par) {
+    uint32_t x = d.wcnt[((uint32_t)par * kBSubs + threadIdx.x) * kBCntStride];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    if (threadIdx.x == 0) d.counters[BC_NWORK0 + par] = x;
 }
 
 __global__ void kb_reset(DevB d) {
@@ -498,6 +653,7 @@ __global__ void kb_reset(DevB d) {
         reinterpret_cast<uint32_t*>(d.active)[i] = 0;
     for (uint64_t i = tid; i < (uint64_t)(d.P + 31) / 32; i += stride) d.pdirty[i] = 0;
     if (tid < BC_NCOUNTERS) d.counters[tid] = 0;
+    if (tid < 2 * kBSubs) d.wcnt[tid * kBCntStride] = 0;
     if (tid < S_NSTAT) d.stat64[tid] = 0;
 }
 
@@ -533,7 +689,7 @@ void launch_b_prepare(const DevB& d, const int32_t* seeds, int64_t S, hipStream_
     const uint64_t V = (uint64_t)d.X * d.Y * d.Z * d.T;
     hipLaunchKernelGGL(kb_reset, dim3(grid_for(2ull * d.NTB + d.P / 32 + 1, 256, 2048)), dim3(256),
                        0, s, d);
-    hipLaunchKernelGGL(kb_admit_field, dim3(grid_for(V, 256, 16384)), dim3(256), 0, s, d);
+    hipLaunchKernelGGL(kb_admit_field, dim3(grid_for(V, 256, 4096)), dim3(256), 0, s, d);
     if (d.P > 0)
         hipLaunchKernelGGL(kb_admit_particles,
                            dim3(grid_for((uint64_t)d.P * d.Tpad, 256, 8192)), dim3(256), 0, s, d);
@@ -541,9 +697,9 @@ void launch_b_prepare(const DevB& d, const int32_t* seeds, int64_t S, hipStream_
         hipLaunchKernelGGL(kb_seeds, dim3(grid_for(S, 256, 1u << 20)), dim3(256), 0, s, d, seeds, S);
 }
 
-void launch_b_round(const DevB& d, uint32_t round, uint32_t nwork_host, hipStream_t s) {
+void launch_b_round(const DevB& d, uint32_t round, hipStream_t s) {
     const int par = round & 1;
-    hipLaunchKernelGGL(kb_sweep, dim3(grid_for(nwork_host, 1, 8192)), dim3(512), 0, s, d, par);
+    hipLaunchKernelGGL(kb_sweep, dim3(grid_for(d.NTB, 1, 2048)), dim3(512), 0, s, d, par);
     if (d.P > 0) {
         hipLaunchKernelGGL(kb_pull, dim3(grid_for((uint64_t)d.P * d.Tpad, 256, 2048)), dim3(256), 0,
                            s, d, par);
@@ -552,6 +708,10 @@ void launch_b_round(const DevB& d, uint32_t round, uint32_t nwork_host, hipStrea
     } else {
         hipLaunchKernelGGL(kb_close, dim3(grid_for(d.NTB, 256, 2048)), dim3(256), 0, s, d, par);
     }
+}
+
+void launch_b_work_total(const DevB& d, int par, hipStream_t s) {
+    hipLaunchKernelGGL(kb_work_total, dim3(1), dim3(64), 0, s, d, par);
 }
 
 void launch_b_count(const DevB& d, hipStream_t s) {

@@ -269,3 +269,40 @@ def test_long_trajectories(T, schedule):
     inst = synth.make_instance(40, 24, 16, T, 1500, n_blobs=4, seed=T, n_seeds=4, tau_f=0.3,
                                tau_p=0.15, attr_mode="noise")
     _assert_parity(inst, tag=f"long T={T} {schedule}", schedule=schedule)
+
+
+@pytest.mark.parametrize("schedule", ["persistent", "launch"])
+def test_phase_timing_fills_device_times(schedule):
+    """With phase timing on, a grow (and a capped grow then its resume)
+    reports device times of its phases, and the masks are the oracle's;
+    with it off the times read 0."""
+    from paper_1903_12294_amd import Grower
+    from paper_1903_12294_amd._lib import MF4DError
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    inst = synth.make_config(1)
+    ofm, opm, _ = oracle_grow(inst["field"], inst["xyz"], inst["attr"], inst["crit"], inst["seeds"])
+    g = Grower(device=0, schedule=schedule)
+    try:
+        g.load_field(inst["field"])
+        g.load_particles(inst["xyz"], inst["attr"])
+        g.set_criteria(*inst["crit"])
+        g.set_seeds(inst["seeds"])
+        g.set_phase_timing(True)
+        st = g.grow()
+        assert st["ms_total"] > 0 and st["ms_rounds"] > 0 and st["ms_admit"] > 0
+        assert np.array_equal(g.read_field_mask(), ofm) and np.array_equal(g.read_particle_mask(), opm)
+        g.set_max_rounds(1)
+        with pytest.raises(MF4DError):
+            g.grow()
+        g.set_max_rounds(0)
+        st = g.grow_resume()
+        assert st["ms_rounds"] > 0
+        assert np.array_equal(g.read_field_mask(), ofm)
+        g.set_phase_timing(False)
+        st = g.grow()
+        assert st["ms_total"] == 0
+        assert np.array_equal(g.read_field_mask(), ofm) and np.array_equal(g.read_particle_mask(), opm)
+        assert g.stats()["members_particle"] == int(opm.sum())
+    finally:
+        g.close()
