@@ -119,17 +119,15 @@ class Timer:
 
 def run_steps(g, fmask, pmask, steps: int, warmup: int, torch, instrumented: bool = False):
     """Warm up, then time `steps` steps; per step: grow, field read, particle
-    read.  Uninstrumented (the headline): two events around the whole loop and
-    nothing else.  Instrumented: the library records its phase events and each
+    read.  Uninstrumented (the headline): one grow_read call per step, two
+    events around the whole loop and nothing else.  Instrumented: grow and
+    the two read calls apart, the library records its phase events and each
     step's read-out is bracketed by events (both cost device time)."""
     g.set_phase_timing(instrumented)
 
     def step():
-        st = g.grow()
-        g.read_field_mask(fmask)
-        if pmask is not None:
-            g.read_particle_mask(pmask)
-        return st
+        # the grow with both read-outs queued behind its rounds (one call)
+        return g.grow_read(fmask, pmask)
 
     for _ in range(warmup):
         step()

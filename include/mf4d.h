@@ -270,6 +270,24 @@ int mf4d_read_field_mask(mf4d_ctx *ctx, uint32_t *dst, size_t nwords, int where)
  * Errors: MF4D_ERR_STATE (nothing grown or no particles), MF4D_ERR_ARG. */
 int mf4d_read_particle_mask(mf4d_ctx *ctx, uint8_t *dst, size_t n, int where);
 
+/* mf4d_grow followed by mf4d_read_field_mask and mf4d_read_particle_mask
+ * into device buffers, in one call: the same labels, masks and statistics.
+ * The read-outs are queued on the device behind the rounds, before the host
+ * waits to learn that the rounds reached the fixed point, and run only if
+ * they did (else they are queued again after the rounds that remain); the
+ * particle read-out runs on a second stream beside the field read-out.  With
+ * a score-ordered scheduler, Jacobi sweeps or phase timing the read-outs
+ * follow the grow as separate calls would.  field_dst (nwords >=
+ * ceil(X*Y*Z*T / 32) words) and particle_dst (n >= T*P bytes) are device
+ * buffers; either may be NULL to skip that read-out.  Ordered on the
+ * context's stream like the MF4D_DEVICE reads: the masks are ready for later
+ * work on that stream when the call returns.  On MF4D_ERR_NOT_CONVERGED the
+ * masks hold the labels as the round cap left them.
+ * Errors: as mf4d_grow; MF4D_ERR_STATE (particle_dst without particles),
+ * MF4D_ERR_ARG (a buffer too small). */
+int mf4d_grow_read(mf4d_ctx *ctx, uint32_t *field_dst, size_t nwords, uint8_t *particle_dst, size_t n,
+                   mf4d_stats *out);
+
 /* Trajectory segments of the grown feature (Section 3.4, visual
  * representation): a trajectory is split where it leaves the feature, and
  * only pieces of at least two consecutive member steps are kept.  Writes

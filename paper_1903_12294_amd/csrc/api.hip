@@ -145,6 +145,9 @@ struct mf4d_ctx {
     uint32_t* dlist = nullptr;
     float2* psum = nullptr;
 
+    // the statistics (S_NSTAT words) and right after them the counters
+    // (C_NCOUNTERS), one allocation on the device and one on the host, so
+    // that one copy brings both back
     uint32_t* counters = nullptr;
     unsigned long long* stat64 = nullptr;
     unsigned long long* slots = nullptr;  // per-block partial statistics
@@ -182,6 +185,12 @@ struct mf4d_ctx {
     bool labels_marked = false;
     hipEvent_t ev_pread = nullptr;    // the particle read-out on the side stream is done
     bool stats_ready = false;         // h_stat / h_counters already hold this grow's statistics
+    // read-outs of mf4d_grow_read, queued behind the rounds (device buffers)
+    uint32_t* rd_f = nullptr;
+    uint8_t* rd_p = nullptr;
+    bool reads_done = false;          // the queued read-outs ran on the final labels
+    hipEvent_t ev_chunk = nullptr;    // end of the last queued chunk of rounds
+    hipEvent_t ev_stat = nullptr;     // its statistics copied to the host
 
     // batched queries
     int Q = 0;
@@ -370,6 +379,8 @@ int read_counters(mf4d_ctx* c) {
     return sync(c);
 }
 
+constexpr size_t kStatBytes = S_NSTAT * sizeof(unsigned long long) + C_NCOUNTERS * sizeof(uint32_t);
+
 Dev make_dev(mf4d_ctx* c) {
     Dev d{};
     d.g = c->g;
@@ -403,6 +414,43 @@ Dev make_dev(mf4d_ctx* c) {
     d.forward_only = c->forward_only;
     for (int i = 0; i < 4; ++i) d.crit[i] = c->crit[i];
     return d;
+}
+
+// Queue the read-outs of mf4d_grow_read behind the rounds queued so far: the
+// particle labels on the side stream (after ev_chunk), the field labels on
+// the context stream, which then waits for the side stream.  With a closed
+// gate they do nothing.
+int queue_reads(mf4d_ctx* c, const ReadGate& gate) {
+    const Dev d = make_dev(c);
+    hipStream_t s = c->stream;
+    if (c->rd_p) {
+        HIP_TRY(hipStreamWaitEvent(c->side, c->ev_chunk, 0));
+        launch_read_particles(d, c->rd_p, c->side, gate);
+        launch_fold_slots(d, SL_MEMBERS_P, S_MEMBERS_P, c->side, true);
+        HIP_TRY(hipEventRecord(c->ev_pread, c->side));
+    }
+    if (c->rd_f) {
+        launch_read_field(d, c->rd_f, s, gate);
+        launch_fold_slots(d, SL_MEMBERS_F, S_MEMBERS_F, s, true);
+    }
+    if (c->rd_p) HIP_TRY(hipStreamWaitEvent(s, c->ev_pread, 0));
+    return MF4D_OK;
+}
+
+// Statistics and counters to the host in one copy; read-outs pending are
+// queued behind it (they run while the host waits for the copy only).
+int read_chunk(mf4d_ctx* c, const ReadGate& gate) {
+    hipStream_t s = c->stream;
+    HIP_TRY(hipEventRecord(c->ev_chunk, s));
+    HIP_TRY(hipMemcpyAsync(c->h_stat, c->stat64, kStatBytes, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(c->ev_stat, s));
+    if (c->rd_f || c->rd_p) {
+        int rc = queue_reads(c, gate);
+        if (rc) return rc;
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventSynchronize(c->ev_stat));
+    return MF4D_OK;
 }
 
 // Jacobi sweeps until one adds nothing (converged) or the cap is hit; each
@@ -456,10 +504,11 @@ int run_rounds(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
         }
         if (launch_rounds_persistent(d, r0, cap, c->device, c->stream)) {
             launch_fold_grow_slots(d, c->stream);
-            HIP_TRY(hipMemcpyAsync(c->h_stat, c->stat64, S_NSTAT * sizeof(unsigned long long),
-                                   hipMemcpyDeviceToHost, c->stream));
-            int rc = read_counters(c);
+            // read-outs pending run unconditionally: the launch ran every
+            // round it was going to
+            int rc = read_chunk(c, ReadGate{});
             if (rc) return rc;
+            c->reads_done = c->rd_f || c->rd_p;
             c->stats_ready = true;
             if (c->h_counters[C_ERR] == 0) {
                 const uint32_t done = c->h_counters[C_ROUNDS];
@@ -492,13 +541,13 @@ int run_rounds(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
         }
         for (int64_t k = 0; k < chunk; ++k)
             launch_round(d, (uint32_t)(c->round + k), c->stream, c->timed ? c->rev + 4 * k : nullptr);
-        launch_work_total(d, (int)((c->round + chunk) & 1), c->stream);
-        // the grow's statistics come back with the same read, so that
-        // finish_stats needs no wait of its own after the last chunk
-        launch_fold_grow_slots(d, c->stream);
-        HIP_TRY(hipMemcpyAsync(c->h_stat, c->stat64, S_NSTAT * sizeof(unsigned long long),
-                               hipMemcpyDeviceToHost, c->stream));
-        int rc = read_counters(c);
+        // work total and the grow's statistics, read back together, so that
+        // finish_stats needs no wait of its own after the last chunk; the
+        // read-outs pending are queued gated on this chunk reaching the
+        // fixed point
+        const int npar = (int)((c->round + chunk) & 1);
+        launch_chunk_end(d, npar, c->stream);
+        int rc = read_chunk(c, ReadGate{c->counters, (uint32_t)(r + chunk), npar});
         if (rc) return rc;
         c->stats_ready = true;
         const int64_t done = (int64_t)c->h_counters[C_ROUNDS] - r;
@@ -512,6 +561,7 @@ int run_rounds(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
         r += done;
         if (done < chunk || c->h_counters[C_NWORK0 + (c->round & 1)] == 0) {
             c->state = 1;
+            c->reads_done = c->rd_f || c->rd_p;  // their gate was open
             break;
         }
     }
@@ -522,10 +572,7 @@ int run_rounds(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
 int finish_stats(mf4d_ctx* c, mf4d_stats* out, bool fresh, int64_t rounds) {
     if (!c->stats_ready) {  // else the last read of the rounds brought them
         launch_fold_grow_slots(make_dev(c), c->stream);
-        HIP_TRY(hipMemcpyAsync(c->h_stat, c->stat64, S_NSTAT * sizeof(unsigned long long),
-                               hipMemcpyDeviceToHost, c->stream));
-        HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, C_NCOUNTERS * sizeof(uint32_t),
-                               hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipMemcpyAsync(c->h_stat, c->stat64, kStatBytes, hipMemcpyDeviceToHost, c->stream));
         int rc = sync(c);
         if (rc) return rc;
     }
@@ -575,7 +622,7 @@ extern "C" {
 
 // Bumped whenever a kernel changes: autotuner caches and recorded hardware
 // counter figures are keyed by it.
-const char* mf4d_version(void) { return "mf4d 0.7.0 (gfx950)"; }
+const char* mf4d_version(void) { return "mf4d 0.7.1 (gfx950)"; }
 
 const char* mf4d_last_error(void) { return g_err.c_str(); }
 
@@ -595,8 +642,9 @@ int mf4d_create(mf4d_ctx** out, int device, void* hip_stream) {
     if (!c) return fail(MF4D_ERR_OOM, "host allocation failed");
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
-    int rc = dev_alloc(&c->counters, C_NCOUNTERS);
-    if (!rc) rc = dev_alloc(&c->stat64, S_NSTAT);
+    static_assert(C_NCOUNTERS % 2 == 0, "counters fill whole 8-byte words");
+    int rc = dev_alloc(&c->stat64, S_NSTAT + C_NCOUNTERS / 2);
+    if (!rc) c->counters = reinterpret_cast<uint32_t*>(c->stat64 + S_NSTAT);
     if (!rc) rc = dev_alloc(&c->bar, kBarWords);
     if (!rc) rc = dev_alloc(&c->slots, (size_t)kSlotStats * kSlots);
     if (!rc) launch_fill_u32((uint32_t*)c->slots, 0, 2ull * kSlotStats * kSlots, c->stream);
@@ -606,17 +654,16 @@ int mf4d_create(mf4d_ctx** out, int device, void* hip_stream) {
         const char* adm = getenv("MF4D_ADMIT");
         if (adm && strcmp(adm, "all") == 0) c->admit_all = 1;
     }
-    if (!rc && hipHostMalloc((void**)&c->h_counters, C_NCOUNTERS * sizeof(uint32_t)) != hipSuccess)
+    if (!rc && hipHostMalloc((void**)&c->h_stat, kStatBytes) != hipSuccess)
         rc = fail(MF4D_ERR_OOM, "pinned host allocation failed");
-    if (!rc && hipHostMalloc((void**)&c->h_stat, S_NSTAT * sizeof(unsigned long long)) != hipSuccess)
-        rc = fail(MF4D_ERR_OOM, "pinned host allocation failed");
+    if (!rc) c->h_counters = reinterpret_cast<uint32_t*>(c->h_stat + S_NSTAT);
     for (int i = 0; !rc && i < 4; ++i)
         if (hipEventCreate(&c->ev[i]) != hipSuccess) rc = fail(MF4D_ERR_HIP, "hipEventCreate failed");
     for (int i = 0; !rc && i < 16; ++i)
         if (hipEventCreate(&c->rev[i]) != hipSuccess) rc = fail(MF4D_ERR_HIP, "hipEventCreate failed");
     if (!rc && hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess)
         rc = fail(MF4D_ERR_HIP, "hipStreamCreateWithFlags failed");
-    for (hipEvent_t* e : {&c->ev_labels, &c->ev_pread})
+    for (hipEvent_t* e : {&c->ev_labels, &c->ev_pread, &c->ev_chunk, &c->ev_stat})
         if (!rc && hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess)
             rc = fail(MF4D_ERR_HIP, "hipEventCreate failed");
     if (rc) {
@@ -635,7 +682,7 @@ void mf4d_destroy(mf4d_ctx* c) {
     if (c->side) (void)hipStreamSynchronize(c->side);
     free_field(c);
     free_particles(c);
-    dev_free(c->counters);
+    c->counters = nullptr;  // inside stat64
     dev_free(c->stat64);
     dev_free(c->slots);
     dev_free(c->bar);
@@ -660,9 +707,9 @@ void mf4d_destroy(mf4d_ctx* c) {
         c->staging = nullptr;
     }
     if (c->side) (void)hipStreamDestroy(c->side);
-    for (hipEvent_t e : {c->ev_labels, c->ev_pread})
+    for (hipEvent_t e : {c->ev_labels, c->ev_pread, c->ev_chunk, c->ev_stat})
         if (e) (void)hipEventDestroy(e);
-    if (c->h_counters) (void)hipHostFree(c->h_counters);
+    c->h_counters = nullptr;  // inside h_stat
     if (c->h_stat) (void)hipHostFree(c->h_stat);
     for (int i = 0; i < 4; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
@@ -1009,8 +1056,10 @@ int verify_round(mf4d_ctx* c, const Dev& d, int64_t* rounds) {
     return rc;
 }
 
-int mf4d_grow(mf4d_ctx* c, mf4d_stats* out) {
-    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+// A fresh grow; with rd_f / rd_p set, their read-outs are queued behind the
+// rounds where the schedule allows it (reads_done then reports whether they
+// ran on the final labels).
+int grow_impl(mf4d_ctx* c, mf4d_stats* out) {
     if (!c->has_field) return fail(MF4D_ERR_STATE, "no field loaded");
     if (!c->has_crit) return fail(MF4D_ERR_STATE, "no criteria set");
     HIP_TRY(hipSetDevice(c->device));
@@ -1081,6 +1130,55 @@ int mf4d_grow(mf4d_ctx* c, mf4d_stats* out) {
     if (out) *out = c->stats;
     mark_labels(c);
     if (c->state == 2) return fail(MF4D_ERR_NOT_CONVERGED, "stopped after %lld rounds", (long long)rounds);
+    return MF4D_OK;
+}
+
+int mf4d_grow(mf4d_ctx* c, mf4d_stats* out) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    c->rd_f = nullptr;
+    c->rd_p = nullptr;
+    return grow_impl(c, out);
+}
+
+int mf4d_grow_read(mf4d_ctx* c, uint32_t* field_dst, size_t nwords, uint8_t* particle_dst, size_t n,
+                   mf4d_stats* out) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    if (!c->has_field) return fail(MF4D_ERR_STATE, "no field loaded");
+    if (particle_dst && !c->has_particles) return fail(MF4D_ERR_STATE, "no particles loaded");
+    const uint64_t V = (uint64_t)c->g.X * c->g.Y * c->g.Z * c->g.T;
+    if (field_dst && nwords < (V + 31) / 32)
+        return fail(MF4D_ERR_ARG, "field_dst holds %zu words, %llu needed", nwords, (unsigned long long)((V + 31) / 32));
+    if (particle_dst && n < (size_t)c->pg.P * c->pg.T)
+        return fail(MF4D_ERR_ARG, "particle_dst holds %zu bytes, %zu needed", n, (size_t)c->pg.P * c->pg.T);
+    // Queued behind the rounds only where the labels are final when the
+    // rounds end: not with a verification round (score-ordered schedulers),
+    // Jacobi sweeps or phase timing (events per round).
+    const bool ordered = c->priority != MF4D_SCHEDULER_PLAIN && !c->admit_all;
+    const bool queue = !ordered && !c->phase_timing && c->schedule != MF4D_SCHED_JACOBI;
+    c->rd_f = queue ? field_dst : nullptr;
+    c->rd_p = queue ? particle_dst : nullptr;
+    c->reads_done = false;
+    int rc = grow_impl(c, out);
+    const bool done = c->reads_done;
+    c->rd_f = nullptr;
+    c->rd_p = nullptr;
+    c->reads_done = false;
+    if (rc != MF4D_OK && rc != MF4D_ERR_NOT_CONVERGED) return rc;
+    // the masks are those of the labels as they stand, converged or not
+    if (done) {
+        c->members_pending[0] = field_dst != nullptr;
+        c->members_pending[1] = particle_dst != nullptr;
+    } else {
+        if (field_dst) {
+            int r2 = mf4d_read_field_mask(c, field_dst, nwords, MF4D_DEVICE);
+            if (r2) return r2;
+        }
+        if (particle_dst) {
+            int r2 = mf4d_read_particle_mask(c, particle_dst, n, MF4D_DEVICE);
+            if (r2) return r2;
+        }
+    }
+    if (rc == MF4D_ERR_NOT_CONVERGED) return fail(rc, "stopped after %lld rounds", (long long)c->stats.rounds);
     return MF4D_OK;
 }
 

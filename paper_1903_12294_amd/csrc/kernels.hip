@@ -196,6 +196,28 @@ __device__ __forceinline__ uint32_t block_exclusive_scan256(uint32_t v, uint32_t
     return wbase + x - v;
 }
 
+// Exclusive prefix of a 64-bit v over a 256-thread block (four 16-bit
+// counters packed in one word scan together); `total` gets the block sum.
+// s_tmp: 10 words.  Every thread of the block must call it.
+__device__ __forceinline__ unsigned long long block_exclusive_scan256_u64(unsigned long long v, uint32_t* s_tmp,
+                                                                         unsigned long long& total) {
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    unsigned long long x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    unsigned long long* s64 = reinterpret_cast<unsigned long long*>(s_tmp);
+    if (lane == 63) s64[wave] = x;
+    __syncthreads();
+    unsigned long long wbase = 0;
+    for (int w = 0; w < wave; ++w) wbase += s64[w];
+    total = s64[0] + s64[1] + s64[2] + s64[3];
+    __syncthreads();
+    return wbase + x - v;
+}
+
 // Block-wide append: each thread reserves `n` slots; one atomic per block.
 __device__ __forceinline__ uint32_t block_append256(uint32_t n, uint32_t* counter, uint32_t* s_tmp) {
     uint32_t total;
@@ -389,11 +411,13 @@ __device__ void sweep_tile(const Dev& d, uint32_t tile, int par) {
     }
     // face bits that may be new to the tile across: those this sweep set, and
     // after pushes every member (the pushed bits are not known apart)
+    // A tile is swept by one wave per phase and nothing else writes its
+    // words meanwhile (pushes and seeds come in other phases): a plain store.
     uint32_t any = 0, fany = 0, fx0 = 0, fx1 = 0;
 #pragma unroll
     for (int t = 0; t < BT; ++t) {
         const uint32_t nw = l[t] & ~l0[t];
-        if (nw) atomicOr(&Lb[t * 64 + lane], nw);
+        if (nw) Lb[t * 64 + lane] = l[t];
         any |= nw;
         const uint32_t fb = pushed ? l[t] : nw;
         fany |= fb;
@@ -660,16 +684,38 @@ __device__ uint32_t close_phase(const Dev& d, int par, uint32_t wave_id, uint32_
     return closed;
 }
 
+// OR of v over the run of consecutive lanes that hold the same key as this
+// lane; the run's last lane (last = true) gets the whole run's OR.
+__device__ __forceinline__ unsigned long long run_or(uint32_t key, unsigned long long v, bool& last) {
+    const int lane = lane_id();
+    const uint32_t kp = (uint32_t)__shfl_up((int)key, 1), kn = (uint32_t)__shfl_down((int)key, 1);
+    last = lane == 63 || kn != key;
+    int h = (lane == 0 || kp != key) ? lane : 0;  // lane of the run's first entry
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(h, o);
+        if (lane >= o) h = max(h, y);
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long y = __shfl_up(v, o);
+        if (lane - o >= h) v |= y;
+    }
+    return v;
+}
+
 // Pull fused with close, for one 64-step label word per particle (W = 1).  A
-// wave takes 256 list entries at a time (4 per lane).  A coupled step whose
-// voxel is a member joins (atomicOr on its particle's label word); the thread
-// whose atomicOr sets the bit closes the particle's runs from the word it got
-// back plus its own bit.  Every bit set before that atomicOr is in the word it
-// returns, so the last setter of a word closes over all of them, and each bit
-// the closure adds is pushed by the thread that set it.  The new steps of the
-// wave are gathered in LDS (s_list: 256 words) and pushed 256 at a time, four
-// per lane (pushes schedule for parity par ^ 1).  Returns this lane's number
-// of joins.
+// wave takes 256 list entries at a time (4 per lane); the list holds a
+// particle's entries side by side, in step order.  A coupled step whose voxel
+// is a member joins; the joining steps of a run of lanes holding the same
+// particle are ORed into the run's last lane, which ORs their trajectory
+// closure into the particle's label word with one atomic.  The label words
+// only ever gain closed sets (closure distributes over union), so the bits
+// that atomic sets, less the joining steps themselves (in member voxels
+// already), are exactly the steps the closure adds; the lane that set them
+// pushes them.  The new steps of the wave are gathered in LDS (s_list: 256
+// words) and pushed 256 at a time, four per lane (pushes schedule for
+// parity par ^ 1).  Returns this lane's number of steps joined.
 __device__ uint32_t pull_close_wave(const Dev& d, int par, uint32_t wave_id, uint32_t nwaves,
                                     uint32_t n, uint32_t* s_list) {
     const PGeom& pg = d.pg;
@@ -695,23 +741,19 @@ __device__ uint32_t pull_close_wave(const Dev& d, int par, uint32_t wave_id, uin
         for (int k = 0; k < 4; ++k) {
             pk[k] = 0;
             nwk[k] = 0ull;
-            if (!mem[k]) continue;
+            if (!__ballot(mem[k])) continue;  // wave-uniform
             const uint32_t p = pg.logTpad >= 0 ? ent[k].x >> pg.logTpad : ent[k].x / (uint32_t)pg.Tpad;
             const uint32_t ts = ent[k].x - p * (uint32_t)pg.Tpad;
-            const unsigned long long bit = 1ull << ts;
-            if (d.Lp[p] & bit) continue;  // joined already: no atomic
-            const unsigned long long old = atomicOr(&d.Lp[p], bit);
-            if (old & bit) continue;
-            ++joins;
-            const unsigned long long known = old | bit;
-            const unsigned long long nw = close_word(known, d.Ap[p], d.forward_only) & ~known;
-            if (nw) {
-                // push only the bits this closure set: a concurrent joiner of
-                // the same run closes it too, and pushing it twice would double
-                // the push work (measured)
-                nwk[k] = nw & ~atomicOr(&d.Lp[p], nw);
-                pk[k] = p;
-            }
+            bool last;
+            const unsigned long long mine =
+                run_or(ent[k].y != kNoVoxel ? p : 0xFFFFFFFFu, mem[k] ? 1ull << ts : 0ull, last);
+            if (!last || !mine) continue;
+            if (!(mine & ~d.Lp[p])) continue;  // joined already: no atomic
+            const unsigned long long cl = close_word(mine, d.Ap[p], d.forward_only);
+            const unsigned long long old = atomicOr(&d.Lp[p], cl);
+            joins += __popcll(mine & ~old);
+            nwk[k] = cl & ~old & ~mine;
+            pk[k] = p;
         }
         while (__ballot((nwk[0] | nwk[1] | nwk[2] | nwk[3]) != 0)) {
             uint32_t cnt = 0;
@@ -825,7 +867,7 @@ struct FoldList {
     int assign;
 };
 
-__global__ __launch_bounds__(1024) void k_fold_slots(Dev d, FoldList f) {
+__device__ void fold_list(const Dev& d, const FoldList& f) {
     __shared__ unsigned long long s_w[16];
     for (int k = 0; k < f.n; ++k) {
         unsigned long long v = 0;
@@ -844,6 +886,8 @@ __global__ __launch_bounds__(1024) void k_fold_slots(Dev d, FoldList f) {
         __syncthreads();
     }
 }
+
+__global__ __launch_bounds__(1024) void k_fold_slots(Dev d, FoldList f) { fold_list(d, f); }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, uint64_t n) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
@@ -1177,9 +1221,9 @@ __global__ __launch_bounds__(256) void k_count_active(Dev d) {
 // Requires Tpad >= 4.
 constexpr uint32_t kStage = 1024;  // staged entries per block (8 KB of LDS)
 __device__ __forceinline__ void flush_stage(const Dev& d, const uint2* s_buf, uint32_t n, uint32_t* s_tmp) {
-    if (threadIdx.x == 0) s_tmp[4] = atomicAdd(&d.counters[C_NLIST], n);
+    if (threadIdx.x == 0) s_tmp[8] = atomicAdd(&d.counters[C_NLIST], n);
     __syncthreads();
-    const uint32_t base = s_tmp[4];
+    const uint32_t base = s_tmp[8];
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) d.clist[base + i] = s_buf[i];
     __syncthreads();
 }
@@ -1262,7 +1306,7 @@ __global__ __launch_bounds__(256) void k_pcand_write(Dev d) {
 // block serialise).  Non-candidates are not touched: their pflag is 0.
 // Requires Tpad >= 4.
 __global__ __launch_bounds__(256) void k_admit_particles(Dev d) {
-    __shared__ uint32_t s_tmp[8];
+    __shared__ __align__(8) uint32_t s_tmp[10];
     __shared__ uint2 s_buf[kStage];
     const PGeom& pg = d.pg;
     const float lo = d.crit[2], hi = d.crit[3];
@@ -1317,23 +1361,39 @@ __global__ __launch_bounds__(256) void k_admit_particles(Dev d) {
             nibs[k] = m;
             cnt += __popc(m);
         }
-        uint32_t total;
-        const uint32_t ex = block_exclusive_scan256(cnt, s_tmp, total);
+        // Positions: the entries of unit set k of every thread come before
+        // those of set k + 1, in thread order within a set, so that the
+        // entries of one unit (its G lanes) are contiguous and in step order
+        // (the pull combines a particle's entries that sit side by side).
+        // Four 16-bit counts scanned in one 64-bit word.
+        unsigned long long packed = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) packed |= (unsigned long long)__popc(nibs[k]) << (16 * k);
+        unsigned long long tot64;
+        const unsigned long long ex64 = block_exclusive_scan256_u64(packed, s_tmp, tot64);
+        uint32_t setbase[4], total = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            setbase[k] = total;
+            total += (uint32_t)(tot64 >> (16 * k)) & 0xFFFFu;
+        }
+        (void)cnt;
         if (nbuf + total > kStage) {  // block-uniform
             flush_stage(d, s_buf, nbuf, s_tmp);
             nbuf = 0;
         }
         const bool direct = total > kStage;  // block-uniform; more than the stage holds
-        uint32_t out = nbuf + ex;
+        uint32_t base = nbuf;
         if (direct) {
-            if (threadIdx.x == 0) s_tmp[4] = atomicAdd(&d.counters[C_NLIST], total);
+            if (threadIdx.x == 0) s_tmp[8] = atomicAdd(&d.counters[C_NLIST], total);
             __syncthreads();
-            out = s_tmp[4] + ex;
+            base = s_tmp[8];
             __syncthreads();
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             if (!nibs[k]) continue;
+            uint32_t out = base + setbase[k] + ((uint32_t)(ex64 >> (16 * k)) & 0xFFFFu);
             const uint32_t bw[4] = {bn[k].x, bn[k].y, bn[k].z, bn[k].w};
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -1586,6 +1646,16 @@ __global__ void k_work_total(Dev d, int par) {
     if (threadIdx.x == 0) d.counters[C_NWORK0 + par] = total;
 }
 
+// End of a chunk of rounds: the work total (first wave) and the statistics fold.
+__global__ __launch_bounds__(1024) void k_chunk_end(Dev d, int par, FoldList f) {
+    if (threadIdx.x < 64) {
+        uint32_t total;
+        wave_excl_scan(d.wcnt[(par * kWorkSubs + lane_id()) * kWcntStride], total);
+        if (threadIdx.x == 0) d.counters[C_NWORK0 + par] = total;
+    }
+    fold_list(d, f);
+}
+
 // ---- one round as three launches ----
 
 template <int BT>
@@ -1696,15 +1766,20 @@ __global__ __launch_bounds__(256) void k_rounds(Dev d, uint32_t round0, uint32_t
 
 // ---- read-out ----
 
+__device__ __forceinline__ bool gate_open(const ReadGate& gate) {
+    return !gate.counters || gate.counters[C_ROUNDS] < gate.rounds || gate.counters[C_NWORK0 + gate.par] == 0u;
+}
+
 // Field labels -> canonical bit words ((t*Z + z)*Y + y)*X + x, with a member
 // count.  When X is a multiple of 32 a canonical word is one tile word: a block
 // stages up to 8 x-consecutive tiles in LDS (rows padded by one word against
 // bank conflicts) and writes whole canonical rows.  Otherwise bit by bit.
 template <int BT>
-__global__ __launch_bounds__(256) void k_read_field_tiles(Dev d, uint32_t* __restrict__ out, int vec) {
+__global__ __launch_bounds__(256) void k_read_field_tiles(Dev d, uint32_t* __restrict__ out, int vec, ReadGate gate) {
     typedef unsigned int v4u __attribute__((ext_vector_type(4)));
     constexpr int WPT = 64 * BT;
     __shared__ uint32_t sl[8 * (WPT + 1)];
+    if (!gate_open(gate)) return;  // the same in every thread
     const Geom& g = d.g;
     const int ty = blockIdx.x, tz = blockIdx.y, tt = blockIdx.z;
     uint32_t cnt = 0;
@@ -1756,7 +1831,8 @@ __global__ __launch_bounds__(256) void k_read_field_tiles(Dev d, uint32_t* __res
     block_slot_sum(d, SL_MEMBERS_F, cnt);
 }
 
-__global__ __launch_bounds__(256) void k_read_field_bits(Dev d, uint32_t* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_read_field_bits(Dev d, uint32_t* __restrict__ out, ReadGate gate) {
+    if (!gate_open(gate)) return;
     const Geom& g = d.g;
     const uint64_t V = (uint64_t)g.X * g.Y * g.Z * g.T;
     const uint64_t nw = (V + 31) >> 5;
@@ -1784,7 +1860,8 @@ __global__ __launch_bounds__(256) void k_read_field_bits(Dev d, uint32_t* __rest
 // Particle labels -> uint8 [T][P].  Fast path (P a multiple of 16): a thread
 // owns 16 consecutive particles and, label word by label word, writes their 16
 // bytes of each step as one 16-byte store.
-__global__ __launch_bounds__(256) void k_read_particles16(Dev d, uint8_t* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_read_particles16(Dev d, uint8_t* __restrict__ out, ReadGate gate) {
+    if (!gate_open(gate)) return;
     const PGeom& pg = d.pg;
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t p0 = q * 16;
@@ -1818,7 +1895,8 @@ __global__ __launch_bounds__(256) void k_read_particles16(Dev d, uint8_t* __rest
 }
 
 // General particle read-out: a thread owns 4 consecutive particles.
-__global__ __launch_bounds__(256) void k_read_particles(Dev d, uint8_t* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_read_particles(Dev d, uint8_t* __restrict__ out, ReadGate gate) {
+    if (!gate_open(gate)) return;
     const PGeom& pg = d.pg;
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t p0 = q * 4;
@@ -1974,12 +2052,17 @@ void launch_fold_slots(const Dev& d, int which, int dst, hipStream_t s, bool ass
     hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(1024), 0, s, d, f);
 }
 
+const FoldList kGrowFold{3,
+                         {SL_PART_VISITS, SL_ACTIVE, SL_TESTED, 0},
+                         {S_PART_VISITS, S_ACTIVE_TILES, S_TILES_TESTED, 0},
+                         0};
+
 void launch_fold_grow_slots(const Dev& d, hipStream_t s) {
-    const FoldList f{3,
-                     {SL_PART_VISITS, SL_ACTIVE, SL_TESTED, 0},
-                     {S_PART_VISITS, S_ACTIVE_TILES, S_TILES_TESTED, 0},
-                     0};
-    hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(1024), 0, s, d, f);
+    hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(1024), 0, s, d, kGrowFold);
+}
+
+void launch_chunk_end(const Dev& d, int par, hipStream_t s) {
+    hipLaunchKernelGGL(k_chunk_end, dim3(1), dim3(1024), 0, s, d, par, kGrowFold);
 }
 
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
@@ -2082,34 +2165,34 @@ bool launch_rounds_persistent(const Dev& d, uint32_t round0, uint32_t max_rounds
     }
 }
 
-void launch_read_field(const Dev& d, uint32_t* out, hipStream_t s) {
+void launch_read_field(const Dev& d, uint32_t* out, hipStream_t s, const ReadGate& gate) {
     const Geom& g = d.g;
     if ((g.X & 31) == 0) {
         const dim3 grid(g.NYt, g.NZt, g.NTt);
         // 16-byte stores when every x-run of tiles is a multiple of 4 words
         const int vec = (g.NXt & 3) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0;
         switch (g.BT) {
-            case 4: hipLaunchKernelGGL(k_read_field_tiles<4>, grid, dim3(256), 0, s, d, out, vec); break;
-            case 8: hipLaunchKernelGGL(k_read_field_tiles<8>, grid, dim3(256), 0, s, d, out, vec); break;
-            default: hipLaunchKernelGGL(k_read_field_tiles<16>, grid, dim3(256), 0, s, d, out, vec); break;
+            case 4: hipLaunchKernelGGL(k_read_field_tiles<4>, grid, dim3(256), 0, s, d, out, vec, gate); break;
+            case 8: hipLaunchKernelGGL(k_read_field_tiles<8>, grid, dim3(256), 0, s, d, out, vec, gate); break;
+            default: hipLaunchKernelGGL(k_read_field_tiles<16>, grid, dim3(256), 0, s, d, out, vec, gate); break;
         }
         return;
     }
     const uint64_t V = (uint64_t)g.X * g.Y * g.Z * g.T;
     hipLaunchKernelGGL(k_read_field_bits, dim3(grid_for((V + 31) / 32, 256, 16384)), dim3(256), 0,
-                       s, d, out);
+                       s, d, out, gate);
 }
 
-void launch_read_particles(const Dev& d, uint8_t* out, hipStream_t s) {
+void launch_read_particles(const Dev& d, uint8_t* out, hipStream_t s, const ReadGate& gate) {
     const PGeom& pg = d.pg;
     if (pg.P == 0) return;
     if ((pg.P & 15) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
         hipLaunchKernelGGL(k_read_particles16, dim3(grid_for(pg.P / 16, 256, 1u << 20)), dim3(256),
-                           0, s, d, out);
+                           0, s, d, out, gate);
         return;
     }
     hipLaunchKernelGGL(k_read_particles, dim3(grid_for((pg.P + 3) / 4, 256, 1u << 20)), dim3(256),
-                       0, s, d, out);
+                       0, s, d, out, gate);
 }
 
 void launch_particle_segments(const Dev& d, uint8_t* out, hipStream_t s) {

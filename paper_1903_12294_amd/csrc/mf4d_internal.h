@@ -84,6 +84,17 @@ enum Stat64 : int {
     S_NSTAT = 8
 };
 
+// Condition under which a queued read-out runs: with counters null always;
+// else only if the chunk of rounds queued before it reached the fixed point,
+// i.e. fewer than `rounds` rounds had work (counters[C_ROUNDS]) or the work
+// list of parity `par` for the next round is empty.  A closed gate makes the
+// read-out a no-op, so that it can be queued before the host knows.
+struct ReadGate {
+    const uint32_t* counters;
+    uint32_t rounds;
+    int par;
+};
+
 // Every device buffer of a context, passed by value to the kernels.
 struct Dev {
     Geom g;
@@ -139,8 +150,8 @@ void launch_work_total(const Dev& d, int par, hipStream_t s);
 // Rounds in one cooperative persistent launch; false if it cannot be launched.
 bool launch_rounds_persistent(const Dev& d, uint32_t round0, uint32_t max_rounds, int device,
                               hipStream_t s);
-void launch_read_field(const Dev& d, uint32_t* out, hipStream_t s);
-void launch_read_particles(const Dev& d, uint8_t* out, hipStream_t s);
+void launch_read_field(const Dev& d, uint32_t* out, hipStream_t s, const ReadGate& gate = ReadGate{});
+void launch_read_particles(const Dev& d, uint8_t* out, hipStream_t s, const ReadGate& gate = ReadGate{});
 // Trajectory segments of the grown feature as uint8 [T][P] (Section 3.4).
 void launch_particle_segments(const Dev& d, uint8_t* out, hipStream_t s);
 // Fold one single-seed grow into per-seed ids: members of the canonical field
@@ -173,5 +184,9 @@ void launch_fold_slots(const Dev& d, int which, int dst, hipStream_t s, bool ass
 // The per-grow statistics (particle visits, active and tested tiles) folded
 // (added) in one launch.
 void launch_fold_grow_slots(const Dev& d, hipStream_t s);
+// End of a chunk of launched rounds, in one launch: the work total of parity
+// par (as launch_work_total) and the per-grow statistics folded (as
+// launch_fold_grow_slots).
+void launch_chunk_end(const Dev& d, int par, hipStream_t s);
 
 }  // namespace mf4d
