@@ -262,6 +262,33 @@ __device__ __forceinline__ void schedule_batch(const Dev& d, const uint32_t* nb,
     }
 }
 
+// As schedule_batch, for a sweep's few neighbours: the flag exchange is
+// issued with the activity loads (two round trips instead of three).  A flag
+// set on a tile with no admissible voxel-step is never read: such a tile is
+// never listed.
+__device__ __forceinline__ void schedule_batch_direct(const Dev& d, const uint32_t* nb, int k, int par) {
+    uint32_t* dirty = d.dirty + (size_t)par * d.g.NT;
+    uint32_t cur[8];
+    uint8_t act[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        act[i] = 0;
+        cur[i] = 1u;
+        if (i < k) {
+            act[i] = d.active[nb[i]];
+            cur[i] = atomicExch(&dirty[nb[i]], 1u);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        if (i < k && act[i] && cur[i] == 0u) {
+            const uint32_t j = (uint32_t)(par * kWorkSubs) + (nb[i] & (kWorkSubs - 1));
+            const uint32_t slot = atomicAdd(&d.wcnt[j * kWcntStride], 1u);
+            d.work[(size_t)j * d.g.WCAP + slot] = nb[i];
+        }
+    }
+}
+
 // Voxel bits set from outside a tile sweep (seeds, particle pushes), before
 // round parity `par`: each owning tile is flagged changed (its coupled steps
 // must be pulled) and scheduled.  Its sweep sees the flag and schedules every
@@ -445,7 +472,7 @@ __device__ void sweep_tile(const Dev& d, uint32_t tile, int par) {
             if (fzp && tz + 1 < g.NZt) nb[k++] = tile + sz;
             if (ftm && tt > 0) nb[k++] = tile - st;
             if (ftp && tt + 1 < g.NTt) nb[k++] = tile + st;
-            schedule_batch(d, nb, k, nx);
+            schedule_batch_direct(d, nb, k, nx);
         }
     }
 }
