@@ -364,37 +364,54 @@ __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_l
         __syncthreads();
     }
     const uint32_t need = s_flags[1] & s_flags[2];
-    // The eight words are written out one by one (the register arrays stay
-    // in registers only with constant indices).
+    // Gauss-Seidel through LDS: the needed words go to LDS once; then each
+    // iteration a voxel with room to grow in a word (admissible for a query
+    // it is not a member of) ORs its neighbours' current words into it and
+    // writes the word back at once if it grew, so a change can travel on
+    // within the same iteration (to waves that read after it).  A saturated
+    // word cannot change and loads nothing.  Reads racing with writes only
+    // see fewer bits (labels only grow); an iteration in which no voxel
+    // changed read final values everywhere, which is the local fixed point.
+    // The eight words are handled one by one (the register arrays stay in
+    // registers only with constant indices).
 #define MF4D_STORE_WORD(k) \
     if ((need >> (k)) & 1u) s_lab[(k) * 512 + tid] = l[k];
 #define MF4D_STEP_WORD(k)                                                   \
-    if ((need >> (k)) & 1u) {                                               \
+    if (((need >> (k)) & 1u) && (a[k] & ~l[k])) {                          \
         uint32_t nbv = l[k] | h[k];                                         \
         _Pragma("unroll") for (int j = 0; j < 8; ++j)                       \
             if (nbr[j] >= 0) nbv |= s_lab[(k) * 512 + nbr[j]];              \
         const uint32_t sv = nbv & a[k];                                     \
-        diff |= sv ^ l[k];                                                  \
-        l[k] = sv;                                                          \
+        if (sv != l[k]) {                                                   \
+            diff = 1u;                                                      \
+            l[k] = sv;                                                      \
+            s_lab[(k) * 512 + tid] = sv;                                    \
+        }                                                                   \
     }
-    while (need) {
+    if (need) {
         MF4D_STORE_WORD(0) MF4D_STORE_WORD(1) MF4D_STORE_WORD(2) MF4D_STORE_WORD(3)
         MF4D_STORE_WORD(4) MF4D_STORE_WORD(5) MF4D_STORE_WORD(6) MF4D_STORE_WORD(7)
         __syncthreads();
-        uint32_t diff = 0;
-        MF4D_STEP_WORD(0) MF4D_STEP_WORD(1) MF4D_STEP_WORD(2) MF4D_STEP_WORD(3)
-        MF4D_STEP_WORD(4) MF4D_STEP_WORD(5) MF4D_STEP_WORD(6) MF4D_STEP_WORD(7)
-        if (!__syncthreads_or(diff != 0)) break;
+        while (true) {
+            uint32_t diff = 0;
+            MF4D_STEP_WORD(0) MF4D_STEP_WORD(1) MF4D_STEP_WORD(2) MF4D_STEP_WORD(3)
+            MF4D_STEP_WORD(4) MF4D_STEP_WORD(5) MF4D_STEP_WORD(6) MF4D_STEP_WORD(7)
+            if (!__syncthreads_or(diff != 0)) break;
+        }
     }
 #undef MF4D_STORE_WORD
 #undef MF4D_STEP_WORD
     uint32_t any = 0;
     if (in) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const uint32_t nw = l[k] & ~l0[k];
-            if (nw) atomicOr(&d.fplanes[v * 8 + k], nw);
-            any |= nw;
+        for (int k = 0; k < 8; ++k) any |= l[k] & ~l0[k];
+        // a tile is swept by one block per phase and nothing else writes its
+        // nodes meanwhile (seeds and pushes come in other phases): the node's
+        // 32 bytes go back with two plain stores
+        if (any) {
+            uint4* lp = reinterpret_cast<uint4*>(d.fplanes + v * 8);
+            lp[0] = make_uint4(l[0], l[1], l[2], l[3]);
+            lp[1] = make_uint4(l[4], l[5], l[6], l[7]);
         }
     }
     if (any) {
@@ -543,6 +560,90 @@ __global__ __launch_bounds__(256) void kb_pull(DevB d, int par) {
 // a few per step.  Every lane runs every chunk (ballots).
 constexpr int kChunk = 16;
 
+// A whole trajectory of up to kWhole steps closed in registers (lane k of the
+// particle's group of eight carries word k): every step's label, ranks and bin
+// are loaded at once (one round trip), the forward and the backward pass run
+// on them, and the new bits are written and pushed in two halves, each half's
+// loads and atomics issued together.  Every lane of the wave calls it.
+constexpr int kWhole = 32;
+__device__ __forceinline__ void close_whole(const DevB& d, uint32_t p, bool valid, int k, int grp, int npar,
+                                            const uint32_t* s_ptab, const uint32_t* s_ftab) {
+    const int Tp = d.Tp;
+    uint32_t lab[kWhole], cur[kWhole], adm[kWhole], bin[kWhole];
+#pragma unroll
+    for (int j = 0; j < kWhole; ++j) {
+        cur[j] = 0;
+        adm[j] = 0;
+        bin[j] = kNoVoxel;
+        if (valid && j < Tp) {
+            cur[j] = d.pplanes[((uint64_t)j * d.P + p) * 8 + k];
+            adm[j] = d.prank[(uint64_t)p * d.Tpad + j];
+            bin[j] = d.bins[(uint64_t)p * d.Tpad + j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kWhole; ++j) adm[j] = j < Tp && valid ? rank_word(s_ptab, adm[j], k) : 0u;
+    uint32_t carry = 0;
+#pragma unroll
+    for (int j = 0; j < kWhole; ++j) {
+        lab[j] = cur[j] | (carry & adm[j]);
+        carry = lab[j];
+    }
+    if (!d.forward_only) {
+        carry = 0;
+#pragma unroll
+        for (int j = kWhole - 1; j >= 0; --j) {
+            lab[j] |= carry & adm[j];
+            carry = lab[j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kWhole; ++j) lab[j] &= ~cur[j];  // the new bits
+#pragma unroll
+    for (int h = 0; h < kWhole; h += 16) {
+        uint32_t bb[16];
+        uint64_t vv[16];
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+            const int j = h + jj;
+            bb[jj] = kNoVoxel;
+            if (lab[j]) atomicOr(&d.pplanes[((uint64_t)j * d.P + p) * 8 + k], lab[j]);
+            const bool gnew = ((__ballot(lab[j] != 0) >> (8 * grp)) & 0xFFull) != 0;
+            if (gnew) bb[jj] = bin[j];
+        }
+        uint32_t rv[16];
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+            vv[jj] = ~0ull;
+            rv[jj] = 0u;
+            if (bb[jj] != kNoVoxel) {
+                int x, y, z, tt;
+                bit_to_xyzt(d.g, bb[jj], x, y, z, tt);
+                vv[jj] = vindex(d, x, y, z, tt);
+                if (lab[h + jj]) rv[jj] = d.vrank[vv[jj]];
+            }
+        }
+        uint32_t got[16];
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+            got[jj] = 0;
+            if (vv[jj] != ~0ull && lab[h + jj]) {
+                const uint32_t pw = lab[h + jj] & rank_word(s_ftab, rv[jj], k);
+                if (pw) got[jj] = ~atomicOr(&d.fplanes[vv[jj] * 8 + k], pw) & pw;
+            }
+        }
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+            const uint32_t gg = (uint32_t)(__ballot(got[jj] != 0) >> (8 * grp)) & 0xFFu;
+            if (got[jj] && k == __builtin_ctz(gg)) {
+                int x, y, z, tt;
+                bit_to_xyzt(d.g, bb[jj], x, y, z, tt);
+                bmark_voxel(d, x, y, z, tt, npar);
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void kb_close(DevB d, int par) {
     __shared__ uint32_t s_ptab[kLdsTab];
     __shared__ uint32_t s_ftab[kLdsTab];
@@ -567,6 +668,10 @@ __global__ __launch_bounds__(256) void kb_close(DevB d, int par) {
         const bool valid = i < nd;
         const uint32_t p = valid ? d.dlist[i] : 0u;
         if (valid && k == 0) atomicAnd(&d.pdirty[p >> 5], ~(1u << (p & 31)));
+        if (d.Tp <= kWhole) {
+            close_whole(d, p, valid, k, grp, npar, s_ptab, s_ftab);
+            continue;
+        }
         for (int dir = 0; dir < ndir; ++dir) {
             uint32_t carry = 0;
             for (int ci = 0; ci < nch; ++ci) {
