@@ -117,13 +117,17 @@ class Timer:
         return self.a.elapsed_time(self.b)
 
 
-def run_steps(g, fmask, pmask, steps: int, warmup: int, torch, instrumented: bool = False):
+def run_steps(g, fmask, pmask, steps: int, warmup: int, torch, instrumented: bool = False,
+              read_async: bool = False):
     """Warm up, then time `steps` steps; per step: grow, field read, particle
     read.  Uninstrumented (the headline): one grow_read call per step, two
     events around the whole loop and nothing else.  Instrumented: grow and
     the two read calls apart, the library records its phase events and each
     step's read-out is bracketed by events (both cost device time)."""
     g.set_phase_timing(instrumented)
+    # asynchronous read-outs: a step's read-outs overlap the next step's grow
+    # (two label sets); the timed region ends after all of them
+    g.set_read_async(read_async and not instrumented)
 
     def step():
         # the grow with both read-outs queued behind its rounds (one call)
@@ -150,12 +154,14 @@ def run_steps(g, fmask, pmask, steps: int, warmup: int, torch, instrumented: boo
             stats.append(st)
         else:
             stats.append(step())
+    g.read_wait()
     ev1.record()
     torch.cuda.synchronize()
     wall = (time.perf_counter() - w0) * 1e3 / steps
     ms = max(ev0.elapsed_time(ev1) / steps, wall)
     last = g.stats()
     g.set_phase_timing(False)
+    g.set_read_async(False)
     mean = lambda k: float(np.mean([s[k] for s in stats]))
     return dict(ms=ms, ms_admit_field=mean("ms_admit_field"), ms_admit=mean("ms_admit"),
                 ms_rounds=mean("ms_rounds"), ms_grow=mean("ms_total"),
@@ -587,6 +593,9 @@ def main():
     ap.add_argument("--tile-t", type=int, choices=[4, 8, 16], help="fix the tile depth (no tuning)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="the headline grow only (no other form)")
+    ap.add_argument("--sync-reads", action="store_true",
+                    help="headline steps with stream-ordered read-outs (default: asynchronous, "
+                         "each step's read-outs beside the next step's rounds)")
     ap.add_argument("--slic-only", action="store_true",
                     help="only the clustering form (for profiling its kernels); prints its JSON object")
     ap.add_argument("--city-only", action="store_true",
@@ -655,7 +664,7 @@ def main():
 
     fmask = torch.empty((V + 31) // 32, dtype=torch.int32, device=dev)
     pmask = torch.empty((T, P), dtype=torch.uint8, device=dev)
-    r0 = run_steps(g, fmask, pmask, args.steps, args.warmup, torch)
+    r0 = run_steps(g, fmask, pmask, args.steps, args.warmup, torch, read_async=not args.sync_reads)
     ms = r0["ms"]
     # the same steps again with the library's phase events, for per-kernel times
     r = run_steps(g, fmask, pmask, args.steps, 1, torch, instrumented=True)
@@ -789,7 +798,9 @@ def main():
                                f"{float(inst['crit'][0])}/{float(inst['crit'][2])}",
                    "voxel_steps": V, "particle_steps": Q,
                    "tile": f"32x8x8x{choice['tile_t']}", "schedule": choice["schedule"],
-                   "admissibility": choice["admit"]},
+                   "admissibility": choice["admit"],
+                   "read_out": "stream-ordered" if args.sync_reads else
+                               "asynchronous: each step's read-outs beside the next step's rounds"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "detail": {

@@ -288,6 +288,26 @@ int mf4d_read_particle_mask(mf4d_ctx *ctx, uint8_t *dst, size_t n, int where);
 int mf4d_grow_read(mf4d_ctx *ctx, uint32_t *field_dst, size_t nwords, uint8_t *particle_dst, size_t n,
                    mf4d_stats *out);
 
+/* Asynchronous read-outs for mf4d_grow_read (on != 0; off by default).  The
+ * call returns with its read-outs deferred: the next asynchronous
+ * mf4d_grow_read grows on the other of two sets of label words (about
+ * X*Y*Z*T / 8 + 9 * T * P bytes more, allocated on first use) and issues
+ * them on the library's second stream once its own admissibility passes are
+ * queued, so they write the masks beside its rounds.  Every other call on
+ * the context (reads, resume, statistics, loads, destroy, ...) and
+ * mf4d_read_wait first issue the read-outs still deferred and order the
+ * context stream after every read-out still running; until then the caller
+ * must not use the masks (synchronising the device is not enough for
+ * read-outs not yet issued).  The masks hold the labels as the grow left
+ * them, converged or not.  Switching the mode settles the same way.
+ * Errors: MF4D_ERR_ARG (ctx NULL). */
+int mf4d_set_read_async(mf4d_ctx *ctx, int on);
+
+/* Issue the deferred asynchronous read-outs and order the context stream
+ * after every read-out still running (see mf4d_set_read_async); returns
+ * without waiting for the device.  Errors: MF4D_ERR_ARG (ctx NULL). */
+int mf4d_read_wait(mf4d_ctx *ctx);
+
 /* Trajectory segments of the grown feature (Section 3.4, visual
  * representation): a trajectory is split where it leaves the feature, and
  * only pieces of at least two consecutive member steps are kept.  Writes

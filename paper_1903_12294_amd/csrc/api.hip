@@ -191,6 +191,31 @@ struct mf4d_ctx {
     bool reads_done = false;          // the queued read-outs ran on the final labels
     hipEvent_t ev_chunk = nullptr;    // end of the last queued chunk of rounds
     hipEvent_t ev_stat = nullptr;     // its statistics copied to the host
+    uint32_t* gsnap = nullptr;        // [2][C_NCOUNTERS]: chunk-end counters per label set (read gate)
+    // Asynchronous read-outs (mf4d_set_read_async): a grow_read leaves its
+    // read-outs deferred; the next asynchronous grow_read grows on the other
+    // of two label sets and issues them on the side stream once its own
+    // admissibility passes are queued, so they run beside its rounds; any
+    // other call issues them at once.  The context stream waits for them
+    // only when a later call needs it.  Set k's buffers are Lf / active / Lp
+    // / pflag while it is current, the *_alt ones otherwise (swapped).
+    bool read_async = false;
+    bool async_grow = false;          // the grow in progress is an asynchronous grow_read
+    struct {
+        uint32_t* f;
+        uint8_t* p;
+        int set;
+        bool valid;
+    } dread = {nullptr, nullptr, 0, false};  // deferred read-outs of the last grow
+    hipEvent_t ev_issue = nullptr;    // where deferred read-outs may start
+    int lset = 0;                     // index of the current label set
+    uint32_t* Lf_alt = nullptr;
+    uint8_t* active_alt = nullptr;
+    unsigned long long* Lp_alt = nullptr;
+    uint8_t* pflag_alt = nullptr;
+    bool alt_ready = false;           // the other set's buffers hold no uninitialised words
+    hipEvent_t ev_read[2] = {nullptr, nullptr};  // read-outs of label set k done
+    bool read_pending[2] = {false, false};
 
     // batched queries
     int Q = 0;
@@ -293,6 +318,9 @@ void free_field(mf4d_ctx* c) {
     dev_free(c->Af);
     dev_free(c->Lf);
     dev_free(c->active);
+    dev_free(c->Lf_alt);
+    dev_free(c->active_alt);
+    c->alt_ready = false;
     dev_free(c->dirty);
     dev_free(c->work);
     dev_free(c->wcnt);
@@ -338,6 +366,9 @@ void free_particles(mf4d_ctx* c) {
     dev_free(c->attr_t);
     dev_free(c->Ap);
     dev_free(c->Lp);
+    dev_free(c->Lp_alt);
+    dev_free(c->pflag_alt);
+    c->alt_ready = false;
     dev_free(c->clist);
     dev_free(c->pdirty);
     dev_free(c->pcand);
@@ -416,24 +447,88 @@ Dev make_dev(mf4d_ctx* c) {
     return d;
 }
 
+// The context's buffers with label set `set` (the current one or the other).
+Dev make_dev_set(mf4d_ctx* c, int set) {
+    Dev d = make_dev(c);
+    if (set != c->lset) {
+        d.Lf = c->Lf_alt;
+        d.active = c->active_alt;
+        d.Lp = c->Lp_alt;
+        d.pflag = c->pflag_alt;
+    }
+    return d;
+}
+
+// Issue the deferred read-outs on the side stream after `after` (recorded on
+// the context stream; null: now), from the label set they belong to.  last:
+// they are the last grow's (its member counts are then the ones reported).
+int issue_deferred(mf4d_ctx* c, hipEvent_t after, bool last) {
+    if (!c->dread.valid) return MF4D_OK;
+    c->dread.valid = false;
+    if (!after) {
+        HIP_TRY(hipEventRecord(c->ev_issue, c->stream));
+        after = c->ev_issue;
+    }
+    HIP_TRY(hipStreamWaitEvent(c->side, after, 0));
+    const Dev d = make_dev_set(c, c->dread.set);
+    if (c->dread.p) {
+        launch_read_particles(d, c->dread.p, c->side);
+        launch_fold_slots(d, SL_MEMBERS_P, S_MEMBERS_P, c->side, true);
+    }
+    if (c->dread.f) {
+        launch_read_field(d, c->dread.f, c->side);
+        launch_fold_slots(d, SL_MEMBERS_F, S_MEMBERS_F, c->side, true);
+    }
+    HIP_TRY(hipEventRecord(c->ev_read[c->dread.set], c->side));
+    c->read_pending[c->dread.set] = true;
+    if (last) {
+        c->members_pending[0] = c->dread.f != nullptr;
+        c->members_pending[1] = c->dread.p != nullptr;
+    }
+    return MF4D_OK;
+}
+
+// Issue deferred read-outs and let the context stream wait for every
+// asynchronous read-out still running: every call other than an
+// asynchronous grow_read starts with it, so nothing it queues can touch
+// labels, member counts or buffers those read-outs use.
+int settle_async(mf4d_ctx* c) {
+    int rc = issue_deferred(c, nullptr, true);
+    if (rc) return rc;
+    for (int k = 0; k < 2; ++k)
+        if (c->read_pending[k]) {
+            HIP_TRY(hipStreamWaitEvent(c->stream, c->ev_read[k], 0));
+            c->read_pending[k] = false;
+        }
+    return MF4D_OK;
+}
+
 // Queue the read-outs of mf4d_grow_read behind the rounds queued so far: the
-// particle labels on the side stream (after ev_chunk), the field labels on
-// the context stream, which then waits for the side stream.  With a closed
-// gate they do nothing.
+// particle labels on the side stream after ev_chunk, the field labels on the
+// context stream.  Gated on the chunk's counter copy: with a closed gate they
+// do nothing.  The context stream's wait for the side stream is queued by the
+// caller (join_reads).
 int queue_reads(mf4d_ctx* c, const ReadGate& gate) {
     const Dev d = make_dev(c);
     hipStream_t s = c->stream;
+    HIP_TRY(hipStreamWaitEvent(c->side, c->ev_chunk, 0));
     if (c->rd_p) {
-        HIP_TRY(hipStreamWaitEvent(c->side, c->ev_chunk, 0));
         launch_read_particles(d, c->rd_p, c->side, gate);
         launch_fold_slots(d, SL_MEMBERS_P, S_MEMBERS_P, c->side, true);
-        HIP_TRY(hipEventRecord(c->ev_pread, c->side));
     }
     if (c->rd_f) {
         launch_read_field(d, c->rd_f, s, gate);
         launch_fold_slots(d, SL_MEMBERS_F, S_MEMBERS_F, s, true);
     }
-    if (c->rd_p) HIP_TRY(hipStreamWaitEvent(s, c->ev_pread, 0));
+    HIP_TRY(hipEventRecord(c->ev_pread, c->side));
+    return MF4D_OK;
+}
+
+// After a chunk's read-outs were queued: the context stream waits for the
+// side stream's part.
+int join_reads(mf4d_ctx* c) {
+    if (!c->rd_p) return MF4D_OK;
+    HIP_TRY(hipStreamWaitEvent(c->stream, c->ev_pread, 0));
     return MF4D_OK;
 }
 
@@ -508,6 +603,8 @@ int run_rounds(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
             // round it was going to
             int rc = read_chunk(c, ReadGate{});
             if (rc) return rc;
+            rc = join_reads(c);
+            if (rc) return rc;
             c->reads_done = c->rd_f || c->rd_p;
             c->stats_ready = true;
             if (c->h_counters[C_ERR] == 0) {
@@ -546,8 +643,9 @@ int run_rounds(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
         // read-outs pending are queued gated on this chunk reaching the
         // fixed point
         const int npar = (int)((c->round + chunk) & 1);
-        launch_chunk_end(d, npar, c->stream);
-        int rc = read_chunk(c, ReadGate{c->counters, (uint32_t)(r + chunk), npar});
+        uint32_t* snap = (c->rd_f || c->rd_p) ? c->gsnap + c->lset * C_NCOUNTERS : nullptr;
+        launch_chunk_end(d, npar, snap, c->stream);
+        int rc = read_chunk(c, ReadGate{snap, (uint32_t)(r + chunk), npar});
         if (rc) return rc;
         c->stats_ready = true;
         const int64_t done = (int64_t)c->h_counters[C_ROUNDS] - r;
@@ -559,7 +657,10 @@ int run_rounds(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
             }
         c->round += (uint32_t)done;
         r += done;
-        if (done < chunk || c->h_counters[C_NWORK0 + (c->round & 1)] == 0) {
+        const bool converged = done < chunk || c->h_counters[C_NWORK0 + (c->round & 1)] == 0;
+        rc = join_reads(c);
+        if (rc) return rc;
+        if (converged) {
             c->state = 1;
             c->reads_done = c->rd_f || c->rd_p;  // their gate was open
             break;
@@ -646,6 +747,7 @@ int mf4d_create(mf4d_ctx** out, int device, void* hip_stream) {
     int rc = dev_alloc(&c->stat64, S_NSTAT + C_NCOUNTERS / 2);
     if (!rc) c->counters = reinterpret_cast<uint32_t*>(c->stat64 + S_NSTAT);
     if (!rc) rc = dev_alloc(&c->bar, kBarWords);
+    if (!rc) rc = dev_alloc(&c->gsnap, 2 * (size_t)C_NCOUNTERS);
     if (!rc) rc = dev_alloc(&c->slots, (size_t)kSlotStats * kSlots);
     if (!rc) launch_fill_u32((uint32_t*)c->slots, 0, 2ull * kSlotStats * kSlots, c->stream);
     if (!rc) {
@@ -663,7 +765,7 @@ int mf4d_create(mf4d_ctx** out, int device, void* hip_stream) {
         if (hipEventCreate(&c->rev[i]) != hipSuccess) rc = fail(MF4D_ERR_HIP, "hipEventCreate failed");
     if (!rc && hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess)
         rc = fail(MF4D_ERR_HIP, "hipStreamCreateWithFlags failed");
-    for (hipEvent_t* e : {&c->ev_labels, &c->ev_pread, &c->ev_chunk, &c->ev_stat})
+    for (hipEvent_t* e : {&c->ev_labels, &c->ev_pread, &c->ev_chunk, &c->ev_stat, &c->ev_read[0], &c->ev_read[1], &c->ev_issue})
         if (!rc && hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess)
             rc = fail(MF4D_ERR_HIP, "hipEventCreate failed");
     if (rc) {
@@ -677,6 +779,7 @@ int mf4d_create(mf4d_ctx** out, int device, void* hip_stream) {
 void mf4d_destroy(mf4d_ctx* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
+    (void)settle_async(c);  // deferred read-outs still write the caller's buffers
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
     if (c->side) (void)hipStreamSynchronize(c->side);
@@ -686,6 +789,7 @@ void mf4d_destroy(mf4d_ctx* c) {
     dev_free(c->stat64);
     dev_free(c->slots);
     dev_free(c->bar);
+    dev_free(c->gsnap);
     dev_free(c->seeds);
     dev_free(c->btab);
     dev_free(c->qseeds);
@@ -707,7 +811,7 @@ void mf4d_destroy(mf4d_ctx* c) {
         c->staging = nullptr;
     }
     if (c->side) (void)hipStreamDestroy(c->side);
-    for (hipEvent_t e : {c->ev_labels, c->ev_pread, c->ev_chunk, c->ev_stat})
+    for (hipEvent_t e : {c->ev_labels, c->ev_pread, c->ev_chunk, c->ev_stat, c->ev_read[0], c->ev_read[1], c->ev_issue})
         if (e) (void)hipEventDestroy(e);
     c->h_counters = nullptr;  // inside h_stat
     if (c->h_stat) (void)hipHostFree(c->h_stat);
@@ -728,6 +832,10 @@ int mf4d_set_tile(mf4d_ctx* c, int bt) {
 
 int mf4d_load_field(mf4d_ctx* c, const float* field, int X, int Y, int Z, int T, int where) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    {
+        const int rs = settle_async(c);  // asynchronous read-outs still running
+        if (rs) return rs;
+    }
     if (!field) return fail(MF4D_ERR_ARG, "field is NULL");
     if (X <= 0 || Y <= 0 || Z <= 0 || T <= 0) return fail(MF4D_ERR_ARG, "dims must be positive");
     if (where != MF4D_HOST && where != MF4D_DEVICE) return fail(MF4D_ERR_ARG, "bad where");
@@ -803,6 +911,10 @@ int mf4d_load_particles(mf4d_ctx* c, const float* xyz, const float* attr, int64_
 int mf4d_load_particles_rate(mf4d_ctx* c, const float* xyz, const float* attr, int64_t P, int Tp,
                              int steps_per_field_step, int where) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    {
+        const int rs = settle_async(c);  // asynchronous read-outs still running
+        if (rs) return rs;
+    }
     if (!c->has_field) return fail(MF4D_ERR_STATE, "load the field before the particles");
     if (P < 0) return fail(MF4D_ERR_ARG, "P < 0");
     if (where != MF4D_HOST && where != MF4D_DEVICE) return fail(MF4D_ERR_ARG, "bad where");
@@ -1063,6 +1175,40 @@ int grow_impl(mf4d_ctx* c, mf4d_stats* out) {
     if (!c->has_field) return fail(MF4D_ERR_STATE, "no field loaded");
     if (!c->has_crit) return fail(MF4D_ERR_STATE, "no criteria set");
     HIP_TRY(hipSetDevice(c->device));
+    if (c->async_grow) {
+        // the read-outs of the grow before are deferred (or still run) on
+        // the current set: grow on the other one (allocated on first use),
+        // once its own read-outs are done
+        int rc = MF4D_OK;
+        if (c->dread.valid && c->dread.set != c->lset) rc = issue_deferred(c, nullptr, false);  // on that set
+        if (rc) return rc;
+        if (!c->Lf_alt) rc = dev_alloc(&c->Lf_alt, c->g.nwords);
+        if (!rc && !c->active_alt) rc = dev_alloc(&c->active_alt, (size_t)c->g.NT + 8);
+        if (!rc && c->has_particles && !c->Lp_alt) rc = dev_alloc(&c->Lp_alt, (size_t)c->pg.P * c->pg.W);
+        if (!rc && c->has_particles && !c->pflag_alt) rc = dev_alloc(&c->pflag_alt, (size_t)c->pg.P);
+        if (rc) return rc;
+        if (!c->alt_ready) {  // labels outside this grow's candidates read as cleared
+            launch_fill_u32(c->Lf_alt, 0u, c->g.nwords, c->stream);
+            if (c->has_particles)
+                launch_fill_u32(reinterpret_cast<uint32_t*>(c->Lp_alt), 0u, 2ull * (uint64_t)c->pg.P * c->pg.W,
+                                c->stream);
+            c->alt_ready = true;
+        }
+        std::swap(c->Lf, c->Lf_alt);
+        std::swap(c->active, c->active_alt);
+        if (c->has_particles) {
+            std::swap(c->Lp, c->Lp_alt);
+            std::swap(c->pflag, c->pflag_alt);
+        }
+        c->lset ^= 1;
+        if (c->read_pending[c->lset]) {
+            HIP_TRY(hipStreamWaitEvent(c->stream, c->ev_read[c->lset], 0));
+            c->read_pending[c->lset] = false;
+        }
+    } else {
+        int rc = settle_async(c);
+        if (rc) return rc;
+    }
     hipStream_t s = c->stream;
     const Dev d = make_dev(c);
     c->state = 0;
@@ -1110,6 +1256,13 @@ int grow_impl(mf4d_ctx* c, mf4d_stats* out) {
     launch_admit_particles(d, s);
     if (c->timed) HIP_TRY(hipEventRecord(c->ev[2], s));
     launch_seeds(d, c->seeds, c->S, s);
+    if (c->async_grow && c->dread.valid) {
+        // the grow before's read-outs, beside this grow's rounds (after its
+        // admissibility passes, the bandwidth-heavy part)
+        HIP_TRY(hipEventRecord(c->ev_issue, s));
+        int rc = issue_deferred(c, c->ev_issue, false);
+        if (rc) return rc;
+    }
     if (ordered) launch_priority_sweep(d, plist, pcount, c->pr_waves, s);
     int64_t rounds = 0;
     int rc = run_rounds(c, d, &rounds);
@@ -1140,6 +1293,21 @@ int mf4d_grow(mf4d_ctx* c, mf4d_stats* out) {
     return grow_impl(c, out);
 }
 
+int mf4d_set_read_async(mf4d_ctx* c, int on) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    HIP_TRY(hipSetDevice(c->device));
+    int rc = settle_async(c);
+    if (rc) return rc;
+    c->read_async = on != 0;
+    return MF4D_OK;
+}
+
+int mf4d_read_wait(mf4d_ctx* c) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    HIP_TRY(hipSetDevice(c->device));
+    return settle_async(c);
+}
+
 int mf4d_grow_read(mf4d_ctx* c, uint32_t* field_dst, size_t nwords, uint8_t* particle_dst, size_t n,
                    mf4d_stats* out) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
@@ -1155,6 +1323,21 @@ int mf4d_grow_read(mf4d_ctx* c, uint32_t* field_dst, size_t nwords, uint8_t* par
     // Jacobi sweeps or phase timing (events per round).
     const bool ordered = c->priority != MF4D_SCHEDULER_PLAIN && !c->admit_all;
     const bool queue = !ordered && !c->phase_timing && c->schedule != MF4D_SCHED_JACOBI;
+    if (queue && c->read_async) {
+        // asynchronous: the read-outs are deferred (issued beside the next
+        // asynchronous grow's rounds, or by the next other call) and read
+        // the labels as this grow leaves them, converged or not
+        c->async_grow = true;
+        int rc = grow_impl(c, out);
+        c->async_grow = false;
+        if (rc != MF4D_OK && rc != MF4D_ERR_NOT_CONVERGED) return rc;
+        c->dread.f = field_dst;
+        c->dread.p = particle_dst;
+        c->dread.set = c->lset;
+        c->dread.valid = field_dst || particle_dst;
+        if (rc == MF4D_ERR_NOT_CONVERGED) return fail(rc, "stopped after %lld rounds", (long long)c->stats.rounds);
+        return MF4D_OK;
+    }
     c->rd_f = queue ? field_dst : nullptr;
     c->rd_p = queue ? particle_dst : nullptr;
     c->reads_done = false;
@@ -1184,6 +1367,10 @@ int mf4d_grow_read(mf4d_ctx* c, uint32_t* field_dst, size_t nwords, uint8_t* par
 
 int mf4d_grow_resume(mf4d_ctx* c, mf4d_stats* out) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    {
+        const int rs = settle_async(c);  // asynchronous read-outs still running
+        if (rs) return rs;
+    }
     if (c->state != 2) return fail(MF4D_ERR_STATE, "nothing to resume");
     HIP_TRY(hipSetDevice(c->device));
     const Dev d = make_dev(c);
@@ -1201,6 +1388,10 @@ int mf4d_grow_resume(mf4d_ctx* c, mf4d_stats* out) {
 
 int mf4d_reset_labels(mf4d_ctx* c) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    {
+        const int rs = settle_async(c);  // asynchronous read-outs still running
+        if (rs) return rs;
+    }
     if (!c->has_field) return fail(MF4D_ERR_STATE, "no field loaded");
     HIP_TRY(hipSetDevice(c->device));
     launch_fill_u32(c->Lf, 0u, c->g.nwords, c->stream);
@@ -1230,6 +1421,10 @@ int settle_members(mf4d_ctx* c) {
 
 int mf4d_read_field_mask(mf4d_ctx* c, uint32_t* dst, size_t nwords, int where) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    {
+        const int rs = settle_async(c);  // asynchronous read-outs still running
+        if (rs) return rs;
+    }
     if (c->state == 0) return fail(MF4D_ERR_STATE, "nothing grown");
     if (!dst) return fail(MF4D_ERR_ARG, "dst is NULL");
     if (where != MF4D_HOST && where != MF4D_DEVICE) return fail(MF4D_ERR_ARG, "bad where");
@@ -1255,6 +1450,10 @@ int mf4d_read_field_mask(mf4d_ctx* c, uint32_t* dst, size_t nwords, int where) {
 
 int mf4d_read_particle_mask(mf4d_ctx* c, uint8_t* dst, size_t n, int where) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    {
+        const int rs = settle_async(c);  // asynchronous read-outs still running
+        if (rs) return rs;
+    }
     if (c->state == 0) return fail(MF4D_ERR_STATE, "nothing grown");
     if (!c->has_particles) return fail(MF4D_ERR_STATE, "no particles loaded");
     if (!dst) return fail(MF4D_ERR_ARG, "dst is NULL");
@@ -1291,6 +1490,10 @@ int mf4d_read_particle_mask(mf4d_ctx* c, uint8_t* dst, size_t n, int where) {
 
 int mf4d_read_particle_segments(mf4d_ctx* c, uint8_t* dst, size_t n, int where) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    {
+        const int rs = settle_async(c);  // asynchronous read-outs still running
+        if (rs) return rs;
+    }
     if (c->state == 0) return fail(MF4D_ERR_STATE, "nothing grown");
     if (!c->has_particles) return fail(MF4D_ERR_STATE, "no particles loaded");
     if (!dst) return fail(MF4D_ERR_ARG, "dst is NULL");
@@ -1315,6 +1518,10 @@ int mf4d_read_particle_segments(mf4d_ctx* c, uint8_t* dst, size_t n, int where) 
 int mf4d_grow_seed_ids(mf4d_ctx* c, int32_t* field_ids, size_t nf, int32_t* particle_ids, size_t np,
                        int where, int64_t* grows) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    {
+        const int rs = settle_async(c);  // asynchronous read-outs still running
+        if (rs) return rs;
+    }
     if (!c->has_field) return fail(MF4D_ERR_STATE, "no field loaded");
     if (!c->has_crit) return fail(MF4D_ERR_STATE, "no criteria set");
     if (where != MF4D_HOST && where != MF4D_DEVICE) return fail(MF4D_ERR_ARG, "bad where");
@@ -1383,6 +1590,7 @@ int mf4d_grow_seed_ids(mf4d_ctx* c, int32_t* field_ids, size_t nf, int32_t* part
         ++ngrow;
         const Dev d = make_dev(c);
         launch_read_field(d, sc.words, s);
+        launch_fold_slots(d, SL_MEMBERS_F, S_MEMBERS_F, s, true);  // clears the member slots
         launch_seed_ids(d, sc.words, sc.seen_f, sc.seen_p, (int32_t)i, fo, po, s);
     }
     c->state = 0;  // the labels hold the last single-seed grow, not the seeds' union
@@ -1399,6 +1607,10 @@ int mf4d_grow_seed_ids(mf4d_ctx* c, int32_t* field_ids, size_t nf, int32_t* part
 int mf4d_set_queries(mf4d_ctx* c, int Q, const float* crit, const int32_t* qxyzt, int64_t S,
                      int where) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    {
+        const int rs = settle_async(c);  // asynchronous read-outs still running
+        if (rs) return rs;
+    }
     if (!c->has_field) return fail(MF4D_ERR_STATE, "load the field before the queries");
     if (Q < 1 || Q > 256) return fail(MF4D_ERR_ARG, "Q = %d not in 1..256", Q);
     if (!crit || S < 0 || (S > 0 && !qxyzt)) return fail(MF4D_ERR_ARG, "bad query arrays");
@@ -1486,6 +1698,10 @@ int mf4d_set_batched_tile(mf4d_ctx* c, int bx, int by, int bz, int bt) {
 int mf4d_grow_batched(mf4d_ctx* c, uint32_t* fplanes, size_t fwords, uint32_t* pplanes,
                       size_t pwords, int where, mf4d_stats* out) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    {
+        const int rs = settle_async(c);  // asynchronous read-outs still running
+        if (rs) return rs;
+    }
     if (!c->has_field) return fail(MF4D_ERR_STATE, "no field loaded");
     if (c->Q == 0) return fail(MF4D_ERR_STATE, "no queries set");
     if (where != MF4D_HOST && where != MF4D_DEVICE) return fail(MF4D_ERR_ARG, "bad where");
@@ -1652,6 +1868,10 @@ int mf4d_grow_batched(mf4d_ctx* c, uint32_t* fplanes, size_t fwords, uint32_t* p
 int mf4d_read_batched(mf4d_ctx* c, uint32_t* fdst, size_t fwords, uint32_t* pdst, size_t pwords,
                       int where) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    {
+        const int rs = settle_async(c);  // asynchronous read-outs still running
+        if (rs) return rs;
+    }
     if (!c->b_grown) return fail(MF4D_ERR_STATE, "no batched grow into the context's planes");
     if (where != MF4D_HOST && where != MF4D_DEVICE) return fail(MF4D_ERR_ARG, "bad where");
     const Geom& g = c->g;
@@ -1705,6 +1925,10 @@ int mf4d_set_scheduler(mf4d_ctx* c, int kind, const void* params, size_t nbytes)
 
 int mf4d_features(mf4d_ctx* c, uint16_t* dst, size_t n, int where) {
     if (!c || !dst) return fail(MF4D_ERR_ARG, "NULL argument");
+    {
+        const int rs = settle_async(c);  // asynchronous read-outs still running
+        if (rs) return rs;
+    }
     if (!c->has_field || !c->has_crit) return fail(MF4D_ERR_STATE, "load a field and set criteria first");
     const size_t need = (size_t)c->bd.T * c->bd.D * c->bd.H * c->bd.W * 16;
     if (n < need) return fail(MF4D_ERR_ARG, "dst holds %zu elements, %zu needed", n, need);
@@ -1719,6 +1943,10 @@ int mf4d_features(mf4d_ctx* c, uint16_t* dst, size_t n, int where) {
 
 int mf4d_brick_labels(mf4d_ctx* c, uint8_t* dst, size_t n, int where) {
     if (!c || !dst) return fail(MF4D_ERR_ARG, "NULL argument");
+    {
+        const int rs = settle_async(c);  // asynchronous read-outs still running
+        if (rs) return rs;
+    }
     if (c->state == 0) return fail(MF4D_ERR_STATE, "nothing grown");
     const size_t need = (size_t)c->bd.T * c->bd.D * c->bd.H * c->bd.W;
     if (n < need) return fail(MF4D_ERR_ARG, "dst holds %zu bytes, %zu needed", n, need);
@@ -1748,6 +1976,10 @@ int mf4d_brick_dims(mf4d_ctx* c, int* dims4) {
 
 int mf4d_last_stats(mf4d_ctx* c, mf4d_stats* out) {
     if (!c || !out) return fail(MF4D_ERR_ARG, "NULL argument");
+    {
+        const int rs = settle_async(c);  // asynchronous read-outs still running
+        if (rs) return rs;
+    }
     if (c->state == 0) return fail(MF4D_ERR_STATE, "nothing grown");
     int rc = settle_members(c);
     if (rc) return rc;
@@ -1809,6 +2041,10 @@ int mf4d_slic_set_params(mf4d_ctx* c, const int* k4, float w_d, float w_f, float
 
 int mf4d_slic_run(mf4d_ctx* c, int* iterations) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    {
+        const int rs = settle_async(c);  // asynchronous read-outs still running
+        if (rs) return rs;
+    }
     if (!c->has_field) return fail(MF4D_ERR_STATE, "no field loaded");
     if (!c->slic_params) return fail(MF4D_ERR_STATE, "no clustering parameters set");
     const Geom& g = c->g;

@@ -477,6 +477,14 @@ __device__ void sweep_tile(const Dev& d, uint32_t tile, int par) {
     }
 }
 
+// Whether a pull tests the coupled steps in `tile`: those of tiles whose
+// members changed since their last pull; with pull_all those of every tile
+// that holds an admissible voxel-step (the label words of other tiles are
+// left from earlier grows, never cleared).
+__device__ __forceinline__ bool pull_tile(const Dev& d, const uint8_t* chg, uint32_t tile) {
+    return d.pull_all ? d.active[tile] != 0 : chg[tile] != 0;
+}
+
 // Pull: a coupled particle-step joins when the voxel holding it is a member.
 // Only steps in tiles whose members changed since their last pull are tested.
 // A particle that gains a step is marked in pdirty for the close phase.
@@ -495,7 +503,7 @@ __device__ void pull_entries(const Dev& d, uint32_t i0, uint32_t stride, uint32_
         bool mem[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            mem[k] = ent[k].y != kNoVoxel && (d.pull_all || chg[ent[k].y >> tshift]) && test_bit(d.Lf, ent[k].y);
+            mem[k] = ent[k].y != kNoVoxel && pull_tile(d, chg, ent[k].y >> tshift) && test_bit(d.Lf, ent[k].y);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             if (!mem[k]) continue;
@@ -761,7 +769,7 @@ __device__ uint32_t pull_close_wave(const Dev& d, int par, uint32_t wave_id, uin
         bool mem[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            mem[k] = ent[k].y != kNoVoxel && (d.pull_all || chg[ent[k].y >> tshift]) && test_bit(d.Lf, ent[k].y);
+            mem[k] = ent[k].y != kNoVoxel && pull_tile(d, chg, ent[k].y >> tshift) && test_bit(d.Lf, ent[k].y);
         uint32_t pk[4];
         unsigned long long nwk[4];
 #pragma unroll
@@ -935,9 +943,15 @@ __global__ void k_reset(Dev d) {
     for (uint64_t i = tid; i < n_act; i += stride) reinterpret_cast<uint32_t*>(d.active)[i] = 0;
     for (uint64_t i = tid; i < n_pd; i += stride) d.pdirty[i] = 0;
     if (tid < C_NCOUNTERS) d.counters[tid] = 0;
-    if (tid < S_NSTAT) d.stat64[tid] = 0;
+    // the member counts (slots and statistics) belong to the read-outs, which
+    // may still run for the grow before (they assign them; their folds clear
+    // the slots)
+    if (tid < S_NSTAT && tid != S_MEMBERS_F && tid != S_MEMBERS_P) d.stat64[tid] = 0;
     for (uint64_t i = tid; i < (uint64_t)kBarWords; i += stride) d.bar[i] = 0;
-    for (uint64_t i = tid; i < (uint64_t)kSlotStats * kSlots; i += stride) d.slots[i] = 0ull;
+    for (uint64_t i = tid; i < (uint64_t)kSlotStats * kSlots; i += stride) {
+        const uint64_t row = i / kSlots;
+        if (row != SL_MEMBERS_F && row != SL_MEMBERS_P) d.slots[i] = 0ull;
+    }
     for (uint64_t i = tid; i < 2ull * kWorkSubs; i += stride) d.wcnt[i * kWcntStride] = 0u;
 }
 
@@ -1673,12 +1687,20 @@ __global__ void k_work_total(Dev d, int par) {
     if (threadIdx.x == 0) d.counters[C_NWORK0 + par] = total;
 }
 
-// End of a chunk of rounds: the work total (first wave) and the statistics fold.
-__global__ __launch_bounds__(1024) void k_chunk_end(Dev d, int par, FoldList f) {
+// End of a chunk of rounds: the work total (first wave), a copy of the round
+// count and that total for the read-outs' gate (snap: C_NCOUNTERS words, not
+// touched by later grows' rounds), and the statistics fold.
+__global__ __launch_bounds__(1024) void k_chunk_end(Dev d, int par, FoldList f, uint32_t* snap) {
     if (threadIdx.x < 64) {
         uint32_t total;
         wave_excl_scan(d.wcnt[(par * kWorkSubs + lane_id()) * kWcntStride], total);
-        if (threadIdx.x == 0) d.counters[C_NWORK0 + par] = total;
+        if (threadIdx.x == 0) {
+            d.counters[C_NWORK0 + par] = total;
+            if (snap) {
+                snap[C_NWORK0 + par] = total;
+                snap[C_ROUNDS] = d.counters[C_ROUNDS];
+            }
+        }
     }
     fold_list(d, f);
 }
@@ -2088,8 +2110,8 @@ void launch_fold_grow_slots(const Dev& d, hipStream_t s) {
     hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(1024), 0, s, d, kGrowFold);
 }
 
-void launch_chunk_end(const Dev& d, int par, hipStream_t s) {
-    hipLaunchKernelGGL(k_chunk_end, dim3(1), dim3(1024), 0, s, d, par, kGrowFold);
+void launch_chunk_end(const Dev& d, int par, uint32_t* snap, hipStream_t s) {
+    hipLaunchKernelGGL(k_chunk_end, dim3(1), dim3(1024), 0, s, d, par, kGrowFold, snap);
 }
 
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {

@@ -185,8 +185,9 @@ void launch_fold_slots(const Dev& d, int which, int dst, hipStream_t s, bool ass
 // (added) in one launch.
 void launch_fold_grow_slots(const Dev& d, hipStream_t s);
 // End of a chunk of launched rounds, in one launch: the work total of parity
-// par (as launch_work_total) and the per-grow statistics folded (as
-// launch_fold_grow_slots).
-void launch_chunk_end(const Dev& d, int par, hipStream_t s);
+// par (as launch_work_total), with snap non-null a copy of counters[C_ROUNDS]
+// and of that total into snap (the read-outs' gate), and the per-grow
+// statistics folded (as launch_fold_grow_slots).
+void launch_chunk_end(const Dev& d, int par, uint32_t* snap, hipStream_t s);
 
 }  // namespace mf4d

@@ -172,6 +172,17 @@ class Grower:
                                             ctypes.byref(st)))
         return st.as_dict()
 
+    def set_read_async(self, on: bool):
+        """grow_read leaves its read-outs deferred: the next grow_read
+        issues them beside its own rounds (two label sets); read_wait() or
+        any other call issues what is deferred and orders the context stream
+        after them."""
+        self._check(self.lib.mf4d_set_read_async(self.ctx, 1 if on else 0))
+
+    def read_wait(self):
+        """Issue deferred read-outs and order the context stream after them."""
+        self._check(self.lib.mf4d_read_wait(self.ctx))
+
     def grow_resume(self) -> dict:
         st = Stats()
         self._check(self.lib.mf4d_grow_resume(self.ctx, ctypes.byref(st)))
