@@ -304,8 +304,15 @@ def bench_slic(torch, log, inst, name, k=SLIC_K, cpu_leg=True):
                        f"c_f = {SLIC_CF}",
             "ms_per_iteration": round(ms_iter, 3), "value": round(N / (ms_iter * 1e-3), 1),
             "unit": "samples/s per iteration",
+            # bound by VALU issue in the candidate loop: the field pass's
+            # wave instructions (SQ_INSTS_VALU + SALU + branch + LDS) per second
+            # against 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64
+            # instruction, from the counter run in
+            # profiles/slic_256x256x256x64_k16x16x16x4_kernel_trace.md (not
+            # measurable without the profiler)
             "roofline": {"bound": "alu (distance evaluation)", "hbm_bytes_per_iteration": b,
-                         "achieved_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)},
+                         "achieved_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "issue_peak_wave_instr_per_s": 6.144e11, "issue_frac_profiled": 0.73},
             "parity_sampled": parity, "parity_samples": int(len(got)),
             "merge": {"eps_m": SLIC_EPS_M, "ms": round(ms_merge, 3), "features": n_feat,
                       "largest_feature_samples": big, "parity_feature_ids": merge_parity},
@@ -668,6 +675,23 @@ def main():
     ms = r0["ms"]
     # the same steps again with the library's phase events, for per-kernel times
     r = run_steps(g, fmask, pmask, args.steps, 1, torch, instrumented=True)
+    # a cold step: the first grow of a fresh context (its first chunk of
+    # rounds is not sized from a previous grow), stream-ordered read-outs
+    g2 = Grower(device=0, tile_t=choice["tile_t"])
+    try:
+        g2.load_field(torch.from_numpy(inst["field"]).to(dev))
+        g2.load_particles(torch.from_numpy(inst["xyz"]).to(dev), torch.from_numpy(inst["attr"]).to(dev))
+        g2.set_criteria(*inst["crit"])
+        g2.set_seeds(inst["seeds"])
+        g2.set_schedule(choice["schedule"])
+        g2.set_admit_mode(choice["admit"])
+        torch.cuda.synchronize()
+        tc0 = time.perf_counter()
+        g2.grow_read(fmask, pmask)
+        torch.cuda.synchronize()
+        ms_cold = (time.perf_counter() - tc0) * 1e3
+    finally:
+        g2.close()
     st = r["stats"]
     log(f"[bench] {args.steps} steps, {ms:.3f} ms/step, rounds {st['rounds']}, "
         f"tile visits {st['tile_visits']}, members {st['members_field']} / {st['members_particle']}")
@@ -812,6 +836,7 @@ def main():
             "kernels": kt, "coupled_steps": st["coupled_steps"],
             "ms_grow": round(r["ms_grow"], 4),
             "ms_per_step_instrumented": round(r["ms"], 4),
+            "ms_first_grow_fresh_context": round(ms_cold, 4),
             "parity_vs_oracle": parity,
             "autotune": tune["table"] if tune else None,
         },

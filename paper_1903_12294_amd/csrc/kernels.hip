@@ -307,6 +307,7 @@ __device__ void mark_voxels(const Dev& d, const uint32_t* b, int par) {
         for (int j = 0; j < k; ++j) dup |= nb[j] == tile;
         if (dup) continue;
         d.chg[par * g.NT + tile] = 1;
+        d.counters[C_CHG0 + par] = 1u;
         nb[k++] = tile;
     }
     schedule_batch(d, nb, k, par);
@@ -460,7 +461,10 @@ __device__ void sweep_tile(const Dev& d, uint32_t tile, int par) {
         const bool fzm = __ballot(zl == 0 && fany) != 0, fzp = __ballot(zl == 7 && fany) != 0;
         const bool ftm = __ballot(nt0 != 0) != 0, ftp = __ballot(nt1 != 0) != 0;
         if (lane == 0) {
-            if (changed) d.chg[par * g.NT + tile] = 1;
+            if (changed) {
+                d.chg[par * g.NT + tile] = 1;
+                d.counters[C_CHG0 + par] = 1u;
+            }
             const int nx = par ^ 1;
             uint32_t nb[8];
             int k = 0;
@@ -1715,6 +1719,7 @@ __global__ __launch_bounds__(256) void k_round_sweep(Dev d, int par) {
     // round's pull; clear them before this round's pull pushes set them again
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < d.g.NT; i += gridDim.x * blockDim.x)
         d.chg[(par ^ 1) * d.g.NT + i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.counters[C_CHG0 + (par ^ 1)] = 0u;
     const uint32_t nwork = sweep_phase<BT>(d, par, wave0, nwaves);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         d.counters[C_RACT] = nwork ? 1u : 0u;  // pull and close of this round read it
@@ -1732,6 +1737,9 @@ __global__ __launch_bounds__(256) void k_round_pull(Dev d, int par) {
     // the swept list is empty again (its dirty flags were cleared by the sweeps)
     if (blockIdx.x == 0 && threadIdx.x < (unsigned)kWorkSubs)
         d.wcnt[(par * kWorkSubs + threadIdx.x) * kWcntStride] = 0u;
+    // no tile's members changed since the last pull (set flags raise the
+    // parity's flag word): nothing can join
+    if (!d.pull_all && !d.counters[C_CHG0 + par]) return;
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t n = d.counters[C_NLIST];
     if (d.pg.W == 1) {

@@ -69,6 +69,8 @@ enum Counter : int {
     C_NCAND = 7,   // candidate tiles
     C_RACT = 8,    // launched rounds: 1 if the current round has work (set by its sweep)
     C_JCHANGED = 9,  // Jacobi sweeps: the sweep added a node
+    C_CHG0 = 10,   // some tile is flagged changed for round parity 0 (cleared by the sweep of parity 1)
+    C_CHG1 = 11,   // likewise for parity 1
     C_NCOUNTERS = 16
 };
 
