@@ -208,6 +208,8 @@ struct mf4d_ctx {
         bool valid;
     } dread = {nullptr, nullptr, 0, false};  // deferred read-outs of the last grow
     hipEvent_t ev_issue = nullptr;    // where deferred read-outs may start
+    int issue_round = 1;              // launched rounds: issue them after this many rounds (measured:
+                                      // after 0-2 alike, after 3 slower)
     int lset = 0;                     // index of the current label set
     uint32_t* Lf_alt = nullptr;
     uint8_t* active_alt = nullptr;
@@ -636,8 +638,14 @@ int run_rounds(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
             c->state = 2;
             break;
         }
-        for (int64_t k = 0; k < chunk; ++k)
+        for (int64_t k = 0; k < chunk; ++k) {
             launch_round(d, (uint32_t)(c->round + k), c->stream, c->timed ? c->rev + 4 * k : nullptr);
+            if (c->async_grow && c->dread.valid && r == 0 && k + 1 == c->issue_round) {
+                HIP_TRY(hipEventRecord(c->ev_issue, c->stream));
+                int rc = issue_deferred(c, c->ev_issue, false);
+                if (rc) return rc;
+            }
+        }
         // work total and the grow's statistics, read back together, so that
         // finish_stats needs no wait of its own after the last chunk; the
         // read-outs pending are queued gated on this chunk reaching the
@@ -1256,9 +1264,11 @@ int grow_impl(mf4d_ctx* c, mf4d_stats* out) {
     launch_admit_particles(d, s);
     if (c->timed) HIP_TRY(hipEventRecord(c->ev[2], s));
     launch_seeds(d, c->seeds, c->S, s);
-    if (c->async_grow && c->dread.valid) {
+    if (c->async_grow && c->dread.valid && (c->schedule != MF4D_SCHED_LAUNCH || c->issue_round == 0)) {
         // the grow before's read-outs, beside this grow's rounds (after its
-        // admissibility passes, the bandwidth-heavy part)
+        // admissibility passes, the bandwidth-heavy part; with launched
+        // rounds after the first issue_round rounds, whose sweeps iterate
+        // longest)
         HIP_TRY(hipEventRecord(c->ev_issue, s));
         int rc = issue_deferred(c, c->ev_issue, false);
         if (rc) return rc;

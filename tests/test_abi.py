@@ -100,3 +100,6 @@ def test_new_calls_reject_null_without_gpu():
     assert lib.mf4d_set_scheduler(None, 0, None, 0) == _lib.MF4D_ERR_ARG
     assert lib.mf4d_read_batched(None, None, 0, None, 0, 0) == _lib.MF4D_ERR_ARG
     assert lib.mf4d_nn_adam_step(None, None, ctypes.c_float(1e-3), 1) == _lib.MF4D_ERR_ARG
+    assert lib.mf4d_grow_read(None, None, 0, None, 0, None) == _lib.MF4D_ERR_ARG
+    assert lib.mf4d_set_read_async(None, 1) == _lib.MF4D_ERR_ARG
+    assert lib.mf4d_read_wait(None) == _lib.MF4D_ERR_ARG
