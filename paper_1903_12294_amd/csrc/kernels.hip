@@ -289,6 +289,35 @@ __device__ __forceinline__ void schedule_batch_direct(const Dev& d, const uint32
     }
 }
 
+// As schedule_batch for up to N tiles (nb[i] = ~0u: none; all their flag
+// loads, then exchanges, then appends issued together; fixed indices only, so
+// that the arrays stay in registers).
+template <int N>
+__device__ __forceinline__ void schedule_batch_n(const Dev& d, const uint32_t* nb, int par) {
+    uint32_t* dirty = d.dirty + (size_t)par * d.g.NT;
+    uint32_t cur[N];
+    uint8_t act[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        act[i] = 0;
+        cur[i] = 1u;
+        if (nb[i] != ~0u) {
+            act[i] = d.active[nb[i]];
+            cur[i] = dirty[nb[i]];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) cur[i] = (nb[i] != ~0u && act[i] && cur[i] == 0u) ? atomicExch(&dirty[nb[i]], 1u) : 1u;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        if (cur[i] == 0u) {
+            const uint32_t j = (uint32_t)(par * kWorkSubs) + (nb[i] & (kWorkSubs - 1));
+            const uint32_t slot = atomicAdd(&d.wcnt[j * kWcntStride], 1u);
+            d.work[(size_t)j * d.g.WCAP + slot] = nb[i];
+        }
+    }
+}
+
 // Voxel bits set from outside a tile sweep (seeds, particle pushes), before
 // round parity `par`: each owning tile is flagged changed (its coupled steps
 // must be pulled) and scheduled.  Its sweep sees the flag and schedules every
@@ -316,6 +345,26 @@ __device__ void mark_voxels(const Dev& d, const uint32_t* b, int par) {
 __device__ __forceinline__ void mark_voxel(const Dev& d, uint32_t b, int par) {
     const uint32_t v[4] = {b, kNoVoxel, kNoVoxel, kNoVoxel};
     mark_voxels(d, v, par);
+}
+
+// mark_voxels for up to N voxels (kNoVoxel: none); a tile already named by an
+// earlier voxel of the lane is marked once.
+template <int N>
+__device__ void mark_voxels_n(const Dev& d, const uint32_t* b, int par) {
+    const Geom& g = d.g;
+    uint32_t tl[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        tl[i] = b[i] != kNoVoxel ? b[i] >> (5 + 6 + g.logBT) : ~0u;
+#pragma unroll
+        for (int j = 0; j < i; ++j)
+            if (tl[j] == tl[i]) tl[i] = ~0u;
+        if (tl[i] != ~0u) {
+            d.chg[par * g.NT + tl[i]] = 1;
+            d.counters[C_CHG0 + par] = 1u;
+        }
+    }
+    schedule_batch_n<N>(d, tl, par);
 }
 
 // ---------------------------------------------------------------------------
@@ -527,20 +576,21 @@ __device__ void pull_entries(const Dev& d, uint32_t i0, uint32_t stride, uint32_
     }
 }
 
-// Push up to 4 particle-steps per lane that joined (flat indices e = p * Tpad
+// Push up to N particle-steps per lane that joined (flat indices e = p * Tpad
 // + t; ~0u: none): each voxel joins when admissible, for round parity `par`.
-// Every step is issued for the 4 together (bins; activity, admissibility and
+// Every step is issued for the N together (bins; activity, admissibility and
 // label words; atomics; marking), and a voxel already a member takes no
 // atomic.
-__device__ void push_four(const Dev& d, const uint32_t* e, int par) {
+template <int N>
+__device__ void push_n(const Dev& d, const uint32_t* e, int par) {
     const Geom& g = d.g;
-    uint32_t b[4];
+    uint32_t b[N];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) b[i] = e[i] != 0xFFFFFFFFu ? d.bins[e[i]] : kNoVoxel;
-    uint8_t a[4];
-    uint32_t aw[4], lw[4];
+    for (int i = 0; i < N; ++i) b[i] = e[i] != 0xFFFFFFFFu ? d.bins[e[i]] : kNoVoxel;
+    uint8_t a[N];
+    uint32_t aw[N], lw[N];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < N; ++i) {
         a[i] = 0;
         aw[i] = lw[i] = 0;
         if (b[i] != kNoVoxel) {
@@ -549,9 +599,10 @@ __device__ void push_four(const Dev& d, const uint32_t* e, int par) {
             lw[i] = d.Lf[b[i] >> 5];
         }
     }
-    uint32_t got[4];
+    uint32_t got[N];
+    uint32_t any = kNoVoxel;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < N; ++i) {
         got[i] = kNoVoxel;
         if (b[i] == kNoVoxel) continue;
         const uint32_t bit = 1u << (b[i] & 31);
@@ -559,8 +610,9 @@ __device__ void push_four(const Dev& d, const uint32_t* e, int par) {
         bool adm = a[i] == 1 && (aw[i] & bit);
         if (a[i] == 2) adm = in_band(d.field[voxel_of_bit(g, b[i])], d.crit[0], d.crit[1]);
         if (adm && !(atomicOr(&d.Lf[b[i] >> 5], bit) & bit)) got[i] = b[i];
+        any &= got[i];
     }
-    if ((got[0] & got[1] & got[2] & got[3]) != kNoVoxel) mark_voxels(d, got, par);
+    if (any != kNoVoxel) mark_voxels_n<N>(d, got, par);
 }
 
 // Push one particle-step that joined (flat index e = p * Tpad + t): its voxel
@@ -624,7 +676,7 @@ __device__ void push_wave_word(const Dev& d, uint32_t p, int w, unsigned long lo
 #pragma unroll
         for (int i = 0; i < 4; ++i) e[i] = (uint32_t)lane + 64 * i < m ? s_list[lane + 64 * i] : 0xFFFFFFFFu;
         wave_sync();
-        push_four(d, e, par);
+        push_n<4>(d, e, par);
     }
 }
 
@@ -744,7 +796,7 @@ __device__ __forceinline__ unsigned long long run_or(uint32_t key, unsigned long
 }
 
 // Pull fused with close, for one 64-step label word per particle (W = 1).  A
-// wave takes 256 list entries at a time (4 per lane); the list holds a
+// wave takes 64 NE list entries at a time (NE per lane); the list holds a
 // particle's entries side by side, in step order.  A coupled step whose voxel
 // is a member joins; the joining steps of a run of lanes holding the same
 // particle are ORed into the run's last lane, which ORs their trajectory
@@ -752,9 +804,10 @@ __device__ __forceinline__ unsigned long long run_or(uint32_t key, unsigned long
 // only ever gain closed sets (closure distributes over union), so the bits
 // that atomic sets, less the joining steps themselves (in member voxels
 // already), are exactly the steps the closure adds; the lane that set them
-// pushes them.  The new steps of the wave are gathered in LDS (s_list: 256
-// words) and pushed 256 at a time, four per lane (pushes schedule for
-// parity par ^ 1).  Returns this lane's number of steps joined.
+// pushes them.  The new steps of the wave are gathered in LDS (s_list: 64 PB
+// words) and pushed 64 PB at a time, PB per lane (pushes schedule for parity
+// par ^ 1).  Returns this lane's number of steps joined.
+template <int NE, int PB>
 __device__ uint32_t pull_close_wave(const Dev& d, int par, uint32_t wave_id, uint32_t nwaves,
                                     uint32_t n, uint32_t* s_list) {
     const PGeom& pg = d.pg;
@@ -762,22 +815,22 @@ __device__ uint32_t pull_close_wave(const Dev& d, int par, uint32_t wave_id, uin
     const uint8_t* chg = d.chg + par * d.g.NT;
     const int lane = lane_id();
     uint32_t joins = 0;
-    for (uint32_t base = wave_id * 256u; base < n; base += nwaves * 256u) {  // wave-uniform
-        uint2 ent[4];
+    for (uint32_t base = wave_id * (64u * NE); base < n; base += nwaves * (64u * NE)) {  // wave-uniform
+        uint2 ent[NE];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < NE; ++k) {
             const uint32_t j = base + k * 64 + lane;
             ent[k] = j < n ? d.clist[j] : make_uint2(0u, kNoVoxel);
         }
         // the label word is read only for steps in changed tiles (most are not)
-        bool mem[4];
+        bool mem[NE];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
+        for (int k = 0; k < NE; ++k)
             mem[k] = ent[k].y != kNoVoxel && pull_tile(d, chg, ent[k].y >> tshift) && test_bit(d.Lf, ent[k].y);
-        uint32_t pk[4];
-        unsigned long long nwk[4];
+        uint32_t pk[NE];
+        unsigned long long nwk[NE];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < NE; ++k) {
             pk[k] = 0;
             nwk[k] = 0ull;
             if (!__ballot(mem[k])) continue;  // wave-uniform
@@ -794,26 +847,30 @@ __device__ uint32_t pull_close_wave(const Dev& d, int par, uint32_t wave_id, uin
             nwk[k] = cl & ~old & ~mine;
             pk[k] = p;
         }
-        while (__ballot((nwk[0] | nwk[1] | nwk[2] | nwk[3]) != 0)) {
+        while (true) {
+            unsigned long long anyn = 0ull;
+#pragma unroll
+            for (int k = 0; k < NE; ++k) anyn |= nwk[k];
+            if (!__ballot(anyn != 0)) break;
             uint32_t cnt = 0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) cnt += __popcll(nwk[k]);
+            for (int k = 0; k < NE; ++k) cnt += __popcll(nwk[k]);
             uint32_t tot;
             uint32_t kk = wave_excl_scan(cnt, tot);
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                while (nwk[k] && kk < 256) {
+            for (int k = 0; k < NE; ++k)
+                while (nwk[k] && kk < 64u * PB) {
                     const int t = __builtin_ctzll(nwk[k]);
                     nwk[k] &= nwk[k] - 1;
                     s_list[kk++] = pk[k] * (uint32_t)pg.Tpad + t;
                 }
             wave_sync();
-            const uint32_t m = tot < 256 ? tot : 256;
-            uint32_t e[4];
+            const uint32_t m = tot < 64u * PB ? tot : 64u * PB;
+            uint32_t e[PB];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) e[i] = (uint32_t)lane + 64 * i < m ? s_list[lane + 64 * i] : 0xFFFFFFFFu;
+            for (int i = 0; i < PB; ++i) e[i] = (uint32_t)lane + 64 * i < m ? s_list[lane + 64 * i] : 0xFFFFFFFFu;
             wave_sync();
-            push_four(d, e, par ^ 1);
+            push_n<PB>(d, e, par ^ 1);
         }
     }
     return joins;
@@ -1744,7 +1801,7 @@ __global__ __launch_bounds__(256) void k_round_pull(Dev d, int par) {
     const uint32_t n = d.counters[C_NLIST];
     if (d.pg.W == 1) {
         const uint32_t joins =
-            pull_close_wave(d, par, tid >> 6, (gridDim.x * blockDim.x) >> 6, n, s_list + 256 * (threadIdx.x >> 6));
+            pull_close_wave<4, 4>(d, par, tid >> 6, (gridDim.x * blockDim.x) >> 6, n, s_list + 256 * (threadIdx.x >> 6));
         block_slot_sum(d, SL_PART_VISITS, joins);
     } else {
         pull_entries(d, tid, gridDim.x * blockDim.x, n, par);
@@ -1767,16 +1824,22 @@ __global__ __launch_bounds__(256) void k_round_close(Dev d, int par) {
 }
 
 // ---- all rounds in one cooperative launch ----
+// Pull entries and pushes per lane per wave step inside the persistent kernel:
+// its grid (two blocks per CU) has a quarter of the waves a launched pull has,
+// so each wave takes more entries at once, and pushes more at once, instead of
+// running the chain of round trips several times over.
+constexpr int kCoopNE = 8;
+
 template <int BT>
 __global__ __launch_bounds__(256) void k_rounds(Dev d, uint32_t round0, uint32_t max_rounds) {
-    __shared__ uint32_t s_list[4 * 256];
+    __shared__ uint32_t s_list[4 * 64 * kCoopNE];
     __shared__ uint32_t s_cnt;
     uint32_t epoch = 0;
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t nthreads = gridDim.x * blockDim.x;
     const uint32_t wave0 = tid >> 6, nwaves = nthreads >> 6;
     const bool parts = d.pg.P > 0;
-    uint32_t* my_list = s_list + 256 * (threadIdx.x >> 6);
+    uint32_t* my_list = s_list + 64 * kCoopNE * (threadIdx.x >> 6);
     if (threadIdx.x == 0) s_cnt = 0;
     uint32_t r = round0;
     uint32_t visits = 0, closed = 0;
@@ -1798,7 +1861,7 @@ __global__ __launch_bounds__(256) void k_rounds(Dev d, uint32_t round0, uint32_t
         if (tid < (unsigned)kWorkSubs) store_relaxed(&d.wcnt[(par * kWorkSubs + tid) * kWcntStride], 0u);
         if (parts) {
             const uint32_t n = load_relaxed(&d.counters[C_NLIST]);
-            if (d.pg.W == 1) closed += pull_close_wave(d, par, wave0, nwaves, n, my_list);
+            if (d.pg.W == 1) closed += pull_close_wave<kCoopNE, kCoopNE>(d, par, wave0, nwaves, n, my_list);
             else pull_entries(d, tid, nthreads, n, par);
         }
         if (!grid_sync(d, epoch)) break;
