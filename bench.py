@@ -169,6 +169,37 @@ def run_steps(g, fmask, pmask, steps: int, warmup: int, torch, instrumented: boo
                 ms_read=float(np.mean(reads)) if reads else 0.0, stats=last)
 
 
+def run_in_flight(gs, bufs, steps: int, warmup: int, torch):
+    """Two grows in flight: contexts gs[0] and gs[1] (each loaded with the
+    same data, each on its own stream) take the steps in turn; step i is
+    submitted on context i % 2 once the host has finished that context's
+    step i - 2, so step i - 1 runs on the device meanwhile.  Wall time over
+    the timed steps, bracketed by device synchronisations."""
+    pending = [False, False]
+    stats = []
+
+    def run(n):
+        for i in range(n):
+            k = i & 1
+            if pending[k]:
+                stats.append(gs[k].grow_finish())
+            gs[k].grow_submit(*bufs[k])
+            pending[k] = True
+        for k in (0, 1):
+            if pending[k]:
+                stats.append(gs[k].grow_finish())
+                pending[k] = False
+
+    run(warmup)
+    torch.cuda.synchronize()
+    stats.clear()
+    w0 = time.perf_counter()
+    run(steps)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - w0) * 1e3 / steps
+    return dict(ms=ms, rounds=[s["rounds"] for s in stats])
+
+
 SLIC_K = (16, 16, 16, 4)     # centres per axis (x, y, z, t): 16,384 centres
 SLIC_W = (1.0, 8.0, 8.0)     # w_d, w_f, w_p
 SLIC_CF = 2.0                # time-to-space factor
@@ -600,6 +631,8 @@ def main():
     ap.add_argument("--tile-t", type=int, choices=[4, 8, 16], help="fix the tile depth (no tuning)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="the headline grow only (no other form)")
+    ap.add_argument("--in-flight", type=int, choices=[1, 2], default=1,
+                    help="grows in flight: 2 = two contexts on two streams take the steps in turn")
     ap.add_argument("--sync-reads", action="store_true",
                     help="headline steps with stream-ordered read-outs (default: asynchronous, "
                          "each step's read-outs beside the next step's rounds)")
@@ -672,7 +705,38 @@ def main():
     fmask = torch.empty((V + 31) // 32, dtype=torch.int32, device=dev)
     pmask = torch.empty((T, P), dtype=torch.uint8, device=dev)
     r0 = run_steps(g, fmask, pmask, args.steps, args.warmup, torch, read_async=not args.sync_reads)
-    ms = r0["ms"]
+    ms_one = r0["ms"]
+    ms = ms_one
+    flight = None
+    if args.in_flight == 2:
+        # a second context on its own stream, loaded with the same data, and
+        # this one moved to a stream of its own: two grows in flight
+        streams = [torch.cuda.Stream(device=dev) for _ in range(2)]
+        ga = Grower(device=0, stream=streams[0].cuda_stream, tile_t=choice["tile_t"])
+        gb = Grower(device=0, stream=streams[1].cuda_stream, tile_t=choice["tile_t"])
+        try:
+            for gx in (ga, gb):
+                gx.load_field(torch.from_numpy(inst["field"]).to(dev))
+                gx.load_particles(torch.from_numpy(inst["xyz"]).to(dev), torch.from_numpy(inst["attr"]).to(dev))
+                gx.set_criteria(*inst["crit"])
+                gx.set_seeds(inst["seeds"])
+                gx.set_schedule(choice["schedule"])
+                gx.set_admit_mode(choice["admit"])
+            bufs = [(torch.full_like(fmask, -1), torch.full_like(pmask, 0xFF)) for _ in range(2)]
+            torch.cuda.synchronize()
+            rf = run_in_flight([ga, gb], bufs, args.steps, args.warmup, torch)
+            torch.cuda.synchronize()
+            same = all(bool(torch.equal(f, fmask) and torch.equal(p, pmask)) for f, p in bufs)
+            flight = {"ms_per_step": round(rf["ms"], 4), "ms_per_step_one_in_flight": round(ms_one, 4),
+                      "masks_equal": same, "rounds": sorted(set(rf["rounds"]))}
+            if not same:
+                raise SystemExit("[bench] two grows in flight gave other masks than one")
+            ms = rf["ms"]
+        finally:
+            ga.close()
+            gb.close()
+            del bufs
+            torch.cuda.empty_cache()
     # the same steps again with the library's phase events, for per-kernel times
     r = run_steps(g, fmask, pmask, args.steps, 1, torch, instrumented=True)
     # a cold step: the first grow of a fresh context (its first chunk of
@@ -823,8 +887,10 @@ def main():
                    "voxel_steps": V, "particle_steps": Q,
                    "tile": f"32x8x8x{choice['tile_t']}", "schedule": choice["schedule"],
                    "admissibility": choice["admit"],
-                   "read_out": "stream-ordered" if args.sync_reads else
-                               "asynchronous: each step's read-outs beside the next step's rounds"},
+                   "in_flight": 2 if flight else 1,
+                   "read_out": ("queued behind each grow's rounds (two contexts alternate)" if flight else
+                                "stream-ordered" if args.sync_reads else
+                                "asynchronous: each step's read-outs beside the next step's rounds")},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "detail": {
@@ -837,6 +903,8 @@ def main():
             "ms_grow": round(r["ms_grow"], 4),
             "ms_per_step_instrumented": round(r["ms"], 4),
             "ms_first_grow_fresh_context": round(ms_cold, 4),
+            "ms_per_step_one_in_flight": round(ms_one, 4),
+            "two_in_flight": flight,
             "parity_vs_oracle": parity,
             "autotune": tune["table"] if tune else None,
         },

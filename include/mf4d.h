@@ -308,6 +308,32 @@ int mf4d_set_read_async(mf4d_ctx *ctx, int on);
  * without waiting for the device.  Errors: MF4D_ERR_ARG (ctx NULL). */
 int mf4d_read_wait(mf4d_ctx *ctx);
 
+/* mf4d_grow_read in two calls, so that the host need not wait for one grow
+ * before it queues the next (Section 3.3's iteration to the fixed point,
+ * with its end tested later).  mf4d_grow_submit queues the grow (reset,
+ * admissibility, seeding, a first chunk of rounds as long as the context's
+ * last converged grow, the statistics copy and the read-outs, gated on that
+ * chunk reaching the fixed point) and returns without waiting for the
+ * device.  mf4d_grow_finish waits for that chunk; if the grow needs more
+ * rounds it runs them and the read-outs as mf4d_grow_read would, and it
+ * returns the grow's statistics and status (MF4D_ERR_NOT_CONVERGED with a
+ * round cap).  Two contexts on two streams, each loaded with the same data,
+ * can so keep two grows in flight: one's rounds, bound by the latency of
+ * dependent memory accesses, run beside the other's admissibility passes and
+ * rounds.  Buffers as mf4d_grow_read; the caller keeps them alive and
+ * unused until mf4d_grow_finish has returned and the context stream has
+ * reached that point.  Any other call on the context (except
+ * mf4d_last_error and mf4d_version) completes a submitted grow first and
+ * keeps its result for mf4d_grow_finish.  With a score-ordered scheduler,
+ * phase timing, Jacobi sweeps or the persistent schedule, mf4d_grow_submit
+ * runs the whole grow at once.
+ * Errors (submit): as mf4d_grow_read's argument and state errors;
+ * MF4D_ERR_STATE (a submitted grow not yet finished).
+ * Errors (finish): MF4D_ERR_STATE (nothing submitted); otherwise the grow's
+ * own, as mf4d_grow_read. */
+int mf4d_grow_submit(mf4d_ctx *ctx, uint32_t *field_dst, size_t nwords, uint8_t *particle_dst, size_t n);
+int mf4d_grow_finish(mf4d_ctx *ctx, mf4d_stats *out);
+
 /* Trajectory segments of the grown feature (Section 3.4, visual
  * representation): a trajectory is split where it leaves the feature, and
  * only pieces of at least two consecutive member steps are kept.  Writes

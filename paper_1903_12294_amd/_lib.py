@@ -118,6 +118,8 @@ SIGNATURES = {
     "mf4d_grow_read": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, POINTER(Stats)]),
     "mf4d_set_read_async": (c_int, [c_void_p, c_int]),
     "mf4d_read_wait": (c_int, [c_void_p]),
+    "mf4d_grow_submit": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_size_t]),
+    "mf4d_grow_finish": (c_int, [c_void_p, POINTER(Stats)]),
     "mf4d_read_field_mask": (c_int, [c_void_p, c_void_p, c_size_t, c_int]),
     "mf4d_read_particle_mask": (c_int, [c_void_p, c_void_p, c_size_t, c_int]),
     "mf4d_read_particle_segments": (c_int, [c_void_p, c_void_p, c_size_t, c_int]),

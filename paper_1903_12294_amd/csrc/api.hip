@@ -218,6 +218,20 @@ struct mf4d_ctx {
     bool alt_ready = false;           // the other set's buffers hold no uninitialised words
     hipEvent_t ev_read[2] = {nullptr, nullptr};  // read-outs of label set k done
     bool read_pending[2] = {false, false};
+    // A submitted grow (mf4d_grow_submit): 2 while its first chunk of rounds
+    // and read-outs are queued and the host has not looked at them, 1 once
+    // its result is kept for mf4d_grow_finish, 0 with none.
+    int submitted = 0;
+    Dev sub_d{};                      // its buffers and criteria
+    int64_t sub_chunk = 0;            // rounds in its queued chunk
+    int sub_npar = 0;
+    uint32_t* sub_f = nullptr;
+    size_t sub_nwords = 0;
+    uint8_t* sub_p = nullptr;
+    size_t sub_n = 0;
+    int sub_rc = 0;
+    std::string sub_err;
+    mf4d_stats sub_stats{};
 
     // batched queries
     int Q = 0;
@@ -414,6 +428,8 @@ int read_counters(mf4d_ctx* c) {
 
 constexpr size_t kStatBytes = S_NSTAT * sizeof(unsigned long long) + C_NCOUNTERS * sizeof(uint32_t);
 
+int settle_submit(mf4d_ctx* c);
+
 Dev make_dev(mf4d_ctx* c) {
     Dev d{};
     d.g = c->g;
@@ -495,6 +511,7 @@ int issue_deferred(mf4d_ctx* c, hipEvent_t after, bool last) {
 // asynchronous grow_read starts with it, so nothing it queues can touch
 // labels, member counts or buffers those read-outs use.
 int settle_async(mf4d_ctx* c) {
+    settle_submit(c);
     int rc = issue_deferred(c, nullptr, true);
     if (rc) return rc;
     for (int k = 0; k < 2; ++k)
@@ -536,7 +553,8 @@ int join_reads(mf4d_ctx* c) {
 
 // Statistics and counters to the host in one copy; read-outs pending are
 // queued behind it (they run while the host waits for the copy only).
-int read_chunk(mf4d_ctx* c, const ReadGate& gate) {
+// queue_stat_copy queues; read_chunk also waits for the copy.
+int queue_stat_copy(mf4d_ctx* c, const ReadGate& gate) {
     hipStream_t s = c->stream;
     HIP_TRY(hipEventRecord(c->ev_chunk, s));
     HIP_TRY(hipMemcpyAsync(c->h_stat, c->stat64, kStatBytes, hipMemcpyDeviceToHost, s));
@@ -546,6 +564,12 @@ int read_chunk(mf4d_ctx* c, const ReadGate& gate) {
         if (rc) return rc;
     }
     HIP_TRY(hipGetLastError());
+    return MF4D_OK;
+}
+
+int read_chunk(mf4d_ctx* c, const ReadGate& gate) {
+    int rc = queue_stat_copy(c, gate);
+    if (rc) return rc;
     HIP_TRY(hipEventSynchronize(c->ev_stat));
     return MF4D_OK;
 }
@@ -587,14 +611,74 @@ int run_jacobi(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
     return MF4D_OK;
 }
 
+// Launched rounds are queued a chunk at a time (a round with an empty work
+// list is a no-op on the device), and the host reads the counters once per
+// chunk.  C_ROUNDS counts the rounds that had work.  Each host read costs
+// about three queued empty rounds (measured), so the first chunk of a grow is
+// as long as the context's last converged grow (4 to 16 rounds), the later
+// ones kRoundChunk; with phase timing every chunk is kRoundChunk (one set of
+// events per round).
+struct RoundChunk {
+    int64_t n;  // rounds queued (0: the round cap was reached)
+    int npar;   // parity of the round after the chunk
+};
+
+// Queue the chunk of rounds that starts r rounds into the grow, its
+// chunk-end kernel, the statistics copy and the read-outs pending (gated on
+// this chunk reaching the fixed point).  The host does not wait.
+int queue_chunk(mf4d_ctx* c, const Dev& d, int64_t r, RoundChunk* ch) {
+    constexpr int64_t kRoundChunk = 4, kMaxChunk = 16;
+    const uint32_t cap = (uint32_t)(c->max_rounds > 0 ? c->max_rounds : 0);
+    int64_t chunk = kRoundChunk;
+    if (r == 0 && !c->timed) chunk = std::min(std::max(c->last_rounds, kRoundChunk), kMaxChunk);
+    if (cap && cap - r < chunk) chunk = cap - r;
+    ch->n = chunk > 0 ? chunk : 0;
+    ch->npar = 0;
+    if (chunk <= 0) return MF4D_OK;
+    for (int64_t k = 0; k < chunk; ++k) {
+        launch_round(d, (uint32_t)(c->round + k), c->stream, c->timed ? c->rev + 4 * k : nullptr);
+        if (c->async_grow && c->dread.valid && r == 0 && k + 1 == c->issue_round) {
+            HIP_TRY(hipEventRecord(c->ev_issue, c->stream));
+            int rc = issue_deferred(c, c->ev_issue, false);
+            if (rc) return rc;
+        }
+    }
+    // work total and the grow's statistics, read back together, so that
+    // finish_stats needs no wait of its own after the last chunk
+    const int npar = (int)((c->round + chunk) & 1);
+    uint32_t* snap = (c->rd_f || c->rd_p) ? c->gsnap + c->lset * C_NCOUNTERS : nullptr;
+    launch_chunk_end(d, npar, snap, c->stream);
+    ch->npar = npar;
+    return queue_stat_copy(c, ReadGate{snap, (uint32_t)(r + chunk), npar});
+}
+
+// Wait for a queued chunk's counters: the rounds it did (r advances by
+// them) and whether the grow reached the fixed point.
+int settle_chunk(mf4d_ctx* c, int64_t* r, const RoundChunk& ch, bool* converged) {
+    HIP_TRY(hipEventSynchronize(c->ev_stat));
+    c->stats_ready = true;
+    const int64_t done = (int64_t)c->h_counters[C_ROUNDS] - *r;
+    for (int64_t k = 0; c->timed && k < done && k < ch.n; ++k)
+        for (int ph = 0; ph < 3; ++ph) {
+            float ms = 0;
+            HIP_TRY(hipEventElapsedTime(&ms, c->rev[4 * k + ph], c->rev[4 * k + ph + 1]));
+            c->ms_phase[ph] += ms;
+        }
+    c->round += (uint32_t)done;
+    *r += done;
+    *converged = done < ch.n || c->h_counters[C_NWORK0 + (c->round & 1)] == 0;
+    return join_reads(c);
+}
+
 // Rounds until a round's work list is empty (converged) or the cap is hit.
 // Persistent: one cooperative launch runs every round; if it cannot be
 // launched, or a grid barrier timed out, the rounds run as launches instead.
-int run_rounds(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
+// queued: a first chunk of launched rounds already queued (a submitted grow).
+int run_rounds(mf4d_ctx* c, const Dev& d, int64_t* rounds_done, const RoundChunk* queued = nullptr) {
     if (c->schedule == MF4D_SCHED_JACOBI) return run_jacobi(c, d, rounds_done);
     const uint32_t cap = (uint32_t)(c->max_rounds > 0 ? c->max_rounds : 0);
     const uint32_t r0 = c->round;
-    if (c->schedule == MF4D_SCHED_PERSISTENT) {
+    if (c->schedule == MF4D_SCHED_PERSISTENT && !queued) {
         if (c->round != 0) {  // a fresh grow's reset cleared them
             launch_fill_u32(c->counters + C_ERR, 0, 2, c->stream);  // C_ERR, C_ROUNDS
             launch_fill_u32(c->bar, 0, kBarWords, c->stream);
@@ -620,53 +704,24 @@ int run_rounds(mf4d_ctx* c, const Dev& d, int64_t* rounds_done) {
         }
         (void)hipGetLastError();
     }
-    // Launches: rounds are queued a chunk at a time (a round with an empty
-    // work list is a no-op on the device), and the host reads the counters once
-    // per chunk.  C_ROUNDS counts the rounds that had work.  Each host read
-    // costs about three queued empty rounds (measured), so the first chunk of a
-    // grow is as long as the context's last converged grow (4 to 16 rounds),
-    // the later ones kRoundChunk; with phase timing every chunk is kRoundChunk
-    // (one set of events per round).
-    constexpr int64_t kRoundChunk = 4, kMaxChunk = 16;
-    if (c->round != 0) launch_fill_u32(c->counters + C_ROUNDS, 0, 1, c->stream);  // fresh: reset cleared it
+    // Launches: rounds are queued a chunk at a time (queue_chunk), the host
+    // waiting for each chunk's counters (settle_chunk).
+    if (!queued && c->round != 0) launch_fill_u32(c->counters + C_ROUNDS, 0, 1, c->stream);  // fresh: reset cleared it
     int64_t r = 0;
+    RoundChunk ch{0, 0};
+    if (queued) ch = *queued;
     while (true) {
-        int64_t chunk = kRoundChunk;
-        if (r == 0 && !c->timed) chunk = std::min(std::max(c->last_rounds, kRoundChunk), kMaxChunk);
-        if (cap && cap - r < chunk) chunk = cap - r;
-        if (chunk <= 0) {  // cap reached with work left
+        if (!queued) {
+            int rc = queue_chunk(c, d, r, &ch);
+            if (rc) return rc;
+        }
+        queued = nullptr;
+        if (ch.n <= 0) {  // cap reached with work left
             c->state = 2;
             break;
         }
-        for (int64_t k = 0; k < chunk; ++k) {
-            launch_round(d, (uint32_t)(c->round + k), c->stream, c->timed ? c->rev + 4 * k : nullptr);
-            if (c->async_grow && c->dread.valid && r == 0 && k + 1 == c->issue_round) {
-                HIP_TRY(hipEventRecord(c->ev_issue, c->stream));
-                int rc = issue_deferred(c, c->ev_issue, false);
-                if (rc) return rc;
-            }
-        }
-        // work total and the grow's statistics, read back together, so that
-        // finish_stats needs no wait of its own after the last chunk; the
-        // read-outs pending are queued gated on this chunk reaching the
-        // fixed point
-        const int npar = (int)((c->round + chunk) & 1);
-        uint32_t* snap = (c->rd_f || c->rd_p) ? c->gsnap + c->lset * C_NCOUNTERS : nullptr;
-        launch_chunk_end(d, npar, snap, c->stream);
-        int rc = read_chunk(c, ReadGate{snap, (uint32_t)(r + chunk), npar});
-        if (rc) return rc;
-        c->stats_ready = true;
-        const int64_t done = (int64_t)c->h_counters[C_ROUNDS] - r;
-        for (int64_t k = 0; c->timed && k < done && k < chunk; ++k)
-            for (int ph = 0; ph < 3; ++ph) {
-                float ms = 0;
-                HIP_TRY(hipEventElapsedTime(&ms, c->rev[4 * k + ph], c->rev[4 * k + ph + 1]));
-                c->ms_phase[ph] += ms;
-            }
-        c->round += (uint32_t)done;
-        r += done;
-        const bool converged = done < chunk || c->h_counters[C_NWORK0 + (c->round & 1)] == 0;
-        rc = join_reads(c);
+        bool converged = false;
+        int rc = settle_chunk(c, &r, ch, &converged);
         if (rc) return rc;
         if (converged) {
             c->state = 1;
@@ -832,6 +887,7 @@ void mf4d_destroy(mf4d_ctx* c) {
 
 int mf4d_set_tile(mf4d_ctx* c, int bt) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    settle_submit(c);  // a submitted grow first
     if (bt != 4 && bt != 8 && bt != 16) return fail(MF4D_ERR_ARG, "tile t-extent %d not in {4,8,16}", bt);
     if (c->has_field) return fail(MF4D_ERR_STATE, "tile shape must be set before the field is loaded");
     c->bt = bt;
@@ -1021,6 +1077,7 @@ int mf4d_load_particles_rate(mf4d_ctx* c, const float* xyz, const float* attr, i
 
 int mf4d_set_criteria(mf4d_ctx* c, float f_lo, float f_hi, float a_lo, float a_hi) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    settle_submit(c);  // a submitted grow first
     if (f_lo != f_lo || f_hi != f_hi || a_lo != a_lo || a_hi != a_hi)
         return fail(MF4D_ERR_ARG, "a criterion bound is NaN");
     c->crit[0] = f_lo;
@@ -1034,6 +1091,7 @@ int mf4d_set_criteria(mf4d_ctx* c, float f_lo, float f_hi, float a_lo, float a_h
 
 int mf4d_set_seeds(mf4d_ctx* c, const int32_t* xyzt, int64_t S, int where) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    settle_submit(c);  // a submitted grow first
     if (!c->has_field) return fail(MF4D_ERR_STATE, "load the field before the seeds");
     if (S < 0 || (S > 0 && !xyzt)) return fail(MF4D_ERR_ARG, "bad seed array");
     if (where != MF4D_HOST && where != MF4D_DEVICE) return fail(MF4D_ERR_ARG, "bad where");
@@ -1087,6 +1145,7 @@ int mf4d_set_seeds(mf4d_ctx* c, const int32_t* xyzt, int64_t S, int where) {
 
 int mf4d_set_max_rounds(mf4d_ctx* c, int64_t cap) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    settle_submit(c);  // a submitted grow first
     if (cap < 0) return fail(MF4D_ERR_ARG, "cap < 0");
     c->max_rounds = cap;
     return MF4D_OK;
@@ -1094,6 +1153,7 @@ int mf4d_set_max_rounds(mf4d_ctx* c, int64_t cap) {
 
 int mf4d_set_admit_mode(mf4d_ctx* c, int mode) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    settle_submit(c);  // a submitted grow first
     if (mode != MF4D_ADMIT_TILES && mode != MF4D_ADMIT_ALL)
         return fail(MF4D_ERR_ARG, "unknown admissibility mode %d", mode);
     c->admit_all = mode == MF4D_ADMIT_ALL;
@@ -1102,6 +1162,7 @@ int mf4d_set_admit_mode(mf4d_ctx* c, int mode) {
 
 int mf4d_set_trajectory_mode(mf4d_ctx* c, int mode) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    settle_submit(c);  // a submitted grow first
     if (mode != MF4D_TRAJ_BOTH && mode != MF4D_TRAJ_FORWARD)
         return fail(MF4D_ERR_ARG, "unknown trajectory mode %d", mode);
     c->forward_only = mode == MF4D_TRAJ_FORWARD;
@@ -1111,6 +1172,7 @@ int mf4d_set_trajectory_mode(mf4d_ctx* c, int mode) {
 
 int mf4d_set_phase_timing(mf4d_ctx* c, int on) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    settle_submit(c);  // a submitted grow first
     if (on != 0 && on != 1) return fail(MF4D_ERR_ARG, "on must be 0 or 1");
     c->phase_timing = on == 1;
     return MF4D_OK;
@@ -1118,6 +1180,7 @@ int mf4d_set_phase_timing(mf4d_ctx* c, int on) {
 
 int mf4d_set_schedule(mf4d_ctx* c, int mode) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    settle_submit(c);  // a submitted grow first
     if (mode != MF4D_SCHED_PERSISTENT && mode != MF4D_SCHED_LAUNCH && mode != MF4D_SCHED_JACOBI)
         return fail(MF4D_ERR_ARG, "unknown schedule %d", mode);
     c->schedule = mode;
@@ -1126,7 +1189,7 @@ int mf4d_set_schedule(mf4d_ctx* c, int mode) {
 
 // Brick statistics (network input) of the loaded field and particles, on the
 // context's stream; computed once per load, when first needed.
-void ensure_brick_stats(mf4d_ctx* c) {
+static void ensure_brick_stats(mf4d_ctx* c) {
     if (c->bstats_valid) return;
     launch_brick_stats(c->g, c->has_particles ? c->pg : PGeom{}, c->bd, c->field,
                        c->has_particles ? c->bins : nullptr, c->bstats, c->stream);
@@ -1134,7 +1197,7 @@ void ensure_brick_stats(mf4d_ctx* c) {
 }
 
 // Buffers of the score-ordered schedulers (sized by the tile count).
-int ensure_priority(mf4d_ctx* c) {
+static int ensure_priority(mf4d_ctx* c) {
     if (c->pr_buf) return MF4D_OK;
     const uint32_t NT = c->g.NT;
     int rc = dev_alloc(&c->pr_buf, 4 * (size_t)NT + 1);
@@ -1156,7 +1219,7 @@ int ensure_priority(mf4d_ctx* c) {
 
 // The verification round after the rounds converged (run as launches
 // whatever the schedule), then plain rounds while it found work.
-int verify_round(mf4d_ctx* c, const Dev& d, int64_t* rounds) {
+static int verify_round(mf4d_ctx* c, const Dev& d, int64_t* rounds) {
     c->stats_ready = false;
     const int par = (int)(c->round & 1);
     launch_verify_schedule(d, par, c->stream);
@@ -1179,7 +1242,15 @@ int verify_round(mf4d_ctx* c, const Dev& d, int64_t* rounds) {
 // A fresh grow; with rd_f / rd_p set, their read-outs are queued behind the
 // rounds where the schedule allows it (reads_done then reports whether they
 // ran on the final labels).
-int grow_impl(mf4d_ctx* c, mf4d_stats* out) {
+// A grow in two halves around its rounds: grow_begin queues the reset,
+// admissibility, seeding and (score-ordered) the priority pass; grow_end
+// runs the verification round, takes the statistics and marks the labels.
+struct GrowRun {
+    Dev d;
+    bool ordered;
+};
+
+static int grow_begin(mf4d_ctx* c, GrowRun* gr) {
     if (!c->has_field) return fail(MF4D_ERR_STATE, "no field loaded");
     if (!c->has_crit) return fail(MF4D_ERR_STATE, "no criteria set");
     HIP_TRY(hipSetDevice(c->device));
@@ -1274,11 +1345,16 @@ int grow_impl(mf4d_ctx* c, mf4d_stats* out) {
         if (rc) return rc;
     }
     if (ordered) launch_priority_sweep(d, plist, pcount, c->pr_waves, s);
-    int64_t rounds = 0;
-    int rc = run_rounds(c, d, &rounds);
-    if (rc) return rc;
+    gr->d = d;
+    gr->ordered = ordered;
+    return MF4D_OK;
+}
+
+static int grow_end(mf4d_ctx* c, const GrowRun& gr, int64_t rounds, mf4d_stats* out) {
+    const Dev& d = gr.d;
+    int rc = MF4D_OK;
     int64_t verify_rounds = 0;
-    if (ordered && c->state == 1) {
+    if (gr.ordered && c->state == 1) {
         // verification round: every tile holding an admissible voxel-step is
         // swept and every coupled particle-step pulled; should anything
         // change, the plain rounds continue until nothing does
@@ -1286,7 +1362,7 @@ int grow_impl(mf4d_ctx* c, mf4d_stats* out) {
         if (rc) return rc;
     }
     if (c->state == 1) c->last_rounds = rounds;
-    if (c->timed) HIP_TRY(hipEventRecord(c->ev[3], s));
+    if (c->timed) HIP_TRY(hipEventRecord(c->ev[3], c->stream));
     rc = finish_stats(c, out, true, rounds + verify_rounds);
     if (rc) return rc;
     c->stats.verify_rounds = verify_rounds;
@@ -1294,6 +1370,16 @@ int grow_impl(mf4d_ctx* c, mf4d_stats* out) {
     mark_labels(c);
     if (c->state == 2) return fail(MF4D_ERR_NOT_CONVERGED, "stopped after %lld rounds", (long long)rounds);
     return MF4D_OK;
+}
+
+static int grow_impl(mf4d_ctx* c, mf4d_stats* out) {
+    GrowRun gr;
+    int rc = grow_begin(c, &gr);
+    if (rc) return rc;
+    int64_t rounds = 0;
+    rc = run_rounds(c, gr.d, &rounds);
+    if (rc) return rc;
+    return grow_end(c, gr, rounds, out);
 }
 
 int mf4d_grow(mf4d_ctx* c, mf4d_stats* out) {
@@ -1318,9 +1404,12 @@ int mf4d_read_wait(mf4d_ctx* c) {
     return settle_async(c);
 }
 
-int mf4d_grow_read(mf4d_ctx* c, uint32_t* field_dst, size_t nwords, uint8_t* particle_dst, size_t n,
-                   mf4d_stats* out) {
-    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+}  // extern "C"
+
+namespace {
+
+int check_read_buffers(mf4d_ctx* c, const uint32_t* field_dst, size_t nwords, const uint8_t* particle_dst,
+                       size_t n) {
     if (!c->has_field) return fail(MF4D_ERR_STATE, "no field loaded");
     if (particle_dst && !c->has_particles) return fail(MF4D_ERR_STATE, "no particles loaded");
     const uint64_t V = (uint64_t)c->g.X * c->g.Y * c->g.Z * c->g.T;
@@ -1328,30 +1417,20 @@ int mf4d_grow_read(mf4d_ctx* c, uint32_t* field_dst, size_t nwords, uint8_t* par
         return fail(MF4D_ERR_ARG, "field_dst holds %zu words, %llu needed", nwords, (unsigned long long)((V + 31) / 32));
     if (particle_dst && n < (size_t)c->pg.P * c->pg.T)
         return fail(MF4D_ERR_ARG, "particle_dst holds %zu bytes, %zu needed", n, (size_t)c->pg.P * c->pg.T);
-    // Queued behind the rounds only where the labels are final when the
-    // rounds end: not with a verification round (score-ordered schedulers),
-    // Jacobi sweeps or phase timing (events per round).
+    return MF4D_OK;
+}
+
+// Read-outs queued behind the rounds only where the labels are final when
+// the rounds end: not with a verification round (score-ordered schedulers),
+// Jacobi sweeps or phase timing (events per round).
+bool reads_can_queue(const mf4d_ctx* c) {
     const bool ordered = c->priority != MF4D_SCHEDULER_PLAIN && !c->admit_all;
-    const bool queue = !ordered && !c->phase_timing && c->schedule != MF4D_SCHED_JACOBI;
-    if (queue && c->read_async) {
-        // asynchronous: the read-outs are deferred (issued beside the next
-        // asynchronous grow's rounds, or by the next other call) and read
-        // the labels as this grow leaves them, converged or not
-        c->async_grow = true;
-        int rc = grow_impl(c, out);
-        c->async_grow = false;
-        if (rc != MF4D_OK && rc != MF4D_ERR_NOT_CONVERGED) return rc;
-        c->dread.f = field_dst;
-        c->dread.p = particle_dst;
-        c->dread.set = c->lset;
-        c->dread.valid = field_dst || particle_dst;
-        if (rc == MF4D_ERR_NOT_CONVERGED) return fail(rc, "stopped after %lld rounds", (long long)c->stats.rounds);
-        return MF4D_OK;
-    }
-    c->rd_f = queue ? field_dst : nullptr;
-    c->rd_p = queue ? particle_dst : nullptr;
-    c->reads_done = false;
-    int rc = grow_impl(c, out);
+    return !ordered && !c->phase_timing && c->schedule != MF4D_SCHED_JACOBI;
+}
+
+// After a grow whose read-outs were queued behind its rounds (rc: the
+// grow's status): where they did not run on the final labels, read out now.
+int finish_grow_read(mf4d_ctx* c, int rc, uint32_t* field_dst, size_t nwords, uint8_t* particle_dst, size_t n) {
     const bool done = c->reads_done;
     c->rd_f = nullptr;
     c->rd_p = nullptr;
@@ -1372,6 +1451,110 @@ int mf4d_grow_read(mf4d_ctx* c, uint32_t* field_dst, size_t nwords, uint8_t* par
         }
     }
     if (rc == MF4D_ERR_NOT_CONVERGED) return fail(rc, "stopped after %lld rounds", (long long)c->stats.rounds);
+    return MF4D_OK;
+}
+
+// The rest of a submitted grow: wait for its first chunk, run the rounds it
+// still needs, take its statistics and read out where needed.
+int complete_submitted(mf4d_ctx* c, mf4d_stats* out) {
+    c->submitted = 0;
+    HIP_TRY(hipSetDevice(c->device));
+    const GrowRun gr{c->sub_d, false};
+    const RoundChunk ch{c->sub_chunk, c->sub_npar};
+    int64_t rounds = 0;
+    int rc = run_rounds(c, gr.d, &rounds, &ch);
+    if (!rc) rc = grow_end(c, gr, rounds, out);
+    return finish_grow_read(c, rc, c->sub_f, c->sub_nwords, c->sub_p, c->sub_n);
+}
+
+// Any call on a context with a submitted grow completes that grow first and
+// keeps its result for mf4d_grow_finish.
+int settle_submit(mf4d_ctx* c) {
+    if (c->submitted != 2) return MF4D_OK;
+    c->sub_rc = complete_submitted(c, &c->sub_stats);
+    c->sub_err = c->sub_rc ? std::string(mf4d_last_error()) : std::string();
+    c->submitted = 1;
+    return MF4D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mf4d_grow_read(mf4d_ctx* c, uint32_t* field_dst, size_t nwords, uint8_t* particle_dst, size_t n,
+                   mf4d_stats* out) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    settle_submit(c);
+    int rc = check_read_buffers(c, field_dst, nwords, particle_dst, n);
+    if (rc) return rc;
+    const bool queue = reads_can_queue(c);
+    if (queue && c->read_async) {
+        // asynchronous: the read-outs are deferred (issued beside the next
+        // asynchronous grow_read's rounds, or by the next other call) and read
+        // the labels as this grow leaves them, converged or not
+        c->async_grow = true;
+        rc = grow_impl(c, out);
+        c->async_grow = false;
+        if (rc != MF4D_OK && rc != MF4D_ERR_NOT_CONVERGED) return rc;
+        c->dread.f = field_dst;
+        c->dread.p = particle_dst;
+        c->dread.set = c->lset;
+        c->dread.valid = field_dst || particle_dst;
+        if (rc == MF4D_ERR_NOT_CONVERGED) return fail(rc, "stopped after %lld rounds", (long long)c->stats.rounds);
+        return MF4D_OK;
+    }
+    c->rd_f = queue ? field_dst : nullptr;
+    c->rd_p = queue ? particle_dst : nullptr;
+    c->reads_done = false;
+    rc = grow_impl(c, out);
+    return finish_grow_read(c, rc, field_dst, nwords, particle_dst, n);
+}
+
+int mf4d_grow_submit(mf4d_ctx* c, uint32_t* field_dst, size_t nwords, uint8_t* particle_dst, size_t n) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    if (c->submitted) return fail(MF4D_ERR_STATE, "a submitted grow awaits mf4d_grow_finish");
+    int rc = check_read_buffers(c, field_dst, nwords, particle_dst, n);
+    if (rc) return rc;
+    if (!reads_can_queue(c) || c->schedule != MF4D_SCHED_LAUNCH) {
+        // the whole grow now; its result waits for mf4d_grow_finish
+        c->sub_rc = mf4d_grow_read(c, field_dst, nwords, particle_dst, n, &c->sub_stats);
+        c->sub_err = c->sub_rc ? std::string(mf4d_last_error()) : std::string();
+        c->submitted = 1;
+        return MF4D_OK;
+    }
+    HIP_TRY(hipSetDevice(c->device));
+    rc = settle_async(c);
+    if (rc) return rc;
+    c->rd_f = field_dst;
+    c->rd_p = particle_dst;
+    c->reads_done = false;
+    GrowRun gr;
+    rc = grow_begin(c, &gr);
+    RoundChunk ch{0, 0};
+    if (!rc) rc = queue_chunk(c, gr.d, 0, &ch);
+    if (rc) {
+        c->rd_f = nullptr;
+        c->rd_p = nullptr;
+        return rc;
+    }
+    c->sub_d = gr.d;
+    c->sub_chunk = ch.n;
+    c->sub_npar = ch.npar;
+    c->sub_f = field_dst;
+    c->sub_nwords = nwords;
+    c->sub_p = particle_dst;
+    c->sub_n = n;
+    c->submitted = 2;
+    return MF4D_OK;
+}
+
+int mf4d_grow_finish(mf4d_ctx* c, mf4d_stats* out) {
+    if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    if (!c->submitted) return fail(MF4D_ERR_STATE, "no submitted grow");
+    if (c->submitted == 2) return complete_submitted(c, out);
+    c->submitted = 0;
+    if (out) *out = c->sub_stats;
+    if (c->sub_rc) return fail(c->sub_rc, "%s", c->sub_err.c_str());
     return MF4D_OK;
 }
 
@@ -1417,7 +1600,7 @@ int mf4d_reset_labels(mf4d_ctx* c) {
 
 // Member counts folded on the device by stream-ordered reads: copy them to
 // the host (once, when asked for) and record them.
-int settle_members(mf4d_ctx* c) {
+static int settle_members(mf4d_ctx* c) {
     if (!c->members_pending[0] && !c->members_pending[1]) return MF4D_OK;
     HIP_TRY(hipMemcpyAsync(c->h_stat + S_MEMBERS_F, c->stat64 + S_MEMBERS_F, 2 * sizeof(unsigned long long),
                            hipMemcpyDeviceToHost, c->stream));
@@ -1689,6 +1872,7 @@ int mf4d_set_queries(mf4d_ctx* c, int Q, const float* crit, const int32_t* qxyzt
 
 int mf4d_set_batched_tile(mf4d_ctx* c, int bx, int by, int bz, int bt) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    settle_submit(c);  // a submitted grow first
     const int e[4] = {bx, by, bz, bt};
     int lg[4];
     for (int i = 0; i < 4; ++i) {
@@ -1900,6 +2084,7 @@ int mf4d_read_batched(mf4d_ctx* c, uint32_t* fdst, size_t fwords, uint32_t* pdst
 
 int mf4d_set_predictor(mf4d_ctx* c, mf4d_net* net, float logit_threshold) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    settle_submit(c);  // a submitted grow first
     if (logit_threshold != logit_threshold) return fail(MF4D_ERR_ARG, "threshold is NaN");
     c->net = net;
     c->pred_thr = logit_threshold;
@@ -1908,6 +2093,7 @@ int mf4d_set_predictor(mf4d_ctx* c, mf4d_net* net, float logit_threshold) {
 
 int mf4d_set_scheduler(mf4d_ctx* c, int kind, const void* params, size_t nbytes) {
     if (!c) return fail(MF4D_ERR_ARG, "ctx is NULL");
+    settle_submit(c);  // a submitted grow first
     if (kind == MF4D_SCHEDULER_PLAIN || kind == MF4D_SCHEDULER_HEURISTIC) {
         if (params || nbytes) return fail(MF4D_ERR_ARG, "this scheduler takes no parameters");
         c->net = nullptr;
@@ -2003,6 +2189,7 @@ int mf4d_last_stats(mf4d_ctx* c, mf4d_stats* out) {
 int mf4d_slic_set_params(mf4d_ctx* c, const int* k4, float w_d, float w_f, float w_p, float c_f,
                          double eps, int max_iter) {
     if (!c || !k4) return fail(MF4D_ERR_ARG, "NULL argument");
+    settle_submit(c);  // a submitted grow first
     int64_t K = 1;
     for (int i = 0; i < 4; ++i) {
         if (k4[i] < 1 || k4[i] > 4096) return fail(MF4D_ERR_ARG, "k[%d] = %d not in [1, 4096]", i, k4[i]);

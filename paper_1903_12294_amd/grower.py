@@ -172,6 +172,25 @@ class Grower:
                                             ctypes.byref(st)))
         return st.as_dict()
 
+    def grow_submit(self, field_out=None, particle_out=None):
+        """Queue grow_read's work and return without waiting for the device;
+        grow_finish() returns its statistics.  The output tensors must stay
+        untouched until then."""
+        for a in (field_out, particle_out):
+            if a is not None and not _is_device_tensor(a):
+                raise ValueError("grow_submit writes device tensors only")
+        fp = ctypes.c_void_p(field_out.data_ptr()) if field_out is not None else None
+        pp = ctypes.c_void_p(particle_out.data_ptr()) if particle_out is not None else None
+        self._check(self.lib.mf4d_grow_submit(self.ctx, fp, field_out.numel() if field_out is not None else 0,
+                                              pp, particle_out.numel() if particle_out is not None else 0))
+
+    def grow_finish(self) -> dict:
+        """Complete the submitted grow (more rounds if it needs them) and
+        return its statistics, as grow_read would."""
+        st = Stats()
+        self._check(self.lib.mf4d_grow_finish(self.ctx, ctypes.byref(st)))
+        return st.as_dict()
+
     def set_read_async(self, on: bool):
         """grow_read leaves its read-outs deferred: the next grow_read
         issues them beside its own rounds (two label sets); read_wait() or

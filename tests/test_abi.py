@@ -103,3 +103,5 @@ def test_new_calls_reject_null_without_gpu():
     assert lib.mf4d_grow_read(None, None, 0, None, 0, None) == _lib.MF4D_ERR_ARG
     assert lib.mf4d_set_read_async(None, 1) == _lib.MF4D_ERR_ARG
     assert lib.mf4d_read_wait(None) == _lib.MF4D_ERR_ARG
+    assert lib.mf4d_grow_submit(None, None, 0, None, 0) == _lib.MF4D_ERR_ARG
+    assert lib.mf4d_grow_finish(None, None) == _lib.MF4D_ERR_ARG
