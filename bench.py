@@ -130,8 +130,9 @@ def run_steps(g, fmask, pmask, steps: int, warmup: int, torch, instrumented: boo
     g.set_read_async(read_async and not instrumented)
 
     def step():
-        # the grow with both read-outs queued behind its rounds (one call)
-        return g.grow_read(fmask, pmask)
+        # the grow with both read-outs queued behind its rounds (one call);
+        # its statistics are read after the timed steps
+        g.grow_read(fmask, pmask, stats=False)
 
     for _ in range(warmup):
         step()
@@ -153,7 +154,7 @@ def run_steps(g, fmask, pmask, steps: int, warmup: int, torch, instrumented: boo
             reads.append(rd.stop())
             stats.append(st)
         else:
-            stats.append(step())
+            step()
     g.read_wait()
     ev1.record()
     torch.cuda.synchronize()
@@ -162,7 +163,7 @@ def run_steps(g, fmask, pmask, steps: int, warmup: int, torch, instrumented: boo
     last = g.stats()
     g.set_phase_timing(False)
     g.set_read_async(False)
-    mean = lambda k: float(np.mean([s[k] for s in stats]))
+    mean = lambda k: float(np.mean([s[k] for s in stats])) if stats else 0.0
     return dict(ms=ms, ms_admit_field=mean("ms_admit_field"), ms_admit=mean("ms_admit"),
                 ms_rounds=mean("ms_rounds"), ms_grow=mean("ms_total"),
                 ms_sweep=mean("ms_sweep"), ms_pull=mean("ms_pull"), ms_close=mean("ms_close"),

@@ -567,11 +567,21 @@ int queue_stat_copy(mf4d_ctx* c, const ReadGate& gate) {
     return MF4D_OK;
 }
 
+// The host waits for a chunk's statistics by polling the event: a grow's
+// rounds take well under a millisecond, and a blocking wait adds a wake-up to
+// every grow while the device idles until the next grow is queued.
+int wait_stat(mf4d_ctx* c) {
+    hipError_t q;
+    while ((q = hipEventQuery(c->ev_stat)) == hipErrorNotReady) {
+    }
+    HIP_TRY(q);
+    return MF4D_OK;
+}
+
 int read_chunk(mf4d_ctx* c, const ReadGate& gate) {
     int rc = queue_stat_copy(c, gate);
     if (rc) return rc;
-    HIP_TRY(hipEventSynchronize(c->ev_stat));
-    return MF4D_OK;
+    return wait_stat(c);
 }
 
 // Jacobi sweeps until one adds nothing (converged) or the cap is hit; each
@@ -655,7 +665,8 @@ int queue_chunk(mf4d_ctx* c, const Dev& d, int64_t r, RoundChunk* ch) {
 // Wait for a queued chunk's counters: the rounds it did (r advances by
 // them) and whether the grow reached the fixed point.
 int settle_chunk(mf4d_ctx* c, int64_t* r, const RoundChunk& ch, bool* converged) {
-    HIP_TRY(hipEventSynchronize(c->ev_stat));
+    int rc = wait_stat(c);
+    if (rc) return rc;
     c->stats_ready = true;
     const int64_t done = (int64_t)c->h_counters[C_ROUNDS] - *r;
     for (int64_t k = 0; c->timed && k < done && k < ch.n; ++k)

@@ -156,21 +156,22 @@ class Grower:
         self._check(self.lib.mf4d_grow(self.ctx, ctypes.byref(st)))
         return st.as_dict()
 
-    def grow_read(self, field_out=None, particle_out=None) -> dict:
+    def grow_read(self, field_out=None, particle_out=None, stats: bool = True):
         """grow() and the read-out of both masks in one call, the read-outs
         queued on the device behind the rounds: field_out (int32 device
         tensor of field_words() words) and particle_out (uint8 device tensor
-        of T*P bytes), either None to skip.  Statistics as grow()."""
+        of T*P bytes), either None to skip.  Statistics as grow() (None with
+        stats=False; stats() still returns them)."""
         for a in (field_out, particle_out):
             if a is not None and not _is_device_tensor(a):
                 raise ValueError("grow_read writes device tensors only")
         fp = ctypes.c_void_p(field_out.data_ptr()) if field_out is not None else None
         pp = ctypes.c_void_p(particle_out.data_ptr()) if particle_out is not None else None
-        st = Stats()
+        st = Stats() if stats else None
         self._check(self.lib.mf4d_grow_read(self.ctx, fp, field_out.numel() if field_out is not None else 0,
                                             pp, particle_out.numel() if particle_out is not None else 0,
-                                            ctypes.byref(st)))
-        return st.as_dict()
+                                            ctypes.byref(st) if stats else None))
+        return st.as_dict() if stats else None
 
     def grow_submit(self, field_out=None, particle_out=None):
         """Queue grow_read's work and return without waiting for the device;
