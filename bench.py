@@ -369,7 +369,9 @@ def bench_batched(args, torch, log):
     X, Y, Z = inst["dims"]
     T, P = inst["T"], inst["P"]
     V = X * Y * Z * T
-    if args.no_tune:
+    if args.batched_tile:
+        tune = {"best": {"tile": list(args.batched_tile)}, "table": None}
+    elif args.no_tune:
         tune = {"best": {"tile": [8, 4, 4, 4]}, "table": None}
     else:
         tune = autotune.tune_batched(inst, crit, qseeds, repeats=1, use_cache=False)
@@ -647,6 +649,8 @@ def main():
                     help="only the learned-scheduling form at the chosen config (for profiling); "
                          "prints its JSON object")
     ap.add_argument("--batched-reps", type=int, default=3)
+    ap.add_argument("--batched-tile", type=int, nargs=4, metavar=("BX", "BY", "BZ", "BT"),
+                    help="fix the batched tile shape (no tuning)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run three 1 GiB device copies (a plain copy kernel of known size, "
                          "the scale for hardware byte counters)")
