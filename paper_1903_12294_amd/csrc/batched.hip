@@ -283,9 +283,23 @@ __global__ void kb_seeds(DevB d, const int32_t* __restrict__ seeds, int64_t S) {
     }
 }
 
+// Lane moves within a row of 16 lanes (DPP): lane i receives lane i - N
+// (shr) or i + N (shl) of its row; a lane whose source lies outside the row
+// receives 0.  Register-only: no LDS traffic.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_row(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+constexpr int kDppRowShr1 = 0x111, kDppRowShr4 = 0x114, kDppRowShl1 = 0x101, kDppRowShl4 = 0x104;
+
 // Sweep one tile (block of 512 threads, one voxel-step each) to a local fixed
 // point: Jacobi steps through LDS over the 8 in-tile neighbours, the out-of-
-// tile neighbours entering as fixed halos.
+// tile neighbours entering as fixed halos.  Tiles of 4 x 4 x 4 x 8 take a
+// faster route: a wave holds one 4 x 4 x 4 cube at one t (a row of 16 lanes
+// is one z-plane), so x and y neighbours are DPP row moves and z neighbours
+// lane permutes; each wave runs its cube to a fixed point with the t
+// neighbours held fixed, and only the t neighbours go through LDS, once per
+// block-wide pass.
 __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_lab,
                             uint32_t* s_flags, const uint32_t* s_ftab) {
     int bx, by, bz, bt;
@@ -388,7 +402,55 @@ __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_l
             s_lab[(k) * 512 + tid] = sv;                                    \
         }                                                                   \
     }
-    if (need) {
+    // The cube route: word k's in-wave fixed point with its t neighbours'
+    // words (read from LDS) and the halos held fixed.  A lane gains only
+    // bits admissible for it; labels only grow, so the loop ends.
+#define MF4D_CUBE_WORD(k)                                                       \
+    if ((need >> (k)) & 1u) {                                                  \
+        uint32_t fx = h[k];                                                    \
+        if (nt0 >= 0) fx |= s_lab[(k) * 512 + nt0];                            \
+        if (nt1 >= 0) fx |= s_lab[(k) * 512 + nt1];                            \
+        const uint32_t ak = a[k];                                              \
+        uint32_t cur = l[k];                                                   \
+        while (true) {                                                         \
+            const uint32_t xm = dpp_row<kDppRowShr1>(cur);                     \
+            const uint32_t xp = dpp_row<kDppRowShl1>(cur);                     \
+            const uint32_t ym = dpp_row<kDppRowShr4>(cur);                     \
+            const uint32_t yp = dpp_row<kDppRowShl4>(cur);                     \
+            const uint32_t zm = (uint32_t)__shfl((int)cur, (lane - 16) & 63);   \
+            const uint32_t zp = (uint32_t)__shfl((int)cur, (lane + 16) & 63);   \
+            uint32_t nb = fx;                                                  \
+            if (xl > 0) nb |= xm;                                              \
+            if (xl < 3) nb |= xp;                                              \
+            if (yl > 0) nb |= ym;                                              \
+            if (yl < 3) nb |= yp;                                              \
+            if (zl > 0) nb |= zm;                                              \
+            if (zl < 3) nb |= zp;                                              \
+            const uint32_t nv = cur | (nb & ak);                               \
+            const bool grew = nv != cur;                                       \
+            cur = nv;                                                          \
+            if (__ballot(grew) == 0) break;                                    \
+        }                                                                      \
+        if (cur != l[k]) {                                                     \
+            diff = 1u;                                                         \
+            l[k] = cur;                                                        \
+        }                                                                      \
+    }
+    const bool cube = d.lx == 2 && d.ly == 2 && d.lz == 2;  // block-uniform
+    if (need && cube) {
+        const int lane = tid & 63;
+        while (true) {
+            MF4D_STORE_WORD(0) MF4D_STORE_WORD(1) MF4D_STORE_WORD(2) MF4D_STORE_WORD(3)
+            MF4D_STORE_WORD(4) MF4D_STORE_WORD(5) MF4D_STORE_WORD(6) MF4D_STORE_WORD(7)
+            __syncthreads();
+            uint32_t diff = 0;
+            MF4D_CUBE_WORD(0) MF4D_CUBE_WORD(1) MF4D_CUBE_WORD(2) MF4D_CUBE_WORD(3)
+            MF4D_CUBE_WORD(4) MF4D_CUBE_WORD(5) MF4D_CUBE_WORD(6) MF4D_CUBE_WORD(7)
+            // every wave has read its t neighbours before the next pass
+            // stores; a pass with no change anywhere is the fixed point
+            if (!__syncthreads_or(diff != 0)) break;
+        }
+    } else if (need) {
         MF4D_STORE_WORD(0) MF4D_STORE_WORD(1) MF4D_STORE_WORD(2) MF4D_STORE_WORD(3)
         MF4D_STORE_WORD(4) MF4D_STORE_WORD(5) MF4D_STORE_WORD(6) MF4D_STORE_WORD(7)
         __syncthreads();
@@ -399,6 +461,7 @@ __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_l
             if (!__syncthreads_or(diff != 0)) break;
         }
     }
+#undef MF4D_CUBE_WORD
 #undef MF4D_STORE_WORD
 #undef MF4D_STEP_WORD
     uint32_t any = 0;

@@ -17,12 +17,14 @@ def _planes_to_masks(fplanes, pplanes, shape, T, P, q):
     return fbits, pbits
 
 
-def _run(inst, crit, qseeds, device_out=True):
+def _run(inst, crit, qseeds, device_out=True, tile=None):
     from paper_1903_12294_amd import Grower
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     g = Grower(device=0)
     try:
+        if tile:
+            g.set_batched_tile(*tile)
         g.load_field(inst["field"])
         if inst["xyz"].shape[1] > 0:
             g.load_particles(inst["xyz"], inst["attr"])
@@ -44,8 +46,8 @@ def _run(inst, crit, qseeds, device_out=True):
     return fp, pp, st
 
 
-def _check(inst, crit, qseeds, queries=None, device_out=True):
-    fp, pp, st = _run(inst, crit, qseeds, device_out)
+def _check(inst, crit, qseeds, queries=None, device_out=True, tile=None):
+    fp, pp, st = _run(inst, crit, qseeds, device_out, tile)
     T, P = inst["field"].shape[0], inst["xyz"].shape[1]
     Q = len(crit)
     res = oracle_grow_queries(inst["field"], inst["xyz"], inst["attr"], crit, qseeds,
@@ -62,8 +64,9 @@ def _check(inst, crit, qseeds, queries=None, device_out=True):
     return st
 
 
+@pytest.mark.parametrize("tile", [None, (4, 4, 4, 8)])
 @pytest.mark.parametrize("seed", range(6))
-def test_random_small_queries(seed):
+def test_random_small_queries(seed, tile):
     from tests.test_oracle_pins import _random_instance
     rng = np.random.default_rng(500 + seed)
     X, Y, Z = (int(v) for v in rng.integers(3, 40, 3))
@@ -77,14 +80,15 @@ def test_random_small_queries(seed):
     n = int(rng.integers(Q, 3 * Q + 1))
     qseeds = np.stack([rng.integers(0, X, n), rng.integers(0, Y, n), rng.integers(0, Z, n),
                        rng.integers(0, T, n), rng.integers(0, Q, n)], 1).astype(np.int32)
-    print(f"[batched] random{seed} {X}x{Y}x{Z}x{T} P={P} Q={Q}", flush=True)
-    _check(inst, crit, qseeds, device_out=(seed % 2 == 0))
+    print(f"[batched] random{seed} {X}x{Y}x{Z}x{T} P={P} Q={Q} tile {tile}", flush=True)
+    _check(inst, crit, qseeds, device_out=(seed % 2 == 0), tile=tile)
 
 
-def test_config1_256_queries():
+@pytest.mark.parametrize("tile", [None, (4, 4, 4, 8)])
+def test_config1_256_queries(tile):
     inst = synth.make_config(1)
     crit, qseeds = synth.make_queries(inst, Q=256)
-    _check(inst, crit, qseeds)
+    _check(inst, crit, qseeds, tile=tile)
 
 
 def test_config1_noise_attr_256_queries():

@@ -113,28 +113,37 @@ def test_config4_every_plane_equals_oracle():
     T, P = inst["T"], inst["P"]
     V = inst["field"].size
     dev = torch.device("cuda:0")
-    print("[fullsize] 128^3x32 x 256 queries: batched grow", flush=True)
+    # the default tile and the 4 x 4 x 4 x 8 tile (its sweep takes the
+    # in-wave cube route)
+    runs = []
     g = Grower(device=0)
     try:
         g.load_field(inst["field"])
         g.load_particles(inst["xyz"], inst["attr"])
         g.set_queries(crit, qseeds)
-        fp = torch.empty((V, 8), dtype=torch.int32, device=dev)
-        pp = torch.empty((T, P, 8), dtype=torch.int32, device=dev)
-        _, _, st = g.grow_batched(fp, pp)
-        torch.cuda.synchronize()
+        for shape in (None, (4, 4, 4, 8)):
+            print(f"[fullsize] 128^3x32 x 256 queries: batched grow, tile {shape}", flush=True)
+            if shape:
+                g.set_batched_tile(*shape)
+            fp = torch.empty((V, 8), dtype=torch.int32, device=dev)
+            pp = torch.empty((T, P, 8), dtype=torch.int32, device=dev)
+            _, _, st = g.grow_batched(fp, pp)
+            torch.cuda.synchronize()
+            runs.append((shape, fp, pp, st))
     finally:
         g.close()
     threads = min(16, os.cpu_count() or 1)
     print(f"[fullsize] 256 oracle grows on {threads} threads", flush=True)
     res = oracle_grow_queries(inst["field"], inst["xyz"], inst["attr"], crit, qseeds, threads=threads)
     assert sorted(res) == list(range(256))
-    for q in range(256):
-        ofm, opm, _ = res[q]
-        plane_f = ((fp[:, q >> 5] >> (q & 31)) & 1).to(torch.uint8)
-        got_f = _pack_plane(plane_f)
-        want_f = torch.from_numpy(ofm.astype(np.int64)).to(dev)
-        assert torch.equal(got_f, want_f), f"query {q}: field plane differs"
-        plane_p = ((pp[..., q >> 5] >> (q & 31)) & 1).to(torch.uint8)
-        assert torch.equal(plane_p, torch.from_numpy(opm).to(dev)), f"query {q}: particle plane differs"
-    print(f"[fullsize] all 256 planes equal; {st['rounds']} rounds", flush=True)
+    for shape, fp, pp, st in runs:
+        for q in range(256):
+            ofm, opm, _ = res[q]
+            plane_f = ((fp[:, q >> 5] >> (q & 31)) & 1).to(torch.uint8)
+            got_f = _pack_plane(plane_f)
+            want_f = torch.from_numpy(ofm.astype(np.int64)).to(dev)
+            assert torch.equal(got_f, want_f), f"tile {shape}, query {q}: field plane differs"
+            plane_p = ((pp[..., q >> 5] >> (q & 31)) & 1).to(torch.uint8)
+            assert torch.equal(plane_p, torch.from_numpy(opm).to(dev)), \
+                f"tile {shape}, query {q}: particle plane differs"
+        print(f"[fullsize] tile {shape}: all 256 planes equal; {st['rounds']} rounds", flush=True)
