@@ -135,26 +135,58 @@ __device__ __forceinline__ void bschedule(const DevB& d, uint32_t tile, int par)
     }
 }
 
+// Schedule up to N tiles for round parity `par` (~0u: none), each only if it
+// holds an admissible node (check: the tile's active flag is read first).
+// The flag loads, the exchanges and the appends are each issued for all N
+// together, so the whole costs three round trips, not three per tile.
+template <int N>
+__device__ __forceinline__ void bschedule_n(const DevB& d, const uint32_t (&tiles)[N], uint32_t check, int par) {
+    uint32_t act[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        act[i] = 0u;
+        if (tiles[i] != ~0u) act[i] = ((check >> i) & 1u) ? (uint32_t)d.active[tiles[i]] : 1u;
+    }
+    uint32_t old[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        old[i] = 1u;
+        if (act[i]) old[i] = atomicExch(&d.dirty[par * d.NTB + tiles[i]], 1u);
+    }
+    uint32_t slot[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        slot[i] = 0u;
+        if (!old[i]) {
+            const uint32_t j = (uint32_t)par * kBSubs + (tiles[i] & (kBSubs - 1));
+            slot[i] = atomicAdd(&d.wcnt[j * kBCntStride], 1u);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        if (!old[i]) {
+            const uint32_t j = (uint32_t)par * kBSubs + (tiles[i] & (kBSubs - 1));
+            d.work[(size_t)j * d.WCAPB + slot[i]] = tiles[i];
+        }
+}
+
 // Voxel bits set from outside a sweep: schedule its tile and the tiles whose
-// face it touches, and flag the tile for the pull.
-__device__ void bmark_voxel(const DevB& d, int x, int y, int z, int t, int par) {
+// face it touches (at most one per axis), and flag the tile for the pull.
+__device__ __forceinline__ void bmark_voxel(const DevB& d, int x, int y, int z, int t, int par) {
     const uint32_t tile = btile_of(d, x, y, z, t);
-    bschedule(d, tile, par);
     d.chg[par * d.NTB + tile] = 1;
     const uint32_t sy = d.NXb, sz = d.NXb * d.NYb, st = sz * d.NZb;
-    uint32_t nb[8];
-    int k = 0;
     const int mx = (1 << d.lx) - 1, my = (1 << d.ly) - 1, mz = (1 << d.lz) - 1, mt = (1 << d.lt) - 1;
-    if ((x & mx) == 0 && x > 0) nb[k++] = tile - 1;
-    if ((x & mx) == mx && x + 1 < d.X) nb[k++] = tile + 1;
-    if ((y & my) == 0 && y > 0) nb[k++] = tile - sy;
-    if ((y & my) == my && y + 1 < d.Y) nb[k++] = tile + sy;
-    if ((z & mz) == 0 && z > 0) nb[k++] = tile - sz;
-    if ((z & mz) == mz && z + 1 < d.Z) nb[k++] = tile + sz;
-    if ((t & mt) == 0 && t > 0) nb[k++] = tile - st;
-    if ((t & mt) == mt && t + 1 < d.T) nb[k++] = tile + st;
-    for (int i = 0; i < k; ++i)
-        if (d.active[nb[i]]) bschedule(d, nb[i], par);
+    uint32_t nb[5] = {tile, ~0u, ~0u, ~0u, ~0u};
+    if ((x & mx) == 0 && x > 0) nb[1] = tile - 1;
+    else if ((x & mx) == mx && x + 1 < d.X) nb[1] = tile + 1;
+    if ((y & my) == 0 && y > 0) nb[2] = tile - sy;
+    else if ((y & my) == my && y + 1 < d.Y) nb[2] = tile + sy;
+    if ((z & mz) == 0 && z > 0) nb[3] = tile - sz;
+    else if ((z & mz) == mz && z + 1 < d.Z) nb[3] = tile + sz;
+    if ((t & mt) == 0 && t > 0) nb[4] = tile - st;
+    else if ((t & mt) == mt && t + 1 < d.T) nb[4] = tile + st;
+    bschedule_n<5>(d, nb, 0x1Eu, par);  // the voxel's own tile unchecked
 }
 
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_tmp,
@@ -317,7 +349,7 @@ __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_l
         s_flags[1] = 0;
         s_flags[2] = 0;
     }
-    uint32_t a[8], l[8], l0[8], h[8];
+    uint32_t a[8], l[8], h[8];
     const uint64_t v = in ? vindex(d, x, y, z, t) : 0;
     if (in) {
         const uint32_t rv = d.vrank[v];
@@ -353,8 +385,7 @@ __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_l
 #pragma unroll
         for (int k = 0; k < 8; ++k) a[k] = l[k] = h[k] = 0;
     }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) l0[k] = l[k];
+    uint32_t grown = 0;  // some word of this node gained bits in this visit
     // in-tile neighbour thread ids (or -1)
     const int nx0 = xl > 0 ? tid - sxl : -1, nx1 = xl < mx ? tid + sxl : -1;
     const int ny0 = yl > 0 ? tid - syl : -1, ny1 = yl < my ? tid + syl : -1;
@@ -398,6 +429,7 @@ __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_l
         const uint32_t sv = nbv & a[k];                                     \
         if (sv != l[k]) {                                                   \
             diff = 1u;                                                      \
+            grown = 1u;                                                     \
             l[k] = sv;                                                      \
             s_lab[(k) * 512 + tid] = sv;                                    \
         }                                                                   \
@@ -433,6 +465,7 @@ __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_l
         }                                                                      \
         if (cur != l[k]) {                                                     \
             diff = 1u;                                                         \
+            grown = 1u;                                                        \
             l[k] = cur;                                                        \
         }                                                                      \
     }
@@ -466,8 +499,7 @@ __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_l
 #undef MF4D_STEP_WORD
     uint32_t any = 0;
     if (in) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) any |= l[k] & ~l0[k];
+        any = grown;
         // a tile is swept by one block per phase and nothing else writes its
         // nodes meanwhile (seeds and pushes come in other phases): the node's
         // 32 bytes go back with two plain stores
@@ -490,25 +522,26 @@ __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_l
         atomicOr(&s_flags[0], faces);
     }
     __syncthreads();
-    if (tid == 0) {
-        const uint32_t f = s_flags[0];
-        if (f) {
-            d.chg[par * d.NTB + tile] = 1;
-            const int nx = par ^ 1;
-            const uint32_t sy = d.NXb, sz = d.NXb * d.NYb, st = sz * d.NZb;
-            uint32_t nb[8];
-            int k = 0;
-            if ((f & 1) && bx > 0) nb[k++] = tile - 1;
-            if ((f & 2) && bx + 1 < d.NXb) nb[k++] = tile + 1;
-            if ((f & 4) && by > 0) nb[k++] = tile - sy;
-            if ((f & 8) && by + 1 < d.NYb) nb[k++] = tile + sy;
-            if ((f & 16) && bz > 0) nb[k++] = tile - sz;
-            if ((f & 32) && bz + 1 < d.NZb) nb[k++] = tile + sz;
-            if ((f & 64) && bt > 0) nb[k++] = tile - st;
-            if ((f & 128) && bt + 1 < d.NTb) nb[k++] = tile + st;
-            for (int i = 0; i < k; ++i)
-                if (d.active[nb[i]]) bschedule(d, nb[i], nx);
+    // lanes 0..7 of the first wave schedule the tiles across the eight faces
+    // that gained bits, side by side
+    const uint32_t f = s_flags[0];
+    if (f && tid < 8) {
+        if (tid == 0) d.chg[par * d.NTB + tile] = 1;
+        const uint32_t sy = d.NXb, sz = d.NXb * d.NYb, st = sz * d.NZb;
+        uint32_t nb[1] = {~0u};
+        if ((f >> tid) & 1u) {
+            switch (tid) {
+                case 0: if (bx > 0) nb[0] = tile - 1; break;
+                case 1: if (bx + 1 < d.NXb) nb[0] = tile + 1; break;
+                case 2: if (by > 0) nb[0] = tile - sy; break;
+                case 3: if (by + 1 < d.NYb) nb[0] = tile + sy; break;
+                case 4: if (bz > 0) nb[0] = tile - sz; break;
+                case 5: if (bz + 1 < d.NZb) nb[0] = tile + sz; break;
+                case 6: if (bt > 0) nb[0] = tile - st; break;
+                default: if (bt + 1 < d.NTb) nb[0] = tile + st; break;
+            }
         }
+        bschedule_n<1>(d, nb, 1u, par ^ 1);
     }
     __syncthreads();
 }
