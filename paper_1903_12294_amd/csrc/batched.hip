@@ -33,22 +33,23 @@ struct Mask8 {
 };
 
 // #{i : s[i] <= v} for s ascending (n <= 256); NaN v gives 0.
+// The predicate holds on a prefix of s: its length by halving steps of
+// fixed sizes (every lane takes the same steps: no divergence, one LDS read
+// each).
 __device__ __forceinline__ int rank_le(const float* s, int n, float v) {
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (s[mid] <= v) lo = mid + 1; else hi = mid;
-    }
-    return lo;
+    if (n <= 0) return 0;
+    int pos = 0;
+    for (int step = 1 << (31 - __clz(n)); step > 0; step >>= 1)
+        if (pos + step <= n && s[pos + step - 1] <= v) pos += step;
+    return pos;
 }
 // #{i : s[i] >= v} for s descending.
 __device__ __forceinline__ int rank_ge(const float* s, int n, float v) {
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (s[mid] >= v) lo = mid + 1; else hi = mid;
-    }
-    return lo;
+    if (n <= 0) return 0;
+    int pos = 0;
+    for (int step = 1 << (31 - __clz(n)); step > 0; step >>= 1)
+        if (pos + step <= n && s[pos + step - 1] >= v) pos += step;
+    return pos;
 }
 
 // Tables: sorted bounds and prefix masks, for one sample type.
@@ -238,25 +239,41 @@ __global__ __launch_bounds__(256) void kb_admit_field(DevB d) {
     const uint32_t* ftab = reinterpret_cast<const uint32_t*>(d.tab + 1024);
     const uint64_t V = (uint64_t)d.X * d.Y * d.Z * d.T;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < V; v += stride) {
-        const float f = __builtin_nontemporal_load(d.field + v);
-        const uint32_t r = (uint32_t)rank_le(s_b, d.Q, f) | ((uint32_t)rank_ge(s_b + 256, d.Q, f) << 16);
-        d.vrank[v] = r;
-        uint4* o = reinterpret_cast<uint4*>(d.fplanes + v * 8);
-        o[0] = make_uint4(0, 0, 0, 0);
-        o[1] = make_uint4(0, 0, 0, 0);
-        uint32_t any = 0;
-        if ((r & 0xFFFFu) && (r >> 16)) {
+    // four voxel-steps per thread and pass (stride apart, so each load and
+    // store instruction stays coalesced): their rank searches interleave
+    constexpr int kU = 4;
+    for (uint64_t v0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v0 < V; v0 += kU * stride) {
+        float f[kU];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) any |= rank_word(ftab, r, k);
+        for (int u = 0; u < kU; ++u) {
+            const uint64_t v = v0 + u * stride;
+            f[u] = v < V ? __builtin_nontemporal_load(d.field + v) : 0.0f;
         }
-        if (any) {
-            const int x = (int)(v % d.X);
-            const uint64_t r = v / d.X;
-            const int y = (int)(r % d.Y);
-            const uint64_t r2 = r / d.Y;
-            const int z = (int)(r2 % d.Z), t = (int)(r2 / d.Z);
-            d.active[btile_of(d, x, y, z, t)] = 1;
+        uint32_t r[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            r[u] = (uint32_t)rank_le(s_b, d.Q, f[u]) | ((uint32_t)rank_ge(s_b + 256, d.Q, f[u]) << 16);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const uint64_t v = v0 + u * stride;
+            if (v >= V) continue;
+            d.vrank[v] = r[u];
+            uint4* o = reinterpret_cast<uint4*>(d.fplanes + v * 8);
+            o[0] = make_uint4(0, 0, 0, 0);
+            o[1] = make_uint4(0, 0, 0, 0);
+            uint32_t any = 0;
+            if ((r[u] & 0xFFFFu) && (r[u] >> 16)) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) any |= rank_word(ftab, r[u], k);
+            }
+            if (any) {
+                const int x = (int)(v % d.X);
+                const uint64_t q = v / d.X;
+                const int y = (int)(q % d.Y);
+                const uint64_t q2 = q / d.Y;
+                const int z = (int)(q2 % d.Z), t = (int)(q2 / d.Z);
+                d.active[btile_of(d, x, y, z, t)] = 1;
+            }
         }
     }
 }
