@@ -47,8 +47,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # 1 GiB copy), per (kernel, library version); a kernel changed since then has none.
 # Source: profiles/grow_256x256x256x64_bt16_launch_hbm_counters.md.
 MEASURED_TRAFFIC = {
-    ("k_round_pull", "mf4d 0.7.3 (gfx950)"): 46040227,
-    ("k_round_sweep<16>", "mf4d 0.7.3 (gfx950)"): 14014472,
+    ("k_round_pull", "mf4d 0.7.4 (gfx950)"): 46042359,
+    ("k_round_sweep<16>", "mf4d 0.7.4 (gfx950)"): 14016282,
 }
 PREDICTOR = os.path.join(ROOT, "paper_1903_12294_amd", "predictor.npy")
 
