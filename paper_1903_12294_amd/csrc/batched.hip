@@ -173,12 +173,16 @@ __device__ __forceinline__ void bschedule_n(const DevB& d, const uint32_t (&tile
 
 // Voxel bits set from outside a sweep: schedule its tile and the tiles whose
 // face it touches (at most one per axis), and flag the tile for the pull.
-__device__ __forceinline__ void bmark_voxel(const DevB& d, int x, int y, int z, int t, int par) {
+// The voxel's tile (flagged for the pull) and the tiles whose face it
+// touches, at most one per axis: slots 0 (own) and 1..4 of nb (~0u: none).
+__device__ __forceinline__ void voxel_targets(const DevB& d, int x, int y, int z, int t, int par,
+                                              uint32_t* nb) {
     const uint32_t tile = btile_of(d, x, y, z, t);
     d.chg[par * d.NTB + tile] = 1;
     const uint32_t sy = d.NXb, sz = d.NXb * d.NYb, st = sz * d.NZb;
     const int mx = (1 << d.lx) - 1, my = (1 << d.ly) - 1, mz = (1 << d.lz) - 1, mt = (1 << d.lt) - 1;
-    uint32_t nb[5] = {tile, ~0u, ~0u, ~0u, ~0u};
+    nb[0] = tile;
+    nb[1] = nb[2] = nb[3] = nb[4] = ~0u;
     if ((x & mx) == 0 && x > 0) nb[1] = tile - 1;
     else if ((x & mx) == mx && x + 1 < d.X) nb[1] = tile + 1;
     if ((y & my) == 0 && y > 0) nb[2] = tile - sy;
@@ -187,7 +191,33 @@ __device__ __forceinline__ void bmark_voxel(const DevB& d, int x, int y, int z, 
     else if ((z & mz) == mz && z + 1 < d.Z) nb[3] = tile + sz;
     if ((t & mt) == 0 && t > 0) nb[4] = tile - st;
     else if ((t & mt) == mt && t + 1 < d.T) nb[4] = tile + st;
+}
+
+__device__ __forceinline__ void bmark_voxel(const DevB& d, int x, int y, int z, int t, int par) {
+    uint32_t nb[5];
+    voxel_targets(d, x, y, z, t, par, nb);
     bschedule_n<5>(d, nb, 0x1Eu, par);  // the voxel's own tile unchecked
+}
+
+// N voxels (bit positions, kNoVoxel: none) marked with one batch of
+// scheduling round trips.
+template <int N>
+__device__ __forceinline__ void bmark_voxels_n(const DevB& d, const uint32_t (&b)[N], int par) {
+    static_assert(5 * N <= 32, "one check bit per target");
+    uint32_t nb[5 * N];
+    uint32_t check = 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) nb[5 * i + j] = ~0u;
+        check |= 0x1Eu << (5 * i);  // every voxel's own tile unchecked
+        if (b[i] != kNoVoxel) {
+            int x, y, z, t;
+            bit_to_xyzt(d.g, b[i], x, y, z, t);
+            voxel_targets(d, x, y, z, t, par, nb + 5 * i);
+        }
+    }
+    bschedule_n<5 * N>(d, nb, check, par);
 }
 
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_tmp,
@@ -712,6 +742,10 @@ __device__ __forceinline__ void close_whole(const DevB& d, uint32_t p, bool vali
     }
 #pragma unroll
     for (int j = 0; j < kWhole; ++j) lab[j] &= ~cur[j];  // the new bits
+    // the voxels that gained bits in any word, each marked once, by lane
+    // jj & 7 of the particle's group: four per lane at most, in one batch
+    // after both halves
+    uint32_t marks[4] = {kNoVoxel, kNoVoxel, kNoVoxel, kNoVoxel};
 #pragma unroll
     for (int h = 0; h < kWhole; h += 16) {
         uint32_t bb[16];
@@ -748,13 +782,10 @@ __device__ __forceinline__ void close_whole(const DevB& d, uint32_t p, bool vali
 #pragma unroll
         for (int jj = 0; jj < 16; ++jj) {
             const uint32_t gg = (uint32_t)(__ballot(got[jj] != 0) >> (8 * grp)) & 0xFFu;
-            if (got[jj] && k == __builtin_ctz(gg)) {
-                int x, y, z, tt;
-                bit_to_xyzt(d.g, bb[jj], x, y, z, tt);
-                bmark_voxel(d, x, y, z, tt, npar);
-            }
+            if (gg && (jj & 7) == k) marks[(h >> 3) + (jj >> 3)] = bb[jj];
         }
     }
+    bmark_voxels_n<4>(d, marks, npar);
 }
 
 __global__ __launch_bounds__(256) void kb_close(DevB d, int par) {
