@@ -125,54 +125,20 @@ __device__ __forceinline__ void bit_to_xyzt(const Geom& g, uint32_t b, int& x, i
     t = (tt << g.logBT) + (wi >> 6);
 }
 
-// The work list of a round parity is kBSubs sub-lists (tile % kBSubs), each
-// with its own counter on its own cache line: appends from every wave to one
-// counter would serialise.
+// Scheduling flags a tile for the round of parity `par` with a plain store
+// (no round trip to wait for); kb_compact turns the flags into that round's
+// work list, dropping tiles without an admissible node.
 __device__ __forceinline__ void bschedule(const DevB& d, uint32_t tile, int par) {
-    if (atomicExch(&d.dirty[par * d.NTB + tile], 1u) == 0u) {
-        const uint32_t j = (uint32_t)par * kBSubs + (tile & (kBSubs - 1));
-        const uint32_t k = atomicAdd(&d.wcnt[j * kBCntStride], 1u);
-        d.work[(size_t)j * d.WCAPB + k] = tile;
-    }
+    d.dirty[par * d.NTB + tile] = 1u;
 }
 
-// Schedule up to N tiles for round parity `par` (~0u: none), each only if it
-// holds an admissible node (check: the tile's active flag is read first).
-// The flag loads, the exchanges and the appends are each issued for all N
-// together, so the whole costs three round trips, not three per tile.
 template <int N>
-__device__ __forceinline__ void bschedule_n(const DevB& d, const uint32_t (&tiles)[N], uint32_t check, int par) {
-    uint32_t act[N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        act[i] = 0u;
-        if (tiles[i] != ~0u) act[i] = ((check >> i) & 1u) ? (uint32_t)d.active[tiles[i]] : 1u;
-    }
-    uint32_t old[N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        old[i] = 1u;
-        if (act[i]) old[i] = atomicExch(&d.dirty[par * d.NTB + tiles[i]], 1u);
-    }
-    uint32_t slot[N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        slot[i] = 0u;
-        if (!old[i]) {
-            const uint32_t j = (uint32_t)par * kBSubs + (tiles[i] & (kBSubs - 1));
-            slot[i] = atomicAdd(&d.wcnt[j * kBCntStride], 1u);
-        }
-    }
+__device__ __forceinline__ void bschedule_n(const DevB& d, const uint32_t (&tiles)[N], int par) {
 #pragma unroll
     for (int i = 0; i < N; ++i)
-        if (!old[i]) {
-            const uint32_t j = (uint32_t)par * kBSubs + (tiles[i] & (kBSubs - 1));
-            d.work[(size_t)j * d.WCAPB + slot[i]] = tiles[i];
-        }
+        if (tiles[i] != ~0u) bschedule(d, tiles[i], par);
 }
 
-// Voxel bits set from outside a sweep: schedule its tile and the tiles whose
-// face it touches (at most one per axis), and flag the tile for the pull.
 // The voxel's tile (flagged for the pull) and the tiles whose face it
 // touches, at most one per axis: slots 0 (own) and 1..4 of nb (~0u: none).
 __device__ __forceinline__ void voxel_targets(const DevB& d, int x, int y, int z, int t, int par,
@@ -196,28 +162,24 @@ __device__ __forceinline__ void voxel_targets(const DevB& d, int x, int y, int z
 __device__ __forceinline__ void bmark_voxel(const DevB& d, int x, int y, int z, int t, int par) {
     uint32_t nb[5];
     voxel_targets(d, x, y, z, t, par, nb);
-    bschedule_n<5>(d, nb, 0x1Eu, par);  // the voxel's own tile unchecked
+    bschedule_n<5>(d, nb, par);
 }
 
-// N voxels (bit positions, kNoVoxel: none) marked with one batch of
-// scheduling round trips.
+// N voxels (bit positions, kNoVoxel: none) marked together.
 template <int N>
 __device__ __forceinline__ void bmark_voxels_n(const DevB& d, const uint32_t (&b)[N], int par) {
-    static_assert(5 * N <= 32, "one check bit per target");
     uint32_t nb[5 * N];
-    uint32_t check = 0;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
 #pragma unroll
         for (int j = 0; j < 5; ++j) nb[5 * i + j] = ~0u;
-        check |= 0x1Eu << (5 * i);  // every voxel's own tile unchecked
         if (b[i] != kNoVoxel) {
             int x, y, z, t;
             bit_to_xyzt(d.g, b[i], x, y, z, t);
             voxel_targets(d, x, y, z, t, par, nb + 5 * i);
         }
     }
-    bschedule_n<5 * N>(d, nb, check, par);
+    bschedule_n<5 * N>(d, nb, par);
 }
 
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_tmp,
@@ -391,7 +353,6 @@ __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_l
     const int x = (bx << d.lx) + xl, y = (by << d.ly) + yl, z = (bz << d.lz) + zl, t = (bt << d.lt) + tl;
     const bool in = x < d.X && y < d.Y && z < d.Z && t < d.T;
     if (tid == 0) {
-        d.dirty[par * d.NTB + tile] = 0u;
         s_flags[0] = 0;
         s_flags[1] = 0;
         s_flags[2] = 0;
@@ -569,8 +530,8 @@ __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_l
         atomicOr(&s_flags[0], faces);
     }
     __syncthreads();
-    // lanes 0..7 of the first wave schedule the tiles across the eight faces
-    // that gained bits, side by side
+    // lanes 0..7 of the first wave flag the tiles across the eight faces
+    // that gained bits
     const uint32_t f = s_flags[0];
     if (f && tid < 8) {
         if (tid == 0) d.chg[par * d.NTB + tile] = 1;
@@ -588,7 +549,7 @@ __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_l
                 default: if (bt + 1 < d.NTb) nb[0] = tile + st; break;
             }
         }
-        bschedule_n<1>(d, nb, 1u, par ^ 1);
+        bschedule_n<1>(d, nb, par ^ 1);
     }
     __syncthreads();
 }
@@ -643,8 +604,6 @@ __global__ __launch_bounds__(512) void kb_sweep(DevB d, int par) {
 __global__ __launch_bounds__(256) void kb_pull(DevB d, int par) {
     __shared__ uint32_t s_tmp[20];
     if (!d.counters[BC_RACT]) return;
-    // the swept list is empty again (its dirty flags were cleared by the sweeps)
-    if (blockIdx.x == 0 && threadIdx.x < kBSubs) d.wcnt[((uint32_t)par * kBSubs + threadIdx.x) * kBCntStride] = 0u;
     const uint32_t* ptab = reinterpret_cast<const uint32_t*>(d.tab + 1024) + 2 * 257 * 8;
     const uint32_t n = d.counters[BC_NLIST];
     for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < n; b0 += gridDim.x * blockDim.x) {
@@ -794,6 +753,10 @@ __global__ __launch_bounds__(256) void kb_close(DevB d, int par) {
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t stride = gridDim.x * blockDim.x;
     if (!d.counters[BC_RACT]) return;
+    // the swept list is empty again (the close runs in every round, with or
+    // without particles; the next list of this parity is built after the
+    // round after this one)
+    if (blockIdx.x == 0 && threadIdx.x < kBSubs) d.wcnt[((uint32_t)par * kBSubs + threadIdx.x) * kBCntStride] = 0u;
     for (uint32_t i = tid; i < d.NTB; i += stride) d.chg[par * d.NTB + i] = 0;
     const uint32_t nd = d.counters[BC_NDIRTYP];
     if (tid == 0 && nd) atomicAdd(&d.stat64[S_PART_VISITS], (unsigned long long)nd);
@@ -885,6 +848,27 @@ __global__ __launch_bounds__(256) void kb_close(DevB d, int par) {
     }
 }
 
+// The work list of the round of parity `par` from the tiles flagged for it
+// (the flags cleared for that parity's next use): a flagged tile joins if it
+// holds a node admissible for some query.  Appends go to sub-list (tile mod
+// kBSubs): 64 counters on separate lines.  force: also after a round without
+// work (the list after seeding).
+__global__ __launch_bounds__(256) void kb_compact(DevB d, int par, int force) {
+    if (!force && !d.counters[BC_RACT]) return;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < d.NTB; i += stride) {
+        uint32_t* f = &d.dirty[(size_t)par * d.NTB + i];
+        if (*f) {
+            *f = 0u;
+            if (d.active[i]) {
+                const uint32_t j = (uint32_t)par * kBSubs + (i & (kBSubs - 1));
+                const uint32_t k = atomicAdd(&d.wcnt[j * kBCntStride], 1u);
+                d.work[(size_t)j * d.WCAPB + k] = i;
+            }
+        }
+    }
+}
+
 // Total length of the work list of parity par, for the host.
 __global__ void kb_work_total(DevB d, int par) {
     uint32_t x = d.wcnt[((uint32_t)par * kBSubs + threadIdx.x) * kBCntStride];
@@ -944,6 +928,7 @@ void launch_b_prepare(const DevB& d, const int32_t* seeds, int64_t S, hipStream_
                            dim3(grid_for((uint64_t)d.P * d.Tpad, 256, 8192)), dim3(256), 0, s, d);
     if (S > 0)
         hipLaunchKernelGGL(kb_seeds, dim3(grid_for(S, 256, 1u << 20)), dim3(256), 0, s, d, seeds, S);
+    hipLaunchKernelGGL(kb_compact, dim3(grid_for(d.NTB, 256, 1024)), dim3(256), 0, s, d, 0, 1);
 }
 
 void launch_b_round(const DevB& d, uint32_t round, hipStream_t s) {
@@ -957,6 +942,7 @@ void launch_b_round(const DevB& d, uint32_t round, hipStream_t s) {
     } else {
         hipLaunchKernelGGL(kb_close, dim3(grid_for(d.NTB, 256, 2048)), dim3(256), 0, s, d, par);
     }
+    hipLaunchKernelGGL(kb_compact, dim3(grid_for(d.NTB, 256, 1024)), dim3(256), 0, s, d, par ^ 1, 0);
 }
 
 void launch_b_work_total(const DevB& d, int par, hipStream_t s) {

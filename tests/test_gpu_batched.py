@@ -85,6 +85,22 @@ def test_random_small_queries(seed, tile):
 
 
 @pytest.mark.parametrize("tile", [None, (4, 4, 4, 8)])
+def test_field_only_queries(tile):
+    """No particles: rounds of sweeps alone, each round's list built anew."""
+    from tests.test_oracle_pins import _random_instance
+    rng = np.random.default_rng(77)
+    inst = _random_instance(rng, 24, 20, 17, 9, 0, 1)
+    Q = 40
+    vals = np.array([0.25, 0.5, 0.75, 1.0, np.inf], np.float32)
+    crit = np.stack([vals[rng.integers(0, 3, Q)], vals[rng.integers(2, 5, Q)],
+                     np.full(Q, -np.inf, np.float32), np.full(Q, np.inf, np.float32)], 1).astype(np.float32)
+    qseeds = np.stack([rng.integers(0, 24, 3 * Q), rng.integers(0, 20, 3 * Q), rng.integers(0, 17, 3 * Q),
+                       rng.integers(0, 9, 3 * Q), rng.integers(0, Q, 3 * Q)], 1).astype(np.int32)
+    st = _check(inst, crit, qseeds, tile=tile)
+    assert st["rounds"] > 1
+
+
+@pytest.mark.parametrize("tile", [None, (4, 4, 4, 8)])
 def test_config1_256_queries(tile):
     inst = synth.make_config(1)
     crit, qseeds = synth.make_queries(inst, Q=256)
