@@ -341,6 +341,7 @@ constexpr int kDppRowShr1 = 0x111, kDppRowShr4 = 0x114, kDppRowShl1 = 0x101, kDp
 // lane permutes; each wave runs its cube to a fixed point with the t
 // neighbours held fixed, and only the t neighbours go through LDS, once per
 // block-wide pass.
+template <bool kCube>
 __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_lab,
                             uint32_t* s_flags, const uint32_t* s_ftab) {
     int bx, by, bz, bt;
@@ -357,17 +358,21 @@ __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_l
         s_flags[1] = 0;
         s_flags[2] = 0;
     }
+    // a: the admissible queries per word; the cube route recomputes them
+    // from the node's ranks where it needs them (fewer registers, more
+    // blocks per CU)
     uint32_t a[8], l[8], h[8];
+    uint32_t rv = 0;  // ranks 0: no query admits the node
     const uint64_t v = in ? vindex(d, x, y, z, t) : 0;
     if (in) {
-        const uint32_t rv = d.vrank[v];
+        rv = d.vrank[v];
         const uint4* lp = reinterpret_cast<const uint4*>(d.fplanes + v * 8);
         const uint4 l01 = lp[0], l23 = lp[1];
         l[0] = l01.x; l[1] = l01.y; l[2] = l01.z; l[3] = l01.w;
         l[4] = l23.x; l[5] = l23.y; l[6] = l23.z; l[7] = l23.w;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            a[k] = rank_word(s_ftab, rv, k);
+            a[k] = kCube ? 0u : rank_word(s_ftab, rv, k);
             h[k] = 0;
         }
         // halos: neighbours outside the tile (inside the grid), each load
@@ -408,7 +413,7 @@ __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_l
         uint32_t room = 0, src = 0;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            room |= (a[k] & ~l[k]) ? 1u << k : 0u;
+            room |= ((kCube ? rank_word(s_ftab, rv, k) : a[k]) & ~l[k]) ? 1u << k : 0u;
             src |= (l[k] | h[k]) ? 1u << k : 0u;
         }
         __syncthreads();  // the flags were cleared
@@ -450,7 +455,7 @@ __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_l
         uint32_t fx = h[k];                                                    \
         if (nt0 >= 0) fx |= s_lab[(k) * 512 + nt0];                            \
         if (nt1 >= 0) fx |= s_lab[(k) * 512 + nt1];                            \
-        const uint32_t ak = a[k];                                              \
+        const uint32_t ak = rank_word(s_ftab, rv, k);                          \
         uint32_t cur = l[k];                                                   \
         while (true) {                                                         \
             const uint32_t xm = dpp_row<kDppRowShr1>(cur);                     \
@@ -477,8 +482,7 @@ __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_l
             l[k] = cur;                                                        \
         }                                                                      \
     }
-    const bool cube = d.lx == 2 && d.ly == 2 && d.lz == 2;  // block-uniform
-    if (need && cube) {
+    if (kCube && need) {
         const int lane = tid & 63;
         while (true) {
             MF4D_STORE_WORD(0) MF4D_STORE_WORD(1) MF4D_STORE_WORD(2) MF4D_STORE_WORD(3)
@@ -557,6 +561,8 @@ __device__ void bsweep_tile(const DevB& d, uint32_t tile, int par, uint32_t* s_l
 // A round's sweep.  Rounds are queued ahead of the host: a round whose work
 // list is empty does nothing (its sweep records that for the round's pull and
 // close), and BC_ROUNDS counts the rounds that had work.
+// kCube: tiles of 4 x 4 x 4 x 8 (the cube route of bsweep_tile).
+template <bool kCube>
 __global__ __launch_bounds__(512) void kb_sweep(DevB d, int par) {
     __shared__ uint32_t s_lab[8 * 512];
     __shared__ uint32_t s_flags[4];
@@ -593,7 +599,7 @@ __global__ __launch_bounds__(512) void kb_sweep(DevB d, int par) {
             if (s_pref[mid] <= w) lo = mid; else hi = mid;
         }
         const uint32_t tile = d.work[((size_t)par * kBSubs + lo) * d.WCAPB + (w - s_pref[lo])];
-        bsweep_tile(d, tile, par, s_lab, s_flags, s_ftab);
+        bsweep_tile<kCube>(d, tile, par, s_lab, s_flags, s_ftab);
         ++visits;
     }
     if (threadIdx.x == 0 && visits) atomicAdd(&d.stat64[S_TILE_VISITS], (unsigned long long)visits);
@@ -933,7 +939,10 @@ void launch_b_prepare(const DevB& d, const int32_t* seeds, int64_t S, hipStream_
 
 void launch_b_round(const DevB& d, uint32_t round, hipStream_t s) {
     const int par = round & 1;
-    hipLaunchKernelGGL(kb_sweep, dim3(grid_for(d.NTB, 1, 2048)), dim3(512), 0, s, d, par);
+    if (d.lx == 2 && d.ly == 2 && d.lz == 2)
+        hipLaunchKernelGGL(kb_sweep<true>, dim3(grid_for(d.NTB, 1, 2048)), dim3(512), 0, s, d, par);
+    else
+        hipLaunchKernelGGL(kb_sweep<false>, dim3(grid_for(d.NTB, 1, 2048)), dim3(512), 0, s, d, par);
     if (d.P > 0) {
         hipLaunchKernelGGL(kb_pull, dim3(grid_for((uint64_t)d.P * d.Tpad, 256, 2048)), dim3(256), 0,
                            s, d, par);
