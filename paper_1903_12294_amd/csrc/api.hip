@@ -797,7 +797,7 @@ extern "C" {
 
 // Bumped whenever a kernel changes: autotuner caches and recorded hardware
 // counter figures are keyed by it.
-const char* mf4d_version(void) { return "mf4d 0.7.5 (gfx950)"; }
+const char* mf4d_version(void) { return "mf4d 0.7.6 (gfx950)"; }
 
 const char* mf4d_last_error(void) { return g_err.c_str(); }
 
