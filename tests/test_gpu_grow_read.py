@@ -196,3 +196,22 @@ def test_grow_read_rejects_bad_buffers():
             g.grow_read(np.zeros(g.field_words(), np.uint32), None)
     finally:
         g.close()
+
+
+def test_grow_read_without_statistics():
+    """stats=False passes no statistics buffer; the masks and the statistics
+    read afterwards are those of the grow."""
+    _need_gpu()
+    inst = synth.make_config(1, attr_mode="noise")
+    ofm, opm, ost = _oracle(inst)
+    g = _grower(inst, schedule="launch")
+    try:
+        fm, pm = _buffers(g)
+        assert g.grow_read(fm, pm, stats=False) is None
+        hf, hp = _host(fm, pm)
+        assert np.array_equal(hf, ofm) and np.array_equal(hp, opm)
+        st = g.stats()
+        assert st["members_field"] == ost["members_field"]
+        assert st["members_particle"] == ost["members_particle"]
+    finally:
+        g.close()
