@@ -627,8 +627,10 @@ def bench_adjacent(g, inst, fmask, pmask, args, torch, forms):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    # 30 timed steps: the last step's read-outs, which no later grow hides,
+    # weigh 1/30 of one read-out per step
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3])
     ap.add_argument("--no-tune", action="store_true", help="default configuration, no autotuning")
     ap.add_argument("--schedule", choices=["persistent", "launch"], help="fix the schedule (no tuning)")
