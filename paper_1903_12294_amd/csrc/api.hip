@@ -139,9 +139,7 @@ struct mf4d_ctx {
     uint2* clist = nullptr;
     uint32_t* wcnt = nullptr;       // work sub-list lengths
     uint32_t* pdirty = nullptr;
-    uint32_t* pcand = nullptr;      // candidate particles of the current grow
     uint8_t* pflag = nullptr;       // P candidate flags
-    uint32_t* pblk = nullptr;       // candidate-pass block counts / offsets
     uint32_t* dlist = nullptr;
     float2* psum = nullptr;
 
@@ -387,9 +385,7 @@ void free_particles(mf4d_ctx* c) {
     c->alt_ready = false;
     dev_free(c->clist);
     dev_free(c->pdirty);
-    dev_free(c->pcand);
     dev_free(c->pflag);
-    dev_free(c->pblk);
     dev_free(c->dlist);
     dev_free(c->psum);
     dev_free(c->b_pown);
@@ -448,9 +444,7 @@ Dev make_dev(mf4d_ctx* c) {
     d.Lp = c->Lp;
     d.clist = c->clist;
     d.pdirty = c->pdirty;
-    d.pcand = c->pcand;
     d.pflag = c->pflag;
-    d.pblk = c->pblk;
     d.slots = c->slots;
     d.counters = c->counters;
     d.stat64 = c->stat64;
@@ -797,7 +791,7 @@ extern "C" {
 
 // Bumped whenever a kernel changes: autotuner caches and recorded hardware
 // counter figures are keyed by it.
-const char* mf4d_version(void) { return "mf4d 0.7.6 (gfx950)"; }
+const char* mf4d_version(void) { return "mf4d 0.7.7 (gfx950)"; }
 
 const char* mf4d_last_error(void) { return g_err.c_str(); }
 
@@ -1026,9 +1020,7 @@ int mf4d_load_particles_rate(mf4d_ctx* c, const float* xyz, const float* attr, i
     if (!rc) rc = dev_alloc(&c->Lp, (size_t)P * pg.W);
     if (!rc) rc = dev_alloc(&c->clist, Q);
     if (!rc) rc = dev_alloc(&c->pdirty, (size_t)(P + 31) / 32);
-    if (!rc) rc = dev_alloc(&c->pcand, (size_t)P);
     if (!rc) rc = dev_alloc(&c->pflag, (size_t)P);
-    if (!rc) rc = dev_alloc(&c->pblk, (size_t)kPBlocks + 1);
     if (!rc) rc = dev_alloc(&c->dlist, (size_t)P);
     if (!rc) rc = dev_alloc(&c->psum, (size_t)P);
     if (rc) {

@@ -1330,74 +1330,6 @@ __device__ __forceinline__ void flush_stage(const Dev& d, const uint2* s_buf, ui
     __syncthreads();
 }
 
-// Candidate particles of a grow: those whose load-time value range meets the
-// band (the others hold no admissible step).  Three passes, no atomics: per
-// block of particles the flags and their count; one block scans the counts;
-// each block writes its candidates, in index order, at its offset.
-__global__ __launch_bounds__(256) void k_pcand_count(Dev d) {
-    __shared__ uint32_t s_tmp[8];
-    const int64_t P = d.pg.P;
-    const int64_t per = (P + kPBlocks - 1) / kPBlocks;
-    const int64_t p0 = blockIdx.x * per, p1 = min(P, p0 + per);
-    const float lo = d.crit[2], hi = d.crit[3];
-    uint32_t c = 0;
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-        const float2 r = d.psum[p];
-        const bool in = r.y >= lo && r.x <= hi;
-        d.pflag[p] = in ? 1 : 0;
-        c += in ? 1u : 0u;
-    }
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
-    if (lane_id() == 0) s_tmp[threadIdx.x >> 6] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) d.pblk[blockIdx.x] = s_tmp[0] + s_tmp[1] + s_tmp[2] + s_tmp[3];
-}
-
-__global__ __launch_bounds__(1024) void k_pcand_scan(Dev d) {
-    static_assert(kPBlocks % 1024 == 0, "each scan thread takes kPBlocks / 1024 counts");
-    constexpr int per = kPBlocks / 1024;
-    __shared__ uint32_t s_w[16];
-    const int lane = lane_id(), wave = threadIdx.x >> 6;
-    uint32_t v[per], sum = 0;
-#pragma unroll
-    for (int i = 0; i < per; ++i) {
-        v[i] = d.pblk[threadIdx.x * per + i];
-        sum += v[i];
-    }
-    uint32_t wt;
-    const uint32_t ex = wave_excl_scan(sum, wt);
-    if (lane == 0) s_w[wave] = wt;
-    __syncthreads();
-    uint32_t base = 0, total = 0;
-    for (int w = 0; w < 16; ++w) {
-        if (w < wave) base += s_w[w];
-        total += s_w[w];
-    }
-    uint32_t at = base + ex;
-#pragma unroll
-    for (int i = 0; i < per; ++i) {
-        d.pblk[threadIdx.x * per + i] = at;
-        at += v[i];
-    }
-    if (threadIdx.x == 0) d.counters[C_NPCAND] = total;
-}
-
-__global__ __launch_bounds__(256) void k_pcand_write(Dev d) {
-    __shared__ uint32_t s_tmp[8];
-    const int64_t P = d.pg.P;
-    const int64_t per = (P + kPBlocks - 1) / kPBlocks;
-    const int64_t p0 = blockIdx.x * per, p1 = min(P, p0 + per);
-    uint32_t off = d.pblk[blockIdx.x];
-    for (int64_t b0 = p0; b0 < p1; b0 += blockDim.x) {  // block-uniform
-        const int64_t p = b0 + threadIdx.x;
-        const uint32_t in = p < p1 && d.pflag[p] ? 1u : 0u;
-        uint32_t total;
-        const uint32_t ex = block_exclusive_scan256(in, s_tmp, total);
-        if (in) d.pcand[off + ex] = (uint32_t)p;
-        off += total;
-    }
-}
-
 // Admissibility of the candidate particles' steps, their labels cleared, and
 // the coupled list: every admissible particle-step that lies in a voxel, as
 // (flat index, voxel bit).  A unit is one 64-step label word of a candidate
@@ -1407,107 +1339,134 @@ __global__ __launch_bounds__(256) void k_pcand_write(Dev d) {
 // global list with one atomic per flush (appends to one counter from every
 // block serialise).  Non-candidates are not touched: their pflag is 0.
 // Requires Tpad >= 4.
+//
+// The candidates are found in the same pass: a block takes kAdmitChunk
+// particles at a time (four consecutive ones per thread), flags those whose
+// load-time value range meets the band (pflag), lists them in index order in
+// LDS and then tests their units; the coupled list keeps each particle's
+// entries side by side in step order.
+constexpr int kAdmitChunk = 1024;
 __global__ __launch_bounds__(256) void k_admit_particles(Dev d) {
     __shared__ __align__(8) uint32_t s_tmp[10];
     __shared__ uint2 s_buf[kStage];
+    __shared__ uint32_t s_cand[kAdmitChunk];
     const PGeom& pg = d.pg;
     const float lo = d.crit[2], hi = d.crit[3];
     const int G = pg.Tpad >= 64 ? 16 : (pg.Tpad >> 2);  // lanes per unit (power of two)
     const uint32_t upb = 256 / G;                       // units per block pass
     const int W = pg.W;
-    const uint64_t nunits = (uint64_t)d.counters[C_NPCAND] * W;
     const int sub = threadIdx.x & (G - 1);
-    const uint64_t gstride = (uint64_t)gridDim.x * upb;
     const v4f* src = reinterpret_cast<const v4f*>(d.attr_t);
     const uint4* bsrc = reinterpret_cast<const uint4*>(d.bins);
     uint32_t nbuf = 0;  // entries staged; the same in every thread
-    for (uint64_t ub = blockIdx.x * (uint64_t)upb; ub < nunits; ub += 4 * gstride) {  // block-uniform
-        v4f v[4];
-        uint32_t e0[4], wi[4];
+    for (int64_t c0 = (int64_t)blockIdx.x * kAdmitChunk; c0 < pg.P;
+         c0 += (int64_t)gridDim.x * kAdmitChunk) {  // block-uniform
+        uint32_t flags = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint64_t u = ub + k * gstride + threadIdx.x / G;
-            const float nan = __builtin_nanf("");
-            v[k] = (v4f){nan, nan, nan, nan};
-            e0[k] = 0xFFFFFFFFu;
-            if (u < nunits) {
-                const uint32_t p = d.pcand[W == 1 ? u : u / W];
-                const uint32_t w = W == 1 ? 0u : (uint32_t)(u % W);
-                e0[k] = p * (uint32_t)pg.Tpad + w * 64u + (uint32_t)sub * 4u;
-                wi[k] = p * (uint32_t)W + w;
-                v[k] = __builtin_nontemporal_load(src + (e0[k] >> 2));
+        for (int j = 0; j < 4; ++j) {
+            const int64_t p = c0 + 4 * threadIdx.x + j;
+            if (p < pg.P) {
+                const float2 r = d.psum[p];
+                const bool in = r.y >= lo && r.x <= hi;
+                d.pflag[p] = in ? 1 : 0;
+                flags |= (in ? 1u : 0u) << j;
             }
         }
-        uint32_t nibs[4];
-        uint4 bn[4];
-        uint32_t cnt = 0;
+        uint32_t ncand;  // the same in every thread
+        uint32_t at = block_exclusive_scan256((uint32_t)__popc(flags), s_tmp, ncand);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t nib = (uint32_t)in_band(v[k].x, lo, hi) |
-                                 ((uint32_t)in_band(v[k].y, lo, hi) << 1) |
-                                 ((uint32_t)in_band(v[k].z, lo, hi) << 2) |
-                                 ((uint32_t)in_band(v[k].w, lo, hi) << 3);
-            unsigned long long x = (unsigned long long)nib << (4 * sub);
-            for (int o = 1; o < G; o <<= 1) x |= __shfl_xor(x, o);
-            if (sub == 0 && e0[k] != 0xFFFFFFFFu) {
-                d.Ap[wi[k]] = x;
-                d.Lp[wi[k]] = 0ull;
+        for (int j = 0; j < 4; ++j)
+            if ((flags >> j) & 1u) s_cand[at++] = (uint32_t)(c0 + 4 * threadIdx.x + j);
+        __syncthreads();
+        const uint32_t nunits = ncand * (uint32_t)W;
+        for (uint32_t ub = 0; ub < nunits; ub += 4 * upb) {  // block-uniform
+            v4f v[4];
+            uint32_t e0[4], wi[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t u = ub + k * upb + threadIdx.x / G;
+                const float nan = __builtin_nanf("");
+                v[k] = (v4f){nan, nan, nan, nan};
+                e0[k] = 0xFFFFFFFFu;
+                if (u < nunits) {
+                    const uint32_t p = s_cand[W == 1 ? u : u / W];
+                    const uint32_t w = W == 1 ? 0u : (uint32_t)(u % W);
+                    e0[k] = p * (uint32_t)pg.Tpad + w * 64u + (uint32_t)sub * 4u;
+                    wi[k] = p * (uint32_t)W + w;
+                    v[k] = __builtin_nontemporal_load(src + (e0[k] >> 2));
+                }
             }
-            bn[k] = make_uint4(kNoVoxel, kNoVoxel, kNoVoxel, kNoVoxel);
-            if (nib) bn[k] = bsrc[e0[k] >> 2];  // nib != 0 implies a unit in range
-            uint32_t m = nib;
-            if (bn[k].x == kNoVoxel) m &= ~1u;
-            if (bn[k].y == kNoVoxel) m &= ~2u;
-            if (bn[k].z == kNoVoxel) m &= ~4u;
-            if (bn[k].w == kNoVoxel) m &= ~8u;
-            nibs[k] = m;
-            cnt += __popc(m);
-        }
-        // Positions: the entries of unit set k of every thread come before
-        // those of set k + 1, in thread order within a set, so that the
-        // entries of one unit (its G lanes) are contiguous and in step order
-        // (the pull combines a particle's entries that sit side by side).
-        // Four 16-bit counts scanned in one 64-bit word.
-        unsigned long long packed = 0;
+            uint32_t nibs[4];
+            uint4 bn[4];
+            uint32_t cnt = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) packed |= (unsigned long long)__popc(nibs[k]) << (16 * k);
-        unsigned long long tot64;
-        const unsigned long long ex64 = block_exclusive_scan256_u64(packed, s_tmp, tot64);
-        uint32_t setbase[4], total = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            setbase[k] = total;
-            total += (uint32_t)(tot64 >> (16 * k)) & 0xFFFFu;
-        }
-        (void)cnt;
-        if (nbuf + total > kStage) {  // block-uniform
-            flush_stage(d, s_buf, nbuf, s_tmp);
-            nbuf = 0;
-        }
-        const bool direct = total > kStage;  // block-uniform; more than the stage holds
-        uint32_t base = nbuf;
-        if (direct) {
-            if (threadIdx.x == 0) s_tmp[8] = atomicAdd(&d.counters[C_NLIST], total);
-            __syncthreads();
-            base = s_tmp[8];
-            __syncthreads();
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (!nibs[k]) continue;
-            uint32_t out = base + setbase[k] + ((uint32_t)(ex64 >> (16 * k)) & 0xFFFFu);
-            const uint32_t bw[4] = {bn[k].x, bn[k].y, bn[k].z, bn[k].w};
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (!((nibs[k] >> j) & 1u)) continue;
-                const uint2 e = make_uint2(e0[k] + j, bw[j]);
-                if (direct) d.clist[out++] = e;
-                else s_buf[out++] = e;
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t nib = (uint32_t)in_band(v[k].x, lo, hi) |
+                                     ((uint32_t)in_band(v[k].y, lo, hi) << 1) |
+                                     ((uint32_t)in_band(v[k].z, lo, hi) << 2) |
+                                     ((uint32_t)in_band(v[k].w, lo, hi) << 3);
+                unsigned long long x = (unsigned long long)nib << (4 * sub);
+                for (int o = 1; o < G; o <<= 1) x |= __shfl_xor(x, o);
+                if (sub == 0 && e0[k] != 0xFFFFFFFFu) {
+                    d.Ap[wi[k]] = x;
+                    d.Lp[wi[k]] = 0ull;
+                }
+                bn[k] = make_uint4(kNoVoxel, kNoVoxel, kNoVoxel, kNoVoxel);
+                if (nib) bn[k] = bsrc[e0[k] >> 2];  // nib != 0 implies a unit in range
+                uint32_t m = nib;
+                if (bn[k].x == kNoVoxel) m &= ~1u;
+                if (bn[k].y == kNoVoxel) m &= ~2u;
+                if (bn[k].z == kNoVoxel) m &= ~4u;
+                if (bn[k].w == kNoVoxel) m &= ~8u;
+                nibs[k] = m;
+                cnt += __popc(m);
             }
+            // Positions: the entries of unit set k of every thread come before
+            // those of set k + 1, in thread order within a set, so that the
+            // entries of one unit (its G lanes) are contiguous and in step order
+            // (the pull combines a particle's entries that sit side by side).
+            // Four 16-bit counts scanned in one 64-bit word.
+            unsigned long long packed = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) packed |= (unsigned long long)__popc(nibs[k]) << (16 * k);
+            unsigned long long tot64;
+            const unsigned long long ex64 = block_exclusive_scan256_u64(packed, s_tmp, tot64);
+            uint32_t setbase[4], total = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                setbase[k] = total;
+                total += (uint32_t)(tot64 >> (16 * k)) & 0xFFFFu;
+            }
+            (void)cnt;
+            if (nbuf + total > kStage) {  // block-uniform
+                flush_stage(d, s_buf, nbuf, s_tmp);
+                nbuf = 0;
+            }
+            const bool direct = total > kStage;  // block-uniform; more than the stage holds
+            uint32_t base = nbuf;
+            if (direct) {
+                if (threadIdx.x == 0) s_tmp[8] = atomicAdd(&d.counters[C_NLIST], total);
+                __syncthreads();
+                base = s_tmp[8];
+                __syncthreads();
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (!nibs[k]) continue;
+                uint32_t out = base + setbase[k] + ((uint32_t)(ex64 >> (16 * k)) & 0xFFFFu);
+                const uint32_t bw[4] = {bn[k].x, bn[k].y, bn[k].z, bn[k].w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (!((nibs[k] >> j) & 1u)) continue;
+                    const uint2 e = make_uint2(e0[k] + j, bw[j]);
+                    if (direct) d.clist[out++] = e;
+                    else s_buf[out++] = e;
+                }
+            }
+            if (!direct) nbuf += total;
         }
-        if (!direct) nbuf += total;
+        __syncthreads();  // every unit of the chunk read its candidate before the next list
     }
-    __syncthreads();
     if (nbuf) flush_stage(d, s_buf, nbuf, s_tmp);
 }
 
@@ -2229,12 +2188,8 @@ void launch_admit_particles(const Dev& d, hipStream_t s) {
     if (pg.Tpad >= 4) {
         const uint64_t n4 = ((uint64_t)pg.P * pg.Tpad) >> 2;
         (void)n4;
-        hipLaunchKernelGGL(k_pcand_count, dim3(kPBlocks), dim3(256), 0, s, d);
-        hipLaunchKernelGGL(k_pcand_scan, dim3(1), dim3(1024), 0, s, d);
-        hipLaunchKernelGGL(k_pcand_write, dim3(kPBlocks), dim3(256), 0, s, d);
-        const uint64_t units = (uint64_t)pg.P * pg.W;  // at most this many candidate words
-        const unsigned upb = 256 / (pg.Tpad >= 64 ? 16 : (pg.Tpad >> 2));
-        hipLaunchKernelGGL(k_admit_particles, dim3(grid_for(units, upb * 4, 2048)), dim3(256), 0, s, d);
+        hipLaunchKernelGGL(k_admit_particles, dim3(grid_for((uint64_t)pg.P, kAdmitChunk, 2048)), dim3(256), 0,
+                           s, d);
     } else {
         hipLaunchKernelGGL(k_admit_particles_short, dim3(grid_for(pg.P, 256, 4096)), dim3(256), 0, s,
                            d);

@@ -8,7 +8,6 @@ namespace mf4d {
 
 constexpr uint32_t kNoVoxel = 0xFFFFFFFFu;
 constexpr int kBarWords = 64 + 32 * 8;  // grid-barrier counters (top, flag, 8 subs), one line each
-constexpr int kPBlocks = 4096;          // blocks of the candidate-particle passes (4 per scan thread)
 // The tile work list of each round parity is split into kWorkSubs sub-lists
 // (tile % kWorkSubs), each with its own counter on its own 128-byte line:
 // appends to one counter from every wave serialise (~11 ns each), spread over
@@ -61,7 +60,7 @@ struct PGeom {
 enum Counter : int {
     C_NWORK0 = 0,  // tiles on work list 0 (even rounds), summed from its sub-lists for the host
     C_NWORK1 = 1,  // tiles on work list 1 (odd rounds), likewise
-    C_NPCAND = 2,  // candidate particles of this grow (value range meets the band)
+    C_UNUSED2 = 2, // (free)
     C_NLIST = 3,   // coupled particle-steps on the flat list
     C_DROPPED = 4, // dropped seeds
     C_ERR = 5,     // set by the persistent kernel if a grid barrier timed out
@@ -116,9 +115,7 @@ struct Dev {
     unsigned long long* Lp;  // [P][W] label bits
     uint2* clist;            // coupled steps (flat index, voxel bit)
     uint32_t* pdirty;        // P bits: particle gained a step this round (to close)
-    uint32_t* pcand;         // candidate particles of this grow, in index order
     uint8_t* pflag;          // P: 1 if the particle is a candidate (its Ap / Lp are valid)
-    uint32_t* pblk;          // kPBlocks + 1: per-block candidate counts, then offsets
     unsigned long long* slots;  // kSlotStats x kSlots partial sums of per-grow statistics
     uint32_t* counters;      // Counter
     unsigned long long* stat64;
