@@ -45,13 +45,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # HBM bytes per launch read from the FETCH_SIZE / WRITE_SIZE counters (scaled by a
 # 1 GiB copy), per (kernel, library version); a kernel changed since then has none.
-# Taken with 0.7.4; 0.7.5 and 0.7.6 changed only the batched grower's kernels, 0.7.7
-# only the particle admissibility pass.
-# Source: profiles/grow_256x256x256x64_bt16_launch_hbm_counters.md.
+# Source: profiles/grow_256x256x256x64_bt16_launch_hbm_counters.md (0.7.7).
 MEASURED_TRAFFIC = {
-    (kernel, version): nbytes
-    for kernel, nbytes in (("k_round_pull", 46042359), ("k_round_sweep<16>", 14016282))
-    for version in ("mf4d 0.7.4 (gfx950)", "mf4d 0.7.5 (gfx950)", "mf4d 0.7.6 (gfx950)", "mf4d 0.7.7 (gfx950)")
+    ("k_round_pull", "mf4d 0.7.7 (gfx950)"): 45795399,
+    ("k_round_sweep<16>", "mf4d 0.7.7 (gfx950)"): 14023401,
 }
 PREDICTOR = os.path.join(ROOT, "paper_1903_12294_amd", "predictor.npy")
 
